@@ -1,0 +1,241 @@
+/*
+ * apm.h -- C ABI of the adaptive particle-mesh (APM) gravity solve on static
+ * nested grids for AMD MI355X (gfx950), after Passy & Bryan, "An adaptive
+ * particle-mesh gravity solver for ENZO".
+ *
+ * The library computes, per grid of a static hierarchy (level 0 = root covering
+ * the unit box, each level refined by 2):
+ *   apm_deposit      TSC mass assignment of particles plus gas into the grid's
+ *                    GravitatingMassField (GMF)                       (Sec. 2)
+ *   apm_solve_level  zero-padded FFT convolution with the optimal influence
+ *                    function and differencing in Fourier space: the grid's own
+ *                    (short-range) acceleration and potential   (Sec. 2.2, Eq. 2-9)
+ *   apm_accel        composition with the parent: parent field interpolated onto
+ *                    the grid plus its own short-range field        (Sec. 2.2)
+ *   apm_interp       TSC interpolation of the composed field to the particles
+ * plus host-side planning, the owner-grid query and FP64 totals.
+ *
+ * Conventions (all calls):
+ *  - Units: box [0,1)^3, gravitational constant G from apm_config (code units).
+ *  - Indices: level-l cell c spans [c, c+1) * dx_l, dx_l = 1/(root_n 2^l).
+ *    Boxes are (lo[3], n[3]) in level-l global cell indices, (x, y, z) order.
+ *  - 3-D arrays are x-fastest: element (x, y, z) of a box of dims (nx, ny, nz)
+ *    sits at ((z * ny) + y) * nx + x.
+ *  - "Packed level buffer": the grids of one level, in grid-index order, each
+ *    at the offset that apm_plan_grid reports.
+ *  - Field buffers hold 4 values per cell, interleaved: (a_x, a_y, a_z, Phi).
+ *  - dtype APM_F32 or APM_F64 applies to every floating array of a call.
+ *  - Array arguments of the compute calls are DEVICE pointers on the context's
+ *    device, owned by the caller.  The library never frees or retains them and
+ *    overwrites outputs.  It owns only the plan, the context, the cached Green's
+ *    functions and its workspace.
+ *  - Compute calls are asynchronous on the context's stream unless stated.
+ *  - Every call returns an apm_status; on error apm_last_error() (thread-local)
+ *    describes it.  No call aborts the process.
+ */
+#ifndef APM_H
+#define APM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  APM_OK = 0,
+  APM_ERR_INVALID = 1,      /* bad argument, descriptor or nesting            */
+  APM_ERR_OOM = 2,          /* device allocation failed or workspace limit    */
+  APM_ERR_DEVICE = 3,       /* no usable device / HIP runtime error           */
+  APM_ERR_RANGE = 4,        /* size beyond a supported maximum                */
+  APM_ERR_UNSUPPORTED = 5,  /* valid request this build does not support      */
+  APM_ERR_STATE = 6         /* call out of order (e.g. missing parent field)  */
+} apm_status;
+
+typedef enum { APM_F32 = 1, APM_F64 = 2 } apm_dtype;
+
+/* Gradient operator D of Eq. 5 and of the differencing (Sec. 2.2 names both). */
+typedef enum {
+  APM_GRAD_SPECTRAL = 0,    /* D(k) = -i k (default)                            */
+  APM_GRAD_FD2 = 1          /* two-point central difference, -i sin(k dx)/dx  */
+} apm_gradient;
+
+typedef struct {
+  double G;                 /* gravitational constant [1.0]                       */
+  int32_t root_n;           /* root cells per axis, power of two in [8, 512]      */
+  double a_cells;           /* S2 softening a_l = a_cells * dx_l [3.4] (Sec. 2.2) */
+  double pad_factor;        /* subgrid zero padding p = ceil(pad_factor * 2 *
+                               a_cells) cells per axis [0.65] (Sec. 2.2)           */
+  int32_t ghost;            /* GMF ghost width of subgrids [3]                    */
+  int32_t brillouin;        /* alias zones n in [-b, b]^3 in Eq. 5 [1] (Eq. 6)    */
+  int32_t gradient;         /* apm_gradient [APM_GRAD_SPECTRAL]                   */
+  int64_t workspace_limit;  /* bytes of device workspace allowed, 0 = no limit    */
+} apm_config;
+
+/* One grid of the static hierarchy.  Grid 0 must be the root: level 0, parent
+ * -1, lo = 0, n = root_n.  A subgrid has level >= 1, a parent of level-1 with a
+ * smaller index, even lo and n >= 2 even, and its GMF box (active box grown by
+ * `ghost` cells) must lie over its parent's active box: parent cells
+ * floor((lo-ghost)/2) .. floor((lo+n+ghost-1)/2) on every axis (with ghost = 3:
+ * 2 parent cells of margin). */
+typedef struct {
+  int32_t level;
+  int32_t parent;
+  int32_t lo[3];
+  int32_t n[3];
+} apm_grid;
+
+/* Derived layout of one grid (apm_plan_grid). */
+typedef struct {
+  int32_t level, parent;
+  int32_t lo[3], n[3];       /* active box                                        */
+  int32_t gmf_lo[3], gmf_n[3];  /* GMF box: active (root) or active +- ghost     */
+  int32_t fld_lo[3], fld_n[3];  /* field box: active (root) or active +- 1       */
+  int32_t fft_n[3];          /* padded FFT lengths M (root 2 root_n, James)       */
+  int64_t gmf_offset;        /* element offset in the level's packed GMF buffer   */
+  int64_t fld_offset;        /* cell offset in the level's packed field buffer    */
+  int64_t gas_offset;        /* element offset in the level's packed gas buffer   */
+  double dx;                 /* cell size of the grid's level                      */
+} apm_grid_layout;
+
+typedef struct {
+  int32_t ngrids;            /* grids on this level                               */
+  int32_t first_grid;        /* index of its first grid (grids sorted by level)   */
+  int64_t gmf_elems;         /* scalars in the packed GMF buffer                  */
+  int64_t fld_cells;         /* cells in the packed field buffer (x4 values)       */
+  int64_t gas_elems;         /* scalars in the packed active-gas buffer           */
+  double dx;
+} apm_level_layout;
+
+typedef struct apm_plan_s* apm_plan;
+typedef struct apm_ctx_s* apm_ctx;
+
+/* ---------------------------------------------------------------- host only -- */
+
+/* Fill cfg with the defaults in brackets above (root_n = 0: must be set). */
+void apm_config_default(apm_config* cfg);
+
+/* Validate a hierarchy and compute its layout (no device needed).
+ * grids: host array of ngrids descriptors, sorted by level, parents first.
+ * On success *out owns a plan to release with apm_plan_destroy.
+ * Errors: APM_ERR_INVALID (descriptor / nesting), APM_ERR_RANGE (FFT length
+ * beyond 1024 or index space beyond int32). */
+apm_status apm_plan_create(const apm_config* cfg, const apm_grid* grids, int32_t ngrids,
+                           apm_plan* out);
+apm_status apm_plan_destroy(apm_plan plan);
+int32_t apm_plan_nlevels(apm_plan plan);                     /* -1 if plan is NULL */
+int32_t apm_plan_ngrids(apm_plan plan);
+apm_status apm_plan_grid(apm_plan plan, int32_t grid, apm_grid_layout* out);
+apm_status apm_plan_level(apm_plan plan, int32_t level, apm_level_layout* out);
+
+/* Thread-local description of the last error of this thread; never NULL. */
+const char* apm_last_error(void);
+
+/* -------------------------------------------------------------- device side -- */
+
+/* Bind a copy of `plan` to HIP device `device` and stream `stream` (a
+ * hipStream_t, NULL = default stream).  Allocates the workspace lazily.
+ * Errors: APM_ERR_DEVICE when no device is visible or it cannot be used. */
+apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out);
+apm_status apm_destroy(apm_ctx ctx);
+apm_status apm_set_stream(apm_ctx ctx, void* stream);
+
+/* Finest grid whose active box holds each particle, lowest index among grids of
+ * that level; -1 for particles with a coordinate outside [0,1) or NaN.
+ * Owner of the TSC interpolation (Sec. 3.1, 3.2: particles take the force of the
+ * grid they live on).  x, y, z: npart values; owner: npart int32 (device). */
+apm_status apm_owner(apm_ctx ctx, apm_dtype dtype, const void* x, const void* y,
+                     const void* z, int64_t npart, int32_t* owner);
+
+/* GravitatingMassField of every grid of `level` (Sec. 2): the TSC density
+ * sum_p m_p W(x_c - x_p) / dx^3 of every in-domain particle whose cloud overlaps
+ * the grid's GMF box (clouds clipped at the box; the modified deposition of Sec. 2
+ * that also takes the parent's and its siblings' particles), plus gas: `gas` on
+ * active cells, `parent_gas` copied piecewise-constant onto the ghost cells.
+ *   x, y, z, m  npart positions (box units) and masses
+ *   gas         packed active-gas buffer of `level` or NULL (no own gas)
+ *   parent_gas  packed active-gas buffer of level-1 or NULL (no ghost gas)
+ *   gmf         out: packed GMF buffer of `level` (gmf_elems scalars)
+ * Accumulation is compensated (Kahan) in the dtype's precision. */
+apm_status apm_deposit(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* x,
+                       const void* y, const void* z, const void* m, int64_t npart,
+                       const void* gas, const void* parent_gas, void* gmf);
+
+/* Own field of every grid of `level` (Sec. 2.2, Eq. 2, 5-9): the GMF zero-padded to
+ * the FFT box, transformed, multiplied by the level's influence functions and
+ * transformed back, the three acceleration components differenced in Fourier
+ * space (a_i = IDFT(-i d_i G_force rho_hat)) and the potential with the
+ * potential-optimal kernel (Phi = IDFT(G_pot rho_hat)).  Root: isolated boundary
+ * on the doubled mesh; subgrids: short-range reference S_l^2 - S_{l-1}^2.
+ *   gmf    packed GMF buffer of `level` (input, not modified)
+ *   field  out: packed field buffer of `level`, 4 values per cell
+ * The Green's functions are generated in FP64 on the device on first use and
+ * cached (Sec. 2.2: cached Green's functions). */
+apm_status apm_solve_level(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* gmf,
+                           void* field);
+
+/* Composition with the parent (Sec. 2.2): on every cell of the field boxes of
+ * `level`, field = own + P(parent_field), P = trilinear interpolation between
+ * cell centres.  At level 0 parent_field must be NULL and field = own.
+ * own and field may be the same buffer. */
+apm_status apm_accel(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* own,
+                     const void* parent_field, void* field);
+
+/* TSC interpolation (same weights as the deposit) of the composed field of
+ * `level` to the particles whose owner grid is on `level`; writes a_x, a_y, a_z
+ * and Phi of those particles only (others untouched).  pot may be NULL. */
+apm_status apm_interp(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* field,
+                      const void* x, const void* y, const void* z, const int32_t* owner,
+                      int64_t npart, void* ax, void* ay, void* az, void* pot);
+
+/* FP64 totals.  out[0 .. nlevels-1]: deposited mass per level (sum over the level's
+ * GMF cells of rho dx^3, i.e. particles + gas, clouds clipped);
+ * out[nlevels + 0] = 1/2 sum_p m_p Phi_p over owned particles,
+ * out[nlevels + 1..3] = sum_p m_p a_p over owned particles.
+ * gmf: host array of nlevels device pointers; m, ax, ay, az, pot, owner as above.
+ * Synchronises the stream (results are on the host on return). */
+apm_status apm_totals(apm_ctx ctx, apm_dtype dtype, const void* const* gmf, const void* m,
+                      const int32_t* owner, int64_t npart, const void* ax, const void* ay,
+                      const void* az, const void* pot, double* out);
+
+/* The whole forward solve in one call: owner, deposit, solve, composition and
+ * interpolation of every level, in the paper's order, into library-owned level
+ * buffers.  gas: host array of nlevels device pointers (or NULL entries / NULL).
+ * ax, ay, az, pot: npart outputs (pot may be NULL).  Fields of level l can be
+ * read back with apm_field_ptr after the call. */
+apm_status apm_solve(apm_ctx ctx, apm_dtype dtype, const void* x, const void* y,
+                     const void* z, const void* m, int64_t npart, const void* const* gas,
+                     void* ax, void* ay, void* az, void* pot);
+
+/* apm_totals over the library-owned GMFs and owner grids of the last apm_solve of
+ * `dtype` (same outputs and synchronisation); m, ax, ay, az, pot as passed to it. */
+apm_status apm_solve_totals(apm_ctx ctx, apm_dtype dtype, const void* m, int64_t npart,
+                            const void* ax, const void* ay, const void* az, const void* pot,
+                            double* out);
+
+/* Device pointer to the library-owned composed field (or GMF) of `level` written
+ * by the last apm_solve; NULL on error. */
+const void* apm_field_ptr(apm_ctx ctx, apm_dtype dtype, int32_t level);
+const void* apm_gmf_ptr(apm_ctx ctx, apm_dtype dtype, int32_t level);
+
+/* ------------------------------------------------------- kernel timing ------ */
+
+/* Measurement support: while enabled (enable != 0), every kernel launch of the
+ * compute calls is bracketed by HIP events recorded on the context's stream, and
+ * the elapsed times are accumulated per kernel name (e.g. "fft_z_conv",
+ * "deposit").  Enabling clears previous totals; disabling keeps them for reading.
+ * The events add a few microseconds per launch, so leave it off for timing whole
+ * steps. */
+apm_status apm_profile(apm_ctx ctx, int32_t enable);
+/* Number of kernel names with accumulated time (waits for pending events); -1 on
+ * error. */
+int32_t apm_profile_count(apm_ctx ctx);
+/* Name (NUL-terminated, truncated to cap bytes), total milliseconds and launch
+ * count of the i-th kernel name, i < apm_profile_count. */
+apm_status apm_profile_entry(apm_ctx ctx, int32_t i, char* name, int32_t cap, double* total_ms,
+                             int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APM_H */

@@ -1,0 +1,53 @@
+"""Build libapm.so (HIP, gfx950) in-tree: each source compiled in parallel, then
+linked.  Used by __graft_entry__.build() and by developers:
+
+    python -m paper_1410_0010_amd.build
+"""
+
+import concurrent.futures
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libapm.so")
+SOURCES = ["plan.cpp", "fft.hip", "greens.hip", "particles.hip", "field.hip", "api.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-command-line-argument"]
+
+
+def _run(cmd):
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in p.stdout.splitlines() if "packed-fp32-ops" not in l)
+    return p.returncode, out
+
+
+def build(verbose: bool = False) -> str:
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src + ".o")
+        jobs.append((obj, [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
+        results = list(ex.map(lambda j: _run(j[1]), jobs))
+    for (obj, cmd), (rc, out) in zip(jobs, results):
+        if verbose and out.strip():
+            print(out)
+        if rc != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{out}")
+    tmp = LIB + ".tmp"
+    rc, out = _run([HIPCC] + FLAGS + ["-shared", "-o", tmp] + [j[0] for j in jobs])
+    if rc != 0:
+        raise RuntimeError(f"link failed\n{out}")
+    os.replace(tmp, LIB)
+    shutil.rmtree(objdir, ignore_errors=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

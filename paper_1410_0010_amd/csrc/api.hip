@@ -1,0 +1,750 @@
+// C ABI of the device side: context, workspace, cached Green's functions and the
+// hot-path entry points declared in include/apm.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "apm_kernels.hpp"
+
+using namespace apm;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+constexpr double kPiD = 3.14159265358979323846;
+
+}  // namespace
+
+struct apm_ctx_s {
+  Plan plan;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t used = 0;
+  GridDesc* d_grids = nullptr;
+  std::vector<int64_t*> d_dep_begin, d_cmp_begin;
+  std::vector<int64_t> dep_blocks, cmp_blocks;
+  std::map<std::pair<int, int>, void*> tw;                        // (dtype, L)
+  std::map<std::tuple<int, int, int>, void*> dsym;                // (dtype, level, M)
+  std::map<std::tuple<int, int, int, int, int>, void*> kern;      // (dtype, level, Mx, My, Mz)
+  std::vector<void*> owned;                                       // every table allocation
+  DevBuf count, items, accum, keyb, rank, scan_tmp, spec, out, tmpfld, owner, totals, bin_totals;
+  std::vector<DevBuf> sorted, sidx;                               // per level
+  std::vector<int64_t> tile_total_slot;                           // per level: count index of total
+  std::vector<DevBuf> gmf[3], fld[3];                             // solve-owned, by dtype
+  size_t spec_elems = 0, out_elems = 0;                           // complex elements (max)
+  // kernel timing: events around every launch while enabled
+  struct Mark { std::string name; hipEvent_t a, b; };
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_next = 0;
+  hipEvent_t ev_open = nullptr;
+  std::vector<Mark> marks;
+  std::vector<std::string> prof_names;
+  std::map<std::string, std::pair<double, int64_t>> prof_acc;
+};
+
+namespace {
+
+apm_status hip_fail(hipError_t e, const char* where) {
+  std::ostringstream s;
+  s << where << ": " << hipGetErrorString(e);
+  return fail(APM_ERR_DEVICE, s.str());
+}
+
+#define HIP_TRY(expr, where)                       \
+  do {                                             \
+    hipError_t _e = (expr);                        \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+#define APM_TRY(expr)                  \
+  do {                                 \
+    apm_status _s = (expr);            \
+    if (_s != APM_OK) return _s;       \
+  } while (0)
+
+apm_status dev_alloc(apm_ctx c, void** p, size_t bytes, const char* what) {
+  if (c->plan.cfg.workspace_limit > 0 && c->used + bytes > (size_t)c->plan.cfg.workspace_limit) {
+    std::ostringstream s;
+    s << what << ": workspace limit " << c->plan.cfg.workspace_limit << " B exceeded";
+    return fail(APM_ERR_OOM, s.str());
+  }
+  hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    std::ostringstream s;
+    s << what << ": hipMalloc(" << bytes << ") failed: " << hipGetErrorString(e);
+    return fail(APM_ERR_OOM, s.str());
+  }
+  c->used += bytes;
+  return APM_OK;
+}
+
+apm_status ensure(apm_ctx c, DevBuf& b, size_t bytes, const char* what) {
+  if (b.p && b.bytes >= bytes) return APM_OK;
+  if (b.p) {
+    HIP_TRY(hipStreamSynchronize(c->stream), "ensure: sync");
+    HIP_TRY(hipFree(b.p), "ensure: free");
+    c->used -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  APM_TRY(dev_alloc(c, &b.p, bytes, what));
+  b.bytes = bytes;
+  return APM_OK;
+}
+
+apm_status upload(apm_ctx c, void** dst, const void* src, size_t bytes, const char* what) {
+  APM_TRY(dev_alloc(c, dst, bytes, what));
+  c->owned.push_back(*dst);
+  HIP_TRY(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), what);
+  return APM_OK;
+}
+
+size_t esize(apm_dtype t) { return t == APM_F32 ? 4 : 8; }
+
+apm_status check_dtype(apm_dtype t) {
+  if (t != APM_F32 && t != APM_F64) return fail(APM_ERR_INVALID, "dtype must be APM_F32 or APM_F64");
+  return APM_OK;
+}
+
+apm_status check_ctx(apm_ctx c) {
+  if (!c) return fail(APM_ERR_INVALID, "NULL context");
+  HIP_TRY(hipSetDevice(c->device), "hipSetDevice");
+  return APM_OK;
+}
+
+apm_status check_level(apm_ctx c, int32_t level) {
+  if (level < 0 || level >= (int32_t)c->plan.levels.size())
+    return fail(APM_ERR_INVALID, "level out of range");
+  return APM_OK;
+}
+
+hipEvent_t next_event(apm_ctx c) {
+  if (c->ev_next == c->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_next++];
+}
+
+void prof_hook(void* user, const char* name, int phase) {
+  apm_ctx c = (apm_ctx)user;
+  if (!c->prof_on) return;
+  hipEvent_t e = next_event(c);
+  if (!e) return;
+  (void)hipEventRecord(e, c->stream);
+  if (phase == 0) {
+    c->ev_open = e;
+  } else if (c->ev_open) {
+    c->marks.push_back({name, c->ev_open, e});
+    c->ev_open = nullptr;
+  }
+}
+
+LaunchHook hook_of(apm_ctx c) {
+  LaunchHook h;
+  if (c->prof_on) { h.fn = prof_hook; h.user = c; }
+  return h;
+}
+
+// time one launcher call under `name`
+template <typename F>
+hipError_t timed(apm_ctx c, const char* name, F&& f) {
+  LaunchHook h = hook_of(c);
+  h(name, 0);
+  hipError_t e = f();
+  h(name, 1);
+  return e;
+}
+
+apm_status prof_collect(apm_ctx c) {
+  for (auto& m : c->marks) {
+    HIP_TRY(hipEventSynchronize(m.b), "profile sync");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, m.a, m.b), "profile elapsed");
+    auto& a = c->prof_acc[m.name];
+    a.first += ms;
+    a.second += 1;
+  }
+  c->marks.clear();
+  c->ev_next = 0;
+  c->prof_names.clear();
+  for (auto& kv : c->prof_acc) c->prof_names.push_back(kv.first);
+  return APM_OK;
+}
+
+// twiddles exp(-2 pi i q / L), q < L, computed in FP64 on the host
+template <typename T>
+apm_status twiddles(apm_ctx c, int L, const void** out) {
+  auto key = std::make_pair((int)sizeof(T), L);
+  auto it = c->tw.find(key);
+  if (it != c->tw.end()) { *out = it->second; return APM_OK; }
+  std::vector<C2<T>> h(L);
+  for (int q = 0; q < L; ++q) {
+    const double a = -2.0 * kPiD * (double)q / (double)L;
+    h[q].x = (T)std::cos(a);
+    h[q].y = (T)std::sin(a);
+  }
+  void* d = nullptr;
+  APM_TRY(upload(c, &d, h.data(), sizeof(C2<T>) * L, "twiddles"));
+  c->tw[key] = d;
+  *out = d;
+  return APM_OK;
+}
+
+// gradient symbols d(m), m in [0, M): k or sin(k dx)/dx for signed m, 0 at M/2
+template <typename T>
+apm_status grad_symbols(apm_ctx c, int level, int M, double dx, const T** out) {
+  auto key = std::make_tuple((int)sizeof(T), level, M);
+  auto it = c->dsym.find(key);
+  if (it != c->dsym.end()) { *out = (const T*)it->second; return APM_OK; }
+  std::vector<T> h(M);
+  for (int m = 0; m < M; ++m) {
+    const int ms = m > M / 2 ? m - M : m;
+    const double k = 2.0 * kPiD * (double)ms / ((double)M * dx);
+    double d = c->plan.cfg.gradient == APM_GRAD_FD2 ? std::sin(k * dx) / dx : k;
+    if (2 * m == M) d = 0.0;
+    h[m] = (T)d;
+  }
+  void* d = nullptr;
+  APM_TRY(upload(c, &d, h.data(), sizeof(T) * M, "gradient symbols"));
+  c->dsym[key] = d;
+  *out = (const T*)d;
+  return APM_OK;
+}
+
+// FP64 octant table (Gf, Gp)/(Mx My Mz) of a grid shape; FP32 copy on request.
+apm_status kernel_table(apm_ctx c, apm_dtype dt, const GridDesc& g, const void** out) {
+  const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
+  auto k64 = std::make_tuple(8, g.level, Mx, My, Mz);
+  auto k32 = std::make_tuple(4, g.level, Mx, My, Mz);
+  if (dt == APM_F32) {
+    auto it = c->kern.find(k32);
+    if (it != c->kern.end()) { *out = it->second; return APM_OK; }
+  }
+  auto it64 = c->kern.find(k64);
+  const int64_t oct = (int64_t)(Mx / 2 + 1) * (My / 2 + 1) * (Mz / 2 + 1);
+  double2* t64 = nullptr;
+  if (it64 != c->kern.end()) {
+    t64 = (double2*)it64->second;
+  } else {
+    void* p = nullptr;
+    APM_TRY(dev_alloc(c, &p, sizeof(double2) * oct, "green's function table"));
+    c->owned.push_back(p);
+    t64 = (double2*)p;
+    const Plan& P = c->plan;
+    InfluenceParams ip{};
+    ip.Mx = Mx; ip.My = My; ip.Mz = Mz;
+    ip.dx = g.dx;
+    ip.a_l = P.cfg.a_cells * g.dx;
+    ip.a_lm1 = g.level == 0 ? -1.0 : P.cfg.a_cells * g.dx * 2.0;
+    ip.G = P.cfg.G;
+    ip.norm = 1.0 / ((double)Mx * My * Mz);
+    ip.bz = P.cfg.brillouin;
+    ip.grad = P.cfg.gradient;
+    ip.james = nullptr;
+    void *b0 = nullptr, *b1 = nullptr, *ct = nullptr;
+    if (g.level == 0) {
+      const int N = P.cfg.root_n;
+      const size_t on = (size_t)(N + 1) * (N + 1) * (N + 1);
+      std::vector<double> cosv(2 * N);
+      for (int q = 0; q < 2 * N; ++q) cosv[q] = std::cos(kPiD * (double)q / (double)N);
+      APM_TRY(dev_alloc(c, &b0, on * 8, "james buffer"));
+      APM_TRY(dev_alloc(c, &b1, on * 8, "james buffer"));
+      APM_TRY(dev_alloc(c, &ct, cosv.size() * 8, "cos table"));
+      HIP_TRY(hipMemcpy(ct, cosv.data(), cosv.size() * 8, hipMemcpyHostToDevice), "cos table");
+      double* res = nullptr;
+      HIP_TRY(launch_james(N, g.dx, ip.a_l, P.cfg.G, (const double*)ct, (double*)b0, (double*)b1,
+                           &res, c->stream), "james kernel");
+      ip.james = res;
+    }
+    HIP_TRY(launch_influence(ip, t64, c->stream), "influence kernel");
+    if (g.level == 0) {
+      HIP_TRY(hipStreamSynchronize(c->stream), "james sync");
+      for (void* q : {b0, b1, ct}) {
+        (void)hipFree(q);
+      }
+      c->used -= ((size_t)(P.cfg.root_n + 1) * (P.cfg.root_n + 1) * (P.cfg.root_n + 1) * 16 +
+                  (size_t)2 * P.cfg.root_n * 8);
+    }
+    c->kern[k64] = t64;
+  }
+  if (dt == APM_F64) { *out = t64; return APM_OK; }
+  void* p32 = nullptr;
+  APM_TRY(dev_alloc(c, &p32, sizeof(float2) * oct, "green's function table (fp32)"));
+  c->owned.push_back(p32);
+  HIP_TRY(launch_to_f32((const double*)t64, (float*)p32, 2 * oct, c->stream), "table to fp32");
+  c->kern[k32] = p32;
+  *out = p32;
+  return APM_OK;
+}
+
+template <typename T>
+apm_status solve_level_t(apm_ctx c, int32_t level, const T* gmf, T* field) {
+  const LevelDesc& L = c->plan.levels[level];
+  APM_TRY(ensure(c, c->spec, c->spec_elems * sizeof(C2<T>), "spectrum buffer"));
+  APM_TRY(ensure(c, c->out, c->out_elems * sizeof(C2<T>), "output spectra buffer"));
+  for (int32_t gi = L.first; gi < L.first + L.count; ++gi) {
+    const GridDesc& g = c->plan.grids[gi];
+    GridConv<T> j{};
+    j.gmf = gmf + g.gmf_offset;
+    for (int a = 0; a < 3; ++a) {
+      j.g[a] = g.gmf_n[a];
+      j.M[a] = g.M[a];
+      j.f[a] = g.fld_n[a];
+      j.off[a] = ((g.fld_lo[a] - g.gmf_lo[a]) % g.M[a] + g.M[a]) % g.M[a];
+    }
+    j.spec = (C2<T>*)c->spec.p;
+    j.out = (C2<T>*)c->out.p;
+    j.field = (V4<T>*)field + g.fld_offset;
+    APM_TRY(kernel_table(c, sizeof(T) == 4 ? APM_F32 : APM_F64, g, &j.kern));
+    for (int a = 0; a < 3; ++a) {
+      APM_TRY(grad_symbols<T>(c, g.level, g.M[a], g.dx, &j.dsym[a]));
+      APM_TRY(twiddles<T>(c, g.M[a], &j.tw[a]));
+    }
+    HIP_TRY(launch_grid_convolution<T>(j, c->stream, hook_of(c)), "convolution");
+  }
+  return APM_OK;
+}
+
+template <typename T>
+apm_status deposit_t(apm_ctx c, int32_t level, const T* x, const T* y, const T* z, const T* m,
+                     int64_t npart, const T* gas, const T* pgas, T* gmf) {
+  const LevelDesc& L = c->plan.levels[level];
+  const int64_t K = L.key_cells;
+  int32_t tn[3];
+  int64_t ntiles = 1;
+  for (int a = 0; a < 3; ++a) {
+    tn[a] = (L.key_n[a] + kTile - 1) / kTile;
+    ntiles *= tn[a];
+  }
+  // counter replicas per tile (blocks pick one by index): up to 16, about 2^18
+  // counters in all
+  int32_t rep = 1;
+  while (rep < 16 && ntiles * rep * 2 <= ((int64_t)1 << 18)) rep *= 2;
+  const int64_t ncount = ntiles * rep + 1;
+  APM_TRY(ensure(c, c->count, (size_t)ncount * 4, "tile counts"));
+  APM_TRY(ensure(c, c->items, (size_t)(ntiles + 1) * 4, "tile work items"));
+  APM_TRY(ensure(c, c->scan_tmp, scan_tmp_elems(ncount) * 4, "scan scratch"));
+  APM_TRY(ensure(c, c->accum, (size_t)K * 8, "fp64 mass grid"));
+  const size_t np = (size_t)std::max<int64_t>(npart, 1);
+  APM_TRY(ensure(c, c->keyb, np * 4, "particle keys"));
+  APM_TRY(ensure(c, c->rank, np * 4, "particle ranks"));
+  c->sorted.resize(c->plan.levels.size());
+  c->sidx.resize(c->plan.levels.size());
+  APM_TRY(ensure(c, c->sorted[level], np * sizeof(V4<T>), "sorted particles"));
+  APM_TRY(ensure(c, c->sidx[level], np * 4, "sorted particle indices"));
+  int32_t* count = (int32_t*)c->count.p;
+  int32_t* items = (int32_t*)c->items.p;
+  double* accum = (double*)c->accum.p;
+  HIP_TRY(timed(c, "bin_clear", [&] {
+            hipError_t e = launch_fill_i32(count, ncount, 0, c->stream);
+            return e != hipSuccess ? e : launch_fill_f64(accum, K, 0.0, c->stream);
+          }), "clear");
+  BinParams<T> bp{};
+  bp.x = x; bp.y = y; bp.z = z; bp.m = m;
+  bp.npart = npart;
+  bp.inv_dx = 1.0 / L.dx;
+  for (int a = 0; a < 3; ++a) {
+    bp.key_lo[a] = L.key_lo[a];
+    bp.key_n[a] = L.key_n[a];
+    bp.tiles_n[a] = tn[a];
+  }
+  bp.rep = rep;
+  bp.count = count;
+  bp.key = (int32_t*)c->keyb.p;
+  bp.rank = (int32_t*)c->rank.p;
+  bp.sidx = (int32_t*)c->sidx[level].p;
+  HIP_TRY(timed(c, "bin_count", [&] { return launch_bin_count<T>(bp, c->stream); }), "bin count");
+  HIP_TRY(timed(c, "bin_scan", [&] {
+            hipError_t e = launch_exclusive_scan(count, ncount, (int32_t*)c->scan_tmp.p, c->stream);
+            if (e == hipSuccess) e = launch_chunk_count(count, (int32_t)ntiles, rep, items, c->stream);
+            return e != hipSuccess ? e
+                                   : launch_exclusive_scan(items, ntiles + 1, (int32_t*)c->scan_tmp.p,
+                                                           c->stream);
+          }), "scan");
+  HIP_TRY(timed(c, "bin_scatter", [&] {
+            return launch_bin_scatter<T>(bp, count, (V4<T>*)c->sorted[level].p, c->stream);
+          }), "bin scatter");
+  APM_TRY(ensure(c, c->bin_totals, c->plan.levels.size() * 4, "binned totals"));
+  HIP_TRY(launch_copy_i32(count + (ncount - 1), (int32_t*)c->bin_totals.p + level, c->stream),
+          "binned total");
+  TileDepositParams<T> tp{};
+  tp.sorted = (const V4<T>*)c->sorted[level].p;
+  tp.start = count;
+  tp.item_start = items;
+  tp.ntiles = (int32_t)ntiles;
+  tp.rep = rep;
+  for (int a = 0; a < 3; ++a) { tp.key_n[a] = L.key_n[a]; tp.tiles_n[a] = tn[a]; }
+  tp.accum = accum;
+  const int64_t max_items = ntiles + (npart + kChunk - 1) / kChunk;
+  HIP_TRY(timed(c, "deposit_tiles", [&] { return launch_deposit_tiles<T>(tp, max_items, c->stream); }),
+          "deposit tiles");
+  DepositParams<T> dp{};
+  dp.grids = c->d_grids + L.first;
+  dp.block_begin = c->d_dep_begin[level];
+  dp.ngrids = L.count;
+  dp.accum = accum;
+  for (int a = 0; a < 3; ++a) { dp.key_lo[a] = L.key_lo[a]; dp.key_n[a] = L.key_n[a]; }
+  dp.dx = L.dx;
+  dp.gas = gas;
+  dp.parent_gas = pgas;
+  dp.gmf = gmf;
+  HIP_TRY(timed(c, "deposit_finalize", [&] {
+            return launch_deposit<T>(dp, c->dep_blocks[level], c->stream);
+          }), "deposit finalize");
+  return APM_OK;
+}
+
+template <typename T>
+__global__ void k_fill_t(T* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (T)0;
+}
+
+template <typename T>
+apm_status zero_t(apm_ctx c, T* p, int64_t n) {
+  if (!p || n == 0) return APM_OK;
+  hipLaunchKernelGGL((k_fill_t<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     c->stream, p, n);
+  HIP_TRY(hipGetLastError(), "zero fill");
+  return APM_OK;
+}
+
+template <typename T>
+apm_status solve_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, const T* m,
+                   int64_t npart, const void* const* gas, T* ax, T* ay, T* az, T* pot) {
+  const Plan& P = c->plan;
+  const int nl = (int)P.levels.size();
+  const int di = (int)dt;
+  c->gmf[di].resize(nl);
+  c->fld[di].resize(nl);
+  size_t maxfld = 0;
+  for (int l = 0; l < nl; ++l) {
+    APM_TRY(ensure(c, c->gmf[di][l], (size_t)P.levels[l].gmf_elems * sizeof(T), "level gmf"));
+    APM_TRY(ensure(c, c->fld[di][l], (size_t)P.levels[l].fld_cells * sizeof(V4<T>), "level field"));
+    maxfld = std::max(maxfld, (size_t)P.levels[l].fld_cells * sizeof(V4<T>));
+  }
+  APM_TRY(ensure(c, c->tmpfld, maxfld, "own field scratch"));
+  APM_TRY(ensure(c, c->owner, (size_t)std::max<int64_t>(npart, 1) * 4, "owner"));
+  int32_t* own = (int32_t*)c->owner.p;
+  HIP_TRY(timed(c, "owner", [&] {
+            return launch_owner<T>(c->d_grids, (int32_t)P.grids.size(), (double)P.cfg.root_n, x, y,
+                                   z, npart, own, c->stream);
+          }), "owner");
+  for (int l = 0; l < nl; ++l) {
+    const T* g = gas ? (const T*)gas[l] : nullptr;
+    const T* pg = (gas && l > 0) ? (const T*)gas[l - 1] : nullptr;
+    APM_TRY(deposit_t<T>(c, l, x, y, z, m, npart, g, pg, (T*)c->gmf[di][l].p));
+  }
+  for (int l = 0; l < nl; ++l) {
+    APM_TRY(solve_level_t<T>(c, l, (const T*)c->gmf[di][l].p, (T*)c->tmpfld.p));
+    const LevelDesc& L = P.levels[l];
+    HIP_TRY(timed(c, "compose", [&] {
+              return launch_compose<T>(c->d_grids + L.first, c->d_cmp_begin[l], L.count,
+                                       (const V4<T>*)c->tmpfld.p,
+                                       l > 0 ? (const V4<T>*)c->fld[di][l - 1].p : nullptr,
+                                       (V4<T>*)c->fld[di][l].p, c->cmp_blocks[l], c->stream);
+            }), "compose");
+  }
+  FieldTable<T> ft{};
+  for (int l = 0; l < nl && l < kMaxLevels; ++l) ft.f[l] = (const V4<T>*)c->fld[di][l].p;
+  HIP_TRY(timed(c, "interp", [&] {
+            return launch_interp_all<T>(c->d_grids, ft, x, y, z, own, npart, ax, ay, az, pot,
+                                        c->stream);
+          }), "interp");
+  return APM_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI ==========
+
+extern "C" {
+
+apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out) {
+  if (!plan || !out) return fail(APM_ERR_INVALID, "apm_create: NULL argument");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return fail(APM_ERR_DEVICE, "apm_create: no HIP device visible");
+  }
+  if (device < 0 || device >= n) return fail(APM_ERR_DEVICE, "apm_create: device index out of range");
+  HIP_TRY(hipSetDevice(device), "apm_create: hipSetDevice");
+  apm_ctx c = new (std::nothrow) apm_ctx_s;
+  if (!c) return fail(APM_ERR_OOM, "apm_create: host allocation failed");
+  c->plan = plan->plan;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  const Plan& P = c->plan;
+  apm_status st = upload(c, (void**)&c->d_grids, P.grids.data(), sizeof(GridDesc) * P.grids.size(),
+                         "grid table");
+  if (st != APM_OK) { apm_destroy(c); return st; }
+  for (const LevelDesc& L : P.levels) {
+    std::vector<int64_t> dep(L.count + 1), cmp(L.count + 1);
+    dep[0] = cmp[0] = 0;
+    for (int i = 0; i < L.count; ++i) {
+      const GridDesc& g = P.grids[L.first + i];
+      const int64_t gc = (int64_t)g.gmf_n[0] * g.gmf_n[1] * g.gmf_n[2];
+      const int64_t fc = (int64_t)g.fld_n[0] * g.fld_n[1] * g.fld_n[2];
+      dep[i + 1] = dep[i] + (gc + kBlock - 1) / kBlock;
+      cmp[i + 1] = cmp[i] + (fc + kBlock - 1) / kBlock;
+      const int64_t W = g.M[0] / 2 + 1;
+      c->spec_elems = std::max(c->spec_elems, (size_t)(g.gmf_n[2] * (int64_t)g.M[1] * W));
+      c->out_elems = std::max(c->out_elems, (size_t)(4 * (int64_t)g.fld_n[2] * g.M[1] * W));
+    }
+    void *d1 = nullptr, *d2 = nullptr;
+    st = upload(c, &d1, dep.data(), dep.size() * 8, "deposit block table");
+    if (st == APM_OK) st = upload(c, &d2, cmp.data(), cmp.size() * 8, "compose block table");
+    if (st != APM_OK) { apm_destroy(c); return st; }
+    c->d_dep_begin.push_back((int64_t*)d1);
+    c->d_cmp_begin.push_back((int64_t*)d2);
+    c->dep_blocks.push_back(dep.back());
+    c->cmp_blocks.push_back(cmp.back());
+  }
+  *out = c;
+  clear_error();
+  return APM_OK;
+}
+
+apm_status apm_destroy(apm_ctx c) {
+  if (!c) return APM_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (void* p : c->owned) (void)hipFree(p);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  DevBuf* bufs[] = {&c->count, &c->items, &c->accum, &c->keyb, &c->rank,
+                    &c->scan_tmp, &c->spec, &c->out, &c->tmpfld, &c->owner, &c->totals,
+                    &c->bin_totals};
+  for (auto& b : c->sorted) if (b.p) (void)hipFree(b.p);
+  for (auto& b : c->sidx) if (b.p) (void)hipFree(b.p);
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  for (auto& v : c->gmf)
+    for (auto& b : v) if (b.p) (void)hipFree(b.p);
+  for (auto& v : c->fld)
+    for (auto& b : v) if (b.p) (void)hipFree(b.p);
+  delete c;
+  return APM_OK;
+}
+
+apm_status apm_set_stream(apm_ctx c, void* stream) {
+  APM_TRY(check_ctx(c));
+  c->stream = (hipStream_t)stream;
+  return APM_OK;
+}
+
+apm_status apm_owner(apm_ctx c, apm_dtype dt, const void* x, const void* y, const void* z,
+                     int64_t npart, int32_t* owner) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (npart < 0 || npart > INT32_MAX) return fail(APM_ERR_RANGE, "apm_owner: npart out of range");
+  if (npart > 0 && (!x || !y || !z || !owner)) return fail(APM_ERR_INVALID, "apm_owner: NULL array");
+  const Plan& P = c->plan;
+  hipError_t e = dt == APM_F32
+      ? launch_owner<float>(c->d_grids, (int32_t)P.grids.size(), (double)P.cfg.root_n,
+                            (const float*)x, (const float*)y, (const float*)z, npart, owner, c->stream)
+      : launch_owner<double>(c->d_grids, (int32_t)P.grids.size(), (double)P.cfg.root_n,
+                             (const double*)x, (const double*)y, (const double*)z, npart, owner,
+                             c->stream);
+  HIP_TRY(e, "apm_owner");
+  return APM_OK;
+}
+
+apm_status apm_deposit(apm_ctx c, apm_dtype dt, int32_t level, const void* x, const void* y,
+                       const void* z, const void* m, int64_t npart, const void* gas,
+                       const void* parent_gas, void* gmf) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  APM_TRY(check_level(c, level));
+  if (npart < 0 || npart > INT32_MAX) return fail(APM_ERR_RANGE, "apm_deposit: npart out of range");
+  if (!gmf || (npart > 0 && (!x || !y || !z || !m)))
+    return fail(APM_ERR_INVALID, "apm_deposit: NULL array");
+  if (level == 0 && parent_gas) return fail(APM_ERR_INVALID, "apm_deposit: root has no parent gas");
+  if (dt == APM_F32)
+    return deposit_t<float>(c, level, (const float*)x, (const float*)y, (const float*)z,
+                            (const float*)m, npart, (const float*)gas, (const float*)parent_gas,
+                            (float*)gmf);
+  return deposit_t<double>(c, level, (const double*)x, (const double*)y, (const double*)z,
+                           (const double*)m, npart, (const double*)gas, (const double*)parent_gas,
+                           (double*)gmf);
+}
+
+apm_status apm_solve_level(apm_ctx c, apm_dtype dt, int32_t level, const void* gmf, void* field) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  APM_TRY(check_level(c, level));
+  if (!gmf || !field) return fail(APM_ERR_INVALID, "apm_solve_level: NULL array");
+  if (dt == APM_F32) return solve_level_t<float>(c, level, (const float*)gmf, (float*)field);
+  return solve_level_t<double>(c, level, (const double*)gmf, (double*)field);
+}
+
+apm_status apm_accel(apm_ctx c, apm_dtype dt, int32_t level, const void* own,
+                     const void* parent_field, void* field) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  APM_TRY(check_level(c, level));
+  if (!own || !field) return fail(APM_ERR_INVALID, "apm_accel: NULL array");
+  if (level == 0 && parent_field) return fail(APM_ERR_INVALID, "apm_accel: root has no parent");
+  if (level > 0 && !parent_field) return fail(APM_ERR_STATE, "apm_accel: parent field required");
+  const LevelDesc& L = c->plan.levels[level];
+  hipError_t e = dt == APM_F32
+      ? launch_compose<float>(c->d_grids + L.first, c->d_cmp_begin[level], L.count,
+                              (const float4*)own, (const float4*)parent_field, (float4*)field,
+                              c->cmp_blocks[level], c->stream)
+      : launch_compose<double>(c->d_grids + L.first, c->d_cmp_begin[level], L.count,
+                               (const double4*)own, (const double4*)parent_field, (double4*)field,
+                               c->cmp_blocks[level], c->stream);
+  HIP_TRY(e, "apm_accel");
+  return APM_OK;
+}
+
+apm_status apm_interp(apm_ctx c, apm_dtype dt, int32_t level, const void* field, const void* x,
+                      const void* y, const void* z, const int32_t* owner, int64_t npart, void* ax,
+                      void* ay, void* az, void* pot) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  APM_TRY(check_level(c, level));
+  if (npart < 0 || npart > INT32_MAX) return fail(APM_ERR_RANGE, "apm_interp: npart out of range");
+  if (npart > 0 && (!field || !x || !y || !z || !owner || !ax || !ay || !az))
+    return fail(APM_ERR_INVALID, "apm_interp: NULL array");
+  hipError_t e = dt == APM_F32
+      ? launch_interp<float>(c->d_grids, level, (const float4*)field, (const float*)x,
+                             (const float*)y, (const float*)z, owner, npart, (float*)ax,
+                             (float*)ay, (float*)az, (float*)pot, c->stream)
+      : launch_interp<double>(c->d_grids, level, (const double4*)field, (const double*)x,
+                              (const double*)y, (const double*)z, owner, npart, (double*)ax,
+                              (double*)ay, (double*)az, (double*)pot, c->stream);
+  HIP_TRY(e, "apm_interp");
+  return APM_OK;
+}
+
+apm_status apm_totals(apm_ctx c, apm_dtype dt, const void* const* gmf, const void* m,
+                      const int32_t* owner, int64_t npart, const void* ax, const void* ay,
+                      const void* az, const void* pot, double* out) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (!out || !gmf) return fail(APM_ERR_INVALID, "apm_totals: NULL argument");
+  if (npart < 0) return fail(APM_ERR_RANGE, "apm_totals: npart < 0");
+  if (npart > 0 && (!m || !owner || !ax || !ay || !az))
+    return fail(APM_ERR_INVALID, "apm_totals: NULL particle array");
+  const Plan& P = c->plan;
+  const int nl = (int)P.levels.size();
+  APM_TRY(ensure(c, c->totals, (size_t)(nl + 4 + 4 * kMaxParts) * 8, "totals"));
+  double* d = (double*)c->totals.p;
+  double* part = d + nl + 4;
+  HIP_TRY(launch_fill_f64(d, nl + 4, 0.0, c->stream), "totals fill");
+  for (int l = 0; l < nl; ++l) {
+    if (!gmf[l]) return fail(APM_ERR_INVALID, "apm_totals: NULL gmf pointer");
+    const double v = P.levels[l].dx * P.levels[l].dx * P.levels[l].dx;
+    hipError_t e = dt == APM_F32
+        ? launch_sum_scaled<float>((const float*)gmf[l], P.levels[l].gmf_elems, v, part, d + l,
+                                   c->stream)
+        : launch_sum_scaled<double>((const double*)gmf[l], P.levels[l].gmf_elems, v, part, d + l,
+                                    c->stream);
+    HIP_TRY(e, "totals mass");
+  }
+  hipError_t e = dt == APM_F32
+      ? launch_particle_totals<float>((const float*)m, owner, npart, (const float*)ax,
+                                      (const float*)ay, (const float*)az, (const float*)pot, part,
+                                      d + nl, c->stream)
+      : launch_particle_totals<double>((const double*)m, owner, npart, (const double*)ax,
+                                       (const double*)ay, (const double*)az, (const double*)pot,
+                                       part, d + nl, c->stream);
+  HIP_TRY(e, "totals particles");
+  HIP_TRY(hipMemcpyAsync(out, d, (size_t)(nl + 4) * 8, hipMemcpyDeviceToHost, c->stream), "totals copy");
+  HIP_TRY(hipStreamSynchronize(c->stream), "totals sync");
+  return APM_OK;
+}
+
+apm_status apm_solve(apm_ctx c, apm_dtype dt, const void* x, const void* y, const void* z,
+                     const void* m, int64_t npart, const void* const* gas, void* ax, void* ay,
+                     void* az, void* pot) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (npart < 0 || npart > INT32_MAX) return fail(APM_ERR_RANGE, "apm_solve: npart out of range");
+  if (npart > 0 && (!x || !y || !z || !m || !ax || !ay || !az))
+    return fail(APM_ERR_INVALID, "apm_solve: NULL array");
+  if (dt == APM_F32)
+    return solve_t<float>(c, dt, (const float*)x, (const float*)y, (const float*)z, (const float*)m,
+                          npart, gas, (float*)ax, (float*)ay, (float*)az, (float*)pot);
+  return solve_t<double>(c, dt, (const double*)x, (const double*)y, (const double*)z,
+                         (const double*)m, npart, gas, (double*)ax, (double*)ay, (double*)az,
+                         (double*)pot);
+}
+
+apm_status apm_solve_totals(apm_ctx c, apm_dtype dt, const void* m, int64_t npart,
+                            const void* ax, const void* ay, const void* az, const void* pot,
+                            double* out) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  const int nl = (int)c->plan.levels.size();
+  if ((int)c->gmf[(int)dt].size() != nl || !c->owner.p ||
+      c->owner.bytes < (size_t)std::max<int64_t>(npart, 1) * 4)
+    return fail(APM_ERR_STATE, "apm_solve_totals: no apm_solve of this dtype/size yet");
+  std::vector<const void*> g(nl);
+  for (int l = 0; l < nl; ++l) g[l] = c->gmf[(int)dt][l].p;
+  return apm_totals(c, dt, g.data(), m, (const int32_t*)c->owner.p, npart, ax, ay, az, pot, out);
+}
+
+const void* apm_field_ptr(apm_ctx c, apm_dtype dt, int32_t level) {
+  if (!c || (dt != APM_F32 && dt != APM_F64) || level < 0 ||
+      level >= (int32_t)c->fld[(int)dt].size())
+    return nullptr;
+  return c->fld[(int)dt][level].p;
+}
+
+apm_status apm_profile(apm_ctx c, int32_t enable) {
+  APM_TRY(check_ctx(c));
+  if (enable) {
+    APM_TRY(prof_collect(c));
+    c->prof_acc.clear();
+    c->prof_names.clear();
+    c->prof_on = true;
+  } else {
+    c->prof_on = false;
+    APM_TRY(prof_collect(c));
+  }
+  return APM_OK;
+}
+
+int32_t apm_profile_count(apm_ctx c) {
+  if (!c || check_ctx(c) != APM_OK || prof_collect(c) != APM_OK) return -1;
+  return (int32_t)c->prof_names.size();
+}
+
+apm_status apm_profile_entry(apm_ctx c, int32_t i, char* name, int32_t cap, double* total_ms,
+                             int64_t* launches) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(prof_collect(c));
+  if (i < 0 || i >= (int32_t)c->prof_names.size() || !name || cap < 1)
+    return fail(APM_ERR_INVALID, "apm_profile_entry: bad index or buffer");
+  const std::string& n = c->prof_names[i];
+  std::snprintf(name, (size_t)cap, "%s", n.c_str());
+  const auto& a = c->prof_acc[n];
+  if (total_ms) *total_ms = a.first;
+  if (launches) *launches = a.second;
+  return APM_OK;
+}
+
+const void* apm_gmf_ptr(apm_ctx c, apm_dtype dt, int32_t level) {
+  if (!c || (dt != APM_F32 && dt != APM_F64) || level < 0 ||
+      level >= (int32_t)c->gmf[(int)dt].size())
+    return nullptr;
+  return c->gmf[(int)dt][level].p;
+}
+
+}  // extern "C"

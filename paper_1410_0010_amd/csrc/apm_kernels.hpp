@@ -1,0 +1,139 @@
+// Launcher interfaces between the ABI layer and the kernels (all on one stream).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "apm_internal.hpp"
+#include "device_common.hpp"
+
+namespace apm {
+
+// One grid's convolution: GMF (dims g) zero-padded into FFT box M, outputs on the
+// field box (dims f) whose first cell sits at transform index off (cyclic).
+template <typename T> struct GridConv {
+  const T* gmf;
+  int g[3], M[3], f[3], off[3];
+  C2<T>* spec;            // g[2] * M[1] * (M[0]/2+1)
+  C2<T>* out;             // 4 * f[2] * M[1] * (M[0]/2+1)
+  void* field;            // f cells of V4<T>
+  const void* kern;       // octant (Gf, Gp) table of C2<T>
+  const T* dsym[3];       // gradient symbols per axis index
+  const void* tw[3];      // twiddle tables per axis length
+};
+// Optional timing hook called around every kernel launch (phase 0 before, 1 after).
+struct LaunchHook {
+  void (*fn)(void* user, const char* name, int phase) = nullptr;
+  void* user = nullptr;
+  void operator()(const char* name, int phase) const { if (fn) fn(user, name, phase); }
+};
+template <typename T> hipError_t launch_grid_convolution(const GridConv<T>& j, hipStream_t s,
+                                                         const LaunchHook& hook);
+
+// Green's functions (FP64): octant table of (force, potential) times `norm`.
+struct InfluenceParams {
+  int Mx, My, Mz;
+  double dx, a_l, a_lm1;   // a_lm1 < 0: root (S_{-1} = 0)
+  double G, norm;
+  int bz, grad;
+  const double* james;     // root only: octant of the doubled-mesh reference kernel
+};
+hipError_t launch_influence(const InfluenceParams& p, double2* out, hipStream_t s);
+hipError_t launch_james(int N, double dx, double a0, double G, const double* costab,
+                        double* buf0, double* buf1, double** result, hipStream_t s);
+hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+
+// Particles: binning by 8^3 tile of the particle's cell i0 = floor(x/dx) inside the
+// level's binning box (union of GMF boxes grown by one cell).
+constexpr int kTile = 8;
+constexpr int kChunk = 2048;       // particles per deposit work item
+template <typename T> struct BinParams {
+  const T* x; const T* y; const T* z; const T* m;
+  int64_t npart;
+  double inv_dx;
+  int32_t key_lo[3], key_n[3];     // binning box (cells)
+  int32_t tiles_n[3];              // tiles per axis
+  int32_t rep;                     // counter replicas per tile (power of two)
+  int32_t* count;                  // tiles * rep + 1 (zeroed by caller), scanned in place;
+                                   // replica r of tile t at t * rep + r
+  int32_t* key;                    // npart: counter slot or -1
+  int32_t* rank;                   // npart: rank within the slot
+  int32_t* sidx;                   // sorted position -> original index (written by scatter)
+};
+template <typename T> hipError_t launch_bin_count(const BinParams<T>& p, hipStream_t s);
+template <typename T> hipError_t launch_bin_scatter(const BinParams<T>& p, const int32_t* start,
+                                                    V4<T>* sorted, hipStream_t s);
+hipError_t launch_exclusive_scan(int32_t* data, int64_t n, int32_t* tmp, hipStream_t s);
+size_t scan_tmp_elems(int64_t n);
+// items[t] = ceil((start[(t+1) rep]-start[t rep]) / kChunk) for t < ntiles, items[ntiles] = 0
+hipError_t launch_chunk_count(const int32_t* start, int32_t ntiles, int32_t rep, int32_t* items,
+                              hipStream_t s);
+
+template <typename T> struct TileDepositParams {
+  const V4<T>* sorted;             // (s_x, s_y, s_z, m), s = x/dx - binning-box origin
+  const int32_t* start;            // scanned replica counts (ntiles * rep + 1)
+  const int32_t* item_start;       // scanned chunk counts (ntiles + 1)
+  int32_t ntiles, rep;
+  int32_t key_n[3], tiles_n[3];
+  double* accum;                   // key-box cells, FP64, zeroed by caller
+};
+template <typename T> hipError_t launch_deposit_tiles(const TileDepositParams<T>& p, int64_t max_items,
+                                                      hipStream_t s);
+
+template <typename T> struct DepositParams {
+  const GridDesc* grids;   // device copy of the level's grids
+  const int64_t* block_begin;  // device: first block of each grid (count + 1 entries)
+  int32_t ngrids;
+  const double* accum;     // FP64 mass per key-box cell
+  int32_t key_lo[3], key_n[3];
+  double dx;
+  const T* gas;            // level active gas (packed) or null
+  const T* parent_gas;     // parent level active gas (packed) or null
+  T* gmf;
+};
+template <typename T> hipError_t launch_deposit(const DepositParams<T>& p, int64_t nblocks,
+                                                hipStream_t s);
+
+template <typename T> hipError_t launch_owner(const GridDesc* grids, int32_t ngrids, double root_n,
+                                              const T* x, const T* y, const T* z, int64_t npart,
+                                              int32_t* owner, hipStream_t s);
+template <typename T> hipError_t launch_interp(const GridDesc* grids, int32_t level,
+                                               const V4<T>* field, const T* x, const T* y,
+                                               const T* z, const int32_t* owner, int64_t npart,
+                                               T* ax, T* ay, T* az, T* pot, hipStream_t s);
+// level `level` over the level's tile-sorted particles (sorted, sidx, total binned
+// count at *total); writes the particles whose owner grid is on that level.
+template <typename T> hipError_t launch_interp_sorted(const GridDesc* grids, int32_t level,
+                                                      const V4<T>* field, const V4<T>* sorted,
+                                                      const int32_t* sidx, const int32_t* total,
+                                                      int64_t max_n, const int32_t key_lo[3],
+                                                      const int32_t* owner, T* ax, T* ay, T* az,
+                                                      T* pot, hipStream_t s);
+// every level in one launch: fields[l] is level l's composed field
+constexpr int kMaxLevels = 21;
+template <typename T> struct FieldTable { const V4<T>* f[kMaxLevels]; };
+template <typename T> hipError_t launch_interp_all(const GridDesc* grids, const FieldTable<T>& fields,
+                                                   const T* x, const T* y, const T* z,
+                                                   const int32_t* owner, int64_t npart, T* ax,
+                                                   T* ay, T* az, T* pot, hipStream_t s);
+template <typename T> hipError_t launch_compose(const GridDesc* grids, const int64_t* block_begin,
+                                                int32_t ngrids, const V4<T>* own,
+                                                const V4<T>* parent, V4<T>* field,
+                                                int64_t nblocks, hipStream_t s);
+// Deterministic FP64 reductions: per-block partials (part, kMaxParts per quantity),
+// then one block sums them in a fixed order into out.
+constexpr int kMaxParts = 1024;
+template <typename T> hipError_t launch_sum_scaled(const T* a, int64_t n, double scale,
+                                                   double* part, double* out, hipStream_t s);
+template <typename T> hipError_t launch_particle_totals(const T* m, const int32_t* owner,
+                                                        int64_t npart, const T* ax, const T* ay,
+                                                        const T* az, const T* pot, double* part,
+                                                        double* out, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, hipStream_t s);  // one value
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+
+constexpr int kBlock = 256;
+
+}  // namespace apm

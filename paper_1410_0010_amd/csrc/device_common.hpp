@@ -1,0 +1,159 @@
+// Device-side helpers: complex arithmetic, small DFTs and the LDS Stockham FFT
+// used by every transform pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+namespace apm {
+
+template <typename T> struct vec;
+template <> struct vec<float> { using c2 = float2; using c4 = float4; };
+template <> struct vec<double> { using c2 = double2; using c4 = double4; };
+template <typename T> using C2 = typename vec<T>::c2;
+template <typename T> using V4 = typename vec<T>::c4;
+
+template <typename T> __device__ __forceinline__ C2<T> mk(T x, T y) { C2<T> r; r.x = x; r.y = y; return r; }
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { a.x += b.x; a.y += b.y; return a; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { a.x -= b.x; a.y -= b.y; return a; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  C r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+// a * conj(b)
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
+  C r; r.x = a.x * b.x + a.y * b.y; r.y = a.y * b.x - a.x * b.y; return r;
+}
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename C> __device__ __forceinline__ C rot90(C a) {
+  C r;
+  if (INV) { r.x = -a.y; r.y = a.x; } else { r.x = a.y; r.y = -a.x; }
+  return r;
+}
+
+template <int L> struct Log2 { static constexpr int v = 1 + Log2<L / 2>::v; };
+template <> struct Log2<1> { static constexpr int v = 0; };
+
+// ---- small DFTs in registers (sign -1 forward, +1 inverse) ----------------------
+template <bool INV, typename C> __device__ __forceinline__ void dft2(C* v) {
+  C a = v[0], b = v[1];
+  v[0] = cadd(a, b); v[1] = csub(a, b);
+}
+template <bool INV, typename C> __device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
+  C t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = rot90<INV>(csub(a1, a3));
+  a0 = cadd(t0, t2); a2 = csub(t0, t2); a1 = cadd(t1, t3); a3 = csub(t1, t3);
+}
+template <bool INV, typename C> __device__ __forceinline__ void dft4(C* v) { dft4<INV>(v[0], v[1], v[2], v[3]); }
+template <bool INV, typename T> __device__ __forceinline__ void dft8(C2<T>* v) {
+  // radix-2 split into even/odd 4-point DFTs, then combine with w8^k
+  C2<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  C2<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<INV>(e0, e1, e2, e3);
+  dft4<INV>(o0, o1, o2, o3);
+  const T h = (T)0.70710678118654752440;   // 1/sqrt(2)
+  // w8^1 = (1 -+ i)/sqrt2, w8^2 = -+i, w8^3 = (-1 -+ i)/sqrt2 (upper sign forward)
+  C2<T> t1, t3;
+  if (INV) {
+    t1 = mk<T>(h * (o1.x - o1.y), h * (o1.x + o1.y));
+    t3 = mk<T>(-h * (o3.x + o3.y), h * (o3.x - o3.y));
+  } else {
+    t1 = mk<T>(h * (o1.x + o1.y), h * (o1.y - o1.x));
+    t3 = mk<T>(h * (o3.y - o3.x), -h * (o3.x + o3.y));
+  }
+  C2<T> t2 = rot90<INV>(o2);
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1); v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2); v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3); v[7] = csub(e3, t3);
+}
+
+// ---- synchronisation between Stockham stages -------------------------------------
+// When a line's L/8 workers fit in one wavefront (L <= 512) its stages only exchange
+// data inside that wavefront: an LDS fence plus a wavefront barrier orders them, and
+// lines of other wavefronts are independent.  Longer lines need the block barrier.
+template <int L> __device__ __forceinline__ void stage_sync() {
+  if constexpr (L / 8 <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// ---- Stockham auto-sort radix stages on one line held in LDS --------------------
+// A line of L complex values; L/8 workers per line; each worker always handles
+// 8 values per stage: one radix-8, two radix-4 or four radix-2 butterflies.
+// Butterfly j of a stage with span NS reads line[j + r L/R], twiddles element r
+// by w_{NS R}^{r (j mod NS)}, transforms, and writes line[(j/NS) NS R + j mod NS
+// + r NS].  tw[q] = exp(-2 pi i q / L).
+template <typename T, int L, int R, int NS, bool INV>
+__device__ __forceinline__ void stockham_stage(C2<T>* line, int w, const C2<T>* __restrict__ tw) {
+  constexpr int B = 8 / R;
+  constexpr int W8 = L / 8;
+  C2<T> v[B][R];
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    const int j = w + q * W8;
+    const int k = j % NS;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[q][r] = line[j + r * (L / R)];
+    if (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C2<T> t = tw[(r * k) * (L / (NS * R))];
+        v[q][r] = INV ? cmulc(v[q][r], t) : cmul(v[q][r], t);
+      }
+    }
+    if (R == 8) dft8<INV, T>(v[q]);
+    else if (R == 4) dft4<INV>(v[q]);
+    else dft2<INV>(v[q]);
+  }
+  stage_sync<L>();
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    const int j = w + q * W8;
+    const int k = j % NS;
+    const int base = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) line[base + r * NS] = v[q][r];
+  }
+  stage_sync<L>();
+}
+
+template <typename T, int L, int NS, bool INV>
+__device__ __forceinline__ void radix8_stages(C2<T>* line, int w, const C2<T>* tw) {
+  if constexpr (NS < L) {
+    stockham_stage<T, L, 8, NS, INV>(line, w, tw);
+    radix8_stages<T, L, NS * 8, INV>(line, w, tw);
+  }
+}
+
+// Full in-place FFT of one LDS line.  Every worker of the line must call it; for
+// L > 512 it contains block barriers, so then every thread of the block must.
+// The caller orders the line's LDS contents before (block barrier after a load
+// with another thread mapping) and after it.  Unnormalised; INV: exp(+2 pi i ...).
+template <typename T, int L, bool INV>
+__device__ __forceinline__ void fft_line(C2<T>* line, int w, const C2<T>* tw) {
+  constexpr int p = Log2<L>::v;
+  constexpr int r0 = p % 3;
+  if constexpr (r0 == 1) {
+    stockham_stage<T, L, 2, 1, INV>(line, w, tw);
+    radix8_stages<T, L, 2, INV>(line, w, tw);
+  } else if constexpr (r0 == 2) {
+    stockham_stage<T, L, 4, 1, INV>(line, w, tw);
+    radix8_stages<T, L, 4, INV>(line, w, tw);
+  } else {
+    radix8_stages<T, L, 1, INV>(line, w, tw);
+  }
+}
+
+// Lines per block for a given element type and length: 4096 (FP32) or 2048
+// (FP64) complex values per block -> 32-33 KB of LDS, 256 or 512 threads.
+template <typename T, int L> struct FFTShape {
+  static constexpr int NL = (std::is_same<T, float>::value ? 4096 : 2048) / L;
+  static constexpr int NT = NL * (L / 8);
+  static constexpr int LS = L + 1;            // padded line stride in LDS
+};
+
+}  // namespace apm

@@ -1,0 +1,258 @@
+"""Python face of the APM library: a Plan (host-side hierarchy layout) and a Context
+(device, stream, cached Green's functions).  Every method is one call of the C ABI
+(include/apm.h) with torch tensors supplying device memory and the current stream;
+no arithmetic of the solve happens here.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _apm
+from ._apm import check
+
+_GRAD = {"spectral": _apm.APM_GRAD_SPECTRAL, "fd2": _apm.APM_GRAD_FD2}
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return _apm.APM_F32
+    if t.dtype == torch.float64:
+        return _apm.APM_F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Validated static hierarchy and its buffer layout (host only)."""
+
+    def __init__(self, root_n: int, grids: Sequence, G: float = 1.0, gradient: str = "spectral",
+                 a_cells: float = 3.4, pad_factor: float = 0.65, ghost: int = 3,
+                 brillouin: int = 1, workspace_limit: int = 0):
+        L = _apm.lib()
+        cfg = _apm.apm_config()
+        L.apm_config_default(ctypes.byref(cfg))
+        cfg.G = G
+        cfg.root_n = root_n
+        cfg.a_cells = a_cells
+        cfg.pad_factor = pad_factor
+        cfg.ghost = ghost
+        cfg.brillouin = brillouin
+        cfg.gradient = _GRAD[gradient]
+        cfg.workspace_limit = workspace_limit
+        arr = (_apm.apm_grid * len(grids))()
+        for i, g in enumerate(grids):
+            arr[i].level = g.level
+            arr[i].parent = g.parent
+            for a in range(3):
+                arr[i].lo[a] = g.lo[a]
+                arr[i].n[a] = g.n[a]
+        h = ctypes.c_void_p()
+        check(L.apm_plan_create(ctypes.byref(cfg), arr, len(grids), ctypes.byref(h)),
+              "apm_plan_create")
+        self.handle = h
+        self.cfg = cfg
+        self.nlevels = L.apm_plan_nlevels(h)
+        self.ngrids = L.apm_plan_ngrids(h)
+        self.grids = [self._grid(i) for i in range(self.ngrids)]
+        self.levels = [self._level(l) for l in range(self.nlevels)]
+
+    def _grid(self, i):
+        out = _apm.apm_grid_layout()
+        check(_apm.lib().apm_plan_grid(self.handle, i, ctypes.byref(out)), "apm_plan_grid")
+        d = {k: (list(getattr(out, k)) if isinstance(getattr(out, k), ctypes.Array)
+                 else getattr(out, k)) for k, _ in out._fields_}
+        d["index"] = i
+        return d
+
+    def _level(self, l):
+        out = _apm.apm_level_layout()
+        check(_apm.lib().apm_plan_level(self.handle, l, ctypes.byref(out)), "apm_plan_level")
+        return {k: getattr(out, k) for k, _ in out._fields_}
+
+    def level_grids(self, l):
+        return [g for g in self.grids if g["level"] == l]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _apm._LIB is not None:
+            _apm._LIB.apm_plan_destroy(h)
+            self.handle = None
+
+
+class Context:
+    """A plan bound to a HIP device and stream (torch's current stream by default)."""
+
+    def __init__(self, plan: Plan, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.plan = plan
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = ctypes.c_void_p()
+        check(_apm.lib().apm_create(plan.handle, device, ctypes.c_void_p(stream), ctypes.byref(h)),
+              "apm_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _apm._LIB is not None:
+            _apm._LIB.apm_destroy(h)
+            self.handle = None
+
+    # --- allocation helpers (torch device memory) ---------------------------------
+    def empty_gmf(self, level, dtype):
+        return self.torch.empty(self.plan.levels[level]["gmf_elems"], dtype=dtype, device=self.device)
+
+    def empty_field(self, level, dtype):
+        return self.torch.empty((self.plan.levels[level]["fld_cells"], 4), dtype=dtype,
+                                device=self.device)
+
+    def pack_gas(self, level, per_grid: Sequence[Optional[np.ndarray]], dtype):
+        """Packed active-gas buffer of a level from per-grid (nz, ny, nx) arrays."""
+        buf = np.zeros(self.plan.levels[level]["gas_elems"], dtype=np.float64)
+        any_gas = False
+        for g in self.plan.level_grids(level):
+            a = per_grid[g["index"]]
+            if a is None:
+                continue
+            any_gas = True
+            n = int(np.prod(g["n"]))
+            buf[g["gas_offset"]:g["gas_offset"] + n] = np.asarray(a, np.float64).ravel()
+        if not any_gas:
+            return None
+        return self.torch.from_numpy(buf).to(device=self.device, dtype=dtype)
+
+    def gmf_view(self, gmf, grid):
+        g = self.plan.grids[grid]
+        n = int(np.prod(g["gmf_n"]))
+        return gmf[g["gmf_offset"]:g["gmf_offset"] + n].view(g["gmf_n"][2], g["gmf_n"][1],
+                                                              g["gmf_n"][0])
+
+    def field_view(self, field, grid):
+        g = self.plan.grids[grid]
+        n = int(np.prod(g["fld_n"]))
+        return field[g["fld_offset"]:g["fld_offset"] + n].view(g["fld_n"][2], g["fld_n"][1],
+                                                               g["fld_n"][0], 4)
+
+    # --- the ABI calls -----------------------------------------------------------
+    def owner(self, x, y, z, out=None):
+        if out is None:
+            out = self.torch.empty(x.shape[0], dtype=self.torch.int32, device=self.device)
+        check(_apm.lib().apm_owner(self.handle, _dtype_code(x), _ptr(x), _ptr(y), _ptr(z),
+                                   x.shape[0], _ptr(out)), "apm_owner")
+        return out
+
+    def deposit(self, level, x, y, z, m, gas=None, parent_gas=None, out=None):
+        if out is None:
+            out = self.empty_gmf(level, x.dtype)
+        check(_apm.lib().apm_deposit(self.handle, _dtype_code(x), level, _ptr(x), _ptr(y), _ptr(z),
+                                     _ptr(m), x.shape[0], _ptr(gas), _ptr(parent_gas), _ptr(out)),
+              "apm_deposit")
+        return out
+
+    def solve_level(self, level, gmf, out=None):
+        if out is None:
+            out = self.empty_field(level, gmf.dtype)
+        check(_apm.lib().apm_solve_level(self.handle, _dtype_code(gmf), level, _ptr(gmf),
+                                         _ptr(out)), "apm_solve_level")
+        return out
+
+    def accel(self, level, own, parent=None, out=None):
+        if out is None:
+            out = self.empty_field(level, own.dtype)
+        check(_apm.lib().apm_accel(self.handle, _dtype_code(own), level, _ptr(own), _ptr(parent),
+                                   _ptr(out)), "apm_accel")
+        return out
+
+    def interp(self, level, field, x, y, z, owner, ax, ay, az, pot=None):
+        check(_apm.lib().apm_interp(self.handle, _dtype_code(field), level, _ptr(field), _ptr(x),
+                                    _ptr(y), _ptr(z), _ptr(owner), x.shape[0], _ptr(ax), _ptr(ay),
+                                    _ptr(az), _ptr(pot)), "apm_interp")
+
+    def totals(self, gmfs: List, m, owner, ax, ay, az, pot=None):
+        nl = self.plan.nlevels
+        arr = (ctypes.c_void_p * nl)(*[g.data_ptr() for g in gmfs])
+        out = (ctypes.c_double * (nl + 4))()
+        check(_apm.lib().apm_totals(self.handle, _dtype_code(m), arr, _ptr(m), _ptr(owner),
+                                    m.shape[0], _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot), out),
+              "apm_totals")
+        return np.array(out[:])
+
+    def solve(self, x, y, z, m, gas: Optional[List] = None, ax=None, ay=None, az=None, pot=None,
+              with_pot=True):
+        n = x.shape[0]
+        mk = lambda: self.torch.empty(n, dtype=x.dtype, device=self.device)
+        ax = mk() if ax is None else ax
+        ay = mk() if ay is None else ay
+        az = mk() if az is None else az
+        if pot is None and with_pot:
+            pot = mk()
+        garr = None
+        if gas is not None:
+            garr = (ctypes.c_void_p * self.plan.nlevels)(
+                *[None if g is None else g.data_ptr() for g in gas])
+        check(_apm.lib().apm_solve(self.handle, _dtype_code(x), _ptr(x), _ptr(y), _ptr(z), _ptr(m),
+                                   n, garr, _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot)), "apm_solve")
+        return ax, ay, az, pot
+
+    def solve_totals(self, m, ax, ay, az, pot=None):
+        """FP64 totals of the last solve() (apm_solve_totals): mass per level, energy,
+        net force.  Synchronises the stream."""
+        nl = self.plan.nlevels
+        out = (ctypes.c_double * (nl + 4))()
+        check(_apm.lib().apm_solve_totals(self.handle, _dtype_code(m), _ptr(m), m.shape[0],
+                                          _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot), out),
+              "apm_solve_totals")
+        return np.array(out[:])
+
+    def profile(self, enable: bool):
+        check(_apm.lib().apm_profile(self.handle, 1 if enable else 0), "apm_profile")
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} accumulated since profiling was enabled."""
+        L = _apm.lib()
+        n = L.apm_profile_count(self.handle)
+        if n < 0:
+            raise RuntimeError("apm_profile_count failed")
+        out = {}
+        buf = ctypes.create_string_buffer(64)
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        for i in range(n):
+            check(L.apm_profile_entry(self.handle, i, buf, 64, ctypes.byref(ms), ctypes.byref(cnt)),
+                  "apm_profile_entry")
+            out[buf.value.decode()] = (ms.value, cnt.value)
+        return out
+
+    def solved_field(self, level, dtype):
+        """Library-owned composed field of `level` from the last solve (a copy)."""
+        code = _apm.APM_F32 if dtype == self.torch.float32 else _apm.APM_F64
+        p = _apm.lib().apm_field_ptr(self.handle, code, level)
+        if not p:
+            raise RuntimeError("no field for this level/dtype: call solve() first")
+        out = self.empty_field(level, dtype)
+        nbytes = out.numel() * out.element_size()
+        self.torch.cuda.synchronize(self.device)
+        _hip_copy(out.data_ptr(), p, nbytes)
+        return out
+
+
+def _hip_copy(dst, src, nbytes):
+    """Device-to-device copy through the HIP runtime torch already loaded."""
+    import torch
+    # a zero-copy view through torch would need the allocation's ownership; copy instead
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.restype = ctypes.c_int
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    rc = hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed: {rc}")

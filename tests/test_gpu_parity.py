@@ -1,0 +1,246 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Every stage is compared on the same seeded inputs: the GMF of every grid, the own
+(short-range) field, the composed field, the owner grid (exact), the particle
+accelerations and potentials, and the FP64 totals.  Tolerances (relative L2 of
+acceleration and potential): 1e-12 in FP64, 1e-5 in FP32; deposited mass 1e-6.
+FP32 runs feed the FP32-rounded inputs to both sides.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import apm_workloads as W
+from apm_workloads import GridSpec
+from oracle import apm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+P = pytest.importorskip("paper_1410_0010_amd")
+
+DEV = torch.device("cuda", 0)
+TOL = {np.float64: dict(gmf=1e-13, field=1e-12, acc=1e-12, pot=1e-12, mass=1e-12),
+       np.float32: dict(gmf=1e-6, field=1e-5, acc=1e-5, pot=1e-5, mass=1e-6)}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / (nb if nb > 0 else 1.0)
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype))).to(DEV)
+
+
+def run_staged(w, dtype, gradient="spectral"):
+    plan = P.Plan(w.root_n, w.grids, gradient=gradient)
+    ctx = P.Context(plan, 0)
+    x, y, z, m = (dev(a, dtype) for a in (w.x, w.y, w.z, w.m))
+    tdt = x.dtype
+    gas = [ctx.pack_gas(l, w.gas, tdt) for l in range(plan.nlevels)]
+    owner = ctx.owner(x, y, z)
+    gmf = [ctx.deposit(l, x, y, z, m, gas[l], gas[l - 1] if l > 0 else None)
+           for l in range(plan.nlevels)]
+    own = [ctx.solve_level(l, gmf[l]) for l in range(plan.nlevels)]
+    fld = []
+    for l in range(plan.nlevels):
+        fld.append(ctx.accel(l, own[l], fld[l - 1] if l > 0 else None))
+    n = w.npart
+    ax, ay, az, pot = (torch.zeros(n, dtype=tdt, device=DEV) for _ in range(4))
+    for l in range(plan.nlevels):
+        ctx.interp(l, fld[l], x, y, z, owner, ax, ay, az, pot)
+    tot = ctx.totals(gmf, m, owner, ax, ay, az, pot)
+    torch.cuda.synchronize()
+    out = dict(plan=plan, ctx=ctx,
+               gmf=[ctx.gmf_view(gmf[g["level"]], g["index"]).cpu().numpy() for g in plan.grids],
+               own=[ctx.field_view(own[g["level"]], g["index"]).cpu().numpy() for g in plan.grids],
+               field=[ctx.field_view(fld[g["level"]], g["index"]).cpu().numpy() for g in plan.grids],
+               owner=owner.cpu().numpy(),
+               acc=np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()], 1),
+               pot=pot.cpu().numpy(), totals=tot, tensors=(x, y, z, m, gas))
+    return out
+
+
+def run_oracle(w, dtype, gradient="spectral", cache=None):
+    cast = lambda a: None if a is None else np.asarray(a, dtype).astype(np.float64)
+    plan = O.OraclePlan(w.root_n, w.grids, gradient=gradient)
+    return O.solve(plan, cast(w.x), cast(w.y), cast(w.z), cast(w.m),
+                   [cast(g) for g in w.gas], cache=cache)
+
+
+def compare(name, w, dtype, got, ref):
+    t = TOL[dtype]
+    assert np.array_equal(got["owner"], ref["owner"]), f"{name}: owner grids differ"
+    for i in range(len(ref["gmf"])):
+        e = rel(got["gmf"][i], ref["gmf"][i])
+        assert e <= t["gmf"], f"{name}: grid {i} GMF rel L2 {e:.3e}"
+        for key in ("own", "field"):
+            refk = ref["short"][i] if key == "own" else ref["field"][i]
+            ea = rel(got[key][i][..., :3], refk[..., :3])
+            ep = rel(got[key][i][..., 3], refk[..., 3])
+            assert ea <= t["field"] and ep <= t["field"], \
+                f"{name}: grid {i} {key} rel L2 acc {ea:.3e} pot {ep:.3e}"
+    if w.npart:
+        own = ref["owner"] >= 0
+        ea = rel(got["acc"][own], ref["acc"][own])
+        ep = rel(got["pot"][own], ref["pot"][own])
+        assert ea <= t["acc"], f"{name}: particle acc rel L2 {ea:.3e}"
+        assert ep <= t["pot"], f"{name}: particle pot rel L2 {ep:.3e}"
+        assert np.all(got["acc"][~own] == 0)
+    nl = got["plan"].nlevels
+    plan = O.OraclePlan(w.root_n, w.grids)
+    for l in range(nl):
+        mref = sum(ref["mass"][g.index] for g in plan.level_grids(l))
+        assert abs(got["totals"][l] - mref) <= t["mass"] * abs(mref), f"{name}: level {l} mass"
+    if w.npart:
+        m64 = np.asarray(w.m, dtype).astype(np.float64)
+        own = ref["owner"] >= 0
+        wref = 0.5 * np.sum(m64[own] * ref["pot"][own])
+        assert abs(got["totals"][nl] - wref) <= 10 * t["pot"] * abs(wref)
+        fref = (m64[own, None] * ref["acc"][own]).sum(0)
+        scale = np.abs(m64[own, None] * ref["acc"][own]).sum()
+        assert np.abs(got["totals"][nl + 1:nl + 4] - fref).max() <= 10 * t["acc"] * scale
+
+
+def slab_workload(npart=3000, seed=77):
+    """Root 64^3 and a chain of thin slab grids (8 cells thick) reaching level 4 with
+    FFT lengths 256, 512 and 1024 along x and 32 across."""
+    grids = [GridSpec(0, -1, (0, 0, 0), (64,) * 3)]
+    xs = [(4, 120), (12, 232), (28, 456), (60, 904)]
+    for lev, (lo, n) in enumerate(xs, start=1):
+        c = 32 * 2 ** lev
+        grids.append(GridSpec(lev, lev - 1, (lo, c - 4, c - 4), (n, 8, 8)))
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.08, 0.92, npart)
+    y = 0.5 + rng.normal(0, 0.002, npart)
+    z = 0.5 + rng.normal(0, 0.002, npart)
+    m = rng.uniform(0.5, 1.5, npart) / npart
+    return W.Workload("slab_chain", 64, grids, x, y, z, m, [None] * len(grids))
+
+
+def tiny_grid_workload():
+    """Root 16^3 plus subgrids of 4, 6 and 10 cells per axis (FFT lengths 16 and 32)."""
+    grids = [GridSpec(0, -1, (0, 0, 0), (16,) * 3),
+             GridSpec(1, 0, (8, 10, 12), (4, 6, 10)),
+             GridSpec(1, 0, (18, 16, 8), (10, 4, 4))]
+    rng = np.random.default_rng(5)
+    p = rng.uniform(0.2, 0.8, (3000, 3))
+    return W.Workload("tiny_grids", 16, grids, p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy(),
+                      np.full(3000, 1.0 / 3000), [None] * 3)
+
+
+def edge_workload():
+    """Particles outside the domain, NaN, on the last cell, and exactly on cell
+    corners; a particle at x = 0."""
+    grids = W.centred_nested_grids(16, 8, 1)
+    x = np.array([0.5, 0.5, -0.01, np.nan, 0.999999, 0.0, 0.25, 1.0, 0.53125])
+    y = np.array([0.5, 0.47, 0.5, 0.5, 0.5, 0.3, 0.25, 0.5, 0.46875])
+    z = np.array([0.5, 0.52, 0.5, 0.5, 0.5, 0.7, 0.25, 0.5, 0.5])
+    m = np.array([1.0, 0.5, 1.0, 1.0, 0.1, 0.2, 0.3, 1.0, 0.7])
+    return W.Workload("edge", 16, grids, x, y, z, m, [None] * 2)
+
+
+CASES = {
+    "root32_gas_4096": W.workload_root32_uniform_gas,
+    "nested32_2x16_plummer": lambda: W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=2,
+                                                                npart=20000),
+    "clumps32_24grids": lambda: W.workload_clumps(root_n=32, ngrids=24, per_clump=400,
+                                                   side_lo=4, side_hi=20),
+    "gas_nested32": lambda: W.workload_plummer_gas(root_n=32, sub_n=16, nlevels=2, npart=5000),
+    "slab_chain_L1024": slab_workload,
+    "tiny_grids_L16": tiny_grid_workload,
+    "edge_particles": edge_workload,
+    "uniform_sphere_gas_only": W.workload_uniform_sphere,
+}
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_parity_small(case, dtype):
+    w = CASES[case]()
+    say(f"[parity] case={case} dtype={dtype.__name__} npart={w.npart} grids={len(w.grids)}")
+    ref = run_oracle(w, dtype)
+    got = run_staged(w, dtype)
+    compare(case, w, dtype, got, ref)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_parity_fd2_gradient(dtype):
+    w = W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=2, npart=8000)
+    say(f"[parity] two-point gradient dtype={dtype.__name__}")
+    compare("fd2", w, dtype, run_staged(w, dtype, "fd2"), run_oracle(w, dtype, "fd2"))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_one_call_solve_matches_staged(dtype):
+    w = W.workload_plummer_gas(root_n=32, sub_n=16, nlevels=2, npart=5000)
+    say(f"[parity] apm_solve vs staged dtype={dtype.__name__}")
+    got = run_staged(w, dtype)
+    ctx = got["ctx"]
+    x, y, z, m, gas = got["tensors"]
+    ax, ay, az, pot = ctx.solve(x, y, z, m, gas)
+    torch.cuda.synchronize()
+    acc = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()], 1)
+    tol = 1e-13 if dtype == np.float64 else 1e-6
+    assert rel(acc, got["acc"]) <= tol and rel(pot.cpu().numpy(), got["pot"]) <= tol
+    for l in range(got["plan"].nlevels):
+        f = ctx.solved_field(l, x.dtype).cpu().numpy()
+        ref = np.concatenate([got["field"][g["index"]].reshape(-1, 4)
+                              for g in got["plan"].level_grids(l)])
+        assert rel(f, ref) <= tol
+
+
+# ---- the benchmarked workload at full size: root 128^3 + 2 x 64^3, 2^20 Plummer -------
+
+@pytest.fixture(scope="module")
+def bench_oracle():
+    w = W.workload_plummer_nested()
+    say("[parity] building oracle for the full bench workload (about a minute)")
+    plan = O.OraclePlan(w.root_n, w.grids)
+    cache = {g.index: O.greens(plan, g) for g in plan.grids}
+    return w, cache
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_parity_bench_workload_full_size(bench_oracle, dtype):
+    w, cache = bench_oracle
+    say(f"[parity] full bench workload dtype={dtype.__name__} npart={w.npart}")
+    ref = run_oracle(w, dtype, cache=cache)
+    got = run_staged(w, dtype)
+    compare("bench_full", w, dtype, got, ref)
+
+
+# ---- error paths through the device entry points ------------------------------------
+
+def test_device_error_paths():
+    import ctypes
+    from paper_1410_0010_amd import _apm
+    w = W.workload_plummer_nested(root_n=16, sub_n=8, nlevels=1, npart=100)
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    lib = P.lib()
+    x = dev(w.x, np.float64)
+    assert lib.apm_deposit(ctx.handle, _apm.APM_F64, 5, None, None, None, None, 0, None, None,
+                           None) == _apm.APM_ERR_INVALID
+    f = ctx.empty_field(1, torch.float64)
+    assert lib.apm_accel(ctx.handle, _apm.APM_F64, 1, ctypes.c_void_p(f.data_ptr()), None,
+                         ctypes.c_void_p(f.data_ptr())) == _apm.APM_ERR_STATE
+    assert lib.apm_deposit(ctx.handle, 7, 0, None, None, None, None, 0, None, None,
+                           None) == _apm.APM_ERR_INVALID
+    small = P.Plan(w.root_n, w.grids, workspace_limit=1024)
+    c2 = P.Context(small, 0)
+    with pytest.raises(P.APMError) as e:
+        c2.deposit(0, x, x, x, x)
+    assert e.value.status == _apm.APM_ERR_OOM
