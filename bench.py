@@ -1,9 +1,10 @@
 """Throughput of the APM nested-grid gravity solve on one MI355X.
 
 A step is one forward solve of the whole hot path over the workload: owner grids,
-TSC deposit of every level (binning + compensated owner-computes deposit), the
-FFT convolution of every grid with Fourier-space differencing, level composition,
-TSC interpolation to every particle and the FP64 totals (mass, energy, net force).
+TSC deposit of every level (tile binning + LDS-tiled deposit with FP64
+accumulation), the FFT convolution of every grid with Fourier-space differencing,
+level composition, TSC interpolation to every particle and the FP64 totals (mass,
+energy, net force).
 Workload (the hierarchy the metric is quoted on): root 128^3 plus two centred
 nested 64^3 levels, 2^20 equal-mass Plummer particles (scale 0.05), no gas,
 synthetic and seeded.
@@ -39,7 +40,8 @@ def kernel_bytes(plan, npart_level, esize):
     move at least once; c = complex bytes = 2 esize)."""
     c = 2 * esize
     b = {k: 0.0 for k in ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
-                          "deposit", "compose", "interp", "bin_count", "bin_scatter")}
+                          "deposit_tiles", "deposit_finalize", "compose", "interp", "bin_count",
+                          "bin_scatter")}
     for g in plan.grids:
         gx, gy, gz = g["gmf_n"]
         fx, fy, fz = g["fld_n"]
@@ -51,14 +53,14 @@ def kernel_bytes(plan, npart_level, esize):
         b["fft_z_conv"] += gz * My * W * c + oct_ * c + 4 * fz * My * W * c
         b["fft_y_inv"] += 4 * fz * My * W * c + 4 * fz * fy * W * c
         b["fft_x_inv"] += 4 * fz * fy * W * c + fx * fy * fz * 4 * esize
-        b["deposit"] += gx * gy * gz * esize
+        b["deposit_finalize"] += gx * gy * gz * (8 + esize)     # FP64 mass in, GMF out
         b["compose"] += fx * fy * fz * 4 * esize * (3 if g["level"] > 0 else 2)
-    for l, n in enumerate(npart_level):
-        b["deposit"] += n * 4 * esize                  # sorted (t_x, t_y, t_z, m)
+    for n in npart_level:
+        b["deposit_tiles"] += n * 4 * esize            # sorted (s_x, s_y, s_z, m) records
     n = npart_level[0]
     nl = len(plan.levels)
     b["bin_count"] = nl * n * (3 * esize + 8)         # positions in, key + rank out
-    b["bin_scatter"] = nl * n * (4 * esize + 8) + sum(npart_level) * 4 * esize
+    b["bin_scatter"] = nl * n * (4 * esize + 8) + sum(npart_level) * (4 * esize + 4)
     b["interp"] = n * (3 * esize + 4 + 4 * esize)     # positions + owner in, a + Phi out
     return b
 
@@ -134,7 +136,6 @@ def main():
 
     # dominant kernel of the FP32 step and its roofline
     npl = []
-    owner_levels = None
     for l in range(plan.nlevels):
         # particles binned on level l: those whose cell lies in the level's binning box
         lo = np.array([min(g["gmf_lo"][a] for g in plan.level_grids(l)) - 1 for a in range(3)])

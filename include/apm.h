@@ -156,7 +156,9 @@ apm_status apm_owner(apm_ctx ctx, apm_dtype dtype, const void* x, const void* y,
  *   gas         packed active-gas buffer of `level` or NULL (no own gas)
  *   parent_gas  packed active-gas buffer of level-1 or NULL (no ghost gas)
  *   gmf         out: packed GMF buffer of `level` (gmf_elems scalars)
- * Accumulation is compensated (Kahan) in the dtype's precision. */
+ * The TSC weights and the accumulation are FP64 for both dtypes (the mass of a
+ * cell is summed in FP64 and rounded once to the dtype), so the FP32 result is
+ * the FP32 rounding of the FP64 sum up to the order of additions. */
 apm_status apm_deposit(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* x,
                        const void* y, const void* z, const void* m, int64_t npart,
                        const void* gas, const void* parent_gas, void* gmf);
