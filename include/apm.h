@@ -220,6 +220,25 @@ apm_status apm_solve_totals(apm_ctx ctx, apm_dtype dtype, const void* m, int64_t
 const void* apm_field_ptr(apm_ctx ctx, apm_dtype dtype, int32_t level);
 const void* apm_gmf_ptr(apm_ctx ctx, apm_dtype dtype, int32_t level);
 
+/* ------------------------------------------- batching, graphs, autotuning ---- */
+
+/* apm_solve runs each transform pass as one launch per FFT length over all grids
+ * of all levels (uneven, non-cubic grids share a launch through a job table) and,
+ * unless disabled here, records its whole launch sequence in a hipGraph on the
+ * second call with identical arguments and library buffers, replaying the graph
+ * on the context's stream afterwards.  A change of any argument pointer, of npart
+ * or a library reallocation drops the graph.  enable = 0 keeps every call eager. */
+apm_status apm_set_graph(apm_ctx ctx, int32_t enable);
+
+/* Autotuner: for every (transform pass, FFT length) of the plan in `dtype`, times
+ * the candidate launch shapes (lines per block) over `reps` launches on the job
+ * tables and buffers of the last apm_solve of that dtype and keeps the fastest for
+ * later calls.  FFT sizes themselves are part of the numeric contract and are not
+ * tuned.  The choices and timings (microseconds per launch) are written as a JSON
+ * object to `report` (cap bytes, NUL-terminated, may be NULL).  Synchronises.
+ * Errors: APM_ERR_STATE if no apm_solve of this dtype ran yet. */
+apm_status apm_autotune(apm_ctx ctx, apm_dtype dtype, int32_t reps, char* report, int32_t cap);
+
 /* ------------------------------------------------------- kernel timing ------ */
 
 /* Measurement support: while enabled (enable != 0), every kernel launch of the

@@ -87,6 +87,8 @@ SIGNATURES = {
                                ctypes.POINTER(ctypes.c_double)]),
     "apm_field_ptr": (_vp, [_vp, _st, _i32]),
     "apm_gmf_ptr": (_vp, [_vp, _st, _i32]),
+    "apm_set_graph": (_st, [_vp, _i32]),
+    "apm_autotune": (_st, [_vp, _st, _i32, ctypes.c_char_p, _i32]),
     "apm_profile": (_st, [_vp, _i32]),
     "apm_profile_count": (_i32, [_vp]),
     "apm_profile_entry": (_st, [_vp, _i32, ctypes.c_char_p, _i32, ctypes.POINTER(ctypes.c_double),

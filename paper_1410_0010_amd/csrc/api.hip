@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <sstream>
 #include <string>
@@ -39,8 +40,22 @@ struct apm_ctx_s {
   DevBuf count, items, accum, keyb, rank, scan_tmp, spec, out, tmpfld, owner, totals, bin_totals;
   std::vector<DevBuf> sorted, sidx;                               // per level
   std::vector<int64_t> tile_total_slot;                           // per level: count index of total
-  std::vector<DevBuf> gmf[3], fld[3];                             // solve-owned, by dtype
-  size_t spec_elems = 0, out_elems = 0;                           // complex elements (max)
+  std::vector<DevBuf> gmf[3], fld[3], own[3];                     // solve-owned, by dtype
+  size_t spec_elems = 0, out_elems = 0;                           // complex elements (sum)
+  std::vector<int64_t> spec_off, out_off;                         // per grid
+  struct JobList { ConvJob* d = nullptr; int n = 0; int64_t blocks = 0; };
+  // (dtype, pass, L, level or -1, lines per block) -> jobs
+  std::map<std::tuple<int, int, int, int, int>, JobList> jobs;
+  std::map<std::tuple<int, int, int>, int> lines;                 // autotuned (dtype, pass, L)
+  std::string tune_report;
+  // hipGraph of apm_solve: captured on the second identical call, replayed after
+  uint64_t epoch = 0;                                             // bumps on reallocation
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  std::vector<uintptr_t> gkey;
+  uint64_t gkey_epoch = ~0ull;
+  int gkey_seen = 0;
+  hipGraphExec_t gexec = nullptr;
   // kernel timing: events around every launch while enabled
   struct Mark { std::string name; hipEvent_t a, b; };
   bool prof_on = false;
@@ -100,10 +115,12 @@ apm_status ensure(apm_ctx c, DevBuf& b, size_t bytes, const char* what) {
   }
   APM_TRY(dev_alloc(c, &b.p, bytes, what));
   b.bytes = bytes;
+  c->epoch++;
   return APM_OK;
 }
 
 apm_status upload(apm_ctx c, void** dst, const void* src, size_t bytes, const char* what) {
+  c->epoch++;
   APM_TRY(dev_alloc(c, dst, bytes, what));
   c->owned.push_back(*dst);
   HIP_TRY(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), what);
@@ -290,32 +307,130 @@ apm_status kernel_table(apm_ctx c, apm_dtype dt, const GridDesc& g, const void**
   return APM_OK;
 }
 
+int pass_axis(int pass) { return pass == PASS_Y_FWD || pass == PASS_Y_INV ? 1 : (pass == PASS_Z_CONV ? 2 : 0); }
+const char* pass_name(int pass) {
+  static const char* n[] = {"fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv"};
+  return n[pass];
+}
+
 template <typename T>
-apm_status solve_level_t(apm_ctx c, int32_t level, const T* gmf, T* field) {
-  const LevelDesc& L = c->plan.levels[level];
-  APM_TRY(ensure(c, c->spec, c->spec_elems * sizeof(C2<T>), "spectrum buffer"));
-  APM_TRY(ensure(c, c->out, c->out_elems * sizeof(C2<T>), "output spectra buffer"));
-  for (int32_t gi = L.first; gi < L.first + L.count; ++gi) {
+int lines_for(apm_ctx c, int pass, int L) {
+  auto it = c->lines.find(std::make_tuple((int)sizeof(T), pass, L));
+  return it != c->lines.end() ? it->second : default_lines<T>(pass, L);
+}
+
+// Grids of `level` (or of every level when level < 0).
+std::vector<int> grid_set(apm_ctx c, int level) {
+  std::vector<int> v;
+  for (const GridDesc& g : c->plan.grids)
+    if (level < 0 || g.level == level) v.push_back(g.index);
+  return v;
+}
+
+// Tables every grid of the set needs (Green's functions, gradient symbols,
+// twiddles).  Allocates and launches on first use.
+template <typename T>
+apm_status prepare_tables(apm_ctx c, const std::vector<int>& set) {
+  for (int gi : set) {
     const GridDesc& g = c->plan.grids[gi];
-    GridConv<T> j{};
-    j.gmf = gmf + g.gmf_offset;
+    const void* k = nullptr;
+    APM_TRY(kernel_table(c, sizeof(T) == 4 ? APM_F32 : APM_F64, g, &k));
+    for (int a = 0; a < 3; ++a) {
+      const T* d = nullptr;
+      const void* t = nullptr;
+      APM_TRY(grad_symbols<T>(c, g.level, g.M[a], g.dx, &d));
+      APM_TRY(twiddles<T>(c, g.M[a], &t));
+    }
+  }
+  return APM_OK;
+}
+
+// Job list of one pass and line length over the grid set (cached).
+template <typename T>
+apm_status job_list(apm_ctx c, int pass, int L, int level, int nl, const apm_ctx_s::JobList** out) {
+  auto key = std::make_tuple((int)sizeof(T), pass, L, level, nl);
+  auto it = c->jobs.find(key);
+  if (it != c->jobs.end()) { *out = &it->second; return APM_OK; }
+  std::vector<ConvJob> v;
+  int64_t blocks = 0;
+  const apm_dtype dt = sizeof(T) == 4 ? APM_F32 : APM_F64;
+  for (int gi : grid_set(c, level)) {
+    const GridDesc& g = c->plan.grids[gi];
+    if (g.M[pass_axis(pass)] != L) continue;
+    ConvJob j{};
+    j.blk0 = blocks;
+    j.level = g.level;
     for (int a = 0; a < 3; ++a) {
       j.g[a] = g.gmf_n[a];
       j.M[a] = g.M[a];
       j.f[a] = g.fld_n[a];
       j.off[a] = ((g.fld_lo[a] - g.gmf_lo[a]) % g.M[a] + g.M[a]) % g.M[a];
     }
-    j.spec = (C2<T>*)c->spec.p;
-    j.out = (C2<T>*)c->out.p;
-    j.field = (V4<T>*)field + g.fld_offset;
-    APM_TRY(kernel_table(c, sizeof(T) == 4 ? APM_F32 : APM_F64, g, &j.kern));
+    j.gmf_off = g.gmf_offset;
+    j.fld_off = g.fld_offset;
+    j.spec_off = c->spec_off[gi];
+    j.out_off = c->out_off[gi];
+    APM_TRY(kernel_table(c, dt, g, &j.kern));
     for (int a = 0; a < 3; ++a) {
-      APM_TRY(grad_symbols<T>(c, g.level, g.M[a], g.dx, &j.dsym[a]));
-      APM_TRY(twiddles<T>(c, g.M[a], &j.tw[a]));
+      const T* d = nullptr;
+      APM_TRY(grad_symbols<T>(c, g.level, g.M[a], g.dx, &d));
+      j.dsym[a] = d;
     }
-    HIP_TRY(launch_grid_convolution<T>(j, c->stream, hook_of(c)), "convolution");
+    blocks += pass_blocks(pass, j.g, j.M, j.f, nl);
+    v.push_back(j);
+  }
+  apm_ctx_s::JobList jl;
+  jl.n = (int)v.size();
+  jl.blocks = blocks;
+  if (!v.empty()) {
+    void* d = nullptr;
+    APM_TRY(upload(c, &d, v.data(), v.size() * sizeof(ConvJob), "job table"));
+    jl.d = (ConvJob*)d;
+  }
+  c->jobs[key] = jl;
+  *out = &c->jobs[key];
+  return APM_OK;
+}
+
+// Distinct line lengths a pass needs over the set.
+std::vector<int> pass_lengths(apm_ctx c, int pass, int level) {
+  std::vector<int> Ls;
+  for (int gi : grid_set(c, level)) {
+    const int L = c->plan.grids[gi].M[pass_axis(pass)];
+    if (std::find(Ls.begin(), Ls.end(), L) == Ls.end()) Ls.push_back(L);
+  }
+  return Ls;
+}
+
+// Own fields of the grid set: the five passes, one launch per (pass, L).
+template <typename T>
+apm_status convolve_t(apm_ctx c, int level, const LevelPtrs<T>& lp) {
+  const std::vector<int> set = grid_set(c, level);
+  APM_TRY(prepare_tables<T>(c, set));
+  APM_TRY(ensure(c, c->spec, c->spec_elems * sizeof(C2<T>), "spectrum buffer"));
+  APM_TRY(ensure(c, c->out, c->out_elems * sizeof(C2<T>), "output spectra buffer"));
+  for (int pass = PASS_X_FWD; pass <= PASS_X_INV; ++pass) {
+    for (int L : pass_lengths(c, pass, level)) {
+      const int nl = lines_for<T>(c, pass, L);
+      const apm_ctx_s::JobList* jl = nullptr;
+      APM_TRY(job_list<T>(c, pass, L, level, nl, &jl));
+      const void* tw = nullptr;
+      APM_TRY(twiddles<T>(c, L, &tw));
+      HIP_TRY(timed(c, pass_name(pass), [&] {
+                return launch_pass<T>(pass, L, nl, jl->d, jl->n, jl->blocks, lp,
+                                      (C2<T>*)c->spec.p, (C2<T>*)c->out.p, tw, c->stream);
+              }), pass_name(pass));
+    }
   }
   return APM_OK;
+}
+
+template <typename T>
+apm_status solve_level_t(apm_ctx c, int32_t level, const T* gmf, T* field) {
+  LevelPtrs<T> lp{};
+  lp.gmf[level] = gmf;
+  lp.fld[level] = (V4<T>*)field;
+  return convolve_t<T>(c, level, lp);
 }
 
 template <typename T>
@@ -423,20 +538,17 @@ apm_status zero_t(apm_ctx c, T* p, int64_t n) {
 }
 
 template <typename T>
-apm_status solve_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, const T* m,
-                   int64_t npart, const void* const* gas, T* ax, T* ay, T* az, T* pot) {
+apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, const T* m,
+                        int64_t npart, const void* const* gas, T* ax, T* ay, T* az, T* pot) {
   const Plan& P = c->plan;
   const int nl = (int)P.levels.size();
   const int di = (int)dt;
   c->gmf[di].resize(nl);
   c->fld[di].resize(nl);
-  size_t maxfld = 0;
   for (int l = 0; l < nl; ++l) {
     APM_TRY(ensure(c, c->gmf[di][l], (size_t)P.levels[l].gmf_elems * sizeof(T), "level gmf"));
     APM_TRY(ensure(c, c->fld[di][l], (size_t)P.levels[l].fld_cells * sizeof(V4<T>), "level field"));
-    maxfld = std::max(maxfld, (size_t)P.levels[l].fld_cells * sizeof(V4<T>));
   }
-  APM_TRY(ensure(c, c->tmpfld, maxfld, "own field scratch"));
   APM_TRY(ensure(c, c->owner, (size_t)std::max<int64_t>(npart, 1) * 4, "owner"));
   int32_t* own = (int32_t*)c->owner.p;
   HIP_TRY(timed(c, "owner", [&] {
@@ -448,12 +560,19 @@ apm_status solve_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, 
     const T* pg = (gas && l > 0) ? (const T*)gas[l - 1] : nullptr;
     APM_TRY(deposit_t<T>(c, l, x, y, z, m, npart, g, pg, (T*)c->gmf[di][l].p));
   }
+  c->own[di].resize(nl);
+  LevelPtrs<T> lp{};
   for (int l = 0; l < nl; ++l) {
-    APM_TRY(solve_level_t<T>(c, l, (const T*)c->gmf[di][l].p, (T*)c->tmpfld.p));
+    APM_TRY(ensure(c, c->own[di][l], (size_t)P.levels[l].fld_cells * sizeof(V4<T>), "level own field"));
+    lp.gmf[l] = (const T*)c->gmf[di][l].p;
+    lp.fld[l] = (V4<T>*)c->own[di][l].p;
+  }
+  APM_TRY(convolve_t<T>(c, -1, lp));
+  for (int l = 0; l < nl; ++l) {
     const LevelDesc& L = P.levels[l];
     HIP_TRY(timed(c, "compose", [&] {
               return launch_compose<T>(c->d_grids + L.first, c->d_cmp_begin[l], L.count,
-                                       (const V4<T>*)c->tmpfld.p,
+                                       (const V4<T>*)c->own[di][l].p,
                                        l > 0 ? (const V4<T>*)c->fld[di][l - 1].p : nullptr,
                                        (V4<T>*)c->fld[di][l].p, c->cmp_blocks[l], c->stream);
             }), "compose");
@@ -464,6 +583,121 @@ apm_status solve_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, 
             return launch_interp_all<T>(c->d_grids, ft, x, y, z, own, npart, ax, ay, az, pot,
                                         c->stream);
           }), "interp");
+  return APM_OK;
+}
+
+void drop_graph(apm_ctx c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+}
+
+// apm_solve with graph capture: a call whose arguments and library buffers match
+// the previous call is captured once (on an internal stream, since the caller's
+// may be the legacy default stream) and replayed on the caller's stream after.
+template <typename T>
+apm_status solve_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, const T* m,
+                   int64_t npart, const void* const* gas, T* ax, T* ay, T* az, T* pot) {
+  if (!c->use_graph || c->prof_on)
+    return solve_body_t<T>(c, dt, x, y, z, m, npart, gas, ax, ay, az, pot);
+  std::vector<uintptr_t> key = {(uintptr_t)dt, (uintptr_t)npart, (uintptr_t)x, (uintptr_t)y,
+                                (uintptr_t)z, (uintptr_t)m, (uintptr_t)ax, (uintptr_t)ay,
+                                (uintptr_t)az, (uintptr_t)pot};
+  for (size_t l = 0; l < c->plan.levels.size(); ++l)
+    key.push_back(gas ? (uintptr_t)gas[l] : 0);
+  if (c->gexec && key == c->gkey && c->epoch == c->gkey_epoch) {
+    HIP_TRY(hipGraphLaunch(c->gexec, c->stream), "graph launch");
+    return APM_OK;
+  }
+  if (key == c->gkey && c->epoch == c->gkey_epoch && c->gkey_seen >= 1) {
+    drop_graph(c);
+    if (!c->cap_stream)
+      HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
+    // the capture stream must see the caller's prior work: record on the caller's
+    // stream, wait on the capture stream before capture begins
+    hipStream_t user = c->stream;
+    HIP_TRY(hipStreamSynchronize(user), "pre-capture sync");
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    c->stream = c->cap_stream;
+    apm_status st = solve_body_t<T>(c, dt, x, y, z, m, npart, gas, ax, ay, az, pot);
+    c->stream = user;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != APM_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(e, "end capture"); }
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { c->gexec = nullptr; return hip_fail(e, "graph instantiate"); }
+    if (c->epoch != c->gkey_epoch) { drop_graph(c); return fail(APM_ERR_STATE, "allocation during capture"); }
+    HIP_TRY(hipGraphLaunch(c->gexec, c->stream), "graph launch");
+    return APM_OK;
+  }
+  drop_graph(c);
+  apm_status st = solve_body_t<T>(c, dt, x, y, z, m, npart, gas, ax, ay, az, pot);
+  c->gkey = key;
+  c->gkey_epoch = c->epoch;
+  c->gkey_seen = st == APM_OK ? 1 : 0;
+  return st;
+}
+
+// Autotuner: lines per block of every (pass, L) of the plan, timed on the real job
+// tables and buffers of the last apm_solve of this precision.
+template <typename T>
+apm_status autotune_t(apm_ctx c, apm_dtype dt, int reps) {
+  const int di = (int)dt;
+  const int nl = (int)c->plan.levels.size();
+  if ((int)c->own[di].size() != nl || !c->spec.p)
+    return fail(APM_ERR_STATE, "apm_autotune: run apm_solve of this precision first");
+  HIP_TRY(hipStreamSynchronize(c->stream), "autotune sync");
+  LevelPtrs<T> lp{};
+  for (int l = 0; l < nl; ++l) {
+    lp.gmf[l] = (const T*)c->gmf[di][l].p;
+    lp.fld[l] = (V4<T>*)c->own[di][l].p;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "event");
+  HIP_TRY(hipEventCreate(&e1), "event");
+  std::ostringstream rep;
+  rep << "{";
+  bool first = true;
+  for (int pass = PASS_X_FWD; pass <= PASS_X_INV; ++pass) {
+    for (int L : pass_lengths(c, pass, -1)) {
+      const int d0 = default_lines<T>(pass, L);
+      const void* tw = nullptr;
+      APM_TRY(twiddles<T>(c, L, &tw));
+      int best = d0;
+      float best_ms = 1e30f;
+      std::ostringstream cand;
+      for (int nlc : {d0 / 4, d0 / 2, d0, d0 * 2, d0 * 4}) {
+        if (pass_lds<T>(pass, L, nlc) == 0) continue;
+        const apm_ctx_s::JobList* jl = nullptr;
+        APM_TRY(job_list<T>(c, pass, L, -1, nlc, &jl));
+        HIP_TRY(launch_pass<T>(pass, L, nlc, jl->d, jl->n, jl->blocks, lp, (C2<T>*)c->spec.p,
+                               (C2<T>*)c->out.p, tw, c->stream), "autotune warm-up");
+        HIP_TRY(hipEventRecord(e0, c->stream), "event");
+        for (int r = 0; r < reps; ++r)
+          HIP_TRY(launch_pass<T>(pass, L, nlc, jl->d, jl->n, jl->blocks, lp, (C2<T>*)c->spec.p,
+                                 (C2<T>*)c->out.p, tw, c->stream), "autotune launch");
+        HIP_TRY(hipEventRecord(e1, c->stream), "event");
+        HIP_TRY(hipEventSynchronize(e1), "event");
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "event");
+        ms /= reps;
+        cand << (cand.tellp() > 0 ? ", " : "") << "\"" << nlc << "\": " << ms * 1e3f;
+        if (ms < best_ms) { best_ms = ms; best = nlc; }
+      }
+      c->lines[std::make_tuple((int)sizeof(T), pass, L)] = best;
+      rep << (first ? "" : ", ") << "\"" << pass_name(pass) << "/" << L << "/"
+          << (sizeof(T) == 4 ? "f32" : "f64") << "\": {\"lines\": " << best << ", \"us\": {"
+          << cand.str() << "}}";
+      first = false;
+    }
+  }
+  rep << "}";
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tune_report = rep.str();
+  drop_graph(c);
+  c->gkey.clear();
   return APM_OK;
 }
 
@@ -503,8 +737,10 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
       dep[i + 1] = dep[i] + (gc + kBlock - 1) / kBlock;
       cmp[i + 1] = cmp[i] + (fc + kBlock - 1) / kBlock;
       const int64_t W = g.M[0] / 2 + 1;
-      c->spec_elems = std::max(c->spec_elems, (size_t)(g.gmf_n[2] * (int64_t)g.M[1] * W));
-      c->out_elems = std::max(c->out_elems, (size_t)(4 * (int64_t)g.fld_n[2] * g.M[1] * W));
+      c->spec_off.push_back((int64_t)c->spec_elems);
+      c->out_off.push_back((int64_t)c->out_elems);
+      c->spec_elems += (size_t)(g.gmf_n[2] * (int64_t)g.M[1] * W);
+      c->out_elems += (size_t)(4 * (int64_t)g.fld_n[2] * g.M[1] * W);
     }
     void *d1 = nullptr, *d2 = nullptr;
     st = upload(c, &d1, dep.data(), dep.size() * 8, "deposit block table");
@@ -524,6 +760,8 @@ apm_status apm_destroy(apm_ctx c) {
   if (!c) return APM_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* p : c->owned) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   DevBuf* bufs[] = {&c->count, &c->items, &c->accum, &c->keyb, &c->rank,
@@ -536,6 +774,8 @@ apm_status apm_destroy(apm_ctx c) {
   for (auto& v : c->gmf)
     for (auto& b : v) if (b.p) (void)hipFree(b.p);
   for (auto& v : c->fld)
+    for (auto& b : v) if (b.p) (void)hipFree(b.p);
+  for (auto& v : c->own)
     for (auto& b : v) if (b.p) (void)hipFree(b.p);
   delete c;
   return APM_OK;
@@ -705,6 +945,23 @@ const void* apm_field_ptr(apm_ctx c, apm_dtype dt, int32_t level) {
       level >= (int32_t)c->fld[(int)dt].size())
     return nullptr;
   return c->fld[(int)dt][level].p;
+}
+
+apm_status apm_autotune(apm_ctx c, apm_dtype dt, int32_t reps, char* report, int32_t cap) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (reps < 1) reps = 5;
+  APM_TRY(dt == APM_F32 ? autotune_t<float>(c, dt, reps) : autotune_t<double>(c, dt, reps));
+  if (report && cap > 0) std::snprintf(report, (size_t)cap, "%s", c->tune_report.c_str());
+  return APM_OK;
+}
+
+apm_status apm_set_graph(apm_ctx c, int32_t enable) {
+  APM_TRY(check_ctx(c));
+  c->use_graph = enable != 0;
+  drop_graph(c);
+  c->gkey.clear();
+  return APM_OK;
 }
 
 apm_status apm_profile(apm_ctx c, int32_t enable) {

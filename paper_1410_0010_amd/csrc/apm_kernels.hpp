@@ -10,26 +10,41 @@
 
 namespace apm {
 
-// One grid's convolution: GMF (dims g) zero-padded into FFT box M, outputs on the
-// field box (dims f) whose first cell sits at transform index off (cyclic).
-template <typename T> struct GridConv {
-  const T* gmf;
-  int g[3], M[3], f[3], off[3];
-  C2<T>* spec;            // g[2] * M[1] * (M[0]/2+1)
-  C2<T>* out;             // 4 * f[2] * M[1] * (M[0]/2+1)
-  void* field;            // f cells of V4<T>
-  const void* kern;       // octant (Gf, Gp) table of C2<T>
-  const T* dsym[3];       // gradient symbols per axis index
-  const void* tw[3];      // twiddle tables per axis length
-};
 // Optional timing hook called around every kernel launch (phase 0 before, 1 after).
 struct LaunchHook {
   void (*fn)(void* user, const char* name, int phase) = nullptr;
   void* user = nullptr;
   void operator()(const char* name, int phase) const { if (fn) fn(user, name, phase); }
 };
-template <typename T> hipError_t launch_grid_convolution(const GridConv<T>& j, hipStream_t s,
-                                                         const LaunchHook& hook);
+
+constexpr int kMaxLevels = 21;
+template <typename T> struct LevelPtrs {
+  const T* gmf[kMaxLevels];        // packed GMF buffer of each level
+  V4<T>* fld[kMaxLevels];          // packed (own) field buffer of each level
+};
+
+// The five transform passes of a grid's convolution.
+enum { PASS_X_FWD = 0, PASS_Y_FWD = 1, PASS_Z_CONV = 2, PASS_Y_INV = 3, PASS_X_INV = 4 };
+
+// One grid in one pass: GMF (dims g) zero-padded into FFT box M, outputs on the field
+// box (dims f) whose first cell sits at transform index off (cyclic).  Offsets are
+// in elements of the level GMF buffer, the level field buffer (cells) and the
+// shared spectrum / output-spectra buffers (complex values).
+struct ConvJob {
+  int64_t blk0;                    // first block of this job in its launch
+  int32_t level;
+  int32_t g[3], M[3], f[3], off[3];
+  int64_t gmf_off, fld_off, spec_off, out_off;
+  const void* kern;                // octant (Gf, Gp) table
+  const void* dsym[3];             // gradient symbols per axis index
+};
+int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], int nl);
+template <typename T> int default_lines(int pass, int L);
+template <typename T> size_t pass_lds(int pass, int L, int nl);   // 0: not launchable
+template <typename T>
+hipError_t launch_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, int64_t nblocks,
+                       const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* out, const void* tw,
+                       hipStream_t s);
 
 // Green's functions (FP64): octant table of (force, potential) times `norm`.
 struct InfluenceParams {
@@ -111,7 +126,6 @@ template <typename T> hipError_t launch_interp_sorted(const GridDesc* grids, int
                                                       const int32_t* owner, T* ax, T* ay, T* az,
                                                       T* pot, hipStream_t s);
 // every level in one launch: fields[l] is level l's composed field
-constexpr int kMaxLevels = 21;
 template <typename T> struct FieldTable { const V4<T>* f[kMaxLevels]; };
 template <typename T> hipError_t launch_interp_all(const GridDesc* grids, const FieldTable<T>& fields,
                                                    const T* x, const T* y, const T* z,

@@ -15,24 +15,45 @@
 // Zero planes/rows of the padding are never read or transformed twice: y_fwd reads
 // only gy rows, z_conv only gz planes, and the inverse passes write only the field
 // box.  Unnormalised transforms; 1/(Mx My Mz) is folded into the kernel table.
+//
+// Batching: each pass is one launch per line length L over any set of grids (all
+// grids of all levels in apm_solve: the levels' convolutions are independent).  A
+// job table lists the grids with the index of their first block; a block finds its
+// grid by binary search.  Lines per block (nl) is a launch parameter, chosen by the
+// autotuner per (pass, L, precision).
 #include "apm_kernels.hpp"
 #include "device_common.hpp"
 
 namespace apm {
 
+// Block -> job: last job whose first block is <= b (jobs sorted by blk0).
+__device__ __forceinline__ int find_job(const ConvJob* __restrict__ jobs, int njobs, int64_t b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].blk0 <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ------------------------------------------------------------------ x forward --
+// Job = one grid; block = nl row pairs of its GMF (rows r = z gy + y).
 template <typename T, int L>
-__global__ void __launch_bounds__((FFTShape<T, L>::NT))
-k_fft_x_fwd(const T* __restrict__ gmf, int gx, int gy, int gz, C2<T>* __restrict__ spec,
-            int My, int W, const C2<T>* __restrict__ tw) {
-  using S = FFTShape<T, L>;
+__global__ void __launch_bounds__(1024)
+k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp,
+            C2<T>* __restrict__ specb, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
+  const int64_t blk = blockIdx.x - J.blk0;
+  const int gx = J.g[0], gy = J.g[1], gz = J.g[2], My = J.M[1], W = J.M[0] / 2 + 1;
+  const T* __restrict__ gmf = lp.gmf[J.level] + J.gmf_off;
+  C2<T>* __restrict__ spec = specb + J.spec_off;
   const int t = threadIdx.x;
   const int b = t / (L / 8), w = t % (L / 8);
-  C2<T>* line = lds + b * S::LS;
+  C2<T>* line = lds + b * L;
   const int64_t rows = (int64_t)gy * gz;
-  const int64_t q = (int64_t)blockIdx.x * S::NL + b;
+  const int64_t q = blk * nl + b;
   const int64_t ra = 2 * q, rb = 2 * q + 1;
   for (int i = w; i < L; i += L / 8) {
     T xa = 0, xb = 0;
@@ -58,68 +79,89 @@ k_fft_x_fwd(const T* __restrict__ gmf, int gx, int gy, int gz, C2<T>* __restrict
 }
 
 // ------------------------------------------------- strided columns (y passes) --
-// Lines along the row index of planes: element (plane p, row r, column c) at
-// buf[p * plane_stride + r * W + c].  Reads rows [0, n_in) (rest zero), writes rows
-// j in [0, n_out) from transform index (out_off + j) mod L.  In place.
+// Lines along y of planes p: element (p, row, column) at buf[p My W + row W + col].
+// INV = false: spectrum, planes z < gz, rows [0, gy) in, all My rows out.
+// INV = true:  output spectra, planes 4 fz, all My rows in, rows j < fy out taken
+//              from transform index (off_y + j) mod L.  In place.
 template <typename T, int L, bool INV>
-__global__ void __launch_bounds__((FFTShape<T, L>::NT))
-k_fft_cols(C2<T>* __restrict__ buf, int64_t plane_stride, int W, int nbw, int n_in, int n_out,
-           int out_off, const C2<T>* __restrict__ tw) {
-  using S = FFTShape<T, L>;
+__global__ void __launch_bounds__(1024)
+k_fft_cols(const ConvJob* __restrict__ jobs, int njobs, int nl, C2<T>* __restrict__ specb,
+           C2<T>* __restrict__ outb, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  constexpr int LS = L + 1;
+  const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
+  const int64_t blk = blockIdx.x - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1];
+  const int nbw = (W + nl - 1) / nl;
+  const int64_t p = blk / nbw;
+  const int c0 = (int)(blk % nbw) * nl;
+  const int n_in = INV ? My : J.g[1];
+  const int n_out = INV ? J.f[1] : My;
+  const int oo = INV ? J.off[1] : 0;
+  C2<T>* base = (INV ? outb + J.out_off : specb + J.spec_off) + p * ((int64_t)My * W) + c0;
+  const int nt = nl * (L / 8);
   const int t = threadIdx.x;
-  const int64_t p = blockIdx.x / nbw;
-  const int c0 = (blockIdx.x % nbw) * S::NL;
-  C2<T>* base = buf + p * plane_stride + c0;
-  for (int idx = t; idx < S::NL * L; idx += S::NT) {
-    const int bb = idx % S::NL, r = idx / S::NL;
+  for (int idx = t; idx < nl * L; idx += nt) {
+    const int bb = idx % nl, r = idx / nl;
     C2<T> v = mk<T>(0, 0);
     if (r < n_in && c0 + bb < W) v = base[(int64_t)r * W + bb];
-    lds[bb * S::LS + r] = v;
+    lds[bb * LS + r] = v;
   }
   __syncthreads();
   const int b = t / (L / 8), w = t % (L / 8);
-  fft_line<T, L, INV>(lds + b * S::LS, w, tw);
+  fft_line<T, L, INV>(lds + b * LS, w, tw);
   __syncthreads();                                   // stores use another mapping
-  for (int idx = t; idx < S::NL * n_out; idx += S::NT) {
-    const int bb = idx % S::NL, j = idx / S::NL;
-    if (c0 + bb < W) base[(int64_t)j * W + bb] = lds[bb * S::LS + ((out_off + j) & (L - 1))];
+  for (int idx = t; idx < nl * n_out; idx += nt) {
+    const int bb = idx % nl, j = idx / nl;
+    if (c0 + bb < W) base[(int64_t)j * W + bb] = lds[bb * LS + ((oo + j) & (L - 1))];
   }
 }
 
 // --------------------------------------------------------- z pass + multiply --
-// For one (ky, block of kx): forward FFT along z of gz nonzero planes, then for
-// each output component c the product with its multiplier and an inverse FFT:
-//   c = 0,1,2: -i d_c(k) Gf(k)   (Fourier-space differencing of the potential)
+// For one (ky, block of kx) of a grid: forward FFT along z of the gz non-zero
+// planes, then for each output c the product with its multiplier and an inverse FFT:
+//   c = 0,1,2: -i d_c(k) Gf(k)   (Fourier-space gradient of the potential)
 //   c = 3:      Gp(k)
 // kern: octant table of (Gf, Gp), index ((|kz| Oy) + |ky|) W + kx, already scaled.
+constexpr int kZConvMaxThreads = 512;     // keeps the FP64 z pass free of spills
+
 template <typename T, int L>
-__global__ void __launch_bounds__((FFTShape<T, L>::NT))
-k_fft_z_conv(const C2<T>* __restrict__ spec, C2<T>* __restrict__ out, int gz, int My, int W,
-             int nbw, int fz, int oz, const C2<T>* __restrict__ kern, const T* __restrict__ dxs,
-             const T* __restrict__ dys, const T* __restrict__ dzs, const C2<T>* __restrict__ tw) {
-  using S = FFTShape<T, L>;
+__global__ void __launch_bounds__(kZConvMaxThreads)
+k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __restrict__ specb,
+             C2<T>* __restrict__ outb, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
-  const int t = threadIdx.x;
-  const int ky = blockIdx.x / nbw;
-  const int c0 = (blockIdx.x % nbw) * S::NL;
+  constexpr int LS = L + 1;
+  const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
+  const int64_t blk = blockIdx.x - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1];
+  const int gz = J.g[2], fz = J.f[2], oz = J.off[2];
+  const int nbw = (W + nl - 1) / nl;
+  const int ky = (int)(blk / nbw);
+  const int c0 = (int)(blk % nbw) * nl;
+  const C2<T>* __restrict__ spec = specb + J.spec_off;
+  C2<T>* __restrict__ out = outb + J.out_off;
+  const C2<T>* __restrict__ kern = (const C2<T>*)J.kern;
+  const T* __restrict__ dxs = (const T*)J.dsym[0];
+  const T* __restrict__ dys = (const T*)J.dsym[1];
+  const T* __restrict__ dzs = (const T*)J.dsym[2];
   const int64_t pstride = (int64_t)My * W;
-  for (int idx = t; idx < S::NL * L; idx += S::NT) {
-    const int bb = idx % S::NL, z = idx / S::NL;
+  const int nt = nl * (L / 8);
+  const int t = threadIdx.x;
+  for (int idx = t; idx < nl * L; idx += nt) {
+    const int bb = idx % nl, z = idx / nl;
     C2<T> v = mk<T>(0, 0);
     if (z < gz && c0 + bb < W) v = spec[z * pstride + (int64_t)ky * W + c0 + bb];
-    lds[bb * S::LS + z] = v;
+    lds[bb * LS + z] = v;
   }
   __syncthreads();
   const int b = t / (L / 8), w = t % (L / 8);
-  C2<T>* line = lds + b * S::LS;
+  C2<T>* line = lds + b * LS;
   fft_line<T, L, false>(line, w, tw);
 
   const int kx = c0 + b;
-  const bool live = kx < W;
-  const int kxc = live ? kx : 0;
+  const int kxc = kx < W ? kx : 0;
   const int Oy = My / 2 + 1;
   const int kyo = ky <= My / 2 ? ky : My - ky;
   const T dxk = dxs[kxc], dyk = dys[ky];
@@ -149,14 +191,13 @@ k_fft_z_conv(const C2<T>* __restrict__ spec, C2<T>* __restrict__ out, int gz, in
     __syncthreads();
     fft_line<T, L, true>(line, w, tw);
     __syncthreads();                                 // stores use another mapping
-    for (int idx = t; idx < S::NL * fz; idx += S::NT) {
-      const int bb = idx % S::NL, j = idx / S::NL;
+    for (int idx = t; idx < nl * fz; idx += nt) {
+      const int bb = idx % nl, j = idx / nl;
       if (c0 + bb < W)
-        out[((int64_t)(c * fz + j) * My + ky) * W + c0 + bb] = lds[bb * S::LS + ((oz + j) & (L - 1))];
+        out[((int64_t)(c * fz + j) * My + ky) * W + c0 + bb] = lds[bb * LS + ((oz + j) & (L - 1))];
     }
     __syncthreads();
   }
-  (void)live;
 }
 
 // ------------------------------------------------------------------ x inverse --
@@ -166,28 +207,28 @@ k_fft_z_conv(const C2<T>* __restrict__ spec, C2<T>* __restrict__ out, int gz, in
 // two rows.  Pairing rows of the same component keeps magnitudes alike (an
 // acceleration and the potential can differ by 1/dx, and a shared complex FFT would
 // hand the larger one's rounding to the smaller).  4 lines per row pair; writes
-// field[r fx + x] = (a_x, a_y, a_z, Phi).  Rows are contiguous, so no LDS padding.
-template <typename T, int L> struct XInvShape {
-  static constexpr int NL = FFTShape<T, L>::NL < 4 ? 4 : FFTShape<T, L>::NL;
-  static constexpr int NT = NL * (L / 8);
-  static constexpr int LS = L;
-};
-
+// field[r fx + x] = (a_x, a_y, a_z, Phi).  Rows are contiguous: no LDS padding.
 template <typename T, int L>
-__global__ void __launch_bounds__((XInvShape<T, L>::NT))
-k_fft_x_inv(const C2<T>* __restrict__ out, int fz, int fy, int fx, int My, int W, int ox,
-            V4<T>* __restrict__ field, const C2<T>* __restrict__ tw) {
-  using S = XInvShape<T, L>;
-  constexpr int G = S::NL / 4;
+__global__ void __launch_bounds__(1024)
+k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __restrict__ outb,
+            LevelPtrs<T> lp, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
+  const int64_t blk = blockIdx.x - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1];
+  const int fx = J.f[0], fy = J.f[1], fz = J.f[2], ox = J.off[0];
+  const C2<T>* __restrict__ out = outb + J.out_off;
+  V4<T>* __restrict__ field = lp.fld[J.level] + J.fld_off;
+  const int G = nl / 4;
+  const int nt = nl * (L / 8);
   const int t = threadIdx.x;
   const int b = t / (L / 8), w = t % (L / 8);
   const int64_t rows = (int64_t)fz * fy;
-  const int64_t q = (int64_t)blockIdx.x * G + b / 4;
+  const int64_t q = blk * G + b / 4;
   const int c = b & 3;
   const int64_t ra = 2 * q, rb = 2 * q + 1;
-  C2<T>* line = lds + b * S::LS;
+  C2<T>* line = lds + b * L;
   if (ra < rows) {
     const C2<T>* A = out + ((int64_t)(c * fz + ra / fy) * My + ra % fy) * W;
     const bool hb = rb < rows;
@@ -204,18 +245,18 @@ k_fft_x_inv(const C2<T>* __restrict__ out, int fz, int fy, int fx, int My, int W
   __syncthreads();
   fft_line<T, L, true>(line, w, tw);
   __syncthreads();                                   // stores read four lines
-  for (int idx = t; idx < G * 2 * fx; idx += S::NT) {
+  for (int idx = t; idx < G * 2 * fx; idx += nt) {
     const int gg = idx / (2 * fx), rem = idx % (2 * fx);
     const int half = rem / fx, x = rem % fx;
-    const int64_t r = 2 * ((int64_t)blockIdx.x * G + gg) + half;
+    const int64_t r = 2 * (blk * G + gg) + half;
     if (r < rows) {
       const int xi = (ox + x) & (L - 1);
-      const C2<T>* L0 = lds + (4 * gg) * S::LS + xi;
+      const C2<T>* L0 = lds + (4 * gg) * L + xi;
       V4<T> o;
       if (half == 0) {
-        o.x = L0[0].x; o.y = L0[S::LS].x; o.z = L0[2 * S::LS].x; o.w = L0[3 * S::LS].x;
+        o.x = L0[0].x; o.y = L0[L].x; o.z = L0[2 * L].x; o.w = L0[3 * L].x;
       } else {
-        o.x = L0[0].y; o.y = L0[S::LS].y; o.z = L0[2 * S::LS].y; o.w = L0[3 * S::LS].y;
+        o.x = L0[0].y; o.y = L0[L].y; o.z = L0[2 * L].y; o.w = L0[3 * L].y;
       }
       field[r * fx + x] = o;
     }
@@ -223,11 +264,38 @@ k_fft_x_inv(const C2<T>* __restrict__ out, int fz, int fy, int fx, int My, int W
 }
 
 // ------------------------------------------------------------------ launchers --
-template <typename T, int L>
-static size_t lds_bytes() { return (size_t)FFTShape<T, L>::NL * FFTShape<T, L>::LS * sizeof(C2<T>); }
+int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], int nl) {
+  const int64_t W = M[0] / 2 + 1;
+  const int64_t nbw = (W + nl - 1) / nl;
+  switch (pass) {
+    case PASS_X_FWD: return (((int64_t)g[1] * g[2] + 1) / 2 + nl - 1) / nl;
+    case PASS_Y_FWD: return nbw * g[2];
+    case PASS_Z_CONV: return nbw * M[1];
+    case PASS_Y_INV: return nbw * 4 * f[2];
+    case PASS_X_INV: return (((int64_t)f[1] * f[2] + 1) / 2 + nl / 4 - 1) / (nl / 4);
+  }
+  return 0;
+}
 
-#define APM_FFT_DISPATCH(Lv, ...)          \
-  switch (Lv) {                            \
+template <typename T> int default_lines(int pass, int L) {
+  int nl = (std::is_same<T, float>::value ? 4096 : 2048) / L;
+  if (pass == PASS_X_INV) return nl < 4 ? 4 : nl;
+  if (pass == PASS_Z_CONV) while (nl > 1 && nl * (L / 8) > kZConvMaxThreads) nl /= 2;
+  return nl;
+}
+
+// LDS bytes of a launch; 0 if the shape is not launchable (threads or LDS)
+template <typename T> size_t pass_lds(int pass, int L, int nl) {
+  const bool padded = pass == PASS_Y_FWD || pass == PASS_Z_CONV || pass == PASS_Y_INV;
+  const size_t bytes = (size_t)nl * (padded ? L + 1 : L) * sizeof(C2<T>);
+  const int max_threads = pass == PASS_Z_CONV ? kZConvMaxThreads : 1024;
+  if (nl < 1 || nl * (L / 8) > max_threads || bytes > 65536) return 0;
+  if (pass == PASS_X_INV && (nl % 4) != 0) return 0;
+  return bytes;
+}
+
+#define APM_FFT_DISPATCH(Lv, ...)                            \
+  switch (Lv) {                                              \
     case 16: { constexpr int LL = 16; __VA_ARGS__; } break;   \
     case 32: { constexpr int LL = 32; __VA_ARGS__; } break;   \
     case 64: { constexpr int LL = 64; __VA_ARGS__; } break;   \
@@ -235,76 +303,55 @@ static size_t lds_bytes() { return (size_t)FFTShape<T, L>::NL * FFTShape<T, L>::
     case 256: { constexpr int LL = 256; __VA_ARGS__; } break; \
     case 512: { constexpr int LL = 512; __VA_ARGS__; } break; \
     case 1024: { constexpr int LL = 1024; __VA_ARGS__; } break; \
-    default: return hipErrorInvalidValue;  \
+    default: return hipErrorInvalidValue;                    \
   }
 
 template <typename T>
-hipError_t launch_grid_convolution(const GridConv<T>& j, hipStream_t s, const LaunchHook& hook) {
-  const int W = j.M[0] / 2 + 1;
-  const int My = j.M[1];
-  // x forward
-  hook("fft_x_fwd", 0);
-  APM_FFT_DISPATCH(j.M[0], {
-    using S = FFTShape<T, LL>;
-    const size_t shm = lds_bytes<T, LL>();
-    const int64_t pairs = ((int64_t)j.g[1] * j.g[2] + 1) / 2;
-    const unsigned nb = (unsigned)((pairs + S::NL - 1) / S::NL);
-    hipLaunchKernelGGL((k_fft_x_fwd<T, LL>), dim3(nb), dim3(S::NT), shm, s,
-                       j.gmf, j.g[0], j.g[1], j.g[2], j.spec, My, W, (const C2<T>*)j.tw[0]);
+hipError_t launch_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, int64_t nblocks,
+                       const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* out, const void* tw,
+                       hipStream_t s) {
+  if (njobs == 0 || nblocks == 0) return hipSuccess;
+  const size_t shm = pass_lds<T>(pass, L, nl);
+  if (shm == 0) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)nblocks), block((unsigned)(nl * (L / 8)));
+  const C2<T>* twc = (const C2<T>*)tw;
+  APM_FFT_DISPATCH(L, {
+    switch (pass) {
+      case PASS_X_FWD:
+        hipLaunchKernelGGL((k_fft_x_fwd<T, LL>), grid, block, shm, s, jobs, njobs, nl, lp, spec, twc);
+        break;
+      case PASS_Y_FWD:
+        hipLaunchKernelGGL((k_fft_cols<T, LL, false>), grid, block, shm, s, jobs, njobs, nl, spec,
+                           out, twc);
+        break;
+      case PASS_Z_CONV:
+        hipLaunchKernelGGL((k_fft_z_conv<T, LL>), grid, block, shm, s, jobs, njobs, nl,
+                           (const C2<T>*)spec, out, twc);
+        break;
+      case PASS_Y_INV:
+        hipLaunchKernelGGL((k_fft_cols<T, LL, true>), grid, block, shm, s, jobs, njobs, nl, spec,
+                           out, twc);
+        break;
+      case PASS_X_INV:
+        hipLaunchKernelGGL((k_fft_x_inv<T, LL>), grid, block, shm, s, jobs, njobs, nl,
+                           (const C2<T>*)out, lp, twc);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
   });
-  hook("fft_x_fwd", 1);
-  // y forward, in place over gz planes
-  hook("fft_y_fwd", 0);
-  APM_FFT_DISPATCH(j.M[1], {
-    using S = FFTShape<T, LL>;
-    const size_t shm = lds_bytes<T, LL>();
-    const int nbw = (W + S::NL - 1) / S::NL;
-    hipLaunchKernelGGL((k_fft_cols<T, LL, false>), dim3((unsigned)(nbw * j.g[2])), dim3(S::NT),
-                       shm, s, j.spec, (int64_t)My * W, W, nbw, j.g[1], My, 0,
-                       (const C2<T>*)j.tw[1]);
-  });
-  hook("fft_y_fwd", 1);
-  // z pass with multiply, 4 outputs
-  hook("fft_z_conv", 0);
-  APM_FFT_DISPATCH(j.M[2], {
-    using S = FFTShape<T, LL>;
-    const size_t shm = lds_bytes<T, LL>();
-    const int nbw = (W + S::NL - 1) / S::NL;
-    hipLaunchKernelGGL((k_fft_z_conv<T, LL>), dim3((unsigned)(nbw * My)), dim3(S::NT),
-                       shm, s, (const C2<T>*)j.spec, j.out, j.g[2], My, W, nbw,
-                       j.f[2], j.off[2], (const C2<T>*)j.kern, j.dsym[0], j.dsym[1], j.dsym[2],
-                       (const C2<T>*)j.tw[2]);
-  });
-  hook("fft_z_conv", 1);
-  // y inverse over 4 fz planes
-  hook("fft_y_inv", 0);
-  APM_FFT_DISPATCH(j.M[1], {
-    using S = FFTShape<T, LL>;
-    const size_t shm = lds_bytes<T, LL>();
-    const int nbw = (W + S::NL - 1) / S::NL;
-    hipLaunchKernelGGL((k_fft_cols<T, LL, true>), dim3((unsigned)(nbw * 4 * j.f[2])),
-                       dim3(S::NT), shm, s, j.out, (int64_t)My * W, W, nbw, My,
-                       j.f[1], j.off[1], (const C2<T>*)j.tw[1]);
-  });
-  hook("fft_y_inv", 1);
-  // x inverse into the field box
-  hook("fft_x_inv", 0);
-  APM_FFT_DISPATCH(j.M[0], {
-    using S = XInvShape<T, LL>;
-    const size_t shm = (size_t)S::NL * S::LS * sizeof(C2<T>);
-    const int64_t pairs = ((int64_t)j.f[1] * j.f[2] + 1) / 2;
-    const unsigned nb = (unsigned)((pairs + S::NL / 4 - 1) / (S::NL / 4));
-    hipLaunchKernelGGL((k_fft_x_inv<T, LL>), dim3(nb), dim3(S::NT), shm, s,
-                       (const C2<T>*)j.out, j.f[2], j.f[1], j.f[0], My, W, j.off[0],
-                       (V4<T>*)j.field, (const C2<T>*)j.tw[0]);
-  });
-  hook("fft_x_inv", 1);
   return hipGetLastError();
 }
 
-template hipError_t launch_grid_convolution<float>(const GridConv<float>&, hipStream_t,
-                                                   const LaunchHook&);
-template hipError_t launch_grid_convolution<double>(const GridConv<double>&, hipStream_t,
-                                                    const LaunchHook&);
+template int default_lines<float>(int, int);
+template int default_lines<double>(int, int);
+template size_t pass_lds<float>(int, int, int);
+template size_t pass_lds<double>(int, int, int);
+template hipError_t launch_pass<float>(int, int, int, const ConvJob*, int, int64_t,
+                                       const LevelPtrs<float>&, C2<float>*, C2<float>*,
+                                       const void*, hipStream_t);
+template hipError_t launch_pass<double>(int, int, int, const ConvJob*, int, int64_t,
+                                        const LevelPtrs<double>&, C2<double>*, C2<double>*,
+                                        const void*, hipStream_t);
 
 }  // namespace apm

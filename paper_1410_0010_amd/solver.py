@@ -214,6 +214,18 @@ class Context:
               "apm_solve_totals")
         return np.array(out[:])
 
+    def set_graph(self, enable: bool):
+        check(_apm.lib().apm_set_graph(self.handle, 1 if enable else 0), "apm_set_graph")
+
+    def autotune(self, dtype, reps: int = 5):
+        """Pick launch shapes for every transform pass (after one solve() of dtype);
+        returns the autotuner's JSON report as a dict."""
+        import json
+        code = _apm.APM_F32 if dtype == self.torch.float32 else _apm.APM_F64
+        buf = ctypes.create_string_buffer(1 << 16)
+        check(_apm.lib().apm_autotune(self.handle, code, reps, buf, len(buf)), "apm_autotune")
+        return json.loads(buf.value.decode())
+
     def profile(self, enable: bool):
         check(_apm.lib().apm_profile(self.handle, 1 if enable else 0), "apm_profile")
 

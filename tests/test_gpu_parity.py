@@ -244,3 +244,59 @@ def test_device_error_paths():
     with pytest.raises(P.APMError) as e:
         c2.deposit(0, x, x, x, x)
     assert e.value.status == _apm.APM_ERR_OOM
+
+
+# ---- batched launches, graph replay and autotuning ------------------------------------
+
+def _solve_np(ctx, t, gas=None):
+    ax, ay, az, pot = ctx.solve(*t, gas)
+    torch.cuda.synchronize()
+    return np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy(),
+                     pot.cpu().numpy()], 1).astype(np.float64)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_graph_replays_match_eager(dtype):
+    """apm_solve is captured on its second identical call and replayed after; every
+    replay, with eager torch work and synchronisations in between, matches the
+    eager result and the oracle."""
+    w = W.workload_clumps(root_n=32, ngrids=12, per_clump=600, side_lo=6, side_hi=18)
+    say(f"[graph] clumps32 dtype={dtype.__name__}")
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    t = [dev(a, dtype) for a in (w.x, w.y, w.z, w.m)]
+    ctx.set_graph(False)
+    ref = _solve_np(ctx, t)
+    ctx.set_graph(True)
+    tol = 1e-12 if dtype == np.float64 else 2e-6
+    scratch = torch.zeros(1 << 20, device=DEV)
+    outs = [torch.empty(w.npart, dtype=t[0].dtype, device=DEV) for _ in range(4)]
+    for rep in range(5):
+        ctx.solve(*t, None, *outs)
+        scratch.add_(1.0)                       # eager work on the same stream
+        torch.cuda.synchronize()
+        got = np.stack([o.cpu().numpy() for o in outs], 1).astype(np.float64)
+        e = rel(got, ref)
+        assert e <= tol, f"replay {rep}: rel {e:.3e}"
+        outs[0].fill_(np.nan)                   # a replay must rewrite its outputs
+    oref = run_oracle(w, dtype)
+    own = oref["owner"] >= 0
+    assert rel(got[own, :3], oref["acc"][own]) <= TOL[dtype]["acc"]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_autotune_keeps_parity(dtype):
+    w = W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=2, npart=20000)
+    say(f"[autotune] nested32 dtype={dtype.__name__}")
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    t = [dev(a, dtype) for a in (w.x, w.y, w.z, w.m)]
+    _solve_np(ctx, t)
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    report = ctx.autotune(tdt, reps=3)
+    assert len(report) >= 5 and all("lines" in v for v in report.values())
+    got = _solve_np(ctx, t)
+    ref = run_oracle(w, dtype)
+    own = ref["owner"] >= 0
+    assert rel(got[own, :3], ref["acc"][own]) <= TOL[dtype]["acc"]
+    assert rel(got[own, 3], ref["pot"][own]) <= TOL[dtype]["pot"]
