@@ -50,16 +50,17 @@ def kernel_bytes(plan, npart_level, esize):
         oct_ = (Mx // 2 + 1) * (My // 2 + 1) * (Mz // 2 + 1)
         b["fft_x_fwd"] += gx * gy * gz * esize + gy * gz * W * c
         b["fft_y_fwd"] += gz * gy * W * c + gz * My * W * c
-        b["fft_z_conv"] += gz * My * W * c + oct_ * c + 4 * fz * My * W * c
-        b["fft_y_inv"] += 4 * fz * My * W * c + 4 * fz * fy * W * c
+        b["fft_z_conv"] += gz * My * W * c + oct_ * c + 3 * fz * My * W * c
+        b["fft_y_inv"] += 3 * fz * My * W * c + 4 * fz * fy * W * c
         b["fft_x_inv"] += 4 * fz * fy * W * c + fx * fy * fz * 4 * esize
         b["deposit_finalize"] += gx * gy * gz * (8 + esize)     # FP64 mass in, GMF out
-        b["compose"] += fx * fy * fz * 4 * esize * (3 if g["level"] > 0 else 2)
+        if g["level"] > 0:      # own field read and rewritten in place, parent at 1/8 density
+            b["compose"] += fx * fy * fz * 4 * esize * (2 + 1 / 8)
     for n in npart_level:
         b["deposit_tiles"] += n * 4 * esize            # sorted (s_x, s_y, s_z, m) records
     n = npart_level[0]
     nl = len(plan.levels)
-    b["bin_count"] = nl * n * (3 * esize + 8)         # positions in, key + rank out
+    b["bin_count"] = n * 3 * esize + nl * n * 8       # positions in once, key + rank per level
     b["bin_scatter"] = nl * n * (4 * esize + 8) + sum(npart_level) * (4 * esize + 4)
     b["interp"] = n * (3 * esize + 4 + 4 * esize)     # positions + owner in, a + Phi out
     return b

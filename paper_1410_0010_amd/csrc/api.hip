@@ -37,12 +37,17 @@ struct apm_ctx_s {
   std::map<std::tuple<int, int, int>, void*> dsym;                // (dtype, level, M)
   std::map<std::tuple<int, int, int, int, int>, void*> kern;      // (dtype, level, Mx, My, Mz)
   std::vector<void*> owned;                                       // every table allocation
-  DevBuf count, items, accum, keyb, rank, scan_tmp, spec, out, tmpfld, owner, totals, bin_totals;
-  std::vector<DevBuf> sorted, sidx;                               // per level
-  std::vector<int64_t> tile_total_slot;                           // per level: count index of total
-  std::vector<DevBuf> gmf[3], fld[3], own[3];                     // solve-owned, by dtype
-  size_t spec_elems = 0, out_elems = 0;                           // complex elements (sum)
-  std::vector<int64_t> spec_off, out_off;                         // per grid
+  DevBuf spec, zbuf, ybuf, tmpfld, owner, totals, binned;
+  // per level: tile counters, work items, FP64 mass grid, particle keys/ranks, the
+  // tile-sorted records and their original indices
+  struct LevelBufs { DevBuf count, items, accum, key, rank, sidx, sorted; };
+  std::vector<LevelBufs> lvb;
+  std::vector<DepLevel> dep_host;                                 // level table, host copy
+  std::vector<unsigned char> dep_dev_copy;                        // bytes last uploaded
+  DevBuf dep_tab;                                                 // level table, device
+  std::vector<DevBuf> gmf[3], fld[3];                             // solve-owned, by dtype
+  size_t spec_elems = 0, z_elems = 0, y_elems = 0;               // complex elements (sum)
+  std::vector<int64_t> spec_off, z_off, y_off;                    // per grid
   struct JobList { ConvJob* d = nullptr; int n = 0; int64_t blocks = 0; };
   // (dtype, pass, L, level or -1, lines per block) -> jobs
   std::map<std::tuple<int, int, int, int, int>, JobList> jobs;
@@ -369,7 +374,8 @@ apm_status job_list(apm_ctx c, int pass, int L, int level, int nl, const apm_ctx
     j.gmf_off = g.gmf_offset;
     j.fld_off = g.fld_offset;
     j.spec_off = c->spec_off[gi];
-    j.out_off = c->out_off[gi];
+    j.z_off = c->z_off[gi];
+    j.y_off = c->y_off[gi];
     APM_TRY(kernel_table(c, dt, g, &j.kern));
     for (int a = 0; a < 3; ++a) {
       const T* d = nullptr;
@@ -408,7 +414,8 @@ apm_status convolve_t(apm_ctx c, int level, const LevelPtrs<T>& lp) {
   const std::vector<int> set = grid_set(c, level);
   APM_TRY(prepare_tables<T>(c, set));
   APM_TRY(ensure(c, c->spec, c->spec_elems * sizeof(C2<T>), "spectrum buffer"));
-  APM_TRY(ensure(c, c->out, c->out_elems * sizeof(C2<T>), "output spectra buffer"));
+  APM_TRY(ensure(c, c->zbuf, c->z_elems * sizeof(C2<T>), "z-pass output buffer"));
+  APM_TRY(ensure(c, c->ybuf, c->y_elems * sizeof(C2<T>), "y-pass output buffer"));
   for (int pass = PASS_X_FWD; pass <= PASS_X_INV; ++pass) {
     for (int L : pass_lengths(c, pass, level)) {
       const int nl = lines_for<T>(c, pass, L);
@@ -418,7 +425,8 @@ apm_status convolve_t(apm_ctx c, int level, const LevelPtrs<T>& lp) {
       APM_TRY(twiddles<T>(c, L, &tw));
       HIP_TRY(timed(c, pass_name(pass), [&] {
                 return launch_pass<T>(pass, L, nl, jl->d, jl->n, jl->blocks, lp,
-                                      (C2<T>*)c->spec.p, (C2<T>*)c->out.p, tw, c->stream);
+                                      (C2<T>*)c->spec.p, (C2<T>*)c->zbuf.p, (C2<T>*)c->ybuf.p,
+                                      tw, c->stream);
               }), pass_name(pass));
     }
   }
@@ -433,91 +441,113 @@ apm_status solve_level_t(apm_ctx c, int32_t level, const T* gmf, T* field) {
   return convolve_t<T>(c, level, lp);
 }
 
+// Uploads the level table if its bytes changed (buffers moved): the stream is
+// drained first so no kernel still reads the old table.
+apm_status sync_dep_table(apm_ctx c) {
+  const size_t bytes = c->dep_host.size() * sizeof(DepLevel);
+  const unsigned char* src = (const unsigned char*)c->dep_host.data();
+  if (c->dep_tab.p && c->dep_dev_copy.size() == bytes &&
+      std::memcmp(c->dep_dev_copy.data(), src, bytes) == 0)
+    return APM_OK;
+  APM_TRY(ensure(c, c->dep_tab, bytes, "level table"));
+  HIP_TRY(hipStreamSynchronize(c->stream), "level table: sync");
+  HIP_TRY(hipMemcpy(c->dep_tab.p, src, bytes, hipMemcpyHostToDevice), "level table upload");
+  c->dep_dev_copy.assign(src, src + bytes);
+  c->epoch++;
+  return APM_OK;
+}
+
+// TSC deposit of levels [l0, l0 + nlev) (Sec. 2): six launches for the batch --
+// clear, tile count, scans, scatter, tile deposit, finalize.  gas/pgas/gmf are
+// indexed by batch position.
 template <typename T>
-apm_status deposit_t(apm_ctx c, int32_t level, const T* x, const T* y, const T* z, const T* m,
-                     int64_t npart, const T* gas, const T* pgas, T* gmf) {
-  const LevelDesc& L = c->plan.levels[level];
-  const int64_t K = L.key_cells;
-  int32_t tn[3];
-  int64_t ntiles = 1;
-  for (int a = 0; a < 3; ++a) {
-    tn[a] = (L.key_n[a] + kTile - 1) / kTile;
-    ntiles *= tn[a];
+apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y, const T* z,
+                            const T* m, int64_t npart, const T* const* gas, const T* const* pgas,
+                            T* const* gmf) {
+  const Plan& P = c->plan;
+  const int nl = (int)P.levels.size();
+  c->lvb.resize(nl);
+  if ((int)c->dep_host.size() != nl) {
+    c->dep_host.resize(nl);
+    std::memset((void*)c->dep_host.data(), 0, nl * sizeof(DepLevel));
   }
-  // counter replicas per tile (blocks pick one by index): up to 16, about 2^18
-  // counters in all
-  int32_t rep = 1;
-  while (rep < 16 && ntiles * rep * 2 <= ((int64_t)1 << 18)) rep *= 2;
-  const int64_t ncount = ntiles * rep + 1;
-  APM_TRY(ensure(c, c->count, (size_t)ncount * 4, "tile counts"));
-  APM_TRY(ensure(c, c->items, (size_t)(ntiles + 1) * 4, "tile work items"));
-  APM_TRY(ensure(c, c->scan_tmp, scan_tmp_elems(ncount) * 4, "scan scratch"));
-  APM_TRY(ensure(c, c->accum, (size_t)K * 8, "fp64 mass grid"));
+  APM_TRY(ensure(c, c->binned, (size_t)nl * 4, "binned totals"));
   const size_t np = (size_t)std::max<int64_t>(npart, 1);
-  APM_TRY(ensure(c, c->keyb, np * 4, "particle keys"));
-  APM_TRY(ensure(c, c->rank, np * 4, "particle ranks"));
-  c->sorted.resize(c->plan.levels.size());
-  c->sidx.resize(c->plan.levels.size());
-  APM_TRY(ensure(c, c->sorted[level], np * sizeof(V4<T>), "sorted particles"));
-  APM_TRY(ensure(c, c->sidx[level], np * 4, "sorted particle indices"));
-  int32_t* count = (int32_t*)c->count.p;
-  int32_t* items = (int32_t*)c->items.p;
-  double* accum = (double*)c->accum.p;
-  HIP_TRY(timed(c, "bin_clear", [&] {
-            hipError_t e = launch_fill_i32(count, ncount, 0, c->stream);
-            return e != hipSuccess ? e : launch_fill_f64(accum, K, 0.0, c->stream);
-          }), "clear");
-  BinParams<T> bp{};
-  bp.x = x; bp.y = y; bp.z = z; bp.m = m;
-  bp.npart = npart;
-  bp.inv_dx = 1.0 / L.dx;
-  for (int a = 0; a < 3; ++a) {
-    bp.key_lo[a] = L.key_lo[a];
-    bp.key_n[a] = L.key_n[a];
-    bp.tiles_n[a] = tn[a];
+  DepIO<T> io{};
+  io.x = x; io.y = y; io.z = z; io.m = m;
+  io.npart = npart;
+  io.nlev = nlev;
+  int64_t max_elems = 0, iblk = 0, fblk = 0;
+  for (int b = 0; b < nlev; ++b) {
+    const int l = l0 + b;
+    const LevelDesc& L = P.levels[l];
+    apm_ctx_s::LevelBufs& B = c->lvb[l];
+    int32_t tn[3];
+    int64_t ntiles = 1;
+    for (int a = 0; a < 3; ++a) {
+      tn[a] = (L.key_n[a] + kTile - 1) / kTile;
+      ntiles *= tn[a];
+    }
+    // counter replicas per tile (blocks pick one by index): up to 16, about 2^17
+    // counters in all; the many blocks of a dense core then spread their one atomic
+    // per (block, tile) over 16 addresses
+    int32_t rep = 1;
+    while (rep < 16 && ntiles * rep * 2 <= ((int64_t)1 << 18)) rep *= 2;
+    const int64_t ncount = ntiles * rep + 1;
+    APM_TRY(ensure(c, B.count, (size_t)ncount * 4, "tile counts"));
+    APM_TRY(ensure(c, B.items, (size_t)(ntiles + 1) * 4, "tile work items"));
+    APM_TRY(ensure(c, B.accum, (size_t)L.key_cells * 8, "fp64 mass grid"));
+    APM_TRY(ensure(c, B.key, np * 4, "particle keys"));
+    APM_TRY(ensure(c, B.rank, np * 4, "particle ranks"));
+    APM_TRY(ensure(c, B.sidx, np * 4, "sorted particle indices"));
+    APM_TRY(ensure(c, B.sorted, np * sizeof(V4<T>), "sorted particles"));
+    DepLevel d;
+    std::memset((void*)&d, 0, sizeof d);
+    d.inv_dx = 1.0 / L.dx;
+    d.dx = L.dx;
+    for (int a = 0; a < 3; ++a) {
+      d.key_lo[a] = L.key_lo[a];
+      d.key_n[a] = L.key_n[a];
+      d.tiles_n[a] = tn[a];
+    }
+    d.ntiles = (int32_t)ntiles;
+    d.rep = rep;
+    d.ngrids = L.count;
+    d.key_cells = L.key_cells;
+    d.count = (int32_t*)B.count.p;
+    d.items = (int32_t*)B.items.p;
+    d.key = (int32_t*)B.key.p;
+    d.rank = (int32_t*)B.rank.p;
+    d.sidx = (int32_t*)B.sidx.p;
+    d.sorted = B.sorted.p;
+    d.accum = (double*)B.accum.p;
+    d.grids = c->d_grids + L.first;
+    d.block_begin = c->d_dep_begin[l];
+    d.binned = (int32_t*)c->binned.p + l;
+    std::memcpy((void*)&c->dep_host[l], &d, sizeof d);
+    max_elems = std::max(max_elems, std::max(ncount, (int64_t)L.key_cells));
+    io.item_blk0[b] = iblk;
+    iblk += ntiles + (npart + kChunk - 1) / kChunk;
+    io.fin_blk0[b] = fblk;
+    fblk += c->dep_blocks[l];
+    io.gas[b] = gas ? gas[b] : nullptr;
+    io.pgas[b] = pgas ? pgas[b] : nullptr;
+    io.gmf[b] = gmf[b];
   }
-  bp.rep = rep;
-  bp.count = count;
-  bp.key = (int32_t*)c->keyb.p;
-  bp.rank = (int32_t*)c->rank.p;
-  bp.sidx = (int32_t*)c->sidx[level].p;
-  HIP_TRY(timed(c, "bin_count", [&] { return launch_bin_count<T>(bp, c->stream); }), "bin count");
-  HIP_TRY(timed(c, "bin_scan", [&] {
-            hipError_t e = launch_exclusive_scan(count, ncount, (int32_t*)c->scan_tmp.p, c->stream);
-            if (e == hipSuccess) e = launch_chunk_count(count, (int32_t)ntiles, rep, items, c->stream);
-            return e != hipSuccess ? e
-                                   : launch_exclusive_scan(items, ntiles + 1, (int32_t*)c->scan_tmp.p,
-                                                           c->stream);
-          }), "scan");
-  HIP_TRY(timed(c, "bin_scatter", [&] {
-            return launch_bin_scatter<T>(bp, count, (V4<T>*)c->sorted[level].p, c->stream);
-          }), "bin scatter");
-  APM_TRY(ensure(c, c->bin_totals, c->plan.levels.size() * 4, "binned totals"));
-  HIP_TRY(launch_copy_i32(count + (ncount - 1), (int32_t*)c->bin_totals.p + level, c->stream),
-          "binned total");
-  TileDepositParams<T> tp{};
-  tp.sorted = (const V4<T>*)c->sorted[level].p;
-  tp.start = count;
-  tp.item_start = items;
-  tp.ntiles = (int32_t)ntiles;
-  tp.rep = rep;
-  for (int a = 0; a < 3; ++a) { tp.key_n[a] = L.key_n[a]; tp.tiles_n[a] = tn[a]; }
-  tp.accum = accum;
-  const int64_t max_items = ntiles + (npart + kChunk - 1) / kChunk;
-  HIP_TRY(timed(c, "deposit_tiles", [&] { return launch_deposit_tiles<T>(tp, max_items, c->stream); }),
+  io.item_blk0[nlev] = iblk;
+  io.fin_blk0[nlev] = fblk;
+  APM_TRY(sync_dep_table(c));
+  const DepLevel* tab = (const DepLevel*)c->dep_tab.p + l0;
+  HIP_TRY(timed(c, "bin_clear", [&] { return launch_dep_clear(tab, nlev, max_elems, c->stream); }),
+          "clear");
+  HIP_TRY(timed(c, "bin_count", [&] { return launch_bin_count<T>(io, tab, c->stream); }), "bin count");
+  HIP_TRY(timed(c, "bin_scan", [&] { return launch_bin_scan(tab, nlev, c->stream); }), "bin scan");
+  HIP_TRY(timed(c, "bin_scatter", [&] { return launch_bin_scatter<T>(io, tab, c->stream); }),
+          "bin scatter");
+  HIP_TRY(timed(c, "deposit_tiles", [&] { return launch_deposit_tiles<T>(io, tab, c->stream); }),
           "deposit tiles");
-  DepositParams<T> dp{};
-  dp.grids = c->d_grids + L.first;
-  dp.block_begin = c->d_dep_begin[level];
-  dp.ngrids = L.count;
-  dp.accum = accum;
-  for (int a = 0; a < 3; ++a) { dp.key_lo[a] = L.key_lo[a]; dp.key_n[a] = L.key_n[a]; }
-  dp.dx = L.dx;
-  dp.gas = gas;
-  dp.parent_gas = pgas;
-  dp.gmf = gmf;
   HIP_TRY(timed(c, "deposit_finalize", [&] {
-            return launch_deposit<T>(dp, c->dep_blocks[level], c->stream);
+            return launch_deposit_finalize<T>(io, tab, c->stream);
           }), "deposit finalize");
   return APM_OK;
 }
@@ -555,25 +585,31 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
             return launch_owner<T>(c->d_grids, (int32_t)P.grids.size(), (double)P.cfg.root_n, x, y,
                                    z, npart, own, c->stream);
           }), "owner");
-  for (int l = 0; l < nl; ++l) {
-    const T* g = gas ? (const T*)gas[l] : nullptr;
-    const T* pg = (gas && l > 0) ? (const T*)gas[l - 1] : nullptr;
-    APM_TRY(deposit_t<T>(c, l, x, y, z, m, npart, g, pg, (T*)c->gmf[di][l].p));
+  {
+    const T* gl[kMaxLevels];
+    const T* pg[kMaxLevels];
+    T* gm[kMaxLevels];
+    for (int l = 0; l < nl; ++l) {
+      gl[l] = gas ? (const T*)gas[l] : nullptr;
+      pg[l] = (gas && l > 0) ? (const T*)gas[l - 1] : nullptr;
+      gm[l] = (T*)c->gmf[di][l].p;
+    }
+    APM_TRY(deposit_levels_t<T>(c, 0, nl, x, y, z, m, npart, gl, pg, gm));
   }
-  c->own[di].resize(nl);
+  // each grid's own field is written straight into the level field, then the
+  // parent's composed field is added in place, level by level (the root has none)
   LevelPtrs<T> lp{};
   for (int l = 0; l < nl; ++l) {
-    APM_TRY(ensure(c, c->own[di][l], (size_t)P.levels[l].fld_cells * sizeof(V4<T>), "level own field"));
     lp.gmf[l] = (const T*)c->gmf[di][l].p;
-    lp.fld[l] = (V4<T>*)c->own[di][l].p;
+    lp.fld[l] = (V4<T>*)c->fld[di][l].p;
   }
   APM_TRY(convolve_t<T>(c, -1, lp));
-  for (int l = 0; l < nl; ++l) {
+  for (int l = 1; l < nl; ++l) {
     const LevelDesc& L = P.levels[l];
     HIP_TRY(timed(c, "compose", [&] {
               return launch_compose<T>(c->d_grids + L.first, c->d_cmp_begin[l], L.count,
-                                       (const V4<T>*)c->own[di][l].p,
-                                       l > 0 ? (const V4<T>*)c->fld[di][l - 1].p : nullptr,
+                                       (const V4<T>*)c->fld[di][l].p,
+                                       (const V4<T>*)c->fld[di][l - 1].p,
                                        (V4<T>*)c->fld[di][l].p, c->cmp_blocks[l], c->stream);
             }), "compose");
   }
@@ -645,13 +681,13 @@ template <typename T>
 apm_status autotune_t(apm_ctx c, apm_dtype dt, int reps) {
   const int di = (int)dt;
   const int nl = (int)c->plan.levels.size();
-  if ((int)c->own[di].size() != nl || !c->spec.p)
+  if ((int)c->fld[di].size() != nl || !c->spec.p)
     return fail(APM_ERR_STATE, "apm_autotune: run apm_solve of this precision first");
   HIP_TRY(hipStreamSynchronize(c->stream), "autotune sync");
   LevelPtrs<T> lp{};
   for (int l = 0; l < nl; ++l) {
     lp.gmf[l] = (const T*)c->gmf[di][l].p;
-    lp.fld[l] = (V4<T>*)c->own[di][l].p;
+    lp.fld[l] = (V4<T>*)c->fld[di][l].p;
   }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "event");
@@ -672,11 +708,13 @@ apm_status autotune_t(apm_ctx c, apm_dtype dt, int reps) {
         const apm_ctx_s::JobList* jl = nullptr;
         APM_TRY(job_list<T>(c, pass, L, -1, nlc, &jl));
         HIP_TRY(launch_pass<T>(pass, L, nlc, jl->d, jl->n, jl->blocks, lp, (C2<T>*)c->spec.p,
-                               (C2<T>*)c->out.p, tw, c->stream), "autotune warm-up");
+                               (C2<T>*)c->zbuf.p, (C2<T>*)c->ybuf.p, tw, c->stream),
+                "autotune warm-up");
         HIP_TRY(hipEventRecord(e0, c->stream), "event");
         for (int r = 0; r < reps; ++r)
           HIP_TRY(launch_pass<T>(pass, L, nlc, jl->d, jl->n, jl->blocks, lp, (C2<T>*)c->spec.p,
-                                 (C2<T>*)c->out.p, tw, c->stream), "autotune launch");
+                                 (C2<T>*)c->zbuf.p, (C2<T>*)c->ybuf.p, tw, c->stream),
+                  "autotune launch");
         HIP_TRY(hipEventRecord(e1, c->stream), "event");
         HIP_TRY(hipEventSynchronize(e1), "event");
         float ms = 0.f;
@@ -738,9 +776,11 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
       cmp[i + 1] = cmp[i] + (fc + kBlock - 1) / kBlock;
       const int64_t W = g.M[0] / 2 + 1;
       c->spec_off.push_back((int64_t)c->spec_elems);
-      c->out_off.push_back((int64_t)c->out_elems);
+      c->z_off.push_back((int64_t)c->z_elems);
+      c->y_off.push_back((int64_t)c->y_elems);
       c->spec_elems += (size_t)(g.gmf_n[2] * (int64_t)g.M[1] * W);
-      c->out_elems += (size_t)(4 * (int64_t)g.fld_n[2] * g.M[1] * W);
+      c->z_elems += (size_t)(3 * (int64_t)g.fld_n[2] * g.M[1] * W);
+      c->y_elems += (size_t)(4 * (int64_t)g.fld_n[2] * g.fld_n[1] * W);
     }
     void *d1 = nullptr, *d2 = nullptr;
     st = upload(c, &d1, dep.data(), dep.size() * 8, "deposit block table");
@@ -764,18 +804,16 @@ apm_status apm_destroy(apm_ctx c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* p : c->owned) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-  DevBuf* bufs[] = {&c->count, &c->items, &c->accum, &c->keyb, &c->rank,
-                    &c->scan_tmp, &c->spec, &c->out, &c->tmpfld, &c->owner, &c->totals,
-                    &c->bin_totals};
-  for (auto& b : c->sorted) if (b.p) (void)hipFree(b.p);
-  for (auto& b : c->sidx) if (b.p) (void)hipFree(b.p);
+  DevBuf* bufs[] = {&c->spec, &c->zbuf, &c->ybuf, &c->tmpfld, &c->owner, &c->totals,
+                    &c->binned, &c->dep_tab};
+  for (auto& B : c->lvb)
+    for (DevBuf* b : {&B.count, &B.items, &B.accum, &B.key, &B.rank, &B.sidx, &B.sorted})
+      if (b->p) (void)hipFree(b->p);
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& v : c->gmf)
     for (auto& b : v) if (b.p) (void)hipFree(b.p);
   for (auto& v : c->fld)
-    for (auto& b : v) if (b.p) (void)hipFree(b.p);
-  for (auto& v : c->own)
     for (auto& b : v) if (b.p) (void)hipFree(b.p);
   delete c;
   return APM_OK;
@@ -814,13 +852,18 @@ apm_status apm_deposit(apm_ctx c, apm_dtype dt, int32_t level, const void* x, co
   if (!gmf || (npart > 0 && (!x || !y || !z || !m)))
     return fail(APM_ERR_INVALID, "apm_deposit: NULL array");
   if (level == 0 && parent_gas) return fail(APM_ERR_INVALID, "apm_deposit: root has no parent gas");
-  if (dt == APM_F32)
-    return deposit_t<float>(c, level, (const float*)x, (const float*)y, (const float*)z,
-                            (const float*)m, npart, (const float*)gas, (const float*)parent_gas,
-                            (float*)gmf);
-  return deposit_t<double>(c, level, (const double*)x, (const double*)y, (const double*)z,
-                           (const double*)m, npart, (const double*)gas, (const double*)parent_gas,
-                           (double*)gmf);
+  if (dt == APM_F32) {
+    const float* g = (const float*)gas;
+    const float* pg = (const float*)parent_gas;
+    float* out = (float*)gmf;
+    return deposit_levels_t<float>(c, level, 1, (const float*)x, (const float*)y, (const float*)z,
+                                   (const float*)m, npart, &g, &pg, &out);
+  }
+  const double* g = (const double*)gas;
+  const double* pg = (const double*)parent_gas;
+  double* out = (double*)gmf;
+  return deposit_levels_t<double>(c, level, 1, (const double*)x, (const double*)y,
+                                  (const double*)z, (const double*)m, npart, &g, &pg, &out);
 }
 
 apm_status apm_solve_level(apm_ctx c, apm_dtype dt, int32_t level, const void* gmf, void* field) {

@@ -29,12 +29,13 @@ enum { PASS_X_FWD = 0, PASS_Y_FWD = 1, PASS_Z_CONV = 2, PASS_Y_INV = 3, PASS_X_I
 // One grid in one pass: GMF (dims g) zero-padded into FFT box M, outputs on the field
 // box (dims f) whose first cell sits at transform index off (cyclic).  Offsets are
 // in elements of the level GMF buffer, the level field buffer (cells) and the
-// shared spectrum / output-spectra buffers (complex values).
+// shared spectrum, z-output (3 fz My W per grid) and y-output (4 fz fy W per grid)
+// buffers (complex values).
 struct ConvJob {
   int64_t blk0;                    // first block of this job in its launch
   int32_t level;
   int32_t g[3], M[3], f[3], off[3];
-  int64_t gmf_off, fld_off, spec_off, out_off;
+  int64_t gmf_off, fld_off, spec_off, z_off, y_off;
   const void* kern;                // octant (Gf, Gp) table
   const void* dsym[3];             // gradient symbols per axis index
 };
@@ -43,8 +44,8 @@ template <typename T> int default_lines(int pass, int L);
 template <typename T> size_t pass_lds(int pass, int L, int nl);   // 0: not launchable
 template <typename T>
 hipError_t launch_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, int64_t nblocks,
-                       const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* out, const void* tw,
-                       hipStream_t s);
+                       const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* zbuf, C2<T>* ybuf,
+                       const void* tw, hipStream_t s);
 
 // Green's functions (FP64): octant table of (force, potential) times `norm`.
 struct InfluenceParams {
@@ -60,55 +61,54 @@ hipError_t launch_james(int N, double dx, double a0, double G, const double* cos
 hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 
 // Particles: binning by 8^3 tile of the particle's cell i0 = floor(x/dx) inside the
-// level's binning box (union of GMF boxes grown by one cell).
+// level's binning box (union of GMF boxes grown by one cell), then the tile-wise
+// TSC deposit.  Every stage is one launch over a batch of consecutive levels.
 constexpr int kTile = 8;
 constexpr int kChunk = 2048;       // particles per deposit work item
-template <typename T> struct BinParams {
-  const T* x; const T* y; const T* z; const T* m;
-  int64_t npart;
-  double inv_dx;
+
+// Static part of one level (device table, rewritten only when buffers move).
+struct DepLevel {
+  double inv_dx, dx;
   int32_t key_lo[3], key_n[3];     // binning box (cells)
   int32_t tiles_n[3];              // tiles per axis
-  int32_t rep;                     // counter replicas per tile (power of two)
-  int32_t* count;                  // tiles * rep + 1 (zeroed by caller), scanned in place;
-                                   // replica r of tile t at t * rep + r
+  int32_t ntiles, rep;             // rep: counter replicas per tile (power of two)
+  int32_t ngrids;
+  int64_t key_cells;
+  int32_t* count;                  // ntiles * rep + 1; replica r of tile t at t rep + r;
+                                   // scanned in place into start offsets
+  int32_t* items;                  // ntiles + 1: scanned work-item counts
   int32_t* key;                    // npart: counter slot or -1
   int32_t* rank;                   // npart: rank within the slot
-  int32_t* sidx;                   // sorted position -> original index (written by scatter)
+  int32_t* sidx;                   // sorted position -> original index
+  void* sorted;                    // npart records (s_x, s_y, s_z, m), s = x/dx - key_lo
+  double* accum;                   // key_cells FP64 mass
+  const GridDesc* grids;           // the level's grids
+  const int64_t* block_begin;      // first finalize block of each grid (ngrids + 1)
+  int32_t* binned;                 // number of particles binned on the level
 };
-template <typename T> hipError_t launch_bin_count(const BinParams<T>& p, hipStream_t s);
-template <typename T> hipError_t launch_bin_scatter(const BinParams<T>& p, const int32_t* start,
-                                                    V4<T>* sorted, hipStream_t s);
-hipError_t launch_exclusive_scan(int32_t* data, int64_t n, int32_t* tmp, hipStream_t s);
-size_t scan_tmp_elems(int64_t n);
-// items[t] = ceil((start[(t+1) rep]-start[t rep]) / kChunk) for t < ntiles, items[ntiles] = 0
-hipError_t launch_chunk_count(const int32_t* start, int32_t ntiles, int32_t rep, int32_t* items,
-                              hipStream_t s);
 
-template <typename T> struct TileDepositParams {
-  const V4<T>* sorted;             // (s_x, s_y, s_z, m), s = x/dx - binning-box origin
-  const int32_t* start;            // scanned replica counts (ntiles * rep + 1)
-  const int32_t* item_start;       // scanned chunk counts (ntiles + 1)
-  int32_t ntiles, rep;
-  int32_t key_n[3], tiles_n[3];
-  double* accum;                   // key-box cells, FP64, zeroed by caller
+// Per-call part: the particles, the batch's block offsets and its in/out buffers
+// (index b = level - first level of the batch).
+template <typename T> struct DepIO {
+  const T* x; const T* y; const T* z; const T* m;
+  int64_t npart;
+  int32_t nlev;
+  int64_t item_blk0[kMaxLevels + 1];   // deposit-tile blocks of level b: [item_blk0[b], [b+1])
+  int64_t fin_blk0[kMaxLevels + 1];    // finalize blocks of level b
+  const T* gas[kMaxLevels];            // level active gas (packed) or null
+  const T* pgas[kMaxLevels];           // parent level active gas (packed) or null
+  T* gmf[kMaxLevels];
 };
-template <typename T> hipError_t launch_deposit_tiles(const TileDepositParams<T>& p, int64_t max_items,
+hipError_t launch_dep_clear(const DepLevel* tab, int nlev, int64_t max_elems, hipStream_t s);
+template <typename T> hipError_t launch_bin_count(const DepIO<T>& io, const DepLevel* tab,
+                                                  hipStream_t s);
+hipError_t launch_bin_scan(const DepLevel* tab, int nlev, hipStream_t s);
+template <typename T> hipError_t launch_bin_scatter(const DepIO<T>& io, const DepLevel* tab,
+                                                    hipStream_t s);
+template <typename T> hipError_t launch_deposit_tiles(const DepIO<T>& io, const DepLevel* tab,
                                                       hipStream_t s);
-
-template <typename T> struct DepositParams {
-  const GridDesc* grids;   // device copy of the level's grids
-  const int64_t* block_begin;  // device: first block of each grid (count + 1 entries)
-  int32_t ngrids;
-  const double* accum;     // FP64 mass per key-box cell
-  int32_t key_lo[3], key_n[3];
-  double dx;
-  const T* gas;            // level active gas (packed) or null
-  const T* parent_gas;     // parent level active gas (packed) or null
-  T* gmf;
-};
-template <typename T> hipError_t launch_deposit(const DepositParams<T>& p, int64_t nblocks,
-                                                hipStream_t s);
+template <typename T> hipError_t launch_deposit_finalize(const DepIO<T>& io, const DepLevel* tab,
+                                                         hipStream_t s);
 
 template <typename T> hipError_t launch_owner(const GridDesc* grids, int32_t ngrids, double root_n,
                                               const T* x, const T* y, const T* z, int64_t npart,
@@ -117,14 +117,6 @@ template <typename T> hipError_t launch_interp(const GridDesc* grids, int32_t le
                                                const V4<T>* field, const T* x, const T* y,
                                                const T* z, const int32_t* owner, int64_t npart,
                                                T* ax, T* ay, T* az, T* pot, hipStream_t s);
-// level `level` over the level's tile-sorted particles (sorted, sidx, total binned
-// count at *total); writes the particles whose owner grid is on that level.
-template <typename T> hipError_t launch_interp_sorted(const GridDesc* grids, int32_t level,
-                                                      const V4<T>* field, const V4<T>* sorted,
-                                                      const int32_t* sidx, const int32_t* total,
-                                                      int64_t max_n, const int32_t key_lo[3],
-                                                      const int32_t* owner, T* ax, T* ay, T* az,
-                                                      T* pot, hipStream_t s);
 // every level in one launch: fields[l] is level l's composed field
 template <typename T> struct FieldTable { const V4<T>* f[kMaxLevels]; };
 template <typename T> hipError_t launch_interp_all(const GridDesc* grids, const FieldTable<T>& fields,

@@ -14,7 +14,22 @@ template <> struct vec<double> { using c2 = double2; using c4 = double4; };
 template <typename T> using C2 = typename vec<T>::c2;
 template <typename T> using V4 = typename vec<T>::c4;
 
+// Tables reached through pointers stored in job records are in global memory, but
+// the compiler cannot tell and would use flat loads, which count against the LDS
+// wait counter too (an LDS wait then also waits for them).  Reading through a
+// global-address-space pointer gives plain global loads.
+template <typename T> using gptr = const __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(const void* p) {
+  return (gptr<T>)p;
+}
+template <typename T> using nvec2 = T __attribute__((ext_vector_type(2)));
+
 template <typename T> __device__ __forceinline__ C2<T> mk(T x, T y) { C2<T> r; r.x = x; r.y = y; return r; }
+// complex element i of a global table reached through a job record
+template <typename T> __device__ __forceinline__ C2<T> load_c2(const void* base, int64_t i) {
+  const nvec2<T> v = as_global<nvec2<T>>(base)[i];
+  return mk<T>(v.x, v.y);
+}
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { a.x += b.x; a.y += b.y; return a; }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { a.x -= b.x; a.y -= b.y; return a; }
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) {

@@ -7,9 +7,12 @@
 //   x_fwd   GMF rows (gx reals, zero-padded to Mx) -> half spectra, two real rows
 //           per complex FFT                                   (gy*gz rows)
 //   y_fwd   columns along y: gy inputs -> My outputs, in place (gz planes)
-//   z_conv  columns along z: gz inputs -> Mz-point forward FFT -> times the four
-//           multipliers -> four inverse FFTs -> fz outputs each (My*W columns)
-//   y_inv   columns along y: My inputs -> fy outputs, in place (4 fz planes)
+//   z_conv  columns along z: gz inputs -> Mz-point forward FFT -> times three
+//           multipliers (Gf, -i d_z Gf, Gp) -> three inverse FFTs -> fz outputs each
+//   y_inv   columns along y: the three z outputs -> four lines per column (a_x from
+//           Gf, a_y = -i d_y Gf, a_z, Phi) -> My-point inverse FFTs -> fy outputs
+//           (the x and y derivatives are applied where d_x, d_y vary along the
+//           line: in the x and y inverse passes; along z they are constants)
 //   x_inv   two rows of one component per complex inverse FFT, Hermitian rows ->
 //           real field-box rows, written as 4-vectors per cell (fy*fz rows)
 // Zero planes/rows of the padding are never read or transformed twice: y_fwd reads
@@ -78,61 +81,64 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
   }
 }
 
-// ------------------------------------------------- strided columns (y passes) --
-// Lines along y of planes p: element (p, row, column) at buf[p My W + row W + col].
-// INV = false: spectrum, planes z < gz, rows [0, gy) in, all My rows out.
-// INV = true:  output spectra, planes 4 fz, all My rows in, rows j < fy out taken
-//              from transform index (off_y + j) mod L.  In place.
-template <typename T, int L, bool INV>
+// ------------------------------------------------------ y forward (columns) --
+// Lines along y of the gz spectrum planes: rows [0, gy) in, all My rows out, in place.
+template <typename T, int L>
 __global__ void __launch_bounds__(1024)
-k_fft_cols(const ConvJob* __restrict__ jobs, int njobs, int nl, C2<T>* __restrict__ specb,
-           C2<T>* __restrict__ outb, const C2<T>* __restrict__ tw) {
+k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* __restrict__ specb,
+            const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
-  constexpr int LS = L + 1;
   const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
   const int64_t blk = blockIdx.x - J.blk0;
-  const int W = J.M[0] / 2 + 1, My = J.M[1];
+  const int W = J.M[0] / 2 + 1, My = J.M[1], gy = J.g[1];
   const int nbw = (W + nl - 1) / nl;
   const int64_t p = blk / nbw;
   const int c0 = (int)(blk % nbw) * nl;
-  const int n_in = INV ? My : J.g[1];
-  const int n_out = INV ? J.f[1] : My;
-  const int oo = INV ? J.off[1] : 0;
-  C2<T>* base = (INV ? outb + J.out_off : specb + J.spec_off) + p * ((int64_t)My * W) + c0;
-  const int nt = nl * (L / 8);
+  C2<T>* base = specb + J.spec_off + p * ((int64_t)My * W) + c0;
   const int t = threadIdx.x;
-  for (int idx = t; idx < nl * L; idx += nt) {
-    const int bb = idx % nl, r = idx / nl;
-    C2<T> v = mk<T>(0, 0);
-    if (r < n_in && c0 + bb < W) v = base[(int64_t)r * W + bb];
-    lds[bb * LS + r] = v;
+  // column-wise mapping: thread t holds column t mod nl, rows t/nl + q L/8 (nl L/8
+  // threads, 8 elements each; all loads issued before the first LDS write)
+  const int cb = t % nl, r0 = t / nl;
+  const bool col_ok = c0 + cb < W;
+  C2<T> v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int r = r0 + q * (L / 8);
+    v[q] = (r < gy && col_ok) ? base[(int64_t)r * W + cb] : mk<T>(0, 0);
   }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
   __syncthreads();
   const int b = t / (L / 8), w = t % (L / 8);
-  fft_line<T, L, INV>(lds + b * LS, w, tw);
+  fft_line<T, L, false>(lds + b * ls, w, tw);
   __syncthreads();                                   // stores use another mapping
-  for (int idx = t; idx < nl * n_out; idx += nt) {
-    const int bb = idx % nl, j = idx / nl;
-    if (c0 + bb < W) base[(int64_t)j * W + bb] = lds[bb * LS + ((oo + j) & (L - 1))];
+  if (col_ok) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = r0 + q * (L / 8);
+      base[(int64_t)j * W + cb] = lds[cb * ls + j];
+    }
   }
 }
 
 // --------------------------------------------------------- z pass + multiply --
 // For one (ky, block of kx) of a grid: forward FFT along z of the gz non-zero
-// planes, then for each output c the product with its multiplier and an inverse FFT:
-//   c = 0,1,2: -i d_c(k) Gf(k)   (Fourier-space gradient of the potential)
-//   c = 3:      Gp(k)
+// planes, then three products and inverse FFTs, written as arrays s = 0, 1, 2 of
+// the z buffer (planes s fz + j, rows ky, columns kx):
+//   s = 0: Gf(k) rho_hat            (the x and y derivatives follow in later passes)
+//   s = 1: -i d_z(k_z) Gf(k) rho_hat
+//   s = 2: Gp(k) rho_hat
 // kern: octant table of (Gf, Gp), index ((|kz| Oy) + |ky|) W + kx, already scaled.
 constexpr int kZConvMaxThreads = 512;     // keeps the FP64 z pass free of spills
 
 template <typename T, int L>
 __global__ void __launch_bounds__(kZConvMaxThreads)
-k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __restrict__ specb,
-             C2<T>* __restrict__ outb, const C2<T>* __restrict__ tw) {
+k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
+             const C2<T>* __restrict__ specb, C2<T>* __restrict__ zb,
+             const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
-  constexpr int LS = L + 1;
   const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
   const int64_t blk = blockIdx.x - J.blk0;
   const int W = J.M[0] / 2 + 1, My = J.M[1];
@@ -141,62 +147,128 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* _
   const int ky = (int)(blk / nbw);
   const int c0 = (int)(blk % nbw) * nl;
   const C2<T>* __restrict__ spec = specb + J.spec_off;
-  C2<T>* __restrict__ out = outb + J.out_off;
-  const C2<T>* __restrict__ kern = (const C2<T>*)J.kern;
-  const T* __restrict__ dxs = (const T*)J.dsym[0];
-  const T* __restrict__ dys = (const T*)J.dsym[1];
-  const T* __restrict__ dzs = (const T*)J.dsym[2];
+  C2<T>* __restrict__ zo = zb + J.z_off;
+  const gptr<T> dzs = as_global<T>(J.dsym[2]);
   const int64_t pstride = (int64_t)My * W;
-  const int nt = nl * (L / 8);
   const int t = threadIdx.x;
-  for (int idx = t; idx < nl * L; idx += nt) {
-    const int bb = idx % nl, z = idx / nl;
-    C2<T> v = mk<T>(0, 0);
-    if (z < gz && c0 + bb < W) v = spec[z * pstride + (int64_t)ky * W + c0 + bb];
-    lds[bb * LS + z] = v;
+  const int cb = t % nl, r0 = t / nl;                // column-wise mapping, as in y_fwd
+  const bool col_ok = c0 + cb < W;
+  {
+    const C2<T>* src = spec + (int64_t)ky * W + c0 + cb;
+    C2<T> v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int z = r0 + q * (L / 8);
+      v[q] = (z < gz && col_ok) ? src[z * pstride] : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
   }
   __syncthreads();
   const int b = t / (L / 8), w = t % (L / 8);
-  C2<T>* line = lds + b * LS;
-  fft_line<T, L, false>(line, w, tw);
-
+  C2<T>* line = lds + b * ls;
+  // this worker's multipliers, loaded while the forward transform runs
   const int kx = c0 + b;
   const int kxc = kx < W ? kx : 0;
   const int Oy = My / 2 + 1;
   const int kyo = ky <= My / 2 ? ky : My - ky;
-  const T dxk = dxs[kxc], dyk = dys[ky];
-  C2<T> X[8], Gk[8];
-  T dzk[8];
+  T gf[8], gp[8], gz_[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int kz = w + q * (L / 8);
     const int kzo = kz <= L / 2 ? kz : L - kz;
-    X[q] = line[kz];
-    Gk[q] = kern[((int64_t)kzo * Oy + kyo) * W + kxc];
-    dzk[q] = dzs[kz];
+    const C2<T> G = load_c2<T>(J.kern, ((int64_t)kzo * Oy + kyo) * W + kxc);
+    gf[q] = G.x;
+    gp[q] = G.y;
+    gz_[q] = dzs[kz] * G.x;
   }
-  for (int c = 0; c < 4; ++c) {
+  fft_line<T, L, false>(line, w, tw);
+  C2<T> X[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) X[q] = line[w + q * (L / 8)];
+  for (int s = 0; s < 3; ++s) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int kz = w + q * (L / 8);
       C2<T> v;
-      if (c == 3) {
-        v = mk<T>(Gk[q].y * X[q].x, Gk[q].y * X[q].y);
-      } else {
-        const T d = (c == 0 ? dxk : (c == 1 ? dyk : dzk[q])) * Gk[q].x;
-        v = mk<T>(d * X[q].y, -d * X[q].x);          // -i d G X
-      }
-      line[kz] = v;
+      if (s == 0) v = mk<T>(gf[q] * X[q].x, gf[q] * X[q].y);
+      else if (s == 1) v = mk<T>(gz_[q] * X[q].y, -gz_[q] * X[q].x);   // -i d_z Gf X
+      else v = mk<T>(gp[q] * X[q].x, gp[q] * X[q].y);
+      line[w + q * (L / 8)] = v;
     }
     __syncthreads();
     fft_line<T, L, true>(line, w, tw);
     __syncthreads();                                 // stores use another mapping
-    for (int idx = t; idx < nl * fz; idx += nt) {
-      const int bb = idx % nl, j = idx / nl;
-      if (c0 + bb < W)
-        out[((int64_t)(c * fz + j) * My + ky) * W + c0 + bb] = lds[bb * LS + ((oz + j) & (L - 1))];
+    if (col_ok) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = r0 + q * (L / 8);
+        if (j < fz)
+          zo[((int64_t)(s * fz + j) * My + ky) * W + c0 + cb] = lds[cb * ls + ((oz + j) & (L - 1))];
+      }
     }
     __syncthreads();
+  }
+}
+
+// -------------------------------------------------------- y inverse (columns) --
+// Block = (plane j < fz, nl columns): 4 lines per column built from one read of
+// the three z arrays: a_x <- Gf rho (its x derivative follows in the x pass),
+// a_y <- -i d_y(k_y) Gf rho, a_z <- array 1, Phi <- array 2; inverse FFT along y;
+// rows j' < fy written from transform index (off_y + j') mod L into the y buffer
+// (planes c fz + j, fy rows, W columns).
+template <typename T, int L>
+__global__ void __launch_bounds__(1024)
+k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
+            const C2<T>* __restrict__ zb, C2<T>* __restrict__ yb, const C2<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
+  const int64_t blk = blockIdx.x - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1];
+  const int fz = J.f[2], fy = J.f[1], oy = J.off[1];
+  const int nbw = (W + nl - 1) / nl;
+  const int j = (int)(blk / nbw);
+  const int c0 = (int)(blk % nbw) * nl;
+  const gptr<T> dys = as_global<T>(J.dsym[1]);
+  const C2<T>* zin = zb + J.z_off + (int64_t)j * My * W + c0;
+  const int64_t zs = (int64_t)fz * My * W;             // stride between z arrays
+  C2<T>* yout = yb + J.y_off + (int64_t)j * fy * W + c0;
+  const int64_t ys = (int64_t)fz * fy * W;             // stride between components
+  const int t = threadIdx.x;
+  // lines: component c of column cb at lds[(c nl + cb) ls]; loads are column-wise,
+  // thread t: column t mod nl, rows t/nl + q L/2 (4 nl L/8 threads, 2 rows each)
+  const int cb = t % nl, r0 = t / nl;
+  const bool col_ok = c0 + cb < W;
+  C2<T> v[2][3];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int64_t o = (int64_t)(r0 + q * (L / 2)) * W + cb;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[q][a] = col_ok ? zin[a * zs + o] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int r = r0 + q * (L / 2);
+    const T d = dys[r];
+    lds[(0 * nl + cb) * ls + r] = v[q][0];
+    lds[(1 * nl + cb) * ls + r] = mk<T>(d * v[q][0].y, -d * v[q][0].x);   // -i d_y Gf rho
+    lds[(2 * nl + cb) * ls + r] = v[q][1];
+    lds[(3 * nl + cb) * ls + r] = v[q][2];
+  }
+  __syncthreads();
+  const int b = t / (L / 8), w = t % (L / 8);
+  fft_line<T, L, true>(lds + b * ls, w, tw);
+  __syncthreads();                                   // stores use another mapping
+  if (col_ok) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int jj = r0 + q * (L / 2);
+      if (jj < fy) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          yout[c * ys + (int64_t)jj * W + cb] = lds[(c * nl + cb) * ls + ((oy + jj) & (L - 1))];
+      }
+    }
   }
 }
 
@@ -206,19 +278,21 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* _
 // Hermitian completion, so the real and imaginary parts of the inverse FFT are the
 // two rows.  Pairing rows of the same component keeps magnitudes alike (an
 // acceleration and the potential can differ by 1/dx, and a shared complex FFT would
-// hand the larger one's rounding to the smaller).  4 lines per row pair; writes
+// hand the larger one's rounding to the smaller).  Component 0 gets its x
+// derivative here: A_0(k) -> -i d_x(k) A_0(k).  4 lines per row pair; writes
 // field[r fx + x] = (a_x, a_y, a_z, Phi).  Rows are contiguous: no LDS padding.
 template <typename T, int L>
 __global__ void __launch_bounds__(1024)
-k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __restrict__ outb,
+k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __restrict__ yb,
             LevelPtrs<T> lp, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
   const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
   const int64_t blk = blockIdx.x - J.blk0;
-  const int W = J.M[0] / 2 + 1, My = J.M[1];
+  const int W = J.M[0] / 2 + 1;
   const int fx = J.f[0], fy = J.f[1], fz = J.f[2], ox = J.off[0];
-  const C2<T>* __restrict__ out = outb + J.out_off;
+  const C2<T>* __restrict__ ybuf = yb + J.y_off;
+  const gptr<T> dxs = as_global<T>(J.dsym[0]);
   V4<T>* __restrict__ field = lp.fld[J.level] + J.fld_off;
   const int G = nl / 4;
   const int nt = nl * (L / 8);
@@ -230,12 +304,18 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
   const int64_t ra = 2 * q, rb = 2 * q + 1;
   C2<T>* line = lds + b * L;
   if (ra < rows) {
-    const C2<T>* A = out + ((int64_t)(c * fz + ra / fy) * My + ra % fy) * W;
+    const int64_t cs = (int64_t)c * rows * W;         // component stride
+    const C2<T>* A = ybuf + cs + ra * W;
     const bool hb = rb < rows;
-    const C2<T>* B = out + ((int64_t)(c * fz + (hb ? rb : ra) / fy) * My + (hb ? rb : ra) % fy) * W;
+    const C2<T>* B = ybuf + cs + (hb ? rb : ra) * W;
     for (int i = w; i < L; i += L / 8) {
       const int k = i <= L / 2 ? i : L - i;
       C2<T> a = A[k], bq = hb ? B[k] : mk<T>(0, 0);
+      if (c == 0) {
+        const T d = dxs[k];
+        a = mk<T>(d * a.y, -d * a.x);
+        bq = mk<T>(d * bq.y, -d * bq.x);
+      }
       if (k == 0 || k == L / 2) { a.y = 0; bq.y = 0; }
       line[i] = i <= L / 2 ? mk<T>(a.x - bq.y, a.y + bq.x) : mk<T>(a.x + bq.y, bq.x - a.y);
     }
@@ -271,7 +351,7 @@ int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], in
     case PASS_X_FWD: return (((int64_t)g[1] * g[2] + 1) / 2 + nl - 1) / nl;
     case PASS_Y_FWD: return nbw * g[2];
     case PASS_Z_CONV: return nbw * M[1];
-    case PASS_Y_INV: return nbw * 4 * f[2];
+    case PASS_Y_INV: return nbw * f[2];
     case PASS_X_INV: return (((int64_t)f[1] * f[2] + 1) / 2 + nl / 4 - 1) / (nl / 4);
   }
   return 0;
@@ -280,16 +360,29 @@ int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], in
 template <typename T> int default_lines(int pass, int L) {
   int nl = (std::is_same<T, float>::value ? 4096 : 2048) / L;
   if (pass == PASS_X_INV) return nl < 4 ? 4 : nl;
+  if (pass == PASS_Y_INV) return nl / 4 < 1 ? 1 : nl / 4;
   if (pass == PASS_Z_CONV) while (nl > 1 && nl * (L / 8) > kZConvMaxThreads) nl /= 2;
   return nl;
 }
 
+static int pass_lines_per_block(int pass, int nl) { return pass == PASS_Y_INV ? 4 * nl : nl; }
+
+// LDS row stride: padded by one element where the load is column-wise, unless the
+// padding would not fit in 64 KB
+template <typename T> static int pass_ls(int pass, int L, int nl) {
+  const bool strided = pass == PASS_Y_FWD || pass == PASS_Z_CONV || pass == PASS_Y_INV;
+  if (!strided) return L;
+  const size_t padded = (size_t)pass_lines_per_block(pass, nl) * (L + 1) * sizeof(C2<T>);
+  return padded <= 65536 ? L + 1 : L;
+}
+
 // LDS bytes of a launch; 0 if the shape is not launchable (threads or LDS)
 template <typename T> size_t pass_lds(int pass, int L, int nl) {
-  const bool padded = pass == PASS_Y_FWD || pass == PASS_Z_CONV || pass == PASS_Y_INV;
-  const size_t bytes = (size_t)nl * (padded ? L + 1 : L) * sizeof(C2<T>);
+  if (nl < 1) return 0;
+  const int lines = pass_lines_per_block(pass, nl);
+  const size_t bytes = (size_t)lines * pass_ls<T>(pass, L, nl) * sizeof(C2<T>);
   const int max_threads = pass == PASS_Z_CONV ? kZConvMaxThreads : 1024;
-  if (nl < 1 || nl * (L / 8) > max_threads || bytes > 65536) return 0;
+  if (lines * (L / 8) > max_threads || bytes > 65536) return 0;
   if (pass == PASS_X_INV && (nl % 4) != 0) return 0;
   return bytes;
 }
@@ -308,12 +401,13 @@ template <typename T> size_t pass_lds(int pass, int L, int nl) {
 
 template <typename T>
 hipError_t launch_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, int64_t nblocks,
-                       const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* out, const void* tw,
-                       hipStream_t s) {
+                       const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* zbuf, C2<T>* ybuf,
+                       const void* tw, hipStream_t s) {
   if (njobs == 0 || nblocks == 0) return hipSuccess;
   const size_t shm = pass_lds<T>(pass, L, nl);
   if (shm == 0) return hipErrorInvalidConfiguration;
-  const dim3 grid((unsigned)nblocks), block((unsigned)(nl * (L / 8)));
+  const int ls = pass_ls<T>(pass, L, nl);
+  const dim3 grid((unsigned)nblocks), block((unsigned)(pass_lines_per_block(pass, nl) * (L / 8)));
   const C2<T>* twc = (const C2<T>*)tw;
   APM_FFT_DISPATCH(L, {
     switch (pass) {
@@ -321,20 +415,19 @@ hipError_t launch_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, 
         hipLaunchKernelGGL((k_fft_x_fwd<T, LL>), grid, block, shm, s, jobs, njobs, nl, lp, spec, twc);
         break;
       case PASS_Y_FWD:
-        hipLaunchKernelGGL((k_fft_cols<T, LL, false>), grid, block, shm, s, jobs, njobs, nl, spec,
-                           out, twc);
+        hipLaunchKernelGGL((k_fft_y_fwd<T, LL>), grid, block, shm, s, jobs, njobs, nl, ls, spec, twc);
         break;
       case PASS_Z_CONV:
-        hipLaunchKernelGGL((k_fft_z_conv<T, LL>), grid, block, shm, s, jobs, njobs, nl,
-                           (const C2<T>*)spec, out, twc);
+        hipLaunchKernelGGL((k_fft_z_conv<T, LL>), grid, block, shm, s, jobs, njobs, nl, ls,
+                           (const C2<T>*)spec, zbuf, twc);
         break;
       case PASS_Y_INV:
-        hipLaunchKernelGGL((k_fft_cols<T, LL, true>), grid, block, shm, s, jobs, njobs, nl, spec,
-                           out, twc);
+        hipLaunchKernelGGL((k_fft_y_inv<T, LL>), grid, block, shm, s, jobs, njobs, nl, ls,
+                           (const C2<T>*)zbuf, ybuf, twc);
         break;
       case PASS_X_INV:
         hipLaunchKernelGGL((k_fft_x_inv<T, LL>), grid, block, shm, s, jobs, njobs, nl,
-                           (const C2<T>*)out, lp, twc);
+                           (const C2<T>*)ybuf, lp, twc);
         break;
       default:
         return hipErrorInvalidValue;
@@ -349,9 +442,9 @@ template size_t pass_lds<float>(int, int, int);
 template size_t pass_lds<double>(int, int, int);
 template hipError_t launch_pass<float>(int, int, int, const ConvJob*, int, int64_t,
                                        const LevelPtrs<float>&, C2<float>*, C2<float>*,
-                                       const void*, hipStream_t);
+                                       C2<float>*, const void*, hipStream_t);
 template hipError_t launch_pass<double>(int, int, int, const ConvJob*, int, int64_t,
                                         const LevelPtrs<double>&, C2<double>*, C2<double>*,
-                                        const void*, hipStream_t);
+                                        C2<double>*, const void*, hipStream_t);
 
 }  // namespace apm

@@ -13,6 +13,8 @@
 // Plummer core holds ~1e5 particles per tile on the root) are split across many
 // blocks, so the load is balanced; FP64 accumulation keeps the result at the
 // working precision's rounding of the exact sum.
+#include <algorithm>
+
 #include "apm_kernels.hpp"
 
 namespace apm {
@@ -30,24 +32,55 @@ template <typename T> __device__ __forceinline__ T tsc_w(int d, T t) {
   return (T)0.75 - t * t;
 }
 
-// Block-aggregated tile counting: each block takes kBinPer particles per thread,
-// inserts their tile keys into an LDS hash table (linear probing, CAS), takes local
-// ranks from LDS atomics, then reserves one range per distinct tile with a single
-// global atomic on the block's replica of that tile's counter.  A tile holding many
-// particles (the Plummer core) thus sees one global atomic per block instead of one
-// per particle or wavefront.
+// Batch level of block blockIdx.x in a launch whose levels own consecutive block
+// ranges [blk0[b], blk0[b + 1]).
+__device__ __forceinline__ int batch_level(const int64_t* blk0, int nlev, int64_t blk) {
+  int b = 0;
+  while (b + 1 < nlev && blk0[b + 1] <= blk) ++b;
+  return b;
+}
+
+// ---- clear: counters and FP64 mass grids of every level of the batch ---------------
+__global__ void __launch_bounds__(kBlock) k_dep_clear(const DepLevel* __restrict__ tab) {
+  const DepLevel& L = tab[blockIdx.y];
+  const int64_t ncount = (int64_t)L.ntiles * L.rep + 1;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ncount; i += stride)
+    L.count[i] = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < L.key_cells; i += stride)
+    L.accum[i] = 0.0;
+}
+
+hipError_t launch_dep_clear(const DepLevel* tab, int nlev, int64_t max_elems, hipStream_t s) {
+  if (nlev == 0) return hipSuccess;
+  const int64_t want = (max_elems + 4 * kBlock - 1) / (4 * kBlock);
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 4096));
+  hipLaunchKernelGGL(k_dep_clear, dim3(nb, (unsigned)nlev), dim3(kBlock), 0, s, tab);
+  return hipGetLastError();
+}
+
+// ---- tile counting ------------------------------------------------------------------
+// Block-aggregated: each block takes kBinPer particles per thread, inserts their tile
+// keys into an LDS hash table (linear probing, CAS), takes local ranks from LDS
+// atomics, then reserves one range per distinct tile with a single global atomic on
+// the block's replica of that tile's counter.  A tile holding many particles (the
+// Plummer core) thus sees one global atomic per block, not one per particle.
+// blockIdx.y = level of the batch.
 constexpr int kBinPer = 8;
 constexpr int kBinBlockParticles = kBlock * kBinPer;     // 2048
 constexpr int kHash = 2 * kBinBlockParticles;            // load factor <= 1/2
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_bin_count(BinParams<T> p) {
+__global__ void __launch_bounds__(kBlock) k_bin_count(DepIO<T> io, const DepLevel* __restrict__ tab) {
   __shared__ int32_t hkey[kHash];
   __shared__ int32_t hcnt[kHash];
+  const DepLevel& L = tab[blockIdx.y];
   for (int h = threadIdx.x; h < kHash; h += kBlock) { hkey[h] = -1; hcnt[h] = 0; }
   __syncthreads();
-  const int32_t r = (int32_t)(blockIdx.x & (p.rep - 1));
+  const int32_t rep = L.rep;
+  const int32_t r = (int32_t)(blockIdx.x & (rep - 1));
   const int64_t base = (int64_t)blockIdx.x * kBinBlockParticles + threadIdx.x;
+  const T sc = (T)L.inv_dx;
   int32_t key[kBinPer], slot[kBinPer], lrank[kBinPer];
 #pragma unroll
   for (int q = 0; q < kBinPer; ++q) {
@@ -55,15 +88,14 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(BinParams<T> p) {
     key[q] = -1;
     slot[q] = -1;
     lrank[q] = 0;
-    if (i < p.npart) {
-      const T x = p.x[i], y = p.y[i], z = p.z[i];
+    if (i < io.npart) {
+      const T x = io.x[i], y = io.y[i], z = io.z[i];
       if (in_domain(x, y, z)) {
-        const T s = (T)p.inv_dx;
-        const int ix = (int)floor(x * s) - p.key_lo[0];
-        const int iy = (int)floor(y * s) - p.key_lo[1];
-        const int iz = (int)floor(z * s) - p.key_lo[2];
-        if (ix >= 0 && ix < p.key_n[0] && iy >= 0 && iy < p.key_n[1] && iz >= 0 && iz < p.key_n[2])
-          key[q] = ((iz / kTile) * p.tiles_n[1] + iy / kTile) * p.tiles_n[0] + ix / kTile;
+        const int ix = (int)floor(x * sc) - L.key_lo[0];
+        const int iy = (int)floor(y * sc) - L.key_lo[1];
+        const int iz = (int)floor(z * sc) - L.key_lo[2];
+        if (ix >= 0 && ix < L.key_n[0] && iy >= 0 && iy < L.key_n[1] && iz >= 0 && iz < L.key_n[2])
+          key[q] = ((iz / kTile) * L.tiles_n[1] + iy / kTile) * L.tiles_n[0] + ix / kTile;
       }
     }
     if (key[q] >= 0) {
@@ -80,150 +112,164 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(BinParams<T> p) {
   __syncthreads();
   for (int h = threadIdx.x; h < kHash; h += kBlock) {
     const int32_t n = hcnt[h];
-    if (n > 0) hcnt[h] = atomicAdd(&p.count[hkey[h] * p.rep + r], n);   // becomes the base
+    if (n > 0) hcnt[h] = atomicAdd(&L.count[hkey[h] * rep + r], n);   // becomes the base
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < kBinPer; ++q) {
     const int64_t i = base + (int64_t)q * kBlock;
-    if (i < p.npart) {
-      p.key[i] = key[q] < 0 ? -1 : key[q] * p.rep + r;        // counter slot
-      p.rank[i] = key[q] < 0 ? 0 : hcnt[slot[q]] + lrank[q];
+    if (i < io.npart) {
+      L.key[i] = key[q] < 0 ? -1 : key[q] * rep + r;          // counter slot
+      L.rank[i] = key[q] < 0 ? 0 : hcnt[slot[q]] + lrank[q];
     }
   }
 }
 
 template <typename T>
-__global__ void k_bin_scatter(BinParams<T> p, const int32_t* __restrict__ start,
-                              V4<T>* __restrict__ sorted) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= p.npart) return;
-  const int32_t key = p.key[i];
+hipError_t launch_bin_count(const DepIO<T>& io, const DepLevel* tab, hipStream_t s) {
+  if (io.npart == 0 || io.nlev == 0) return hipSuccess;
+  const unsigned nb = (unsigned)((io.npart + kBinBlockParticles - 1) / kBinBlockParticles);
+  hipLaunchKernelGGL((k_bin_count<T>), dim3(nb, (unsigned)io.nlev), dim3(kBlock), 0, s, io, tab);
+  return hipGetLastError();
+}
+
+// ---- per-level scans: one block of kScanThreads per level ---------------------------
+// The replica counters, in tile-major order, are scanned in place into start offsets
+// (the final entry becomes the binned total); then work items per tile
+// ceil(tile count / kChunk) are scanned into item starts.
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 16;                         // consecutive counters per thread
+constexpr int kWaves = kScanThreads / 64;
+
+// Exclusive prefix sum over the block (wavefront shuffles, then the wave totals);
+// *total gets the block sum.  sh holds kWaves ints.
+__device__ static int32_t block_exclusive_sum(int32_t v, int32_t* sh, int32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) sh[wave] = incl;
+  __syncthreads();
+  int32_t wbase = 0, sum = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const int32_t t = sh[w];
+    wbase += w < wave ? t : 0;
+    sum += t;
+  }
+  __syncthreads();                                   // sh reused by the next call
+  *total = sum;
+  return wbase + incl - v;
+}
+
+// Exclusive scan of data[0, n) in place by the whole block; returns the sum.  data
+// must be 16-byte aligned (whole 16-counter runs move as four 16-byte vectors).
+__device__ static int32_t block_scan_inplace(int32_t* data, int64_t n, int32_t* sh) {
+  int32_t carry = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += (int64_t)kScanThreads * kScanPer) {
+    const int64_t base = c0 + (int64_t)threadIdx.x * kScanPer;
+    int32_t v[kScanPer];
+    const bool whole = base + kScanPer <= n;
+    if (whole) {
+      const int4* p4 = reinterpret_cast<const int4*>(data + base);
+#pragma unroll
+      for (int k = 0; k < kScanPer / 4; ++k) {
+        const int4 q = p4[k];
+        v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k) v[k] = base + k < n ? data[base + k] : 0;
+    }
+    int32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) sum += v[k];
+    int32_t chunk;
+    int32_t ex = carry + block_exclusive_sum(sum, sh, &chunk);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const int32_t n_k = v[k];
+      v[k] = ex;
+      ex += n_k;
+    }
+    if (whole) {
+      int4* p4 = reinterpret_cast<int4*>(data + base);
+#pragma unroll
+      for (int k = 0; k < kScanPer / 4; ++k)
+        p4[k] = make_int4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k)
+        if (base + k < n) data[base + k] = v[k];
+    }
+    carry += chunk;
+  }
+  return carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_bin_scan(const DepLevel* __restrict__ tab) {
+  __shared__ int32_t sh[kWaves];
+  const DepLevel& L = tab[blockIdx.x];
+  const int rep = L.rep;
+  const int32_t nt = L.ntiles;
+  const int32_t total = block_scan_inplace(L.count, (int64_t)nt * rep + 1, sh);
+  __syncthreads();                                   // the block's writes visible to it
+  for (int32_t t0 = 0; t0 <= nt; t0 += kScanThreads * kScanPer) {
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+      const int32_t t = t0 + q * kScanThreads + (int32_t)threadIdx.x;
+      if (t < nt)
+        L.items[t] = (L.count[(int64_t)(t + 1) * rep] - L.count[(int64_t)t * rep] + kChunk - 1) /
+                     kChunk;
+      else if (t == nt)
+        L.items[t] = 0;
+    }
+  }
+  __syncthreads();
+  block_scan_inplace(L.items, (int64_t)nt + 1, sh);
+  if (threadIdx.x == 0) *L.binned = total;
+}
+
+hipError_t launch_bin_scan(const DepLevel* tab, int nlev, hipStream_t s) {
+  if (nlev == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bin_scan, dim3((unsigned)nlev), dim3(kScanThreads), 0, s, tab);
+  return hipGetLastError();
+}
+
+// ---- scatter into tile order --------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bin_scatter(DepIO<T> io, const DepLevel* __restrict__ tab) {
+  const DepLevel& L = tab[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= io.npart) return;
+  const int32_t key = L.key[i];
   if (key < 0) return;
-  const int32_t tile = key / p.rep;
-  const int tx = tile % p.tiles_n[0], ty = (tile / p.tiles_n[0]) % p.tiles_n[1],
-            tz = tile / (p.tiles_n[0] * p.tiles_n[1]);
-  (void)tx; (void)ty; (void)tz;
-  const T s = (T)p.inv_dx;
+  const T sc = (T)L.inv_dx;
   V4<T> r;
   // exact: x/dx is exact (dx a power of two) and the origin an integer below it
-  r.x = p.x[i] * s - (T)p.key_lo[0];
-  r.y = p.y[i] * s - (T)p.key_lo[1];
-  r.z = p.z[i] * s - (T)p.key_lo[2];
-  r.w = p.m[i];
-  const int32_t slot = start[key] + p.rank[i];
-  sorted[slot] = r;
-  p.sidx[slot] = (int32_t)i;
+  r.x = io.x[i] * sc - (T)L.key_lo[0];
+  r.y = io.y[i] * sc - (T)L.key_lo[1];
+  r.z = io.z[i] * sc - (T)L.key_lo[2];
+  r.w = io.m[i];
+  const int32_t slot = L.count[key] + L.rank[i];
+  ((V4<T>*)L.sorted)[slot] = r;
+  L.sidx[slot] = (int32_t)i;
 }
 
 template <typename T>
-hipError_t launch_bin_count(const BinParams<T>& p, hipStream_t s) {
-  if (p.npart == 0) return hipSuccess;
-  const unsigned nb = (unsigned)((p.npart + kBinBlockParticles - 1) / kBinBlockParticles);
-  hipLaunchKernelGGL((k_bin_count<T>), dim3(nb), dim3(kBlock), 0, s, p);
+hipError_t launch_bin_scatter(const DepIO<T>& io, const DepLevel* tab, hipStream_t s) {
+  if (io.npart == 0 || io.nlev == 0) return hipSuccess;
+  const unsigned nb = (unsigned)((io.npart + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((k_bin_scatter<T>), dim3(nb, (unsigned)io.nlev), dim3(kBlock), 0, s, io, tab);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_bin_scatter(const BinParams<T>& p, const int32_t* start, V4<T>* sorted,
-                              hipStream_t s) {
-  if (p.npart == 0) return hipSuccess;
-  const unsigned nb = (unsigned)((p.npart + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_bin_scatter<T>), dim3(nb), dim3(kBlock), 0, s, p, start, sorted);
-  return hipGetLastError();
-}
-
-__global__ void k_chunk_count(const int32_t* __restrict__ start, int32_t ntiles, int32_t rep,
-                              int32_t* __restrict__ items) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > ntiles) return;
-  items[t] = t < ntiles
-      ? (start[(t + 1) * rep] - start[t * rep] + kChunk - 1) / kChunk : 0;
-}
-
-hipError_t launch_chunk_count(const int32_t* start, int32_t ntiles, int32_t rep, int32_t* items,
-                              hipStream_t s) {
-  const unsigned nb = (unsigned)((ntiles + 1 + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_chunk_count, dim3(nb), dim3(kBlock), 0, s, start, ntiles, rep, items);
-  return hipGetLastError();
-}
-
-// ---- exclusive scan of int32 (three passes, 1024 elements per block) ------------
-constexpr int kScanPer = 4;
-constexpr int kScanBlock = kBlock * kScanPer;
-
-__device__ static int32_t block_exclusive_scan(int32_t v, int32_t* sh, int32_t* total) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const int32_t add = t >= off ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
-  }
-  const int32_t incl = sh[t];
-  *total = sh[kBlock - 1];
-  __syncthreads();
-  return incl - v;
-}
-
-__global__ void k_scan_blocks(int32_t* __restrict__ data, int64_t n, int32_t* __restrict__ sums) {
-  __shared__ int32_t sh[kBlock];
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
-  int32_t v[kScanPer], s = 0;
-  for (int q = 0; q < kScanPer; ++q) {
-    v[q] = (base + q < n) ? data[base + q] : 0;
-    s += v[q];
-  }
-  int32_t total;
-  int32_t ex = block_exclusive_scan(s, sh, &total);
-  for (int q = 0; q < kScanPer; ++q) {
-    if (base + q < n) data[base + q] = ex;
-    ex += v[q];
-  }
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-__global__ void k_scan_sums(int32_t* __restrict__ sums, int64_t nsums) {
-  __shared__ int32_t sh[kBlock];
-  int32_t carry = 0;
-  for (int64_t c0 = 0; c0 < nsums; c0 += kScanBlock) {
-    const int64_t base = c0 + (int64_t)threadIdx.x * kScanPer;
-    int32_t v[kScanPer], s = 0;
-    for (int q = 0; q < kScanPer; ++q) {
-      v[q] = (base + q < nsums) ? sums[base + q] : 0;
-      s += v[q];
-    }
-    int32_t total;
-    int32_t ex = block_exclusive_scan(s, sh, &total) + carry;
-    for (int q = 0; q < kScanPer; ++q) {
-      if (base + q < nsums) sums[base + q] = ex;
-      ex += v[q];
-    }
-    carry += total;
-  }
-}
-
-__global__ void k_scan_add(int32_t* __restrict__ data, int64_t n, const int32_t* __restrict__ sums) {
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
-  const int32_t add = sums[blockIdx.x];
-  for (int q = 0; q < kScanPer; ++q)
-    if (base + q < n) data[base + q] += add;
-}
-
-size_t scan_tmp_elems(int64_t n) { return (size_t)((n + kScanBlock - 1) / kScanBlock) + 1; }
-
-hipError_t launch_exclusive_scan(int32_t* data, int64_t n, int32_t* tmp, hipStream_t s) {
-  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kBlock), 0, s, data, n, tmp);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, tmp, nb);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, s, data, n,
-                     (const int32_t*)tmp);
-  return hipGetLastError();
-}
-
-// ---- deposit: one thread per GMF cell ------------------------------------------
+// ---- deposit: work item = chunk of one tile ------------------------------------------
+// LDS accumulation over the tile and its one-cell halo, then global FP64 atomics
+// into the level's key-box grid.  Blocks past a level's item count exit at once.
 __device__ __forceinline__ int find_grid(const int64_t* __restrict__ begin, int ngrids, int64_t b) {
   int lo = 0, hi = ngrids - 1;
   while (lo < hi) {
@@ -233,30 +279,31 @@ __device__ __forceinline__ int find_grid(const int64_t* __restrict__ begin, int 
   return lo;
 }
 
-// Work item = chunk of one tile: LDS accumulation over the tile and its one-cell
-// halo, then global FP64 atomics into the key-box grid.
 constexpr int kTH = kTile + 2;
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_deposit_tiles(TileDepositParams<T> p) {
+__global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const DepLevel* __restrict__ tab) {
   __shared__ double acc[kTH * kTH * kTH];
-  const int32_t total = p.item_start[p.ntiles];
-  const int64_t item = blockIdx.x;
+  const int lb = batch_level(io.item_blk0, io.nlev, blockIdx.x);
+  const DepLevel& L = tab[lb];
+  const int32_t total = L.items[L.ntiles];
+  const int64_t item = blockIdx.x - io.item_blk0[lb];
   if (item >= total) return;                        // uniform for the block
-  int lo = 0, hi = p.ntiles - 1;                    // last tile with item_start <= item
+  int lo = 0, hi = L.ntiles - 1;                    // last tile with item start <= item
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (p.item_start[mid] <= item) lo = mid; else hi = mid - 1;
+    if (L.items[mid] <= item) lo = mid; else hi = mid - 1;
   }
   const int tile = lo;
-  const int64_t begin = p.start[(int64_t)tile * p.rep] + (item - p.item_start[tile]) * (int64_t)kChunk;
-  const int64_t end = min((int64_t)p.start[(int64_t)(tile + 1) * p.rep], begin + kChunk);
+  const int64_t begin = L.count[(int64_t)tile * L.rep] + (item - L.items[tile]) * (int64_t)kChunk;
+  const int64_t end = min((int64_t)L.count[(int64_t)(tile + 1) * L.rep], begin + kChunk);
   for (int c = threadIdx.x; c < kTH * kTH * kTH; c += kBlock) acc[c] = 0.0;
   __syncthreads();
-  const int ox = (tile % p.tiles_n[0]) * kTile, oy = ((tile / p.tiles_n[0]) % p.tiles_n[1]) * kTile,
-            oz = (tile / (p.tiles_n[0] * p.tiles_n[1])) * kTile;
+  const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
+            oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;
+  const V4<T>* __restrict__ sorted = (const V4<T>*)L.sorted;
   for (int64_t q = begin + threadIdx.x; q < end; q += kBlock) {
-    const V4<T> v = p.sorted[q];
+    const V4<T> v = sorted[q];
     const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
     const int ix = min(max((int)fx - ox, 0), kTile - 1), iy = min(max((int)fy - oy, 0), kTile - 1),
               iz = min(max((int)fz - oz, 0), kTile - 1);
@@ -285,52 +332,61 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(TileDepositParams<T> p
     const double v = acc[c];
     if (v == 0.0) continue;
     const int gx = tx0 + c % kTH, gy = ty0 + (c / kTH) % kTH, gz = tz0 + c / (kTH * kTH);
-    if (gx < 0 || gx >= p.key_n[0] || gy < 0 || gy >= p.key_n[1] || gz < 0 || gz >= p.key_n[2])
+    if (gx < 0 || gx >= L.key_n[0] || gy < 0 || gy >= L.key_n[1] || gz < 0 || gz >= L.key_n[2])
       continue;
-    atomicAdd(p.accum + ((int64_t)gz * p.key_n[1] + gy) * p.key_n[0] + gx, v);
+    atomicAdd(L.accum + ((int64_t)gz * L.key_n[1] + gy) * L.key_n[0] + gx, v);
   }
 }
 
 template <typename T>
-hipError_t launch_deposit_tiles(const TileDepositParams<T>& p, int64_t max_items, hipStream_t s) {
-  if (max_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_deposit_tiles<T>), dim3((unsigned)max_items), dim3(kBlock), 0, s, p);
+hipError_t launch_deposit_tiles(const DepIO<T>& io, const DepLevel* tab, hipStream_t s) {
+  const int64_t nb = io.item_blk0[io.nlev];
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_deposit_tiles<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab);
   return hipGetLastError();
 }
 
-// Finalize: GMF cell c of every grid of the level = accumulated mass / dx^3 + gas
-// (own gas on active cells, the parent's copied onto ghost cells).
+// ---- finalize: GMF cell = accumulated mass / dx^3 + gas ------------------------------
+// (own gas on active cells, the parent's copied onto ghost cells); one thread per GMF
+// cell of every grid of every level of the batch.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_deposit(DepositParams<T> p) {
-  const int gi = find_grid(p.block_begin, p.ngrids, blockIdx.x);
-  const GridDesc& g = p.grids[gi];
+__global__ void __launch_bounds__(kBlock) k_deposit_finalize(DepIO<T> io, const DepLevel* __restrict__ tab) {
+  const int lb = batch_level(io.fin_blk0, io.nlev, blockIdx.x);
+  const DepLevel& L = tab[lb];
+  const int64_t blk = blockIdx.x - io.fin_blk0[lb];
+  const int gi = find_grid(L.block_begin, L.ngrids, blk);
+  const GridDesc& g = L.grids[gi];
   const int64_t cells = (int64_t)g.gmf_n[0] * g.gmf_n[1] * g.gmf_n[2];
-  const int64_t local = (blockIdx.x - p.block_begin[gi]) * (int64_t)kBlock + threadIdx.x;
+  const int64_t local = (blk - L.block_begin[gi]) * (int64_t)kBlock + threadIdx.x;
   if (local >= cells) return;
   const int lx = (int)(local % g.gmf_n[0]);
   const int ly = (int)((local / g.gmf_n[0]) % g.gmf_n[1]);
   const int lz = (int)(local / ((int64_t)g.gmf_n[0] * g.gmf_n[1]));
   const int cx = g.gmf_lo[0] + lx, cy = g.gmf_lo[1] + ly, cz = g.gmf_lo[2] + lz;
-  const double mass = p.accum[((int64_t)(cz - p.key_lo[2]) * p.key_n[1] + (cy - p.key_lo[1])) *
-                                  p.key_n[0] + (cx - p.key_lo[0])];
-  T rho = (T)(mass / (p.dx * p.dx * p.dx));
+  const double mass = L.accum[((int64_t)(cz - L.key_lo[2]) * L.key_n[1] + (cy - L.key_lo[1])) *
+                                  L.key_n[0] + (cx - L.key_lo[0])];
+  T rho = (T)(mass / (L.dx * L.dx * L.dx));
   const bool active = cx >= g.lo[0] && cx < g.lo[0] + g.n[0] && cy >= g.lo[1] &&
                       cy < g.lo[1] + g.n[1] && cz >= g.lo[2] && cz < g.lo[2] + g.n[2];
+  const T* gas = io.gas[lb];
+  const T* pgas = io.pgas[lb];
   if (active) {
-    if (p.gas)
-      rho += p.gas[g.gas_offset + ((int64_t)(cz - g.lo[2]) * g.n[1] + (cy - g.lo[1])) * g.n[0] +
-                   (cx - g.lo[0])];
-  } else if (p.parent_gas && g.parent >= 0) {
+    if (gas)
+      rho += gas[g.gas_offset + ((int64_t)(cz - g.lo[2]) * g.n[1] + (cy - g.lo[1])) * g.n[0] +
+                 (cx - g.lo[0])];
+  } else if (pgas && g.parent >= 0) {
     const int px = (cx >> 1) - g.parent_lo[0], py = (cy >> 1) - g.parent_lo[1],
               pz = (cz >> 1) - g.parent_lo[2];
-    rho += p.parent_gas[g.parent_gas_offset + ((int64_t)pz * g.parent_n[1] + py) * g.parent_n[0] + px];
+    rho += pgas[g.parent_gas_offset + ((int64_t)pz * g.parent_n[1] + py) * g.parent_n[0] + px];
   }
-  p.gmf[g.gmf_offset + local] = rho;
+  io.gmf[lb][g.gmf_offset + local] = rho;
 }
 
 template <typename T>
-hipError_t launch_deposit(const DepositParams<T>& p, int64_t nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_deposit<T>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, p);
+hipError_t launch_deposit_finalize(const DepIO<T>& io, const DepLevel* tab, hipStream_t s) {
+  const int64_t nb = io.fin_blk0[io.nlev];
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_deposit_finalize<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab);
   return hipGetLastError();
 }
 
@@ -423,61 +479,6 @@ hipError_t launch_interp(const GridDesc* grids, int32_t level, const V4<T>* fiel
 }
 
 template <typename T>
-__global__ void k_interp_sorted(const GridDesc* __restrict__ grids, int32_t level,
-                                const V4<T>* __restrict__ field, const V4<T>* __restrict__ sorted,
-                                const int32_t* __restrict__ sidx, const int32_t* __restrict__ total,
-                                int32_t klx, int32_t kly, int32_t klz,
-                                const int32_t* __restrict__ owner, T* __restrict__ ax,
-                                T* __restrict__ ay, T* __restrict__ az, T* __restrict__ pot) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= *total) return;
-  const int32_t i = sidx[q];
-  const int32_t o = owner[i];
-  if (o < 0) return;
-  const GridDesc& g = grids[o];
-  if (g.level != level) return;
-  const V4<T> v = sorted[q];
-  const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
-  const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
-  const int ix = (int)fx + klx - g.fld_lo[0], iy = (int)fy + kly - g.fld_lo[1],
-            iz = (int)fz + klz - g.fld_lo[2];
-  const V4<T>* F = field + g.fld_offset;
-  T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int cz = iz + dz;
-    if (cz < 0 || cz >= g.fld_n[2]) continue;
-    const T wz = tsc_w(dz, tz);
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int cy = iy + dy;
-      if (cy < 0 || cy >= g.fld_n[1]) continue;
-      const T wzy = wz * tsc_w(dy, ty);
-      const V4<T>* row = F + ((int64_t)cz * g.fld_n[1] + cy) * g.fld_n[0];
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int cx = ix + dx;
-        if (cx < 0 || cx >= g.fld_n[0]) continue;
-        const T w = wzy * tsc_w(dx, tx);
-        const V4<T> f = row[cx];
-        acc0 += w * f.x; acc1 += w * f.y; acc2 += w * f.z; acc3 += w * f.w;
-      }
-    }
-  }
-  ax[i] = acc0; ay[i] = acc1; az[i] = acc2;
-  if (pot) pot[i] = acc3;
-}
-
-template <typename T>
-hipError_t launch_interp_sorted(const GridDesc* grids, int32_t level, const V4<T>* field,
-                                const V4<T>* sorted, const int32_t* sidx, const int32_t* total,
-                                int64_t max_n, const int32_t key_lo[3], const int32_t* owner,
-                                T* ax, T* ay, T* az, T* pot, hipStream_t s) {
-  if (max_n == 0) return hipSuccess;
-  const unsigned nb = (unsigned)((max_n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_interp_sorted<T>), dim3(nb), dim3(kBlock), 0, s, grids, level, field,
-                     sorted, sidx, total, key_lo[0], key_lo[1], key_lo[2], owner, ax, ay, az, pot);
-  return hipGetLastError();
-}
-
-template <typename T>
 __global__ void k_interp_all(const GridDesc* __restrict__ grids, FieldTable<T> fields,
                              const T* __restrict__ x, const T* __restrict__ y,
                              const T* __restrict__ z, const int32_t* __restrict__ owner,
@@ -528,15 +529,10 @@ hipError_t launch_interp_all(const GridDesc* grids, const FieldTable<T>& fields,
 }
 
 #define APM_INST(T)                                                                          \
-  template hipError_t launch_bin_count<T>(const BinParams<T>&, hipStream_t);                   \
-  template hipError_t launch_bin_scatter<T>(const BinParams<T>&, const int32_t*, V4<T>*,        \
-                                            hipStream_t);                                       \
-  template hipError_t launch_deposit<T>(const DepositParams<T>&, int64_t, hipStream_t);        \
-  template hipError_t launch_deposit_tiles<T>(const TileDepositParams<T>&, int64_t, hipStream_t); \
-  template hipError_t launch_interp_sorted<T>(const GridDesc*, int32_t, const V4<T>*,            \
-                                              const V4<T>*, const int32_t*, const int32_t*,      \
-                                              int64_t, const int32_t*, const int32_t*, T*, T*,   \
-                                              T*, T*, hipStream_t);                              \
+  template hipError_t launch_bin_count<T>(const DepIO<T>&, const DepLevel*, hipStream_t);      \
+  template hipError_t launch_bin_scatter<T>(const DepIO<T>&, const DepLevel*, hipStream_t);    \
+  template hipError_t launch_deposit_tiles<T>(const DepIO<T>&, const DepLevel*, hipStream_t);  \
+  template hipError_t launch_deposit_finalize<T>(const DepIO<T>&, const DepLevel*, hipStream_t); \
   template hipError_t launch_interp_all<T>(const GridDesc*, const FieldTable<T>&, const T*,      \
                                            const T*, const T*, const int32_t*, int64_t, T*, T*,  \
                                            T*, T*, hipStream_t);                                 \
