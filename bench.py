@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB a few times (the reference "
+                         "kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); "
@@ -80,10 +83,21 @@ def main():
         sys.exit(2)
 
     import torch
+    dev = torch.device("cuda", 0)
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": src.numel() * 4,
+                          "launches": 5}))
+        return
+
     import apm_workloads as W
     from paper_1410_0010_amd import Context, Plan
 
-    dev = torch.device("cuda", 0)
     w = W.workload_plummer_nested()
     plan = Plan(w.root_n, w.grids)
     ctx = Context(plan, 0)

@@ -40,7 +40,7 @@ struct apm_ctx_s {
   DevBuf spec, zbuf, ybuf, tmpfld, owner, totals, binned;
   // per level: tile counters, work items, FP64 mass grid, particle keys/ranks, the
   // tile-sorted records and their original indices
-  struct LevelBufs { DevBuf count, items, accum, key, rank, sidx, sorted; };
+  struct LevelBufs { DevBuf count, items, accum, key, rank, sref, sorted; };
   std::vector<LevelBufs> lvb;
   std::vector<DepLevel> dep_host;                                 // level table, host copy
   std::vector<unsigned char> dep_dev_copy;                        // bytes last uploaded
@@ -371,6 +371,7 @@ apm_status job_list(apm_ctx c, int pass, int L, int level, int nl, const apm_ctx
       j.f[a] = g.fld_n[a];
       j.off[a] = ((g.fld_lo[a] - g.gmf_lo[a]) % g.M[a] + g.M[a]) % g.M[a];
     }
+    j.pitch = (g.M[0] / 2 + 1 + kRowAlign - 1) / kRowAlign * kRowAlign;
     j.gmf_off = g.gmf_offset;
     j.fld_off = g.fld_offset;
     j.spec_off = c->spec_off[gi];
@@ -462,8 +463,8 @@ apm_status sync_dep_table(apm_ctx c) {
 // indexed by batch position.
 template <typename T>
 apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y, const T* z,
-                            const T* m, int64_t npart, const T* const* gas, const T* const* pgas,
-                            T* const* gmf) {
+                            const T* m, int64_t npart, const int32_t* owner, const T* const* gas,
+                            const T* const* pgas, T* const* gmf) {
   const Plan& P = c->plan;
   const int nl = (int)P.levels.size();
   c->lvb.resize(nl);
@@ -475,6 +476,7 @@ apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y,
   const size_t np = (size_t)std::max<int64_t>(npart, 1);
   DepIO<T> io{};
   io.x = x; io.y = y; io.z = z; io.m = m;
+  io.owner = owner;
   io.npart = npart;
   io.nlev = nlev;
   int64_t max_elems = 0, iblk = 0, fblk = 0;
@@ -499,7 +501,7 @@ apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y,
     APM_TRY(ensure(c, B.accum, (size_t)L.key_cells * 8, "fp64 mass grid"));
     APM_TRY(ensure(c, B.key, np * 4, "particle keys"));
     APM_TRY(ensure(c, B.rank, np * 4, "particle ranks"));
-    APM_TRY(ensure(c, B.sidx, np * 4, "sorted particle indices"));
+    APM_TRY(ensure(c, B.sref, np * 8, "sorted particle references"));
     APM_TRY(ensure(c, B.sorted, np * sizeof(V4<T>), "sorted particles"));
     DepLevel d;
     std::memset((void*)&d, 0, sizeof d);
@@ -512,13 +514,14 @@ apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y,
     }
     d.ntiles = (int32_t)ntiles;
     d.rep = rep;
+    d.first = L.first;
     d.ngrids = L.count;
     d.key_cells = L.key_cells;
     d.count = (int32_t*)B.count.p;
     d.items = (int32_t*)B.items.p;
     d.key = (int32_t*)B.key.p;
     d.rank = (int32_t*)B.rank.p;
-    d.sidx = (int32_t*)B.sidx.p;
+    d.sref = (int2*)B.sref.p;
     d.sorted = B.sorted.p;
     d.accum = (double*)B.accum.p;
     d.grids = c->d_grids + L.first;
@@ -583,7 +586,7 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
   int32_t* own = (int32_t*)c->owner.p;
   HIP_TRY(timed(c, "owner", [&] {
             return launch_owner<T>(c->d_grids, (int32_t)P.grids.size(), (double)P.cfg.root_n, x, y,
-                                   z, npart, own, c->stream);
+                                   z, npart, own, ax, ay, az, pot, c->stream);
           }), "owner");
   {
     const T* gl[kMaxLevels];
@@ -594,7 +597,7 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
       pg[l] = (gas && l > 0) ? (const T*)gas[l - 1] : nullptr;
       gm[l] = (T*)c->gmf[di][l].p;
     }
-    APM_TRY(deposit_levels_t<T>(c, 0, nl, x, y, z, m, npart, gl, pg, gm));
+    APM_TRY(deposit_levels_t<T>(c, 0, nl, x, y, z, m, npart, own, gl, pg, gm));
   }
   // each grid's own field is written straight into the level field, then the
   // parent's composed field is added in place, level by level (the root has none)
@@ -613,11 +616,17 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
                                        (V4<T>*)c->fld[di][l].p, c->cmp_blocks[l], c->stream);
             }), "compose");
   }
-  FieldTable<T> ft{};
-  for (int l = 0; l < nl && l < kMaxLevels; ++l) ft.f[l] = (const V4<T>*)c->fld[di][l].p;
+  InterpIO<T> io{};
+  io.nlev = nl;
+  const int64_t nbp = (npart + kBlock - 1) / kBlock;
+  for (int l = 0; l < nl; ++l) {
+    io.blk0[l] = l * nbp;
+    io.fld[l] = (const V4<T>*)c->fld[di][l].p;
+  }
+  io.blk0[nl] = nl * nbp;
+  io.ax = ax; io.ay = ay; io.az = az; io.pot = pot;
   HIP_TRY(timed(c, "interp", [&] {
-            return launch_interp_all<T>(c->d_grids, ft, x, y, z, own, npart, ax, ay, az, pot,
-                                        c->stream);
+            return launch_interp_sorted<T>(io, (const DepLevel*)c->dep_tab.p, c->d_grids, c->stream);
           }), "interp");
   return APM_OK;
 }
@@ -774,7 +783,7 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
       const int64_t fc = (int64_t)g.fld_n[0] * g.fld_n[1] * g.fld_n[2];
       dep[i + 1] = dep[i] + (gc + kBlock - 1) / kBlock;
       cmp[i + 1] = cmp[i] + (fc + kBlock - 1) / kBlock;
-      const int64_t W = g.M[0] / 2 + 1;
+      const int64_t W = (g.M[0] / 2 + 1 + kRowAlign - 1) / kRowAlign * kRowAlign;   // row pitch
       c->spec_off.push_back((int64_t)c->spec_elems);
       c->z_off.push_back((int64_t)c->z_elems);
       c->y_off.push_back((int64_t)c->y_elems);
@@ -807,7 +816,7 @@ apm_status apm_destroy(apm_ctx c) {
   DevBuf* bufs[] = {&c->spec, &c->zbuf, &c->ybuf, &c->tmpfld, &c->owner, &c->totals,
                     &c->binned, &c->dep_tab};
   for (auto& B : c->lvb)
-    for (DevBuf* b : {&B.count, &B.items, &B.accum, &B.key, &B.rank, &B.sidx, &B.sorted})
+    for (DevBuf* b : {&B.count, &B.items, &B.accum, &B.key, &B.rank, &B.sref, &B.sorted})
       if (b->p) (void)hipFree(b->p);
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
@@ -834,10 +843,11 @@ apm_status apm_owner(apm_ctx c, apm_dtype dt, const void* x, const void* y, cons
   const Plan& P = c->plan;
   hipError_t e = dt == APM_F32
       ? launch_owner<float>(c->d_grids, (int32_t)P.grids.size(), (double)P.cfg.root_n,
-                            (const float*)x, (const float*)y, (const float*)z, npart, owner, c->stream)
+                            (const float*)x, (const float*)y, (const float*)z, npart, owner,
+                            nullptr, nullptr, nullptr, nullptr, c->stream)
       : launch_owner<double>(c->d_grids, (int32_t)P.grids.size(), (double)P.cfg.root_n,
                              (const double*)x, (const double*)y, (const double*)z, npart, owner,
-                             c->stream);
+                             nullptr, nullptr, nullptr, nullptr, c->stream);
   HIP_TRY(e, "apm_owner");
   return APM_OK;
 }
@@ -857,13 +867,13 @@ apm_status apm_deposit(apm_ctx c, apm_dtype dt, int32_t level, const void* x, co
     const float* pg = (const float*)parent_gas;
     float* out = (float*)gmf;
     return deposit_levels_t<float>(c, level, 1, (const float*)x, (const float*)y, (const float*)z,
-                                   (const float*)m, npart, &g, &pg, &out);
+                                   (const float*)m, npart, nullptr, &g, &pg, &out);
   }
   const double* g = (const double*)gas;
   const double* pg = (const double*)parent_gas;
   double* out = (double*)gmf;
   return deposit_levels_t<double>(c, level, 1, (const double*)x, (const double*)y,
-                                  (const double*)z, (const double*)m, npart, &g, &pg, &out);
+                                  (const double*)z, (const double*)m, npart, nullptr, &g, &pg, &out);
 }
 
 apm_status apm_solve_level(apm_ctx c, apm_dtype dt, int32_t level, const void* gmf, void* field) {

@@ -31,10 +31,13 @@ enum { PASS_X_FWD = 0, PASS_Y_FWD = 1, PASS_Z_CONV = 2, PASS_Y_INV = 3, PASS_X_I
 // in elements of the level GMF buffer, the level field buffer (cells) and the
 // shared spectrum, z-output (3 fz My W per grid) and y-output (4 fz fy W per grid)
 // buffers (complex values).
+constexpr int kRowAlign = 16;      // row pitch granularity (complex values): 128 B or more
 struct ConvJob {
   int64_t blk0;                    // first block of this job in its launch
   int32_t level;
   int32_t g[3], M[3], f[3], off[3];
+  int32_t pitch;                   // complex values per row of the spectrum, z and y
+                                   // buffers: W = Mx/2 + 1 rounded up to kRowAlign
   int64_t gmf_off, fld_off, spec_off, z_off, y_off;
   const void* kern;                // octant (Gf, Gp) table
   const void* dsym[3];             // gradient symbols per axis index
@@ -72,15 +75,16 @@ struct DepLevel {
   int32_t key_lo[3], key_n[3];     // binning box (cells)
   int32_t tiles_n[3];              // tiles per axis
   int32_t ntiles, rep;             // rep: counter replicas per tile (power of two)
-  int32_t ngrids;
+  int32_t first, ngrids;           // the level's grids: [first, first + ngrids)
   int64_t key_cells;
   int32_t* count;                  // ntiles * rep + 1; replica r of tile t at t rep + r;
                                    // scanned in place into start offsets
   int32_t* items;                  // ntiles + 1: scanned work-item counts
   int32_t* key;                    // npart: counter slot or -1
   int32_t* rank;                   // npart: rank within the slot
-  int32_t* sidx;                   // sorted position -> original index
-  void* sorted;                    // npart records (s_x, s_y, s_z, m), s = x/dx - key_lo
+  int2* sref;                      // sorted position -> (original index, owner grid if
+                                   // that grid is on this level, else -1)
+  void* sorted;                    // npart records (x/dx, y/dx, z/dx, m); x/dx is exact
   double* accum;                   // key_cells FP64 mass
   const GridDesc* grids;           // the level's grids
   const int64_t* block_begin;      // first finalize block of each grid (ngrids + 1)
@@ -91,6 +95,7 @@ struct DepLevel {
 // (index b = level - first level of the batch).
 template <typename T> struct DepIO {
   const T* x; const T* y; const T* z; const T* m;
+  const int32_t* owner;                // owner grid per particle, or null (no owners)
   int64_t npart;
   int32_t nlev;
   int64_t item_blk0[kMaxLevels + 1];   // deposit-tile blocks of level b: [item_blk0[b], [b+1])
@@ -110,19 +115,27 @@ template <typename T> hipError_t launch_deposit_tiles(const DepIO<T>& io, const 
 template <typename T> hipError_t launch_deposit_finalize(const DepIO<T>& io, const DepLevel* tab,
                                                          hipStream_t s);
 
+// owner grid of every particle; where the outputs are given, particles outside the
+// domain (owner -1) get zero acceleration and potential there
 template <typename T> hipError_t launch_owner(const GridDesc* grids, int32_t ngrids, double root_n,
                                               const T* x, const T* y, const T* z, int64_t npart,
-                                              int32_t* owner, hipStream_t s);
+                                              int32_t* owner, T* ax, T* ay, T* az, T* pot,
+                                              hipStream_t s);
 template <typename T> hipError_t launch_interp(const GridDesc* grids, int32_t level,
                                                const V4<T>* field, const T* x, const T* y,
                                                const T* z, const int32_t* owner, int64_t npart,
                                                T* ax, T* ay, T* az, T* pot, hipStream_t s);
-// every level in one launch: fields[l] is level l's composed field
-template <typename T> struct FieldTable { const V4<T>* f[kMaxLevels]; };
-template <typename T> hipError_t launch_interp_all(const GridDesc* grids, const FieldTable<T>& fields,
-                                                   const T* x, const T* y, const T* z,
-                                                   const int32_t* owner, int64_t npart, T* ax,
-                                                   T* ay, T* az, T* pot, hipStream_t s);
+// TSC interpolation over the tile-sorted lists of a batch of levels (one launch):
+// entry q of level b is interpolated from the composed field fld[b] of its owner
+// grid when that grid is on level b, and written to the particle's original slot.
+template <typename T> struct InterpIO {
+  int32_t nlev;
+  int64_t blk0[kMaxLevels + 1];        // blocks of level b: [blk0[b], blk0[b + 1])
+  const V4<T>* fld[kMaxLevels];
+  T* ax; T* ay; T* az; T* pot;
+};
+template <typename T> hipError_t launch_interp_sorted(const InterpIO<T>& io, const DepLevel* tab,
+                                                      const GridDesc* grids, hipStream_t s);
 template <typename T> hipError_t launch_compose(const GridDesc* grids, const int64_t* block_begin,
                                                 int32_t ngrids, const V4<T>* own,
                                                 const V4<T>* parent, V4<T>* field,

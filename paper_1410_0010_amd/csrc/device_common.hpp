@@ -23,12 +23,32 @@ template <typename T> __device__ __forceinline__ gptr<T> as_global(const void* p
   return (gptr<T>)p;
 }
 template <typename T> using nvec2 = T __attribute__((ext_vector_type(2)));
+template <typename T> using nvec4 = T __attribute__((ext_vector_type(4)));
 
 template <typename T> __device__ __forceinline__ C2<T> mk(T x, T y) { C2<T> r; r.x = x; r.y = y; return r; }
+// Marks a loaded value as used at this point (an empty asm statement: no instruction
+// is emitted).  Placed after a batch of loads, it keeps the compiler from sinking
+// each load into the loop iteration that consumes it, which would expose every
+// load's latency on its own.
+template <typename V> __device__ __forceinline__ void pin4(V& v) {
+  asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+}
+
 // complex element i of a global table reached through a job record
 template <typename T> __device__ __forceinline__ C2<T> load_c2(const void* base, int64_t i) {
   const nvec2<T> v = as_global<nvec2<T>>(base)[i];
   return mk<T>(v.x, v.y);
+}
+// element i of a global array of 4-vectors / int pairs reached through a table
+template <typename T> __device__ __forceinline__ V4<T> load_v4(const void* base, int64_t i) {
+  const nvec4<T> v = as_global<nvec4<T>>(base)[i];
+  V4<T> r;
+  r.x = v.x; r.y = v.y; r.z = v.z; r.w = v.w;
+  return r;
+}
+__device__ __forceinline__ int2 load_i2(const void* base, int64_t i) {
+  const nvec2<int> v = as_global<nvec2<int>>(base)[i];
+  return make_int2(v.x, v.y);
 }
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { a.x += b.x; a.y += b.y; return a; }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { a.x -= b.x; a.y -= b.y; return a; }
@@ -80,6 +100,18 @@ template <bool INV, typename T> __device__ __forceinline__ void dft8(C2<T>* v) {
   v[1] = cadd(e1, t1); v[5] = csub(e1, t1);
   v[2] = cadd(e2, t2); v[6] = csub(e2, t2);
   v[3] = cadd(e3, t3); v[7] = csub(e3, t3);
+}
+
+// ---- XCD-aware block order -------------------------------------------------------
+// The dispatcher hands workgroups to the 8 XCDs round-robin (block b to XCD b mod 8),
+// and each XCD has its own L2.  Remapping so every XCD runs one contiguous range of
+// logical blocks keeps neighbouring blocks -- which read the two halves of the same
+// cache lines -- on one L2.  A bijection of [0, n) for any n.
+constexpr int kXCD = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
+  const int64_t q = n / kXCD, r = n % kXCD;
+  const int64_t x = b % kXCD, i = b / kXCD;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
 // ---- synchronisation between Stockham stages -------------------------------------

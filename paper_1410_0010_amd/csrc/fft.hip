@@ -3,7 +3,8 @@
 // differencing, and the inverse transforms of the four outputs (a_x, a_y, a_z, Phi).
 //
 // Spectrum layout (complex, x fastest): planes z, rows y (My of them), columns
-// kx in [0, W), W = Mx/2 + 1.  Five passes per grid:
+// kx in [0, W), W = Mx/2 + 1, rows P = pitch apart (W rounded up to 16 values, so
+// a block's column segment never straddles more cache lines than it must).  Five passes per grid:
 //   x_fwd   GMF rows (gx reals, zero-padded to Mx) -> half spectra, two real rows
 //           per complex FFT                                   (gy*gz rows)
 //   y_fwd   columns along y: gy inputs -> My outputs, in place (gz planes)
@@ -47,9 +48,10 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
             C2<T>* __restrict__ specb, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
-  const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
-  const int64_t blk = blockIdx.x - J.blk0;
-  const int gx = J.g[0], gy = J.g[1], gz = J.g[2], My = J.M[1], W = J.M[0] / 2 + 1;
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int gx = J.g[0], gy = J.g[1], gz = J.g[2], My = J.M[1], P = J.pitch;
   const T* __restrict__ gmf = lp.gmf[J.level] + J.gmf_off;
   C2<T>* __restrict__ spec = specb + J.spec_off;
   const int t = threadIdx.x;
@@ -70,8 +72,8 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
   fft_line<T, L, false>(line, w, tw);
   if (ra < rows) {
     const int64_t za = ra / gy, ya = ra % gy, zb = rb / gy, yb = rb % gy;
-    C2<T>* outa = spec + (za * My + ya) * W;
-    C2<T>* outb = spec + (zb * My + yb) * W;
+    C2<T>* outa = spec + (za * My + ya) * P;
+    C2<T>* outb = spec + (zb * My + yb) * P;
     const T h = (T)0.5;
     for (int k = w; k <= L / 2; k += L / 8) {
       C2<T> z = line[k], m = line[(L - k) & (L - 1)];
@@ -89,13 +91,14 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
             const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
-  const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
-  const int64_t blk = blockIdx.x - J.blk0;
-  const int W = J.M[0] / 2 + 1, My = J.M[1], gy = J.g[1];
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1], gy = J.g[1], P = J.pitch;
   const int nbw = (W + nl - 1) / nl;
   const int64_t p = blk / nbw;
   const int c0 = (int)(blk % nbw) * nl;
-  C2<T>* base = specb + J.spec_off + p * ((int64_t)My * W) + c0;
+  C2<T>* base = specb + J.spec_off + p * ((int64_t)My * P) + c0;
   const int t = threadIdx.x;
   // column-wise mapping: thread t holds column t mod nl, rows t/nl + q L/8 (nl L/8
   // threads, 8 elements each; all loads issued before the first LDS write)
@@ -105,7 +108,7 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int r = r0 + q * (L / 8);
-    v[q] = (r < gy && col_ok) ? base[(int64_t)r * W + cb] : mk<T>(0, 0);
+    v[q] = (r < gy && col_ok) ? base[(int64_t)r * P + cb] : mk<T>(0, 0);
   }
 #pragma unroll
   for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
@@ -117,7 +120,7 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int j = r0 + q * (L / 8);
-      base[(int64_t)j * W + cb] = lds[cb * ls + j];
+      base[(int64_t)j * P + cb] = lds[cb * ls + j];
     }
   }
 }
@@ -139,9 +142,10 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
              const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
-  const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
-  const int64_t blk = blockIdx.x - J.blk0;
-  const int W = J.M[0] / 2 + 1, My = J.M[1];
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1], P = J.pitch;
   const int gz = J.g[2], fz = J.f[2], oz = J.off[2];
   const int nbw = (W + nl - 1) / nl;
   const int ky = (int)(blk / nbw);
@@ -149,12 +153,12 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const C2<T>* __restrict__ spec = specb + J.spec_off;
   C2<T>* __restrict__ zo = zb + J.z_off;
   const gptr<T> dzs = as_global<T>(J.dsym[2]);
-  const int64_t pstride = (int64_t)My * W;
+  const int64_t pstride = (int64_t)My * P;
   const int t = threadIdx.x;
   const int cb = t % nl, r0 = t / nl;                // column-wise mapping, as in y_fwd
   const bool col_ok = c0 + cb < W;
   {
-    const C2<T>* src = spec + (int64_t)ky * W + c0 + cb;
+    const C2<T>* src = spec + (int64_t)ky * P + c0 + cb;
     C2<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -203,7 +207,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       for (int q = 0; q < 8; ++q) {
         const int j = r0 + q * (L / 8);
         if (j < fz)
-          zo[((int64_t)(s * fz + j) * My + ky) * W + c0 + cb] = lds[cb * ls + ((oz + j) & (L - 1))];
+          zo[((int64_t)(s * fz + j) * My + ky) * P + c0 + cb] = lds[cb * ls + ((oz + j) & (L - 1))];
       }
     }
     __syncthreads();
@@ -222,18 +226,19 @@ k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
             const C2<T>* __restrict__ zb, C2<T>* __restrict__ yb, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
-  const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
-  const int64_t blk = blockIdx.x - J.blk0;
-  const int W = J.M[0] / 2 + 1, My = J.M[1];
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1], P = J.pitch;
   const int fz = J.f[2], fy = J.f[1], oy = J.off[1];
   const int nbw = (W + nl - 1) / nl;
   const int j = (int)(blk / nbw);
   const int c0 = (int)(blk % nbw) * nl;
   const gptr<T> dys = as_global<T>(J.dsym[1]);
-  const C2<T>* zin = zb + J.z_off + (int64_t)j * My * W + c0;
-  const int64_t zs = (int64_t)fz * My * W;             // stride between z arrays
-  C2<T>* yout = yb + J.y_off + (int64_t)j * fy * W + c0;
-  const int64_t ys = (int64_t)fz * fy * W;             // stride between components
+  const C2<T>* zin = zb + J.z_off + (int64_t)j * My * P + c0;
+  const int64_t zs = (int64_t)fz * My * P;             // stride between z arrays
+  C2<T>* yout = yb + J.y_off + (int64_t)j * fy * P + c0;
+  const int64_t ys = (int64_t)fz * fy * P;             // stride between components
   const int t = threadIdx.x;
   // lines: component c of column cb at lds[(c nl + cb) ls]; loads are column-wise,
   // thread t: column t mod nl, rows t/nl + q L/2 (4 nl L/8 threads, 2 rows each)
@@ -242,7 +247,7 @@ k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   C2<T> v[2][3];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const int64_t o = (int64_t)(r0 + q * (L / 2)) * W + cb;
+    const int64_t o = (int64_t)(r0 + q * (L / 2)) * P + cb;
 #pragma unroll
     for (int a = 0; a < 3; ++a) v[q][a] = col_ok ? zin[a * zs + o] : mk<T>(0, 0);
   }
@@ -266,7 +271,7 @@ k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       if (jj < fy) {
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-          yout[c * ys + (int64_t)jj * W + cb] = lds[(c * nl + cb) * ls + ((oy + jj) & (L - 1))];
+          yout[c * ys + (int64_t)jj * P + cb] = lds[(c * nl + cb) * ls + ((oy + jj) & (L - 1))];
       }
     }
   }
@@ -287,9 +292,10 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
             LevelPtrs<T> lp, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
-  const ConvJob& J = jobs[find_job(jobs, njobs, blockIdx.x)];
-  const int64_t blk = blockIdx.x - J.blk0;
-  const int W = J.M[0] / 2 + 1;
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int P = J.pitch;
   const int fx = J.f[0], fy = J.f[1], fz = J.f[2], ox = J.off[0];
   const C2<T>* __restrict__ ybuf = yb + J.y_off;
   const gptr<T> dxs = as_global<T>(J.dsym[0]);
@@ -304,10 +310,10 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
   const int64_t ra = 2 * q, rb = 2 * q + 1;
   C2<T>* line = lds + b * L;
   if (ra < rows) {
-    const int64_t cs = (int64_t)c * rows * W;         // component stride
-    const C2<T>* A = ybuf + cs + ra * W;
+    const int64_t cs = (int64_t)c * rows * P;         // component stride
+    const C2<T>* A = ybuf + cs + ra * P;
     const bool hb = rb < rows;
-    const C2<T>* B = ybuf + cs + (hb ? rb : ra) * W;
+    const C2<T>* B = ybuf + cs + (hb ? rb : ra) * P;
     for (int i = w; i < L; i += L / 8) {
       const int k = i <= L / 2 ? i : L - i;
       C2<T> a = A[k], bq = hb ? B[k] : mk<T>(0, 0);

@@ -40,6 +40,53 @@ __device__ __forceinline__ int batch_level(const int64_t* blk0, int nlev, int64_
   return b;
 }
 
+// TSC gather of the 27 cells around cell (ix, iy, iz) (box-relative) of a field box of
+// dims n, with offsets t from the cell centre.  Branch-free: a cell outside the box
+// gets weight 0 and a clamped (valid) address, so all 27 loads are issued together.
+template <typename T>
+__device__ __forceinline__ V4<T> tsc_gather(const V4<T>* __restrict__ F, int nx, int ny, int nz,
+                                            int ix, int iy, int iz, T tx, T ty, T tz) {
+  const int n[3] = {nx, ny, nz};
+  int cx[3], cy[3], cz[3];
+  T wx[3], wy[3], wz[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int x = ix + d - 1, y = iy + d - 1, z = iz + d - 1;
+    const bool okx = (x >= 0) & (x < nx), oky = (y >= 0) & (y < ny), okz = (z >= 0) & (z < nz);
+    cx[d] = okx ? x : 0;
+    cy[d] = oky ? y : 0;
+    cz[d] = okz ? z : 0;
+    wx[d] = okx ? tsc_w(d - 1, tx) : (T)0;
+    wy[d] = oky ? tsc_w(d - 1, ty) : (T)0;
+    wz[d] = okz ? tsc_w(d - 1, tz) : (T)0;
+  }
+  V4<T> acc;
+  acc.x = 0; acc.y = 0; acc.z = 0; acc.w = 0;
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz) {                   // a plane of 9 loads at a time
+    V4<T> f[9];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      const V4<T>* row = F + ((int64_t)cz[dz] * n[1] + cy[dy]) * n[0];
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) f[3 * dy + dx] = row[cx[dx]];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) pin4(f[k]);
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      const T wzy = wz[dz] * wy[dy];
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const V4<T>& v = f[3 * dy + dx];
+        const T w = wzy * wx[dx];
+        acc.x += w * v.x; acc.y += w * v.y; acc.z += w * v.z; acc.w += w * v.w;
+      }
+    }
+  }
+  return acc;
+}
+
 // ---- clear: counters and FP64 mass grids of every level of the batch ---------------
 __global__ void __launch_bounds__(kBlock) k_dep_clear(const DepLevel* __restrict__ tab) {
   const DepLevel& L = tab[blockIdx.y];
@@ -82,14 +129,22 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(DepIO<T> io, const DepLeve
   const int64_t base = (int64_t)blockIdx.x * kBinBlockParticles + threadIdx.x;
   const T sc = (T)L.inv_dx;
   int32_t key[kBinPer], slot[kBinPer], lrank[kBinPer];
+  T px[kBinPer], py[kBinPer], pz[kBinPer];
+#pragma unroll
+  for (int q = 0; q < kBinPer; ++q) {                // all loads before the hashing
+    const int64_t i = base + (int64_t)q * kBlock;
+    const bool ok = i < io.npart;
+    px[q] = ok ? io.x[i] : (T)-1;
+    py[q] = ok ? io.y[i] : (T)-1;
+    pz[q] = ok ? io.z[i] : (T)-1;
+  }
 #pragma unroll
   for (int q = 0; q < kBinPer; ++q) {
-    const int64_t i = base + (int64_t)q * kBlock;
     key[q] = -1;
     slot[q] = -1;
     lrank[q] = 0;
-    if (i < io.npart) {
-      const T x = io.x[i], y = io.y[i], z = io.z[i];
+    {
+      const T x = px[q], y = py[q], z = pz[q];
       if (in_domain(x, y, z)) {
         const int ix = (int)floor(x * sc) - L.key_lo[0];
         const int iy = (int)floor(y * sc) - L.key_lo[1];
@@ -249,14 +304,18 @@ __global__ void __launch_bounds__(kBlock) k_bin_scatter(DepIO<T> io, const DepLe
   if (key < 0) return;
   const T sc = (T)L.inv_dx;
   V4<T> r;
-  // exact: x/dx is exact (dx a power of two) and the origin an integer below it
-  r.x = io.x[i] * sc - (T)L.key_lo[0];
-  r.y = io.y[i] * sc - (T)L.key_lo[1];
-  r.z = io.z[i] * sc - (T)L.key_lo[2];
+  r.x = io.x[i] * sc;                                // exact: dx is a power of two
+  r.y = io.y[i] * sc;
+  r.z = io.z[i] * sc;
   r.w = io.m[i];
+  int32_t og = -1;
+  if (io.owner) {
+    const int32_t o = io.owner[i];
+    if (o >= L.first && o < L.first + L.ngrids) og = o;
+  }
   const int32_t slot = L.count[key] + L.rank[i];
   ((V4<T>*)L.sorted)[slot] = r;
-  L.sidx[slot] = (int32_t)i;
+  L.sref[slot] = make_int2((int32_t)i, og);
 }
 
 template <typename T>
@@ -301,12 +360,24 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
   __syncthreads();
   const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
             oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;
-  const V4<T>* __restrict__ sorted = (const V4<T>*)L.sorted;
-  for (int64_t q = begin + threadIdx.x; q < end; q += kBlock) {
-    const V4<T> v = sorted[q];
+  static_assert(kChunk == 8 * kBlock, "a chunk is eight records per thread");
+  V4<T> rec[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {                      // the whole chunk's loads first
+    const int64_t q = begin + threadIdx.x + (int64_t)k * kBlock;
+    rec[k] = load_v4<T>(L.sorted, q < end ? q : begin);   // begin < end: a valid record
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) pin4(rec[k]);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (begin + threadIdx.x + (int64_t)k * kBlock >= end) break;
+    const V4<T> v = rec[k];
     const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
-    const int ix = min(max((int)fx - ox, 0), kTile - 1), iy = min(max((int)fy - oy, 0), kTile - 1),
-              iz = min(max((int)fz - oz, 0), kTile - 1);
+    // cell relative to the tile origin (always inside the tile; clamped defensively)
+    const int ix = min(max((int)fx - L.key_lo[0] - ox, 0), kTile - 1),
+              iy = min(max((int)fy - L.key_lo[1] - oy, 0), kTile - 1),
+              iz = min(max((int)fz - L.key_lo[2] - oz, 0), kTile - 1);
     const double tx = (double)(v.x - fx) - 0.5, ty = (double)(v.y - fy) - 0.5,
                  tz = (double)(v.z - fz) - 0.5;
     const double wx[3] = {0.5 * (0.5 - tx) * (0.5 - tx), 0.75 - tx * tx, 0.5 * (0.5 + tx) * (0.5 + tx)};
@@ -394,7 +465,8 @@ hipError_t launch_deposit_finalize(const DepIO<T>& io, const DepLevel* tab, hipS
 template <typename T>
 __global__ void k_owner(const GridDesc* __restrict__ grids, int32_t ngrids, double root_n,
                         const T* __restrict__ x, const T* __restrict__ y, const T* __restrict__ z,
-                        int64_t npart, int32_t* __restrict__ owner) {
+                        int64_t npart, int32_t* __restrict__ owner, T* __restrict__ ax,
+                        T* __restrict__ ay, T* __restrict__ az, T* __restrict__ pot) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npart) return;
   const T px = x[i], py = y[i], pz = z[i];
@@ -415,15 +487,20 @@ __global__ void k_owner(const GridDesc* __restrict__ grids, int32_t ngrids, doub
     }
   }
   owner[i] = best;
+  if (best < 0 && ax) {
+    ax[i] = 0; ay[i] = 0; az[i] = 0;
+    if (pot) pot[i] = 0;
+  }
 }
 
 template <typename T>
 hipError_t launch_owner(const GridDesc* grids, int32_t ngrids, double root_n, const T* x,
-                        const T* y, const T* z, int64_t npart, int32_t* owner, hipStream_t s) {
+                        const T* y, const T* z, int64_t npart, int32_t* owner, T* ax, T* ay, T* az,
+                        T* pot, hipStream_t s) {
   if (npart == 0) return hipSuccess;
   const unsigned nb = (unsigned)((npart + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_owner<T>), dim3(nb), dim3(kBlock), 0, s, grids, ngrids, root_n, x, y, z,
-                     npart, owner);
+                     npart, owner, ax, ay, az, pot);
   return hipGetLastError();
 }
 
@@ -442,29 +519,14 @@ __global__ void k_interp(const GridDesc* __restrict__ grids, int32_t level,
   if (g.level != level) return;
   const T s = (T)(1.0 / g.dx);
   const T sx = x[i] * s, sy = y[i] * s, sz = z[i] * s;
-  const int ix = (int)floor(sx), iy = (int)floor(sy), iz = (int)floor(sz);
-  const T tx = sx - (T)ix - (T)0.5, ty = sy - (T)iy - (T)0.5, tz = sz - (T)iz - (T)0.5;
-  T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-  const V4<T>* F = field + g.fld_offset;
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int cz = iz + dz - g.fld_lo[2];
-    if (cz < 0 || cz >= g.fld_n[2]) continue;
-    const T wz = tsc_w(dz, tz);
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int cy = iy + dy - g.fld_lo[1];
-      if (cy < 0 || cy >= g.fld_n[1]) continue;
-      const T wzy = wz * tsc_w(dy, ty);
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int cx = ix + dx - g.fld_lo[0];
-        if (cx < 0 || cx >= g.fld_n[0]) continue;
-        const T w = wzy * tsc_w(dx, tx);
-        const V4<T> f = F[((int64_t)cz * g.fld_n[1] + cy) * g.fld_n[0] + cx];
-        acc0 += w * f.x; acc1 += w * f.y; acc2 += w * f.z; acc3 += w * f.w;
-      }
-    }
-  }
-  ax[i] = acc0; ay[i] = acc1; az[i] = acc2;
-  if (pot) pot[i] = acc3;
+  const T fx = floor(sx), fy = floor(sy), fz = floor(sz);
+  const int64_t off = g.fld_offset;
+  const int nx = g.fld_n[0], ny = g.fld_n[1], nz = g.fld_n[2];
+  const V4<T> a = tsc_gather<T>(field + off, nx, ny, nz, (int)fx - g.fld_lo[0],
+                                (int)fy - g.fld_lo[1], (int)fz - g.fld_lo[2], sx - fx - (T)0.5,
+                                sy - fy - (T)0.5, sz - fz - (T)0.5);
+  ax[i] = a.x; ay[i] = a.y; az[i] = a.z;
+  if (pot) pot[i] = a.w;
 }
 
 template <typename T>
@@ -478,53 +540,37 @@ hipError_t launch_interp(const GridDesc* grids, int32_t level, const V4<T>* fiel
   return hipGetLastError();
 }
 
+// Sorted-order interpolation: consecutive lanes hold particles of one tile, so their
+// 27-cell gathers share cache lines; each entry owned on this level writes its
+// particle's outputs in the original order.
 template <typename T>
-__global__ void k_interp_all(const GridDesc* __restrict__ grids, FieldTable<T> fields,
-                             const T* __restrict__ x, const T* __restrict__ y,
-                             const T* __restrict__ z, const int32_t* __restrict__ owner,
-                             int64_t npart, T* __restrict__ ax, T* __restrict__ ay,
-                             T* __restrict__ az, T* __restrict__ pot) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npart) return;
-  const int32_t o = owner[i];
-  T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-  if (o >= 0) {
-    const GridDesc& g = grids[o];
-    const T s = (T)(1.0 / g.dx);
-    const T sx = x[i] * s, sy = y[i] * s, sz = z[i] * s;
-    const int ix = (int)floor(sx), iy = (int)floor(sy), iz = (int)floor(sz);
-    const T tx = sx - (T)ix - (T)0.5, ty = sy - (T)iy - (T)0.5, tz = sz - (T)iz - (T)0.5;
-    const V4<T>* F = fields.f[g.level] + g.fld_offset;
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int cz = iz + dz - g.fld_lo[2];
-      if (cz < 0 || cz >= g.fld_n[2]) continue;
-      const T wz = tsc_w(dz, tz);
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int cy = iy + dy - g.fld_lo[1];
-        if (cy < 0 || cy >= g.fld_n[1]) continue;
-        const T wzy = wz * tsc_w(dy, ty);
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int cx = ix + dx - g.fld_lo[0];
-          if (cx < 0 || cx >= g.fld_n[0]) continue;
-          const T w = wzy * tsc_w(dx, tx);
-          const V4<T> f = F[((int64_t)cz * g.fld_n[1] + cy) * g.fld_n[0] + cx];
-          acc0 += w * f.x; acc1 += w * f.y; acc2 += w * f.z; acc3 += w * f.w;
-        }
-      }
-    }
-  }
-  ax[i] = acc0; ay[i] = acc1; az[i] = acc2;
-  if (pot) pot[i] = acc3;
+__global__ void __launch_bounds__(kBlock) k_interp_sorted(InterpIO<T> io, const DepLevel* __restrict__ tab,
+                                                          const GridDesc* __restrict__ grids) {
+  const int lb = batch_level(io.blk0, io.nlev, blockIdx.x);
+  const DepLevel& L = tab[lb];
+  const int64_t q = (blockIdx.x - io.blk0[lb]) * (int64_t)kBlock + threadIdx.x;
+  if (q >= *L.binned) return;
+  const int2 r = load_i2(L.sref, q);
+  const V4<T> v = load_v4<T>(L.sorted, q);
+  if (r.y < 0) return;
+  const GridDesc& g = grids[r.y];
+  const int64_t off = g.fld_offset;
+  const int nx = g.fld_n[0], ny = g.fld_n[1], nz = g.fld_n[2];
+  const int lx = g.fld_lo[0], ly = g.fld_lo[1], lz = g.fld_lo[2];
+  const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
+  const V4<T> a = tsc_gather<T>(io.fld[lb] + off, nx, ny, nz, (int)fx - lx, (int)fy - ly,
+                                (int)fz - lz, v.x - fx - (T)0.5, v.y - fy - (T)0.5,
+                                v.z - fz - (T)0.5);
+  io.ax[r.x] = a.x; io.ay[r.x] = a.y; io.az[r.x] = a.z;
+  if (io.pot) io.pot[r.x] = a.w;
 }
 
 template <typename T>
-hipError_t launch_interp_all(const GridDesc* grids, const FieldTable<T>& fields, const T* x,
-                             const T* y, const T* z, const int32_t* owner, int64_t npart, T* ax,
-                             T* ay, T* az, T* pot, hipStream_t s) {
-  if (npart == 0) return hipSuccess;
-  const unsigned nb = (unsigned)((npart + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_interp_all<T>), dim3(nb), dim3(kBlock), 0, s, grids, fields, x, y, z,
-                     owner, npart, ax, ay, az, pot);
+hipError_t launch_interp_sorted(const InterpIO<T>& io, const DepLevel* tab, const GridDesc* grids,
+                                hipStream_t s) {
+  const int64_t nb = io.blk0[io.nlev];
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_interp_sorted<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab, grids);
   return hipGetLastError();
 }
 
@@ -533,11 +579,10 @@ hipError_t launch_interp_all(const GridDesc* grids, const FieldTable<T>& fields,
   template hipError_t launch_bin_scatter<T>(const DepIO<T>&, const DepLevel*, hipStream_t);    \
   template hipError_t launch_deposit_tiles<T>(const DepIO<T>&, const DepLevel*, hipStream_t);  \
   template hipError_t launch_deposit_finalize<T>(const DepIO<T>&, const DepLevel*, hipStream_t); \
-  template hipError_t launch_interp_all<T>(const GridDesc*, const FieldTable<T>&, const T*,      \
-                                           const T*, const T*, const int32_t*, int64_t, T*, T*,  \
-                                           T*, T*, hipStream_t);                                 \
   template hipError_t launch_owner<T>(const GridDesc*, int32_t, double, const T*, const T*,     \
-                                      const T*, int64_t, int32_t*, hipStream_t);                \
+                                      const T*, int64_t, int32_t*, T*, T*, T*, T*, hipStream_t); \
+  template hipError_t launch_interp_sorted<T>(const InterpIO<T>&, const DepLevel*,              \
+                                              const GridDesc*, hipStream_t);                    \
   template hipError_t launch_interp<T>(const GridDesc*, int32_t, const V4<T>*, const T*,       \
                                        const T*, const T*, const int32_t*, int64_t, T*, T*, T*, \
                                        T*, hipStream_t);
