@@ -209,11 +209,49 @@ apm_status apm_solve(apm_ctx ctx, apm_dtype dtype, const void* x, const void* y,
                      const void* z, const void* m, int64_t npart, const void* const* gas,
                      void* ax, void* ay, void* az, void* pot);
 
-/* apm_totals over the library-owned GMFs and owner grids of the last apm_solve of
- * `dtype` (same outputs and synchronisation); m, ax, ay, az, pot as passed to it. */
+/* Totals of the last apm_solve of `dtype` over its library-owned GMFs, owner grids
+ * and composed fields; m, gas, ax, ay, az, pot as passed to it (gas may be NULL).
+ * out has nlevels + 5 entries: out[0..nlevels) deposited mass per level as in
+ * apm_totals; out[nlevels] the potential energy W = 1/2 sum_p m_p Phi_p (owned
+ * particles) + 1/2 sum rho_gas Phi dx^3 (active gas cells owned by their grid:
+ * no finer grid and no lower-index grid of the level contains the cell centre);
+ * out[nlevels + 1..3] sum_p m_p a_p; out[nlevels + 4] the gas part of W.
+ * Synchronises. */
 apm_status apm_solve_totals(apm_ctx ctx, apm_dtype dtype, const void* m, int64_t npart,
-                            const void* ax, const void* ay, const void* az, const void* pot,
-                            double* out);
+                            const void* const* gas, const void* ax, const void* ay,
+                            const void* az, const void* pot, double* out);
+
+/* Gas part of the potential energy of one level (as in apm_solve_totals) from its
+ * packed active gas and its composed field (apm_accel output layout).  Written to
+ * *out; synchronises. */
+apm_status apm_gas_energy(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* gas,
+                          const void* field, double* out);
+
+/* ------------------------------------------------------ time integration ---- */
+
+/* Leapfrog pieces (Sec. 2 time-centring; every level on one step, no subcycling,
+ * Sec. 3.1, 3.5).  apm_kick: v += h a.  apm_drift: x += h v.  Arrays are npart
+ * device values of `dtype`, updated in place; asynchronous. */
+apm_status apm_kick(apm_ctx ctx, apm_dtype dtype, int64_t npart, void* vx, void* vy, void* vz,
+                    const void* ax, const void* ay, const void* az, double h);
+apm_status apm_drift(apm_ctx ctx, apm_dtype dtype, int64_t npart, void* x, void* y, void* z,
+                     const void* vx, const void* vy, const void* vz, double h);
+
+/* Kinetic energy 1/2 sum_p m_p |v_p|^2 in FP64 into *out; synchronises. */
+apm_status apm_kinetic_energy(apm_ctx ctx, apm_dtype dtype, const void* m, const void* vx,
+                              const void* vy, const void* vz, int64_t npart, double* out);
+
+/* nsteps kick-drift-kick steps of size h: an initial apm_solve at x, then per step
+ * v += (h/2) a; x += h v; apm_solve; v += (h/2) a.  x..vz are updated in place; on
+ * return ax, ay, az, pot hold the accelerations and potentials at the final
+ * positions (pot may be NULL: a library buffer is used).  gas as in apm_solve,
+ * held fixed.  energy (host, NULL or nsteps + 1 values) receives the total energy
+ * K + W after the initial solve and after every step, W as in apm_solve_totals.
+ * Synchronises once at the end. */
+apm_status apm_leapfrog(apm_ctx ctx, apm_dtype dtype, void* x, void* y, void* z, void* vx,
+                        void* vy, void* vz, const void* m, int64_t npart, const void* const* gas,
+                        double h, int32_t nsteps, void* ax, void* ay, void* az, void* pot,
+                        double* energy);
 
 /* Device pointer to the library-owned composed field (or GMF) of `level` written
  * by the last apm_solve; NULL on error. */

@@ -83,8 +83,16 @@ SIGNATURES = {
                          ctypes.POINTER(ctypes.c_double)]),
     "apm_solve": (_st, [_vp, _st, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_vp), _vp, _vp, _vp,
                         _vp]),
-    "apm_solve_totals": (_st, [_vp, _st, _vp, _i64, _vp, _vp, _vp, _vp,
+    "apm_solve_totals": (_st, [_vp, _st, _vp, _i64, ctypes.POINTER(_vp), _vp, _vp, _vp, _vp,
                                ctypes.POINTER(ctypes.c_double)]),
+    "apm_gas_energy": (_st, [_vp, _st, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "apm_kick": (_st, [_vp, _st, _i64, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double]),
+    "apm_drift": (_st, [_vp, _st, _i64, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double]),
+    "apm_kinetic_energy": (_st, [_vp, _st, _vp, _vp, _vp, _vp, _i64,
+                                 ctypes.POINTER(ctypes.c_double)]),
+    "apm_leapfrog": (_st, [_vp, _st, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_vp),
+                           ctypes.c_double, _i32, _vp, _vp, _vp, _vp,
+                           ctypes.POINTER(ctypes.c_double)]),
     "apm_field_ptr": (_vp, [_vp, _st, _i32]),
     "apm_gmf_ptr": (_vp, [_vp, _st, _i32]),
     "apm_set_graph": (_st, [_vp, _i32]),

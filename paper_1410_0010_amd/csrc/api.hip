@@ -31,13 +31,13 @@ struct apm_ctx_s {
   hipStream_t stream = nullptr;
   size_t used = 0;
   GridDesc* d_grids = nullptr;
-  std::vector<int64_t*> d_dep_begin, d_cmp_begin;
-  std::vector<int64_t> dep_blocks, cmp_blocks;
+  std::vector<int64_t*> d_dep_begin, d_cmp_begin, d_act_begin;     // per level: first block
+  std::vector<int64_t> dep_blocks, cmp_blocks, act_blocks;         // of each grid, and total
   std::map<std::pair<int, int>, void*> tw;                        // (dtype, L)
   std::map<std::tuple<int, int, int>, void*> dsym;                // (dtype, level, M)
   std::map<std::tuple<int, int, int, int, int>, void*> kern;      // (dtype, level, Mx, My, Mz)
   std::vector<void*> owned;                                       // every table allocation
-  DevBuf spec, zbuf, ybuf, tmpfld, owner, totals, binned;
+  DevBuf spec, zbuf, ybuf, tmpfld, owner, totals, binned, gpart, energy, lf_pot;
   // per level: tile counters, work items, FP64 mass grid, particle keys/ranks, the
   // tile-sorted records and their original indices
   struct LevelBufs { DevBuf count, items, accum, key, rank, sref, sorted; };
@@ -752,6 +752,83 @@ apm_status autotune_t(apm_ctx c, apm_dtype dt, int reps) {
 
 // =================================================================== C ABI ==========
 
+// Gas energy of every level with gas into dev[0] (added); partials in c->gpart.
+template <typename T>
+apm_status gas_energy_levels_t(apm_ctx c, const void* const* gas, const V4<T>* const* fields,
+                               double* dev) {
+  const Plan& P = c->plan;
+  int64_t maxb = 1;
+  for (int64_t b : c->act_blocks) maxb = std::max(maxb, b);
+  APM_TRY(ensure(c, c->gpart, (size_t)maxb * 8, "gas energy partials"));
+  for (size_t l = 0; l < P.levels.size(); ++l) {
+    if (!gas || !gas[l]) continue;
+    const LevelDesc& L = P.levels[l];
+    HIP_TRY(launch_gas_energy<T>(c->d_grids, (int32_t)P.grids.size(), L.first, L.count,
+                                 c->d_act_begin[l], c->act_blocks[l], (double)P.cfg.root_n,
+                                 (const T*)gas[l], fields[l], (double*)c->gpart.p, dev, c->stream),
+            "gas energy");
+  }
+  return APM_OK;
+}
+
+// Energy terms of step slot e (6 doubles: K, W_particles, sum m a (3), W_gas) after a
+// solve; all on the stream, no synchronisation.
+template <typename T>
+apm_status step_energy_t(apm_ctx c, apm_dtype dt, const T* m, const T* vx, const T* vy,
+                         const T* vz, int64_t n, const T* ax, const T* ay, const T* az,
+                         const T* pot, const void* const* gas, double* e) {
+  double* part = (double*)c->totals.p + 8;
+  HIP_TRY(launch_kinetic<T>(m, vx, vy, vz, n, part, e, c->stream), "leapfrog kinetic");
+  HIP_TRY(launch_particle_totals<T>(m, (const int32_t*)c->owner.p, n, ax, ay, az, pot, part, e + 1,
+                                    c->stream), "leapfrog particle energy");
+  const int nl = (int)c->plan.levels.size();
+  std::vector<const V4<T>*> f(nl);
+  for (int l = 0; l < nl; ++l) f[l] = (const V4<T>*)c->fld[(int)dt][l].p;
+  APM_TRY(gas_energy_levels_t<T>(c, gas, f.data(), e + 5));
+  return APM_OK;
+}
+
+template <typename T>
+apm_status leapfrog_t(apm_ctx c, apm_dtype dt, T* x, T* y, T* z, T* vx, T* vy, T* vz, const T* m,
+                      int64_t n, const void* const* gas, double h, int32_t nsteps, T* ax, T* ay,
+                      T* az, T* pot, double* energy) {
+  const int nl = (int)c->plan.levels.size();
+  APM_TRY(ensure(c, c->totals, (size_t)(nl + 4 + 8 + 4 * kMaxParts) * 8, "totals"));
+  if (!pot) {
+    APM_TRY(ensure(c, c->lf_pot, (size_t)std::max<int64_t>(n, 1) * sizeof(T), "leapfrog potential"));
+    pot = (T*)c->lf_pot.p;
+  }
+  const size_t ne = energy ? (size_t)(nsteps + 1) * 6 : 0;
+  if (energy) {
+    APM_TRY(ensure(c, c->energy, ne * 8, "leapfrog energies"));
+    HIP_TRY(launch_fill_f64((double*)c->energy.p, (int64_t)ne, 0.0, c->stream), "energy fill");
+  }
+  double* E = (double*)c->energy.p;
+  APM_TRY(solve_t<T>(c, dt, x, y, z, m, n, gas, ax, ay, az, pot));
+  if (energy) APM_TRY(step_energy_t<T>(c, dt, m, vx, vy, vz, n, ax, ay, az, pot, gas, E));
+  for (int32_t s = 0; s < nsteps; ++s) {
+    HIP_TRY(timed(c, "kick_drift", [&] {
+              return launch_kick_drift<T>(n, x, y, z, vx, vy, vz, ax, ay, az, 0.5 * h, h, c->stream);
+            }), "leapfrog kick-drift");
+    APM_TRY(solve_t<T>(c, dt, x, y, z, m, n, gas, ax, ay, az, pot));
+    HIP_TRY(timed(c, "kick", [&] {
+              return launch_kick_drift<T>(n, nullptr, nullptr, nullptr, vx, vy, vz, ax, ay, az,
+                                          0.5 * h, 0.0, c->stream);
+            }), "leapfrog kick");
+    if (energy)
+      APM_TRY(step_energy_t<T>(c, dt, m, vx, vy, vz, n, ax, ay, az, pot, gas, E + 6 * (s + 1)));
+  }
+  if (energy) {
+    std::vector<double> h6(ne);
+    HIP_TRY(hipMemcpyAsync(h6.data(), E, ne * 8, hipMemcpyDeviceToHost, c->stream), "energy copy");
+    HIP_TRY(hipStreamSynchronize(c->stream), "leapfrog sync");
+    for (int32_t s = 0; s <= nsteps; ++s) energy[s] = h6[6 * s] + h6[6 * s + 1] + h6[6 * s + 5];
+  } else {
+    HIP_TRY(hipStreamSynchronize(c->stream), "leapfrog sync");
+  }
+  return APM_OK;
+}
+
 extern "C" {
 
 apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out) {
@@ -775,14 +852,16 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
                          "grid table");
   if (st != APM_OK) { apm_destroy(c); return st; }
   for (const LevelDesc& L : P.levels) {
-    std::vector<int64_t> dep(L.count + 1), cmp(L.count + 1);
-    dep[0] = cmp[0] = 0;
+    std::vector<int64_t> dep(L.count + 1), cmp(L.count + 1), act(L.count + 1);
+    dep[0] = cmp[0] = act[0] = 0;
     for (int i = 0; i < L.count; ++i) {
       const GridDesc& g = P.grids[L.first + i];
       const int64_t gc = (int64_t)g.gmf_n[0] * g.gmf_n[1] * g.gmf_n[2];
       const int64_t fc = (int64_t)g.fld_n[0] * g.fld_n[1] * g.fld_n[2];
+      const int64_t ac = (int64_t)g.n[0] * g.n[1] * g.n[2];
       dep[i + 1] = dep[i] + (gc + kBlock - 1) / kBlock;
       cmp[i + 1] = cmp[i] + (fc + kBlock - 1) / kBlock;
+      act[i + 1] = act[i] + (ac + kBlock - 1) / kBlock;
       const int64_t W = (g.M[0] / 2 + 1 + kRowAlign - 1) / kRowAlign * kRowAlign;   // row pitch
       c->spec_off.push_back((int64_t)c->spec_elems);
       c->z_off.push_back((int64_t)c->z_elems);
@@ -791,14 +870,17 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
       c->z_elems += (size_t)(3 * (int64_t)g.fld_n[2] * g.M[1] * W);
       c->y_elems += (size_t)(4 * (int64_t)g.fld_n[2] * g.fld_n[1] * W);
     }
-    void *d1 = nullptr, *d2 = nullptr;
+    void *d1 = nullptr, *d2 = nullptr, *d3 = nullptr;
     st = upload(c, &d1, dep.data(), dep.size() * 8, "deposit block table");
     if (st == APM_OK) st = upload(c, &d2, cmp.data(), cmp.size() * 8, "compose block table");
+    if (st == APM_OK) st = upload(c, &d3, act.data(), act.size() * 8, "active cell block table");
     if (st != APM_OK) { apm_destroy(c); return st; }
     c->d_dep_begin.push_back((int64_t*)d1);
     c->d_cmp_begin.push_back((int64_t*)d2);
+    c->d_act_begin.push_back((int64_t*)d3);
     c->dep_blocks.push_back(dep.back());
     c->cmp_blocks.push_back(cmp.back());
+    c->act_blocks.push_back(act.back());
   }
   *out = c;
   clear_error();
@@ -814,7 +896,7 @@ apm_status apm_destroy(apm_ctx c) {
   for (void* p : c->owned) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   DevBuf* bufs[] = {&c->spec, &c->zbuf, &c->ybuf, &c->tmpfld, &c->owner, &c->totals,
-                    &c->binned, &c->dep_tab};
+                    &c->binned, &c->dep_tab, &c->gpart, &c->energy, &c->lf_pot};
   for (auto& B : c->lvb)
     for (DevBuf* b : {&B.count, &B.items, &B.accum, &B.key, &B.rank, &B.sref, &B.sorted})
       if (b->p) (void)hipFree(b->p);
@@ -980,17 +1062,141 @@ apm_status apm_solve(apm_ctx c, apm_dtype dt, const void* x, const void* y, cons
 }
 
 apm_status apm_solve_totals(apm_ctx c, apm_dtype dt, const void* m, int64_t npart,
-                            const void* ax, const void* ay, const void* az, const void* pot,
-                            double* out) {
+                            const void* const* gas, const void* ax, const void* ay,
+                            const void* az, const void* pot, double* out) {
   APM_TRY(check_ctx(c));
   APM_TRY(check_dtype(dt));
+  if (!out) return fail(APM_ERR_INVALID, "apm_solve_totals: NULL out");
   const int nl = (int)c->plan.levels.size();
-  if ((int)c->gmf[(int)dt].size() != nl || !c->owner.p ||
+  const int di = (int)dt;
+  if ((int)c->gmf[di].size() != nl || (int)c->fld[di].size() != nl || !c->owner.p ||
       c->owner.bytes < (size_t)std::max<int64_t>(npart, 1) * 4)
     return fail(APM_ERR_STATE, "apm_solve_totals: no apm_solve of this dtype/size yet");
   std::vector<const void*> g(nl);
-  for (int l = 0; l < nl; ++l) g[l] = c->gmf[(int)dt][l].p;
-  return apm_totals(c, dt, g.data(), m, (const int32_t*)c->owner.p, npart, ax, ay, az, pot, out);
+  for (int l = 0; l < nl; ++l) g[l] = c->gmf[di][l].p;
+  APM_TRY(apm_totals(c, dt, g.data(), m, (const int32_t*)c->owner.p, npart, ax, ay, az, pot, out));
+  out[nl + 4] = 0.0;
+  if (gas) {
+    double* d = (double*)c->totals.p;                // apm_totals sized it for nl + 4 + parts
+    HIP_TRY(launch_fill_f64(d, 1, 0.0, c->stream), "gas energy fill");
+    if (dt == APM_F32) {
+      std::vector<const V4<float>*> f(nl);
+      for (int l = 0; l < nl; ++l) f[l] = (const V4<float>*)c->fld[di][l].p;
+      APM_TRY(gas_energy_levels_t<float>(c, gas, f.data(), d));
+    } else {
+      std::vector<const V4<double>*> f(nl);
+      for (int l = 0; l < nl; ++l) f[l] = (const V4<double>*)c->fld[di][l].p;
+      APM_TRY(gas_energy_levels_t<double>(c, gas, f.data(), d));
+    }
+    double wg = 0.0;
+    HIP_TRY(hipMemcpyAsync(&wg, d, 8, hipMemcpyDeviceToHost, c->stream), "gas energy copy");
+    HIP_TRY(hipStreamSynchronize(c->stream), "gas energy sync");
+    out[nl + 4] = wg;
+    out[nl] += wg;
+  }
+  return APM_OK;
+}
+
+apm_status apm_gas_energy(apm_ctx c, apm_dtype dt, int32_t level, const void* gas,
+                          const void* field, double* out) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  APM_TRY(check_level(c, level));
+  if (!gas || !field || !out) return fail(APM_ERR_INVALID, "apm_gas_energy: NULL argument");
+  const int nl = (int)c->plan.levels.size();
+  APM_TRY(ensure(c, c->totals, (size_t)(nl + 4 + 4 * kMaxParts) * 8, "totals"));
+  double* d = (double*)c->totals.p;
+  HIP_TRY(launch_fill_f64(d, 1, 0.0, c->stream), "gas energy fill");
+  std::vector<const void*> g(nl, nullptr);
+  g[level] = gas;
+  if (dt == APM_F32) {
+    std::vector<const V4<float>*> f(nl, nullptr);
+    f[level] = (const V4<float>*)field;
+    APM_TRY(gas_energy_levels_t<float>(c, g.data(), f.data(), d));
+  } else {
+    std::vector<const V4<double>*> f(nl, nullptr);
+    f[level] = (const V4<double>*)field;
+    APM_TRY(gas_energy_levels_t<double>(c, g.data(), f.data(), d));
+  }
+  HIP_TRY(hipMemcpyAsync(out, d, 8, hipMemcpyDeviceToHost, c->stream), "gas energy copy");
+  HIP_TRY(hipStreamSynchronize(c->stream), "gas energy sync");
+  return APM_OK;
+}
+
+apm_status apm_kick(apm_ctx c, apm_dtype dt, int64_t npart, void* vx, void* vy, void* vz,
+                    const void* ax, const void* ay, const void* az, double h) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (npart < 0) return fail(APM_ERR_RANGE, "apm_kick: npart < 0");
+  if (npart > 0 && (!vx || !vy || !vz || !ax || !ay || !az))
+    return fail(APM_ERR_INVALID, "apm_kick: NULL array");
+  hipError_t e = dt == APM_F32
+      ? launch_kick_drift<float>(npart, nullptr, nullptr, nullptr, (float*)vx, (float*)vy,
+                                 (float*)vz, (const float*)ax, (const float*)ay, (const float*)az,
+                                 h, 0.0, c->stream)
+      : launch_kick_drift<double>(npart, nullptr, nullptr, nullptr, (double*)vx, (double*)vy,
+                                  (double*)vz, (const double*)ax, (const double*)ay,
+                                  (const double*)az, h, 0.0, c->stream);
+  HIP_TRY(e, "apm_kick");
+  return APM_OK;
+}
+
+apm_status apm_drift(apm_ctx c, apm_dtype dt, int64_t npart, void* x, void* y, void* z,
+                     const void* vx, const void* vy, const void* vz, double h) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (npart < 0) return fail(APM_ERR_RANGE, "apm_drift: npart < 0");
+  if (npart > 0 && (!x || !y || !z || !vx || !vy || !vz))
+    return fail(APM_ERR_INVALID, "apm_drift: NULL array");
+  hipError_t e = dt == APM_F32
+      ? launch_kick_drift<float>(npart, (float*)x, (float*)y, (float*)z, (float*)vx, (float*)vy,
+                                 (float*)vz, nullptr, nullptr, nullptr, 0.0, h, c->stream)
+      : launch_kick_drift<double>(npart, (double*)x, (double*)y, (double*)z, (double*)vx,
+                                  (double*)vy, (double*)vz, nullptr, nullptr, nullptr, 0.0, h,
+                                  c->stream);
+  HIP_TRY(e, "apm_drift");
+  return APM_OK;
+}
+
+apm_status apm_kinetic_energy(apm_ctx c, apm_dtype dt, const void* m, const void* vx,
+                              const void* vy, const void* vz, int64_t npart, double* out) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (!out) return fail(APM_ERR_INVALID, "apm_kinetic_energy: NULL out");
+  if (npart < 0) return fail(APM_ERR_RANGE, "apm_kinetic_energy: npart < 0");
+  if (npart > 0 && (!m || !vx || !vy || !vz))
+    return fail(APM_ERR_INVALID, "apm_kinetic_energy: NULL array");
+  const int nl = (int)c->plan.levels.size();
+  APM_TRY(ensure(c, c->totals, (size_t)(nl + 4 + 4 * kMaxParts) * 8, "totals"));
+  double* d = (double*)c->totals.p;
+  HIP_TRY(launch_fill_f64(d, 1, 0.0, c->stream), "kinetic fill");
+  hipError_t e = dt == APM_F32
+      ? launch_kinetic<float>((const float*)m, (const float*)vx, (const float*)vy,
+                              (const float*)vz, npart, d + nl + 4, d, c->stream)
+      : launch_kinetic<double>((const double*)m, (const double*)vx, (const double*)vy,
+                               (const double*)vz, npart, d + nl + 4, d, c->stream);
+  HIP_TRY(e, "kinetic energy");
+  HIP_TRY(hipMemcpyAsync(out, d, 8, hipMemcpyDeviceToHost, c->stream), "kinetic copy");
+  HIP_TRY(hipStreamSynchronize(c->stream), "kinetic sync");
+  return APM_OK;
+}
+
+apm_status apm_leapfrog(apm_ctx c, apm_dtype dt, void* x, void* y, void* z, void* vx, void* vy,
+                        void* vz, const void* m, int64_t npart, const void* const* gas, double h,
+                        int32_t nsteps, void* ax, void* ay, void* az, void* pot, double* energy) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (npart < 0 || npart > INT32_MAX) return fail(APM_ERR_RANGE, "apm_leapfrog: npart out of range");
+  if (nsteps < 0) return fail(APM_ERR_RANGE, "apm_leapfrog: nsteps < 0");
+  if (npart > 0 && (!x || !y || !z || !vx || !vy || !vz || !m || !ax || !ay || !az))
+    return fail(APM_ERR_INVALID, "apm_leapfrog: NULL array");
+  if (dt == APM_F32)
+    return leapfrog_t<float>(c, dt, (float*)x, (float*)y, (float*)z, (float*)vx, (float*)vy,
+                             (float*)vz, (const float*)m, npart, gas, h, nsteps, (float*)ax,
+                             (float*)ay, (float*)az, (float*)pot, energy);
+  return leapfrog_t<double>(c, dt, (double*)x, (double*)y, (double*)z, (double*)vx, (double*)vy,
+                            (double*)vz, (const double*)m, npart, gas, h, nsteps, (double*)ax,
+                            (double*)ay, (double*)az, (double*)pot, energy);
 }
 
 const void* apm_field_ptr(apm_ctx c, apm_dtype dt, int32_t level) {

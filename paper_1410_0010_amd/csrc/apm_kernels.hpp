@@ -149,6 +149,23 @@ template <typename T> hipError_t launch_particle_totals(const T* m, const int32_
                                                         int64_t npart, const T* ax, const T* ay,
                                                         const T* az, const T* pot, double* part,
                                                         double* out, hipStream_t s);
+// out[q] += scale * sum_{b < nparts} part[q * kMaxParts + b], q < nq (fixed order;
+// with nq = 1 any nparts)
+hipError_t launch_sum_parts(const double* part, int nparts, int nq, double scale, double* out,
+                            hipStream_t s);
+// time integration and energy terms (dynamics.hip)
+template <typename T> hipError_t launch_kick_drift(int64_t n, T* x, T* y, T* z, T* vx, T* vy,
+                                                   T* vz, const T* ax, const T* ay, const T* az,
+                                                   double hk, double hd, hipStream_t s);
+template <typename T> hipError_t launch_kinetic(const T* m, const T* vx, const T* vy, const T* vz,
+                                                int64_t n, double* part, double* out,
+                                                hipStream_t s);
+template <typename T> hipError_t launch_gas_energy(const GridDesc* grids, int32_t ngrids,
+                                                   int32_t first, int32_t count,
+                                                   const int64_t* begin, int64_t nblocks,
+                                                   double root_n, const T* gas,
+                                                   const V4<T>* field, double* part, double* out,
+                                                   hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, hipStream_t s);  // one value
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);

@@ -97,6 +97,12 @@ __global__ void __launch_bounds__(kBlock) k_sum_parts(const double* __restrict__
   }
 }
 
+hipError_t launch_sum_parts(const double* part, int nparts, int nq, double scale, double* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kBlock), 0, s, part, nparts, nq, scale, out);
+  return hipGetLastError();
+}
+
 static int nparts_for(int64_t n) {
   int64_t nb = (n + kBlock - 1) / kBlock;
   return (int)(nb > kMaxParts ? kMaxParts : (nb < 1 ? 1 : nb));

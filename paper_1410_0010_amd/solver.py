@@ -204,15 +204,58 @@ class Context:
                                    n, garr, _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot)), "apm_solve")
         return ax, ay, az, pot
 
-    def solve_totals(self, m, ax, ay, az, pot=None):
-        """FP64 totals of the last solve() (apm_solve_totals): mass per level, energy,
-        net force.  Synchronises the stream."""
+    def _gas_array(self, gas):
+        if gas is None:
+            return None
+        return (ctypes.c_void_p * self.plan.nlevels)(
+            *[None if g is None else g.data_ptr() for g in gas])
+
+    def solve_totals(self, m, ax, ay, az, pot=None, gas=None):
+        """FP64 totals of the last solve() (apm_solve_totals): mass per level, energy W
+        (particles + gas), net force, gas part of W.  Synchronises the stream."""
         nl = self.plan.nlevels
-        out = (ctypes.c_double * (nl + 4))()
+        out = (ctypes.c_double * (nl + 5))()
         check(_apm.lib().apm_solve_totals(self.handle, _dtype_code(m), _ptr(m), m.shape[0],
-                                          _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot), out),
-              "apm_solve_totals")
+                                          self._gas_array(gas), _ptr(ax), _ptr(ay), _ptr(az),
+                                          _ptr(pot), out), "apm_solve_totals")
         return np.array(out[:])
+
+    def gas_energy(self, level, gas, field):
+        out = ctypes.c_double()
+        check(_apm.lib().apm_gas_energy(self.handle, _dtype_code(gas), level, _ptr(gas),
+                                        _ptr(field), ctypes.byref(out)), "apm_gas_energy")
+        return out.value
+
+    def kick(self, vx, vy, vz, ax, ay, az, h):
+        check(_apm.lib().apm_kick(self.handle, _dtype_code(vx), vx.shape[0], _ptr(vx), _ptr(vy),
+                                  _ptr(vz), _ptr(ax), _ptr(ay), _ptr(az), h), "apm_kick")
+
+    def drift(self, x, y, z, vx, vy, vz, h):
+        check(_apm.lib().apm_drift(self.handle, _dtype_code(x), x.shape[0], _ptr(x), _ptr(y),
+                                   _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), h), "apm_drift")
+
+    def kinetic_energy(self, m, vx, vy, vz):
+        out = ctypes.c_double()
+        check(_apm.lib().apm_kinetic_energy(self.handle, _dtype_code(m), _ptr(m), _ptr(vx),
+                                            _ptr(vy), _ptr(vz), m.shape[0], ctypes.byref(out)),
+              "apm_kinetic_energy")
+        return out.value
+
+    def leapfrog(self, x, y, z, vx, vy, vz, m, h, nsteps, gas=None, ax=None, ay=None, az=None,
+                 pot=None, energy=True):
+        """nsteps KDK steps in place (apm_leapfrog); returns (ax, ay, az, pot, energies)
+        with energies an (nsteps + 1) array of K + W, or None."""
+        n = x.shape[0]
+        mk = lambda: self.torch.empty(n, dtype=x.dtype, device=self.device)
+        ax = mk() if ax is None else ax
+        ay = mk() if ay is None else ay
+        az = mk() if az is None else az
+        e = (ctypes.c_double * (nsteps + 1))() if energy else None
+        check(_apm.lib().apm_leapfrog(self.handle, _dtype_code(x), _ptr(x), _ptr(y), _ptr(z),
+                                      _ptr(vx), _ptr(vy), _ptr(vz), _ptr(m), n,
+                                      self._gas_array(gas), h, nsteps, _ptr(ax), _ptr(ay),
+                                      _ptr(az), _ptr(pot), e), "apm_leapfrog")
+        return ax, ay, az, pot, (np.array(e[:]) if energy else None)
 
     def set_graph(self, enable: bool):
         check(_apm.lib().apm_set_graph(self.handle, 1 if enable else 0), "apm_set_graph")

@@ -1,0 +1,165 @@
+"""GPU parity of the time integration and of the energy terms (through the C ABI)
+against the FP64 oracle: the gas part of the potential energy, apm_solve_totals,
+and kick-drift-kick leapfrog steps (positions, velocities, accelerations and the
+total energy after every step).  Tolerances as in the solve: relative L2 1e-12 in
+FP64 and 1e-5 in FP32, on FP32-rounded inputs for the FP32 runs."""
+
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import apm_workloads as W
+from oracle import apm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+P = pytest.importorskip("paper_1410_0010_amd")
+
+DEV = torch.device("cuda", 0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / (nb if nb > 0 else 1.0)
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype))).to(DEV)
+
+
+def rounded(w, dtype):
+    """The workload's arrays as the dtype sees them, in FP64 for the oracle."""
+    f = lambda a: None if a is None else np.asarray(a, dtype).astype(np.float64)
+    gas = [f(g) for g in w.gas]
+    return f(w.x), f(w.y), f(w.z), f(w.m), gas
+
+
+GAS_CASES = {
+    "root32_gas_4096": W.workload_root32_uniform_gas,
+    "gas_nested32": lambda: W.workload_plummer_gas(root_n=32, sub_n=16, nlevels=2, npart=5000),
+    "uniform_sphere_gas_only": W.workload_uniform_sphere,
+}
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(GAS_CASES))
+def test_gas_energy_and_solve_totals(case, dtype):
+    w = GAS_CASES[case]()
+    say(f"[dynamics] gas energy case={case} dtype={dtype.__name__}")
+    x64, y64, z64, m64, gas64 = rounded(w, dtype)
+    plan_o = O.OraclePlan(w.root_n, w.grids)
+    ref = O.solve(plan_o, x64, y64, z64, m64, gas64)
+    wgas_ref = O.gas_energy(plan_o, ref["field"], gas64)
+
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    x, y, z, m = (dev(a, dtype) for a in (w.x, w.y, w.z, w.m))
+    gas = [ctx.pack_gas(l, w.gas, x.dtype) for l in range(plan.nlevels)]
+    ax, ay, az, pot = ctx.solve(x, y, z, m, gas)
+    tot = ctx.solve_totals(m, ax, ay, az, pot, gas=gas)
+    nl = plan.nlevels
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    assert abs(tot[nl + 4] - wgas_ref) <= tol * abs(wgas_ref), (tot[nl + 4], wgas_ref)
+    assert abs(tot[nl] - ref["energy"]) <= tol * abs(ref["energy"]), (tot[nl], ref["energy"])
+    # the per-level entry point on the library's composed fields
+    staged = 0.0
+    for l in range(nl):
+        if gas[l] is not None:
+            staged += ctx.gas_energy(l, gas[l], ctx.solved_field(l, x.dtype))
+    assert abs(staged - wgas_ref) <= tol * abs(wgas_ref)
+
+
+def test_gas_energy_zero_without_gas():
+    w = W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=1, npart=2000)
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    x, y, z, m = (dev(a, np.float64) for a in (w.x, w.y, w.z, w.m))
+    ax, ay, az, pot = ctx.solve(x, y, z, m)
+    tot = ctx.solve_totals(m, ax, ay, az, pot)
+    assert tot[plan.nlevels + 4] == 0.0
+
+
+def dynamics_workload(npart=3000, with_gas=False):
+    """The large nested run's geometry at small size: root 32^3 and three centred 16^3
+    levels (finest half-width 0.03125, as in the 512^3 + 3 x 256^3 run), Plummer
+    b = 0.02 with equilibrium velocities and the two orbiting point masses."""
+    w = W.workload_large_nested(root_n=32, sub_n=16, nlevels=3, npart=npart, b=0.02)
+    if with_gas:
+        rng = np.random.default_rng(4242)
+        gas = [0.2 * W.gaussian_random_field_gas(rng, 32)]
+        for g in w.grids[1:]:
+            gas.append(W.inject_gas(gas[g.parent], w.grids[g.parent], g))
+        w = dataclasses.replace(w, gas=gas)
+    return w
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("with_gas", [False, True], ids=["nogas", "gas"])
+def test_leapfrog_matches_oracle(dtype, with_gas):
+    w = dynamics_workload(with_gas=with_gas)
+    nsteps, h = 6, 0.0515 / 400
+    say(f"[dynamics] leapfrog dtype={dtype.__name__} gas={with_gas} npart={w.npart} "
+        f"steps={nsteps}")
+    x64, y64, z64, m64, gas64 = rounded(w, dtype)
+    v64 = [np.asarray(v, dtype).astype(np.float64) for v in (w.vx, w.vy, w.vz)]
+    plan_o = O.OraclePlan(w.root_n, w.grids)
+    ref = O.leapfrog(plan_o, x64, y64, z64, *v64, m64, h, nsteps, gas=gas64)
+    last = O.solve(plan_o, ref["x"], ref["y"], ref["z"], m64, gas64)
+
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    x, y, z, m, vx, vy, vz = (dev(a, dtype) for a in (w.x, w.y, w.z, w.m, w.vx, w.vy, w.vz))
+    gas = [ctx.pack_gas(l, w.gas, x.dtype) for l in range(plan.nlevels)]
+    pot = torch.empty_like(x)
+    ax, ay, az, pot, energy = ctx.leapfrog(x, y, z, vx, vy, vz, m, h, nsteps, gas=gas, pot=pot)
+    torch.cuda.synchronize()
+    got = lambda t: t.cpu().numpy().astype(np.float64)
+    pos = np.stack([got(x), got(y), got(z)], 1)
+    vel = np.stack([got(vx), got(vy), got(vz)], 1)
+    pos_ref = np.stack([ref["x"], ref["y"], ref["z"]], 1)
+    vel_ref = np.stack([ref["vx"], ref["vy"], ref["vz"]], 1)
+    own = last["owner"] >= 0
+    acc = np.stack([got(ax), got(ay), got(az)], 1)
+    if dtype == np.float64:
+        tp, tv, ta, te = 1e-13, 1e-11, 1e-11, 1e-11
+    else:
+        tp, tv, ta, te = 1e-6, 1e-5, 2e-5, 1e-5
+    assert rel(pos, pos_ref) <= tp, rel(pos, pos_ref)
+    assert rel(vel, vel_ref) <= tv, rel(vel, vel_ref)
+    assert rel(acc[own], last["acc"][own]) <= ta, rel(acc[own], last["acc"][own])
+    assert rel(got(pot)[own], last["pot"][own]) <= ta
+    assert energy.shape == (nsteps + 1,)
+    assert rel(energy, ref["energy"]) <= te, (energy, ref["energy"])
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_kick_drift_kinetic(dtype):
+    rng = np.random.default_rng(7)
+    n = 10007
+    a = [rng.standard_normal(n) for _ in range(10)]
+    ctx = P.Context(P.Plan(16, [W.GridSpec(0, -1, (0, 0, 0), (16,) * 3)]), 0)
+    t = [dev(v, dtype) for v in a]
+    x, y, z, vx, vy, vz, ax, ay, az, m = t
+    ctx.kick(vx, vy, vz, ax, ay, az, 0.25)
+    ctx.drift(x, y, z, vx, vy, vz, 0.5)
+    r = [np.asarray(v, dtype).astype(np.float64) for v in a]
+    v_ref = [r[3 + i] + 0.25 * r[6 + i] for i in range(3)]
+    x_ref = [r[i] + 0.5 * v_ref[i] for i in range(3)]
+    tol = 1e-15 if dtype == np.float64 else 1e-6
+    for got_, ref_ in zip((vx, vy, vz, x, y, z), v_ref + x_ref):
+        assert rel(got_.cpu().numpy(), ref_) <= tol
+    k = ctx.kinetic_energy(m, vx, vy, vz)
+    vv = [v.cpu().numpy().astype(np.float64) for v in (vx, vy, vz)]
+    k_ref = 0.5 * np.sum(r[9] * (vv[0] ** 2 + vv[1] ** 2 + vv[2] ** 2))
+    assert abs(k - k_ref) <= 1e-12 * abs(k_ref)
