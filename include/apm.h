@@ -227,6 +227,31 @@ apm_status apm_solve_totals(apm_ctx ctx, apm_dtype dtype, const void* m, int64_t
 apm_status apm_gas_energy(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* gas,
                           const void* field, double* out);
 
+/* ------------------------------------------------------------- adjoint ------ */
+
+/* Reverse sweep of the last apm_solve on this context (same dtype, npart and x, y, z,
+ * m pointers, with unchanged contents; APM_ERR_STATE otherwise): the gradient of
+ *     L = wbar W + sum_p abar_p . a_p + sum_p phibar_p Phi_p
+ * (W as in apm_solve_totals, a and Phi the solve's outputs) with respect to the
+ * particle positions, masses and the gas.  Each forward step is transposed in
+ * reverse order: the TSC interpolation (its weights' derivatives give the position
+ * terms), the level composition (Sec. 2.2, trilinear prolongation), each grid's
+ * convolution (Eq. 2 with Fourier-space differencing; the transposed kernel has
+ * multipliers +i d_i Gf and Gp), the deposit (Sec. 2).  Owner grids are held fixed.
+ * The transposes are linear, so nothing of the forward spectra is kept: the reverse
+ * sweep reads the forward composed fields and tile-sorted particles that apm_solve
+ * leaves in the context.  Cotangents accumulate in FP64 for both dtypes.
+ * gas: as passed to apm_solve.  pot: the solve's potentials (needed if wbar != 0).
+ * abar_x/y/z, phibar: npart values each, or NULL for zero.
+ * xbar, ybar, zbar, mbar: npart outputs (any may be NULL).  gas_bar: NULL or host
+ * array of nlevels device pointers, a packed active-gas cotangent of a level for
+ * each level with gas (NULL entries skipped).  Asynchronous. */
+apm_status apm_solve_adjoint(apm_ctx ctx, apm_dtype dtype, const void* x, const void* y,
+                             const void* z, const void* m, int64_t npart, const void* const* gas,
+                             const void* pot, const void* abar_x, const void* abar_y,
+                             const void* abar_z, const void* phibar, double wbar, void* xbar,
+                             void* ybar, void* zbar, void* mbar, void* const* gas_bar);
+
 /* ------------------------------------------------------ time integration ---- */
 
 /* Leapfrog pieces (Sec. 2 time-centring; every level on one step, no subcycling,

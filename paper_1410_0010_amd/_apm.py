@@ -86,6 +86,9 @@ SIGNATURES = {
     "apm_solve_totals": (_st, [_vp, _st, _vp, _i64, ctypes.POINTER(_vp), _vp, _vp, _vp, _vp,
                                ctypes.POINTER(ctypes.c_double)]),
     "apm_gas_energy": (_st, [_vp, _st, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "apm_solve_adjoint": (_st, [_vp, _st, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_vp), _vp,
+                                _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp,
+                                ctypes.POINTER(_vp)]),
     "apm_kick": (_st, [_vp, _st, _i64, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double]),
     "apm_drift": (_st, [_vp, _st, _i64, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double]),
     "apm_kinetic_energy": (_st, [_vp, _st, _vp, _vp, _vp, _vp, _i64,

@@ -1,0 +1,465 @@
+// Reverse sweep of the solve, particle and field side (the transposes of Sec. 2
+// deposit and interpolation and of the Sec. 2.2 level composition).  For a loss
+// L = wbar W + sum_p abar_p . a_p + sum_p phibar_p Phi_p the cotangents flow:
+//
+//   particles --interp^T--> field boxes (FP64) --composition^T (finest first)-->
+//   own-field cotangents --convolution^T (fft_adj.hip)--> GMF cotangents
+//   --deposit^T--> level key boxes (FP64) --TSC gather--> particle gradients.
+//
+// All cotangent accumulation is FP64.  Particles are visited in the tile order the
+// forward deposit built (the sorted lists and work items stay valid until the next
+// solve), so neighbouring lanes touch neighbouring cells.
+#include "apm_kernels.hpp"
+
+namespace apm {
+
+template <typename T> __device__ __forceinline__ T tsc_w_a(int d, T t) {
+  const T h = (T)0.5;
+  if (d < 0) { const T u = h - t; return h * u * u; }
+  if (d > 0) { const T u = h + t; return h * u * u; }
+  return (T)0.75 - t * t;
+}
+// d/dt of tsc_w_a
+template <typename T> __device__ __forceinline__ T tsc_dw_a(int d, T t) {
+  if (d < 0) return t - (T)0.5;
+  if (d > 0) return (T)0.5 + t;
+  return (T)-2 * t;
+}
+
+__device__ __forceinline__ int batch_of(const int64_t* blk0, int nlev, int64_t blk) {
+  int b = 0;
+  while (b + 1 < nlev && blk0[b + 1] <= blk) ++b;
+  return b;
+}
+
+// ---- zero a list of FP64 ranges (blockIdx.y = range) ---------------------------------
+__global__ void __launch_bounds__(kBlock) k_zero_ranges(ZeroList zl) {
+  double* p = zl.p[blockIdx.y];
+  const int64_t n = zl.n[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    p[i] = 0.0;
+}
+
+hipError_t launch_zero_ranges(const ZeroList& zl, hipStream_t s) {
+  if (zl.count == 0) return hipSuccess;
+  int64_t mx = 0;
+  for (int i = 0; i < zl.count; ++i) mx = zl.n[i] > mx ? zl.n[i] : mx;
+  int64_t nb = (mx + 4 * kBlock - 1) / (4 * kBlock);
+  nb = nb < 1 ? 1 : (nb > 4096 ? 4096 : nb);
+  hipLaunchKernelGGL(k_zero_ranges, dim3((unsigned)nb, (unsigned)zl.count), dim3(kBlock), 0, s, zl);
+  return hipGetLastError();
+}
+
+// ---- interpolation transpose ---------------------------------------------------------
+// Work item = (level, tile, chunk) of the forward deposit.  Entries owned by a grid of
+// the level add w * (abar, phibar + wbar m / 2) to an LDS tile (halo-extended, FP64, 4
+// components) when their owner is the chunk's first owner grid g*, else straight to
+// the field cotangent in HBM; the tile is then added to g*'s field box.  Each owned
+// entry also adds its position gradient  sum_f grad w(f) . <F(f), cot>  (F the forward
+// composed field) to the particle's FP64 accumulators (one writer per particle).
+constexpr int kTH3 = 10 * 10 * 10;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __restrict__ grids) {
+  __shared__ double acc[4 * kTH3];
+  __shared__ int gstar;
+  const int lb = batch_of(io.item_blk0, io.nlev, blockIdx.x);
+  const DepLevel& L = tab[lb];
+  const int32_t total = L.items[L.ntiles];
+  const int64_t item = blockIdx.x - io.item_blk0[lb];
+  if (item >= total) return;                        // uniform for the block
+  int lo = 0, hi = L.ntiles - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (L.items[mid] <= item) lo = mid; else hi = mid - 1;
+  }
+  const int tile = lo;
+  const int64_t begin = L.count[(int64_t)tile * L.rep] + (item - L.items[tile]) * (int64_t)kChunk;
+  const int64_t end = min((int64_t)L.count[(int64_t)(tile + 1) * L.rep], begin + kChunk);
+  for (int c = threadIdx.x; c < 4 * kTH3; c += kBlock) acc[c] = 0.0;
+  if (threadIdx.x == 0) gstar = INT32_MAX;
+  __syncthreads();
+  const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
+            oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;
+  static_assert(kChunk == 8 * kBlock, "a chunk is eight records per thread");
+  int2 ref[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int64_t q = begin + threadIdx.x + (int64_t)k * kBlock;
+    ref[k] = q < end ? load_i2(L.sref, q) : make_int2(0, -1);
+    if (ref[k].y >= 0) atomicMin(&gstar, ref[k].y);
+  }
+  __syncthreads();
+  const int gs = gstar;
+  const V4<T>* F = io.fld[lb];
+  double* fbar = io.fbar[lb];
+#pragma unroll 1
+  for (int k = 0; k < 8; ++k) {
+    if (ref[k].y < 0) continue;
+    const int64_t q = begin + threadIdx.x + (int64_t)k * kBlock;
+    const int64_t i = ref[k].x;
+    const V4<T> v = load_v4<T>(L.sorted, q);
+    const double cot[4] = {io.abx ? (double)io.abx[i] : 0.0, io.aby ? (double)io.aby[i] : 0.0,
+                           io.abz ? (double)io.abz[i] : 0.0,
+                           (io.phib ? (double)io.phib[i] : 0.0) + io.wbar * 0.5 * (double)v.w};
+    const GridDesc& g = grids[ref[k].y];
+    const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
+    const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
+    const int cx = (int)fx - g.fld_lo[0], cy = (int)fy - g.fld_lo[1], cz = (int)fz - g.fld_lo[2];
+    const int nx = g.fld_n[0], ny = g.fld_n[1], nz = g.fld_n[2];
+    const bool local = ref[k].y == gs;
+    // cell relative to the tile origin (always inside the tile; clamped defensively)
+    const int ix = min(max((int)fx - L.key_lo[0] - ox, 0), kTile - 1),
+              iy = min(max((int)fy - L.key_lo[1] - oy, 0), kTile - 1),
+              iz = min(max((int)fz - L.key_lo[2] - oz, 0), kTile - 1);
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int zz = cz + dz;
+      const double wz = tsc_w_a(dz, tz), dwz = tsc_dw_a(dz, tz);
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = cy + dy;
+        const double wy = tsc_w_a(dy, ty), dwy = tsc_dw_a(dy, ty);
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int xx = cx + dx;
+          if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
+          const double wx = tsc_w_a(dx, tx), dwx = tsc_dw_a(dx, tx);
+          const int64_t cell = g.fld_offset + ((int64_t)zz * ny + yy) * nx + xx;
+          const V4<T> f = F[cell];
+          const double s = cot[0] * f.x + cot[1] * f.y + cot[2] * f.z + cot[3] * f.w;
+          gx += dwx * wy * wz * s;
+          gy += wx * dwy * wz * s;
+          gz += wx * wy * dwz * s;
+          const double w = wx * wy * wz;
+          if (local) {
+            double* a = acc + 4 * (((iz + dz + 1) * 10 + (iy + dy + 1)) * 10 + (ix + dx + 1));
+            atomicAdd(a + 0, w * cot[0]);
+            atomicAdd(a + 1, w * cot[1]);
+            atomicAdd(a + 2, w * cot[2]);
+            atomicAdd(a + 3, w * cot[3]);
+          } else {
+            double* a = fbar + 4 * cell;
+            atomicAdd(a + 0, w * cot[0]);
+            atomicAdd(a + 1, w * cot[1]);
+            atomicAdd(a + 2, w * cot[2]);
+            atomicAdd(a + 3, w * cot[3]);
+          }
+        }
+      }
+    }
+    const double inv = 1.0 / g.dx;
+    io.pacc[1][i] += gx * inv;
+    io.pacc[2][i] += gy * inv;
+    io.pacc[3][i] += gz * inv;
+  }
+  __syncthreads();
+  if (gs == INT32_MAX) return;                      // no owned entry in this chunk
+  const GridDesc& g = grids[gs];
+  for (int c = threadIdx.x; c < kTH3; c += kBlock) {
+    const double* a = acc + 4 * c;
+    if (a[0] == 0.0 && a[1] == 0.0 && a[2] == 0.0 && a[3] == 0.0) continue;
+    const int lx = c % 10, ly = (c / 10) % 10, lz = c / 100;
+    const int xx = L.key_lo[0] + ox + lx - 1 - g.fld_lo[0];
+    const int yy = L.key_lo[1] + oy + ly - 1 - g.fld_lo[1];
+    const int zz = L.key_lo[2] + oz + lz - 1 - g.fld_lo[2];
+    if (xx < 0 || xx >= g.fld_n[0] || yy < 0 || yy >= g.fld_n[1] || zz < 0 || zz >= g.fld_n[2])
+      continue;                                     // cannot hold weight (owned stencils lie inside)
+    double* f = fbar + 4 * (g.fld_offset + ((int64_t)zz * g.fld_n[1] + yy) * g.fld_n[0] + xx);
+    atomicAdd(f + 0, a[0]);
+    atomicAdd(f + 1, a[1]);
+    atomicAdd(f + 2, a[2]);
+    atomicAdd(f + 3, a[3]);
+  }
+}
+
+template <typename T>
+hipError_t launch_adj_interp(const AdjIO<T>& io, const DepLevel* tab, const GridDesc* grids,
+                             hipStream_t s) {
+  const int64_t nb = io.item_blk0[io.nlev];
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_adj_interp<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab, grids);
+  return hipGetLastError();
+}
+
+// ---- gas-energy seeds: owned active gas cells of one level ---------------------------
+// fbar.w += wbar rho dx^3 / 2 and gas_bar += wbar Phi dx^3 / 2 (the two factors of the
+// gas term of W).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adj_gas_seed(const GridDesc* __restrict__ grids, int32_t ngrids, int32_t first, int32_t count,
+               const int64_t* __restrict__ begin, double root_n, const T* __restrict__ gas,
+               const V4<T>* __restrict__ field, double wbar, double* __restrict__ fbar,
+               double* __restrict__ gas_bar) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const GridDesc& g = grids[first + lo];
+  const int64_t cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  const int64_t local = (b - begin[lo]) * (int64_t)kBlock + threadIdx.x;
+  if (local >= cells) return;
+  const int lx = (int)(local % g.n[0]);
+  const int ly = (int)((local / g.n[0]) % g.n[1]);
+  const int lz = (int)(local / ((int64_t)g.n[0] * g.n[1]));
+  const double px = (g.lo[0] + lx + 0.5) * g.dx, py = (g.lo[1] + ly + 0.5) * g.dx,
+               pz = (g.lo[2] + lz + 0.5) * g.dx;
+  int best = -1, bestlev = -1;
+  for (int gi = ngrids - 1; gi >= 0; --gi) {
+    const GridDesc& h = grids[gi];
+    if (h.level < bestlev) break;
+    const double inv = root_n * (double)(1 << h.level);
+    const int cx = (int)floor(px * inv), cy = (int)floor(py * inv), cz = (int)floor(pz * inv);
+    if (cx >= h.lo[0] && cx < h.lo[0] + h.n[0] && cy >= h.lo[1] && cy < h.lo[1] + h.n[1] &&
+        cz >= h.lo[2] && cz < h.lo[2] + h.n[2]) {
+      best = gi;
+      bestlev = h.level;
+    }
+  }
+  if (best != first + lo) return;
+  const int64_t fc = g.fld_offset + ((int64_t)(g.lo[2] + lz - g.fld_lo[2]) * g.fld_n[1] +
+                                     (g.lo[1] + ly - g.fld_lo[1])) * g.fld_n[0] +
+                     (g.lo[0] + lx - g.fld_lo[0]);
+  const double v = g.dx * g.dx * g.dx * 0.5 * wbar;
+  fbar[4 * fc + 3] += v * (double)gas[g.gas_offset + local];
+  gas_bar[g.gas_offset + local] += v * (double)field[fc].w;
+}
+
+template <typename T>
+hipError_t launch_adj_gas_seed(const GridDesc* grids, int32_t ngrids, int32_t first, int32_t count,
+                               const int64_t* begin, int64_t nblocks, double root_n, const T* gas,
+                               const V4<T>* field, double wbar, double* fbar, double* gas_bar,
+                               hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_adj_gas_seed<T>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, grids,
+                     ngrids, first, count, begin, root_n, gas, field, wbar, fbar, gas_bar);
+  return hipGetLastError();
+}
+
+// ---- composition transpose: one child level into its parents -------------------------
+// Thread = parent field cell q in the footprint of one child grid; it gathers the child
+// cells 2q-1, 2q, 2q+1, 2q+2 per axis (weights 1/4, 3/4, 3/4, 1/4: the trilinear
+// prolongation between cell centres, transposed) and adds the sum to the parent.
+__global__ void __launch_bounds__(kBlock)
+k_adj_restrict(const GridDesc* __restrict__ grids, int32_t first, int32_t count,
+               const int64_t* __restrict__ begin, const double* __restrict__ child_bar,
+               double* __restrict__ parent_bar) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const GridDesc& g = grids[first + lo];
+  int flo[3], fn[3];
+  int64_t cells = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int l0 = (g.fld_lo[a] >> 1) - 1, h0 = ((g.fld_lo[a] + g.fld_n[a] - 1) >> 1) + 1;
+    flo[a] = max(l0, g.parent_fld_lo[a]);
+    fn[a] = min(h0, g.parent_fld_lo[a] + g.parent_fld_n[a] - 1) - flo[a] + 1;
+    cells *= fn[a] > 0 ? fn[a] : 0;
+  }
+  const int64_t local = (b - begin[lo]) * (int64_t)kBlock + threadIdx.x;
+  if (local >= cells) return;
+  const int q[3] = {flo[0] + (int)(local % fn[0]), flo[1] + (int)((local / fn[0]) % fn[1]),
+                    flo[2] + (int)(local / ((int64_t)fn[0] * fn[1]))};
+  const double wts[4] = {0.25, 0.75, 0.75, 0.25};
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int kz = 0; kz < 4; ++kz) {
+    const int cz = 2 * q[2] - 1 + kz - g.fld_lo[2];
+    if (cz < 0 || cz >= g.fld_n[2]) continue;
+    for (int ky = 0; ky < 4; ++ky) {
+      const int cy = 2 * q[1] - 1 + ky - g.fld_lo[1];
+      if (cy < 0 || cy >= g.fld_n[1]) continue;
+      for (int kx = 0; kx < 4; ++kx) {
+        const int cx = 2 * q[0] - 1 + kx - g.fld_lo[0];
+        if (cx < 0 || cx >= g.fld_n[0]) continue;
+        const double w = wts[kz] * wts[ky] * wts[kx];
+        const double* a = child_bar + 4 * (g.fld_offset + ((int64_t)cz * g.fld_n[1] + cy) * g.fld_n[0] + cx);
+        s0 += w * a[0]; s1 += w * a[1]; s2 += w * a[2]; s3 += w * a[3];
+      }
+    }
+  }
+  if (s0 == 0.0 && s1 == 0.0 && s2 == 0.0 && s3 == 0.0) return;
+  double* p = parent_bar + 4 * (g.parent_fld_offset +
+                                ((int64_t)(q[2] - g.parent_fld_lo[2]) * g.parent_fld_n[1] +
+                                 (q[1] - g.parent_fld_lo[1])) * g.parent_fld_n[0] +
+                                (q[0] - g.parent_fld_lo[0]));
+  atomicAdd(p + 0, s0);
+  atomicAdd(p + 1, s1);
+  atomicAdd(p + 2, s2);
+  atomicAdd(p + 3, s3);
+}
+
+hipError_t launch_adj_restrict(const GridDesc* grids, int32_t first, int32_t count,
+                               const int64_t* begin, int64_t nblocks, const double* child_bar,
+                               double* parent_bar, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_restrict, dim3((unsigned)nblocks), dim3(kBlock), 0, s, grids, first,
+                     count, begin, child_bar, parent_bar);
+  return hipGetLastError();
+}
+
+// ---- deposit transpose, grid side ------------------------------------------------------
+// Thread = GMF cell of a grid: the level's FP64 key-box cotangent += gmf_bar / dx^3;
+// own gas (active cells) += gmf_bar; the parent's gas += gmf_bar on ghost cells.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adj_deposit_grid(AdjIO<T> io, const DepLevel* __restrict__ tab) {
+  const int lb = batch_of(io.fin_blk0, io.nlev, blockIdx.x);
+  const DepLevel& L = tab[lb];
+  const int64_t blk = blockIdx.x - io.fin_blk0[lb];
+  int lo = 0, hi = L.ngrids - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (L.block_begin[mid] <= blk) lo = mid; else hi = mid - 1;
+  }
+  const GridDesc& g = L.grids[lo];
+  const int64_t cells = (int64_t)g.gmf_n[0] * g.gmf_n[1] * g.gmf_n[2];
+  const int64_t local = (blk - L.block_begin[lo]) * (int64_t)kBlock + threadIdx.x;
+  if (local >= cells) return;
+  const double gb = (double)io.gmf_bar[lb][g.gmf_offset + local];
+  if (gb == 0.0) return;
+  const int lx = (int)(local % g.gmf_n[0]);
+  const int ly = (int)((local / g.gmf_n[0]) % g.gmf_n[1]);
+  const int lz = (int)(local / ((int64_t)g.gmf_n[0] * g.gmf_n[1]));
+  const int cx = g.gmf_lo[0] + lx, cy = g.gmf_lo[1] + ly, cz = g.gmf_lo[2] + lz;
+  atomicAdd(L.accum + ((int64_t)(cz - L.key_lo[2]) * L.key_n[1] + (cy - L.key_lo[1])) * L.key_n[0] +
+                (cx - L.key_lo[0]),
+            gb / (L.dx * L.dx * L.dx));
+  const bool active = cx >= g.lo[0] && cx < g.lo[0] + g.n[0] && cy >= g.lo[1] &&
+                      cy < g.lo[1] + g.n[1] && cz >= g.lo[2] && cz < g.lo[2] + g.n[2];
+  if (active) {
+    // atomic: a finer level of the same launch adds its ghost cells to this array
+    double* gbar = io.gas_bar[lb];
+    if (gbar)
+      atomicAdd(gbar + g.gas_offset + ((int64_t)(cz - g.lo[2]) * g.n[1] + (cy - g.lo[1])) * g.n[0] +
+                    (cx - g.lo[0]),
+                gb);
+  } else if (g.parent >= 0) {
+    double* pbar = io.pgas_bar[lb];
+    if (pbar) {
+      const int px = (cx >> 1) - g.parent_lo[0], py = (cy >> 1) - g.parent_lo[1],
+                pz = (cz >> 1) - g.parent_lo[2];
+      atomicAdd(pbar + g.parent_gas_offset + ((int64_t)pz * g.parent_n[1] + py) * g.parent_n[0] + px,
+                gb);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_adj_deposit_grid(const AdjIO<T>& io, const DepLevel* tab, hipStream_t s) {
+  const int64_t nb = io.fin_blk0[io.nlev];
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_adj_deposit_grid<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab);
+  return hipGetLastError();
+}
+
+// ---- deposit transpose, particle side --------------------------------------------------
+// Entry q of a level's sorted list: mbar += sum_c w(c) A(c), xbar += m sum_c grad w(c)
+// A(c), A the level's key-box cotangent.  Entries of different levels share particles:
+// FP64 atomics into the accumulators.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
+  const int lb = batch_of(io.part_blk0, io.nlev, blockIdx.x);
+  const DepLevel& L = tab[lb];
+  const int64_t q = (blockIdx.x - io.part_blk0[lb]) * (int64_t)kBlock + threadIdx.x;
+  if (q >= *L.binned) return;
+  const int2 r = load_i2(L.sref, q);
+  const V4<T> v = load_v4<T>(L.sorted, q);
+  const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
+  const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
+  const int cx = (int)fx - L.key_lo[0], cy = (int)fy - L.key_lo[1], cz = (int)fz - L.key_lo[2];
+  const int nx = L.key_n[0], ny = L.key_n[1], nz = L.key_n[2];
+  double sm = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int zz = cz + dz;
+    const double wz = tsc_w_a(dz, tz), dwz = tsc_dw_a(dz, tz);
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = cy + dy;
+      const double wy = tsc_w_a(dy, ty), dwy = tsc_dw_a(dy, ty);
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xx = cx + dx;
+        if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
+        const double wx = tsc_w_a(dx, tx), dwx = tsc_dw_a(dx, tx);
+        const double a = L.accum[((int64_t)zz * ny + yy) * nx + xx];
+        sm += wx * wy * wz * a;
+        gx += dwx * wy * wz * a;
+        gy += wx * dwy * wz * a;
+        gz += wx * wy * dwz * a;
+      }
+    }
+  }
+  const double m = (double)v.w * L.inv_dx;
+  atomicAdd(io.pacc[0] + r.x, sm);
+  atomicAdd(io.pacc[1] + r.x, m * gx);
+  atomicAdd(io.pacc[2] + r.x, m * gy);
+  atomicAdd(io.pacc[3] + r.x, m * gz);
+}
+
+template <typename T>
+hipError_t launch_adj_deposit_particles(const AdjIO<T>& io, const DepLevel* tab, hipStream_t s) {
+  const int64_t nb = io.part_blk0[io.nlev];
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_adj_deposit_particles<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab);
+  return hipGetLastError();
+}
+
+// ---- outputs -----------------------------------------------------------------------------
+// xbar = accumulated; mbar = accumulated + wbar Phi_p / 2 on owned particles.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adj_finish(AdjIO<T> io, const int32_t* __restrict__ owner, const T* __restrict__ pot,
+             T* __restrict__ xb, T* __restrict__ yb, T* __restrict__ zb, T* __restrict__ mb) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= io.npart) return;
+  double mm = io.pacc[0][i];
+  if (io.wbar != 0.0 && owner[i] >= 0 && pot) mm += io.wbar * 0.5 * (double)pot[i];
+  if (mb) mb[i] = (T)mm;
+  if (xb) xb[i] = (T)io.pacc[1][i];
+  if (yb) yb[i] = (T)io.pacc[2][i];
+  if (zb) zb[i] = (T)io.pacc[3][i];
+}
+
+template <typename T>
+hipError_t launch_adj_finish(const AdjIO<T>& io, const int32_t* owner, const T* pot, T* xb, T* yb,
+                             T* zb, T* mb, hipStream_t s) {
+  if (io.npart == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_adj_finish<T>), dim3((unsigned)((io.npart + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, io, owner, pot, xb, yb, zb, mb);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_to_t(const double* __restrict__ a, T* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i] = (T)a[i];
+}
+
+template <typename T>
+hipError_t launch_to_t(const double* a, T* b, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_to_t<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     a, b, n);
+  return hipGetLastError();
+}
+
+#define APM_INST_A(T)                                                                         \
+  template hipError_t launch_adj_interp<T>(const AdjIO<T>&, const DepLevel*, const GridDesc*,   \
+                                           hipStream_t);                                       \
+  template hipError_t launch_adj_gas_seed<T>(const GridDesc*, int32_t, int32_t, int32_t,       \
+                                             const int64_t*, int64_t, double, const T*,        \
+                                             const V4<T>*, double, double*, double*,           \
+                                             hipStream_t);                                     \
+  template hipError_t launch_adj_deposit_grid<T>(const AdjIO<T>&, const DepLevel*, hipStream_t); \
+  template hipError_t launch_adj_deposit_particles<T>(const AdjIO<T>&, const DepLevel*,        \
+                                                      hipStream_t);                            \
+  template hipError_t launch_adj_finish<T>(const AdjIO<T>&, const int32_t*, const T*, T*, T*,   \
+                                           T*, T*, hipStream_t);                                \
+  template hipError_t launch_to_t<T>(const double*, T*, int64_t, hipStream_t);
+APM_INST_A(float)
+APM_INST_A(double)
+
+}  // namespace apm

@@ -33,6 +33,13 @@ struct apm_ctx_s {
   GridDesc* d_grids = nullptr;
   std::vector<int64_t*> d_dep_begin, d_cmp_begin, d_act_begin;     // per level: first block
   std::vector<int64_t> dep_blocks, cmp_blocks, act_blocks;         // of each grid, and total
+  std::vector<int64_t*> d_foot_begin;                              // restriction footprints
+  std::vector<int64_t> foot_blocks;
+  // reverse sweep: FP64 field and gas cotangents per level, GMF cotangents by dtype,
+  // FP64 per-particle accumulators; the forward state it needs is the last apm_solve's
+  std::vector<DevBuf> adj_fbar, adj_gas, adj_gmf[3];
+  DevBuf adj_pacc;
+  std::vector<uintptr_t> last_solve;                               // (dtype, n, x, y, z, m)
   std::map<std::pair<int, int>, void*> tw;                        // (dtype, L)
   std::map<std::tuple<int, int, int>, void*> dsym;                // (dtype, level, M)
   std::map<std::tuple<int, int, int, int, int>, void*> kern;      // (dtype, level, Mx, My, Mz)
@@ -312,15 +319,21 @@ apm_status kernel_table(apm_ctx c, apm_dtype dt, const GridDesc& g, const void**
   return APM_OK;
 }
 
-int pass_axis(int pass) { return pass == PASS_Y_FWD || pass == PASS_Y_INV ? 1 : (pass == PASS_Z_CONV ? 2 : 0); }
+int pass_axis(int pass) {
+  const int p = mirror_pass(pass);
+  return p == PASS_Y_FWD || p == PASS_Y_INV ? 1 : (p == PASS_Z_CONV ? 2 : 0);
+}
 const char* pass_name(int pass) {
-  static const char* n[] = {"fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv"};
+  static const char* n[] = {"fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
+                            "adj_fft_x",  "adj_fft_y",  "adj_fft_z",  "adj_fft_y_inv",
+                            "adj_fft_x_inv"};
   return n[pass];
 }
 
 template <typename T>
 int lines_for(apm_ctx c, int pass, int L) {
-  auto it = c->lines.find(std::make_tuple((int)sizeof(T), pass, L));
+  // an adjoint pass has the shape of the forward pass it reverses: its tuned value
+  auto it = c->lines.find(std::make_tuple((int)sizeof(T), mirror_pass(pass), L));
   return it != c->lines.end() ? it->second : default_lines<T>(pass, L);
 }
 
@@ -640,8 +653,25 @@ void drop_graph(apm_ctx c) {
 // the previous call is captured once (on an internal stream, since the caller's
 // may be the legacy default stream) and replayed on the caller's stream after.
 template <typename T>
+apm_status solve_graph_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, const T* m,
+                         int64_t npart, const void* const* gas, T* ax, T* ay, T* az, T* pot);
+
+// The forward solve; records which inputs the library-owned state (sorted particles,
+// owners, fields) belongs to, for the reverse sweep.
+template <typename T>
 apm_status solve_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, const T* m,
                    int64_t npart, const void* const* gas, T* ax, T* ay, T* az, T* pot) {
+  c->last_solve.clear();
+  apm_status st = solve_graph_t<T>(c, dt, x, y, z, m, npart, gas, ax, ay, az, pot);
+  if (st == APM_OK)
+    c->last_solve = {(uintptr_t)dt, (uintptr_t)npart, (uintptr_t)x, (uintptr_t)y, (uintptr_t)z,
+                     (uintptr_t)m};
+  return st;
+}
+
+template <typename T>
+apm_status solve_graph_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, const T* m,
+                         int64_t npart, const void* const* gas, T* ax, T* ay, T* az, T* pot) {
   if (!c->use_graph || c->prof_on)
     return solve_body_t<T>(c, dt, x, y, z, m, npart, gas, ax, ay, az, pot);
   std::vector<uintptr_t> key = {(uintptr_t)dt, (uintptr_t)npart, (uintptr_t)x, (uintptr_t)y,
@@ -829,6 +859,141 @@ apm_status leapfrog_t(apm_ctx c, apm_dtype dt, T* x, T* y, T* z, T* vx, T* vy, T
   return APM_OK;
 }
 
+// Reverse sweep of the last apm_solve of this dtype (see include/apm.h).
+template <typename T>
+apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, const T* m,
+                     int64_t n, const void* const* gas, const T* pot, const T* abx, const T* aby,
+                     const T* abz, const T* phib, double wbar, T* xb, T* yb, T* zb, T* mb,
+                     void* const* gas_bar) {
+  const Plan& P = c->plan;
+  const int nl = (int)P.levels.size();
+  const int di = (int)dt;
+  const std::vector<uintptr_t> key = {(uintptr_t)dt, (uintptr_t)n, (uintptr_t)x, (uintptr_t)y,
+                                      (uintptr_t)z, (uintptr_t)m};
+  if (c->last_solve != key || (int)c->fld[di].size() != nl || (int)c->lvb.size() != nl)
+    return fail(APM_ERR_STATE, "apm_solve_adjoint: needs the apm_solve of the same particles "
+                               "and dtype as the last solve on this context");
+  c->adj_fbar.resize(nl);
+  c->adj_gas.resize(nl);
+  c->adj_gmf[di].resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    APM_TRY(ensure(c, c->adj_fbar[l], (size_t)P.levels[l].fld_cells * 32, "field cotangents"));
+    APM_TRY(ensure(c, c->adj_gmf[di][l], (size_t)P.levels[l].gmf_elems * sizeof(T), "gmf cotangents"));
+    if (gas && gas[l])
+      APM_TRY(ensure(c, c->adj_gas[l], (size_t)std::max<int64_t>(P.levels[l].gas_elems, 1) * 8,
+                     "gas cotangents"));
+  }
+  APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * 32, "particle cotangents"));
+  ZeroList zl{};
+  hipError_t zerr = hipSuccess;
+  auto add = [&](void* p, int64_t cnt) {            // cleared in batches of up to 48 ranges
+    if (zl.count == 48) {
+      if (zerr == hipSuccess) zerr = launch_zero_ranges(zl, c->stream);
+      zl.count = 0;
+    }
+    zl.p[zl.count] = (double*)p;
+    zl.n[zl.count] = cnt;
+    zl.count++;
+  };
+  AdjIO<T> io{};
+  io.nlev = nl;
+  io.npart = n;
+  io.wbar = wbar;
+  io.abx = abx; io.aby = aby; io.abz = abz; io.phib = phib;
+  double* pacc = (double*)c->adj_pacc.p;
+  for (int k = 0; k < 4; ++k) io.pacc[k] = pacc + (int64_t)k * n;
+  add(pacc, 4 * n);
+  int64_t iblk = 0, fblk = 0, pblk = 0;
+  const int64_t nbp = (n + kBlock - 1) / kBlock;
+  for (int l = 0; l < nl; ++l) {
+    const DepLevel& d = c->dep_host[l];
+    io.item_blk0[l] = iblk;
+    iblk += (int64_t)d.ntiles + (n + kChunk - 1) / kChunk;
+    io.fin_blk0[l] = fblk;
+    fblk += c->dep_blocks[l];
+    io.part_blk0[l] = pblk;
+    pblk += nbp;
+    io.fld[l] = (const V4<T>*)c->fld[di][l].p;
+    io.fbar[l] = (double*)c->adj_fbar[l].p;
+    io.gmf_bar[l] = (const T*)c->adj_gmf[di][l].p;
+    io.gas_bar[l] = (gas && gas[l]) ? (double*)c->adj_gas[l].p : nullptr;
+    io.pgas_bar[l] = (l > 0 && gas && gas[l - 1]) ? (double*)c->adj_gas[l - 1].p : nullptr;
+    add(io.fbar[l], P.levels[l].fld_cells * 4);
+    add(c->lvb[l].accum.p, P.levels[l].key_cells);
+    if (io.gas_bar[l]) add(io.gas_bar[l], P.levels[l].gas_elems);
+  }
+  io.item_blk0[nl] = iblk;
+  io.fin_blk0[nl] = fblk;
+  io.part_blk0[nl] = pblk;
+  const DepLevel* tab = (const DepLevel*)c->dep_tab.p;
+  HIP_TRY(zerr, "adjoint clear");
+  HIP_TRY(timed(c, "adj_clear", [&] { return launch_zero_ranges(zl, c->stream); }), "adjoint clear");
+  HIP_TRY(timed(c, "adj_interp", [&] { return launch_adj_interp<T>(io, tab, c->d_grids, c->stream); }),
+          "interpolation transpose");
+  if (wbar != 0.0 && gas) {
+    for (int l = 0; l < nl; ++l) {
+      if (!gas[l]) continue;
+      const LevelDesc& L = P.levels[l];
+      HIP_TRY(timed(c, "adj_gas_seed", [&] {
+                return launch_adj_gas_seed<T>(c->d_grids, (int32_t)P.grids.size(), L.first, L.count,
+                                              c->d_act_begin[l], c->act_blocks[l],
+                                              (double)P.cfg.root_n, (const T*)gas[l], io.fld[l],
+                                              wbar, io.fbar[l], io.gas_bar[l], c->stream);
+              }), "gas energy seeds");
+    }
+  }
+  for (int l = nl - 1; l >= 1; --l) {
+    const LevelDesc& L = P.levels[l];
+    HIP_TRY(timed(c, "adj_restrict", [&] {
+              return launch_adj_restrict(c->d_grids, L.first, L.count, c->d_foot_begin[l],
+                                         c->foot_blocks[l], io.fbar[l], io.fbar[l - 1], c->stream);
+            }), "composition transpose");
+  }
+  // transposed convolution of every grid of every level
+  const std::vector<int> set = grid_set(c, -1);
+  APM_TRY(prepare_tables<T>(c, set));
+  APM_TRY(ensure(c, c->spec, c->spec_elems * sizeof(C2<T>), "spectrum buffer"));
+  APM_TRY(ensure(c, c->zbuf, c->z_elems * sizeof(C2<T>), "z-pass output buffer"));
+  APM_TRY(ensure(c, c->ybuf, c->y_elems * sizeof(C2<T>), "y-pass output buffer"));
+  AdjPtrs<T> ap{};
+  for (int l = 0; l < nl; ++l) {
+    ap.gmf[l] = (T*)c->adj_gmf[di][l].p;
+    ap.fbar[l] = io.fbar[l];
+  }
+  for (int pass = PASS_AX; pass <= PASS_AXI; ++pass) {
+    for (int L : pass_lengths(c, pass, -1)) {
+      const int nlines = lines_for<T>(c, pass, L);
+      const apm_ctx_s::JobList* jl = nullptr;
+      APM_TRY(job_list<T>(c, pass, L, -1, nlines, &jl));
+      const void* tw = nullptr;
+      APM_TRY(twiddles<T>(c, L, &tw));
+      HIP_TRY(timed(c, pass_name(pass), [&] {
+                return launch_adj_pass<T>(pass, L, nlines, jl->d, jl->n, jl->blocks, ap,
+                                          (C2<T>*)c->spec.p, (C2<T>*)c->zbuf.p, (C2<T>*)c->ybuf.p,
+                                          tw, c->stream);
+              }), pass_name(pass));
+    }
+  }
+  HIP_TRY(timed(c, "adj_deposit_grid", [&] { return launch_adj_deposit_grid<T>(io, tab, c->stream); }),
+          "deposit transpose (grids)");
+  HIP_TRY(timed(c, "adj_deposit_particles", [&] {
+            return launch_adj_deposit_particles<T>(io, tab, c->stream);
+          }), "deposit transpose (particles)");
+  HIP_TRY(timed(c, "adj_finish", [&] {
+            return launch_adj_finish<T>(io, (const int32_t*)c->owner.p, pot, xb, yb, zb, mb, c->stream);
+          }), "adjoint outputs");
+  if (gas_bar) {
+    for (int l = 0; l < nl; ++l) {
+      if (!gas_bar[l]) continue;
+      if (!io.gas_bar[l])
+        return fail(APM_ERR_INVALID, "apm_solve_adjoint: gas_bar given for a level without gas");
+      HIP_TRY(launch_to_t<T>(io.gas_bar[l], (T*)gas_bar[l], P.levels[l].gas_elems, c->stream),
+              "gas cotangent output");
+    }
+  }
+  return APM_OK;
+}
+
 extern "C" {
 
 apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out) {
@@ -852,8 +1017,8 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
                          "grid table");
   if (st != APM_OK) { apm_destroy(c); return st; }
   for (const LevelDesc& L : P.levels) {
-    std::vector<int64_t> dep(L.count + 1), cmp(L.count + 1), act(L.count + 1);
-    dep[0] = cmp[0] = act[0] = 0;
+    std::vector<int64_t> dep(L.count + 1), cmp(L.count + 1), act(L.count + 1), foot(L.count + 1);
+    dep[0] = cmp[0] = act[0] = foot[0] = 0;
     for (int i = 0; i < L.count; ++i) {
       const GridDesc& g = P.grids[L.first + i];
       const int64_t gc = (int64_t)g.gmf_n[0] * g.gmf_n[1] * g.gmf_n[2];
@@ -862,6 +1027,17 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
       dep[i + 1] = dep[i] + (gc + kBlock - 1) / kBlock;
       cmp[i + 1] = cmp[i] + (fc + kBlock - 1) / kBlock;
       act[i + 1] = act[i] + (ac + kBlock - 1) / kBlock;
+      int64_t fc2 = 0;                               // parent field cells under g's stencils
+      if (g.parent >= 0) {
+        fc2 = 1;
+        for (int a = 0; a < 3; ++a) {
+          const int l0 = std::max((g.fld_lo[a] >> 1) - 1, g.parent_fld_lo[a]);
+          const int h0 = std::min(((g.fld_lo[a] + g.fld_n[a] - 1) >> 1) + 1,
+                                  g.parent_fld_lo[a] + g.parent_fld_n[a] - 1);
+          fc2 *= std::max(h0 - l0 + 1, 0);
+        }
+      }
+      foot[i + 1] = foot[i] + (fc2 + kBlock - 1) / kBlock;
       const int64_t W = (g.M[0] / 2 + 1 + kRowAlign - 1) / kRowAlign * kRowAlign;   // row pitch
       c->spec_off.push_back((int64_t)c->spec_elems);
       c->z_off.push_back((int64_t)c->z_elems);
@@ -870,11 +1046,14 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
       c->z_elems += (size_t)(3 * (int64_t)g.fld_n[2] * g.M[1] * W);
       c->y_elems += (size_t)(4 * (int64_t)g.fld_n[2] * g.fld_n[1] * W);
     }
-    void *d1 = nullptr, *d2 = nullptr, *d3 = nullptr;
+    void *d1 = nullptr, *d2 = nullptr, *d3 = nullptr, *d4 = nullptr;
     st = upload(c, &d1, dep.data(), dep.size() * 8, "deposit block table");
     if (st == APM_OK) st = upload(c, &d2, cmp.data(), cmp.size() * 8, "compose block table");
     if (st == APM_OK) st = upload(c, &d3, act.data(), act.size() * 8, "active cell block table");
+    if (st == APM_OK) st = upload(c, &d4, foot.data(), foot.size() * 8, "restriction block table");
     if (st != APM_OK) { apm_destroy(c); return st; }
+    c->d_foot_begin.push_back((int64_t*)d4);
+    c->foot_blocks.push_back(foot.back());
     c->d_dep_begin.push_back((int64_t*)d1);
     c->d_cmp_begin.push_back((int64_t*)d2);
     c->d_act_begin.push_back((int64_t*)d3);
@@ -900,6 +1079,9 @@ apm_status apm_destroy(apm_ctx c) {
   for (auto& B : c->lvb)
     for (DevBuf* b : {&B.count, &B.items, &B.accum, &B.key, &B.rank, &B.sref, &B.sorted})
       if (b->p) (void)hipFree(b->p);
+  for (auto* v : {&c->adj_fbar, &c->adj_gas, &c->adj_gmf[0], &c->adj_gmf[1], &c->adj_gmf[2]})
+    for (auto& b : *v) if (b.p) (void)hipFree(b.p);
+  if (c->adj_pacc.p) (void)hipFree(c->adj_pacc.p);
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto& v : c->gmf)
@@ -1261,6 +1443,31 @@ const void* apm_gmf_ptr(apm_ctx c, apm_dtype dt, int32_t level) {
       level >= (int32_t)c->gmf[(int)dt].size())
     return nullptr;
   return c->gmf[(int)dt][level].p;
+}
+
+
+apm_status apm_solve_adjoint(apm_ctx c, apm_dtype dt, const void* x, const void* y, const void* z,
+                             const void* m, int64_t npart, const void* const* gas,
+                             const void* pot, const void* abar_x, const void* abar_y,
+                             const void* abar_z, const void* phibar, double wbar, void* xbar,
+                             void* ybar, void* zbar, void* mbar, void* const* gas_bar) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (npart < 0 || npart > INT32_MAX) return fail(APM_ERR_RANGE, "apm_solve_adjoint: npart out of range");
+  if (npart > 0 && (!x || !y || !z || !m))
+    return fail(APM_ERR_INVALID, "apm_solve_adjoint: NULL particle array");
+  if (wbar != 0.0 && npart > 0 && !pot)
+    return fail(APM_ERR_INVALID, "apm_solve_adjoint: wbar != 0 needs the solve's potentials");
+  if (dt == APM_F32)
+    return adjoint_t<float>(c, dt, (const float*)x, (const float*)y, (const float*)z,
+                            (const float*)m, npart, gas, (const float*)pot, (const float*)abar_x,
+                            (const float*)abar_y, (const float*)abar_z, (const float*)phibar, wbar,
+                            (float*)xbar, (float*)ybar, (float*)zbar, (float*)mbar, gas_bar);
+  return adjoint_t<double>(c, dt, (const double*)x, (const double*)y, (const double*)z,
+                           (const double*)m, npart, gas, (const double*)pot, (const double*)abar_x,
+                           (const double*)abar_y, (const double*)abar_z, (const double*)phibar,
+                           wbar, (double*)xbar, (double*)ybar, (double*)zbar, (double*)mbar,
+                           gas_bar);
 }
 
 }  // extern "C"

@@ -23,8 +23,21 @@ template <typename T> struct LevelPtrs {
   V4<T>* fld[kMaxLevels];          // packed (own) field buffer of each level
 };
 
-// The five transform passes of a grid's convolution.
-enum { PASS_X_FWD = 0, PASS_Y_FWD = 1, PASS_Z_CONV = 2, PASS_Y_INV = 3, PASS_X_INV = 4 };
+// The five transform passes of a grid's convolution, and the five of its transpose
+// (each adjoint pass runs one forward pass backwards, with that pass's launch shape).
+enum { PASS_X_FWD = 0, PASS_Y_FWD = 1, PASS_Z_CONV = 2, PASS_Y_INV = 3, PASS_X_INV = 4,
+       PASS_AX = 5, PASS_AY = 6, PASS_AZ = 7, PASS_AYI = 8, PASS_AXI = 9 };
+// forward pass whose launch shape an adjoint pass shares
+inline int mirror_pass(int pass) {
+  switch (pass) {
+    case PASS_AX: return PASS_X_INV;
+    case PASS_AY: return PASS_Y_INV;
+    case PASS_AZ: return PASS_Z_CONV;
+    case PASS_AYI: return PASS_Y_FWD;
+    case PASS_AXI: return PASS_X_FWD;
+  }
+  return pass;
+}
 
 // One grid in one pass: GMF (dims g) zero-padded into FFT box M, outputs on the field
 // box (dims f) whose first cell sits at transform index off (cyclic).  Offsets are
@@ -44,11 +57,25 @@ struct ConvJob {
 };
 int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], int nl);
 template <typename T> int default_lines(int pass, int L);
+constexpr int kZConvMaxThreads = 512;     // keeps the FP64 z passes free of spills
 template <typename T> size_t pass_lds(int pass, int L, int nl);   // 0: not launchable
+template <typename T> int pass_row_stride(int pass, int L, int nl); // LDS line stride
+int pass_threads(int pass, int L, int nl);
 template <typename T>
 hipError_t launch_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, int64_t nblocks,
                        const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* zbuf, C2<T>* ybuf,
                        const void* tw, hipStream_t s);
+
+// Buffers of the transposed convolution: GMF cotangents out (working precision) and
+// FP64 field-box cotangents in (4 per cell, field layout), per level.
+template <typename T> struct AdjPtrs {
+  T* gmf[kMaxLevels];
+  const double* fbar[kMaxLevels];
+};
+template <typename T>
+hipError_t launch_adj_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, int64_t nblocks,
+                           const AdjPtrs<T>& ap, C2<T>* spec, C2<T>* zbuf, C2<T>* ybuf,
+                           const void* tw, hipStream_t s);
 
 // Green's functions (FP64): octant table of (force, potential) times `norm`.
 struct InfluenceParams {
@@ -136,6 +163,50 @@ template <typename T> struct InterpIO {
 };
 template <typename T> hipError_t launch_interp_sorted(const InterpIO<T>& io, const DepLevel* tab,
                                                       const GridDesc* grids, hipStream_t s);
+// ---- reverse sweep (adjoint.hip) ----
+struct ZeroList {                      // FP64 ranges to clear in one launch
+  double* p[48];
+  int64_t n[48];
+  int32_t count;
+};
+hipError_t launch_zero_ranges(const ZeroList& zl, hipStream_t s);
+template <typename T> struct AdjIO {
+  int32_t nlev;                        // levels of the batch (b = level - first)
+  int64_t npart;
+  double wbar;                         // weight of W in the loss
+  const T* abx; const T* aby; const T* abz;   // acceleration cotangents (npart)
+  const T* phib;                       // potential cotangents (npart) or null
+  int64_t item_blk0[kMaxLevels + 1];   // interpolation-transpose blocks (deposit items)
+  int64_t fin_blk0[kMaxLevels + 1];    // GMF-cell blocks
+  int64_t part_blk0[kMaxLevels + 1];   // sorted-list blocks
+  const V4<T>* fld[kMaxLevels];        // forward composed fields
+  double* fbar[kMaxLevels];            // field cotangents, FP64, 4 per field cell
+  const T* gmf_bar[kMaxLevels];        // GMF cotangents
+  double* gas_bar[kMaxLevels];         // own-gas cotangent of the level, or null
+  double* pgas_bar[kMaxLevels];        // the parent level's gas cotangent, or null
+  double* pacc[4];                     // per particle, FP64: mbar, xbar, ybar, zbar
+};
+template <typename T> hipError_t launch_adj_interp(const AdjIO<T>& io, const DepLevel* tab,
+                                                   const GridDesc* grids, hipStream_t s);
+template <typename T> hipError_t launch_adj_gas_seed(const GridDesc* grids, int32_t ngrids,
+                                                     int32_t first, int32_t count,
+                                                     const int64_t* begin, int64_t nblocks,
+                                                     double root_n, const T* gas,
+                                                     const V4<T>* field, double wbar,
+                                                     double* fbar, double* gas_bar,
+                                                     hipStream_t s);
+hipError_t launch_adj_restrict(const GridDesc* grids, int32_t first, int32_t count,
+                               const int64_t* begin, int64_t nblocks, const double* child_bar,
+                               double* parent_bar, hipStream_t s);
+template <typename T> hipError_t launch_adj_deposit_grid(const AdjIO<T>& io, const DepLevel* tab,
+                                                         hipStream_t s);
+template <typename T> hipError_t launch_adj_deposit_particles(const AdjIO<T>& io,
+                                                              const DepLevel* tab, hipStream_t s);
+template <typename T> hipError_t launch_adj_finish(const AdjIO<T>& io, const int32_t* owner,
+                                                   const T* pot, T* xb, T* yb, T* zb, T* mb,
+                                                   hipStream_t s);
+template <typename T> hipError_t launch_to_t(const double* a, T* b, int64_t n, hipStream_t s);
+
 template <typename T> hipError_t launch_compose(const GridDesc* grids, const int64_t* block_begin,
                                                 int32_t ngrids, const V4<T>* own,
                                                 const V4<T>* parent, V4<T>* field,

@@ -133,7 +133,6 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
 //   s = 1: -i d_z(k_z) Gf(k) rho_hat
 //   s = 2: Gp(k) rho_hat
 // kern: octant table of (Gf, Gp), index ((|kz| Oy) + |ky|) W + kx, already scaled.
-constexpr int kZConvMaxThreads = 512;     // keeps the FP64 z pass free of spills
 
 template <typename T, int L>
 __global__ void __launch_bounds__(kZConvMaxThreads)
@@ -351,6 +350,7 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
 
 // ------------------------------------------------------------------ launchers --
 int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], int nl) {
+  pass = mirror_pass(pass);
   const int64_t W = M[0] / 2 + 1;
   const int64_t nbw = (W + nl - 1) / nl;
   switch (pass) {
@@ -364,6 +364,7 @@ int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], in
 }
 
 template <typename T> int default_lines(int pass, int L) {
+  pass = mirror_pass(pass);
   int nl = (std::is_same<T, float>::value ? 4096 : 2048) / L;
   if (pass == PASS_X_INV) return nl < 4 ? 4 : nl;
   if (pass == PASS_Y_INV) return nl / 4 < 1 ? 1 : nl / 4;
@@ -371,11 +372,14 @@ template <typename T> int default_lines(int pass, int L) {
   return nl;
 }
 
-static int pass_lines_per_block(int pass, int nl) { return pass == PASS_Y_INV ? 4 * nl : nl; }
+static int pass_lines_per_block(int pass, int nl) {
+  return mirror_pass(pass) == PASS_Y_INV ? 4 * nl : nl;
+}
 
 // LDS row stride: padded by one element where the load is column-wise, unless the
 // padding would not fit in 64 KB
 template <typename T> static int pass_ls(int pass, int L, int nl) {
+  pass = mirror_pass(pass);
   const bool strided = pass == PASS_Y_FWD || pass == PASS_Z_CONV || pass == PASS_Y_INV;
   if (!strided) return L;
   const size_t padded = (size_t)pass_lines_per_block(pass, nl) * (L + 1) * sizeof(C2<T>);
@@ -383,7 +387,11 @@ template <typename T> static int pass_ls(int pass, int L, int nl) {
 }
 
 // LDS bytes of a launch; 0 if the shape is not launchable (threads or LDS)
+template <typename T> int pass_row_stride(int pass, int L, int nl) { return pass_ls<T>(pass, L, nl); }
+int pass_threads(int pass, int L, int nl) { return pass_lines_per_block(pass, nl) * (L / 8); }
+
 template <typename T> size_t pass_lds(int pass, int L, int nl) {
+  pass = mirror_pass(pass);
   if (nl < 1) return 0;
   const int lines = pass_lines_per_block(pass, nl);
   const size_t bytes = (size_t)lines * pass_ls<T>(pass, L, nl) * sizeof(C2<T>);
@@ -446,6 +454,8 @@ template int default_lines<float>(int, int);
 template int default_lines<double>(int, int);
 template size_t pass_lds<float>(int, int, int);
 template size_t pass_lds<double>(int, int, int);
+template int pass_row_stride<float>(int, int, int);
+template int pass_row_stride<double>(int, int, int);
 template hipError_t launch_pass<float>(int, int, int, const ConvJob*, int, int64_t,
                                        const LevelPtrs<float>&, C2<float>*, C2<float>*,
                                        C2<float>*, const void*, hipStream_t);

@@ -1,0 +1,394 @@
+// Transpose of the per-grid convolution (Sec. 2.2, Eq. 2, reversed): from the four
+// field-box cotangents (a_x, a_y, a_z, Phi) of a grid to the cotangent of its GMF.
+// The forward map is a real cyclic convolution on the zero-padded M box with
+// Fourier multipliers -i d_i Gf (force) and Gp (potential); its transpose is the
+// cyclic convolution with the flipped kernels, multipliers conj(-i d_i Gf) =
+// +i d_i Gf and Gp, the four inputs summed into one output:
+//
+//   S(k) = Gf(k) [ i d_x X_x + i d_y X_y + i d_z X_z ](k) + Gp(k) X_Phi(k),
+//   GMF_bar = GMF-box part of IDFT(S),  X_c = DFT(field-box cotangent c, zero padded).
+//
+// Because d_i depends only on k_i, each derivative is applied in the pass along its
+// axis and the a_x / a_y / a_z terms are merged as early as possible.  The passes
+// run the forward ones backwards, on the same buffers and job tables:
+//   ax   field-box rows (4 components) -> half spectra; row pairs share a complex
+//        FFT; +i d_x on component 0                         (y buffer: 4 arrays)
+//   ay   columns along y: 4 lines -> FFT -> [X_x + i d_y X_y, X_z, X_Phi]  (z buffer)
+//   az   columns along z: 3 FFTs -> S = Gf (U + i d_z V) + Gp P -> inverse FFT ->
+//        the gz GMF planes                                   (spectrum buffer)
+//   ayi  columns along y: inverse FFT, the gy GMF rows kept, in place
+//   axi  GMF rows: Hermitian half spectra -> inverse real FFT, two rows per complex
+//        FFT -> the gx GMF cells
+// Unnormalised transforms; the kernel table carries 1/(Mx My Mz) as in the forward.
+#include "apm_kernels.hpp"
+#include "device_common.hpp"
+
+namespace apm {
+
+__device__ __forceinline__ int find_job_a(const ConvJob* __restrict__ jobs, int njobs, int64_t b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].blk0 <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// (i d) z for real d
+template <typename T> __device__ __forceinline__ C2<T> mul_id(T d, C2<T> z) {
+  return mk<T>(-d * z.y, d * z.x);
+}
+
+// ------------------------------------------------------------------ ax ----------
+// Block = nl/4 row pairs of the field box (rows r = j fy + y), 4 lines per pair (one
+// per component): line = comp(row 2q) + i comp(row 2q + 1) at transform positions
+// (ox + x) mod L.  Output: half spectra into the y buffer, rows of component c.
+template <typename T, int L>
+__global__ void __launch_bounds__(1024)
+k_adj_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
+        C2<T>* __restrict__ yb, const C2<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job_a(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int P = J.pitch;
+  const int fx = J.f[0], fy = J.f[1], fz = J.f[2], ox = J.off[0];
+  C2<T>* __restrict__ ybuf = yb + J.y_off;
+  const gptr<T> dxs = as_global<T>(J.dsym[0]);
+  const double* __restrict__ fb = ap.fbar[J.level] + 4 * J.fld_off;
+  const int G = nl / 4;
+  const int nt = nl * (L / 8);
+  const int t = threadIdx.x;
+  const int b = t / (L / 8), w = t % (L / 8);
+  const int64_t rows = (int64_t)fz * fy;
+  for (int i = t; i < nl * L; i += nt) lds[i] = mk<T>(0, 0);
+  __syncthreads();
+  for (int idx = t; idx < G * 2 * fx; idx += nt) {
+    const int gg = idx / (2 * fx), rem = idx % (2 * fx);
+    const int half = rem / fx, x = rem % fx;
+    const int64_t r = 2 * (blk * G + gg) + half;
+    if (r < rows) {
+      const double* cell = fb + 4 * (r * fx + x);
+      const int xi = (ox + x) & (L - 1);
+      C2<T>* L0 = lds + (4 * gg) * L + xi;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (half == 0) L0[c * L].x = (T)cell[c];
+        else L0[c * L].y = (T)cell[c];
+      }
+    }
+  }
+  __syncthreads();
+  C2<T>* line = lds + b * L;
+  fft_line<T, L, false>(line, w, tw);
+  const int64_t q = blk * G + b / 4;
+  const int c = b & 3;
+  const int64_t ra = 2 * q, rb = 2 * q + 1;
+  if (ra < rows) {
+    const int64_t cs = (int64_t)c * rows * P;
+    C2<T>* outa = ybuf + cs + ra * P;
+    C2<T>* outb = ybuf + cs + rb * P;
+    const T h = (T)0.5;
+    for (int k = w; k <= L / 2; k += L / 8) {
+      const C2<T> z = line[k], m = line[(L - k) & (L - 1)];
+      C2<T> A = mk<T>(h * (z.x + m.x), h * (z.y - m.y));
+      C2<T> B = mk<T>(h * (z.y + m.y), h * (m.x - z.x));
+      if (c == 0) {
+        const T d = dxs[k];
+        A = mul_id<T>(d, A);
+        B = mul_id<T>(d, B);
+      }
+      outa[k] = A;
+      if (rb < rows) outb[k] = B;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ ay ----------
+// Block = (plane j < fz, nl columns), 4 lines per column from the 4 y-buffer arrays
+// (rows y < fy at positions (oy + y) mod L, zero elsewhere); forward FFT; writes
+// U = X_x + i d_y X_y, V = X_z, P = X_Phi as z-buffer arrays 0, 1, 2 (all My rows).
+template <typename T, int L>
+__global__ void __launch_bounds__(1024)
+k_adj_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
+        const C2<T>* __restrict__ yb, C2<T>* __restrict__ zb, const C2<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job_a(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1], P = J.pitch;
+  const int fz = J.f[2], fy = J.f[1], oy = J.off[1];
+  const int nbw = (W + nl - 1) / nl;
+  const int j = (int)(blk / nbw);
+  const int c0 = (int)(blk % nbw) * nl;
+  const gptr<T> dys = as_global<T>(J.dsym[1]);
+  const C2<T>* yin = yb + J.y_off + (int64_t)j * fy * P + c0;
+  const int64_t ys = (int64_t)fz * fy * P;
+  C2<T>* zout = zb + J.z_off + (int64_t)j * My * P + c0;
+  const int64_t zs = (int64_t)fz * My * P;
+  const int t = threadIdx.x;
+  const int cb = t % nl, r0 = t / nl;                // column-wise: rows r0 + q L/2
+  const bool col_ok = c0 + cb < W;
+  C2<T> v[2][4];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int r = r0 + q * (L / 2);                  // transform position
+    const int y = (r - oy) & (L - 1);                // field row landing there
+    const bool ok = col_ok && y < fy;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      v[q][a] = ok ? yin[a * ys + (int64_t)y * P + cb] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int r = r0 + q * (L / 2);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) lds[(a * nl + cb) * ls + r] = v[q][a];
+  }
+  __syncthreads();
+  const int b = t / (L / 8), w = t % (L / 8);
+  fft_line<T, L, false>(lds + b * ls, w, tw);
+  __syncthreads();                                   // stores read four lines
+  if (col_ok) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int k = r0 + q * (L / 2);
+      const T d = dys[k];
+      const C2<T> X0 = lds[(0 * nl + cb) * ls + k], X1 = lds[(1 * nl + cb) * ls + k];
+      const C2<T> U = cadd(X0, mul_id<T>(d, X1));
+      zout[(int64_t)k * P + cb] = U;
+      zout[zs + (int64_t)k * P + cb] = lds[(2 * nl + cb) * ls + k];
+      zout[2 * zs + (int64_t)k * P + cb] = lds[(3 * nl + cb) * ls + k];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ az ----------
+// Block = (ky, nl columns), one line per column: the three z-buffer arrays in turn
+// (planes j < fz at positions (oz + j) mod L) -> forward FFT -> accumulated into
+// S = Gf (U + i d_z V) + Gp P in registers; then the inverse FFT of S and the gz GMF
+// planes into the spectrum buffer.
+template <typename T, int L>
+__global__ void __launch_bounds__(kZConvMaxThreads)
+k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
+        const C2<T>* __restrict__ zb, C2<T>* __restrict__ specb, const C2<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job_a(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1], P = J.pitch;
+  const int gz = J.g[2], fz = J.f[2], oz = J.off[2];
+  const int nbw = (W + nl - 1) / nl;
+  const int ky = (int)(blk / nbw);
+  const int c0 = (int)(blk % nbw) * nl;
+  const C2<T>* zin = zb + J.z_off + (int64_t)ky * P + c0;
+  const int64_t pstride = (int64_t)My * P;
+  const int64_t zs = (int64_t)fz * pstride;
+  C2<T>* spec = specb + J.spec_off + (int64_t)ky * P + c0;
+  const gptr<T> dzs = as_global<T>(J.dsym[2]);
+  const int t = threadIdx.x;
+  const int cb = t % nl, r0 = t / nl;
+  const bool col_ok = c0 + cb < W;
+  const int b = t / (L / 8), w = t % (L / 8);
+  C2<T>* line = lds + b * ls;
+  const int kx = c0 + b;
+  const int kxc = kx < W ? kx : 0;
+  const int Oy = My / 2 + 1;
+  const int kyo = ky <= My / 2 ? ky : My - ky;
+  T gf[8], gp[8], dz[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int kz = w + q * (L / 8);
+    const int kzo = kz <= L / 2 ? kz : L - kz;
+    const C2<T> G = load_c2<T>(J.kern, ((int64_t)kzo * Oy + kyo) * W + kxc);
+    gf[q] = G.x;
+    gp[q] = G.y;
+    dz[q] = dzs[kz];
+  }
+  C2<T> S[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) S[q] = mk<T>(0, 0);
+  for (int s = 0; s < 3; ++s) {
+    C2<T> v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = r0 + q * (L / 8);                // transform position
+      const int jz = (r - oz) & (L - 1);             // field plane landing there
+      v[q] = (col_ok && jz < fz) ? zin[s * zs + (int64_t)jz * pstride + cb] : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
+    __syncthreads();
+    fft_line<T, L, false>(line, w, tw);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const C2<T> X = line[w + q * (L / 8)];
+      if (s == 0) S[q] = cadd(S[q], mk<T>(gf[q] * X.x, gf[q] * X.y));
+      else if (s == 1) S[q] = cadd(S[q], mul_id<T>(gf[q] * dz[q], X));
+      else S[q] = cadd(S[q], mk<T>(gp[q] * X.x, gp[q] * X.y));
+    }
+    __syncthreads();                                 // the line is reloaded next
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) line[w + q * (L / 8)] = S[q];
+  __syncthreads();
+  fft_line<T, L, true>(line, w, tw);
+  __syncthreads();                                   // stores use another mapping
+  if (col_ok) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int z = r0 + q * (L / 8);
+      if (z < gz) spec[z * pstride + cb] = lds[cb * ls + z];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ ayi ---------
+// Block = (plane z < gz, nl columns): inverse FFT along y of all My rows, rows
+// [0, gy) written back in place.
+template <typename T, int L>
+__global__ void __launch_bounds__(1024)
+k_adj_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* __restrict__ specb,
+            const C2<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job_a(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1], gy = J.g[1], P = J.pitch;
+  const int nbw = (W + nl - 1) / nl;
+  const int64_t p = blk / nbw;
+  const int c0 = (int)(blk % nbw) * nl;
+  C2<T>* base = specb + J.spec_off + p * ((int64_t)My * P) + c0;
+  const int t = threadIdx.x;
+  const int cb = t % nl, r0 = t / nl;
+  const bool col_ok = c0 + cb < W;
+  C2<T> v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int r = r0 + q * (L / 8);
+    v[q] = col_ok ? base[(int64_t)r * P + cb] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
+  __syncthreads();
+  const int b = t / (L / 8), w = t % (L / 8);
+  fft_line<T, L, true>(lds + b * ls, w, tw);
+  __syncthreads();
+  if (col_ok) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = r0 + q * (L / 8);
+      if (r < gy) base[(int64_t)r * P + cb] = lds[cb * ls + r];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ axi ---------
+// Block = nl GMF row pairs (rows r = z gy + y): the two Hermitian half spectra form
+// one complex line A + i B, whose inverse FFT has the two real rows as its real and
+// imaginary parts; cells x < gx are written to the GMF cotangent.
+template <typename T, int L>
+__global__ void __launch_bounds__(1024)
+k_adj_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
+            const C2<T>* __restrict__ specb, const C2<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job_a(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int gx = J.g[0], gy = J.g[1], gz = J.g[2], My = J.M[1], P = J.pitch;
+  const C2<T>* __restrict__ spec = specb + J.spec_off;
+  T* __restrict__ out = ap.gmf[J.level] + J.gmf_off;
+  const int t = threadIdx.x;
+  const int b = t / (L / 8), w = t % (L / 8);
+  C2<T>* line = lds + b * L;
+  const int64_t rows = (int64_t)gy * gz;
+  const int64_t q = blk * nl + b;
+  const int64_t ra = 2 * q, rb = 2 * q + 1;
+  if (ra < rows) {
+    const bool hb = rb < rows;
+    const int64_t za = ra / gy, ya = ra % gy, zb = hb ? rb / gy : za, yb = hb ? rb % gy : ya;
+    const C2<T>* A = spec + (za * My + ya) * P;
+    const C2<T>* B = spec + (zb * My + yb) * P;
+    for (int i = w; i < L; i += L / 8) {
+      const int k = i <= L / 2 ? i : L - i;
+      C2<T> a = A[k], bq = hb ? B[k] : mk<T>(0, 0);
+      if (k == 0 || k == L / 2) { a.y = 0; bq.y = 0; }
+      line[i] = i <= L / 2 ? mk<T>(a.x - bq.y, a.y + bq.x) : mk<T>(a.x + bq.y, bq.x - a.y);
+    }
+  } else {
+    for (int i = w; i < L; i += L / 8) line[i] = mk<T>(0, 0);
+  }
+  __syncthreads();
+  fft_line<T, L, true>(line, w, tw);
+  if (ra < rows) {
+    for (int x = w; x < gx; x += L / 8) {
+      const C2<T> v = line[x];
+      out[ra * gx + x] = v.x;
+      if (rb < rows) out[rb * gx + x] = v.y;
+    }
+  }
+}
+
+#define APM_ADJ_DISPATCH(Lv, ...)                            \
+  switch (Lv) {                                              \
+    case 16: { constexpr int LL = 16; __VA_ARGS__; } break;   \
+    case 32: { constexpr int LL = 32; __VA_ARGS__; } break;   \
+    case 64: { constexpr int LL = 64; __VA_ARGS__; } break;   \
+    case 128: { constexpr int LL = 128; __VA_ARGS__; } break; \
+    case 256: { constexpr int LL = 256; __VA_ARGS__; } break; \
+    case 512: { constexpr int LL = 512; __VA_ARGS__; } break; \
+    case 1024: { constexpr int LL = 1024; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;                    \
+  }
+
+template <typename T>
+hipError_t launch_adj_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, int64_t nblocks,
+                           const AdjPtrs<T>& ap, C2<T>* spec, C2<T>* zbuf, C2<T>* ybuf,
+                           const void* tw, hipStream_t s) {
+  if (njobs == 0 || nblocks == 0) return hipSuccess;
+  const size_t shm = pass_lds<T>(pass, L, nl);
+  if (shm == 0) return hipErrorInvalidConfiguration;
+  const int ls = pass_row_stride<T>(pass, L, nl);
+  const dim3 grid((unsigned)nblocks), block((unsigned)pass_threads(pass, L, nl));
+  const C2<T>* twc = (const C2<T>*)tw;
+  APM_ADJ_DISPATCH(L, {
+    switch (pass) {
+      case PASS_AX:
+        hipLaunchKernelGGL((k_adj_x<T, LL>), grid, block, shm, s, jobs, njobs, nl, ap, ybuf, twc);
+        break;
+      case PASS_AY:
+        hipLaunchKernelGGL((k_adj_y<T, LL>), grid, block, shm, s, jobs, njobs, nl, ls,
+                           (const C2<T>*)ybuf, zbuf, twc);
+        break;
+      case PASS_AZ:
+        hipLaunchKernelGGL((k_adj_z<T, LL>), grid, block, shm, s, jobs, njobs, nl, ls,
+                           (const C2<T>*)zbuf, spec, twc);
+        break;
+      case PASS_AYI:
+        hipLaunchKernelGGL((k_adj_y_inv<T, LL>), grid, block, shm, s, jobs, njobs, nl, ls, spec,
+                           twc);
+        break;
+      case PASS_AXI:
+        hipLaunchKernelGGL((k_adj_x_inv<T, LL>), grid, block, shm, s, jobs, njobs, nl, ap,
+                           (const C2<T>*)spec, twc);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+  });
+  return hipGetLastError();
+}
+
+template hipError_t launch_adj_pass<float>(int, int, int, const ConvJob*, int, int64_t,
+                                           const AdjPtrs<float>&, C2<float>*, C2<float>*,
+                                           C2<float>*, const void*, hipStream_t);
+template hipError_t launch_adj_pass<double>(int, int, int, const ConvJob*, int, int64_t,
+                                            const AdjPtrs<double>&, C2<double>*, C2<double>*,
+                                            C2<double>*, const void*, hipStream_t);
+
+}  // namespace apm

@@ -220,6 +220,30 @@ class Context:
                                           _ptr(pot), out), "apm_solve_totals")
         return np.array(out[:])
 
+    def solve_adjoint(self, x, y, z, m, gas=None, pot=None, abar=None, phibar=None, wbar=0.0,
+                      want_gas=True):
+        """Reverse sweep of the last solve() of these particles (apm_solve_adjoint):
+        gradients of wbar W + sum abar.a + sum phibar Phi.  Returns (xbar, ybar, zbar,
+        mbar, gas_bar), gas_bar a per-level list (None where a level has no gas)."""
+        n = x.shape[0]
+        mk = lambda: self.torch.empty(n, dtype=x.dtype, device=self.device)
+        xb, yb, zb, mb = mk(), mk(), mk(), mk()
+        ab = abar if abar is not None else (None, None, None)
+        gas_bar = None
+        garr_out = None
+        if gas is not None and want_gas:
+            gas_bar = [None if g is None else
+                       self.torch.empty(self.plan.levels[l]["gas_elems"], dtype=x.dtype,
+                                        device=self.device) for l, g in enumerate(gas)]
+            garr_out = (ctypes.c_void_p * self.plan.nlevels)(
+                *[None if g is None else g.data_ptr() for g in gas_bar])
+        check(_apm.lib().apm_solve_adjoint(self.handle, _dtype_code(x), _ptr(x), _ptr(y), _ptr(z),
+                                           _ptr(m), n, self._gas_array(gas), _ptr(pot),
+                                           _ptr(ab[0]), _ptr(ab[1]), _ptr(ab[2]), _ptr(phibar),
+                                           float(wbar), _ptr(xb), _ptr(yb), _ptr(zb), _ptr(mb),
+                                           garr_out), "apm_solve_adjoint")
+        return xb, yb, zb, mb, gas_bar
+
     def gas_energy(self, level, gas, field):
         out = ctypes.c_double()
         check(_apm.lib().apm_gas_energy(self.handle, _dtype_code(gas), level, _ptr(gas),

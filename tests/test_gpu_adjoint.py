@@ -1,0 +1,195 @@
+"""GPU parity of the reverse sweep (apm_solve_adjoint through the C ABI) against the
+FP64 oracle adjoint (oracle/apm_adjoint.py, itself pinned by finite differences and
+transpose identities), and a finite-difference check of the autograd wrappers on
+the GPU.  Tolerances: relative L2 1e-11 in FP64 and 1e-5 in FP32 (FP32-rounded
+inputs on both sides)."""
+
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import apm_workloads as W
+from oracle import apm_adjoint as A
+from oracle import apm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+P = pytest.importorskip("paper_1410_0010_amd")
+from paper_1410_0010_amd import autograd as AG  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / (nb if nb > 0 else 1.0)
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype))).to(DEV)
+
+
+def rounded(w, dtype):
+    f = lambda a: None if a is None else np.asarray(a, dtype).astype(np.float64)
+    return f(w.x), f(w.y), f(w.z), f(w.m), [f(g) for g in w.gas]
+
+
+def gas_clumps():
+    """24 overlapping level-1 grids (several grids per tile, restriction from many
+    children) with gas on the root injected into every grid."""
+    w = W.workload_clumps(root_n=32, ngrids=24, per_clump=300, side_lo=4, side_hi=20)
+    rng = np.random.default_rng(77)
+    gas = [0.5 * W.gaussian_random_field_gas(rng, 32)]
+    for g in w.grids[1:]:
+        gas.append(W.inject_gas(gas[g.parent], w.grids[g.parent], g))
+    return dataclasses.replace(w, gas=gas)
+
+
+CASES = {
+    "gas_nested32": lambda: W.workload_plummer_gas(root_n=32, sub_n=16, nlevels=2, npart=6000),
+    "plummer_nested32_3lev": lambda: W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=3,
+                                                                npart=8000),
+    "root32_gas_4096": W.workload_root32_uniform_gas,
+    "clumps32_24grids_gas": gas_clumps,
+}
+
+
+def gpu_adjoint(w, dtype, abar=None, phibar=None, wbar=0.0):
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    x, y, z, m = (dev(a, dtype) for a in (w.x, w.y, w.z, w.m))
+    gas = [ctx.pack_gas(l, w.gas, x.dtype) for l in range(plan.nlevels)]
+    has_gas = any(g is not None for g in gas)
+    ax, ay, az, pot = ctx.solve(x, y, z, m, gas if has_gas else None)
+    ab = None if abar is None else tuple(dev(abar[:, k], dtype) for k in range(3))
+    pb = None if phibar is None else dev(phibar, dtype)
+    xb, yb, zb, mb, gb = ctx.solve_adjoint(x, y, z, m, gas if has_gas else None, pot, ab, pb, wbar)
+    torch.cuda.synchronize()
+    got = lambda t: t.cpu().numpy().astype(np.float64)
+    gas_out = None
+    if gb is not None:
+        gas_out = {}
+        for l in range(plan.nlevels):
+            if gb[l] is None:
+                continue
+            flat = got(gb[l])
+            for g in plan.level_grids(l):
+                n = int(np.prod(g["n"]))
+                gas_out[g["index"]] = flat[g["gas_offset"]:g["gas_offset"] + n].reshape(
+                    g["n"][2], g["n"][1], g["n"][0])
+    return dict(x=np.stack([got(xb), got(yb), got(zb)], 1), m=got(mb), gas=gas_out)
+
+
+def check(name, dtype, got, ref, w):
+    tol = 1e-11 if dtype == np.float64 else 1e-5
+    ex = rel(got["x"], ref["x"])
+    em = rel(got["m"], ref["m"])
+    say(f"[adjoint] {name} {dtype.__name__}: x {ex:.2e} m {em:.2e}")
+    assert ex <= tol, f"{name}: position gradient rel L2 {ex:.3e}"
+    assert em <= tol, f"{name}: mass gradient rel L2 {em:.3e}"
+    if got["gas"] is not None:
+        for gi, arr in got["gas"].items():
+            r = ref["gas"][gi]
+            eg = rel(arr, r)
+            assert eg <= tol, f"{name}: gas gradient of grid {gi} rel L2 {eg:.3e}"
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_energy_gradient_matches_oracle(case, dtype):
+    w = CASES[case]()
+    say(f"[adjoint] energy gradient case={case} dtype={dtype.__name__} npart={w.npart}")
+    x, y, z, m, gas = rounded(w, dtype)
+    ref = A.energy_gradient(O.OraclePlan(w.root_n, w.grids), x, y, z, m, gas)
+    check(case, dtype, gpu_adjoint(w, dtype, wbar=1.0), ref, w)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("case", ["gas_nested32", "clumps32_24grids_gas"])
+def test_general_loss_gradient_matches_oracle(case, dtype):
+    w = CASES[case]()
+    rng = np.random.default_rng(3)
+    ab = np.asarray(rng.standard_normal((w.npart, 3)), dtype).astype(np.float64)
+    pb = np.asarray(rng.standard_normal(w.npart), dtype).astype(np.float64)
+    say(f"[adjoint] general loss case={case} dtype={dtype.__name__}")
+    x, y, z, m, gas = rounded(w, dtype)
+    ref = A.adjoint(O.OraclePlan(w.root_n, w.grids), x, y, z, m, gas, abar=ab, phibar=pb,
+                    wbar=0.5)
+    check(case, dtype, gpu_adjoint(w, dtype, ab, pb, 0.5), ref, w)
+
+
+def test_adjoint_needs_matching_solve():
+    w = W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=1, npart=1000)
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    x, y, z, m = (dev(a, np.float64) for a in (w.x, w.y, w.z, w.m))
+    with pytest.raises(P.APMError):
+        ctx.solve_adjoint(x, y, z, m, wbar=1.0, pot=torch.zeros_like(x))
+    ax, ay, az, pot = ctx.solve(x, y, z, m)
+    x2 = x.clone()
+    with pytest.raises(P.APMError):
+        ctx.solve_adjoint(x2, y, z, m, wbar=1.0, pot=pot)
+
+
+def test_autograd_energy_finite_difference_fp64():
+    """d W / d(x, m, gas) from torch.autograd (the reverse sweep) against central
+    differences of the GPU forward energy along random directions (FP64)."""
+    w = W.workload_plummer_gas(root_n=32, sub_n=16, nlevels=2, npart=3000)
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    x, y, z, m = (dev(a, np.float64).requires_grad_() for a in (w.x, w.y, w.z, w.m))
+    gas = [ctx.pack_gas(l, w.gas, torch.float64) for l in range(plan.nlevels)]
+    for g in gas:
+        g.requires_grad_()
+    e = AG.potential_energy(ctx, x, y, z, m, gas)
+    grads = torch.autograd.grad(e, [x, y, z, m] + gas)
+    rng = np.random.default_rng(5)
+    dirs = [dev(rng.standard_normal(t.shape[0]), np.float64) for t in [x, y, z, m] + gas]
+
+    def energy_at(s, which):
+        with torch.no_grad():
+            vals = [t.detach().clone() for t in [x, y, z, m] + gas]
+            for k in which:
+                vals[k] = vals[k] + s * dirs[k] * (vals[k] if k >= 3 else 1.0)
+            ax, ay, az, pot = ctx.solve(*vals[:4], vals[4:])
+            return ctx.solve_totals(vals[3], ax, ay, az, pot, gas=vals[4:])[plan.nlevels]
+
+    # positions: W is C1 in x (quadratic TSC pieces); masses and gas: W is quadratic
+    for which, eps, tol in (([0, 1, 2], 1e-7, 1e-6), ([3], 1e-3, 1e-9), ([4, 5, 6], 1e-3, 1e-9)):
+        fd = (energy_at(eps, which) - energy_at(-eps, which)) / (2 * eps)
+        an = sum(float(torch.sum(grads[k] * dirs[k] * ((x, y, z, m, *gas)[k].detach()
+                                                      if k >= 3 else 1.0))) for k in which)
+        scale = sum(float(torch.sum(torch.abs(grads[k] * dirs[k] * ((x, y, z, m, *gas)[k].detach()
+                                                                   if k >= 3 else 1.0))))
+                    for k in which)
+        say(f"[adjoint] autograd FD {which}: fd {fd:.10e} adjoint {an:.10e}")
+        assert abs(fd - an) <= tol * scale
+
+
+def test_autograd_solve_backward_matches_adjoint_fp32():
+    w = W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=2, npart=4000)
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    x, y, z, m = (dev(a, np.float32).requires_grad_() for a in (w.x, w.y, w.z, w.m))
+    ax, ay, az, pot = AG.solve(ctx, x, y, z, m)
+    rng = np.random.default_rng(8)
+    c = [dev(rng.standard_normal(w.npart), np.float32) for _ in range(4)]
+    loss = (ax * c[0]).sum() + (ay * c[1]).sum() + (az * c[2]).sum() + (pot * c[3]).sum()
+    g = torch.autograd.grad(loss, [x, y, z, m])
+    xr, yr, zr, mr, _ = rounded(w, np.float32)
+    ref = A.adjoint(O.OraclePlan(w.root_n, w.grids), xr, yr, zr, mr,
+                    abar=np.stack([t.cpu().numpy() for t in c[:3]], 1).astype(np.float64),
+                    phibar=c[3].cpu().numpy().astype(np.float64))
+    got = np.stack([t.cpu().numpy() for t in g[:3]], 1)
+    assert rel(got, ref["x"]) <= 1e-5 and rel(g[3].cpu().numpy(), ref["m"]) <= 1e-5
