@@ -1,20 +1,30 @@
 """Throughput of the APM nested-grid gravity solve on one MI355X.
 
-A step is one forward solve of the whole hot path over the workload: owner grids,
-TSC deposit of every level (tile binning + LDS-tiled deposit with FP64
-accumulation), the FFT convolution of every grid with Fourier-space differencing,
-level composition, TSC interpolation to every particle and the FP64 totals (mass,
-energy, net force).
-Workload (the hierarchy the metric is quoted on): root 128^3 plus two centred
-nested 64^3 levels, 2^20 equal-mass Plummer particles (scale 0.05), no gas,
-synthetic and seeded.
+A step is one pass of the whole hot path over the workload:
+  forward  owner grids, TSC deposit of every level (tile binning + LDS-tiled
+           deposit with FP64 accumulation), the FFT convolution of every grid with
+           Fourier-space differencing, level composition, TSC interpolation to every
+           particle, and the FP64 totals (mass per level, energy, net force);
+  adjoint  the reverse sweep for the gradient of the potential energy W with respect
+           to positions and masses (and gas), after the forward solve.
+Workloads (synthetic and seeded, shaped like the paper's tests):
+  plummer_nested  root 128^3 + 2 nested 64^3 levels, 2^20 Plummer particles
+                  (b = 0.05), no gas -- the default and the headline line;
+  root32_gas      single isolated root 32^3, 4096 particles + Gaussian gas blob;
+  clumps          root 64^3 + 256 non-cubic level-1 grids (sides 8..48) on 256
+                  Plummer clumps, 2^21 particles, lognormal masses;
+  plummer_gas     root 256^3 + 2 nested 128^3 levels, 2^22 Plummer particles plus a
+                  lognormal k^-2 random gas field (forward + adjoint);
+  large_nested    root 512^3 + 3 nested 256^3 levels, 2^24 Plummer particles plus two
+                  orbiting point masses; also 100 leapfrog steps and the energy drift.
 
-Prints one JSON line:  value = particles/s of the FP32 step (inputs resident in
-HBM), with cells/s, the FP64 step, errors against the FP64 oracle, the roofline of
-the dominant kernel (HIP events on the library stream, in a second pass of the
-same steps) and the oracle timed on the host as the CPU baseline.
+Prints one JSON line: value = particles/s of the FP32 forward step (inputs resident in
+HBM), with cells/s, the forward+adjoint step, the FP64 steps, errors against the FP64
+oracle, the roofline of the dominant kernel (HIP events on the library stream) and the
+oracle timed on the host as the CPU baseline.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload plummer_nested]
+                    [--no-cpu-baseline] [--no-fp64] [--no-adjoint]
 """
 
 import argparse
@@ -35,13 +45,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(plan, npart_level, esize):
-    """Algorithmic HBM bytes per step of each kernel name (what the method must
-    move at least once; c = complex bytes = 2 esize)."""
+def kernel_bytes(plan, npart, npart_level, esize):
+    """Algorithmic HBM bytes per step of each kernel name: what the method must move
+    at least once (c = complex bytes = 2 esize)."""
     c = 2 * esize
-    b = {k: 0.0 for k in ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
-                          "deposit_tiles", "deposit_finalize", "compose", "interp", "bin_count",
-                          "bin_scatter")}
+    names = ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv", "deposit_tiles",
+             "deposit_finalize", "compose", "interp", "bin_count", "bin_scatter", "adj_fft_x",
+             "adj_fft_y", "adj_fft_z", "adj_fft_y_inv", "adj_fft_x_inv", "adj_interp",
+             "adj_deposit_grid", "adj_deposit_particles", "adj_restrict")
+    b = {k: 0.0 for k in names}
     for g in plan.grids:
         gx, gy, gz = g["gmf_n"]
         fx, fy, fz = g["fld_n"]
@@ -53,17 +65,58 @@ def kernel_bytes(plan, npart_level, esize):
         b["fft_z_conv"] += gz * My * W * c + oct_ * c + 3 * fz * My * W * c
         b["fft_y_inv"] += 3 * fz * My * W * c + 4 * fz * fy * W * c
         b["fft_x_inv"] += 4 * fz * fy * W * c + fx * fy * fz * 4 * esize
+        # the transposed passes move the same arrays in the other direction; their
+        # field-box input is the FP64 cotangent
+        b["adj_fft_x"] += fx * fy * fz * 4 * 8 + 4 * fz * fy * W * c
+        b["adj_fft_y"] += 4 * fz * fy * W * c + 3 * fz * My * W * c
+        b["adj_fft_z"] += 3 * fz * My * W * c + oct_ * c + gz * My * W * c
+        b["adj_fft_y_inv"] += gz * My * W * c + gz * gy * W * c
+        b["adj_fft_x_inv"] += gy * gz * W * c + gx * gy * gz * esize
         b["deposit_finalize"] += gx * gy * gz * (8 + esize)     # FP64 mass in, GMF out
+        b["adj_deposit_grid"] += gx * gy * gz * (esize + 8)     # GMF cotangent in, FP64 out
         if g["level"] > 0:      # own field read and rewritten in place, parent at 1/8 density
             b["compose"] += fx * fy * fz * 4 * esize * (2 + 1 / 8)
-    for n in npart_level:
-        b["deposit_tiles"] += n * 4 * esize            # sorted (s_x, s_y, s_z, m) records
-    n = npart_level[0]
+            b["adj_restrict"] += fx * fy * fz * 4 * 8 * (1 + 2 / 8)
+    binned = sum(npart_level)
+    for nb in npart_level:
+        b["deposit_tiles"] += nb * 4 * esize           # sorted (x/dx, y/dx, z/dx, m) records
+        b["adj_deposit_particles"] += nb * (4 * esize + 8 + 4 * 8)
     nl = len(plan.levels)
-    b["bin_count"] = n * 3 * esize + nl * n * 8       # positions in once, key + rank per level
-    b["bin_scatter"] = nl * n * (4 * esize + 8) + sum(npart_level) * (4 * esize + 4)
-    b["interp"] = n * (3 * esize + 4 + 4 * esize)     # positions + owner in, a + Phi out
+    b["bin_count"] = npart * 3 * esize + nl * npart * 8      # positions once, key + rank per level
+    b["bin_scatter"] = nl * npart * (4 * esize + 8) + binned * (4 * esize + 8)
+    b["interp"] = binned * (4 * esize + 8) + npart * 4 * esize   # sorted records in, a + Phi out
+    b["adj_interp"] = binned * (4 * esize + 8) + npart * (esize + 3 * 8)
     return b
+
+
+WORKLOADS = {
+    "plummer_nested": ("plummer_nested: root 128^3 + 2 nested 64^3 levels, 2^20 Plummer "
+                       "particles (b=0.05), no gas"),
+    "root32_gas": ("root32_gas: single isolated root 32^3, 4096 particles uniform in the "
+                   "central half-box + Gaussian gas blob (sigma 0.1, mass 1)"),
+    "clumps": ("clumps: root 64^3 + 256 level-1 grids, sides uniform in [8,48] per axis "
+               "(non-cubic, centred on clumps, may overlap), 2^21 particles in 256 Plummer "
+               "clumps (b=0.01), lognormal masses"),
+    "plummer_gas": ("plummer_gas: root 256^3 + 2 nested 128^3 levels, 2^22 Plummer particles "
+                    "(b=0.05) + lognormal k^-2 random gas field"),
+    "large_nested": ("large_nested: root 512^3 (1024^3 padded FFT) + 3 nested 256^3 levels, "
+                     "2^24 Plummer particles (b=0.02) + 2 orbiting point masses m=0.1"),
+}
+
+
+def make_workload(name):
+    import apm_workloads as W
+    if name == "plummer_nested":
+        return W.workload_plummer_nested()
+    if name == "root32_gas":
+        return W.workload_root32_uniform_gas()
+    if name == "clumps":
+        return W.workload_clumps()
+    if name == "plummer_gas":
+        return W.workload_plummer_gas()
+    if name == "large_nested":
+        return W.workload_large_nested()
+    raise ValueError(name)
 
 
 def main():
@@ -71,8 +124,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plummer_nested", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--leapfrog-steps", type=int, default=100,
+                    help="KDK steps timed for large_nested (energy drift)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB a few times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -95,33 +152,45 @@ def main():
                           "launches": 5}))
         return
 
-    import apm_workloads as W
     from paper_1410_0010_amd import Context, Plan
 
-    w = W.workload_plummer_nested()
+    w = make_workload(args.workload)
     plan = Plan(w.root_n, w.grids)
     ctx = Context(plan, 0)
     active = w.active_cells()
-    log(f"workload {w.name}: {w.npart} particles, {len(w.grids)} grids, {active} active cells")
+    n = w.npart
+    log(f"workload {w.name}: {n} particles, {len(w.grids)} grids, {active} active cells")
+    fp64_ok = not args.no_fp64 and args.workload != "large_nested"
+    do_adj = not args.no_adjoint
 
     def tens(dtype):
-        return [torch.from_numpy(np.ascontiguousarray(a.astype(dtype))).to(dev)
+        return [torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype))).to(dev)
                 for a in (w.x, w.y, w.z, w.m)]
+
+    def gas_for(tdt):
+        g = [ctx.pack_gas(l, w.gas, tdt) for l in range(plan.nlevels)]
+        return g if any(v is not None for v in g) else None
 
     tuned = {}
 
-    def run(dtype, steps, warmup, profile=False):
+    def run(dtype, steps, warmup, adjoint=False, profile=False):
         x, y, z, m = tens(dtype)
-        n = w.npart
+        gas = gas_for(x.dtype)
         out = [torch.empty(n, dtype=x.dtype, device=dev) for _ in range(4)]
-        tot = None
-        ctx.solve(x, y, z, m, None, *out)
+        grads = None
+        ctx.solve(x, y, z, m, gas, *out)
         torch.cuda.synchronize()
         if x.dtype not in tuned:
             tuned[x.dtype] = ctx.autotune(x.dtype, reps=5)
+
+        def step():
+            ctx.solve(x, y, z, m, gas, *out)
+            tot = ctx.solve_totals(m, *out, gas=gas)
+            g = ctx.solve_adjoint(x, y, z, m, gas, out[3], wbar=1.0) if adjoint else None
+            return tot, g
+
         for _ in range(warmup):
-            ctx.solve(x, y, z, m, None, *out)
-            tot = ctx.solve_totals(m, *out)
+            step()
         torch.cuda.synchronize()
         if profile:
             ctx.profile(True)
@@ -131,8 +200,7 @@ def main():
         t0 = time.perf_counter()
         s0.record()
         for _ in range(steps):
-            ctx.solve(x, y, z, m, None, *out)
-            tot = ctx.solve_totals(m, *out)
+            tot, grads = step()
         s1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -141,35 +209,46 @@ def main():
         if profile:
             ctx.profile(False)
             prof = ctx.profile_read()
-        acc = np.stack([o.cpu().numpy().astype(np.float64) for o in out[:3]], 1)
-        return dict(ms=ms, wall_ms=1000 * wall / steps, totals=tot, acc=acc,
-                    pot=out[3].cpu().numpy().astype(np.float64), prof=prof)
+        res = dict(ms=ms, wall_ms=1000 * wall / steps, totals=tot, prof=prof,
+                   acc=np.stack([o.cpu().numpy().astype(np.float64) for o in out[:3]], 1),
+                   pot=out[3].cpu().numpy().astype(np.float64))
+        if grads is not None:
+            res["gx"] = np.stack([t.cpu().numpy().astype(np.float64) for t in grads[:3]], 1)
+            res["gm"] = grads[3].cpu().numpy().astype(np.float64)
+        return res
 
-    log(f"FP32: warmup {args.warmup}, {args.steps} timed steps")
+    log(f"FP32 forward: warmup {args.warmup}, {args.steps} timed steps")
     r32 = run(np.float32, args.steps, args.warmup)
-    log(f"FP32: {r32['ms']:.3f} ms/step")
+    log(f"FP32 forward: {r32['ms']:.3f} ms/step")
+    a32 = a64 = r64 = None
+    if do_adj:
+        a32 = run(np.float32, args.steps, 1, adjoint=True)
+        log(f"FP32 forward+adjoint: {a32['ms']:.3f} ms/step")
     log("FP32: profiled pass (HIP events around every kernel)")
-    p32 = run(np.float32, args.steps, 1, profile=True)
-    r64 = None
-    if not args.no_fp64:
+    psteps = max(3, args.steps // 4)
+    p32 = run(np.float32, psteps, 1, adjoint=do_adj, profile=True)
+    if fp64_ok:
         r64 = run(np.float64, args.steps, args.warmup)
-        log(f"FP64: {r64['ms']:.3f} ms/step")
+        log(f"FP64 forward: {r64['ms']:.3f} ms/step")
+        if do_adj:
+            a64 = run(np.float64, args.steps, 1, adjoint=True)
+            log(f"FP64 forward+adjoint: {a64['ms']:.3f} ms/step")
 
-    # dominant kernel of the FP32 step and its roofline
+    # per-kernel times of the FP32 step, the dominant forward kernel and its roofline
     npl = []
+    pos = np.stack([w.x, w.y, w.z], 1)
     for l in range(plan.nlevels):
-        # particles binned on level l: those whose cell lies in the level's binning box
         lo = np.array([min(g["gmf_lo"][a] for g in plan.level_grids(l)) - 1 for a in range(3)])
         hi = np.array([max(g["gmf_lo"][a] + g["gmf_n"][a] for g in plan.level_grids(l)) + 1
                        for a in range(3)])
-        inv = 1.0 / plan.levels[l]["dx"]
-        cx = np.floor(np.stack([w.x, w.y, w.z], 1) * inv)
-        npl.append(int(np.all((cx >= lo) & (cx < hi), axis=1).sum()))
-    kb = kernel_bytes(plan, npl, 4)
-    steps = args.steps
-    per_kernel = {k: dict(ms_per_step=v[0] / steps, launches_per_step=v[1] / steps)
+        cx = np.floor(pos * (1.0 / plan.levels[l]["dx"]))
+        inside = np.all((cx >= lo) & (cx < hi), axis=1) & np.all((pos >= 0) & (pos < 1), axis=1)
+        npl.append(int(inside.sum()))
+    kb = kernel_bytes(plan, n, npl, 4)
+    per_kernel = {k: dict(ms_per_step=v[0] / psteps, launches_per_step=v[1] / psteps)
                   for k, v in p32["prof"].items()}
-    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_step"])
+    forward_names = [k for k in per_kernel if not k.startswith("adj")]
+    dom = max(forward_names, key=lambda k: per_kernel[k]["ms_per_step"])
     dom_ms = per_kernel[dom]["ms_per_step"]
     dom_launch_ms = dom_ms / per_kernel[dom]["launches_per_step"]
     achieved = kb.get(dom, 0.0) / (dom_ms * 1e-3) / 1e9
@@ -180,35 +259,84 @@ def main():
         f"{k} {v['ms_per_step'] * 1e3:.1f}us" + (f" {v['gbs']:.0f}GB/s" if 'gbs' in v else "")
         for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1]['ms_per_step'])))
 
+    # leapfrog (large nested run): KDK steps, energy drift
+    lf = None
+    if args.workload == "large_nested" and args.leapfrog_steps > 0:
+        x, y, z, m = tens(np.float32)
+        vx, vy, vz = (torch.from_numpy(np.asarray(v, np.float32)).to(dev)
+                      for v in (w.vx, w.vy, w.vz))
+        r, b = 0.036, 0.02
+        v = np.sqrt(r * (0.1 / (2 * r) ** 2 + r ** 3 / (r * r + b * b) ** 1.5 / r ** 2))
+        h = 2 * np.pi * r / v / 400
+        nst = args.leapfrog_steps
+        pot = torch.empty_like(x)
+        ctx.leapfrog(x, y, z, vx, vy, vz, m, h, 1, pot=pot)      # warm-up and graph capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, _, energy = ctx.leapfrog(x, y, z, vx, vy, vz, m, h, nst, pot=pot)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        drift = float(abs(energy[-1] - energy[0]) / abs(energy[0]))
+        lf = {"steps": nst, "dt": h, "seconds": sec, "ms_per_step": 1000 * sec / nst,
+              "particle_steps_per_s": n * nst / sec, "energy_first": float(energy[0]),
+              "energy_last": float(energy[-1]), "energy_drift": drift,
+              "energy_max_rel_dev": float(np.max(np.abs(energy - energy[0])) / abs(energy[0]))}
+        log(f"leapfrog: {nst} steps, {lf['ms_per_step']:.2f} ms/step, energy drift {drift:.3e}")
+
     # errors against the FP64 oracle and the oracle's own time (CPU baseline)
     cpu = None
     err = {}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload in ("plummer_nested", "root32_gas"):
         from oracle import apm_oracle as O
-        log("oracle: Green's functions (cached, as on the GPU), then one timed forward solve")
+        from oracle import apm_adjoint as A
+        log("oracle: Green's functions (cached, as on the GPU), then one timed forward solve "
+            "and one timed reverse sweep")
         op = O.OraclePlan(w.root_n, w.grids)
         cache = {g.index: O.greens(op, g) for g in op.grids}
-        x32 = [a.astype(np.float32).astype(np.float64) for a in (w.x, w.y, w.z, w.m)]
+        rd = lambda a: None if a is None else np.asarray(a, np.float32).astype(np.float64)
+        x32 = [rd(a) for a in (w.x, w.y, w.z, w.m)]
+        g32 = [rd(a) for a in w.gas]
         t0 = time.perf_counter()
-        ref32 = O.solve(op, *x32, cache=cache)
-        t_or = time.perf_counter() - t0
-        log(f"oracle solve {t_or:.1f} s")
+        ref32 = O.solve(op, *x32, g32, cache=cache)
+        t_fwd = time.perf_counter() - t0
+        t_adj = None
+        if do_adj:
+            t0 = time.perf_counter()
+            adj32 = A.energy_gradient(op, *x32, g32, cache=cache, fwd=ref32)
+            t_adj = time.perf_counter() - t0
+        log(f"oracle forward {t_fwd:.1f} s" + (f", reverse sweep {t_adj:.1f} s" if t_adj else ""))
         own = ref32["owner"] >= 0
         rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
         err["fp32_acc_rel_l2"] = rel(r32["acc"][own], ref32["acc"][own])
         err["fp32_pot_rel_l2"] = rel(r32["pot"][own], ref32["pot"][own])
+        if a32 is not None:
+            err["fp32_grad_x_rel_l2"] = rel(a32["gx"], adj32["x"])
+            err["fp32_grad_m_rel_l2"] = rel(a32["gm"], adj32["m"])
         if r64 is not None:
-            ref64 = O.solve(op, w.x, w.y, w.z, w.m, cache=cache)
+            x64 = [np.asarray(a, np.float64) for a in (w.x, w.y, w.z, w.m)]
+            g64 = [None if a is None else np.asarray(a, np.float64) for a in w.gas]
+            ref64 = O.solve(op, *x64, g64, cache=cache)
             err["fp64_acc_rel_l2"] = rel(r64["acc"][own], ref64["acc"][own])
             err["fp64_pot_rel_l2"] = rel(r64["pot"][own], ref64["pot"][own])
-        cpu = {"value": w.npart / t_or, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            if a64 is not None:
+                adj64 = A.energy_gradient(op, *x64, g64, cache=cache, fwd=ref64)
+                err["fp64_grad_x_rel_l2"] = rel(a64["gx"], adj64["x"])
+                err["fp64_grad_m_rel_l2"] = rel(a64["gm"], adj64["m"])
+        cpu = {"value": n / t_fwd, "unit": "particles/s", "cores": 1, "kind": "oracle",
                "sample": "the full workload, one forward solve (numpy FP64, single thread), "
                          "Green's functions precomputed as on the GPU",
-               "seconds": t_or}
+               "seconds": t_fwd}
+        if t_adj is not None:
+            cpu["fwd_adjoint"] = {"value": n / (t_fwd + t_adj), "unit": "particles/s",
+                                  "seconds": t_fwd + t_adj}
 
-    value = w.npart / (r32["ms"] * 1e-3)
+    value = n / (r32["ms"] * 1e-3)
+    step_info = lambda r: None if r is None else {
+        "particles_per_s": n / (r["ms"] * 1e-3), "cells_per_s": active / (r["ms"] * 1e-3),
+        "ms_per_step": r["ms"]}
     line = {
-        "metric": "particles/s per APM forward solve (+ cells/s, fp32 vs fp64, % HBM peak)",
+        "metric": "particles/s per APM forward solve (+ cells/s, fwd+adjoint, fp32 vs fp64, "
+                  "% HBM peak)",
         "value": value,
         "unit": "particles/s",
         "n_gpus": 1,
@@ -220,19 +348,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "plummer_nested: root 128^3 + 2 nested 64^3 levels, "
-                               "2^20 Plummer particles (b=0.05), no gas",
-                   "particles": w.npart, "active_cells": active, "grids": len(w.grids),
-                   "fft": "256^3 root (doubled, isolated), 128^3 subgrids",
+        "config": {"workload": WORKLOADS[args.workload],
+                   "particles": n, "active_cells": active, "grids": len(w.grids),
+                   "fft_dims_first_grids": [g["fft_n"] for g in plan.grids[:4]],
                    "gradient": "spectral"},
         "cells_per_s": active / (r32["ms"] * 1e-3),
-        "fp64": None if r64 is None else {
-            "particles_per_s": w.npart / (r64["ms"] * 1e-3),
-            "cells_per_s": active / (r64["ms"] * 1e-3), "ms_per_step": r64["ms"]},
+        "fwd_adjoint_fp32": step_info(a32),
+        "fp64": step_info(r64),
+        "fwd_adjoint_fp64": step_info(a64),
         "error_vs_fp64_oracle": err,
         "totals_fp32": {"mass_per_level": list(r32["totals"][:plan.nlevels]),
                         "energy": r32["totals"][plan.nlevels],
-                        "net_force": list(r32["totals"][plan.nlevels + 1:])},
+                        "net_force": list(r32["totals"][plan.nlevels + 1:plan.nlevels + 4])},
+        "leapfrog_fp32": lf,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_ms": dom_launch_ms,

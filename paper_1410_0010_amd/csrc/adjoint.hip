@@ -52,18 +52,24 @@ hipError_t launch_zero_ranges(const ZeroList& zl, hipStream_t s) {
 
 // ---- interpolation transpose ---------------------------------------------------------
 // Work item = (level, tile, chunk) of the forward deposit.  Entries owned by a grid of
-// the level add w * (abar, phibar + wbar m / 2) to an LDS tile (halo-extended, FP64, 4
-// components) when their owner is the chunk's first owner grid g*, else straight to
-// the field cotangent in HBM; the tile is then added to g*'s field box.  Each owned
+// the level add w * (abar, phibar + wbar m / 2) to an LDS tile (halo-extended, FP64)
+// of their owner grid -- one tile for the chunk's first owner grid with 4 components,
+// or up to 4 grids' tiles with the Phi component alone -- and straight to the field
+// cotangent in HBM when their grid has no tile; each tile is then added to its
+// grid's field box.  Each owned
 // entry also adds its position gradient  sum_f grad w(f) . <F(f), cot>  (F the forward
 // composed field) to the particle's FP64 accumulators (one writer per particle).
 constexpr int kTH3 = 10 * 10 * 10;
 
-template <typename T>
+template <typename T, int NC>
 __global__ void __launch_bounds__(kBlock)
 k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __restrict__ grids) {
-  __shared__ double acc[4 * kTH3];
-  __shared__ int gstar;
+  // NC = 4 components, or 1 when only Phi flows back; then KG = 4 LDS tiles, one per
+  // distinct owner grid of the chunk (overlapping grids of a level share tiles)
+  constexpr int KG = NC == 1 ? 4 : 1;
+  __shared__ double acc[KG * NC * kTH3];
+  __shared__ int gsl[KG];
+  __shared__ int gnext;
   const int lb = batch_of(io.item_blk0, io.nlev, blockIdx.x);
   const DepLevel& L = tab[lb];
   const int32_t total = L.items[L.ntiles];
@@ -77,29 +83,43 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
   const int tile = lo;
   const int64_t begin = L.count[(int64_t)tile * L.rep] + (item - L.items[tile]) * (int64_t)kChunk;
   const int64_t end = min((int64_t)L.count[(int64_t)(tile + 1) * L.rep], begin + kChunk);
-  for (int c = threadIdx.x; c < 4 * kTH3; c += kBlock) acc[c] = 0.0;
-  if (threadIdx.x == 0) gstar = INT32_MAX;
-  __syncthreads();
+  for (int c = threadIdx.x; c < KG * NC * kTH3; c += kBlock) acc[c] = 0.0;
   const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
             oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;
   static_assert(kChunk == 8 * kBlock, "a chunk is eight records per thread");
   int2 ref[8];
+  V4<T> rec[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < 8; ++k) {                      // the chunk's loads first
     const int64_t q = begin + threadIdx.x + (int64_t)k * kBlock;
-    ref[k] = q < end ? load_i2(L.sref, q) : make_int2(0, -1);
-    if (ref[k].y >= 0) atomicMin(&gstar, ref[k].y);
+    const int64_t qc = q < end ? q : begin;          // begin < end: a valid entry
+    ref[k] = load_i2(L.sref, qc);
+    rec[k] = load_v4<T>(L.sorted, qc);
+    if (q >= end) ref[k].y = -1;
   }
-  __syncthreads();
-  const int gs = gstar;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) pin4(rec[k]);
+  // the KG smallest distinct owner grids of the chunk, one round each
+  int prev = -1;
+  for (int r = 0; r < KG; ++r) {
+    if (threadIdx.x == 0) gnext = INT32_MAX;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (ref[k].y > prev) atomicMin(&gnext, ref[k].y);
+    __syncthreads();
+    prev = gnext;
+    if (threadIdx.x == 0) gsl[r] = prev;
+    __syncthreads();
+  }
   const V4<T>* F = io.fld[lb];
   double* fbar = io.fbar[lb];
+  const int c0 = 4 - NC;                            // first component carried
 #pragma unroll 1
   for (int k = 0; k < 8; ++k) {
     if (ref[k].y < 0) continue;
-    const int64_t q = begin + threadIdx.x + (int64_t)k * kBlock;
     const int64_t i = ref[k].x;
-    const V4<T> v = load_v4<T>(L.sorted, q);
+    const V4<T> v = rec[k];
     const double cot[4] = {io.abx ? (double)io.abx[i] : 0.0, io.aby ? (double)io.aby[i] : 0.0,
                            io.abz ? (double)io.abz[i] : 0.0,
                            (io.phib ? (double)io.phib[i] : 0.0) + io.wbar * 0.5 * (double)v.w};
@@ -108,67 +128,100 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
     const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
     const int cx = (int)fx - g.fld_lo[0], cy = (int)fy - g.fld_lo[1], cz = (int)fz - g.fld_lo[2];
     const int nx = g.fld_n[0], ny = g.fld_n[1], nz = g.fld_n[2];
-    const bool local = ref[k].y == gs;
+    int slot = -1;                                  // LDS tile of this particle's grid
+#pragma unroll
+    for (int r = 0; r < KG; ++r)
+      if (gsl[r] == ref[k].y) slot = r;
+    const bool local = slot >= 0;
     // cell relative to the tile origin (always inside the tile; clamped defensively)
     const int ix = min(max((int)fx - L.key_lo[0] - ox, 0), kTile - 1),
               iy = min(max((int)fy - L.key_lo[1] - oy, 0), kTile - 1),
               iz = min(max((int)fz - L.key_lo[2] - oz, 0), kTile - 1);
+    // per-axis cells (clamped into the box, weight 0 outside: all 27 loads issue
+    // together) and weights
+    int ax_[3], ay_[3], az_[3];
+    double wx[3], wy[3], wz[3], dwx[3], dwy[3], dwz[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
+      const bool ox_ = (xx >= 0) & (xx < nx), oy_ = (yy >= 0) & (yy < ny), oz_ = (zz >= 0) & (zz < nz);
+      ax_[d] = ox_ ? xx : 0; ay_[d] = oy_ ? yy : 0; az_[d] = oz_ ? zz : 0;
+      wx[d] = ox_ ? (double)tsc_w_a(d - 1, tx) : 0.0;
+      wy[d] = oy_ ? (double)tsc_w_a(d - 1, ty) : 0.0;
+      wz[d] = oz_ ? (double)tsc_w_a(d - 1, tz) : 0.0;
+      dwx[d] = ox_ ? (double)tsc_dw_a(d - 1, tx) : 0.0;
+      dwy[d] = oy_ ? (double)tsc_dw_a(d - 1, ty) : 0.0;
+      dwz[d] = oz_ ? (double)tsc_dw_a(d - 1, tz) : 0.0;
+    }
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int zz = cz + dz;
-      const double wz = tsc_w_a(dz, tz), dwz = tsc_dw_a(dz, tz);
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int yy = cy + dy;
-        const double wy = tsc_w_a(dy, ty), dwy = tsc_dw_a(dy, ty);
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int xx = cx + dx;
-          if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
-          const double wx = tsc_w_a(dx, tx), dwx = tsc_dw_a(dx, tx);
-          const int64_t cell = g.fld_offset + ((int64_t)zz * ny + yy) * nx + xx;
-          const V4<T> f = F[cell];
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+      V4<T> f9[9];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+          f9[3 * dy + dx] = F[g.fld_offset + ((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]];
+#pragma unroll
+      for (int k9 = 0; k9 < 9; ++k9) pin4(f9[k9]);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const V4<T>& f = f9[3 * dy + dx];
           const double s = cot[0] * f.x + cot[1] * f.y + cot[2] * f.z + cot[3] * f.w;
-          gx += dwx * wy * wz * s;
-          gy += wx * dwy * wz * s;
-          gz += wx * wy * dwz * s;
-          const double w = wx * wy * wz;
+          gx += dwx[dx] * wy[dy] * wz[dz] * s;
+          gy += wx[dx] * dwy[dy] * wz[dz] * s;
+          gz += wx[dx] * wy[dy] * dwz[dz] * s;
+        }
+      }
+    }
+    // scatter of the cotangent (skipped components are zero for every particle)
+#pragma unroll 1
+    for (int dz = 0; dz < 3; ++dz) {
+      for (int dy = 0; dy < 3; ++dy) {
+        for (int dx = 0; dx < 3; ++dx) {
+          const double w = wx[dx] * wy[dy] * wz[dz];
+          if (w == 0.0) continue;
           if (local) {
-            double* a = acc + 4 * (((iz + dz + 1) * 10 + (iy + dy + 1)) * 10 + (ix + dx + 1));
-            atomicAdd(a + 0, w * cot[0]);
-            atomicAdd(a + 1, w * cot[1]);
-            atomicAdd(a + 2, w * cot[2]);
-            atomicAdd(a + 3, w * cot[3]);
+            double* a = acc + NC * ((slot * 10 + iz + dz) * 100 + (iy + dy) * 10 + (ix + dx));
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) atomicAdd(a + cc, w * cot[c0 + cc]);
           } else {
-            double* a = fbar + 4 * cell;
-            atomicAdd(a + 0, w * cot[0]);
-            atomicAdd(a + 1, w * cot[1]);
-            atomicAdd(a + 2, w * cot[2]);
-            atomicAdd(a + 3, w * cot[3]);
+            double* a = fbar + 4 * (g.fld_offset + ((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]);
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) atomicAdd(a + c0 + cc, w * cot[c0 + cc]);
           }
         }
       }
     }
     const double inv = 1.0 / g.dx;
-    io.pacc[1][i] += gx * inv;
-    io.pacc[2][i] += gy * inv;
-    io.pacc[3][i] += gz * inv;
+    double* pi = io.pint + 4 * i;                   // one writer: the owner level's entry
+    pi[0] = gx * inv;
+    pi[1] = gy * inv;
+    pi[2] = gz * inv;
   }
   __syncthreads();
-  if (gs == INT32_MAX) return;                      // no owned entry in this chunk
-  const GridDesc& g = grids[gs];
-  for (int c = threadIdx.x; c < kTH3; c += kBlock) {
-    const double* a = acc + 4 * c;
-    if (a[0] == 0.0 && a[1] == 0.0 && a[2] == 0.0 && a[3] == 0.0) continue;
-    const int lx = c % 10, ly = (c / 10) % 10, lz = c / 100;
-    const int xx = L.key_lo[0] + ox + lx - 1 - g.fld_lo[0];
-    const int yy = L.key_lo[1] + oy + ly - 1 - g.fld_lo[1];
-    const int zz = L.key_lo[2] + oz + lz - 1 - g.fld_lo[2];
-    if (xx < 0 || xx >= g.fld_n[0] || yy < 0 || yy >= g.fld_n[1] || zz < 0 || zz >= g.fld_n[2])
-      continue;                                     // cannot hold weight (owned stencils lie inside)
-    double* f = fbar + 4 * (g.fld_offset + ((int64_t)zz * g.fld_n[1] + yy) * g.fld_n[0] + xx);
-    atomicAdd(f + 0, a[0]);
-    atomicAdd(f + 1, a[1]);
-    atomicAdd(f + 2, a[2]);
-    atomicAdd(f + 3, a[3]);
+  for (int r = 0; r < KG; ++r) {
+    const int gs = gsl[r];
+    if (gs == INT32_MAX) break;                     // no more owner grids in the chunk
+    const GridDesc& g = grids[gs];
+    for (int c = threadIdx.x; c < kTH3; c += kBlock) {
+      const double* a = acc + NC * (r * kTH3 + c);
+      bool any = false;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) any |= a[cc] != 0.0;
+      if (!any) continue;
+      const int lx = c % 10, ly = (c / 10) % 10, lz = c / 100;
+      const int xx = L.key_lo[0] + ox + lx - 1 - g.fld_lo[0];
+      const int yy = L.key_lo[1] + oy + ly - 1 - g.fld_lo[1];
+      const int zz = L.key_lo[2] + oz + lz - 1 - g.fld_lo[2];
+      if (xx < 0 || xx >= g.fld_n[0] || yy < 0 || yy >= g.fld_n[1] || zz < 0 || zz >= g.fld_n[2])
+        continue;                                   // cannot hold weight (owned stencils lie inside)
+      double* f = fbar + 4 * (g.fld_offset + ((int64_t)zz * g.fld_n[1] + yy) * g.fld_n[0] + xx);
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) atomicAdd(f + c0 + cc, a[cc]);
+    }
   }
 }
 
@@ -177,7 +230,10 @@ hipError_t launch_adj_interp(const AdjIO<T>& io, const DepLevel* tab, const Grid
                              hipStream_t s) {
   const int64_t nb = io.item_blk0[io.nlev];
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_adj_interp<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab, grids);
+  if (io.c0 == 3)
+    hipLaunchKernelGGL((k_adj_interp<T, 1>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab, grids);
+  else
+    hipLaunchKernelGGL((k_adj_interp<T, 4>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab, grids);
   return hipGetLastError();
 }
 
@@ -186,10 +242,10 @@ hipError_t launch_adj_interp(const AdjIO<T>& io, const DepLevel* tab, const Grid
 // gas term of W).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_adj_gas_seed(const GridDesc* __restrict__ grids, int32_t ngrids, int32_t first, int32_t count,
-               const int64_t* __restrict__ begin, double root_n, const T* __restrict__ gas,
-               const V4<T>* __restrict__ field, double wbar, double* __restrict__ fbar,
-               double* __restrict__ gas_bar) {
+k_adj_gas_seed(const GridDesc* __restrict__ grids, const OwnerLevel* __restrict__ om, int32_t nlev,
+               int32_t first, int32_t count, const int64_t* __restrict__ begin,
+               const T* __restrict__ gas, const V4<T>* __restrict__ field, double wbar,
+               double* __restrict__ fbar, double* __restrict__ gas_bar) {
   const int64_t b = blockIdx.x;
   int lo = 0, hi = count - 1;
   while (lo < hi) {
@@ -205,19 +261,7 @@ k_adj_gas_seed(const GridDesc* __restrict__ grids, int32_t ngrids, int32_t first
   const int lz = (int)(local / ((int64_t)g.n[0] * g.n[1]));
   const double px = (g.lo[0] + lx + 0.5) * g.dx, py = (g.lo[1] + ly + 0.5) * g.dx,
                pz = (g.lo[2] + lz + 0.5) * g.dx;
-  int best = -1, bestlev = -1;
-  for (int gi = ngrids - 1; gi >= 0; --gi) {
-    const GridDesc& h = grids[gi];
-    if (h.level < bestlev) break;
-    const double inv = root_n * (double)(1 << h.level);
-    const int cx = (int)floor(px * inv), cy = (int)floor(py * inv), cz = (int)floor(pz * inv);
-    if (cx >= h.lo[0] && cx < h.lo[0] + h.n[0] && cy >= h.lo[1] && cy < h.lo[1] + h.n[1] &&
-        cz >= h.lo[2] && cz < h.lo[2] + h.n[2]) {
-      best = gi;
-      bestlev = h.level;
-    }
-  }
-  if (best != first + lo) return;
+  if (owner_lookup(om, nlev, px, py, pz) != first + lo) return;
   const int64_t fc = g.fld_offset + ((int64_t)(g.lo[2] + lz - g.fld_lo[2]) * g.fld_n[1] +
                                      (g.lo[1] + ly - g.fld_lo[1])) * g.fld_n[0] +
                      (g.lo[0] + lx - g.fld_lo[0]);
@@ -227,13 +271,13 @@ k_adj_gas_seed(const GridDesc* __restrict__ grids, int32_t ngrids, int32_t first
 }
 
 template <typename T>
-hipError_t launch_adj_gas_seed(const GridDesc* grids, int32_t ngrids, int32_t first, int32_t count,
-                               const int64_t* begin, int64_t nblocks, double root_n, const T* gas,
-                               const V4<T>* field, double wbar, double* fbar, double* gas_bar,
-                               hipStream_t s) {
+hipError_t launch_adj_gas_seed(const GridDesc* grids, const OwnerLevel* om, int32_t nlev,
+                               int32_t first, int32_t count, const int64_t* begin, int64_t nblocks,
+                               const T* gas, const V4<T>* field, double wbar, double* fbar,
+                               double* gas_bar, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_adj_gas_seed<T>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, grids,
-                     ngrids, first, count, begin, root_n, gas, field, wbar, fbar, gas_bar);
+  hipLaunchKernelGGL((k_adj_gas_seed<T>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, grids, om,
+                     nlev, first, count, begin, gas, field, wbar, fbar, gas_bar);
   return hipGetLastError();
 }
 
@@ -357,9 +401,9 @@ hipError_t launch_adj_deposit_grid(const AdjIO<T>& io, const DepLevel* tab, hipS
 }
 
 // ---- deposit transpose, particle side --------------------------------------------------
-// Entry q of a level's sorted list: mbar += sum_c w(c) A(c), xbar += m sum_c grad w(c)
-// A(c), A the level's key-box cotangent.  Entries of different levels share particles:
-// FP64 atomics into the accumulators.
+// Entry q of a level's sorted list: (sum_c w(c) A(c), m sum_c grad w(c) A(c)), A the
+// level's key-box cotangent, stored in the level's per-particle slot (the levels are
+// summed per particle at the end, so no atomics).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
@@ -373,30 +417,47 @@ k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
   const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
   const int cx = (int)fx - L.key_lo[0], cy = (int)fy - L.key_lo[1], cz = (int)fz - L.key_lo[2];
   const int nx = L.key_n[0], ny = L.key_n[1], nz = L.key_n[2];
-  double sm = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int zz = cz + dz;
-    const double wz = tsc_w_a(dz, tz), dwz = tsc_dw_a(dz, tz);
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int yy = cy + dy;
-      const double wy = tsc_w_a(dy, ty), dwy = tsc_dw_a(dy, ty);
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int xx = cx + dx;
-        if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
-        const double wx = tsc_w_a(dx, tx), dwx = tsc_dw_a(dx, tx);
-        const double a = L.accum[((int64_t)zz * ny + yy) * nx + xx];
-        sm += wx * wy * wz * a;
-        gx += dwx * wy * wz * a;
-        gy += wx * dwy * wz * a;
-        gz += wx * wy * dwz * a;
-      }
-    }
+  int ax_[3], ay_[3], az_[3];
+  double wx[3], wy[3], wz[3], dwx[3], dwy[3], dwz[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
+    const bool ox_ = (xx >= 0) & (xx < nx), oy_ = (yy >= 0) & (yy < ny), oz_ = (zz >= 0) & (zz < nz);
+    ax_[d] = ox_ ? xx : 0; ay_[d] = oy_ ? yy : 0; az_[d] = oz_ ? zz : 0;
+    wx[d] = ox_ ? (double)tsc_w_a(d - 1, tx) : 0.0;
+    wy[d] = oy_ ? (double)tsc_w_a(d - 1, ty) : 0.0;
+    wz[d] = oz_ ? (double)tsc_w_a(d - 1, tz) : 0.0;
+    dwx[d] = ox_ ? (double)tsc_dw_a(d - 1, tx) : 0.0;
+    dwy[d] = oy_ ? (double)tsc_dw_a(d - 1, ty) : 0.0;
+    dwz[d] = oz_ ? (double)tsc_dw_a(d - 1, tz) : 0.0;
   }
+  double a27[27];
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx)
+        a27[(dz * 3 + dy) * 3 + dx] = L.accum[((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]];
+  double sm = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const double a = a27[(dz * 3 + dy) * 3 + dx];
+        sm += wx[dx] * wy[dy] * wz[dz] * a;
+        gx += dwx[dx] * wy[dy] * wz[dz] * a;
+        gy += wx[dx] * dwy[dy] * wz[dz] * a;
+        gz += wx[dx] * wy[dy] * dwz[dz] * a;
+      }
   const double m = (double)v.w * L.inv_dx;
-  atomicAdd(io.pacc[0] + r.x, sm);
-  atomicAdd(io.pacc[1] + r.x, m * gx);
-  atomicAdd(io.pacc[2] + r.x, m * gy);
-  atomicAdd(io.pacc[3] + r.x, m * gz);
+  double* o = io.plev[lb] + 4 * (int64_t)r.x;       // one writer per (level, particle)
+  o[0] = sm;
+  o[1] = m * gx;
+  o[2] = m * gy;
+  o[3] = m * gz;
 }
 
 template <typename T>
@@ -408,27 +469,39 @@ hipError_t launch_adj_deposit_particles(const AdjIO<T>& io, const DepLevel* tab,
 }
 
 // ---- outputs -----------------------------------------------------------------------------
-// xbar = accumulated; mbar = accumulated + wbar Phi_p / 2 on owned particles.
+// mbar, xbar = the sum over the levels the particle was binned on (key >= 0) of the
+// deposit transpose, plus the interpolation transpose's position gradient and
+// wbar Phi_p / 2 (mass) for owned particles.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_adj_finish(AdjIO<T> io, const int32_t* __restrict__ owner, const T* __restrict__ pot,
-             T* __restrict__ xb, T* __restrict__ yb, T* __restrict__ zb, T* __restrict__ mb) {
+k_adj_finish(AdjIO<T> io, const DepLevel* __restrict__ tab, const int32_t* __restrict__ owner,
+             const T* __restrict__ pot, T* __restrict__ xb, T* __restrict__ yb,
+             T* __restrict__ zb, T* __restrict__ mb) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= io.npart) return;
-  double mm = io.pacc[0][i];
-  if (io.wbar != 0.0 && owner[i] >= 0 && pot) mm += io.wbar * 0.5 * (double)pot[i];
-  if (mb) mb[i] = (T)mm;
-  if (xb) xb[i] = (T)io.pacc[1][i];
-  if (yb) yb[i] = (T)io.pacc[2][i];
-  if (zb) zb[i] = (T)io.pacc[3][i];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int l = 0; l < io.nlev; ++l) {
+    if (tab[l].key[i] < 0) continue;
+    const double* o = io.plev[l] + 4 * i;
+    s0 += o[0]; s1 += o[1]; s2 += o[2]; s3 += o[3];
+  }
+  if (owner[i] >= 0) {
+    const double* pi = io.pint + 4 * i;
+    s1 += pi[0]; s2 += pi[1]; s3 += pi[2];
+    if (io.wbar != 0.0 && pot) s0 += io.wbar * 0.5 * (double)pot[i];
+  }
+  if (mb) mb[i] = (T)s0;
+  if (xb) xb[i] = (T)s1;
+  if (yb) yb[i] = (T)s2;
+  if (zb) zb[i] = (T)s3;
 }
 
 template <typename T>
-hipError_t launch_adj_finish(const AdjIO<T>& io, const int32_t* owner, const T* pot, T* xb, T* yb,
-                             T* zb, T* mb, hipStream_t s) {
+hipError_t launch_adj_finish(const AdjIO<T>& io, const DepLevel* tab, const int32_t* owner,
+                             const T* pot, T* xb, T* yb, T* zb, T* mb, hipStream_t s) {
   if (io.npart == 0) return hipSuccess;
   hipLaunchKernelGGL((k_adj_finish<T>), dim3((unsigned)((io.npart + kBlock - 1) / kBlock)),
-                     dim3(kBlock), 0, s, io, owner, pot, xb, yb, zb, mb);
+                     dim3(kBlock), 0, s, io, tab, owner, pot, xb, yb, zb, mb);
   return hipGetLastError();
 }
 
@@ -449,15 +522,15 @@ hipError_t launch_to_t(const double* a, T* b, int64_t n, hipStream_t s) {
 #define APM_INST_A(T)                                                                         \
   template hipError_t launch_adj_interp<T>(const AdjIO<T>&, const DepLevel*, const GridDesc*,   \
                                            hipStream_t);                                       \
-  template hipError_t launch_adj_gas_seed<T>(const GridDesc*, int32_t, int32_t, int32_t,       \
-                                             const int64_t*, int64_t, double, const T*,        \
-                                             const V4<T>*, double, double*, double*,           \
+  template hipError_t launch_adj_gas_seed<T>(const GridDesc*, const OwnerLevel*, int32_t,       \
+                                             int32_t, int32_t, const int64_t*, int64_t,        \
+                                             const T*, const V4<T>*, double, double*, double*, \
                                              hipStream_t);                                     \
   template hipError_t launch_adj_deposit_grid<T>(const AdjIO<T>&, const DepLevel*, hipStream_t); \
   template hipError_t launch_adj_deposit_particles<T>(const AdjIO<T>&, const DepLevel*,        \
                                                       hipStream_t);                            \
-  template hipError_t launch_adj_finish<T>(const AdjIO<T>&, const int32_t*, const T*, T*, T*,   \
-                                           T*, T*, hipStream_t);                                \
+  template hipError_t launch_adj_finish<T>(const AdjIO<T>&, const DepLevel*, const int32_t*,    \
+                                           const T*, T*, T*, T*, T*, hipStream_t);              \
   template hipError_t launch_to_t<T>(const double*, T*, int64_t, hipStream_t);
 APM_INST_A(float)
 APM_INST_A(double)

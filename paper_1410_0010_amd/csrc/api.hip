@@ -33,6 +33,7 @@ struct apm_ctx_s {
   GridDesc* d_grids = nullptr;
   std::vector<int64_t*> d_dep_begin, d_cmp_begin, d_act_begin;     // per level: first block
   std::vector<int64_t> dep_blocks, cmp_blocks, act_blocks;         // of each grid, and total
+  OwnerLevel* d_owner_map = nullptr;                               // owner lookup per level
   std::vector<int64_t*> d_foot_begin;                              // restriction footprints
   std::vector<int64_t> foot_blocks;
   // reverse sweep: FP64 field and gas cotangents per level, GMF cotangents by dtype,
@@ -326,7 +327,7 @@ int pass_axis(int pass) {
 const char* pass_name(int pass) {
   static const char* n[] = {"fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
                             "adj_fft_x",  "adj_fft_y",  "adj_fft_z",  "adj_fft_y_inv",
-                            "adj_fft_x_inv"};
+                            "adj_fft_x_inv", "adj_fft_x",  "adj_fft_y",  "adj_fft_z"};
   return n[pass];
 }
 
@@ -598,8 +599,8 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
   APM_TRY(ensure(c, c->owner, (size_t)std::max<int64_t>(npart, 1) * 4, "owner"));
   int32_t* own = (int32_t*)c->owner.p;
   HIP_TRY(timed(c, "owner", [&] {
-            return launch_owner<T>(c->d_grids, (int32_t)P.grids.size(), (double)P.cfg.root_n, x, y,
-                                   z, npart, own, ax, ay, az, pot, c->stream);
+            return launch_owner<T>(c->d_owner_map, (int32_t)P.levels.size(), x, y, z, npart, own,
+                                   ax, ay, az, pot, c->stream);
           }), "owner");
   {
     const T* gl[kMaxLevels];
@@ -793,9 +794,9 @@ apm_status gas_energy_levels_t(apm_ctx c, const void* const* gas, const V4<T>* c
   for (size_t l = 0; l < P.levels.size(); ++l) {
     if (!gas || !gas[l]) continue;
     const LevelDesc& L = P.levels[l];
-    HIP_TRY(launch_gas_energy<T>(c->d_grids, (int32_t)P.grids.size(), L.first, L.count,
-                                 c->d_act_begin[l], c->act_blocks[l], (double)P.cfg.root_n,
-                                 (const T*)gas[l], fields[l], (double*)c->gpart.p, dev, c->stream),
+    HIP_TRY(launch_gas_energy<T>(c->d_grids, c->d_owner_map, (int32_t)P.levels.size(), L.first,
+                                 L.count, c->d_act_begin[l], c->act_blocks[l], (const T*)gas[l],
+                                 fields[l], (double*)c->gpart.p, dev, c->stream),
             "gas energy");
   }
   return APM_OK;
@@ -883,7 +884,9 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
       APM_TRY(ensure(c, c->adj_gas[l], (size_t)std::max<int64_t>(P.levels[l].gas_elems, 1) * 8,
                      "gas cotangents"));
   }
-  APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * 32, "particle cotangents"));
+  // per particle, 4 FP64 each: the interpolation transpose's slot and one per level
+  APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * 32 * (nl + 1),
+                 "particle cotangents"));
   ZeroList zl{};
   hipError_t zerr = hipSuccess;
   auto add = [&](void* p, int64_t cnt) {            // cleared in batches of up to 48 ranges
@@ -900,9 +903,11 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
   io.npart = n;
   io.wbar = wbar;
   io.abx = abx; io.aby = aby; io.abz = abz; io.phib = phib;
+  const bool pot_only = !abx && !aby && !abz;       // the Phi cotangent alone flows back
+  io.c0 = pot_only ? 3 : 0;
   double* pacc = (double*)c->adj_pacc.p;
-  for (int k = 0; k < 4; ++k) io.pacc[k] = pacc + (int64_t)k * n;
-  add(pacc, 4 * n);
+  io.pint = pacc;
+  for (int l = 0; l < nl; ++l) io.plev[l] = pacc + 4 * (int64_t)n * (l + 1);
   int64_t iblk = 0, fblk = 0, pblk = 0;
   const int64_t nbp = (n + kBlock - 1) / kBlock;
   for (int l = 0; l < nl; ++l) {
@@ -935,9 +940,9 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
       if (!gas[l]) continue;
       const LevelDesc& L = P.levels[l];
       HIP_TRY(timed(c, "adj_gas_seed", [&] {
-                return launch_adj_gas_seed<T>(c->d_grids, (int32_t)P.grids.size(), L.first, L.count,
-                                              c->d_act_begin[l], c->act_blocks[l],
-                                              (double)P.cfg.root_n, (const T*)gas[l], io.fld[l],
+                return launch_adj_gas_seed<T>(c->d_grids, c->d_owner_map, (int32_t)P.levels.size(),
+                                              L.first, L.count, c->d_act_begin[l],
+                                              c->act_blocks[l], (const T*)gas[l], io.fld[l],
                                               wbar, io.fbar[l], io.gas_bar[l], c->stream);
               }), "gas energy seeds");
     }
@@ -960,7 +965,9 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
     ap.gmf[l] = (T*)c->adj_gmf[di][l].p;
     ap.fbar[l] = io.fbar[l];
   }
-  for (int pass = PASS_AX; pass <= PASS_AXI; ++pass) {
+  const int seq_full[5] = {PASS_AX, PASS_AY, PASS_AZ, PASS_AYI, PASS_AXI};
+  const int seq_pot[5] = {PASS_APX, PASS_APY, PASS_APZ, PASS_AYI, PASS_AXI};
+  for (int pass : pot_only ? seq_pot : seq_full) {
     for (int L : pass_lengths(c, pass, -1)) {
       const int nlines = lines_for<T>(c, pass, L);
       const apm_ctx_s::JobList* jl = nullptr;
@@ -980,7 +987,8 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
             return launch_adj_deposit_particles<T>(io, tab, c->stream);
           }), "deposit transpose (particles)");
   HIP_TRY(timed(c, "adj_finish", [&] {
-            return launch_adj_finish<T>(io, (const int32_t*)c->owner.p, pot, xb, yb, zb, mb, c->stream);
+            return launch_adj_finish<T>(io, tab, (const int32_t*)c->owner.p, pot, xb, yb, zb, mb,
+                                        c->stream);
           }), "adjoint outputs");
   if (gas_bar) {
     for (int l = 0; l < nl; ++l) {
@@ -1061,6 +1069,47 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
     c->cmp_blocks.push_back(cmp.back());
     c->act_blocks.push_back(act.back());
   }
+  // owner lookup: each level's single grid box, or a table of the lowest-index grid
+  // per cell over the bounding box of the level's active boxes
+  std::vector<OwnerLevel> om(P.levels.size());
+  for (size_t l = 0; l < P.levels.size(); ++l) {
+    const LevelDesc& L = P.levels[l];
+    OwnerLevel& o = om[l];
+    o.inv_dx = 1.0 / L.dx;
+    o.table = nullptr;
+    if (L.count == 1) {
+      const GridDesc& g = P.grids[L.first];
+      for (int a = 0; a < 3; ++a) { o.lo[a] = g.lo[a]; o.n[a] = g.n[a]; }
+      o.single = L.first;
+      continue;
+    }
+    o.single = -1;
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) { lo[a] = INT32_MAX; hi[a] = INT32_MIN; }
+    for (int i = 0; i < L.count; ++i) {
+      const GridDesc& g = P.grids[L.first + i];
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], g.lo[a]);
+        hi[a] = std::max(hi[a], g.lo[a] + g.n[a]);
+      }
+    }
+    for (int a = 0; a < 3; ++a) { o.lo[a] = lo[a]; o.n[a] = hi[a] - lo[a]; }
+    std::vector<int32_t> tab((size_t)o.n[0] * o.n[1] * o.n[2], -1);
+    for (int i = L.count - 1; i >= 0; --i) {          // lower indices overwrite
+      const GridDesc& g = P.grids[L.first + i];
+      for (int z = 0; z < g.n[2]; ++z)
+        for (int y = 0; y < g.n[1]; ++y) {
+          const size_t row = ((size_t)(g.lo[2] + z - lo[2]) * o.n[1] + (g.lo[1] + y - lo[1])) * o.n[0];
+          for (int x = 0; x < g.n[0]; ++x) tab[row + g.lo[0] + x - lo[0]] = L.first + i;
+        }
+    }
+    void* d = nullptr;
+    st = upload(c, &d, tab.data(), tab.size() * 4, "owner table");
+    if (st != APM_OK) { apm_destroy(c); return st; }
+    o.table = (const int32_t*)d;
+  }
+  st = upload(c, (void**)&c->d_owner_map, om.data(), om.size() * sizeof(OwnerLevel), "owner map");
+  if (st != APM_OK) { apm_destroy(c); return st; }
   *out = c;
   clear_error();
   return APM_OK;
@@ -1106,12 +1155,12 @@ apm_status apm_owner(apm_ctx c, apm_dtype dt, const void* x, const void* y, cons
   if (npart > 0 && (!x || !y || !z || !owner)) return fail(APM_ERR_INVALID, "apm_owner: NULL array");
   const Plan& P = c->plan;
   hipError_t e = dt == APM_F32
-      ? launch_owner<float>(c->d_grids, (int32_t)P.grids.size(), (double)P.cfg.root_n,
-                            (const float*)x, (const float*)y, (const float*)z, npart, owner,
-                            nullptr, nullptr, nullptr, nullptr, c->stream)
-      : launch_owner<double>(c->d_grids, (int32_t)P.grids.size(), (double)P.cfg.root_n,
-                             (const double*)x, (const double*)y, (const double*)z, npart, owner,
-                             nullptr, nullptr, nullptr, nullptr, c->stream);
+      ? launch_owner<float>(c->d_owner_map, (int32_t)P.levels.size(), (const float*)x,
+                            (const float*)y, (const float*)z, npart, owner, nullptr, nullptr,
+                            nullptr, nullptr, c->stream)
+      : launch_owner<double>(c->d_owner_map, (int32_t)P.levels.size(), (const double*)x,
+                             (const double*)y, (const double*)z, npart, owner, nullptr, nullptr,
+                             nullptr, nullptr, c->stream);
   HIP_TRY(e, "apm_owner");
   return APM_OK;
 }

@@ -26,7 +26,9 @@ template <typename T> struct LevelPtrs {
 // The five transform passes of a grid's convolution, and the five of its transpose
 // (each adjoint pass runs one forward pass backwards, with that pass's launch shape).
 enum { PASS_X_FWD = 0, PASS_Y_FWD = 1, PASS_Z_CONV = 2, PASS_Y_INV = 3, PASS_X_INV = 4,
-       PASS_AX = 5, PASS_AY = 6, PASS_AZ = 7, PASS_AYI = 8, PASS_AXI = 9 };
+       PASS_AX = 5, PASS_AY = 6, PASS_AZ = 7, PASS_AYI = 8, PASS_AXI = 9,
+       // potential-only transposes (zero acceleration cotangents)
+       PASS_APX = 10, PASS_APY = 11, PASS_APZ = 12 };
 // forward pass whose launch shape an adjoint pass shares
 inline int mirror_pass(int pass) {
   switch (pass) {
@@ -35,6 +37,9 @@ inline int mirror_pass(int pass) {
     case PASS_AZ: return PASS_Z_CONV;
     case PASS_AYI: return PASS_Y_FWD;
     case PASS_AXI: return PASS_X_FWD;
+    case PASS_APX: return PASS_X_FWD;
+    case PASS_APY: return PASS_Y_FWD;
+    case PASS_APZ: return PASS_Z_CONV;
   }
   return pass;
 }
@@ -142,10 +147,33 @@ template <typename T> hipError_t launch_deposit_tiles(const DepIO<T>& io, const 
 template <typename T> hipError_t launch_deposit_finalize(const DepIO<T>& io, const DepLevel* tab,
                                                          hipStream_t s);
 
+// Owner lookup (finest grid whose active box holds a point, lowest index on that level):
+// per level either its single grid's active box or, for several grids, a table over
+// the bounding box of their active boxes with the lowest-index grid of every cell.
+struct OwnerLevel {
+  double inv_dx;
+  int32_t lo[3], n[3];             // box (level cells)
+  int32_t single;                  // the grid if the level has one, else -1
+  const int32_t* table;            // n[0] n[1] n[2] grid indices (-1: none), or null
+};
+__device__ __forceinline__ int owner_lookup(const OwnerLevel* __restrict__ om, int nlev, double px,
+                                            double py, double pz) {
+  for (int l = nlev - 1; l >= 0; --l) {
+    const OwnerLevel& o = om[l];
+    const int cx = (int)floor(px * o.inv_dx) - o.lo[0];
+    const int cy = (int)floor(py * o.inv_dx) - o.lo[1];
+    const int cz = (int)floor(pz * o.inv_dx) - o.lo[2];
+    if (cx < 0 || cx >= o.n[0] || cy < 0 || cy >= o.n[1] || cz < 0 || cz >= o.n[2]) continue;
+    const int g = o.single >= 0 ? o.single : o.table[((int64_t)cz * o.n[1] + cy) * o.n[0] + cx];
+    if (g >= 0) return g;
+  }
+  return -1;
+}
+
 // owner grid of every particle; where the outputs are given, particles outside the
 // domain (owner -1) get zero acceleration and potential there
-template <typename T> hipError_t launch_owner(const GridDesc* grids, int32_t ngrids, double root_n,
-                                              const T* x, const T* y, const T* z, int64_t npart,
+template <typename T> hipError_t launch_owner(const OwnerLevel* om, int32_t nlev, const T* x,
+                                              const T* y, const T* z, int64_t npart,
                                               int32_t* owner, T* ax, T* ay, T* az, T* pot,
                                               hipStream_t s);
 template <typename T> hipError_t launch_interp(const GridDesc* grids, int32_t level,
@@ -172,6 +200,7 @@ struct ZeroList {                      // FP64 ranges to clear in one launch
 hipError_t launch_zero_ranges(const ZeroList& zl, hipStream_t s);
 template <typename T> struct AdjIO {
   int32_t nlev;                        // levels of the batch (b = level - first)
+  int32_t c0;                          // first non-zero cotangent component (3: Phi only)
   int64_t npart;
   double wbar;                         // weight of W in the loss
   const T* abx; const T* aby; const T* abz;   // acceleration cotangents (npart)
@@ -184,15 +213,17 @@ template <typename T> struct AdjIO {
   const T* gmf_bar[kMaxLevels];        // GMF cotangents
   double* gas_bar[kMaxLevels];         // own-gas cotangent of the level, or null
   double* pgas_bar[kMaxLevels];        // the parent level's gas cotangent, or null
-  double* pacc[4];                     // per particle, FP64: mbar, xbar, ybar, zbar
+  double* pint;                        // per particle (4 FP64): the interpolation
+                                       // transpose's position gradient (owned particles)
+  double* plev[kMaxLevels];            // per level and particle (4 FP64): the deposit
+                                       // transpose's (mbar, xbar, ybar, zbar) (binned ones)
 };
 template <typename T> hipError_t launch_adj_interp(const AdjIO<T>& io, const DepLevel* tab,
                                                    const GridDesc* grids, hipStream_t s);
-template <typename T> hipError_t launch_adj_gas_seed(const GridDesc* grids, int32_t ngrids,
-                                                     int32_t first, int32_t count,
+template <typename T> hipError_t launch_adj_gas_seed(const GridDesc* grids, const OwnerLevel* om,
+                                                     int32_t nlev, int32_t first, int32_t count,
                                                      const int64_t* begin, int64_t nblocks,
-                                                     double root_n, const T* gas,
-                                                     const V4<T>* field, double wbar,
+                                                     const T* gas, const V4<T>* field, double wbar,
                                                      double* fbar, double* gas_bar,
                                                      hipStream_t s);
 hipError_t launch_adj_restrict(const GridDesc* grids, int32_t first, int32_t count,
@@ -202,9 +233,9 @@ template <typename T> hipError_t launch_adj_deposit_grid(const AdjIO<T>& io, con
                                                          hipStream_t s);
 template <typename T> hipError_t launch_adj_deposit_particles(const AdjIO<T>& io,
                                                               const DepLevel* tab, hipStream_t s);
-template <typename T> hipError_t launch_adj_finish(const AdjIO<T>& io, const int32_t* owner,
-                                                   const T* pot, T* xb, T* yb, T* zb, T* mb,
-                                                   hipStream_t s);
+template <typename T> hipError_t launch_adj_finish(const AdjIO<T>& io, const DepLevel* tab,
+                                                   const int32_t* owner, const T* pot, T* xb,
+                                                   T* yb, T* zb, T* mb, hipStream_t s);
 template <typename T> hipError_t launch_to_t(const double* a, T* b, int64_t n, hipStream_t s);
 
 template <typename T> hipError_t launch_compose(const GridDesc* grids, const int64_t* block_begin,
@@ -231,12 +262,11 @@ template <typename T> hipError_t launch_kick_drift(int64_t n, T* x, T* y, T* z, 
 template <typename T> hipError_t launch_kinetic(const T* m, const T* vx, const T* vy, const T* vz,
                                                 int64_t n, double* part, double* out,
                                                 hipStream_t s);
-template <typename T> hipError_t launch_gas_energy(const GridDesc* grids, int32_t ngrids,
-                                                   int32_t first, int32_t count,
+template <typename T> hipError_t launch_gas_energy(const GridDesc* grids, const OwnerLevel* om,
+                                                   int32_t nlev, int32_t first, int32_t count,
                                                    const int64_t* begin, int64_t nblocks,
-                                                   double root_n, const T* gas,
-                                                   const V4<T>* field, double* part, double* out,
-                                                   hipStream_t s);
+                                                   const T* gas, const V4<T>* field, double* part,
+                                                   double* out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, hipStream_t s);  // one value
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);

@@ -79,9 +79,10 @@ hipError_t launch_kinetic(const T* m, const T* vx, const T* vy, const T* vz, int
 // cell of the level; per-block partials part[b].
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_gas_energy(const GridDesc* __restrict__ grids, int32_t ngrids, int32_t first, int32_t count,
-             const int64_t* __restrict__ begin, double root_n, const T* __restrict__ gas,
-             const V4<T>* __restrict__ field, double* __restrict__ part) {
+k_gas_energy(const GridDesc* __restrict__ grids, const OwnerLevel* __restrict__ om, int32_t nlev,
+             int32_t first, int32_t count, const int64_t* __restrict__ begin,
+             const T* __restrict__ gas, const V4<T>* __restrict__ field,
+             double* __restrict__ part) {
   double e = 0.0;
   const int64_t b = blockIdx.x;
   int gl = 0;                                        // grid of this block within the level
@@ -103,19 +104,7 @@ k_gas_energy(const GridDesc* __restrict__ grids, int32_t ngrids, int32_t first, 
     // owner of the cell centre: finest grid containing it, lowest index on that level
     const double px = (g.lo[0] + lx + 0.5) * g.dx, py = (g.lo[1] + ly + 0.5) * g.dx,
                  pz = (g.lo[2] + lz + 0.5) * g.dx;   // exact: dx is a power of two
-    int best = -1, bestlev = -1;
-    for (int gi = ngrids - 1; gi >= 0; --gi) {
-      const GridDesc& h = grids[gi];
-      if (h.level < bestlev) break;
-      const double inv = root_n * (double)(1 << h.level);
-      const int cx = (int)floor(px * inv), cy = (int)floor(py * inv), cz = (int)floor(pz * inv);
-      if (cx >= h.lo[0] && cx < h.lo[0] + h.n[0] && cy >= h.lo[1] && cy < h.lo[1] + h.n[1] &&
-          cz >= h.lo[2] && cz < h.lo[2] + h.n[2]) {
-        best = gi;
-        bestlev = h.level;
-      }
-    }
-    if (best == first + gl) {
+    if (owner_lookup(om, nlev, px, py, pz) == first + gl) {
       const double rho = (double)gas[g.gas_offset + local];
       const int fx = g.lo[0] + lx - g.fld_lo[0], fy = g.lo[1] + ly - g.fld_lo[1],
                 fz = g.lo[2] + lz - g.fld_lo[2];
@@ -129,12 +118,13 @@ k_gas_energy(const GridDesc* __restrict__ grids, int32_t ngrids, int32_t first, 
 }
 
 template <typename T>
-hipError_t launch_gas_energy(const GridDesc* grids, int32_t ngrids, int32_t first, int32_t count,
-                             const int64_t* begin, int64_t nblocks, double root_n, const T* gas,
-                             const V4<T>* field, double* part, double* out, hipStream_t s) {
+hipError_t launch_gas_energy(const GridDesc* grids, const OwnerLevel* om, int32_t nlev,
+                             int32_t first, int32_t count, const int64_t* begin, int64_t nblocks,
+                             const T* gas, const V4<T>* field, double* part, double* out,
+                             hipStream_t s) {
   if (nblocks == 0 || !gas) return hipSuccess;
-  hipLaunchKernelGGL((k_gas_energy<T>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, grids, ngrids,
-                     first, count, begin, root_n, gas, field, part);
+  hipLaunchKernelGGL((k_gas_energy<T>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, grids, om,
+                     nlev, first, count, begin, gas, field, part);
   return launch_sum_parts(part, (int)nblocks, 1, 1.0, out, s);
 }
 
@@ -143,8 +133,8 @@ hipError_t launch_gas_energy(const GridDesc* grids, int32_t ngrids, int32_t firs
                                            const T*, double, double, hipStream_t);             \
   template hipError_t launch_kinetic<T>(const T*, const T*, const T*, const T*, int64_t,        \
                                         double*, double*, hipStream_t);                         \
-  template hipError_t launch_gas_energy<T>(const GridDesc*, int32_t, int32_t, int32_t,          \
-                                           const int64_t*, int64_t, double, const T*,          \
+  template hipError_t launch_gas_energy<T>(const GridDesc*, const OwnerLevel*, int32_t, int32_t,  \
+                                           int32_t, const int64_t*, int64_t, const T*,         \
                                            const V4<T>*, double*, double*, hipStream_t);
 APM_INST_D(float)
 APM_INST_D(double)

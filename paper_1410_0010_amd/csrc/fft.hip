@@ -350,9 +350,12 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
 
 // ------------------------------------------------------------------ launchers --
 int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], int nl) {
-  pass = mirror_pass(pass);
   const int64_t W = M[0] / 2 + 1;
   const int64_t nbw = (W + nl - 1) / nl;
+  // potential-only transposes: the forward x / y pass shapes over the field box
+  if (pass == PASS_APX) return (((int64_t)f[1] * f[2] + 1) / 2 + nl - 1) / nl;
+  if (pass == PASS_APY) return nbw * f[2];
+  pass = mirror_pass(pass);
   switch (pass) {
     case PASS_X_FWD: return (((int64_t)g[1] * g[2] + 1) / 2 + nl - 1) / nl;
     case PASS_Y_FWD: return nbw * g[2];

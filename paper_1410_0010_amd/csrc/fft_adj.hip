@@ -334,6 +334,159 @@ k_adj_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   }
 }
 
+// ---------------------------------------------- potential-only transposes ------
+// When the acceleration cotangents are all zero (a loss on potentials or on W only)
+// the transposed convolution is the scalar one with Gp: one line per row / column.
+//   apx  field-box rows of the Phi cotangent -> half spectra (y buffer array 0)
+//   apy  columns along y (fy rows at (oy + y) mod L) -> FFT (z buffer array 0)
+//   apz  columns along z (fz planes at (oz + j) mod L) -> FFT -> Gp -> inverse FFT
+//        -> the gz GMF planes; then ayi and axi as above.
+template <typename T, int L>
+__global__ void __launch_bounds__(1024)
+k_adjp_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
+         C2<T>* __restrict__ yb, const C2<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job_a(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int P = J.pitch;
+  const int fx = J.f[0], fy = J.f[1], fz = J.f[2], ox = J.off[0];
+  C2<T>* __restrict__ ybuf = yb + J.y_off;
+  const double* __restrict__ fb = ap.fbar[J.level] + 4 * J.fld_off;
+  const int t = threadIdx.x;
+  const int b = t / (L / 8), w = t % (L / 8);
+  C2<T>* line = lds + b * L;
+  const int64_t rows = (int64_t)fz * fy;
+  const int64_t q = blk * nl + b;
+  const int64_t ra = 2 * q, rb = 2 * q + 1;
+  for (int i = w; i < L; i += L / 8) {
+    const int x = (i - ox) & (L - 1);                // field cell landing at position i
+    T xa = 0, xb = 0;
+    if (x < fx) {
+      if (ra < rows) xa = (T)fb[4 * (ra * fx + x) + 3];
+      if (rb < rows) xb = (T)fb[4 * (rb * fx + x) + 3];
+    }
+    line[i] = mk<T>(xa, xb);
+  }
+  __syncthreads();
+  fft_line<T, L, false>(line, w, tw);
+  if (ra < rows) {
+    C2<T>* outa = ybuf + ra * P;
+    C2<T>* outb = ybuf + rb * P;
+    const T h = (T)0.5;
+    for (int k = w; k <= L / 2; k += L / 8) {
+      const C2<T> z = line[k], m = line[(L - k) & (L - 1)];
+      outa[k] = mk<T>(h * (z.x + m.x), h * (z.y - m.y));
+      if (rb < rows) outb[k] = mk<T>(h * (z.y + m.y), h * (m.x - z.x));
+    }
+  }
+}
+
+template <typename T, int L>
+__global__ void __launch_bounds__(1024)
+k_adjp_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
+         const C2<T>* __restrict__ yb, C2<T>* __restrict__ zb, const C2<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job_a(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1], P = J.pitch;
+  const int fy = J.f[1], oy = J.off[1];
+  const int nbw = (W + nl - 1) / nl;
+  const int j = (int)(blk / nbw);
+  const int c0 = (int)(blk % nbw) * nl;
+  const C2<T>* yin = yb + J.y_off + (int64_t)j * fy * P + c0;
+  C2<T>* zout = zb + J.z_off + (int64_t)j * My * P + c0;
+  const int t = threadIdx.x;
+  const int cb = t % nl, r0 = t / nl;
+  const bool col_ok = c0 + cb < W;
+  C2<T> v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int r = r0 + q * (L / 8);
+    const int y = (r - oy) & (L - 1);
+    v[q] = (col_ok && y < fy) ? yin[(int64_t)y * P + cb] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
+  __syncthreads();
+  const int b = t / (L / 8), w = t % (L / 8);
+  fft_line<T, L, false>(lds + b * ls, w, tw);
+  __syncthreads();
+  if (col_ok) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = r0 + q * (L / 8);
+      zout[(int64_t)k * P + cb] = lds[cb * ls + k];
+    }
+  }
+}
+
+template <typename T, int L>
+__global__ void __launch_bounds__(kZConvMaxThreads)
+k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
+         const C2<T>* __restrict__ zb, C2<T>* __restrict__ specb, const C2<T>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+  const ConvJob& J = jobs[find_job_a(jobs, njobs, gb)];
+  const int64_t blk = gb - J.blk0;
+  const int W = J.M[0] / 2 + 1, My = J.M[1], P = J.pitch;
+  const int gz = J.g[2], fz = J.f[2], oz = J.off[2];
+  const int nbw = (W + nl - 1) / nl;
+  const int ky = (int)(blk / nbw);
+  const int c0 = (int)(blk % nbw) * nl;
+  const C2<T>* zin = zb + J.z_off + (int64_t)ky * P + c0;
+  const int64_t pstride = (int64_t)My * P;
+  C2<T>* spec = specb + J.spec_off + (int64_t)ky * P + c0;
+  const int t = threadIdx.x;
+  const int cb = t % nl, r0 = t / nl;
+  const bool col_ok = c0 + cb < W;
+  const int b = t / (L / 8), w = t % (L / 8);
+  C2<T>* line = lds + b * ls;
+  const int kx = c0 + b;
+  const int kxc = kx < W ? kx : 0;
+  const int Oy = My / 2 + 1;
+  const int kyo = ky <= My / 2 ? ky : My - ky;
+  T gp[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int kz = w + q * (L / 8);
+    const int kzo = kz <= L / 2 ? kz : L - kz;
+    gp[q] = load_c2<T>(J.kern, ((int64_t)kzo * Oy + kyo) * W + kxc).y;
+  }
+  {
+    C2<T> v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = r0 + q * (L / 8);
+      const int jz = (r - oz) & (L - 1);
+      v[q] = (col_ok && jz < fz) ? zin[(int64_t)jz * pstride + cb] : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
+  }
+  __syncthreads();
+  fft_line<T, L, false>(line, w, tw);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const C2<T> X = line[w + q * (L / 8)];
+    line[w + q * (L / 8)] = mk<T>(gp[q] * X.x, gp[q] * X.y);
+  }
+  __syncthreads();
+  fft_line<T, L, true>(line, w, tw);
+  __syncthreads();
+  if (col_ok) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int z = r0 + q * (L / 8);
+      if (z < gz) spec[z * pstride + cb] = lds[cb * ls + z];
+    }
+  }
+}
+
 #define APM_ADJ_DISPATCH(Lv, ...)                            \
   switch (Lv) {                                              \
     case 16: { constexpr int LL = 16; __VA_ARGS__; } break;   \
@@ -376,6 +529,17 @@ hipError_t launch_adj_pass(int pass, int L, int nl, const ConvJob* jobs, int njo
       case PASS_AXI:
         hipLaunchKernelGGL((k_adj_x_inv<T, LL>), grid, block, shm, s, jobs, njobs, nl, ap,
                            (const C2<T>*)spec, twc);
+        break;
+      case PASS_APX:
+        hipLaunchKernelGGL((k_adjp_x<T, LL>), grid, block, shm, s, jobs, njobs, nl, ap, ybuf, twc);
+        break;
+      case PASS_APY:
+        hipLaunchKernelGGL((k_adjp_y<T, LL>), grid, block, shm, s, jobs, njobs, nl, ls,
+                           (const C2<T>*)ybuf, zbuf, twc);
+        break;
+      case PASS_APZ:
+        hipLaunchKernelGGL((k_adjp_z<T, LL>), grid, block, shm, s, jobs, njobs, nl, ls,
+                           (const C2<T>*)zbuf, spec, twc);
         break;
       default:
         return hipErrorInvalidValue;

@@ -463,29 +463,14 @@ hipError_t launch_deposit_finalize(const DepIO<T>& io, const DepLevel* tab, hipS
 
 // ---- owner grid -------------------------------------------------------------------
 template <typename T>
-__global__ void k_owner(const GridDesc* __restrict__ grids, int32_t ngrids, double root_n,
-                        const T* __restrict__ x, const T* __restrict__ y, const T* __restrict__ z,
-                        int64_t npart, int32_t* __restrict__ owner, T* __restrict__ ax,
-                        T* __restrict__ ay, T* __restrict__ az, T* __restrict__ pot) {
+__global__ void k_owner(const OwnerLevel* __restrict__ om, int32_t nlev, const T* __restrict__ x,
+                        const T* __restrict__ y, const T* __restrict__ z, int64_t npart,
+                        int32_t* __restrict__ owner, T* __restrict__ ax, T* __restrict__ ay,
+                        T* __restrict__ az, T* __restrict__ pot) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npart) return;
   const T px = x[i], py = y[i], pz = z[i];
-  int32_t best = -1;
-  if (in_domain(px, py, pz)) {
-    int bestlev = -1;
-    for (int gi = ngrids - 1; gi >= 0; --gi) {
-      const GridDesc& g = grids[gi];
-      if (g.level < bestlev) break;
-      const double inv = root_n * (double)(1 << g.level);
-      const int cx = (int)floor((double)px * inv), cy = (int)floor((double)py * inv),
-                cz = (int)floor((double)pz * inv);
-      if (cx >= g.lo[0] && cx < g.lo[0] + g.n[0] && cy >= g.lo[1] && cy < g.lo[1] + g.n[1] &&
-          cz >= g.lo[2] && cz < g.lo[2] + g.n[2]) {
-        best = gi;
-        bestlev = g.level;
-      }
-    }
-  }
+  const int32_t best = in_domain(px, py, pz) ? owner_lookup(om, nlev, px, py, pz) : -1;
   owner[i] = best;
   if (best < 0 && ax) {
     ax[i] = 0; ay[i] = 0; az[i] = 0;
@@ -494,13 +479,12 @@ __global__ void k_owner(const GridDesc* __restrict__ grids, int32_t ngrids, doub
 }
 
 template <typename T>
-hipError_t launch_owner(const GridDesc* grids, int32_t ngrids, double root_n, const T* x,
-                        const T* y, const T* z, int64_t npart, int32_t* owner, T* ax, T* ay, T* az,
-                        T* pot, hipStream_t s) {
+hipError_t launch_owner(const OwnerLevel* om, int32_t nlev, const T* x, const T* y, const T* z,
+                        int64_t npart, int32_t* owner, T* ax, T* ay, T* az, T* pot, hipStream_t s) {
   if (npart == 0) return hipSuccess;
   const unsigned nb = (unsigned)((npart + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_owner<T>), dim3(nb), dim3(kBlock), 0, s, grids, ngrids, root_n, x, y, z,
-                     npart, owner, ax, ay, az, pot);
+  hipLaunchKernelGGL((k_owner<T>), dim3(nb), dim3(kBlock), 0, s, om, nlev, x, y, z, npart, owner,
+                     ax, ay, az, pot);
   return hipGetLastError();
 }
 
@@ -579,8 +563,8 @@ hipError_t launch_interp_sorted(const InterpIO<T>& io, const DepLevel* tab, cons
   template hipError_t launch_bin_scatter<T>(const DepIO<T>&, const DepLevel*, hipStream_t);    \
   template hipError_t launch_deposit_tiles<T>(const DepIO<T>&, const DepLevel*, hipStream_t);  \
   template hipError_t launch_deposit_finalize<T>(const DepIO<T>&, const DepLevel*, hipStream_t); \
-  template hipError_t launch_owner<T>(const GridDesc*, int32_t, double, const T*, const T*,     \
-                                      const T*, int64_t, int32_t*, T*, T*, T*, T*, hipStream_t); \
+  template hipError_t launch_owner<T>(const OwnerLevel*, int32_t, const T*, const T*, const T*, \
+                                      int64_t, int32_t*, T*, T*, T*, T*, hipStream_t);          \
   template hipError_t launch_interp_sorted<T>(const InterpIO<T>&, const DepLevel*,              \
                                               const GridDesc*, hipStream_t);                    \
   template hipError_t launch_interp<T>(const GridDesc*, int32_t, const V4<T>*, const T*,       \
