@@ -1020,6 +1020,20 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
   c->plan = plan->plan;
   c->device = device;
   c->stream = (hipStream_t)stream;
+  {
+    // transform kernels may use up to the device's LDS per workgroup (once per
+    // process and device, before any launch or capture)
+    static std::vector<int> lds_done;
+    if (std::find(lds_done.begin(), lds_done.end(), device) == lds_done.end()) {
+      hipError_t e = allow_lds_forward();
+      if (e == hipSuccess) e = allow_lds_adjoint();
+      if (e != hipSuccess) {
+        apm_destroy(c);
+        return hip_fail(e, "apm_create: LDS limit");
+      }
+      lds_done.push_back(device);
+    }
+  }
   const Plan& P = c->plan;
   apm_status st = upload(c, (void**)&c->d_grids, P.grids.data(), sizeof(GridDesc) * P.grids.size(),
                          "grid table");

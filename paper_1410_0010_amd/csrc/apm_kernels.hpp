@@ -63,6 +63,9 @@ struct ConvJob {
 int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], int nl);
 template <typename T> int default_lines(int pass, int L);
 constexpr int kZConvMaxThreads = 512;     // keeps the FP64 z passes free of spills
+constexpr int kMaxLDS = 163840;           // dynamic LDS per workgroup on gfx950
+hipError_t allow_lds_forward();           // raise every transform kernel's LDS limit
+hipError_t allow_lds_adjoint();
 template <typename T> size_t pass_lds(int pass, int L, int nl);   // 0: not launchable
 template <typename T> int pass_row_stride(int pass, int L, int nl); // LDS line stride
 int pass_threads(int pass, int L, int nl);

@@ -56,7 +56,7 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
   C2<T>* __restrict__ spec = specb + J.spec_off;
   const int t = threadIdx.x;
   const int b = t / (L / 8), w = t % (L / 8);
-  C2<T>* line = lds + b * L;
+  C2<T>* line = lds + b * line_stride(L);
   const int64_t rows = (int64_t)gy * gz;
   const int64_t q = blk * nl + b;
   const int64_t ra = 2 * q, rb = 2 * q + 1;
@@ -66,7 +66,7 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
       if (ra < rows) xa = gmf[ra * gx + i];
       if (rb < rows) xb = gmf[rb * gx + i];
     }
-    line[i] = mk<T>(xa, xb);
+    line[swz<L>(i)] = mk<T>(xa, xb);
   }
   __syncthreads();
   fft_line<T, L, false>(line, w, tw);
@@ -76,7 +76,7 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
     C2<T>* outb = spec + (zb * My + yb) * P;
     const T h = (T)0.5;
     for (int k = w; k <= L / 2; k += L / 8) {
-      C2<T> z = line[k], m = line[(L - k) & (L - 1)];
+      C2<T> z = line[swz<L>(k)], m = line[swz<L>((L - k) & (L - 1))];
       outa[k] = mk<T>(h * (z.x + m.x), h * (z.y - m.y));
       if (rb < rows) outb[k] = mk<T>(h * (z.y + m.y), h * (m.x - z.x));
     }
@@ -111,7 +111,7 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
     v[q] = (r < gy && col_ok) ? base[(int64_t)r * P + cb] : mk<T>(0, 0);
   }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
+  for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
   __syncthreads();
   const int b = t / (L / 8), w = t % (L / 8);
   fft_line<T, L, false>(lds + b * ls, w, tw);
@@ -120,7 +120,7 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int j = r0 + q * (L / 8);
-      base[(int64_t)j * P + cb] = lds[cb * ls + j];
+      base[(int64_t)j * P + cb] = lds[cb * ls + swz<L>(j)];
     }
   }
 }
@@ -165,7 +165,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       v[q] = (z < gz && col_ok) ? src[z * pstride] : mk<T>(0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
+    for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
   }
   __syncthreads();
   const int b = t / (L / 8), w = t % (L / 8);
@@ -188,7 +188,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   fft_line<T, L, false>(line, w, tw);
   C2<T> X[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) X[q] = line[w + q * (L / 8)];
+  for (int q = 0; q < 8; ++q) X[q] = line[swz<L>(w + q * (L / 8))];
   for (int s = 0; s < 3; ++s) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -196,7 +196,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       if (s == 0) v = mk<T>(gf[q] * X[q].x, gf[q] * X[q].y);
       else if (s == 1) v = mk<T>(gz_[q] * X[q].y, -gz_[q] * X[q].x);   // -i d_z Gf X
       else v = mk<T>(gp[q] * X[q].x, gp[q] * X[q].y);
-      line[w + q * (L / 8)] = v;
+      line[swz<L>(w + q * (L / 8))] = v;
     }
     __syncthreads();
     fft_line<T, L, true>(line, w, tw);
@@ -206,7 +206,8 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       for (int q = 0; q < 8; ++q) {
         const int j = r0 + q * (L / 8);
         if (j < fz)
-          zo[((int64_t)(s * fz + j) * My + ky) * P + c0 + cb] = lds[cb * ls + ((oz + j) & (L - 1))];
+          zo[((int64_t)(s * fz + j) * My + ky) * P + c0 + cb] =
+              lds[cb * ls + swz<L>((oz + j) & (L - 1))];
       }
     }
     __syncthreads();
@@ -254,10 +255,11 @@ k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   for (int q = 0; q < 2; ++q) {
     const int r = r0 + q * (L / 2);
     const T d = dys[r];
-    lds[(0 * nl + cb) * ls + r] = v[q][0];
-    lds[(1 * nl + cb) * ls + r] = mk<T>(d * v[q][0].y, -d * v[q][0].x);   // -i d_y Gf rho
-    lds[(2 * nl + cb) * ls + r] = v[q][1];
-    lds[(3 * nl + cb) * ls + r] = v[q][2];
+    const int rs = swz<L>(r);
+    lds[(0 * nl + cb) * ls + rs] = v[q][0];
+    lds[(1 * nl + cb) * ls + rs] = mk<T>(d * v[q][0].y, -d * v[q][0].x);   // -i d_y Gf rho
+    lds[(2 * nl + cb) * ls + rs] = v[q][1];
+    lds[(3 * nl + cb) * ls + rs] = v[q][2];
   }
   __syncthreads();
   const int b = t / (L / 8), w = t % (L / 8);
@@ -270,7 +272,7 @@ k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       if (jj < fy) {
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-          yout[c * ys + (int64_t)jj * P + cb] = lds[(c * nl + cb) * ls + ((oy + jj) & (L - 1))];
+          yout[c * ys + (int64_t)jj * P + cb] = lds[(c * nl + cb) * ls + swz<L>((oy + jj) & (L - 1))];
       }
     }
   }
@@ -307,7 +309,8 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
   const int64_t q = blk * G + b / 4;
   const int c = b & 3;
   const int64_t ra = 2 * q, rb = 2 * q + 1;
-  C2<T>* line = lds + b * L;
+  constexpr int LS = line_stride(L);
+  C2<T>* line = lds + b * LS;
   if (ra < rows) {
     const int64_t cs = (int64_t)c * rows * P;         // component stride
     const C2<T>* A = ybuf + cs + ra * P;
@@ -322,10 +325,10 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
         bq = mk<T>(d * bq.y, -d * bq.x);
       }
       if (k == 0 || k == L / 2) { a.y = 0; bq.y = 0; }
-      line[i] = i <= L / 2 ? mk<T>(a.x - bq.y, a.y + bq.x) : mk<T>(a.x + bq.y, bq.x - a.y);
+      line[swz<L>(i)] = i <= L / 2 ? mk<T>(a.x - bq.y, a.y + bq.x) : mk<T>(a.x + bq.y, bq.x - a.y);
     }
   } else {
-    for (int i = w; i < L; i += L / 8) line[i] = mk<T>(0, 0);
+    for (int i = w; i < L; i += L / 8) line[swz<L>(i)] = mk<T>(0, 0);
   }
   __syncthreads();
   fft_line<T, L, true>(line, w, tw);
@@ -335,13 +338,13 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
     const int half = rem / fx, x = rem % fx;
     const int64_t r = 2 * (blk * G + gg) + half;
     if (r < rows) {
-      const int xi = (ox + x) & (L - 1);
-      const C2<T>* L0 = lds + (4 * gg) * L + xi;
+      const int xi = swz<L>((ox + x) & (L - 1));
+      const C2<T>* L0 = lds + (4 * gg) * LS + xi;
       V4<T> o;
       if (half == 0) {
-        o.x = L0[0].x; o.y = L0[L].x; o.z = L0[2 * L].x; o.w = L0[3 * L].x;
+        o.x = L0[0].x; o.y = L0[LS].x; o.z = L0[2 * LS].x; o.w = L0[3 * LS].x;
       } else {
-        o.x = L0[0].y; o.y = L0[L].y; o.z = L0[2 * L].y; o.w = L0[3 * L].y;
+        o.x = L0[0].y; o.y = L0[LS].y; o.z = L0[2 * LS].y; o.w = L0[3 * LS].y;
       }
       field[r * fx + x] = o;
     }
@@ -379,17 +382,12 @@ static int pass_lines_per_block(int pass, int nl) {
   return mirror_pass(pass) == PASS_Y_INV ? 4 * nl : nl;
 }
 
-// LDS row stride: padded by one element where the load is column-wise, unless the
-// padding would not fit in 64 KB
+// LDS line stride: line_stride(L) for every pass (the swizzled layout).
 template <typename T> static int pass_ls(int pass, int L, int nl) {
-  pass = mirror_pass(pass);
-  const bool strided = pass == PASS_Y_FWD || pass == PASS_Z_CONV || pass == PASS_Y_INV;
-  if (!strided) return L;
-  const size_t padded = (size_t)pass_lines_per_block(pass, nl) * (L + 1) * sizeof(C2<T>);
-  return padded <= 65536 ? L + 1 : L;
+  (void)pass; (void)nl;
+  return line_stride(L);
 }
 
-// LDS bytes of a launch; 0 if the shape is not launchable (threads or LDS)
 template <typename T> int pass_row_stride(int pass, int L, int nl) { return pass_ls<T>(pass, L, nl); }
 int pass_threads(int pass, int L, int nl) { return pass_lines_per_block(pass, nl) * (L / 8); }
 
@@ -399,7 +397,7 @@ template <typename T> size_t pass_lds(int pass, int L, int nl) {
   const int lines = pass_lines_per_block(pass, nl);
   const size_t bytes = (size_t)lines * pass_ls<T>(pass, L, nl) * sizeof(C2<T>);
   const int max_threads = pass == PASS_Z_CONV ? kZConvMaxThreads : 1024;
-  if (lines * (L / 8) > max_threads || bytes > 65536) return 0;
+  if (lines * (L / 8) > max_threads || bytes > (size_t)kMaxLDS) return 0;
   if (pass == PASS_X_INV && (nl % 4) != 0) return 0;
   return bytes;
 }
@@ -459,6 +457,30 @@ template size_t pass_lds<float>(int, int, int);
 template size_t pass_lds<double>(int, int, int);
 template int pass_row_stride<float>(int, int, int);
 template int pass_row_stride<double>(int, int, int);
+// Every transform kernel may use up to kMaxLDS bytes of dynamic LDS (the gfx950 limit
+// per workgroup); set once per process, before any launch or graph capture.
+template <typename T, int L> static hipError_t allow_lds_fwd() {
+  const void* f[] = {(const void*)&k_fft_x_fwd<T, L>, (const void*)&k_fft_y_fwd<T, L>,
+                     (const void*)&k_fft_z_conv<T, L>, (const void*)&k_fft_y_inv<T, L>,
+                     (const void*)&k_fft_x_inv<T, L>};
+  for (const void* k : f) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLDS);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t allow_lds_forward() {
+  hipError_t e = hipSuccess;
+#define APM_ALLOW(LL)                                                         \
+  if (e == hipSuccess) e = allow_lds_fwd<float, LL>();                         \
+  if (e == hipSuccess) e = allow_lds_fwd<double, LL>();
+  APM_ALLOW(16) APM_ALLOW(32) APM_ALLOW(64) APM_ALLOW(128) APM_ALLOW(256) APM_ALLOW(512)
+  APM_ALLOW(1024)
+#undef APM_ALLOW
+  return e;
+}
+
 template hipError_t launch_pass<float>(int, int, int, const ConvJob*, int, int64_t,
                                        const LevelPtrs<float>&, C2<float>*, C2<float>*,
                                        C2<float>*, const void*, hipStream_t);

@@ -62,7 +62,8 @@ k_adj_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   const int t = threadIdx.x;
   const int b = t / (L / 8), w = t % (L / 8);
   const int64_t rows = (int64_t)fz * fy;
-  for (int i = t; i < nl * L; i += nt) lds[i] = mk<T>(0, 0);
+  constexpr int LS = line_stride(L);
+  for (int i = t; i < nl * LS; i += nt) lds[i] = mk<T>(0, 0);
   __syncthreads();
   for (int idx = t; idx < G * 2 * fx; idx += nt) {
     const int gg = idx / (2 * fx), rem = idx % (2 * fx);
@@ -70,17 +71,17 @@ k_adj_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
     const int64_t r = 2 * (blk * G + gg) + half;
     if (r < rows) {
       const double* cell = fb + 4 * (r * fx + x);
-      const int xi = (ox + x) & (L - 1);
-      C2<T>* L0 = lds + (4 * gg) * L + xi;
+      const int xi = swz<L>((ox + x) & (L - 1));
+      C2<T>* L0 = lds + (4 * gg) * LS + xi;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        if (half == 0) L0[c * L].x = (T)cell[c];
-        else L0[c * L].y = (T)cell[c];
+        if (half == 0) L0[c * LS].x = (T)cell[c];
+        else L0[c * LS].y = (T)cell[c];
       }
     }
   }
   __syncthreads();
-  C2<T>* line = lds + b * L;
+  C2<T>* line = lds + b * LS;
   fft_line<T, L, false>(line, w, tw);
   const int64_t q = blk * G + b / 4;
   const int c = b & 3;
@@ -91,7 +92,7 @@ k_adj_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
     C2<T>* outb = ybuf + cs + rb * P;
     const T h = (T)0.5;
     for (int k = w; k <= L / 2; k += L / 8) {
-      const C2<T> z = line[k], m = line[(L - k) & (L - 1)];
+      const C2<T> z = line[swz<L>(k)], m = line[swz<L>((L - k) & (L - 1))];
       C2<T> A = mk<T>(h * (z.x + m.x), h * (z.y - m.y));
       C2<T> B = mk<T>(h * (z.y + m.y), h * (m.x - z.x));
       if (c == 0) {
@@ -143,7 +144,7 @@ k_adj_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const int r = r0 + q * (L / 2);
+    const int r = swz<L>(r0 + q * (L / 2));
 #pragma unroll
     for (int a = 0; a < 4; ++a) lds[(a * nl + cb) * ls + r] = v[q][a];
   }
@@ -155,12 +156,13 @@ k_adj_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int k = r0 + q * (L / 2);
+      const int ks = swz<L>(k);
       const T d = dys[k];
-      const C2<T> X0 = lds[(0 * nl + cb) * ls + k], X1 = lds[(1 * nl + cb) * ls + k];
+      const C2<T> X0 = lds[(0 * nl + cb) * ls + ks], X1 = lds[(1 * nl + cb) * ls + ks];
       const C2<T> U = cadd(X0, mul_id<T>(d, X1));
       zout[(int64_t)k * P + cb] = U;
-      zout[zs + (int64_t)k * P + cb] = lds[(2 * nl + cb) * ls + k];
-      zout[2 * zs + (int64_t)k * P + cb] = lds[(3 * nl + cb) * ls + k];
+      zout[zs + (int64_t)k * P + cb] = lds[(2 * nl + cb) * ls + ks];
+      zout[2 * zs + (int64_t)k * P + cb] = lds[(3 * nl + cb) * ls + ks];
     }
   }
 }
@@ -220,12 +222,12 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       v[q] = (col_ok && jz < fz) ? zin[s * zs + (int64_t)jz * pstride + cb] : mk<T>(0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
+    for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
     __syncthreads();
     fft_line<T, L, false>(line, w, tw);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const C2<T> X = line[w + q * (L / 8)];
+      const C2<T> X = line[swz<L>(w + q * (L / 8))];
       if (s == 0) S[q] = cadd(S[q], mk<T>(gf[q] * X.x, gf[q] * X.y));
       else if (s == 1) S[q] = cadd(S[q], mul_id<T>(gf[q] * dz[q], X));
       else S[q] = cadd(S[q], mk<T>(gp[q] * X.x, gp[q] * X.y));
@@ -233,7 +235,7 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
     __syncthreads();                                 // the line is reloaded next
   }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) line[w + q * (L / 8)] = S[q];
+  for (int q = 0; q < 8; ++q) line[swz<L>(w + q * (L / 8))] = S[q];
   __syncthreads();
   fft_line<T, L, true>(line, w, tw);
   __syncthreads();                                   // stores use another mapping
@@ -241,7 +243,7 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int z = r0 + q * (L / 8);
-      if (z < gz) spec[z * pstride + cb] = lds[cb * ls + z];
+      if (z < gz) spec[z * pstride + cb] = lds[cb * ls + swz<L>(z)];
     }
   }
 }
@@ -273,7 +275,7 @@ k_adj_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
     v[q] = col_ok ? base[(int64_t)r * P + cb] : mk<T>(0, 0);
   }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
+  for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
   __syncthreads();
   const int b = t / (L / 8), w = t % (L / 8);
   fft_line<T, L, true>(lds + b * ls, w, tw);
@@ -282,7 +284,7 @@ k_adj_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int r = r0 + q * (L / 8);
-      if (r < gy) base[(int64_t)r * P + cb] = lds[cb * ls + r];
+      if (r < gy) base[(int64_t)r * P + cb] = lds[cb * ls + swz<L>(r)];
     }
   }
 }
@@ -305,7 +307,7 @@ k_adj_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   T* __restrict__ out = ap.gmf[J.level] + J.gmf_off;
   const int t = threadIdx.x;
   const int b = t / (L / 8), w = t % (L / 8);
-  C2<T>* line = lds + b * L;
+  C2<T>* line = lds + b * line_stride(L);
   const int64_t rows = (int64_t)gy * gz;
   const int64_t q = blk * nl + b;
   const int64_t ra = 2 * q, rb = 2 * q + 1;
@@ -318,16 +320,16 @@ k_adj_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
       const int k = i <= L / 2 ? i : L - i;
       C2<T> a = A[k], bq = hb ? B[k] : mk<T>(0, 0);
       if (k == 0 || k == L / 2) { a.y = 0; bq.y = 0; }
-      line[i] = i <= L / 2 ? mk<T>(a.x - bq.y, a.y + bq.x) : mk<T>(a.x + bq.y, bq.x - a.y);
+      line[swz<L>(i)] = i <= L / 2 ? mk<T>(a.x - bq.y, a.y + bq.x) : mk<T>(a.x + bq.y, bq.x - a.y);
     }
   } else {
-    for (int i = w; i < L; i += L / 8) line[i] = mk<T>(0, 0);
+    for (int i = w; i < L; i += L / 8) line[swz<L>(i)] = mk<T>(0, 0);
   }
   __syncthreads();
   fft_line<T, L, true>(line, w, tw);
   if (ra < rows) {
     for (int x = w; x < gx; x += L / 8) {
-      const C2<T> v = line[x];
+      const C2<T> v = line[swz<L>(x)];
       out[ra * gx + x] = v.x;
       if (rb < rows) out[rb * gx + x] = v.y;
     }
@@ -356,7 +358,7 @@ k_adjp_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   const double* __restrict__ fb = ap.fbar[J.level] + 4 * J.fld_off;
   const int t = threadIdx.x;
   const int b = t / (L / 8), w = t % (L / 8);
-  C2<T>* line = lds + b * L;
+  C2<T>* line = lds + b * line_stride(L);
   const int64_t rows = (int64_t)fz * fy;
   const int64_t q = blk * nl + b;
   const int64_t ra = 2 * q, rb = 2 * q + 1;
@@ -367,7 +369,7 @@ k_adjp_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
       if (ra < rows) xa = (T)fb[4 * (ra * fx + x) + 3];
       if (rb < rows) xb = (T)fb[4 * (rb * fx + x) + 3];
     }
-    line[i] = mk<T>(xa, xb);
+    line[swz<L>(i)] = mk<T>(xa, xb);
   }
   __syncthreads();
   fft_line<T, L, false>(line, w, tw);
@@ -376,7 +378,7 @@ k_adjp_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
     C2<T>* outb = ybuf + rb * P;
     const T h = (T)0.5;
     for (int k = w; k <= L / 2; k += L / 8) {
-      const C2<T> z = line[k], m = line[(L - k) & (L - 1)];
+      const C2<T> z = line[swz<L>(k)], m = line[swz<L>((L - k) & (L - 1))];
       outa[k] = mk<T>(h * (z.x + m.x), h * (z.y - m.y));
       if (rb < rows) outb[k] = mk<T>(h * (z.y + m.y), h * (m.x - z.x));
     }
@@ -410,7 +412,7 @@ k_adjp_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
     v[q] = (col_ok && y < fy) ? yin[(int64_t)y * P + cb] : mk<T>(0, 0);
   }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
+  for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
   __syncthreads();
   const int b = t / (L / 8), w = t % (L / 8);
   fft_line<T, L, false>(lds + b * ls, w, tw);
@@ -419,7 +421,7 @@ k_adjp_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int k = r0 + q * (L / 8);
-      zout[(int64_t)k * P + cb] = lds[cb * ls + k];
+      zout[(int64_t)k * P + cb] = lds[cb * ls + swz<L>(k)];
     }
   }
 }
@@ -466,14 +468,15 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       v[q] = (col_ok && jz < fz) ? zin[(int64_t)jz * pstride + cb] : mk<T>(0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) lds[cb * ls + r0 + q * (L / 8)] = v[q];
+    for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
   }
   __syncthreads();
   fft_line<T, L, false>(line, w, tw);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const C2<T> X = line[w + q * (L / 8)];
-    line[w + q * (L / 8)] = mk<T>(gp[q] * X.x, gp[q] * X.y);
+    const int k = swz<L>(w + q * (L / 8));
+    const C2<T> X = line[k];
+    line[k] = mk<T>(gp[q] * X.x, gp[q] * X.y);
   }
   __syncthreads();
   fft_line<T, L, true>(line, w, tw);
@@ -482,7 +485,7 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int z = r0 + q * (L / 8);
-      if (z < gz) spec[z * pstride + cb] = lds[cb * ls + z];
+      if (z < gz) spec[z * pstride + cb] = lds[cb * ls + swz<L>(z)];
     }
   }
 }
@@ -546,6 +549,29 @@ hipError_t launch_adj_pass(int pass, int L, int nl, const ConvJob* jobs, int njo
     }
   });
   return hipGetLastError();
+}
+
+template <typename T, int L> static hipError_t allow_lds_adj() {
+  const void* f[] = {(const void*)&k_adj_x<T, L>, (const void*)&k_adj_y<T, L>,
+                     (const void*)&k_adj_z<T, L>, (const void*)&k_adj_y_inv<T, L>,
+                     (const void*)&k_adj_x_inv<T, L>, (const void*)&k_adjp_x<T, L>,
+                     (const void*)&k_adjp_y<T, L>, (const void*)&k_adjp_z<T, L>};
+  for (const void* k : f) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLDS);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t allow_lds_adjoint() {
+  hipError_t e = hipSuccess;
+#define APM_ALLOW(LL)                                                         \
+  if (e == hipSuccess) e = allow_lds_adj<float, LL>();                         \
+  if (e == hipSuccess) e = allow_lds_adj<double, LL>();
+  APM_ALLOW(16) APM_ALLOW(32) APM_ALLOW(64) APM_ALLOW(128) APM_ALLOW(256) APM_ALLOW(512)
+  APM_ALLOW(1024)
+#undef APM_ALLOW
+  return e;
 }
 
 template hipError_t launch_adj_pass<float>(int, int, int, const ConvJob*, int, int64_t,
