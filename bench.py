@@ -50,7 +50,8 @@ def kernel_bytes(plan, npart, npart_level, esize):
     at least once (c = complex bytes = 2 esize)."""
     c = 2 * esize
     names = ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv", "deposit_tiles",
-             "deposit_finalize", "compose", "interp", "bin_count", "bin_scatter", "adj_fft_x",
+             "deposit_finalize", "compose", "interp", "unpack", "bin_count", "bin_scatter",
+             "adj_fft_x",
              "adj_fft_y", "adj_fft_z", "adj_fft_y_inv", "adj_fft_x_inv", "adj_interp",
              "adj_deposit_grid", "adj_deposit_particles", "adj_restrict")
     b = {k: 0.0 for k in names}
@@ -85,6 +86,7 @@ def kernel_bytes(plan, npart, npart_level, esize):
     b["bin_count"] = npart * 3 * esize + nl * npart * 8      # positions once, key + rank per level
     b["bin_scatter"] = nl * npart * (4 * esize + 8) + binned * (4 * esize + 8)
     b["interp"] = binned * (4 * esize + 8) + npart * 4 * esize   # sorted records in, a + Phi out
+    b["unpack"] = npart * (4 * esize + 4 + 4 * esize)   # (a, Phi) records + owner in, 4 arrays out
     b["adj_interp"] = binned * (4 * esize + 8) + npart * (esize + 3 * 8)
     return b
 

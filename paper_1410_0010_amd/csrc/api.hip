@@ -45,7 +45,7 @@ struct apm_ctx_s {
   std::map<std::tuple<int, int, int>, void*> dsym;                // (dtype, level, M)
   std::map<std::tuple<int, int, int, int, int>, void*> kern;      // (dtype, level, Mx, My, Mz)
   std::vector<void*> owned;                                       // every table allocation
-  DevBuf spec, zbuf, ybuf, tmpfld, owner, totals, binned, gpart, energy, lf_pot;
+  DevBuf spec, zbuf, ybuf, pres, owner, totals, binned, gpart, energy, lf_pot;
   // per level: tile counters, work items, FP64 mass grid, particle keys/ranks, the
   // tile-sorted records and their original indices
   struct LevelBufs { DevBuf count, items, accum, key, rank, sref, sorted; };
@@ -600,7 +600,7 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
   int32_t* own = (int32_t*)c->owner.p;
   HIP_TRY(timed(c, "owner", [&] {
             return launch_owner<T>(c->d_owner_map, (int32_t)P.levels.size(), x, y, z, npart, own,
-                                   ax, ay, az, pot, c->stream);
+                                   (T*)nullptr, (T*)nullptr, (T*)nullptr, (T*)nullptr, c->stream);
           }), "owner");
   {
     const T* gl[kMaxLevels];
@@ -638,10 +638,14 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
     io.fld[l] = (const V4<T>*)c->fld[di][l].p;
   }
   io.blk0[nl] = nl * nbp;
-  io.ax = ax; io.ay = ay; io.az = az; io.pot = pot;
+  APM_TRY(ensure(c, c->pres, (size_t)std::max<int64_t>(npart, 1) * sizeof(V4<T>), "particle results"));
+  io.res = (V4<T>*)c->pres.p;
   HIP_TRY(timed(c, "interp", [&] {
             return launch_interp_sorted<T>(io, (const DepLevel*)c->dep_tab.p, c->d_grids, c->stream);
           }), "interp");
+  HIP_TRY(timed(c, "unpack", [&] {
+            return launch_unpack<T>(io.res, own, npart, ax, ay, az, pot, c->stream);
+          }), "unpack");
   return APM_OK;
 }
 
@@ -1137,7 +1141,7 @@ apm_status apm_destroy(apm_ctx c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* p : c->owned) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-  DevBuf* bufs[] = {&c->spec, &c->zbuf, &c->ybuf, &c->tmpfld, &c->owner, &c->totals,
+  DevBuf* bufs[] = {&c->spec, &c->zbuf, &c->ybuf, &c->pres, &c->owner, &c->totals,
                     &c->binned, &c->dep_tab, &c->gpart, &c->energy, &c->lf_pot};
   for (auto& B : c->lvb)
     for (DevBuf* b : {&B.count, &B.items, &B.accum, &B.key, &B.rank, &B.sref, &B.sorted})
