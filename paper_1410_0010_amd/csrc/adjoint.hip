@@ -72,17 +72,12 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
   __shared__ int gnext;
   const int lb = batch_of(io.item_blk0, io.nlev, blockIdx.x);
   const DepLevel& L = tab[lb];
-  const int32_t total = L.items[L.ntiles];
   const int64_t item = blockIdx.x - io.item_blk0[lb];
+  const int32_t total = L.items[L.ntiles];
+  const int4 wk = L.work[item];                     // in the table's room; read with the count
   if (item >= total) return;                        // uniform for the block
-  int lo = 0, hi = L.ntiles - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (L.items[mid] <= item) lo = mid; else hi = mid - 1;
-  }
-  const int tile = lo;
-  const int64_t begin = L.count[(int64_t)tile * L.rep] + (item - L.items[tile]) * (int64_t)kChunk;
-  const int64_t end = min((int64_t)L.count[(int64_t)(tile + 1) * L.rep], begin + kChunk);
+  const int tile = wk.x;
+  const int64_t begin = wk.y, end = wk.z;
   for (int c = threadIdx.x; c < KG * NC * kTH3; c += kBlock) acc[c] = 0.0;
   const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
             oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;

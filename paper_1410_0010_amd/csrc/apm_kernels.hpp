@@ -115,6 +115,8 @@ struct DepLevel {
   int32_t* count;                  // ntiles * rep + 1; replica r of tile t at t rep + r;
                                    // scanned in place into start offsets
   int32_t* items;                  // ntiles + 1: scanned work-item counts
+  int4* work;                      // work item -> (tile, first entry, end entry, 0); room
+                                   // for ntiles + ceil(npart / kChunk) items
   int32_t* key;                    // npart: counter slot or -1
   int32_t* rank;                   // npart: rank within the slot
   int2* sref;                      // sorted position -> (original index, owner grid if

@@ -285,6 +285,17 @@ __global__ void __launch_bounds__(kScanThreads) k_bin_scan(const DepLevel* __res
   }
   __syncthreads();
   block_scan_inplace(L.items, (int64_t)nt + 1, sh);
+  __syncthreads();
+  // the work table: item -> its tile and entry range, so a deposit block needs one
+  // load to find its work instead of a search over the tiles
+  for (int32_t t = (int32_t)threadIdx.x; t < nt; t += kScanThreads) {
+    const int32_t i0 = L.items[t], i1 = L.items[t + 1];
+    const int32_t b0 = L.count[(int64_t)t * rep], e0 = L.count[(int64_t)(t + 1) * rep];
+    for (int32_t k = i0; k < i1; ++k) {
+      const int32_t b = b0 + (k - i0) * kChunk;
+      L.work[k] = make_int4(t, b, min(e0, b + kChunk), 0);
+    }
+  }
   if (threadIdx.x == 0) *L.binned = total;
 }
 
@@ -345,17 +356,12 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
   __shared__ double acc[kTH * kTH * kTH];
   const int lb = batch_level(io.item_blk0, io.nlev, blockIdx.x);
   const DepLevel& L = tab[lb];
-  const int32_t total = L.items[L.ntiles];
   const int64_t item = blockIdx.x - io.item_blk0[lb];
+  const int32_t total = L.items[L.ntiles];
+  const int4 wk = L.work[item];                     // in the table's room; read with the count
   if (item >= total) return;                        // uniform for the block
-  int lo = 0, hi = L.ntiles - 1;                    // last tile with item start <= item
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (L.items[mid] <= item) lo = mid; else hi = mid - 1;
-  }
-  const int tile = lo;
-  const int64_t begin = L.count[(int64_t)tile * L.rep] + (item - L.items[tile]) * (int64_t)kChunk;
-  const int64_t end = min((int64_t)L.count[(int64_t)(tile + 1) * L.rep], begin + kChunk);
+  const int tile = wk.x;
+  const int64_t begin = wk.y, end = wk.z;
   for (int c = threadIdx.x; c < kTH * kTH * kTH; c += kBlock) acc[c] = 0.0;
   __syncthreads();
   const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
