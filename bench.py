@@ -91,6 +91,20 @@ def kernel_bytes(plan, npart, npart_level, esize):
     return b
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` (FP32) from the committed counter summary
+    profiles/<kernel>_<workload>_fp32_counters.md: FETCH_SIZE and WRITE_SIZE per
+    dispatch (KiB), each scaled by the factor a plain copy of known size gives.  None
+    when there is no summary or it was taken on other native sources."""
+    from paper_1410_0010_amd import profstats
+    rec = profstats.traffic_record(
+        os.path.join(ROOT, "profiles", f"{kernel}_{workload}_fp32_counters.md"))
+    if not rec or rec.get("kernel") != kernel or rec.get("sources_sha256") != profstats.sources_sha256():
+        return None
+    return 1024.0 * (float(rec["fetch_kib"]) * float(rec["fetch_scale"]) +
+                     float(rec["write_kib"]) * float(rec["write_scale"]))
+
+
 WORKLOADS = {
     "plummer_nested": ("plummer_nested: root 128^3 + 2 nested 64^3 levels, 2^20 Plummer "
                        "particles (b=0.05), no gas"),
@@ -179,6 +193,7 @@ def main():
         x, y, z, m = tens(dtype)
         gas = gas_for(x.dtype)
         out = [torch.empty(n, dtype=x.dtype, device=dev) for _ in range(4)]
+        tot_dev = torch.zeros(plan.nlevels + 5, dtype=torch.float64, device=dev)
         grads = None
         ctx.solve(x, y, z, m, gas, *out)
         torch.cuda.synchronize()
@@ -187,7 +202,7 @@ def main():
 
         def step():
             ctx.solve(x, y, z, m, gas, *out)
-            tot = ctx.solve_totals(m, *out, gas=gas)
+            tot = ctx.solve_totals(m, *out, gas=gas, out=tot_dev)    # stays on the GPU
             g = ctx.solve_adjoint(x, y, z, m, gas, out[3], wbar=1.0) if adjoint else None
             return tot, g
 
@@ -211,7 +226,7 @@ def main():
         if profile:
             ctx.profile(False)
             prof = ctx.profile_read()
-        res = dict(ms=ms, wall_ms=1000 * wall / steps, totals=tot, prof=prof,
+        res = dict(ms=ms, wall_ms=1000 * wall / steps, totals=tot.cpu().numpy(), prof=prof,
                    acc=np.stack([o.cpu().numpy().astype(np.float64) for o in out[:3]], 1),
                    pot=out[3].cpu().numpy().astype(np.float64))
         if grads is not None:
@@ -252,7 +267,8 @@ def main():
     forward_names = [k for k in per_kernel if not k.startswith("adj")]
     dom = max(forward_names, key=lambda k: per_kernel[k]["ms_per_step"])
     dom_ms = per_kernel[dom]["ms_per_step"]
-    dom_launch_ms = dom_ms / per_kernel[dom]["launches_per_step"]
+    dom_launches = per_kernel[dom]["launches_per_step"]
+    dom_launch_ms = dom_ms / dom_launches
     achieved = kb.get(dom, 0.0) / (dom_ms * 1e-3) / 1e9
     for k in per_kernel:
         if kb.get(k):
@@ -402,8 +418,10 @@ def main():
                         "net_force": list(r32["totals"][plan.nlevels + 1:plan.nlevels + 4])},
         "leapfrog_fp32": lf,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, args.workload),
                      "avg_launch_ms": dom_launch_ms,
+                     "algorithmic_bytes_per_launch": kb.get(dom, 0.0) / dom_launches,
                      "algorithmic_bytes_per_step": kb.get(dom, 0.0),
                      "profiled_ms_per_step": p32["ms"]},
         "kernels_fp32": per_kernel,

@@ -221,6 +221,16 @@ apm_status apm_solve_totals(apm_ctx ctx, apm_dtype dtype, const void* m, int64_t
                             const void* const* gas, const void* ax, const void* ay,
                             const void* az, const void* pot, double* out);
 
+/* apm_solve_totals without the synchronisation: the same nlevels + 5 FP64 values are
+ * written to out_dev, a device array the caller owns, in stream order (so a step
+ * loop can keep them on the GPU and read them when it needs them).  The library's
+ * totals scratch is reused by the next totals call: calls on one context are
+ * ordered by its stream.  APM_ERR_INVALID for a NULL out_dev; APM_ERR_STATE as for
+ * apm_solve_totals.  Asynchronous. */
+apm_status apm_solve_totals_async(apm_ctx ctx, apm_dtype dtype, const void* m, int64_t npart,
+                                  const void* const* gas, const void* ax, const void* ay,
+                                  const void* az, const void* pot, double* out_dev);
+
 /* Gas part of the potential energy of one level (as in apm_solve_totals) from its
  * packed active gas and its composed field (apm_accel output layout).  Written to
  * *out; synchronises. */

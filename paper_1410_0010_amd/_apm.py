@@ -85,6 +85,8 @@ SIGNATURES = {
                         _vp]),
     "apm_solve_totals": (_st, [_vp, _st, _vp, _i64, ctypes.POINTER(_vp), _vp, _vp, _vp, _vp,
                                ctypes.POINTER(ctypes.c_double)]),
+    "apm_solve_totals_async": (_st, [_vp, _st, _vp, _i64, ctypes.POINTER(_vp), _vp, _vp, _vp, _vp,
+                                     _vp]),
     "apm_gas_energy": (_st, [_vp, _st, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
     "apm_solve_adjoint": (_st, [_vp, _st, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_vp), _vp,
                                 _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp,

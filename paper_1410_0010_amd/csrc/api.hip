@@ -1009,6 +1009,56 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
   return APM_OK;
 }
 
+// Layout of the totals scratch (doubles): [0] W_gas accumulator, [kTotOut ..) the
+// synchronous entry points' results, [kTotPart ..) reduction partials.
+constexpr int64_t kTotOut = 8, kTotPart = 64;
+
+// A9 totals on the stream into out_dev (nlev + 5 doubles, device): three launches, plus
+// the gas-energy passes when gas is given (they read the composed fields of the last
+// solve of this dtype).
+template <typename T>
+apm_status totals_t(apm_ctx c, apm_dtype dt, const void* const* gmf, const T* m,
+                    const int32_t* owner, int64_t npart, const T* ax, const T* ay, const T* az,
+                    const T* pot, const void* const* gas, double* out_dev) {
+  const Plan& P = c->plan;
+  const int nl = (int)P.levels.size();
+  APM_TRY(ensure(c, c->totals, (size_t)(kTotPart + (kMaxLevels + 4) * kMaxParts) * 8, "totals"));
+  double* d = (double*)c->totals.p;
+  TotalsIO<T> io{};
+  io.nlev = nl;
+  for (int l = 0; l < nl; ++l) {
+    if (!gmf[l]) return fail(APM_ERR_INVALID, "totals: NULL gmf pointer");
+    io.gmf[l] = (const T*)gmf[l];
+    io.gmf_n[l] = P.levels[l].gmf_elems;
+    io.vol[l] = P.levels[l].dx * P.levels[l].dx * P.levels[l].dx;
+  }
+  io.m = m; io.owner = owner; io.npart = npart;
+  io.ax = ax; io.ay = ay; io.az = az; io.pot = pot;
+  io.part = d + kTotPart;
+  io.out = out_dev;
+  bool any_gas = false;
+  for (int l = 0; gas && l < nl; ++l) any_gas = any_gas || gas[l];
+  if (any_gas) {
+    HIP_TRY(launch_fill_f64(d, 1, 0.0, c->stream), "gas energy fill");
+    std::vector<const V4<T>*> f(nl);
+    for (int l = 0; l < nl; ++l) f[l] = (const V4<T>*)c->fld[(int)dt][l].p;
+    APM_TRY(gas_energy_levels_t<T>(c, gas, f.data(), d));
+    io.gas_w = d;
+  }
+  HIP_TRY(launch_totals<T>(io, c->stream), "totals");
+  return APM_OK;
+}
+
+apm_status totals_any(apm_ctx c, apm_dtype dt, const void* const* gmf, const void* m,
+                      const int32_t* owner, int64_t npart, const void* ax, const void* ay,
+                      const void* az, const void* pot, const void* const* gas, double* out_dev) {
+  if (dt == APM_F32)
+    return totals_t<float>(c, dt, gmf, (const float*)m, owner, npart, (const float*)ax,
+                           (const float*)ay, (const float*)az, (const float*)pot, gas, out_dev);
+  return totals_t<double>(c, dt, gmf, (const double*)m, owner, npart, (const double*)ax,
+                          (const double*)ay, (const double*)az, (const double*)pot, gas, out_dev);
+}
+
 extern "C" {
 
 apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out) {
@@ -1268,31 +1318,12 @@ apm_status apm_totals(apm_ctx c, apm_dtype dt, const void* const* gmf, const voi
   if (npart < 0) return fail(APM_ERR_RANGE, "apm_totals: npart < 0");
   if (npart > 0 && (!m || !owner || !ax || !ay || !az))
     return fail(APM_ERR_INVALID, "apm_totals: NULL particle array");
-  const Plan& P = c->plan;
-  const int nl = (int)P.levels.size();
-  APM_TRY(ensure(c, c->totals, (size_t)(nl + 4 + 4 * kMaxParts) * 8, "totals"));
-  double* d = (double*)c->totals.p;
-  double* part = d + nl + 4;
-  HIP_TRY(launch_fill_f64(d, nl + 4, 0.0, c->stream), "totals fill");
-  for (int l = 0; l < nl; ++l) {
-    if (!gmf[l]) return fail(APM_ERR_INVALID, "apm_totals: NULL gmf pointer");
-    const double v = P.levels[l].dx * P.levels[l].dx * P.levels[l].dx;
-    hipError_t e = dt == APM_F32
-        ? launch_sum_scaled<float>((const float*)gmf[l], P.levels[l].gmf_elems, v, part, d + l,
-                                   c->stream)
-        : launch_sum_scaled<double>((const double*)gmf[l], P.levels[l].gmf_elems, v, part, d + l,
-                                    c->stream);
-    HIP_TRY(e, "totals mass");
-  }
-  hipError_t e = dt == APM_F32
-      ? launch_particle_totals<float>((const float*)m, owner, npart, (const float*)ax,
-                                      (const float*)ay, (const float*)az, (const float*)pot, part,
-                                      d + nl, c->stream)
-      : launch_particle_totals<double>((const double*)m, owner, npart, (const double*)ax,
-                                       (const double*)ay, (const double*)az, (const double*)pot,
-                                       part, d + nl, c->stream);
-  HIP_TRY(e, "totals particles");
-  HIP_TRY(hipMemcpyAsync(out, d, (size_t)(nl + 4) * 8, hipMemcpyDeviceToHost, c->stream), "totals copy");
+  const int nl = (int)c->plan.levels.size();
+  APM_TRY(ensure(c, c->totals, (size_t)(kTotPart + (kMaxLevels + 4) * kMaxParts) * 8, "totals"));
+  double* res = (double*)c->totals.p + kTotOut;
+  APM_TRY(totals_any(c, dt, gmf, m, owner, npart, ax, ay, az, pot, nullptr, res));
+  HIP_TRY(hipMemcpyAsync(out, res, (size_t)(nl + 4) * 8, hipMemcpyDeviceToHost, c->stream),
+          "totals copy");
   HIP_TRY(hipStreamSynchronize(c->stream), "totals sync");
   return APM_OK;
 }
@@ -1313,40 +1344,52 @@ apm_status apm_solve(apm_ctx c, apm_dtype dt, const void* x, const void* y, cons
                          (double*)pot);
 }
 
-apm_status apm_solve_totals(apm_ctx c, apm_dtype dt, const void* m, int64_t npart,
-                            const void* const* gas, const void* ax, const void* ay,
-                            const void* az, const void* pot, double* out) {
+static apm_status solve_totals_check(apm_ctx c, apm_dtype dt, const void* m, int64_t npart,
+                                     const void* ax, const void* ay, const void* az) {
   APM_TRY(check_ctx(c));
   APM_TRY(check_dtype(dt));
-  if (!out) return fail(APM_ERR_INVALID, "apm_solve_totals: NULL out");
   const int nl = (int)c->plan.levels.size();
   const int di = (int)dt;
   if ((int)c->gmf[di].size() != nl || (int)c->fld[di].size() != nl || !c->owner.p ||
       c->owner.bytes < (size_t)std::max<int64_t>(npart, 1) * 4)
     return fail(APM_ERR_STATE, "apm_solve_totals: no apm_solve of this dtype/size yet");
-  std::vector<const void*> g(nl);
-  for (int l = 0; l < nl; ++l) g[l] = c->gmf[di][l].p;
-  APM_TRY(apm_totals(c, dt, g.data(), m, (const int32_t*)c->owner.p, npart, ax, ay, az, pot, out));
-  out[nl + 4] = 0.0;
-  if (gas) {
-    double* d = (double*)c->totals.p;                // apm_totals sized it for nl + 4 + parts
-    HIP_TRY(launch_fill_f64(d, 1, 0.0, c->stream), "gas energy fill");
-    if (dt == APM_F32) {
-      std::vector<const V4<float>*> f(nl);
-      for (int l = 0; l < nl; ++l) f[l] = (const V4<float>*)c->fld[di][l].p;
-      APM_TRY(gas_energy_levels_t<float>(c, gas, f.data(), d));
-    } else {
-      std::vector<const V4<double>*> f(nl);
-      for (int l = 0; l < nl; ++l) f[l] = (const V4<double>*)c->fld[di][l].p;
-      APM_TRY(gas_energy_levels_t<double>(c, gas, f.data(), d));
-    }
-    double wg = 0.0;
-    HIP_TRY(hipMemcpyAsync(&wg, d, 8, hipMemcpyDeviceToHost, c->stream), "gas energy copy");
-    HIP_TRY(hipStreamSynchronize(c->stream), "gas energy sync");
-    out[nl + 4] = wg;
-    out[nl] += wg;
-  }
+  if (npart < 0) return fail(APM_ERR_RANGE, "apm_solve_totals: npart < 0");
+  if (npart > 0 && (!m || !ax || !ay || !az))
+    return fail(APM_ERR_INVALID, "apm_solve_totals: NULL particle array");
   return APM_OK;
+}
+
+static apm_status solve_totals_into(apm_ctx c, apm_dtype dt, const void* m, int64_t npart,
+                                    const void* const* gas, const void* ax, const void* ay,
+                                    const void* az, const void* pot, double* out_dev) {
+  const int nl = (int)c->plan.levels.size();
+  std::vector<const void*> g(nl);
+  for (int l = 0; l < nl; ++l) g[l] = c->gmf[(int)dt][l].p;
+  return totals_any(c, dt, g.data(), m, (const int32_t*)c->owner.p, npart, ax, ay, az, pot, gas,
+                    out_dev);
+}
+
+apm_status apm_solve_totals(apm_ctx c, apm_dtype dt, const void* m, int64_t npart,
+                            const void* const* gas, const void* ax, const void* ay,
+                            const void* az, const void* pot, double* out) {
+  APM_TRY(solve_totals_check(c, dt, m, npart, ax, ay, az));
+  if (!out) return fail(APM_ERR_INVALID, "apm_solve_totals: NULL out");
+  const int nl = (int)c->plan.levels.size();
+  APM_TRY(ensure(c, c->totals, (size_t)(kTotPart + (kMaxLevels + 4) * kMaxParts) * 8, "totals"));
+  double* res = (double*)c->totals.p + kTotOut;
+  APM_TRY(solve_totals_into(c, dt, m, npart, gas, ax, ay, az, pot, res));
+  HIP_TRY(hipMemcpyAsync(out, res, (size_t)(nl + 5) * 8, hipMemcpyDeviceToHost, c->stream),
+          "totals copy");
+  HIP_TRY(hipStreamSynchronize(c->stream), "totals sync");
+  return APM_OK;
+}
+
+apm_status apm_solve_totals_async(apm_ctx c, apm_dtype dt, const void* m, int64_t npart,
+                                  const void* const* gas, const void* ax, const void* ay,
+                                  const void* az, const void* pot, double* out_dev) {
+  APM_TRY(solve_totals_check(c, dt, m, npart, ax, ay, az));
+  if (!out_dev) return fail(APM_ERR_INVALID, "apm_solve_totals_async: NULL out");
+  return solve_totals_into(c, dt, m, npart, gas, ax, ay, az, pot, out_dev);
 }
 
 apm_status apm_gas_energy(apm_ctx c, apm_dtype dt, int32_t level, const void* gas,

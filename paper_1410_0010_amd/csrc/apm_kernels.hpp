@@ -259,6 +259,22 @@ template <typename T> hipError_t launch_particle_totals(const T* m, const int32_
                                                         int64_t npart, const T* ax, const T* ay,
                                                         const T* az, const T* pot, double* part,
                                                         double* out, hipStream_t s);
+// Totals of a solve in three launches: every level's GMF sum (one launch over all
+// levels) and the particle sums leave partials at part[q kMaxParts + b] (q < nlev:
+// levels, then W_p and sum m a); one block then writes out[0..nlev + 5) in a fixed
+// order: scaled level masses, W (+ *gas_w), sum m a, W_gas (*gas_w, or 0).
+template <typename T> struct TotalsIO {
+  int32_t nlev;
+  const T* gmf[kMaxLevels];
+  int64_t gmf_n[kMaxLevels];
+  double vol[kMaxLevels];              // dx^3 of the level
+  const T* m; const int32_t* owner; int64_t npart;
+  const T* ax; const T* ay; const T* az; const T* pot;
+  const double* gas_w;                 // device scalar W_gas, or null
+  double* part;                        // (nlev + 4) kMaxParts doubles
+  double* out;                         // nlev + 5 doubles
+};
+template <typename T> hipError_t launch_totals(const TotalsIO<T>& io, hipStream_t s);
 // out[q] += scale * sum_{b < nparts} part[q * kMaxParts + b], q < nq (fixed order;
 // with nq = 1 any nparts)
 hipError_t launch_sum_parts(const double* part, int nparts, int nq, double scale, double* out,

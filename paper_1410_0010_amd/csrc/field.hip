@@ -154,6 +154,52 @@ hipError_t launch_particle_totals(const T* m, const int32_t* owner, int64_t npar
   return hipGetLastError();
 }
 
+// level sums: blockIdx.y = level, nb blocks per level (blocks past a level's size add 0)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_level_mass(TotalsIO<T> io, int nb) {
+  const int l = blockIdx.y;
+  const T* __restrict__ a = io.gmf[l];
+  const int64_t n = io.gmf_n[l];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)nb * kBlock)
+    acc += (double)a[i];
+  const double r = block_sum(acc);
+  if (threadIdx.x == 0) io.part[(int64_t)l * kMaxParts + blockIdx.x] = r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_totals_finish(TotalsIO<T> io, int nb_mass, int nb_part) {
+  const int nl = io.nlev;
+  for (int q = 0; q < nl + 4; ++q) {
+    const int nb = q < nl ? nb_mass : nb_part;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) acc += io.part[(int64_t)q * kMaxParts + b];
+    const double r = block_sum(acc);
+    if (threadIdx.x == 0) io.out[q] = q < nl ? io.vol[q] * r : r;
+  }
+  if (threadIdx.x == 0) {
+    const double wg = io.gas_w ? *io.gas_w : 0.0;
+    io.out[nl] += wg;
+    io.out[nl + 4] = wg;
+  }
+}
+
+template <typename T>
+hipError_t launch_totals(const TotalsIO<T>& io, hipStream_t s) {
+  int64_t nmax = 1;
+  for (int l = 0; l < io.nlev; ++l) nmax = io.gmf_n[l] > nmax ? io.gmf_n[l] : nmax;
+  const int nb_mass = nparts_for(nmax);
+  const int nb_part = io.npart > 0 ? nparts_for(io.npart) : 0;
+  if (io.nlev > 0)
+    hipLaunchKernelGGL((k_level_mass<T>), dim3(nb_mass, io.nlev), dim3(kBlock), 0, s, io, nb_mass);
+  if (nb_part > 0)
+    hipLaunchKernelGGL((k_particle_totals<T>), dim3(nb_part), dim3(kBlock), 0, s, io.m, io.owner,
+                       io.npart, io.ax, io.ay, io.az, io.pot,
+                       io.part + (int64_t)io.nlev * kMaxParts);
+  hipLaunchKernelGGL((k_totals_finish<T>), dim3(1), dim3(kBlock), 0, s, io, nb_mass, nb_part);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -187,6 +233,7 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
                                         const V4<T>*, V4<T>*, int64_t, hipStream_t);             \
   template hipError_t launch_sum_scaled<T>(const T*, int64_t, double, double*, double*,          \
                                           hipStream_t);                                         \
+  template hipError_t launch_totals<T>(const TotalsIO<T>&, hipStream_t);                        \
   template hipError_t launch_particle_totals<T>(const T*, const int32_t*, int64_t, const T*,     \
                                                 const T*, const T*, const T*, double*, double*,  \
                                                 hipStream_t);

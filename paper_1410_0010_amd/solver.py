@@ -210,10 +210,21 @@ class Context:
         return (ctypes.c_void_p * self.plan.nlevels)(
             *[None if g is None else g.data_ptr() for g in gas])
 
-    def solve_totals(self, m, ax, ay, az, pot=None, gas=None):
+    def solve_totals(self, m, ax, ay, az, pot=None, gas=None, out=None):
         """FP64 totals of the last solve() (apm_solve_totals): mass per level, energy W
-        (particles + gas), net force, gas part of W.  Synchronises the stream."""
+        (particles + gas), net force, gas part of W.  Synchronises the stream and
+        returns a numpy array; with `out` (a float64 device tensor of nlevels + 5
+        values) it runs apm_solve_totals_async instead and returns `out` without
+        synchronising."""
         nl = self.plan.nlevels
+        if out is not None:
+            if out.dtype != self.torch.float64 or out.numel() < nl + 5 or not out.is_cuda:
+                raise ValueError(f"out must be a float64 device tensor of {nl + 5} values")
+            check(_apm.lib().apm_solve_totals_async(self.handle, _dtype_code(m), _ptr(m),
+                                                    m.shape[0], self._gas_array(gas), _ptr(ax),
+                                                    _ptr(ay), _ptr(az), _ptr(pot), _ptr(out)),
+                  "apm_solve_totals_async")
+            return out
         out = (ctypes.c_double * (nl + 5))()
         check(_apm.lib().apm_solve_totals(self.handle, _dtype_code(m), _ptr(m), m.shape[0],
                                           self._gas_array(gas), _ptr(ax), _ptr(ay), _ptr(az),

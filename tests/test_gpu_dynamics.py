@@ -72,6 +72,12 @@ def test_gas_energy_and_solve_totals(case, dtype):
     tol = 1e-12 if dtype == np.float64 else 1e-5
     assert abs(tot[nl + 4] - wgas_ref) <= tol * abs(wgas_ref), (tot[nl + 4], wgas_ref)
     assert abs(tot[nl] - ref["energy"]) <= tol * abs(ref["energy"]), (tot[nl], ref["energy"])
+    # the asynchronous variant runs the same kernels in the same order: identical bits
+    tot_dev = torch.full((nl + 5,), -1.0, dtype=torch.float64, device=DEV)
+    ctx.solve_totals(m, ax, ay, az, pot, gas=gas, out=tot_dev)
+    assert np.array_equal(tot_dev.cpu().numpy(), tot)
+    with pytest.raises(ValueError):
+        ctx.solve_totals(m, ax, ay, az, pot, gas=gas, out=tot_dev[:2])
     # the per-level entry point on the library's composed fields
     staged = 0.0
     for l in range(nl):
