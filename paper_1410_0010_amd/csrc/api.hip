@@ -48,7 +48,7 @@ struct apm_ctx_s {
   DevBuf spec, zbuf, ybuf, pres, owner, totals, binned, gpart, energy, lf_pot;
   // per level: tile counters, work items, FP64 mass grid, particle keys/ranks, the
   // tile-sorted records and their original indices
-  struct LevelBufs { DevBuf count, items, work, accum, key, rank, sref, sorted; };
+  struct LevelBufs { DevBuf count, items, work, bsum, accum, key, rank, sref, sorted; };
   std::vector<LevelBufs> lvb;
   std::vector<DepLevel> dep_host;                                 // level table, host copy
   std::vector<unsigned char> dep_dev_copy;                        // bytes last uploaded
@@ -514,6 +514,7 @@ apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y,
     APM_TRY(ensure(c, B.items, (size_t)(ntiles + 1) * 4, "tile work items"));
     const int64_t nwork = ntiles + (npart + kChunk - 1) / kChunk;    // deposit blocks of the level
     APM_TRY(ensure(c, B.work, (size_t)std::max<int64_t>(nwork, 1) * sizeof(int4), "work table"));
+    APM_TRY(ensure(c, B.bsum, (size_t)((ntiles + 255) / 256 + 1) * sizeof(int2), "scan block sums"));
     APM_TRY(ensure(c, B.accum, (size_t)L.key_cells * 8, "fp64 mass grid"));
     APM_TRY(ensure(c, B.key, np * 4, "particle keys"));
     APM_TRY(ensure(c, B.rank, np * 4, "particle ranks"));
@@ -536,6 +537,7 @@ apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y,
     d.count = (int32_t*)B.count.p;
     d.items = (int32_t*)B.items.p;
     d.work = (int4*)B.work.p;
+    d.bsum = (int2*)B.bsum.p;
     d.key = (int32_t*)B.key.p;
     d.rank = (int32_t*)B.rank.p;
     d.sref = (int2*)B.sref.p;
@@ -561,7 +563,10 @@ apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y,
   HIP_TRY(timed(c, "bin_clear", [&] { return launch_dep_clear(tab, nlev, max_elems, c->stream); }),
           "clear");
   HIP_TRY(timed(c, "bin_count", [&] { return launch_bin_count<T>(io, tab, c->stream); }), "bin count");
-  HIP_TRY(timed(c, "bin_scan", [&] { return launch_bin_scan(tab, nlev, c->stream); }), "bin scan");
+  int32_t max_tiles = 1;
+  for (int b = 0; b < nlev; ++b) max_tiles = std::max(max_tiles, c->dep_host[l0 + b].ntiles);
+  HIP_TRY(timed(c, "bin_scan", [&] { return launch_bin_scan(tab, nlev, max_tiles, c->stream); }),
+          "bin scan");
   HIP_TRY(timed(c, "bin_scatter", [&] { return launch_bin_scatter<T>(io, tab, c->stream); }),
           "bin scatter");
   HIP_TRY(timed(c, "deposit_tiles", [&] { return launch_deposit_tiles<T>(io, tab, c->stream); }),
@@ -1197,7 +1202,8 @@ apm_status apm_destroy(apm_ctx c) {
   DevBuf* bufs[] = {&c->spec, &c->zbuf, &c->ybuf, &c->pres, &c->owner, &c->totals,
                     &c->binned, &c->dep_tab, &c->gpart, &c->energy, &c->lf_pot};
   for (auto& B : c->lvb)
-    for (DevBuf* b : {&B.count, &B.items, &B.work, &B.accum, &B.key, &B.rank, &B.sref, &B.sorted})
+    for (DevBuf* b : {&B.count, &B.items, &B.work, &B.bsum, &B.accum, &B.key, &B.rank, &B.sref,
+                      &B.sorted})
       if (b->p) (void)hipFree(b->p);
   for (auto* v : {&c->adj_fbar, &c->adj_gas, &c->adj_gmf[0], &c->adj_gmf[1], &c->adj_gmf[2]})
     for (auto& b : *v) if (b.p) (void)hipFree(b.p);

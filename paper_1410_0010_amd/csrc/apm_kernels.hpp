@@ -117,6 +117,7 @@ struct DepLevel {
   int32_t* items;                  // ntiles + 1: scanned work-item counts
   int4* work;                      // work item -> (tile, first entry, end entry, 0); room
                                    // for ntiles + ceil(npart / kChunk) items
+  int2* bsum;                      // per 256 tiles: (count, items) sums, then their starts
   int32_t* key;                    // npart: counter slot or -1
   int32_t* rank;                   // npart: rank within the slot
   int2* sref;                      // sorted position -> (original index, owner grid if
@@ -144,7 +145,7 @@ template <typename T> struct DepIO {
 hipError_t launch_dep_clear(const DepLevel* tab, int nlev, int64_t max_elems, hipStream_t s);
 template <typename T> hipError_t launch_bin_count(const DepIO<T>& io, const DepLevel* tab,
                                                   hipStream_t s);
-hipError_t launch_bin_scan(const DepLevel* tab, int nlev, hipStream_t s);
+hipError_t launch_bin_scan(const DepLevel* tab, int nlev, int32_t max_tiles, hipStream_t s);
 template <typename T> hipError_t launch_bin_scatter(const DepIO<T>& io, const DepLevel* tab,
                                                     hipStream_t s);
 template <typename T> hipError_t launch_deposit_tiles(const DepIO<T>& io, const DepLevel* tab,

@@ -188,120 +188,126 @@ hipError_t launch_bin_count(const DepIO<T>& io, const DepLevel* tab, hipStream_t
   return hipGetLastError();
 }
 
-// ---- per-level scans: one block of kScanThreads per level ---------------------------
-// The replica counters, in tile-major order, are scanned in place into start offsets
-// (the final entry becomes the binned total); then work items per tile
-// ceil(tile count / kChunk) are scanned into item starts.
-constexpr int kScanThreads = 1024;
-constexpr int kScanPer = 16;                         // consecutive counters per thread
-constexpr int kWaves = kScanThreads / 64;
+// ---- per-level scans ------------------------------------------------------------------
+// The replica counters, in tile-major order, become start offsets in place (entry
+// ntiles * rep becomes the binned total); each tile's work items, ceil(tile count /
+// kChunk), get item starts and work-table entries.  Three short launches, all levels
+// in each: per-block sums over kScanTiles tiles (one tile per thread), a scan of
+// those sums per level, then every block scans its own tiles from its offset.
+constexpr int kScanTiles = 256;                      // tiles per block (one per thread)
+constexpr int kScanThreads = 1024;                   // threads of the per-level scan
 
-// Exclusive prefix sum over the block (wavefront shuffles, then the wave totals);
-// *total gets the block sum.  sh holds kWaves ints.
-__device__ static int32_t block_exclusive_sum(int32_t v, int32_t* sh, int32_t* total) {
+// Exclusive prefix sums of two values over a block of NT threads (wavefront shuffles,
+// then the wave totals); *tot gets the block sums.  sh holds 2 NT / 64 ints.
+template <int NT>
+__device__ static int2 block_scan2(int2 v, int32_t* sh, int2* tot) {
+  constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int32_t incl = v;
+  int2 inc = v;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
-    const int32_t o = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += o;
+    const int32_t ox = __shfl_up(inc.x, off, 64), oy = __shfl_up(inc.y, off, 64);
+    if (lane >= off) { inc.x += ox; inc.y += oy; }
   }
-  if (lane == 63) sh[wave] = incl;
+  if (lane == 63) { sh[wave] = inc.x; sh[NW + wave] = inc.y; }
   __syncthreads();
-  int32_t wbase = 0, sum = 0;
+  int2 base = make_int2(0, 0), sum = make_int2(0, 0);
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    const int32_t t = sh[w];
-    wbase += w < wave ? t : 0;
-    sum += t;
+  for (int w = 0; w < NW; ++w) {
+    const int32_t a = sh[w], b = sh[NW + w];
+    if (w < wave) { base.x += a; base.y += b; }
+    sum.x += a; sum.y += b;
   }
   __syncthreads();                                   // sh reused by the next call
-  *total = sum;
-  return wbase + incl - v;
+  *tot = sum;
+  return make_int2(base.x + inc.x - v.x, base.y + inc.y - v.y);
 }
 
-// Exclusive scan of data[0, n) in place by the whole block; returns the sum.  data
-// must be 16-byte aligned (whole 16-counter runs move as four 16-byte vectors).
-__device__ static int32_t block_scan_inplace(int32_t* data, int64_t n, int32_t* sh) {
-  int32_t carry = 0;
-  for (int64_t c0 = 0; c0 < n; c0 += (int64_t)kScanThreads * kScanPer) {
-    const int64_t base = c0 + (int64_t)threadIdx.x * kScanPer;
-    int32_t v[kScanPer];
-    const bool whole = base + kScanPer <= n;
-    if (whole) {
-      const int4* p4 = reinterpret_cast<const int4*>(data + base);
+// tile t's count (sum of its replicas, kept in v) and work items
+__device__ __forceinline__ int2 tile_count(const DepLevel& L, int32_t t, int32_t* v) {
+  int32_t tot = 0;
+  if (t < L.ntiles) {
+    const int rep = L.rep;
+    const int32_t* c = L.count + (int64_t)t * rep;
+    if (rep >= 4) {                                  // rep: power of two, <= 16
 #pragma unroll
-      for (int k = 0; k < kScanPer / 4; ++k) {
-        const int4 q = p4[k];
-        v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
-      }
+      for (int k = 0; k < 4; ++k)
+        if (4 * k < rep) {
+          const int4 q = reinterpret_cast<const int4*>(c)[k];
+          v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+        }
     } else {
-#pragma unroll
-      for (int k = 0; k < kScanPer; ++k) v[k] = base + k < n ? data[base + k] : 0;
+      for (int r = 0; r < rep; ++r) v[r] = c[r];
     }
-    int32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) sum += v[k];
-    int32_t chunk;
-    int32_t ex = carry + block_exclusive_sum(sum, sh, &chunk);
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      const int32_t n_k = v[k];
-      v[k] = ex;
-      ex += n_k;
-    }
-    if (whole) {
-      int4* p4 = reinterpret_cast<int4*>(data + base);
-#pragma unroll
-      for (int k = 0; k < kScanPer / 4; ++k)
-        p4[k] = make_int4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
-    } else {
-#pragma unroll
-      for (int k = 0; k < kScanPer; ++k)
-        if (base + k < n) data[base + k] = v[k];
-    }
-    carry += chunk;
+    for (int r = 0; r < rep; ++r) tot += v[r];
   }
-  return carry;
+  return make_int2(tot, (tot + kChunk - 1) / kChunk);
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_bin_scan(const DepLevel* __restrict__ tab) {
-  __shared__ int32_t sh[kWaves];
+__global__ void __launch_bounds__(kScanTiles) k_scan_tiles(const DepLevel* __restrict__ tab) {
+  __shared__ int32_t sh[2 * kScanTiles / 64];
+  const DepLevel& L = tab[blockIdx.y];
+  if ((int64_t)blockIdx.x * kScanTiles >= L.ntiles) return;   // uniform for the block
+  int32_t v[16];
+  const int2 c = tile_count(L, (int32_t)(blockIdx.x * kScanTiles + threadIdx.x), v);
+  int2 tot;
+  block_scan2<kScanTiles>(c, sh, &tot);
+  if (threadIdx.x == 0) L.bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_blocks(const DepLevel* __restrict__ tab) {
+  __shared__ int32_t sh[2 * kScanThreads / 64];
   const DepLevel& L = tab[blockIdx.x];
-  const int rep = L.rep;
-  const int32_t nt = L.ntiles;
-  const int32_t total = block_scan_inplace(L.count, (int64_t)nt * rep + 1, sh);
-  __syncthreads();                                   // the block's writes visible to it
-  for (int32_t t0 = 0; t0 <= nt; t0 += kScanThreads * kScanPer) {
-#pragma unroll
-    for (int q = 0; q < kScanPer; ++q) {
-      const int32_t t = t0 + q * kScanThreads + (int32_t)threadIdx.x;
-      if (t < nt)
-        L.items[t] = (L.count[(int64_t)(t + 1) * rep] - L.count[(int64_t)t * rep] + kChunk - 1) /
-                     kChunk;
-      else if (t == nt)
-        L.items[t] = 0;
-    }
+  const int32_t nb = (L.ntiles + kScanTiles - 1) / kScanTiles;
+  int2 carry = make_int2(0, 0);
+  for (int32_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+    const int32_t b = b0 + (int32_t)threadIdx.x;
+    const int2 v = b < nb ? L.bsum[b] : make_int2(0, 0);
+    int2 tot;
+    const int2 ex = block_scan2<kScanThreads>(v, sh, &tot);
+    if (b < nb) L.bsum[b] = make_int2(carry.x + ex.x, carry.y + ex.y);
+    carry.x += tot.x;
+    carry.y += tot.y;
   }
-  __syncthreads();
-  block_scan_inplace(L.items, (int64_t)nt + 1, sh);
-  __syncthreads();
-  // the work table: item -> its tile and entry range, so a deposit block needs one
-  // load to find its work instead of a search over the tiles
-  for (int32_t t = (int32_t)threadIdx.x; t < nt; t += kScanThreads) {
-    const int32_t i0 = L.items[t], i1 = L.items[t + 1];
-    const int32_t b0 = L.count[(int64_t)t * rep], e0 = L.count[(int64_t)(t + 1) * rep];
-    for (int32_t k = i0; k < i1; ++k) {
-      const int32_t b = b0 + (k - i0) * kChunk;
-      L.work[k] = make_int4(t, b, min(e0, b + kChunk), 0);
-    }
+  if (threadIdx.x == 0) {
+    L.count[(int64_t)L.ntiles * L.rep] = carry.x;
+    L.items[L.ntiles] = carry.y;
+    *L.binned = carry.x;
   }
-  if (threadIdx.x == 0) *L.binned = total;
 }
 
-hipError_t launch_bin_scan(const DepLevel* tab, int nlev, hipStream_t s) {
+__global__ void __launch_bounds__(kScanTiles) k_scan_emit(const DepLevel* __restrict__ tab) {
+  __shared__ int32_t sh[2 * kScanTiles / 64];
+  const DepLevel& L = tab[blockIdx.y];
+  if ((int64_t)blockIdx.x * kScanTiles >= L.ntiles) return;   // uniform for the block
+  const int32_t t = (int32_t)(blockIdx.x * kScanTiles + threadIdx.x);
+  int32_t v[16];
+  const int2 c = tile_count(L, t, v);
+  int2 tot;
+  const int2 ex = block_scan2<kScanTiles>(c, sh, &tot);
+  if (t >= L.ntiles) return;
+  const int2 off = L.bsum[blockIdx.x];
+  const int32_t start = off.x + ex.x, istart = off.y + ex.y;
+  const int rep = L.rep;
+  int32_t o = start;
+  for (int r = 0; r < rep; ++r) {                    // replica starts (tile-major)
+    const int32_t n = v[r];
+    L.count[(int64_t)t * rep + r] = o;
+    o += n;
+  }
+  L.items[t] = istart;
+  for (int32_t q = 0; q < c.y; ++q) {                // the tile's work items
+    const int32_t b = start + q * kChunk;
+    L.work[istart + q] = make_int4(t, b, min(start + c.x, b + kChunk), 0);
+  }
+}
+
+hipError_t launch_bin_scan(const DepLevel* tab, int nlev, int32_t max_tiles, hipStream_t s) {
   if (nlev == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bin_scan, dim3((unsigned)nlev), dim3(kScanThreads), 0, s, tab);
+  const unsigned nb = (unsigned)((max_tiles + kScanTiles - 1) / kScanTiles);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(nb, (unsigned)nlev), dim3(kScanTiles), 0, s, tab);
+  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nlev), dim3(kScanThreads), 0, s, tab);
+  hipLaunchKernelGGL(k_scan_emit, dim3(nb, (unsigned)nlev), dim3(kScanTiles), 0, s, tab);
   return hipGetLastError();
 }
 
