@@ -65,6 +65,9 @@ struct apm_ctx_s {
   uint64_t epoch = 0;                                             // bumps on reallocation
   bool use_graph = true;
   hipStream_t cap_stream = nullptr;
+  // second branch of the solve: the subgrid levels' transforms run beside the root's
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<uintptr_t> gkey;
   uint64_t gkey_epoch = ~0ull;
   int gkey_seen = 0;
@@ -339,10 +342,13 @@ int lines_for(apm_ctx c, int pass, int L) {
 }
 
 // Grids of `level` (or of every level when level < 0).
+// level >= 0: that level; kAllLevels: every level; kSubLevels: every level but the root
+constexpr int kAllLevels = -1, kSubLevels = -2;
 std::vector<int> grid_set(apm_ctx c, int level) {
   std::vector<int> v;
   for (const GridDesc& g : c->plan.grids)
-    if (level < 0 || g.level == level) v.push_back(g.index);
+    if (level == kAllLevels || g.level == level || (level == kSubLevels && g.level > 0))
+      v.push_back(g.index);
   return v;
 }
 
@@ -448,6 +454,31 @@ apm_status convolve_t(apm_ctx c, int level, const LevelPtrs<T>& lp) {
   return APM_OK;
 }
 
+// The own fields of every level.  The root's passes and the subgrid levels' passes
+// touch disjoint parts of the buffers, so the subgrid levels run on a second stream
+// forked from and joined back to the context's stream (two branches of the captured
+// graph; the launches of one length then overlap the other's tails).  Serial while
+// kernels are being timed one by one.
+template <typename T>
+apm_status convolve_branches_t(apm_ctx c, const LevelPtrs<T>& lp) {
+  if (c->prof_on || c->plan.levels.size() < 2) return convolve_t<T>(c, kAllLevels, lp);
+  if (!c->aux_stream)
+    HIP_TRY(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking), "second stream");
+  if (!c->ev_fork) HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "fork event");
+  if (!c->ev_join) HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "join event");
+  HIP_TRY(hipEventRecord(c->ev_fork, c->stream), "fork record");
+  HIP_TRY(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0), "fork wait");
+  hipStream_t main = c->stream;
+  c->stream = c->aux_stream;
+  apm_status st = convolve_t<T>(c, kSubLevels, lp);
+  c->stream = main;
+  if (st == APM_OK) st = convolve_t<T>(c, 0, lp);
+  // join in every case, so a capture never ends with the branch left open
+  HIP_TRY(hipEventRecord(c->ev_join, c->aux_stream), "join record");
+  HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join wait");
+  return st;
+}
+
 template <typename T>
 apm_status solve_level_t(apm_ctx c, int32_t level, const T* gmf, T* field) {
   LevelPtrs<T> lp{};
@@ -504,11 +535,11 @@ apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y,
       tn[a] = (L.key_n[a] + kTile - 1) / kTile;
       ntiles *= tn[a];
     }
-    // counter replicas per tile (blocks pick one by index): up to 16, about 2^17
+    // counter replicas per tile (blocks pick one by index): up to kMaxRep, about 2^17
     // counters in all; the many blocks of a dense core then spread their one atomic
-    // per (block, tile) over 16 addresses
+    // per (block, tile) over that many addresses
     int32_t rep = 1;
-    while (rep < 16 && ntiles * rep * 2 <= ((int64_t)1 << 18)) rep *= 2;
+    while (rep < kMaxRep && ntiles * rep * 2 <= ((int64_t)1 << 18)) rep *= 2;
     const int64_t ncount = ntiles * rep + 1;
     APM_TRY(ensure(c, B.count, (size_t)ncount * 4, "tile counts"));
     APM_TRY(ensure(c, B.items, (size_t)(ntiles + 1) * 4, "tile work items"));
@@ -628,7 +659,7 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
     lp.gmf[l] = (const T*)c->gmf[di][l].p;
     lp.fld[l] = (V4<T>*)c->fld[di][l].p;
   }
-  APM_TRY(convolve_t<T>(c, -1, lp));
+  APM_TRY(convolve_branches_t<T>(c, lp));
   for (int l = 1; l < nl; ++l) {
     const LevelDesc& L = P.levels[l];
     HIP_TRY(timed(c, "compose", [&] {
@@ -1197,6 +1228,9 @@ apm_status apm_destroy(apm_ctx c) {
   (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   for (void* p : c->owned) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   DevBuf* bufs[] = {&c->spec, &c->zbuf, &c->ybuf, &c->pres, &c->owner, &c->totals,

@@ -102,6 +102,7 @@ hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s)
 // level's binning box (union of GMF boxes grown by one cell), then the tile-wise
 // TSC deposit.  Every stage is one launch over a batch of consecutive levels.
 constexpr int kTile = 8;
+constexpr int kMaxRep = 16;        // counter replicas per tile, at most (a power of two)
 constexpr int kChunk = 2048;       // particles per deposit work item
 
 // Static part of one level (device table, rewritten only when buffers move).

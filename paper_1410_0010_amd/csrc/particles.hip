@@ -223,23 +223,20 @@ __device__ static int2 block_scan2(int2 v, int32_t* sh, int2* tot) {
   return make_int2(base.x + inc.x - v.x, base.y + inc.y - v.y);
 }
 
-// tile t's count (sum of its replicas, kept in v) and work items
-__device__ __forceinline__ int2 tile_count(const DepLevel& L, int32_t t, int32_t* v) {
+// tile t's count (sum of its replicas) and work items
+__device__ __forceinline__ int2 tile_count(const DepLevel& L, int32_t t) {
   int32_t tot = 0;
   if (t < L.ntiles) {
-    const int rep = L.rep;
+    const int rep = L.rep;                           // power of two, <= kMaxRep
     const int32_t* c = L.count + (int64_t)t * rep;
-    if (rep >= 4) {                                  // rep: power of two, <= 16
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (4 * k < rep) {
-          const int4 q = reinterpret_cast<const int4*>(c)[k];
-          v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
-        }
+    if (rep >= 4) {
+      for (int k = 0; k < rep / 4; ++k) {
+        const int4 q = reinterpret_cast<const int4*>(c)[k];
+        tot += q.x + q.y + q.z + q.w;
+      }
     } else {
-      for (int r = 0; r < rep; ++r) v[r] = c[r];
+      for (int r = 0; r < rep; ++r) tot += c[r];
     }
-    for (int r = 0; r < rep; ++r) tot += v[r];
   }
   return make_int2(tot, (tot + kChunk - 1) / kChunk);
 }
@@ -248,8 +245,7 @@ __global__ void __launch_bounds__(kScanTiles) k_scan_tiles(const DepLevel* __res
   __shared__ int32_t sh[2 * kScanTiles / 64];
   const DepLevel& L = tab[blockIdx.y];
   if ((int64_t)blockIdx.x * kScanTiles >= L.ntiles) return;   // uniform for the block
-  int32_t v[16];
-  const int2 c = tile_count(L, (int32_t)(blockIdx.x * kScanTiles + threadIdx.x), v);
+  const int2 c = tile_count(L, (int32_t)(blockIdx.x * kScanTiles + threadIdx.x));
   int2 tot;
   block_scan2<kScanTiles>(c, sh, &tot);
   if (threadIdx.x == 0) L.bsum[blockIdx.x] = tot;
@@ -281,8 +277,7 @@ __global__ void __launch_bounds__(kScanTiles) k_scan_emit(const DepLevel* __rest
   const DepLevel& L = tab[blockIdx.y];
   if ((int64_t)blockIdx.x * kScanTiles >= L.ntiles) return;   // uniform for the block
   const int32_t t = (int32_t)(blockIdx.x * kScanTiles + threadIdx.x);
-  int32_t v[16];
-  const int2 c = tile_count(L, t, v);
+  const int2 c = tile_count(L, t);
   int2 tot;
   const int2 ex = block_scan2<kScanTiles>(c, sh, &tot);
   if (t >= L.ntiles) return;
@@ -290,9 +285,10 @@ __global__ void __launch_bounds__(kScanTiles) k_scan_emit(const DepLevel* __rest
   const int32_t start = off.x + ex.x, istart = off.y + ex.y;
   const int rep = L.rep;
   int32_t o = start;
-  for (int r = 0; r < rep; ++r) {                    // replica starts (tile-major)
-    const int32_t n = v[r];
-    L.count[(int64_t)t * rep + r] = o;
+  int32_t* cnt = L.count + (int64_t)t * rep;
+  for (int r = 0; r < rep; ++r) {                    // replica starts (tile-major), in place
+    const int32_t n = cnt[r];
+    cnt[r] = o;
     o += n;
   }
   L.items[t] = istart;
