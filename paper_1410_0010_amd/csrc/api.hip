@@ -904,6 +904,48 @@ apm_status leapfrog_t(apm_ctx c, apm_dtype dt, T* x, T* y, T* z, T* vx, T* vy, T
 }
 
 // Reverse sweep of the last apm_solve of this dtype (see include/apm.h).
+// Transposed convolution passes of a grid set (see convolve_t).
+template <typename T>
+apm_status adj_convolve_t(apm_ctx c, int level, const AdjPtrs<T>& ap, bool pot_only) {
+  const int seq_full[5] = {PASS_AX, PASS_AY, PASS_AZ, PASS_AYI, PASS_AXI};
+  const int seq_pot[5] = {PASS_APX, PASS_APY, PASS_APZ, PASS_AYI, PASS_AXI};
+  for (int pass : pot_only ? seq_pot : seq_full) {
+    for (int L : pass_lengths(c, pass, level)) {
+      const int nlines = lines_for<T>(c, pass, L);
+      const apm_ctx_s::JobList* jl = nullptr;
+      APM_TRY(job_list<T>(c, pass, L, level, nlines, &jl));
+      const void* tw = nullptr;
+      APM_TRY(twiddles<T>(c, L, &tw));
+      HIP_TRY(timed(c, pass_name(pass), [&] {
+                return launch_adj_pass<T>(pass, L, nlines, jl->d, jl->n, jl->blocks, ap,
+                                          (C2<T>*)c->spec.p, (C2<T>*)c->zbuf.p, (C2<T>*)c->ybuf.p,
+                                          tw, c->stream);
+              }), pass_name(pass));
+    }
+  }
+  return APM_OK;
+}
+
+// As convolve_branches_t: the subgrid levels' transposes on the second stream.
+template <typename T>
+apm_status adj_convolve_branches_t(apm_ctx c, const AdjPtrs<T>& ap, bool pot_only) {
+  if (c->prof_on || c->plan.levels.size() < 2) return adj_convolve_t<T>(c, kAllLevels, ap, pot_only);
+  if (!c->aux_stream)
+    HIP_TRY(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking), "second stream");
+  if (!c->ev_fork) HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "fork event");
+  if (!c->ev_join) HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "join event");
+  HIP_TRY(hipEventRecord(c->ev_fork, c->stream), "fork record");
+  HIP_TRY(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0), "fork wait");
+  hipStream_t main = c->stream;
+  c->stream = c->aux_stream;
+  apm_status st = adj_convolve_t<T>(c, kSubLevels, ap, pot_only);
+  c->stream = main;
+  if (st == APM_OK) st = adj_convolve_t<T>(c, 0, ap, pot_only);
+  HIP_TRY(hipEventRecord(c->ev_join, c->aux_stream), "join record");
+  HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join wait");
+  return st;
+}
+
 template <typename T>
 apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, const T* m,
                      int64_t n, const void* const* gas, const T* pot, const T* abx, const T* aby,
@@ -1008,22 +1050,7 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
     ap.gmf[l] = (T*)c->adj_gmf[di][l].p;
     ap.fbar[l] = io.fbar[l];
   }
-  const int seq_full[5] = {PASS_AX, PASS_AY, PASS_AZ, PASS_AYI, PASS_AXI};
-  const int seq_pot[5] = {PASS_APX, PASS_APY, PASS_APZ, PASS_AYI, PASS_AXI};
-  for (int pass : pot_only ? seq_pot : seq_full) {
-    for (int L : pass_lengths(c, pass, -1)) {
-      const int nlines = lines_for<T>(c, pass, L);
-      const apm_ctx_s::JobList* jl = nullptr;
-      APM_TRY(job_list<T>(c, pass, L, -1, nlines, &jl));
-      const void* tw = nullptr;
-      APM_TRY(twiddles<T>(c, L, &tw));
-      HIP_TRY(timed(c, pass_name(pass), [&] {
-                return launch_adj_pass<T>(pass, L, nlines, jl->d, jl->n, jl->blocks, ap,
-                                          (C2<T>*)c->spec.p, (C2<T>*)c->zbuf.p, (C2<T>*)c->ybuf.p,
-                                          tw, c->stream);
-              }), pass_name(pass));
-    }
-  }
+  APM_TRY(adj_convolve_branches_t<T>(c, ap, pot_only));
   HIP_TRY(timed(c, "adj_deposit_grid", [&] { return launch_adj_deposit_grid<T>(io, tab, c->stream); }),
           "deposit transpose (grids)");
   HIP_TRY(timed(c, "adj_deposit_particles", [&] {
