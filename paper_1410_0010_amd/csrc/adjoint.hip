@@ -56,9 +56,7 @@ hipError_t launch_zero_ranges(const ZeroList& zl, hipStream_t s) {
 // of their owner grid -- one tile for the chunk's first owner grid with 4 components,
 // or up to 4 grids' tiles with the Phi component alone -- and straight to the field
 // cotangent in HBM when their grid has no tile; each tile is then added to its
-// grid's field box.  Each owned
-// entry also adds its position gradient  sum_f grad w(f) . <F(f), cot>  (F the forward
-// composed field) to the particle's FP64 accumulators (one writer per particle).
+// grid's field box.  The entries' position gradients are k_adj_interp_grad's.
 constexpr int kTH3 = 10 * 10 * 10;
 
 template <typename T, int NC>
@@ -107,10 +105,9 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
     if (threadIdx.x == 0) gsl[r] = prev;
     __syncthreads();
   }
-  const V4<T>* F = io.fld[lb];
   double* fbar = io.fbar[lb];
   const int c0 = 4 - NC;                            // first component carried
-#pragma unroll 1
+#pragma unroll
   for (int k = 0; k < 8; ++k) {
     if (ref[k].y < 0) continue;
     const int64_t i = ref[k].x;
@@ -132,10 +129,9 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
     const int ix = min(max((int)fx - L.key_lo[0] - ox, 0), kTile - 1),
               iy = min(max((int)fy - L.key_lo[1] - oy, 0), kTile - 1),
               iz = min(max((int)fz - L.key_lo[2] - oz, 0), kTile - 1);
-    // per-axis cells (clamped into the box, weight 0 outside: all 27 loads issue
-    // together) and weights
+    // per-axis cells (clamped into the box, weight 0 outside) and weights
     int ax_[3], ay_[3], az_[3];
-    double wx[3], wy[3], wz[3], dwx[3], dwy[3], dwz[3];
+    double wx[3], wy[3], wz[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
@@ -144,32 +140,6 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
       wx[d] = ox_ ? (double)tsc_w_a(d - 1, tx) : 0.0;
       wy[d] = oy_ ? (double)tsc_w_a(d - 1, ty) : 0.0;
       wz[d] = oz_ ? (double)tsc_w_a(d - 1, tz) : 0.0;
-      dwx[d] = ox_ ? (double)tsc_dw_a(d - 1, tx) : 0.0;
-      dwy[d] = oy_ ? (double)tsc_dw_a(d - 1, ty) : 0.0;
-      dwz[d] = oz_ ? (double)tsc_dw_a(d - 1, tz) : 0.0;
-    }
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz) {
-      V4<T> f9[9];
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx)
-          f9[3 * dy + dx] = F[g.fld_offset + ((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]];
-#pragma unroll
-      for (int k9 = 0; k9 < 9; ++k9) pin4(f9[k9]);
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy) {
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          const V4<T>& f = f9[3 * dy + dx];
-          const double s = cot[0] * f.x + cot[1] * f.y + cot[2] * f.z + cot[3] * f.w;
-          gx += dwx[dx] * wy[dy] * wz[dz] * s;
-          gy += wx[dx] * dwy[dy] * wz[dz] * s;
-          gz += wx[dx] * wy[dy] * dwz[dz] * s;
-        }
-      }
     }
     // scatter of the cotangent (skipped components are zero for every particle)
 #pragma unroll 1
@@ -190,11 +160,6 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
         }
       }
     }
-    const double inv = 1.0 / g.dx;
-    double* pi = io.pint + 4 * i;                   // one writer: the owner level's entry
-    pi[0] = gx * inv;
-    pi[1] = gy * inv;
-    pi[2] = gz * inv;
   }
   __syncthreads();
   for (int r = 0; r < KG; ++r) {
@@ -220,6 +185,76 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
   }
 }
 
+// Position part of the interpolation transpose: one thread per tile-sorted entry of a
+// level (neighbouring lanes gather neighbouring cells), owned entries only:
+//   pint[i] = (1/dx) sum_f grad w(f) . <F(f), cot_i>
+// with F the forward composed field of the owner grid and cot_i the particle's
+// cotangent (abar, phibar + wbar m / 2).  One writer per particle.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adj_interp_grad(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __restrict__ grids) {
+  const int lb = batch_of(io.part_blk0, io.nlev, blockIdx.x);
+  const DepLevel& L = tab[lb];
+  const int64_t q = (blockIdx.x - io.part_blk0[lb]) * (int64_t)kBlock + threadIdx.x;
+  if (q >= *L.binned) return;
+  const int2 r = load_i2(L.sref, q);
+  const V4<T> v = load_v4<T>(L.sorted, q);
+  if (r.y < 0) return;
+  const int64_t i = r.x;
+  const double cot[4] = {io.abx ? (double)io.abx[i] : 0.0, io.aby ? (double)io.aby[i] : 0.0,
+                         io.abz ? (double)io.abz[i] : 0.0,
+                         (io.phib ? (double)io.phib[i] : 0.0) + io.wbar * 0.5 * (double)v.w};
+  const GridDesc& g = grids[r.y];
+  const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
+  const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
+  const int cx = (int)fx - g.fld_lo[0], cy = (int)fy - g.fld_lo[1], cz = (int)fz - g.fld_lo[2];
+  const int nx = g.fld_n[0], ny = g.fld_n[1], nz = g.fld_n[2];
+  // per-axis cells (clamped into the box, weight 0 outside: the loads issue together)
+  int ax_[3], ay_[3], az_[3];
+  double wx[3], wy[3], wz[3], dwx[3], dwy[3], dwz[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
+    const bool ox_ = (xx >= 0) & (xx < nx), oy_ = (yy >= 0) & (yy < ny), oz_ = (zz >= 0) & (zz < nz);
+    ax_[d] = ox_ ? xx : 0; ay_[d] = oy_ ? yy : 0; az_[d] = oz_ ? zz : 0;
+    wx[d] = ox_ ? (double)tsc_w_a(d - 1, tx) : 0.0;
+    wy[d] = oy_ ? (double)tsc_w_a(d - 1, ty) : 0.0;
+    wz[d] = oz_ ? (double)tsc_w_a(d - 1, tz) : 0.0;
+    dwx[d] = ox_ ? (double)tsc_dw_a(d - 1, tx) : 0.0;
+    dwy[d] = oy_ ? (double)tsc_dw_a(d - 1, ty) : 0.0;
+    dwz[d] = oz_ ? (double)tsc_dw_a(d - 1, tz) : 0.0;
+  }
+  const V4<T>* F = io.fld[lb] + g.fld_offset;
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz) {
+    V4<T> f9[9];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx)
+        f9[3 * dy + dx] = load_v4<T>(F, ((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]);
+#pragma unroll
+    for (int k9 = 0; k9 < 9; ++k9) pin4(f9[k9]);
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const V4<T>& f = f9[3 * dy + dx];
+        const double s = cot[0] * f.x + cot[1] * f.y + cot[2] * f.z + cot[3] * f.w;
+        gx += dwx[dx] * wy[dy] * wz[dz] * s;
+        gy += wx[dx] * dwy[dy] * wz[dz] * s;
+        gz += wx[dx] * wy[dy] * dwz[dz] * s;
+      }
+    }
+  }
+  const double inv = 1.0 / g.dx;
+  double* pi = io.pint + 4 * i;
+  pi[0] = gx * inv;
+  pi[1] = gy * inv;
+  pi[2] = gz * inv;
+}
+
 template <typename T>
 hipError_t launch_adj_interp(const AdjIO<T>& io, const DepLevel* tab, const GridDesc* grids,
                              hipStream_t s) {
@@ -229,6 +264,9 @@ hipError_t launch_adj_interp(const AdjIO<T>& io, const DepLevel* tab, const Grid
     hipLaunchKernelGGL((k_adj_interp<T, 1>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab, grids);
   else
     hipLaunchKernelGGL((k_adj_interp<T, 4>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab, grids);
+  const int64_t np = io.part_blk0[io.nlev];
+  if (np > 0)
+    hipLaunchKernelGGL((k_adj_interp_grad<T>), dim3((unsigned)np), dim3(kBlock), 0, s, io, tab, grids);
   return hipGetLastError();
 }
 
