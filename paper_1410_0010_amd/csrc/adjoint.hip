@@ -464,6 +464,7 @@ k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
     dwy[d] = oy_ ? (double)tsc_dw_a(d - 1, ty) : 0.0;
     dwz[d] = oz_ ? (double)tsc_dw_a(d - 1, tz) : 0.0;
   }
+  const gptr<double> acc_g = as_global<double>(L.accum);
   double a27[27];
 #pragma unroll
   for (int dz = 0; dz < 3; ++dz)
@@ -471,7 +472,7 @@ k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx)
-        a27[(dz * 3 + dy) * 3 + dx] = L.accum[((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]];
+        a27[(dz * 3 + dy) * 3 + dx] = acc_g[((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]];
   double sm = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
 #pragma unroll
   for (int dz = 0; dz < 3; ++dz)
@@ -514,7 +515,7 @@ k_adj_finish(AdjIO<T> io, const DepLevel* __restrict__ tab, const int32_t* __res
   if (i >= io.npart) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int l = 0; l < io.nlev; ++l) {
-    if (tab[l].key[i] < 0) continue;
+    if (as_global<int32_t>(tab[l].key)[i] < 0) continue;
     const double* o = io.plev[l] + 4 * i;
     s0 += o[0]; s1 += o[1]; s2 += o[2]; s3 += o[3];
   }

@@ -22,6 +22,15 @@ template <typename T> using gptr = const __attribute__((address_space(1))) T*;
 template <typename T> __device__ __forceinline__ gptr<T> as_global(const void* p) {
   return (gptr<T>)p;
 }
+// writable counterpart, for stores and atomics through table pointers
+template <typename T> using gmut = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gmut<T> as_global_mut(void* p) {
+  return (gmut<T>)p;
+}
+// relaxed device-scope atomic add through a global-address-space pointer
+template <typename T> __device__ __forceinline__ T global_add(gmut<T> p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 template <typename T> using nvec2 = T __attribute__((ext_vector_type(2)));
 template <typename T> using nvec4 = T __attribute__((ext_vector_type(4)));
 

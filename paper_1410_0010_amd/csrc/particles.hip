@@ -167,15 +167,16 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(DepIO<T> io, const DepLeve
   __syncthreads();
   for (int h = threadIdx.x; h < kHash; h += kBlock) {
     const int32_t n = hcnt[h];
-    if (n > 0) hcnt[h] = atomicAdd(&L.count[hkey[h] * rep + r], n);   // becomes the base
+    if (n > 0) hcnt[h] = global_add(as_global_mut<int32_t>(L.count) + hkey[h] * rep + r, n);   // the base
   }
   __syncthreads();
+  const gmut<int32_t> kout = as_global_mut<int32_t>(L.key), rout = as_global_mut<int32_t>(L.rank);
 #pragma unroll
   for (int q = 0; q < kBinPer; ++q) {
     const int64_t i = base + (int64_t)q * kBlock;
     if (i < io.npart) {
-      L.key[i] = key[q] < 0 ? -1 : key[q] * rep + r;          // counter slot
-      L.rank[i] = key[q] < 0 ? 0 : hcnt[slot[q]] + lrank[q];
+      kout[i] = key[q] < 0 ? -1 : key[q] * rep + r;           // counter slot
+      rout[i] = key[q] < 0 ? 0 : hcnt[slot[q]] + lrank[q];
     }
   }
 }
@@ -313,7 +314,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_scatter(DepIO<T> io, const DepLe
   const DepLevel& L = tab[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= io.npart) return;
-  const int32_t key = L.key[i];
+  const int32_t key = as_global<int32_t>(L.key)[i];
   if (key < 0) return;
   const T sc = (T)L.inv_dx;
   V4<T> r;
@@ -326,9 +327,9 @@ __global__ void __launch_bounds__(kBlock) k_bin_scatter(DepIO<T> io, const DepLe
     const int32_t o = io.owner[i];
     if (o >= L.first && o < L.first + L.ngrids) og = o;
   }
-  const int32_t slot = L.count[key] + L.rank[i];
-  ((V4<T>*)L.sorted)[slot] = r;
-  L.sref[slot] = make_int2((int32_t)i, og);
+  const int32_t slot = as_global<int32_t>(L.count)[key] + as_global<int32_t>(L.rank)[i];
+  as_global_mut<nvec4<T>>(L.sorted)[slot] = nvec4<T>{r.x, r.y, r.z, r.w};
+  as_global_mut<nvec2<int32_t>>(L.sref)[slot] = nvec2<int32_t>{(int32_t)i, og};
 }
 
 template <typename T>
@@ -413,7 +414,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
     const int gx = tx0 + c % kTH, gy = ty0 + (c / kTH) % kTH, gz = tz0 + c / (kTH * kTH);
     if (gx < 0 || gx >= L.key_n[0] || gy < 0 || gy >= L.key_n[1] || gz < 0 || gz >= L.key_n[2])
       continue;
-    atomicAdd(L.accum + ((int64_t)gz * L.key_n[1] + gy) * L.key_n[0] + gx, v);
+    global_add(as_global_mut<double>(L.accum) + ((int64_t)gz * L.key_n[1] + gy) * L.key_n[0] + gx, v);
   }
 }
 
@@ -442,8 +443,8 @@ __global__ void __launch_bounds__(kBlock) k_deposit_finalize(DepIO<T> io, const 
   const int ly = (int)((local / g.gmf_n[0]) % g.gmf_n[1]);
   const int lz = (int)(local / ((int64_t)g.gmf_n[0] * g.gmf_n[1]));
   const int cx = g.gmf_lo[0] + lx, cy = g.gmf_lo[1] + ly, cz = g.gmf_lo[2] + lz;
-  const double mass = L.accum[((int64_t)(cz - L.key_lo[2]) * L.key_n[1] + (cy - L.key_lo[1])) *
-                                  L.key_n[0] + (cx - L.key_lo[0])];
+  const double mass = as_global<double>(L.accum)[((int64_t)(cz - L.key_lo[2]) * L.key_n[1] +
+                                                  (cy - L.key_lo[1])) * L.key_n[0] + (cx - L.key_lo[0])];
   T rho = (T)(mass / (L.dx * L.dx * L.dx));
   const bool active = cx >= g.lo[0] && cx < g.lo[0] + g.n[0] && cy >= g.lo[1] &&
                       cy < g.lo[1] + g.n[1] && cz >= g.lo[2] && cz < g.lo[2] + g.n[2];
