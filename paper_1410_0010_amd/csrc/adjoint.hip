@@ -57,7 +57,7 @@ hipError_t launch_zero_ranges(const ZeroList& zl, hipStream_t s) {
 // or up to 4 grids' tiles with the Phi component alone -- and straight to the field
 // cotangent in HBM when their grid has no tile; each tile is then added to its
 // grid's field box.  The entries' position gradients are k_adj_interp_grad's.
-constexpr int kTH3 = 10 * 10 * 10;
+constexpr int kTH3 = kHaloCells;
 
 template <typename T, int NC>
 __global__ void __launch_bounds__(kBlock)

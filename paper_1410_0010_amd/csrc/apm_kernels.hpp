@@ -102,6 +102,7 @@ hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s)
 // level's binning box (union of GMF boxes grown by one cell), then the tile-wise
 // TSC deposit.  Every stage is one launch over a batch of consecutive levels.
 constexpr int kTile = 8;
+constexpr int kHaloCells = (kTile + 2) * (kTile + 2) * (kTile + 2);   // tile + one-cell halo
 constexpr int kMaxRep = 16;        // counter replicas per tile, at most (a power of two)
 constexpr int kChunk = 2048;       // particles per deposit work item
 
@@ -124,7 +125,7 @@ struct DepLevel {
   int2* sref;                      // sorted position -> (original index, owner grid if
                                    // that grid is on this level, else -1)
   void* sorted;                    // npart records (x/dx, y/dx, z/dx, m); x/dx is exact
-  double* accum;                   // key_cells FP64 mass
+  double* accum;                   // key_cells FP64 mass (the reverse sweep: GMF cotangent)
   const GridDesc* grids;           // the level's grids
   const int64_t* block_begin;      // first finalize block of each grid (ngrids + 1)
   int32_t* binned;                 // number of particles binned on the level
