@@ -153,16 +153,17 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   C2<T>* __restrict__ zo = zb + J.z_off;
   const gptr<T> dzs = as_global<T>(J.dsym[2]);
   const int64_t pstride = (int64_t)My * P;
+  const int64_t qstride = (int64_t)(L / 8) * pstride;   // uniform: q steps by a scalar
   const int t = threadIdx.x;
   const int cb = t % nl, r0 = t / nl;                // column-wise mapping, as in y_fwd
   const bool col_ok = c0 + cb < W;
   {
-    const C2<T>* src = spec + (int64_t)ky * P + c0 + cb;
+    const C2<T>* src = spec + (int64_t)ky * P + c0 + cb + r0 * pstride;
     C2<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int z = r0 + q * (L / 8);
-      v[q] = (z < gz && col_ok) ? src[z * pstride] : mk<T>(0, 0);
+      v[q] = (z < gz && col_ok) ? src[q * qstride] : mk<T>(0, 0);
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
@@ -175,12 +176,14 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int kxc = kx < W ? kx : 0;
   const int Oy = My / 2 + 1;
   const int kyo = ky <= My / 2 ? ky : My - ky;
+  // table index kzo Oy W + kyo W + kx: < 2^31, and kzo, Oy W < 2^24 (24-bit multiply)
+  const uint32_t plane = (uint32_t)(Oy * W), rowcol = (uint32_t)(kyo * W + kxc);
   T gf[8], gp[8], gz_[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int kz = w + q * (L / 8);
     const int kzo = kz <= L / 2 ? kz : L - kz;
-    const C2<T> G = load_c2<T>(J.kern, ((int64_t)kzo * Oy + kyo) * W + kxc);
+    const C2<T> G = load_c2<T>(J.kern, __umul24((uint32_t)kzo, plane) + rowcol);
     gf[q] = G.x;
     gp[q] = G.y;
     gz_[q] = dzs[kz] * G.x;
@@ -202,12 +205,11 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
     fft_line<T, L, true>(line, w, tw);
     __syncthreads();                                 // stores use another mapping
     if (col_ok) {
+      C2<T>* dst = zo + ((int64_t)s * fz + r0) * pstride + (int64_t)ky * P + c0 + cb;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int j = r0 + q * (L / 8);
-        if (j < fz)
-          zo[((int64_t)(s * fz + j) * My + ky) * P + c0 + cb] =
-              lds[cb * ls + swz<L>((oz + j) & (L - 1))];
+        if (j < fz) dst[q * qstride] = lds[cb * ls + swz<L>((oz + j) & (L - 1))];
       }
     }
     __syncthreads();

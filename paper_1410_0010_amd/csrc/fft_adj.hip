@@ -200,12 +200,15 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int kxc = kx < W ? kx : 0;
   const int Oy = My / 2 + 1;
   const int kyo = ky <= My / 2 ? ky : My - ky;
+  // 24-bit multiplies: kzo, jz < 2^11, Oy W and My P < 2^24, every product < 2^31
+  const uint32_t plane = (uint32_t)(Oy * W), rowcol = (uint32_t)(kyo * W + kxc);
+  const uint32_t ps32 = (uint32_t)pstride;
   T gf[8], gp[8], dz[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int kz = w + q * (L / 8);
     const int kzo = kz <= L / 2 ? kz : L - kz;
-    const C2<T> G = load_c2<T>(J.kern, ((int64_t)kzo * Oy + kyo) * W + kxc);
+    const C2<T> G = load_c2<T>(J.kern, __umul24((uint32_t)kzo, plane) + rowcol);
     gf[q] = G.x;
     gp[q] = G.y;
     dz[q] = dzs[kz];
@@ -214,12 +217,13 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 #pragma unroll
   for (int q = 0; q < 8; ++q) S[q] = mk<T>(0, 0);
   for (int s = 0; s < 3; ++s) {
+    const C2<T>* zs_in = zin + s * zs;
     C2<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int r = r0 + q * (L / 8);                // transform position
       const int jz = (r - oz) & (L - 1);             // field plane landing there
-      v[q] = (col_ok && jz < fz) ? zin[s * zs + (int64_t)jz * pstride + cb] : mk<T>(0, 0);
+      v[q] = (col_ok && jz < fz) ? zs_in[__umul24((uint32_t)jz, ps32) + cb] : mk<T>(0, 0);
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
@@ -240,10 +244,12 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   fft_line<T, L, true>(line, w, tw);
   __syncthreads();                                   // stores use another mapping
   if (col_ok) {
+    C2<T>* dst = spec + r0 * pstride + cb;
+    const int64_t qstride = (int64_t)(L / 8) * pstride;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int z = r0 + q * (L / 8);
-      if (z < gz) spec[z * pstride + cb] = lds[cb * ls + swz<L>(z)];
+      if (z < gz) dst[q * qstride] = lds[cb * ls + swz<L>(z)];
     }
   }
 }
@@ -452,12 +458,15 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int kxc = kx < W ? kx : 0;
   const int Oy = My / 2 + 1;
   const int kyo = ky <= My / 2 ? ky : My - ky;
+  // 24-bit multiplies: kzo, jz < 2^11, Oy W and My P < 2^24, every product < 2^31
+  const uint32_t plane = (uint32_t)(Oy * W), rowcol = (uint32_t)(kyo * W + kxc);
+  const uint32_t ps32 = (uint32_t)pstride;
   T gp[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int kz = w + q * (L / 8);
     const int kzo = kz <= L / 2 ? kz : L - kz;
-    gp[q] = load_c2<T>(J.kern, ((int64_t)kzo * Oy + kyo) * W + kxc).y;
+    gp[q] = load_c2<T>(J.kern, __umul24((uint32_t)kzo, plane) + rowcol).y;
   }
   {
     C2<T> v[8];
@@ -465,7 +474,7 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
     for (int q = 0; q < 8; ++q) {
       const int r = r0 + q * (L / 8);
       const int jz = (r - oz) & (L - 1);
-      v[q] = (col_ok && jz < fz) ? zin[(int64_t)jz * pstride + cb] : mk<T>(0, 0);
+      v[q] = (col_ok && jz < fz) ? zin[__umul24((uint32_t)jz, ps32) + cb] : mk<T>(0, 0);
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
@@ -482,10 +491,12 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   fft_line<T, L, true>(line, w, tw);
   __syncthreads();
   if (col_ok) {
+    C2<T>* dst = spec + r0 * pstride + cb;
+    const int64_t qstride = (int64_t)(L / 8) * pstride;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int z = r0 + q * (L / 8);
-      if (z < gz) spec[z * pstride + cb] = lds[cb * ls + swz<L>(z)];
+      if (z < gz) dst[q * qstride] = lds[cb * ls + swz<L>(z)];
     }
   }
 }
