@@ -454,29 +454,13 @@ apm_status convolve_t(apm_ctx c, int level, const LevelPtrs<T>& lp) {
   return APM_OK;
 }
 
-// The own fields of every level.  The root's passes and the subgrid levels' passes
-// touch disjoint parts of the buffers, so the subgrid levels run on a second stream
-// forked from and joined back to the context's stream (two branches of the captured
-// graph; the launches of one length then overlap the other's tails).  Serial while
-// kernels are being timed one by one.
-template <typename T>
-apm_status convolve_branches_t(apm_ctx c, const LevelPtrs<T>& lp) {
-  if (c->prof_on || c->plan.levels.size() < 2) return convolve_t<T>(c, kAllLevels, lp);
+// The second stream and the fork / join events of a two-branch solve (created once).
+apm_status prepare_branch_stream(apm_ctx c) {
   if (!c->aux_stream)
     HIP_TRY(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking), "second stream");
   if (!c->ev_fork) HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "fork event");
   if (!c->ev_join) HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "join event");
-  HIP_TRY(hipEventRecord(c->ev_fork, c->stream), "fork record");
-  HIP_TRY(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0), "fork wait");
-  hipStream_t main = c->stream;
-  c->stream = c->aux_stream;
-  apm_status st = convolve_t<T>(c, kSubLevels, lp);
-  c->stream = main;
-  if (st == APM_OK) st = convolve_t<T>(c, 0, lp);
-  // join in every case, so a capture never ends with the branch left open
-  HIP_TRY(hipEventRecord(c->ev_join, c->aux_stream), "join record");
-  HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join wait");
-  return st;
+  return APM_OK;
 }
 
 template <typename T>
@@ -503,13 +487,20 @@ apm_status sync_dep_table(apm_ctx c) {
   return APM_OK;
 }
 
-// TSC deposit of levels [l0, l0 + nlev) (Sec. 2): six launches for the batch --
-// clear, tile count, scans, scatter, tile deposit, finalize.  gas/pgas/gmf are
-// indexed by batch position.
+// A deposit batch: its launch arguments, prepared before any of its launches.
+template <typename T> struct DepBatch {
+  int l0 = 0, nlev = 0;
+  DepIO<T> io{};
+  int64_t max_elems = 0;
+  int32_t max_tiles = 1;
+};
+
+// Buffers and level-table entries of levels [l0, l0 + nlev); the table itself is
+// uploaded by sync_dep_table (once for every batch of a solve).
 template <typename T>
-apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y, const T* z,
-                            const T* m, int64_t npart, const int32_t* owner, const T* const* gas,
-                            const T* const* pgas, T* const* gmf) {
+apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y, const T* z,
+                             const T* m, int64_t npart, const int32_t* owner, const T* const* gas,
+                             const T* const* pgas, T* const* gmf, DepBatch<T>* out) {
   const Plan& P = c->plan;
   const int nl = (int)P.levels.size();
   c->lvb.resize(nl);
@@ -589,13 +580,27 @@ apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y,
   }
   io.item_blk0[nlev] = iblk;
   io.fin_blk0[nlev] = fblk;
-  APM_TRY(sync_dep_table(c));
-  const DepLevel* tab = (const DepLevel*)c->dep_tab.p + l0;
+  out->l0 = l0;
+  out->nlev = nlev;
+  out->io = io;
+  out->max_elems = max_elems;
+  out->max_tiles = 1;
+  for (int b = 0; b < nlev; ++b) out->max_tiles = std::max(out->max_tiles, c->dep_host[l0 + b].ntiles);
+  return APM_OK;
+}
+
+// TSC deposit of a prepared batch (Sec. 2), on the context's stream: six launches --
+// clear, tile count, scans, scatter, tile deposit, finalize.
+template <typename T>
+apm_status deposit_launch_t(apm_ctx c, const DepBatch<T>& d) {
+  const DepIO<T>& io = d.io;
+  const int nlev = d.nlev;
+  const int64_t max_elems = d.max_elems;
+  const int32_t max_tiles = d.max_tiles;
+  const DepLevel* tab = (const DepLevel*)c->dep_tab.p + d.l0;
   HIP_TRY(timed(c, "bin_clear", [&] { return launch_dep_clear(tab, nlev, max_elems, c->stream); }),
           "clear");
   HIP_TRY(timed(c, "bin_count", [&] { return launch_bin_count<T>(io, tab, c->stream); }), "bin count");
-  int32_t max_tiles = 1;
-  for (int b = 0; b < nlev; ++b) max_tiles = std::max(max_tiles, c->dep_host[l0 + b].ntiles);
   HIP_TRY(timed(c, "bin_scan", [&] { return launch_bin_scan(tab, nlev, max_tiles, c->stream); }),
           "bin scan");
   HIP_TRY(timed(c, "bin_scatter", [&] { return launch_bin_scatter<T>(io, tab, c->stream); }),
@@ -606,6 +611,18 @@ apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y,
             return launch_deposit_finalize<T>(io, tab, c->stream);
           }), "deposit finalize");
   return APM_OK;
+}
+
+// TSC deposit of levels [l0, l0 + nlev) in one batch.  gas/pgas/gmf are indexed by
+// batch position.
+template <typename T>
+apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y, const T* z,
+                            const T* m, int64_t npart, const int32_t* owner, const T* const* gas,
+                            const T* const* pgas, T* const* gmf) {
+  DepBatch<T> d;
+  APM_TRY(deposit_prepare_t<T>(c, l0, nlev, x, y, z, m, npart, owner, gas, pgas, gmf, &d));
+  APM_TRY(sync_dep_table(c));
+  return deposit_launch_t<T>(c, d);
 }
 
 template <typename T>
@@ -650,16 +667,42 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
       pg[l] = (gas && l > 0) ? (const T*)gas[l - 1] : nullptr;
       gm[l] = (T*)c->gmf[di][l].p;
     }
-    APM_TRY(deposit_levels_t<T>(c, 0, nl, x, y, z, m, npart, own, gl, pg, gm));
+    // each grid's own field is written straight into the level field, then the
+    // parent's composed field is added in place, level by level (the root has none)
+    LevelPtrs<T> lp{};
+    for (int l = 0; l < nl; ++l) {
+      lp.gmf[l] = (const T*)c->gmf[di][l].p;
+      lp.fld[l] = (V4<T>*)c->fld[di][l].p;
+    }
+    if (c->prof_on || nl < 2) {                      // one stream (kernels timed one by one)
+      APM_TRY(deposit_levels_t<T>(c, 0, nl, x, y, z, m, npart, own, gl, pg, gm));
+      APM_TRY(convolve_t<T>(c, kAllLevels, lp));
+    } else {
+      // The root's deposit and transforms, and those of the subgrid levels, touch
+      // disjoint buffers until the composition: the subgrid levels run on a second
+      // stream, forked from and joined back to the context's stream (two branches of
+      // the captured graph).
+      DepBatch<T> d0, d1;
+      APM_TRY(deposit_prepare_t<T>(c, 0, 1, x, y, z, m, npart, own, gl, pg, gm, &d0));
+      APM_TRY(deposit_prepare_t<T>(c, 1, nl - 1, x, y, z, m, npart, own, gl + 1, pg + 1, gm + 1,
+                                   &d1));
+      APM_TRY(sync_dep_table(c));
+      APM_TRY(prepare_branch_stream(c));
+      HIP_TRY(hipEventRecord(c->ev_fork, c->stream), "fork record");
+      HIP_TRY(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0), "fork wait");
+      hipStream_t main = c->stream;
+      c->stream = c->aux_stream;
+      apm_status st = deposit_launch_t<T>(c, d1);
+      if (st == APM_OK) st = convolve_t<T>(c, kSubLevels, lp);
+      c->stream = main;
+      if (st == APM_OK) st = deposit_launch_t<T>(c, d0);
+      if (st == APM_OK) st = convolve_t<T>(c, 0, lp);
+      // join in every case, so a capture never ends with the branch left open
+      HIP_TRY(hipEventRecord(c->ev_join, c->aux_stream), "join record");
+      HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join wait");
+      APM_TRY(st);
+    }
   }
-  // each grid's own field is written straight into the level field, then the
-  // parent's composed field is added in place, level by level (the root has none)
-  LevelPtrs<T> lp{};
-  for (int l = 0; l < nl; ++l) {
-    lp.gmf[l] = (const T*)c->gmf[di][l].p;
-    lp.fld[l] = (V4<T>*)c->fld[di][l].p;
-  }
-  APM_TRY(convolve_branches_t<T>(c, lp));
   for (int l = 1; l < nl; ++l) {
     const LevelDesc& L = P.levels[l];
     HIP_TRY(timed(c, "compose", [&] {
@@ -926,14 +969,11 @@ apm_status adj_convolve_t(apm_ctx c, int level, const AdjPtrs<T>& ap, bool pot_o
   return APM_OK;
 }
 
-// As convolve_branches_t: the subgrid levels' transposes on the second stream.
+// The subgrid levels' transposes on the second stream (as in the forward solve).
 template <typename T>
 apm_status adj_convolve_branches_t(apm_ctx c, const AdjPtrs<T>& ap, bool pot_only) {
   if (c->prof_on || c->plan.levels.size() < 2) return adj_convolve_t<T>(c, kAllLevels, ap, pot_only);
-  if (!c->aux_stream)
-    HIP_TRY(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking), "second stream");
-  if (!c->ev_fork) HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "fork event");
-  if (!c->ev_join) HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "join event");
+  APM_TRY(prepare_branch_stream(c));
   HIP_TRY(hipEventRecord(c->ev_fork, c->stream), "fork record");
   HIP_TRY(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0), "fork wait");
   hipStream_t main = c->stream;
