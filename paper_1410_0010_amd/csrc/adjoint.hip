@@ -249,10 +249,7 @@ k_adj_interp_grad(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc*
     }
   }
   const double inv = 1.0 / g.dx;
-  double* pi = io.pint + 4 * i;
-  pi[0] = gx * inv;
-  pi[1] = gy * inv;
-  pi[2] = gz * inv;
+  io.pint[i] = V4<T>{(T)(gx * inv), (T)(gy * inv), (T)(gz * inv), (T)0};
 }
 
 template <typename T>
@@ -487,11 +484,7 @@ k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
         gz += wx[dx] * wy[dy] * dwz[dz] * a;
       }
   const double m = (double)v.w * L.inv_dx;
-  double* o = io.plev[lb] + 4 * (int64_t)r.x;       // one writer per (level, particle)
-  o[0] = sm;
-  o[1] = m * gx;
-  o[2] = m * gy;
-  o[3] = m * gz;
+  io.plev[lb][r.x] = V4<T>{(T)sm, (T)(m * gx), (T)(m * gy), (T)(m * gz)};   // one writer
 }
 
 template <typename T>
@@ -516,12 +509,12 @@ k_adj_finish(AdjIO<T> io, const DepLevel* __restrict__ tab, const int32_t* __res
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int l = 0; l < io.nlev; ++l) {
     if (as_global<int32_t>(tab[l].key)[i] < 0) continue;
-    const double* o = io.plev[l] + 4 * i;
-    s0 += o[0]; s1 += o[1]; s2 += o[2]; s3 += o[3];
+    const V4<T> o = load_v4<T>(io.plev[l], i);
+    s0 += (double)o.x; s1 += (double)o.y; s2 += (double)o.z; s3 += (double)o.w;
   }
   if (owner[i] >= 0) {
-    const double* pi = io.pint + 4 * i;
-    s1 += pi[0]; s2 += pi[1]; s3 += pi[2];
+    const V4<T> pi = load_v4<T>(io.pint, i);
+    s1 += (double)pi.x; s2 += (double)pi.y; s3 += (double)pi.z;
     if (io.wbar != 0.0 && pot) s0 += io.wbar * 0.5 * (double)pot[i];
   }
   if (mb) mb[i] = (T)s0;

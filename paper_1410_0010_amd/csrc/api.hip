@@ -1010,7 +1010,7 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
                      "gas cotangents"));
   }
   // per particle, 4 FP64 each: the interpolation transpose's slot and one per level
-  APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * 32 * (nl + 1),
+  APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * sizeof(V4<T>) * (nl + 1),
                  "particle cotangents"));
   ZeroList zl{};
   hipError_t zerr = hipSuccess;
@@ -1030,9 +1030,9 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
   io.abx = abx; io.aby = aby; io.abz = abz; io.phib = phib;
   const bool pot_only = !abx && !aby && !abz;       // the Phi cotangent alone flows back
   io.c0 = pot_only ? 3 : 0;
-  double* pacc = (double*)c->adj_pacc.p;
+  V4<T>* pacc = (V4<T>*)c->adj_pacc.p;
   io.pint = pacc;
-  for (int l = 0; l < nl; ++l) io.plev[l] = pacc + 4 * (int64_t)n * (l + 1);
+  for (int l = 0; l < nl; ++l) io.plev[l] = pacc + (int64_t)n * (l + 1);
   int64_t iblk = 0, fblk = 0, pblk = 0;
   const int64_t nbp = (n + kBlock - 1) / kBlock;
   for (int l = 0; l < nl; ++l) {
