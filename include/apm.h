@@ -250,7 +250,8 @@ apm_status apm_gas_energy(apm_ctx ctx, apm_dtype dtype, int32_t level, const voi
  * multipliers +i d_i Gf and Gp), the deposit (Sec. 2).  Owner grids are held fixed.
  * The transposes are linear, so nothing of the forward spectra is kept: the reverse
  * sweep reads the forward composed fields and tile-sorted particles that apm_solve
- * leaves in the context.  Cotangents accumulate in FP64 for both dtypes.
+ * leaves in the context.  Field, GMF and gas cotangents accumulate in FP64 for both
+ * dtypes; each particle's per-level terms are rounded to dtype before their FP64 sum.
  * gas: as passed to apm_solve.  pot: the solve's potentials (needed if wbar != 0).
  * abar_x/y/z, phibar: npart values each, or NULL for zero.
  * xbar, ybar, zbar, mbar: npart outputs (any may be NULL).  gas_bar: NULL or host

@@ -1116,7 +1116,7 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
 // synchronous entry points' results, [kTotPart ..) reduction partials.
 constexpr int64_t kTotOut = 8, kTotPart = 64;
 
-// A9 totals on the stream into out_dev (nlev + 5 doubles, device): three launches, plus
+// A9 totals on the stream into out_dev (nlev + 5 doubles, device): two launches, plus
 // the gas-energy passes when gas is given (they read the composed fields of the last
 // solve of this dtype).
 template <typename T>

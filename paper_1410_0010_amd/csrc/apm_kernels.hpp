@@ -265,10 +265,10 @@ template <typename T> hipError_t launch_particle_totals(const T* m, const int32_
                                                         int64_t npart, const T* ax, const T* ay,
                                                         const T* az, const T* pot, double* part,
                                                         double* out, hipStream_t s);
-// Totals of a solve in three launches: every level's GMF sum (one launch over all
-// levels) and the particle sums leave partials at part[q kMaxParts + b] (q < nlev:
-// levels, then W_p and sum m a); one block then writes out[0..nlev + 5) in a fixed
-// order: scaled level masses, W (+ *gas_w), sum m a, W_gas (*gas_w, or 0).
+// Totals of a solve in two launches: every level's GMF sum and the particle sums
+// leave partials at part[q kMaxParts + b] (q < nlev: levels, then W_p and sum m a);
+// then one block per quantity writes out[0..nlev + 5) in a fixed order: scaled level
+// masses, W (+ *gas_w), sum m a, W_gas (*gas_w, or 0).
 template <typename T> struct TotalsIO {
   int32_t nlev;
   const T* gmf[kMaxLevels];

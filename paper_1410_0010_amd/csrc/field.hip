@@ -154,34 +154,59 @@ hipError_t launch_particle_totals(const T* m, const int32_t* owner, int64_t npar
   return hipGetLastError();
 }
 
-// level sums: blockIdx.y = level, nb blocks per level (blocks past a level's size add 0)
+// Partial sums of a solve's totals, one launch: blockIdx.y < nlev sums level y's GMF
+// (nb_mass blocks; blocks past a level's size add 0), blockIdx.y = nlev the particle
+// terms W_p, sum m a (nb_part blocks).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_level_mass(TotalsIO<T> io, int nb) {
+__global__ void __launch_bounds__(kBlock) k_totals_parts(TotalsIO<T> io, int nb_mass, int nb_part) {
   const int l = blockIdx.y;
-  const T* __restrict__ a = io.gmf[l];
-  const int64_t n = io.gmf_n[l];
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)nb * kBlock)
-    acc += (double)a[i];
-  const double r = block_sum(acc);
-  if (threadIdx.x == 0) io.part[(int64_t)l * kMaxParts + blockIdx.x] = r;
+  if (l < io.nlev) {
+    if ((int)blockIdx.x >= nb_mass) return;
+    const T* __restrict__ a = io.gmf[l];
+    const int64_t n = io.gmf_n[l];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)nb_mass * kBlock)
+      acc += (double)a[i];
+    const double r = block_sum(acc);
+    if (threadIdx.x == 0) io.part[(int64_t)l * kMaxParts + blockIdx.x] = r;
+    return;
+  }
+  if ((int)blockIdx.x >= nb_part) return;
+  double w = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < io.npart;
+       i += (int64_t)nb_part * kBlock) {
+    if (io.owner[i] < 0) continue;
+    const double mi = (double)io.m[i];
+    if (io.pot) w += 0.5 * mi * (double)io.pot[i];
+    fx += mi * (double)io.ax[i];
+    fy += mi * (double)io.ay[i];
+    fz += mi * (double)io.az[i];
+  }
+  const double rw = block_sum(w), rx = block_sum(fx), ry = block_sum(fy), rz = block_sum(fz);
+  if (threadIdx.x == 0) {
+    double* part = io.part + (int64_t)io.nlev * kMaxParts;
+    part[0 * kMaxParts + blockIdx.x] = rw;
+    part[1 * kMaxParts + blockIdx.x] = rx;
+    part[2 * kMaxParts + blockIdx.x] = ry;
+    part[3 * kMaxParts + blockIdx.x] = rz;
+  }
 }
 
+// out[q] for q = blockIdx.x < nlev + 5, each block one quantity (fixed summation order)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_totals_finish(TotalsIO<T> io, int nb_mass, int nb_part) {
   const int nl = io.nlev;
-  for (int q = 0; q < nl + 4; ++q) {
-    const int nb = q < nl ? nb_mass : nb_part;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) acc += io.part[(int64_t)q * kMaxParts + b];
-    const double r = block_sum(acc);
-    if (threadIdx.x == 0) io.out[q] = q < nl ? io.vol[q] * r : r;
+  const int q = blockIdx.x;
+  const double wg = io.gas_w ? *io.gas_w : 0.0;
+  if (q == nl + 4) {
+    if (threadIdx.x == 0) io.out[q] = wg;
+    return;
   }
-  if (threadIdx.x == 0) {
-    const double wg = io.gas_w ? *io.gas_w : 0.0;
-    io.out[nl] += wg;
-    io.out[nl + 4] = wg;
-  }
+  const int nb = q < nl ? nb_mass : nb_part;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) acc += io.part[(int64_t)q * kMaxParts + b];
+  const double r = block_sum(acc);
+  if (threadIdx.x == 0) io.out[q] = q < nl ? io.vol[q] * r : (q == nl ? r + wg : r);
 }
 
 template <typename T>
@@ -190,13 +215,10 @@ hipError_t launch_totals(const TotalsIO<T>& io, hipStream_t s) {
   for (int l = 0; l < io.nlev; ++l) nmax = io.gmf_n[l] > nmax ? io.gmf_n[l] : nmax;
   const int nb_mass = nparts_for(nmax);
   const int nb_part = io.npart > 0 ? nparts_for(io.npart) : 0;
-  if (io.nlev > 0)
-    hipLaunchKernelGGL((k_level_mass<T>), dim3(nb_mass, io.nlev), dim3(kBlock), 0, s, io, nb_mass);
-  if (nb_part > 0)
-    hipLaunchKernelGGL((k_particle_totals<T>), dim3(nb_part), dim3(kBlock), 0, s, io.m, io.owner,
-                       io.npart, io.ax, io.ay, io.az, io.pot,
-                       io.part + (int64_t)io.nlev * kMaxParts);
-  hipLaunchKernelGGL((k_totals_finish<T>), dim3(1), dim3(kBlock), 0, s, io, nb_mass, nb_part);
+  const int nbx = nb_mass > nb_part ? nb_mass : nb_part;
+  hipLaunchKernelGGL((k_totals_parts<T>), dim3(nbx, io.nlev + 1), dim3(kBlock), 0, s, io, nb_mass,
+                     nb_part);
+  hipLaunchKernelGGL((k_totals_finish<T>), dim3(io.nlev + 5), dim3(kBlock), 0, s, io, nb_mass, nb_part);
   return hipGetLastError();
 }
 

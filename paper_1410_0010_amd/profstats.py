@@ -29,7 +29,7 @@ FAMILY = {
     "k_adj_x_inv": "adj_fft_x_inv",
     "k_dep_clear": "bin_clear", "k_bin_count": "bin_count", "k_scan_tiles": "bin_scan",
     "k_scan_blocks": "bin_scan", "k_scan_emit": "bin_scan", "k_deposit_sparse": "deposit_sparse",
-    "k_adj_interp_grad": "adj_interp", "k_level_mass": "totals", "k_particle_totals": "totals",
+    "k_adj_interp_grad": "adj_interp", "k_totals_parts": "totals", "k_particle_totals": "totals",
     "k_totals_finish": "totals",
     "k_bin_scatter": "bin_scatter", "k_deposit_tiles": "deposit_tiles",
     "k_deposit_finalize": "deposit_finalize", "k_owner": "owner", "k_compose": "compose",
