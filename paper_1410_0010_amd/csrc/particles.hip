@@ -165,9 +165,21 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(DepIO<T> io, const DepLeve
     }
   }
   __syncthreads();
-  for (int h = threadIdx.x; h < kHash; h += kBlock) {
-    const int32_t n = hcnt[h];
-    if (n > 0) hcnt[h] = global_add(as_global_mut<int32_t>(L.count) + hkey[h] * rep + r, n);   // the base
+  {
+    // one range per distinct tile: all of this thread's global atomics are issued
+    // before any of their results is waited for
+    static_assert(kHash % kBlock == 0, "whole hash slots per thread");
+    constexpr int kSlots = kHash / kBlock;
+    const gmut<int32_t> cnt = as_global_mut<int32_t>(L.count);
+    int32_t n[kSlots], base[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) n[k] = hcnt[threadIdx.x + k * kBlock];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k)
+      base[k] = n[k] > 0 ? global_add(cnt + hkey[threadIdx.x + k * kBlock] * rep + r, n[k]) : 0;
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k)
+      if (n[k] > 0) hcnt[threadIdx.x + k * kBlock] = base[k];   // becomes the base
   }
   __syncthreads();
   const gmut<int32_t> kout = as_global_mut<int32_t>(L.key), rout = as_global_mut<int32_t>(L.rank);
