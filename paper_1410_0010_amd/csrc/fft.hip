@@ -132,7 +132,7 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
 //   s = 0: Gf(k) rho_hat            (the x and y derivatives follow in later passes)
 //   s = 1: -i d_z(k_z) Gf(k) rho_hat
 //   s = 2: Gp(k) rho_hat
-// kern: octant table of (Gf, Gp), index ((|kz| Oy) + |ky|) W + kx, already scaled.
+// kern: octant table of (Gf, Gp), index ((|ky| W) + kx) Oz + |kz|, already scaled.
 
 template <typename T, int L>
 __global__ void __launch_bounds__(kZConvMaxThreads)
@@ -174,16 +174,16 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   // this worker's multipliers, loaded while the forward transform runs
   const int kx = c0 + b;
   const int kxc = kx < W ? kx : 0;
-  const int Oy = My / 2 + 1;
   const int kyo = ky <= My / 2 ? ky : My - ky;
-  // table index kzo Oy W + kyo W + kx: < 2^31, and kzo, Oy W < 2^24 (24-bit multiply)
-  const uint32_t plane = (uint32_t)(Oy * W), rowcol = (uint32_t)(kyo * W + kxc);
+  // this column's multipliers: one contiguous run of L/2 + 1 in the table
+  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)(kyo * W + kxc) * (L / 2 + 1);
   T gf[8], gp[8], gz_[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int kz = w + q * (L / 8);
     const int kzo = kz <= L / 2 ? kz : L - kz;
-    const C2<T> G = load_c2<T>(J.kern, __umul24((uint32_t)kzo, plane) + rowcol);
+    const nvec2<T> gv = gcol[kzo];
+    const C2<T> G = mk<T>(gv.x, gv.y);
     gf[q] = G.x;
     gp[q] = G.y;
     gz_[q] = dzs[kz] * G.x;

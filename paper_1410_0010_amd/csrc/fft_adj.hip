@@ -198,17 +198,18 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   C2<T>* line = lds + b * ls;
   const int kx = c0 + b;
   const int kxc = kx < W ? kx : 0;
-  const int Oy = My / 2 + 1;
   const int kyo = ky <= My / 2 ? ky : My - ky;
-  // 24-bit multiplies: kzo, jz < 2^11, Oy W and My P < 2^24, every product < 2^31
-  const uint32_t plane = (uint32_t)(Oy * W), rowcol = (uint32_t)(kyo * W + kxc);
+  // 24-bit multiplies: jz < 2^11, My P < 2^24, every product < 2^31
   const uint32_t ps32 = (uint32_t)pstride;
+  // this column's multipliers: one contiguous run of L/2 + 1 in the table
+  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)(kyo * W + kxc) * (L / 2 + 1);
   T gf[8], gp[8], dz[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int kz = w + q * (L / 8);
     const int kzo = kz <= L / 2 ? kz : L - kz;
-    const C2<T> G = load_c2<T>(J.kern, __umul24((uint32_t)kzo, plane) + rowcol);
+    const nvec2<T> gv = gcol[kzo];
+    const C2<T> G = mk<T>(gv.x, gv.y);
     gf[q] = G.x;
     gp[q] = G.y;
     dz[q] = dzs[kz];
@@ -456,17 +457,17 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   C2<T>* line = lds + b * ls;
   const int kx = c0 + b;
   const int kxc = kx < W ? kx : 0;
-  const int Oy = My / 2 + 1;
   const int kyo = ky <= My / 2 ? ky : My - ky;
-  // 24-bit multiplies: kzo, jz < 2^11, Oy W and My P < 2^24, every product < 2^31
-  const uint32_t plane = (uint32_t)(Oy * W), rowcol = (uint32_t)(kyo * W + kxc);
+  // 24-bit multiplies: jz < 2^11, My P < 2^24, every product < 2^31
   const uint32_t ps32 = (uint32_t)pstride;
+  // this column's multipliers: one contiguous run of L/2 + 1 in the table
+  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)(kyo * W + kxc) * (L / 2 + 1);
   T gp[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int kz = w + q * (L / 8);
     const int kzo = kz <= L / 2 ? kz : L - kz;
-    gp[q] = load_c2<T>(J.kern, __umul24((uint32_t)kzo, plane) + rowcol).y;
+    gp[q] = gcol[kzo].y;
   }
   {
     C2<T> v[8];

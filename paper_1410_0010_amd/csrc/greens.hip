@@ -10,7 +10,8 @@
 // Root (level 0, isolated): the level-0 kernels (reference S_0^2) made isolated as
 // the doubled-mesh reference potential (James) plus optimal - reference.
 // Tables hold the octant |m_i| <= M_i/2 (both kernels are even in every axis),
-// scaled by 1/(Mx My Mz) for the unnormalised transforms.
+// scaled by 1/(Mx My Mz) for the unnormalised transforms, at ((|my| Ox) + |mx|) Oz
+// + |mz| (Ox = Mx/2 + 1, Oz = Mz/2 + 1).
 #include <cmath>
 
 #include "apm_kernels.hpp"
@@ -134,7 +135,9 @@ __global__ void k_influence(InfluenceParams p, double2* __restrict__ out) {
       gp = jm + (gp - gref);
     }
   }
-  out[i] = make_double2(gf * p.norm, gp * p.norm);
+  // stored kz-fastest, ((my Ox) + mx) Oz + mz: the z pass reads each column's
+  // multipliers as one contiguous run
+  out[((int64_t)my * Ox + mx) * Oz + mz] = make_double2(gf * p.norm, gp * p.norm);
 }
 
 hipError_t launch_influence(const InfluenceParams& p, double2* out, hipStream_t s) {
