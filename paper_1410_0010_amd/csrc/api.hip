@@ -589,8 +589,8 @@ apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y
   return APM_OK;
 }
 
-// TSC deposit of a prepared batch (Sec. 2), on the context's stream: six launches --
-// clear, tile count, scans, scatter, tile deposit, finalize.
+// TSC deposit of a prepared batch (Sec. 2), on the context's stream: eight launches --
+// clear, tile count, three scan launches, scatter, tile deposit, finalize.
 template <typename T>
 apm_status deposit_launch_t(apm_ctx c, const DepBatch<T>& d) {
   const DepIO<T>& io = d.io;
@@ -1009,7 +1009,8 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
       APM_TRY(ensure(c, c->adj_gas[l], (size_t)std::max<int64_t>(P.levels[l].gas_elems, 1) * 8,
                      "gas cotangents"));
   }
-  // per particle, 4 FP64 each: the interpolation transpose's slot and one per level
+  // per particle, one 4-vector of T each: the interpolation transpose's record and
+  // one per level
   APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * sizeof(V4<T>) * (nl + 1),
                  "particle cotangents"));
   ZeroList zl{};

@@ -6,9 +6,10 @@
 // grown by one cell), with block-aggregated atomics (one global atomic per distinct
 // tile in a block of 2048 particles), and scattered tile by tile as 16 B records (s_x, s_y, s_z, m),
 // s = x/dx - binning-box origin, plus the original index.  A work item is one tile's chunk of at most kChunk
-// particles; its block accumulates the 27 TSC contributions of every particle in
-// a 10^3 halo-extended tile in LDS with FP64 atomics, then adds the non-zero cells
-// to an FP64 key-box grid with global atomics.  A finalize pass divides by dx^3,
+// particles; its block counting-sorts the chunk by cell, sums the 27 TSC
+// contributions of each same-cell run in registers, adds them to a 10^3
+// halo-extended tile in LDS with FP64 atomics, then adds the non-zero cells to an
+// FP64 key-box grid with global atomics.  A finalize pass divides by dx^3,
 // adds the gas and writes the GMF in the working precision.  Heavy tiles (a
 // Plummer core holds ~1e5 particles per tile on the root) are split across many
 // blocks, so the load is balanced; FP64 accumulation keeps the result at the
