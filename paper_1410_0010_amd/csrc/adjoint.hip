@@ -187,7 +187,7 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
 
 // Position part of the interpolation transpose: one thread per tile-sorted entry of a
 // level (neighbouring lanes gather neighbouring cells), owned entries only:
-//   pint[i] = (1/dx) sum_f grad w(f) . <F(f), cot_i>
+//   pint[level][q] = (1/dx) sum_f grad w(f) . <F(f), cot_i>
 // with F the forward composed field of the owner grid and cot_i the particle's
 // cotangent (abar, phibar + wbar m / 2).  One writer per particle.
 template <typename T>
@@ -249,7 +249,8 @@ k_adj_interp_grad(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc*
     }
   }
   const double inv = 1.0 / g.dx;
-  io.pint[i] = V4<T>{(T)(gx * inv), (T)(gy * inv), (T)(gz * inv), (T)0};
+  // at the entry's sorted position on its owner level (coalesced), not at i
+  io.pint[lb][q] = V4<T>{(T)(gx * inv), (T)(gy * inv), (T)(gz * inv), (T)0};
 }
 
 template <typename T>
@@ -484,7 +485,7 @@ k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
         gz += wx[dx] * wy[dy] * dwz[dz] * a;
       }
   const double m = (double)v.w * L.inv_dx;
-  io.plev[lb][r.x] = V4<T>{(T)sm, (T)(m * gx), (T)(m * gy), (T)(m * gz)};   // one writer
+  io.plev[lb][q] = V4<T>{(T)sm, (T)(m * gx), (T)(m * gy), (T)(m * gz)};   // sorted position
 }
 
 template <typename T>
@@ -498,7 +499,8 @@ hipError_t launch_adj_deposit_particles(const AdjIO<T>& io, const DepLevel* tab,
 // ---- outputs -----------------------------------------------------------------------------
 // mbar, xbar = the sum over the levels the particle was binned on (key >= 0) of the
 // deposit transpose, plus the interpolation transpose's position gradient and
-// wbar Phi_p / 2 (mass) for owned particles.
+// wbar Phi_p / 2 (mass) for owned particles.  Each level's terms are read at the
+// particle's sorted position there, count[key] + rank (the forward binning's).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_adj_finish(AdjIO<T> io, const DepLevel* __restrict__ tab, const int32_t* __restrict__ owner,
@@ -507,14 +509,20 @@ k_adj_finish(AdjIO<T> io, const DepLevel* __restrict__ tab, const int32_t* __res
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= io.npart) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const int32_t og = owner[i];
   for (int l = 0; l < io.nlev; ++l) {
-    if (as_global<int32_t>(tab[l].key)[i] < 0) continue;
-    const V4<T> o = load_v4<T>(io.plev[l], i);
+    // the particle's entry on level l: sorted position count[key] + rank
+    const int32_t key = as_global<int32_t>(tab[l].key)[i];
+    if (key < 0) continue;
+    const int32_t q = as_global<int32_t>(tab[l].count)[key] + as_global<int32_t>(tab[l].rank)[i];
+    const V4<T> o = load_v4<T>(io.plev[l], q);
     s0 += (double)o.x; s1 += (double)o.y; s2 += (double)o.z; s3 += (double)o.w;
+    if (og >= tab[l].first && og < tab[l].first + tab[l].ngrids) {   // owned on this level
+      const V4<T> pi = load_v4<T>(io.pint[l], q);
+      s1 += (double)pi.x; s2 += (double)pi.y; s3 += (double)pi.z;
+    }
   }
-  if (owner[i] >= 0) {
-    const V4<T> pi = load_v4<T>(io.pint, i);
-    s1 += (double)pi.x; s2 += (double)pi.y; s3 += (double)pi.z;
+  if (og >= 0) {
     if (io.wbar != 0.0 && pot) s0 += io.wbar * 0.5 * (double)pot[i];
   }
   if (mb) mb[i] = (T)s0;

@@ -1009,9 +1009,9 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
       APM_TRY(ensure(c, c->adj_gas[l], (size_t)std::max<int64_t>(P.levels[l].gas_elems, 1) * 8,
                      "gas cotangents"));
   }
-  // per particle, one 4-vector of T each: the interpolation transpose's record and
-  // one per level
-  APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * sizeof(V4<T>) * (nl + 1),
+  // per level and sorted entry, two 4-vectors of T: the interpolation transpose's
+  // record and the deposit transpose's
+  APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * sizeof(V4<T>) * 2 * nl,
                  "particle cotangents"));
   ZeroList zl{};
   hipError_t zerr = hipSuccess;
@@ -1032,8 +1032,10 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
   const bool pot_only = !abx && !aby && !abz;       // the Phi cotangent alone flows back
   io.c0 = pot_only ? 3 : 0;
   V4<T>* pacc = (V4<T>*)c->adj_pacc.p;
-  io.pint = pacc;
-  for (int l = 0; l < nl; ++l) io.plev[l] = pacc + (int64_t)n * (l + 1);
+  for (int l = 0; l < nl; ++l) {
+    io.plev[l] = pacc + (int64_t)n * (2 * l);
+    io.pint[l] = pacc + (int64_t)n * (2 * l + 1);
+  }
   int64_t iblk = 0, fblk = 0, pblk = 0;
   const int64_t nbp = (n + kBlock - 1) / kBlock;
   for (int l = 0; l < nl; ++l) {

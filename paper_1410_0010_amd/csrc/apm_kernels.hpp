@@ -224,13 +224,13 @@ template <typename T> struct AdjIO {
   const T* gmf_bar[kMaxLevels];        // GMF cotangents
   double* gas_bar[kMaxLevels];         // own-gas cotangent of the level, or null
   double* pgas_bar[kMaxLevels];        // the parent level's gas cotangent, or null
-  // Per-particle partial results, in the working precision T (each is one term of a
-  // sum over at most a few levels, formed in FP64 and rounded once; one scattered
-  // record per particle and level):
-  V4<T>* pint;                         // the interpolation transpose's position gradient
-                                       // (x, y, z; owned particles)
+  // Per-entry partial results, in the working precision T (each is one term of a
+  // sum over at most a few levels, formed in FP64 and rounded once), stored at the
+  // entry's tile-sorted position on its level (coalesced):
+  V4<T>* pint[kMaxLevels];             // per level: the interpolation transpose's
+                                       // position gradient (x, y, z; owned entries)
   V4<T>* plev[kMaxLevels];             // per level: the deposit transpose's
-                                       // (mbar, xbar, ybar, zbar) (binned particles)
+                                       // (mbar, xbar, ybar, zbar) (binned entries)
 };
 template <typename T> hipError_t launch_adj_interp(const AdjIO<T>& io, const DepLevel* tab,
                                                    const GridDesc* grids, hipStream_t s);
