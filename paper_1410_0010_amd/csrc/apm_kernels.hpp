@@ -195,13 +195,16 @@ template <typename T> struct InterpIO {
   int32_t nlev;
   int64_t blk0[kMaxLevels + 1];        // blocks of level b: [blk0[b], blk0[b + 1])
   const V4<T>* fld[kMaxLevels];
-  V4<T>* res;                          // (a_x, a_y, a_z, Phi) per particle, original order
+  V4<T>* res[kMaxLevels];              // per level: (a_x, a_y, a_z, Phi) of each owned
+                                       // entry at its tile-sorted position (coalesced)
 };
 template <typename T> hipError_t launch_interp_sorted(const InterpIO<T>& io, const DepLevel* tab,
                                                       const GridDesc* grids, hipStream_t s);
-// res -> the four per-particle output arrays (zero where owner < 0); pot may be null
-template <typename T> hipError_t launch_unpack(const V4<T>* res, const int32_t* owner, int64_t npart,
-                                               T* ax, T* ay, T* az, T* pot, hipStream_t s);
+// the records -> the four per-particle output arrays, each particle's read at its
+// sorted position on its owner's level (zero where owner < 0); pot may be null
+template <typename T> hipError_t launch_unpack(const InterpIO<T>& io, const DepLevel* tab,
+                                               const int32_t* owner, int64_t npart, T* ax, T* ay,
+                                               T* az, T* pot, hipStream_t s);
 // ---- reverse sweep (adjoint.hip) ----
 struct ZeroList {                      // FP64 ranges to clear in one launch
   double* p[48];

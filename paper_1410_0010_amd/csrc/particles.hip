@@ -638,29 +638,39 @@ __global__ void __launch_bounds__(kBlock) k_interp_sorted(InterpIO<T> io, const 
   const V4<T> a = tsc_gather<T>(io.fld[lb] + off, nx, ny, nz, (int)fx - lx, (int)fy - ly,
                                 (int)fz - lz, v.x - fx - (T)0.5, v.y - fy - (T)0.5,
                                 v.z - fz - (T)0.5);
-  io.res[r.x] = a;                                   // one scattered record, not four
+  io.res[lb][q] = a;                                 // sorted position: a coalesced store
 }
 
-// Records in particle order -> the four output arrays (coalesced on both sides).
+// Records -> the four output arrays (coalesced stores): particle i's record is read
+// at its sorted position count[key] + rank on its owner's level.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_unpack(const V4<T>* __restrict__ res,
+__global__ void __launch_bounds__(kBlock) k_unpack(InterpIO<T> io, const DepLevel* __restrict__ tab,
                                                    const int32_t* __restrict__ owner, int64_t npart,
                                                    T* __restrict__ ax, T* __restrict__ ay,
                                                    T* __restrict__ az, T* __restrict__ pot) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= npart) return;
-  V4<T> v = load_v4<T>(res, i);
-  if (owner[i] < 0) v = V4<T>{0, 0, 0, 0};
+  const int32_t og = owner[i];
+  V4<T> v = V4<T>{0, 0, 0, 0};
+  if (og >= 0) {
+    int l = 0;
+    while (l + 1 < io.nlev && og >= tab[l + 1].first) ++l;   // levels hold ascending grids
+    const DepLevel& L = tab[l];
+    const int32_t q = as_global<int32_t>(L.count)[as_global<int32_t>(L.key)[i]] +
+                      as_global<int32_t>(L.rank)[i];
+    v = load_v4<T>(io.res[l], q);
+  }
   ax[i] = v.x; ay[i] = v.y; az[i] = v.z;
   if (pot) pot[i] = v.w;
 }
 
 template <typename T>
-hipError_t launch_unpack(const V4<T>* res, const int32_t* owner, int64_t npart, T* ax, T* ay, T* az,
-                         T* pot, hipStream_t s) {
+hipError_t launch_unpack(const InterpIO<T>& io, const DepLevel* tab, const int32_t* owner,
+                         int64_t npart, T* ax, T* ay, T* az, T* pot, hipStream_t s) {
   if (npart <= 0) return hipSuccess;
   const unsigned nb = (unsigned)((npart + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_unpack<T>), dim3(nb), dim3(kBlock), 0, s, res, owner, npart, ax, ay, az, pot);
+  hipLaunchKernelGGL((k_unpack<T>), dim3(nb), dim3(kBlock), 0, s, io, tab, owner, npart, ax, ay, az,
+                     pot);
   return hipGetLastError();
 }
 
@@ -682,8 +692,8 @@ hipError_t launch_interp_sorted(const InterpIO<T>& io, const DepLevel* tab, cons
                                       int64_t, int32_t*, T*, T*, T*, T*, hipStream_t);          \
   template hipError_t launch_interp_sorted<T>(const InterpIO<T>&, const DepLevel*,              \
                                               const GridDesc*, hipStream_t);                    \
-  template hipError_t launch_unpack<T>(const V4<T>*, const int32_t*, int64_t, T*, T*, T*, T*,    \
-                                       hipStream_t);                                            \
+  template hipError_t launch_unpack<T>(const InterpIO<T>&, const DepLevel*, const int32_t*,     \
+                                       int64_t, T*, T*, T*, T*, hipStream_t);                   \
   template hipError_t launch_interp<T>(const GridDesc*, int32_t, const V4<T>*, const T*,       \
                                        const T*, const T*, const int32_t*, int64_t, T*, T*, T*, \
                                        T*, hipStream_t);
