@@ -339,20 +339,35 @@ k_adj_restrict(const GridDesc* __restrict__ grids, int32_t first, int32_t count,
   if (local >= cells) return;
   const int q[3] = {flo[0] + (int)(local % fn[0]), flo[1] + (int)((local / fn[0]) % fn[1]),
                     flo[2] + (int)(local / ((int64_t)fn[0] * fn[1]))};
+  // the 4 child cells per axis, clamped into the box with weight 0 outside, so a
+  // row's four loads issue together
   const double wts[4] = {0.25, 0.75, 0.75, 0.25};
+  int ci[3][4];
+  double cw[3][4];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = 2 * q[a] - 1 + k - g.fld_lo[a];
+      const bool ok = c >= 0 && c < g.fld_n[a];
+      ci[a][k] = ok ? c : 0;
+      cw[a][k] = ok ? wts[k] : 0.0;
+    }
+  const V4<double>* cb = reinterpret_cast<const V4<double>*>(child_bar) + g.fld_offset;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
   for (int kz = 0; kz < 4; ++kz) {
-    const int cz = 2 * q[2] - 1 + kz - g.fld_lo[2];
-    if (cz < 0 || cz >= g.fld_n[2]) continue;
+#pragma unroll
     for (int ky = 0; ky < 4; ++ky) {
-      const int cy = 2 * q[1] - 1 + ky - g.fld_lo[1];
-      if (cy < 0 || cy >= g.fld_n[1]) continue;
+      const int64_t row = ((int64_t)ci[2][kz] * g.fld_n[1] + ci[1][ky]) * g.fld_n[0];
+      V4<double> v[4];
+#pragma unroll
+      for (int kx = 0; kx < 4; ++kx) v[kx] = load_v4<double>(cb, row + ci[0][kx]);
+      const double wzy = cw[2][kz] * cw[1][ky];
+#pragma unroll
       for (int kx = 0; kx < 4; ++kx) {
-        const int cx = 2 * q[0] - 1 + kx - g.fld_lo[0];
-        if (cx < 0 || cx >= g.fld_n[0]) continue;
-        const double w = wts[kz] * wts[ky] * wts[kx];
-        const double* a = child_bar + 4 * (g.fld_offset + ((int64_t)cz * g.fld_n[1] + cy) * g.fld_n[0] + cx);
-        s0 += w * a[0]; s1 += w * a[1]; s2 += w * a[2]; s3 += w * a[3];
+        const double w = wzy * cw[0][kx];
+        s0 += w * v[kx].x; s1 += w * v[kx].y; s2 += w * v[kx].z; s3 += w * v[kx].w;
       }
     }
   }
