@@ -400,97 +400,125 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
 #pragma unroll
   for (int k = 0; k < 8; ++k) pin4(rec[k]);
   __syncthreads();                                   // counters cleared
-  // counting sort of the chunk by cell of the tile (cells clamped into the tile
-  // defensively; every binned particle's cell is inside its tile)
-  int cell[8], rk[8];
+  if (n <= kBlock) {
+    // a small chunk (at most one record per thread): each record's 27 weighted masses
+    // go straight to the LDS tile; sorting would cost more than it saves
+    if ((int)threadIdx.x < n) {
+      const V4<T> v = rec[0];
+      const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
+      const int ix = min(max((int)fx - bx, 0), kTile - 1), iy = min(max((int)fy - by, 0), kTile - 1),
+                iz = min(max((int)fz - bz, 0), kTile - 1);
+      const double tx = (double)(v.x - fx) - 0.5, ty = (double)(v.y - fy) - 0.5,
+                   tz = (double)(v.z - fz) - 0.5;
+      const double wx[3] = {0.5 * (0.5 - tx) * (0.5 - tx), 0.75 - tx * tx, 0.5 * (0.5 + tx) * (0.5 + tx)};
+      const double wy[3] = {0.5 * (0.5 - ty) * (0.5 - ty), 0.75 - ty * ty, 0.5 * (0.5 + ty) * (0.5 + ty)};
+      const double wz[3] = {0.5 * (0.5 - tz) * (0.5 - tz), 0.75 - tz * tz, 0.5 * (0.5 + tz) * (0.5 + tz)};
+      const double m = (double)v.w;
+      double* base = acc + (iz * kTH + iy) * kTH + ix;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    cell[k] = -1;
-    rk[k] = 0;
-    if ((int)threadIdx.x + k * kBlock < n) {
-      const int ix = min(max((int)floor(rec[k].x) - bx, 0), kTile - 1),
-                iy = min(max((int)floor(rec[k].y) - by, 0), kTile - 1),
-                iz = min(max((int)floor(rec[k].z) - bz, 0), kTile - 1);
-      cell[k] = (iz * kTile + iy) * kTile + ix;
-      rk[k] = atomicAdd(&cstart[cell[k]], 1);
-    }
-  }
-  __syncthreads();
-  {                                                  // exclusive scan of the 512 counts
-    static_assert(kCells == 2 * kBlock, "two cells per thread");
-    const int a = cstart[2 * threadIdx.x], b = cstart[2 * threadIdx.x + 1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int incl = a + b;
+      for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int o = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += o;
-    }
-    __shared__ int wsum[kBlock / 64];
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    int wbase = 0;
+        for (int dy = 0; dy < 3; ++dy) {
+          const double mzy = m * wz[dz] * wy[dy];
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) wbase += w < wave ? wsum[w] : 0;
-    const int ex = wbase + incl - (a + b);
-    cstart[2 * threadIdx.x] = ex;
-    cstart[2 * threadIdx.x + 1] = ex + a;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-    if (cell[k] >= 0) srec[cstart[cell[k]] + rk[k]] = nvec4<T>{rec[k].x, rec[k].y, rec[k].z, rec[k].w};
-  __syncthreads();
-  // eight consecutive sorted records per thread: a run of one cell accumulates its
-  // 27 weighted masses in registers and adds them to the tile once
-  double a27[27];
-#pragma unroll
-  for (int c = 0; c < 27; ++c) a27[c] = 0.0;
-  int cur = -1;
-  auto flush = [&](int cl) {
-    const int ix = cl % kTile, iy = (cl / kTile) % kTile, iz = cl / (kTile * kTile);
-    double* base = acc + (iz * kTH + iy) * kTH + ix;  // halo tile index of cell i0 + d - 1
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          atomicAdd(base + (dz * kTH + dy) * kTH + dx, a27[(dz * 3 + dy) * 3 + dx]);
-          a27[(dz * 3 + dy) * 3 + dx] = 0.0;
+          for (int dx = 0; dx < 3; ++dx) atomicAdd(base + (dz * kTH + dy) * kTH + dx, mzy * wx[dx]);
         }
-  };
-  for (int j = 0; j < 8; ++j) {
-    const int e = (int)threadIdx.x * 8 + j;
-    if (e >= n) break;
-    const nvec4<T> v = srec[e];
-    const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
-    const int ix = min(max((int)fx - bx, 0), kTile - 1), iy = min(max((int)fy - by, 0), kTile - 1),
-              iz = min(max((int)fz - bz, 0), kTile - 1);
-    const int cl = (iz * kTile + iy) * kTile + ix;
-    if (cl != cur) {
-      if (cur >= 0) flush(cur);
-      cur = cl;
     }
-    const double tx = (double)(v.x - fx) - 0.5, ty = (double)(v.y - fy) - 0.5,
-                 tz = (double)(v.z - fz) - 0.5;
-    const double wx[3] = {0.5 * (0.5 - tx) * (0.5 - tx), 0.75 - tx * tx, 0.5 * (0.5 + tx) * (0.5 + tx)};
-    const double wy[3] = {0.5 * (0.5 - ty) * (0.5 - ty), 0.75 - ty * ty, 0.5 * (0.5 + ty) * (0.5 + ty)};
-    const double wz[3] = {0.5 * (0.5 - tz) * (0.5 - tz), 0.75 - tz * tz, 0.5 * (0.5 + tz) * (0.5 + tz)};
-    const double m = (double)v.w;
+  } else {
+    // counting sort of the chunk by cell of the tile (cells clamped into the tile
+    // defensively; every binned particle's cell is inside its tile)
+    int cell[8], rk[8];
 #pragma unroll
-    for (int dz = 0; dz < 3; ++dz) {
-      const double mz = m * wz[dz];
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy) {
-        const double mzy = mz * wy[dy];
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) a27[(dz * 3 + dy) * 3 + dx] += mzy * wx[dx];
+    for (int k = 0; k < 8; ++k) {
+      cell[k] = -1;
+      rk[k] = 0;
+      if ((int)threadIdx.x + k * kBlock < n) {
+        const int ix = min(max((int)floor(rec[k].x) - bx, 0), kTile - 1),
+                  iy = min(max((int)floor(rec[k].y) - by, 0), kTile - 1),
+                  iz = min(max((int)floor(rec[k].z) - bz, 0), kTile - 1);
+        cell[k] = (iz * kTile + iy) * kTile + ix;
+        rk[k] = atomicAdd(&cstart[cell[k]], 1);
       }
     }
+    __syncthreads();
+    {                                                  // exclusive scan of the 512 counts
+      static_assert(kCells == 2 * kBlock, "two cells per thread");
+      const int a = cstart[2 * threadIdx.x], b = cstart[2 * threadIdx.x + 1];
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      int incl = a + b;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+      }
+      __shared__ int wsum[kBlock / 64];
+      if (lane == 63) wsum[wave] = incl;
+      __syncthreads();
+      int wbase = 0;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w) wbase += w < wave ? wsum[w] : 0;
+      const int ex = wbase + incl - (a + b);
+      cstart[2 * threadIdx.x] = ex;
+      cstart[2 * threadIdx.x + 1] = ex + a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (cell[k] >= 0) srec[cstart[cell[k]] + rk[k]] = nvec4<T>{rec[k].x, rec[k].y, rec[k].z, rec[k].w};
+    __syncthreads();
+    // eight consecutive sorted records per thread: a run of one cell accumulates its
+    // 27 weighted masses in registers and adds them to the tile once
+    double a27[27];
+#pragma unroll
+    for (int c = 0; c < 27; ++c) a27[c] = 0.0;
+    int cur = -1;
+    auto flush = [&](int cl) {
+      const int ix = cl % kTile, iy = (cl / kTile) % kTile, iz = cl / (kTile * kTile);
+      double* base = acc + (iz * kTH + iy) * kTH + ix;  // halo tile index of cell i0 + d - 1
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            atomicAdd(base + (dz * kTH + dy) * kTH + dx, a27[(dz * 3 + dy) * 3 + dx]);
+            a27[(dz * 3 + dy) * 3 + dx] = 0.0;
+          }
+    };
+    for (int j = 0; j < 8; ++j) {
+      const int e = (int)threadIdx.x * 8 + j;
+      if (e >= n) break;
+      const nvec4<T> v = srec[e];
+      const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
+      const int ix = min(max((int)fx - bx, 0), kTile - 1), iy = min(max((int)fy - by, 0), kTile - 1),
+                iz = min(max((int)fz - bz, 0), kTile - 1);
+      const int cl = (iz * kTile + iy) * kTile + ix;
+      if (cl != cur) {
+        if (cur >= 0) flush(cur);
+        cur = cl;
+      }
+      const double tx = (double)(v.x - fx) - 0.5, ty = (double)(v.y - fy) - 0.5,
+                   tz = (double)(v.z - fz) - 0.5;
+      const double wx[3] = {0.5 * (0.5 - tx) * (0.5 - tx), 0.75 - tx * tx, 0.5 * (0.5 + tx) * (0.5 + tx)};
+      const double wy[3] = {0.5 * (0.5 - ty) * (0.5 - ty), 0.75 - ty * ty, 0.5 * (0.5 + ty) * (0.5 + ty)};
+      const double wz[3] = {0.5 * (0.5 - tz) * (0.5 - tz), 0.75 - tz * tz, 0.5 * (0.5 + tz) * (0.5 + tz)};
+      const double m = (double)v.w;
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz) {
+        const double mz = m * wz[dz];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const double mzy = mz * wy[dy];
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) a27[(dz * 3 + dy) * 3 + dx] += mzy * wx[dx];
+        }
+      }
+    }
+    if (cur >= 0) flush(cur);
   }
-  if (cur >= 0) flush(cur);
   __syncthreads();
+  // flush: consecutive threads take consecutive halo-tile cells, so a wave's atomics
+  // fall on a few rows of the key-box grid
   const int tx0 = ox - 1, ty0 = oy - 1, tz0 = oz - 1;
   for (int c = threadIdx.x; c < kTH3; c += kBlock) {
     const double v = acc[c];
