@@ -76,7 +76,7 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
   if (item >= total) return;                        // uniform for the block
   const int tile = wk.x;
   const int64_t begin = wk.y, end = wk.z;
-  for (int c = threadIdx.x; c < KG * NC * kTH3; c += kBlock) acc[c] = 0.0;
+  if (threadIdx.x < KG) gsl[threadIdx.x] = INT32_MAX;
   const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
             oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;
   static_assert(kChunk == 8 * kBlock, "a chunk is eight records per thread");
@@ -92,8 +92,9 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) pin4(rec[k]);
-  // the KG smallest distinct owner grids of the chunk, one round each
-  int prev = -1;
+  // the KG smallest distinct owner grids of the chunk, one round each, until a round
+  // finds none (the usual chunk has one); then only those tiles are cleared
+  int prev = -1, ng = 0;
   for (int r = 0; r < KG; ++r) {
     if (threadIdx.x == 0) gnext = INT32_MAX;
     __syncthreads();
@@ -101,10 +102,14 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
     for (int k = 0; k < 8; ++k)
       if (ref[k].y > prev) atomicMin(&gnext, ref[k].y);
     __syncthreads();
-    prev = gnext;
+    prev = gnext;                                    // the same value in every thread
     if (threadIdx.x == 0) gsl[r] = prev;
     __syncthreads();
+    if (prev == INT32_MAX) break;
+    ++ng;
   }
+  for (int c = threadIdx.x; c < ng * NC * kTH3; c += kBlock) acc[c] = 0.0;
+  __syncthreads();
   double* fbar = io.fbar[lb];
   const int c0 = 4 - NC;                            // first component carried
 #pragma unroll
