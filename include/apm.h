@@ -158,7 +158,9 @@ apm_status apm_owner(apm_ctx ctx, apm_dtype dtype, const void* x, const void* y,
  *   gmf         out: packed GMF buffer of `level` (gmf_elems scalars)
  * The TSC weights and the accumulation are FP64 for both dtypes (the mass of a
  * cell is summed in FP64 and rounded once to the dtype), so the FP32 result is
- * the FP32 rounding of the FP64 sum up to the order of additions. */
+ * the FP32 rounding of the FP64 sum up to the order of additions.  The level's
+ * library-owned binning is rebuilt for these particles, so the state that
+ * apm_solve_adjoint needs is gone until the next apm_solve. */
 apm_status apm_deposit(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* x,
                        const void* y, const void* z, const void* m, int64_t npart,
                        const void* gas, const void* parent_gas, void* gmf);
@@ -310,7 +312,10 @@ apm_status apm_set_graph(apm_ctx ctx, int32_t enable);
  * later calls.  FFT sizes themselves are part of the numeric contract and are not
  * tuned.  The choices and timings (microseconds per launch) are written as a JSON
  * object to `report` (cap bytes, NUL-terminated, may be NULL).  Synchronises.
- * Errors: APM_ERR_STATE if no apm_solve of this dtype ran yet. */
+ * The trial launches overwrite the library-owned level fields, so
+ * apm_solve_adjoint, the gas term of apm_solve_totals and apm_field_ptr's contents
+ * need a new apm_solve after this call (the first two return APM_ERR_STATE until
+ * then).  Errors: APM_ERR_STATE if no apm_solve of this dtype ran yet. */
 apm_status apm_autotune(apm_ctx ctx, apm_dtype dtype, int32_t reps, char* report, int32_t cap);
 
 /* ------------------------------------------------------- kernel timing ------ */

@@ -864,6 +864,7 @@ apm_status autotune_t(apm_ctx c, apm_dtype dt, int reps) {
   c->tune_report = rep.str();
   drop_graph(c);
   c->gkey.clear();
+  c->last_solve.clear();                            // the trial launches wrote the level fields
   return APM_OK;
 }
 
@@ -1362,12 +1363,14 @@ apm_status apm_deposit(apm_ctx c, apm_dtype dt, int32_t level, const void* x, co
     const float* g = (const float*)gas;
     const float* pg = (const float*)parent_gas;
     float* out = (float*)gmf;
+    c->last_solve.clear();                           // the level's binning is replaced
     return deposit_levels_t<float>(c, level, 1, (const float*)x, (const float*)y, (const float*)z,
                                    (const float*)m, npart, nullptr, &g, &pg, &out);
   }
   const double* g = (const double*)gas;
   const double* pg = (const double*)parent_gas;
   double* out = (double*)gmf;
+  c->last_solve.clear();                             // the level's binning is replaced
   return deposit_levels_t<double>(c, level, 1, (const double*)x, (const double*)y,
                                   (const double*)z, (const double*)m, npart, nullptr, &g, &pg, &out);
 }
@@ -1471,6 +1474,17 @@ static apm_status solve_totals_check(apm_ctx c, apm_dtype dt, const void* m, int
   return APM_OK;
 }
 
+// The gas term reads the composed level fields: they must be those of the last
+// apm_solve of this dtype (apm_autotune and apm_deposit invalidate them).
+static apm_status solve_totals_gas_check(apm_ctx c, apm_dtype dt, const void* const* gas) {
+  bool any = false;
+  for (size_t l = 0; gas && l < c->plan.levels.size(); ++l) any = any || gas[l];
+  if (any && (c->last_solve.empty() || c->last_solve[0] != (uintptr_t)dt))
+    return fail(APM_ERR_STATE, "apm_solve_totals: the level fields are not those of an apm_solve "
+                               "of this dtype (apm_autotune or apm_deposit ran since)");
+  return APM_OK;
+}
+
 static apm_status solve_totals_into(apm_ctx c, apm_dtype dt, const void* m, int64_t npart,
                                     const void* const* gas, const void* ax, const void* ay,
                                     const void* az, const void* pot, double* out_dev) {
@@ -1485,6 +1499,7 @@ apm_status apm_solve_totals(apm_ctx c, apm_dtype dt, const void* m, int64_t npar
                             const void* const* gas, const void* ax, const void* ay,
                             const void* az, const void* pot, double* out) {
   APM_TRY(solve_totals_check(c, dt, m, npart, ax, ay, az));
+  APM_TRY(solve_totals_gas_check(c, dt, gas));
   if (!out) return fail(APM_ERR_INVALID, "apm_solve_totals: NULL out");
   const int nl = (int)c->plan.levels.size();
   APM_TRY(ensure(c, c->totals, (size_t)(kTotPart + (kMaxLevels + 4) * kMaxParts) * 8, "totals"));
@@ -1500,6 +1515,7 @@ apm_status apm_solve_totals_async(apm_ctx c, apm_dtype dt, const void* m, int64_
                                   const void* const* gas, const void* ax, const void* ay,
                                   const void* az, const void* pot, double* out_dev) {
   APM_TRY(solve_totals_check(c, dt, m, npart, ax, ay, az));
+  APM_TRY(solve_totals_gas_check(c, dt, gas));
   if (!out_dev) return fail(APM_ERR_INVALID, "apm_solve_totals_async: NULL out");
   return solve_totals_into(c, dt, m, npart, gas, ax, ay, az, pot, out_dev);
 }

@@ -140,6 +140,33 @@ def test_adjoint_needs_matching_solve():
     x2 = x.clone()
     with pytest.raises(P.APMError):
         ctx.solve_adjoint(x2, y, z, m, wbar=1.0, pot=pot)
+    # the autotuner's trial launches overwrite the level fields; a deposit rebinds a
+    # level: either leaves no state for the reverse sweep until the next solve
+    ctx.autotune(torch.float64, reps=1)
+    with pytest.raises(P.APMError):
+        ctx.solve_adjoint(x, y, z, m, wbar=1.0, pot=pot)
+    ax, ay, az, pot = ctx.solve(x, y, z, m)
+    ctx.solve_adjoint(x, y, z, m, wbar=1.0, pot=pot)
+    ctx.deposit(0, x, y, z, m)
+    with pytest.raises(P.APMError):
+        ctx.solve_adjoint(x, y, z, m, wbar=1.0, pot=pot)
+
+
+def test_gas_totals_need_a_current_solve():
+    w = W.workload_plummer_gas(root_n=32, sub_n=16, nlevels=1, npart=2000)
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    x, y, z, m = (dev(a, np.float64) for a in (w.x, w.y, w.z, w.m))
+    gas = [ctx.pack_gas(l, w.gas, x.dtype) for l in range(plan.nlevels)]
+    ax, ay, az, pot = ctx.solve(x, y, z, m, gas)
+    before = ctx.solve_totals(m, ax, ay, az, pot, gas=gas)
+    ctx.autotune(torch.float64, reps=1)
+    with pytest.raises(P.APMError):
+        ctx.solve_totals(m, ax, ay, az, pot, gas=gas)
+    ctx.solve_totals(m, ax, ay, az, pot)             # no gas term: GMF and particles only
+    ax, ay, az, pot = ctx.solve(x, y, z, m, gas)
+    after = ctx.solve_totals(m, ax, ay, az, pot, gas=gas)
+    assert np.allclose(before, after, rtol=1e-12, atol=0)
 
 
 def test_autograd_energy_finite_difference_fp64():
