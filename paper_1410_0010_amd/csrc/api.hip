@@ -5,6 +5,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <tuple>
@@ -1189,7 +1190,9 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
   {
     // transform kernels may use up to the device's LDS per workgroup (once per
     // process and device, before any launch or capture)
+    static std::mutex lds_mutex;
     static std::vector<int> lds_done;
+    std::lock_guard<std::mutex> lock(lds_mutex);
     if (std::find(lds_done.begin(), lds_done.end(), device) == lds_done.end()) {
       hipError_t e = allow_lds_forward();
       if (e == hipSuccess) e = allow_lds_adjoint();
