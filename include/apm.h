@@ -32,6 +32,10 @@
  *  - Compute calls are asynchronous on the context's stream unless stated.
  *  - Every call returns an apm_status; on error apm_last_error() (thread-local)
  *    describes it.  No call aborts the process.
+ *  - A context is used by one host thread at a time (calls on it are not
+ *    synchronised with each other); different contexts may be used concurrently.
+ *    apm_solve may run part of its work on a second stream of the context, forked
+ *    from and joined back to the context's stream within the call.
  */
 #ifndef APM_H
 #define APM_H
