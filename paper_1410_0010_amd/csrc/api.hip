@@ -691,13 +691,14 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
       APM_TRY(prepare_branch_stream(c));
       HIP_TRY(hipEventRecord(c->ev_fork, c->stream), "fork record");
       HIP_TRY(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0), "fork wait");
+      // the root's branch, the longer one, is enqueued (and captured) first
+      apm_status st = deposit_launch_t<T>(c, d0);
+      if (st == APM_OK) st = convolve_t<T>(c, 0, lp);
       hipStream_t main = c->stream;
       c->stream = c->aux_stream;
-      apm_status st = deposit_launch_t<T>(c, d1);
+      if (st == APM_OK) st = deposit_launch_t<T>(c, d1);
       if (st == APM_OK) st = convolve_t<T>(c, kSubLevels, lp);
       c->stream = main;
-      if (st == APM_OK) st = deposit_launch_t<T>(c, d0);
-      if (st == APM_OK) st = convolve_t<T>(c, 0, lp);
       // join in every case, so a capture never ends with the branch left open
       HIP_TRY(hipEventRecord(c->ev_join, c->aux_stream), "join record");
       HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join, 0), "join wait");
