@@ -43,6 +43,9 @@ __all__ = [
     "workload_self_force",
     "workload_uniform_sphere",
     "inject_gas",
+    "grid_centre_gas",
+    "workload_sine_wave",
+    "workload_plummer_periodic",
     "BENCH_WORKLOADS",
 ]
 
@@ -72,6 +75,7 @@ class Workload:
     vz: Optional[np.ndarray] = None
     G: float = 1.0
     note: str = ""
+    boundary: str = "isolated"                 # root boundary: "isolated" or "periodic"
 
     @property
     def npart(self) -> int:
@@ -174,6 +178,14 @@ def root_uniform_gas(root_n, fn):
     """Sample fn(x, y, z) at root cell centres; returns (N, N, N) array [z][y][x]."""
     c = (np.arange(root_n) + 0.5) / root_n
     zz, yy, xx = np.meshgrid(c, c, c, indexing="ij")
+    return fn(xx, yy, zz)
+
+
+def grid_centre_gas(root_n, spec, fn):
+    """Sample fn(x, y, z) at the cell centres of a grid's active box; (nz, ny, nx)."""
+    d = 1.0 / (root_n * 2 ** spec.level)
+    cs = [(spec.lo[a] + np.arange(spec.n[a]) + 0.5) * d for a in range(3)]
+    zz, yy, xx = np.meshgrid(cs[2], cs[1], cs[0], indexing="ij")
     return fn(xx, yy, zz)
 
 
@@ -389,10 +401,43 @@ def workload_uniform_sphere(root_n=32, radius=0.3, rho0=1.0, rho_out=1e-10, sub=
     return Workload("uniform_sphere", root_n, grids, e, e.copy(), e.copy(), e.copy(), gas)
 
 
+def workload_sine_wave(period=1.0, root_n=64, ntracer=4096, seed=SEED_BASE + 6):
+    """The sine wave test (Sec. 3, periodic boundary): gas density
+    2 + sin(2 pi x / period) sampled at the cell centres of every grid, a periodic
+    root of root_n^3 and two static levels covering [0.34375, 0.65625)^3 (level 1)
+    and [0.421875, 0.578125)^3 (level 2).  ``ntracer`` massless particles uniform in
+    the box sample the field (their deposit adds nothing)."""
+    rng = np.random.default_rng(seed)
+    grids = [GridSpec(0, -1, (0, 0, 0), (root_n,) * 3),
+             _box_grid(root_n, 1, 0, 0.34375, 0.65625),
+             _box_grid(root_n, 2, 1, 0.421875, 0.578125)]
+    fn = lambda x, y, z: 2.0 + np.sin(2.0 * np.pi * x / period)
+    gas = [grid_centre_gas(root_n, g, fn) for g in grids]
+    p = rng.uniform(0.0, 1.0, (ntracer, 3))
+    return Workload(f"sine_wave_P{period:g}_root{root_n}", root_n, grids,
+                    p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy(), np.zeros(ntracer), gas,
+                    boundary="periodic")
+
+
+def workload_plummer_periodic(seed=SEED_BASE + 7, root_n=128, sub_n=64, nlevels=2,
+                              npart=2 ** 20, b=0.05):
+    """The nested Plummer geometry of workload_plummer_nested with a periodic root:
+    equal masses, total mass 1, no gas; positions anywhere in [0, 1)^3 (the tail
+    reaches the box edges, where the root's clouds wrap)."""
+    rng = np.random.default_rng(seed)
+    x, y, z = plummer_positions(rng, npart, b)
+    m = np.full(npart, 1.0 / npart)
+    grids = centred_nested_grids(root_n, sub_n, nlevels)
+    return Workload(f"plummer{npart}_root{root_n}_{nlevels}x{sub_n}_periodic", root_n, grids,
+                    x, y, z, m, [None] * len(grids), boundary="periodic")
+
+
 BENCH_WORKLOADS = {
     "root32_uniform_gas": workload_root32_uniform_gas,
     "plummer_nested": workload_plummer_nested,
     "clumps": workload_clumps,
     "plummer_gas": workload_plummer_gas,
     "large_nested": workload_large_nested,
+    "sine_wave": workload_sine_wave,
+    "plummer_periodic": workload_plummer_periodic,
 }

@@ -66,6 +66,20 @@ Readings of the paper used here (each one also listed in the design notes):
       get zero acceleration.
   R18 The potential is composed like the acceleration: Phi = P(Phi_parent) + phi.
   R20 Energy W = 1/2 sum_p m_p Phi_p + 1/2 sum over owned gas cells rho Phi dx^3.
+
+Periodic boundary (Sec. 2.1 for the periodic root Green's function, and the sine
+wave test of Sec. 3): with boundary="periodic"
+  R23 the root's kernels are the level-0 optimal influence functions of Eq. 5
+      (reference S_0^2, R3) on the root's own N^3 mesh, no doubling, with the
+      k = 0 value of both set to 0;
+  R24 the average density of the system, rho_bar = (sum of the in-domain particle
+      masses + root gas mass) / box volume, is subtracted from the GMF of every
+      grid, on every GMF cell, before its convolution (the solve needs zero net
+      mass); the GMF itself (and the deposited mass it reports) is the density;
+  R25 the root's TSC clouds and interpolation stencils wrap around the box edges
+      (cell indices modulo N); subgrids are unchanged (their GMF boxes lie inside
+      the root's active box);
+  R26 the leapfrog drift maps positions back into [0, 1).
 """
 
 from __future__ import annotations
@@ -125,8 +139,13 @@ class OraclePlan:
 
     def __init__(self, root_n: int, grids: Sequence, G: float = 1.0,
                  a_cells: float = A_CELLS, pad_factor: float = PAD_FACTOR,
-                 ghost: int = GHOST, fft_policy: str = "pow2", gradient: str = "spectral"):
+                 ghost: int = GHOST, fft_policy: str = "pow2", gradient: str = "spectral",
+                 boundary: str = "isolated"):
         self.root_n = int(root_n)
+        if boundary not in ("isolated", "periodic"):
+            raise ValueError(boundary)
+        self.boundary = boundary
+        self.periodic = boundary == "periodic"
         self.G = float(G)
         self.a_cells = float(a_cells)
         self.ghost = int(ghost)
@@ -143,7 +162,8 @@ class OraclePlan:
             if g.level == 0:
                 gmf_lo, gmf_n = lo.copy(), n.copy()
                 fld_lo, fld_n = lo.copy(), n.copy()
-                M = np.array([2 * self.root_n] * 3, dtype=np.int64)
+                M = np.array([self.root_n if self.periodic else 2 * self.root_n] * 3,
+                             dtype=np.int64)
             else:
                 b = self.ghost
                 gmf_lo, gmf_n = lo - b, n + 2 * b
@@ -188,7 +208,9 @@ def valid_particles(x, y, z):
 def deposit_particles(plan: OraclePlan, g: OGrid, x, y, z, m) -> np.ndarray:
     """TSC mass density of all in-domain particles on g's GMF box (R12).
 
-    rho(c) = sum_p m_p W(c - x_p) / dx^3, clouds clipped at the GMF box."""
+    rho(c) = sum_p m_p W(c - x_p) / dx^3, clouds clipped at the GMF box; on a
+    periodic root the clouds wrap around the box edges instead (R25)."""
+    wrap = plan.periodic and g.level == 0
     ok = valid_particles(x, y, z)
     x, y, z, m = x[ok], y[ok], z[ok], m[ok]
     gx, gy, gz = (int(v) for v in g.gmf_n)
@@ -199,10 +221,16 @@ def deposit_particles(plan: OraclePlan, g: OGrid, x, y, z, m) -> np.ndarray:
     wx, wy, wz = tsc_weights(tx), tsc_weights(ty), tsc_weights(tz)
     for dz in (-1, 0, 1):
         cz = iz + dz - g.gmf_lo[2]
+        if wrap:
+            cz = cz % gz
         for dy in (-1, 0, 1):
             cy = iy + dy - g.gmf_lo[1]
+            if wrap:
+                cy = cy % gy
             for dxo in (-1, 0, 1):
                 cx = ix + dxo - g.gmf_lo[0]
+                if wrap:
+                    cx = cx % gx
                 inside = (cx >= 0) & (cx < gx) & (cy >= 0) & (cy < gy) & (cz >= 0) & (cz < gz)
                 w = m * wx[dxo + 1] * wy[dy + 1] * wz[dz + 1]
                 flat = (cz * gy + cy) * gx + cx
@@ -503,8 +531,25 @@ def greens_root(plan: OraclePlan):
     return gj + dF, gj + dP
 
 
+def greens_root_periodic(plan: OraclePlan):
+    """(force kernel, potential kernel) of the periodic root on its N^3 rfft grid
+    (R23): the level-0 optimal influence functions of Eq. 5 taken directly in
+    Fourier space, zero at k = 0 (there the force multiplier vanishes and the
+    mean density carries no potential)."""
+    g = plan.grids[0]
+    kx, ky, kz = _rfft_k(g.M, g.dx)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        fo, po = influence(kx, ky, kz, g.dx, plan.a_soft(0), None, plan.G,
+                           _rfft_d(g.M, g.dx, plan.gradient))
+    fo[0, 0, 0] = 0.0
+    po[0, 0, 0] = 0.0
+    return fo, po
+
+
 def greens(plan: OraclePlan, g: OGrid):
-    return greens_root(plan) if g.level == 0 else greens_sub(plan, g)
+    if g.level > 0:
+        return greens_sub(plan, g)
+    return greens_root_periodic(plan) if plan.periodic else greens_root(plan)
 
 
 # --------------------------------------------------------------------------
@@ -609,12 +654,14 @@ def owner_of(plan: OraclePlan, x, y, z) -> np.ndarray:
 
 
 def interp(plan: OraclePlan, fields: List[np.ndarray], own: np.ndarray, x, y, z):
-    """TSC interpolation of (ax, ay, az, Phi) from each particle's owner grid (R15)."""
+    """TSC interpolation of (ax, ay, az, Phi) from each particle's owner grid (R15);
+    the stencil wraps around the box edges on a periodic root (R25)."""
     out = np.zeros((x.shape[0], 4))
     for g in plan.grids:
         sel = np.nonzero(own == g.index)[0]
         if sel.size == 0:
             continue
+        wrap = plan.periodic and g.level == 0
         F = fields[g.index]
         ix, tx = cell_coords(x[sel], g.dx)
         iy, ty = cell_coords(y[sel], g.dx)
@@ -622,10 +669,16 @@ def interp(plan: OraclePlan, fields: List[np.ndarray], own: np.ndarray, x, y, z)
         wx, wy, wz = tsc_weights(tx), tsc_weights(ty), tsc_weights(tz)
         for dz in (-1, 0, 1):
             cz = iz + dz - g.fld_lo[2]
+            if wrap:
+                cz = cz % g.fld_n[2]
             for dy in (-1, 0, 1):
                 cy = iy + dy - g.fld_lo[1]
+                if wrap:
+                    cy = cy % g.fld_n[1]
                 for dxo in (-1, 0, 1):
                     cx = ix + dxo - g.fld_lo[0]
+                    if wrap:
+                        cx = cx % g.fld_n[0]
                     inside = ((cx >= 0) & (cx < g.fld_n[0]) & (cy >= 0) & (cy < g.fld_n[1])
                               & (cz >= 0) & (cz < g.fld_n[2]))
                     w = wx[dxo + 1] * wy[dy + 1] * wz[dz + 1]
@@ -660,7 +713,9 @@ def solve(plan: OraclePlan, x, y, z, m, gas=None, cache: Optional[dict] = None):
     particles.  ``cache`` keeps Green's functions between calls (the paper caches
     frequently used Green's functions, Sec. 2.2).  Returns per-grid gmf, short
     (own short-range field), field (composed), per-particle acc (N,3), pot (N,),
-    owner, and FP64 totals: mass per grid, energy, net force on particles."""
+    owner, and FP64 totals: mass per grid, energy, net force on particles.  With a
+    periodic root the average density rho_bar (returned too) is subtracted from
+    every GMF before its convolution (R24)."""
     x = np.asarray(x, np.float64); y = np.asarray(y, np.float64)
     z = np.asarray(z, np.float64); m = np.asarray(m, np.float64)
     if gas is None:
@@ -672,7 +727,8 @@ def solve(plan: OraclePlan, x, y, z, m, gas=None, cache: Optional[dict] = None):
         if g.index not in cache:
             cache[g.index] = greens(plan, g)
     gmf = [deposit_grid(plan, g, x, y, z, m, gas) for g in plan.grids]
-    short = [convolve(plan, g, gmf[g.index], cache[g.index]) for g in plan.grids]
+    rho_bar = mean_density(plan, x, y, z, m, gas) if plan.periodic else 0.0
+    short = [convolve(plan, g, gmf[g.index] - rho_bar, cache[g.index]) for g in plan.grids]
     fld = [None] * len(plan.grids)
     for lev in range(plan.nlevels):
         for g in plan.level_grids(lev):
@@ -684,7 +740,17 @@ def solve(plan: OraclePlan, x, y, z, m, gas=None, cache: Optional[dict] = None):
     w = 0.5 * float(np.sum(m[own >= 0] * pa[own >= 0, 3])) + gas_energy(plan, fld, gas)
     fnet = (m[:, None] * pa[:, :3]).sum(axis=0)
     return dict(gmf=gmf, short=short, field=fld, owner=own, acc=pa[:, :3], pot=pa[:, 3],
-                mass=mass, energy=w, net_force=fnet)
+                mass=mass, energy=w, net_force=fnet, rho_bar=rho_bar)
+
+
+def mean_density(plan: OraclePlan, x, y, z, m, gas) -> float:
+    """Average density of the system (R24): the in-domain particle mass plus the
+    root's gas mass over the unit box."""
+    ok = valid_particles(x, y, z)
+    tot = float(np.sum(m[ok]))
+    if gas[0] is not None:
+        tot += float(np.sum(gas[0])) * plan.grids[0].dx ** 3
+    return tot
 
 
 # --------------------------------------------------------------------------
@@ -725,6 +791,13 @@ def pp_reference_accel(x, y, z, m, a: float, G: float = 1.0):
     return acc
 
 
+def wrap_unit(a: np.ndarray) -> np.ndarray:
+    """a modulo 1 in [0, 1): a - floor(a), with the value that rounds up to 1 (a tiny
+    negative a) mapped to 0, the same point of the periodic box."""
+    r = a - np.floor(a)
+    return np.where(r >= 1.0, 0.0, r)
+
+
 def leapfrog(plan: OraclePlan, x, y, z, vx, vy, vz, m, dt: float, nsteps: int,
              gas=None, every: int = 1):
     """Kick-drift-kick leapfrog with every level on the same step (no subcycling,
@@ -746,6 +819,8 @@ def leapfrog(plan: OraclePlan, x, y, z, vx, vy, vz, m, dt: float, nsteps: int,
     for s in range(nsteps):
         vx += 0.5 * dt * a[:, 0]; vy += 0.5 * dt * a[:, 1]; vz += 0.5 * dt * a[:, 2]
         x += dt * vx; y += dt * vy; z += dt * vz
+        if plan.periodic:                                  # R26
+            x, y, z = wrap_unit(x), wrap_unit(y), wrap_unit(z)
         a, w = accel(x, y, z)
         vx += 0.5 * dt * a[:, 0]; vy += 0.5 * dt * a[:, 1]; vz += 0.5 * dt * a[:, 2]
         if (s + 1) % every == 0:
