@@ -16,7 +16,12 @@ Workloads (synthetic and seeded, shaped like the paper's tests):
   plummer_gas     root 256^3 + 2 nested 128^3 levels, 2^22 Plummer particles plus a
                   lognormal k^-2 random gas field (forward + adjoint);
   large_nested    root 512^3 + 3 nested 256^3 levels, 2^24 Plummer particles plus two
-                  orbiting point masses; also 100 leapfrog steps and the energy drift.
+                  orbiting point masses; also 100 leapfrog steps and the energy drift;
+  plummer_periodic  the plummer_nested geometry with a periodic root (root FFT 128^3,
+                  not 256^3), 2^20 Plummer particles reaching the box edges (forward);
+  sine_wave       the sine wave test: periodic root 64^3 + levels over
+                  [0.34375, 0.65625)^3 and [0.421875, 0.578125)^3, gas 2 + sin(2 pi x),
+                  4096 massless tracer particles (forward).
 
 Prints one JSON line: value = particles/s of the FP32 forward step (inputs resident in
 HBM), with cells/s, the forward+adjoint step, the FP64 steps, errors against the FP64
@@ -87,6 +92,9 @@ def kernel_bytes(plan, npart, npart_level, esize):
     b["bin_scatter"] = nl * npart * (4 * esize + 8) + binned * (4 * esize + 8)
     b["interp"] = binned * (4 * esize + 8) + npart * 4 * esize   # sorted records in, a + Phi out
     b["unpack"] = npart * (4 * esize + 4 + 4 * esize)   # (a, Phi) records + owner in, 4 arrays out
+    if plan.cfg.boundary == 1:                          # periodic: the average density
+        N = plan.grids[0]["n"][0]
+        b["mean_density"] = npart * 4 * esize + N ** 3 * esize
     b["adj_interp"] = binned * (4 * esize + 8) + npart * (esize + 3 * 8)
     return b
 
@@ -117,6 +125,11 @@ WORKLOADS = {
                     "(b=0.05) + lognormal k^-2 random gas field"),
     "large_nested": ("large_nested: root 512^3 (1024^3 padded FFT) + 3 nested 256^3 levels, "
                      "2^24 Plummer particles (b=0.02) + 2 orbiting point masses m=0.1"),
+    "plummer_periodic": ("plummer_periodic: periodic root 128^3 (128^3 FFT) + 2 nested 64^3 "
+                         "levels, 2^20 Plummer particles (b=0.05) over the whole box, no gas"),
+    "sine_wave": ("sine_wave: the sine wave test, periodic root 64^3 + levels over "
+                  "[0.34375,0.65625)^3 and [0.421875,0.578125)^3 (40^3 each), gas "
+                  "2 + sin(2 pi x), 4096 massless tracers"),
 }
 
 
@@ -132,6 +145,10 @@ def make_workload(name):
         return W.workload_plummer_gas()
     if name == "large_nested":
         return W.workload_large_nested()
+    if name == "plummer_periodic":
+        return W.workload_plummer_periodic()
+    if name == "sine_wave":
+        return W.workload_sine_wave()
     raise ValueError(name)
 
 
@@ -171,13 +188,13 @@ def main():
     from paper_1410_0010_amd import Context, Plan
 
     w = make_workload(args.workload)
-    plan = Plan(w.root_n, w.grids)
+    plan = Plan(w.root_n, w.grids, boundary=w.boundary)
     ctx = Context(plan, 0)
     active = w.active_cells()
     n = w.npart
     log(f"workload {w.name}: {n} particles, {len(w.grids)} grids, {active} active cells")
     fp64_ok = not args.no_fp64 and args.workload != "large_nested"
-    do_adj = not args.no_adjoint
+    do_adj = not args.no_adjoint and w.boundary == "isolated"   # no periodic reverse sweep
 
     def tens(dtype):
         return [torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype))).to(dev)
@@ -342,12 +359,13 @@ def main():
     # errors against the FP64 oracle and the oracle's own time (CPU baseline)
     cpu = None
     err = {}
-    if not args.no_cpu_baseline and args.workload in ("plummer_nested", "root32_gas"):
+    if not args.no_cpu_baseline and args.workload in ("plummer_nested", "root32_gas",
+                                                      "plummer_periodic", "sine_wave"):
         from oracle import apm_oracle as O
         from oracle import apm_adjoint as A
         log("oracle: Green's functions (cached, as on the GPU), then one timed forward solve "
             "and one timed reverse sweep")
-        op = O.OraclePlan(w.root_n, w.grids)
+        op = O.OraclePlan(w.root_n, w.grids, boundary=w.boundary)
         cache = {g.index: O.greens(op, g) for g in op.grids}
         rd = lambda a: None if a is None else np.asarray(a, np.float32).astype(np.float64)
         x32 = [rd(a) for a in (w.x, w.y, w.z, w.m)]
@@ -407,7 +425,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload],
                    "particles": n, "active_cells": active, "grids": len(w.grids),
                    "fft_dims_first_grids": [g["fft_n"] for g in plan.grids[:4]],
-                   "gradient": "spectral"},
+                   "gradient": "spectral", "boundary": w.boundary},
         "cells_per_s": active / (r32["ms"] * 1e-3),
         "fwd_adjoint_fp32": step_info(a32),
         "fp64": step_info(r64),

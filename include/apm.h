@@ -64,9 +64,23 @@ typedef enum {
   APM_GRAD_FD2 = 1          /* two-point central difference, -i sin(k dx)/dx  */
 } apm_gradient;
 
+/* Boundary condition of the root grid (Sec. 2.1 gives the Green's function of both;
+ * the sine wave test of Sec. 3 uses the periodic one). */
+typedef enum {
+  APM_BC_ISOLATED = 0,      /* isolated: the root's kernel made isolated on the
+                               doubled mesh (James), FFT length 2 root_n (default)  */
+  APM_BC_PERIODIC = 1       /* periodic: the root's kernel is Eq. 5 taken directly
+                               in Fourier space on the root's own mesh, zero at
+                               k = 0; FFT length root_n; the average density of the
+                               system is subtracted from every grid's GMF before its
+                               convolution (zero net mass); the root's TSC clouds
+                               and interpolation stencils wrap at the box edges    */
+} apm_boundary;
+
 typedef struct {
   double G;                 /* gravitational constant [1.0]                       */
-  int32_t root_n;           /* root cells per axis, power of two in [8, 512]      */
+  int32_t root_n;           /* root cells per axis, power of two in [8, 512]
+                               (isolated) or [8, 1024] (periodic)                 */
   double a_cells;           /* S2 softening a_l = a_cells * dx_l [3.4] (Sec. 2.2) */
   double pad_factor;        /* subgrid zero padding p = ceil(pad_factor * 2 *
                                a_cells) cells per axis [0.65] (Sec. 2.2)           */
@@ -74,6 +88,7 @@ typedef struct {
   int32_t brillouin;        /* alias zones n in [-b, b]^3 in Eq. 5 [1] (Eq. 6)    */
   int32_t gradient;         /* apm_gradient [APM_GRAD_SPECTRAL]                   */
   int64_t workspace_limit;  /* bytes of device workspace allowed, 0 = no limit    */
+  int32_t boundary;         /* apm_boundary of the root [APM_BC_ISOLATED]         */
 } apm_config;
 
 /* One grid of the static hierarchy.  Grid 0 must be the root: level 0, parent
@@ -95,7 +110,8 @@ typedef struct {
   int32_t lo[3], n[3];       /* active box                                        */
   int32_t gmf_lo[3], gmf_n[3];  /* GMF box: active (root) or active +- ghost     */
   int32_t fld_lo[3], fld_n[3];  /* field box: active (root) or active +- 1       */
-  int32_t fft_n[3];          /* padded FFT lengths M (root 2 root_n, James)       */
+  int32_t fft_n[3];          /* FFT lengths M (root: 2 root_n isolated, root_n
+                                periodic; subgrids: zero-padded)                  */
   int64_t gmf_offset;        /* element offset in the level's packed GMF buffer   */
   int64_t fld_offset;        /* cell offset in the level's packed field buffer    */
   int64_t gas_offset;        /* element offset in the level's packed gas buffer   */
@@ -164,7 +180,11 @@ apm_status apm_owner(apm_ctx ctx, apm_dtype dtype, const void* x, const void* y,
  * cell is summed in FP64 and rounded once to the dtype), so the FP32 result is
  * the FP32 rounding of the FP64 sum up to the order of additions.  The level's
  * library-owned binning is rebuilt for these particles, so the state that
- * apm_solve_adjoint needs is gone until the next apm_solve. */
+ * apm_solve_adjoint needs is gone until the next apm_solve.
+ * Periodic plans: at level 0 the clouds wrap around the box edges, and the call
+ * also records in the context the average density of the system, (sum of the
+ * in-domain particle masses + sum of `gas` dx_0^3) / 1, that apm_solve_level of a
+ * subgrid level subtracts. */
 apm_status apm_deposit(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* x,
                        const void* y, const void* z, const void* m, int64_t npart,
                        const void* gas, const void* parent_gas, void* gmf);
@@ -174,7 +194,10 @@ apm_status apm_deposit(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* 
  * transformed back, the three acceleration components differenced in Fourier
  * space (a_i = IDFT(-i d_i G_force rho_hat)) and the potential with the
  * potential-optimal kernel (Phi = IDFT(G_pot rho_hat)).  Root: isolated boundary
- * on the doubled mesh; subgrids: short-range reference S_l^2 - S_{l-1}^2.
+ * on the doubled mesh, or periodic (kernel zero at k = 0); subgrids: short-range
+ * reference S_l^2 - S_{l-1}^2.  Periodic plans: a subgrid level's GMF is convolved
+ * minus the average density recorded by the last level-0 apm_deposit or apm_solve
+ * of this context (APM_ERR_STATE if there was none).
  *   gmf    packed GMF buffer of `level` (input, not modified)
  *   field  out: packed field buffer of `level`, 4 values per cell
  * The Green's functions are generated in FP64 on the device on first use and
@@ -189,7 +212,8 @@ apm_status apm_solve_level(apm_ctx ctx, apm_dtype dtype, int32_t level, const vo
 apm_status apm_accel(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* own,
                      const void* parent_field, void* field);
 
-/* TSC interpolation (same weights as the deposit) of the composed field of
+/* TSC interpolation (same weights as the deposit; wrapping at the box edges on a
+ * periodic root) of the composed field of
  * `level` to the particles whose owner grid is on `level`; writes a_x, a_y, a_z
  * and Phi of those particles only (others untouched).  pot may be NULL. */
 apm_status apm_interp(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* field,
@@ -208,7 +232,9 @@ apm_status apm_totals(apm_ctx ctx, apm_dtype dtype, const void* const* gmf, cons
 
 /* The whole forward solve in one call: owner, deposit, solve, composition and
  * interpolation of every level, in the paper's order, into library-owned level
- * buffers.  gas: host array of nlevels device pointers (or NULL entries / NULL).
+ * buffers (periodic plans: the average density is computed from the particles and
+ * the root's gas first and subtracted from every subgrid GMF; the root's kernel
+ * removes it from the root).  gas: host array of nlevels device pointers (or NULL entries / NULL).
  * ax, ay, az, pot: npart outputs (pot may be NULL).  Fields of level l can be
  * read back with apm_field_ptr after the call. */
 apm_status apm_solve(apm_ctx ctx, apm_dtype dtype, const void* x, const void* y,
@@ -262,7 +288,8 @@ apm_status apm_gas_energy(apm_ctx ctx, apm_dtype dtype, int32_t level, const voi
  * abar_x/y/z, phibar: npart values each, or NULL for zero.
  * xbar, ybar, zbar, mbar: npart outputs (any may be NULL).  gas_bar: NULL or host
  * array of nlevels device pointers, a packed active-gas cotangent of a level for
- * each level with gas (NULL entries skipped).  Asynchronous. */
+ * each level with gas (NULL entries skipped).  Asynchronous.
+ * APM_ERR_UNSUPPORTED for periodic plans. */
 apm_status apm_solve_adjoint(apm_ctx ctx, apm_dtype dtype, const void* x, const void* y,
                              const void* z, const void* m, int64_t npart, const void* const* gas,
                              const void* pot, const void* abar_x, const void* abar_y,
@@ -272,7 +299,8 @@ apm_status apm_solve_adjoint(apm_ctx ctx, apm_dtype dtype, const void* x, const 
 /* ------------------------------------------------------ time integration ---- */
 
 /* Leapfrog pieces (Sec. 2 time-centring; every level on one step, no subcycling,
- * Sec. 3.1, 3.5).  apm_kick: v += h a.  apm_drift: x += h v.  Arrays are npart
+ * Sec. 3.1, 3.5).  apm_kick: v += h a.  apm_drift: x += h v, then, for periodic
+ * plans, x - floor(x) (a value that rounds to 1 becomes 0).  Arrays are npart
  * device values of `dtype`, updated in place; asynchronous. */
 apm_status apm_kick(apm_ctx ctx, apm_dtype dtype, int64_t npart, void* vx, void* vy, void* vz,
                     const void* ax, const void* ay, const void* az, double h);

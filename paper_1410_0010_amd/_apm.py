@@ -22,6 +22,8 @@ APM_F32 = 1
 APM_F64 = 2
 APM_GRAD_SPECTRAL = 0
 APM_GRAD_FD2 = 1
+APM_BC_ISOLATED = 0
+APM_BC_PERIODIC = 1
 
 STATUS_NAMES = {0: "APM_OK", 1: "APM_ERR_INVALID", 2: "APM_ERR_OOM", 3: "APM_ERR_DEVICE",
                 4: "APM_ERR_RANGE", 5: "APM_ERR_UNSUPPORTED", 6: "APM_ERR_STATE"}
@@ -31,7 +33,8 @@ class apm_config(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double), ("root_n", ctypes.c_int32),
                 ("a_cells", ctypes.c_double), ("pad_factor", ctypes.c_double),
                 ("ghost", ctypes.c_int32), ("brillouin", ctypes.c_int32),
-                ("gradient", ctypes.c_int32), ("workspace_limit", ctypes.c_int64)]
+                ("gradient", ctypes.c_int32), ("workspace_limit", ctypes.c_int64),
+                ("boundary", ctypes.c_int32)]
 
 
 class apm_grid(ctypes.Structure):

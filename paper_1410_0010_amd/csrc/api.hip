@@ -42,6 +42,10 @@ struct apm_ctx_s {
   std::vector<DevBuf> adj_fbar, adj_gas, adj_gmf[3];
   DevBuf adj_pacc;
   std::vector<uintptr_t> last_solve;                               // (dtype, n, x, y, z, m)
+  // periodic plans: the average density (partials, then the value at kMaxParts), set
+  // by a level-0 deposit or a solve; allocated once, so job tables may hold it
+  DevBuf meanbuf;
+  bool mean_set = false;
   std::map<std::pair<int, int>, void*> tw;                        // (dtype, L)
   std::map<std::tuple<int, int, int>, void*> dsym;                // (dtype, level, M)
   std::map<std::tuple<int, int, int, int, int>, void*> kern;      // (dtype, level, Mx, My, Mz)
@@ -289,7 +293,8 @@ apm_status kernel_table(apm_ctx c, apm_dtype dt, const GridDesc& g, const void**
     ip.grad = P.cfg.gradient;
     ip.james = nullptr;
     void *b0 = nullptr, *b1 = nullptr, *ct = nullptr;
-    if (g.level == 0) {
+    const bool james = g.level == 0 && P.cfg.boundary == APM_BC_ISOLATED;
+    if (james) {
       const int N = P.cfg.root_n;
       const size_t on = (size_t)(N + 1) * (N + 1) * (N + 1);
       std::vector<double> cosv(2 * N);
@@ -304,7 +309,7 @@ apm_status kernel_table(apm_ctx c, apm_dtype dt, const GridDesc& g, const void**
       ip.james = res;
     }
     HIP_TRY(launch_influence(ip, t64, c->stream), "influence kernel");
-    if (g.level == 0) {
+    if (james) {
       HIP_TRY(hipStreamSynchronize(c->stream), "james sync");
       for (void* q : {b0, b1, ct}) {
         (void)hipFree(q);
@@ -395,6 +400,9 @@ apm_status job_list(apm_ctx c, int pass, int L, int level, int nl, const apm_ctx
     j.pitch = (g.M[0] / 2 + 1 + kRowAlign - 1) / kRowAlign * kRowAlign;
     j.gmf_off = g.gmf_offset;
     j.fld_off = g.fld_offset;
+    j.mean = (c->plan.cfg.boundary == APM_BC_PERIODIC && g.level > 0)
+                 ? (const double*)c->meanbuf.p + kMaxParts
+                 : nullptr;
     j.spec_off = c->spec_off[gi];
     j.z_off = c->z_off[gi];
     j.y_off = c->y_off[gi];
@@ -466,6 +474,9 @@ apm_status prepare_branch_stream(apm_ctx c) {
 
 template <typename T>
 apm_status solve_level_t(apm_ctx c, int32_t level, const T* gmf, T* field) {
+  if (c->plan.cfg.boundary == APM_BC_PERIODIC && level > 0 && !c->mean_set)
+    return fail(APM_ERR_STATE, "apm_solve_level: a periodic subgrid level needs the average "
+                               "density of a level-0 apm_deposit or an apm_solve first");
   LevelPtrs<T> lp{};
   lp.gmf[level] = gmf;
   lp.fld[level] = (V4<T>*)field;
@@ -556,6 +567,7 @@ apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y
     d.rep = rep;
     d.first = L.first;
     d.ngrids = L.count;
+    d.wrap = (l == 0 && P.cfg.boundary == APM_BC_PERIODIC) ? P.cfg.root_n : 0;
     d.key_cells = L.key_cells;
     d.count = (int32_t*)B.count.p;
     d.items = (int32_t*)B.items.p;
@@ -641,6 +653,22 @@ apm_status zero_t(apm_ctx c, T* p, int64_t n) {
   return APM_OK;
 }
 
+// Average density of a periodic system from the particles and the root gas into the
+// context's scalar (read by the subgrids' forward x pass).
+template <typename T>
+apm_status mean_density_t(apm_ctx c, const T* x, const T* y, const T* z, const T* m,
+                          int64_t npart, const T* root_gas) {
+  const int64_t N = c->plan.cfg.root_n;
+  const double dx = c->plan.grids[0].dx;
+  double* mb = (double*)c->meanbuf.p;
+  HIP_TRY(timed(c, "mean_density", [&] {
+            return launch_mean_density<T>(x, y, z, m, npart, root_gas, N * N * N, dx * dx * dx, mb,
+                                          mb + kMaxParts, c->stream);
+          }), "mean density");
+  c->mean_set = true;
+  return APM_OK;
+}
+
 template <typename T>
 apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, const T* m,
                         int64_t npart, const void* const* gas, T* ax, T* ay, T* az, T* pot) {
@@ -659,6 +687,8 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
             return launch_owner<T>(c->d_owner_map, (int32_t)P.levels.size(), x, y, z, npart, own,
                                    (T*)nullptr, (T*)nullptr, (T*)nullptr, (T*)nullptr, c->stream);
           }), "owner");
+  if (P.cfg.boundary == APM_BC_PERIODIC) APM_TRY(mean_density_t<T>(c, x, y, z, m, npart,
+                                                                   gas ? (const T*)gas[0] : nullptr));
   {
     const T* gl[kMaxLevels];
     const T* pg[kMaxLevels];
@@ -930,12 +960,13 @@ apm_status leapfrog_t(apm_ctx c, apm_dtype dt, T* x, T* y, T* z, T* vx, T* vy, T
   if (energy) APM_TRY(step_energy_t<T>(c, dt, m, vx, vy, vz, n, ax, ay, az, pot, gas, E));
   for (int32_t s = 0; s < nsteps; ++s) {
     HIP_TRY(timed(c, "kick_drift", [&] {
-              return launch_kick_drift<T>(n, x, y, z, vx, vy, vz, ax, ay, az, 0.5 * h, h, c->stream);
+              return launch_kick_drift<T>(n, x, y, z, vx, vy, vz, ax, ay, az, 0.5 * h, h,
+                                          c->plan.cfg.boundary == APM_BC_PERIODIC, c->stream);
             }), "leapfrog kick-drift");
     APM_TRY(solve_t<T>(c, dt, x, y, z, m, n, gas, ax, ay, az, pot));
     HIP_TRY(timed(c, "kick", [&] {
               return launch_kick_drift<T>(n, nullptr, nullptr, nullptr, vx, vy, vz, ax, ay, az,
-                                          0.5 * h, 0.0, c->stream);
+                                          0.5 * h, 0.0, 0, c->stream);
             }), "leapfrog kick");
     if (energy)
       APM_TRY(step_energy_t<T>(c, dt, m, vx, vy, vz, n, ax, ay, az, pot, gas, E + 6 * (s + 1)));
@@ -1207,6 +1238,8 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
   const Plan& P = c->plan;
   apm_status st = upload(c, (void**)&c->d_grids, P.grids.data(), sizeof(GridDesc) * P.grids.size(),
                          "grid table");
+  if (st == APM_OK && P.cfg.boundary == APM_BC_PERIODIC)
+    st = ensure(c, c->meanbuf, (size_t)(kMaxParts + 1) * 8, "average density");
   if (st != APM_OK) { apm_destroy(c); return st; }
   for (const LevelDesc& L : P.levels) {
     std::vector<int64_t> dep(L.count + 1), cmp(L.count + 1), act(L.count + 1), foot(L.count + 1);
@@ -1311,7 +1344,7 @@ apm_status apm_destroy(apm_ctx c) {
   for (void* p : c->owned) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   DevBuf* bufs[] = {&c->spec, &c->zbuf, &c->ybuf, &c->pres, &c->owner, &c->totals,
-                    &c->binned, &c->dep_tab, &c->gpart, &c->energy, &c->lf_pot};
+                    &c->binned, &c->dep_tab, &c->gpart, &c->energy, &c->lf_pot, &c->meanbuf};
   for (auto& B : c->lvb)
     for (DevBuf* b : {&B.count, &B.items, &B.work, &B.bsum, &B.accum, &B.key, &B.rank, &B.sref,
                       &B.sorted})
@@ -1363,20 +1396,29 @@ apm_status apm_deposit(apm_ctx c, apm_dtype dt, int32_t level, const void* x, co
   if (!gmf || (npart > 0 && (!x || !y || !z || !m)))
     return fail(APM_ERR_INVALID, "apm_deposit: NULL array");
   if (level == 0 && parent_gas) return fail(APM_ERR_INVALID, "apm_deposit: root has no parent gas");
+  c->last_solve.clear();                             // the level's binning is replaced
+  const bool mean = level == 0 && c->plan.cfg.boundary == APM_BC_PERIODIC;
   if (dt == APM_F32) {
     const float* g = (const float*)gas;
     const float* pg = (const float*)parent_gas;
     float* out = (float*)gmf;
-    c->last_solve.clear();                           // the level's binning is replaced
-    return deposit_levels_t<float>(c, level, 1, (const float*)x, (const float*)y, (const float*)z,
-                                   (const float*)m, npart, nullptr, &g, &pg, &out);
+    APM_TRY(deposit_levels_t<float>(c, level, 1, (const float*)x, (const float*)y, (const float*)z,
+                                    (const float*)m, npart, nullptr, &g, &pg, &out));
+    if (mean)
+      APM_TRY(mean_density_t<float>(c, (const float*)x, (const float*)y, (const float*)z,
+                                    (const float*)m, npart, g));
+    return APM_OK;
   }
   const double* g = (const double*)gas;
   const double* pg = (const double*)parent_gas;
   double* out = (double*)gmf;
-  c->last_solve.clear();                             // the level's binning is replaced
-  return deposit_levels_t<double>(c, level, 1, (const double*)x, (const double*)y,
-                                  (const double*)z, (const double*)m, npart, nullptr, &g, &pg, &out);
+  APM_TRY(deposit_levels_t<double>(c, level, 1, (const double*)x, (const double*)y,
+                                   (const double*)z, (const double*)m, npart, nullptr, &g, &pg,
+                                   &out));
+  if (mean)
+    APM_TRY(mean_density_t<double>(c, (const double*)x, (const double*)y, (const double*)z,
+                                   (const double*)m, npart, g));
+  return APM_OK;
 }
 
 apm_status apm_solve_level(apm_ctx c, apm_dtype dt, int32_t level, const void* gmf, void* field) {
@@ -1560,10 +1602,10 @@ apm_status apm_kick(apm_ctx c, apm_dtype dt, int64_t npart, void* vx, void* vy, 
   hipError_t e = dt == APM_F32
       ? launch_kick_drift<float>(npart, nullptr, nullptr, nullptr, (float*)vx, (float*)vy,
                                  (float*)vz, (const float*)ax, (const float*)ay, (const float*)az,
-                                 h, 0.0, c->stream)
+                                 h, 0.0, 0, c->stream)
       : launch_kick_drift<double>(npart, nullptr, nullptr, nullptr, (double*)vx, (double*)vy,
                                   (double*)vz, (const double*)ax, (const double*)ay,
-                                  (const double*)az, h, 0.0, c->stream);
+                                  (const double*)az, h, 0.0, 0, c->stream);
   HIP_TRY(e, "apm_kick");
   return APM_OK;
 }
@@ -1575,11 +1617,12 @@ apm_status apm_drift(apm_ctx c, apm_dtype dt, int64_t npart, void* x, void* y, v
   if (npart < 0) return fail(APM_ERR_RANGE, "apm_drift: npart < 0");
   if (npart > 0 && (!x || !y || !z || !vx || !vy || !vz))
     return fail(APM_ERR_INVALID, "apm_drift: NULL array");
+  const int wrap = c->plan.cfg.boundary == APM_BC_PERIODIC;
   hipError_t e = dt == APM_F32
       ? launch_kick_drift<float>(npart, (float*)x, (float*)y, (float*)z, (float*)vx, (float*)vy,
-                                 (float*)vz, nullptr, nullptr, nullptr, 0.0, h, c->stream)
+                                 (float*)vz, nullptr, nullptr, nullptr, 0.0, h, wrap, c->stream)
       : launch_kick_drift<double>(npart, (double*)x, (double*)y, (double*)z, (double*)vx,
-                                  (double*)vy, (double*)vz, nullptr, nullptr, nullptr, 0.0, h,
+                                  (double*)vy, (double*)vz, nullptr, nullptr, nullptr, 0.0, h, wrap,
                                   c->stream);
   HIP_TRY(e, "apm_drift");
   return APM_OK;
@@ -1698,6 +1741,8 @@ apm_status apm_solve_adjoint(apm_ctx c, apm_dtype dt, const void* x, const void*
                              void* ybar, void* zbar, void* mbar, void* const* gas_bar) {
   APM_TRY(check_ctx(c));
   APM_TRY(check_dtype(dt));
+  if (c->plan.cfg.boundary == APM_BC_PERIODIC)
+    return fail(APM_ERR_UNSUPPORTED, "apm_solve_adjoint: periodic plans have no reverse sweep");
   if (npart < 0 || npart > INT32_MAX) return fail(APM_ERR_RANGE, "apm_solve_adjoint: npart out of range");
   if (npart > 0 && (!x || !y || !z || !m))
     return fail(APM_ERR_INVALID, "apm_solve_adjoint: NULL particle array");

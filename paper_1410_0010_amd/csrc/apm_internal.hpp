@@ -23,6 +23,7 @@ struct GridDesc {
   int64_t parent_gas_offset;
   int32_t parent_lo[3], parent_n[3];          // parent active box
   int32_t parent_fld_lo[3], parent_fld_n[3];  // parent field box
+  int32_t wrap;                    // periodic root: cells per axis (stencils wrap), else 0
   double dx;
 };
 

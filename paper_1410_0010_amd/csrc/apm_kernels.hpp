@@ -59,6 +59,8 @@ struct ConvJob {
   int64_t gmf_off, fld_off, spec_off, z_off, y_off;
   const void* kern;                // octant (Gf, Gp) table
   const void* dsym[3];             // gradient symbols per axis index
+  const double* mean;              // periodic plans, subgrids: device scalar, the average
+                                   // density subtracted from the GMF; else null
 };
 int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], int nl);
 template <typename T> int default_lines(int pass, int L);
@@ -91,7 +93,8 @@ struct InfluenceParams {
   double dx, a_l, a_lm1;   // a_lm1 < 0: root (S_{-1} = 0)
   double G, norm;
   int bz, grad;
-  const double* james;     // root only: octant of the doubled-mesh reference kernel
+  const double* james;     // isolated root: octant of the doubled-mesh reference kernel
+                           // (null with a_lm1 < 0: the periodic root)
 };
 hipError_t launch_influence(const InfluenceParams& p, double2* out, hipStream_t s);
 hipError_t launch_james(int N, double dx, double a0, double G, const double* costab,
@@ -113,6 +116,7 @@ struct DepLevel {
   int32_t tiles_n[3];              // tiles per axis
   int32_t ntiles, rep;             // rep: counter replicas per tile (power of two)
   int32_t first, ngrids;           // the level's grids: [first, first + ngrids)
+  int32_t wrap;                    // periodic root: cells per axis (clouds wrap), else 0
   int64_t key_cells;
   int32_t* count;                  // ntiles * rep + 1; replica r of tile t at t rep + r;
                                    // scanned in place into start offsets
@@ -288,10 +292,18 @@ template <typename T> hipError_t launch_totals(const TotalsIO<T>& io, hipStream_
 // with nq = 1 any nparts)
 hipError_t launch_sum_parts(const double* part, int nparts, int nq, double scale, double* out,
                             hipStream_t s);
-// time integration and energy terms (dynamics.hip)
+// Average density of a periodic system: (sum of the in-domain particle masses + sum
+// of the root gas times vol) over the unit box, into out[0] (written, not added);
+// per-block partials in part (kMaxParts doubles).  gas may be null.
+template <typename T> hipError_t launch_mean_density(const T* x, const T* y, const T* z,
+                                                     const T* m, int64_t npart, const T* gas,
+                                                     int64_t ngas, double vol, double* part,
+                                                     double* out, hipStream_t s);
+// time integration and energy terms (dynamics.hip); wrap != 0: drifted positions are
+// taken modulo 1 (periodic box)
 template <typename T> hipError_t launch_kick_drift(int64_t n, T* x, T* y, T* z, T* vx, T* vy,
                                                    T* vz, const T* ax, const T* ay, const T* az,
-                                                   double hk, double hd, hipStream_t s);
+                                                   double hk, double hd, int wrap, hipStream_t s);
 template <typename T> hipError_t launch_kinetic(const T* m, const T* vx, const T* vy, const T* vz,
                                                 int64_t n, double* part, double* out,
                                                 hipStream_t s);

@@ -5,12 +5,19 @@
 
 namespace apm {
 
-// v += hk a, then x += hd v (hd = 0: a kick alone; hk = 0: a drift alone).
+// Position modulo 1 in [0, 1) (periodic box); a value that rounds up to 1 is 0.
+template <typename T> __device__ __forceinline__ T wrap_unit(T v) {
+  v -= floor(v);
+  return v >= (T)1 ? (T)0 : v;
+}
+
+// v += hk a, then x += hd v (hd = 0: a kick alone; hk = 0: a drift alone); wrap: the
+// drifted positions are taken modulo 1.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_kick_drift(int64_t n, T* __restrict__ x, T* __restrict__ y, T* __restrict__ z,
              T* __restrict__ vx, T* __restrict__ vy, T* __restrict__ vz, const T* __restrict__ ax,
-             const T* __restrict__ ay, const T* __restrict__ az, T hk, T hd) {
+             const T* __restrict__ ay, const T* __restrict__ az, T hk, T hd, int wrap) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   T u = vx[i], v = vy[i], w = vz[i];
@@ -21,18 +28,25 @@ k_kick_drift(int64_t n, T* __restrict__ x, T* __restrict__ y, T* __restrict__ z,
     vx[i] = u; vy[i] = v; vz[i] = w;
   }
   if (x) {
-    x[i] += hd * u;
-    y[i] += hd * v;
-    z[i] += hd * w;
+    T px = x[i] + hd * u, py = y[i] + hd * v, pz = z[i] + hd * w;
+    if (wrap) {
+      px = wrap_unit(px);
+      py = wrap_unit(py);
+      pz = wrap_unit(pz);
+    }
+    x[i] = px;
+    y[i] = py;
+    z[i] = pz;
   }
 }
 
 template <typename T>
 hipError_t launch_kick_drift(int64_t n, T* x, T* y, T* z, T* vx, T* vy, T* vz, const T* ax,
-                             const T* ay, const T* az, double hk, double hd, hipStream_t s) {
+                             const T* ay, const T* az, double hk, double hd, int wrap,
+                             hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL((k_kick_drift<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
-                     0, s, n, x, y, z, vx, vy, vz, ax, ay, az, (T)hk, (T)hd);
+                     0, s, n, x, y, z, vx, vy, vz, ax, ay, az, (T)hk, (T)hd, wrap);
   return hipGetLastError();
 }
 
@@ -130,7 +144,7 @@ hipError_t launch_gas_energy(const GridDesc* grids, const OwnerLevel* om, int32_
 
 #define APM_INST_D(T)                                                                         \
   template hipError_t launch_kick_drift<T>(int64_t, T*, T*, T*, T*, T*, T*, const T*, const T*, \
-                                           const T*, double, double, hipStream_t);             \
+                                           const T*, double, double, int, hipStream_t);        \
   template hipError_t launch_kinetic<T>(const T*, const T*, const T*, const T*, int64_t,        \
                                         double*, double*, hipStream_t);                         \
   template hipError_t launch_gas_energy<T>(const GridDesc*, const OwnerLevel*, int32_t, int32_t,  \

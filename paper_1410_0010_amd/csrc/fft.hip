@@ -60,11 +60,15 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
   const int64_t rows = (int64_t)gy * gz;
   const int64_t q = blk * nl + b;
   const int64_t ra = 2 * q, rb = 2 * q + 1;
+  // a subgrid of a periodic plan convolves its GMF minus the average density (on the
+  // GMF box only; the padding stays zero), the difference formed in FP64
+  const bool sub = J.mean != nullptr;
+  const double mu = sub ? as_global<double>(J.mean)[0] : 0.0;
   for (int i = w; i < L; i += L / 8) {
     T xa = 0, xb = 0;
     if (i < gx) {
-      if (ra < rows) xa = gmf[ra * gx + i];
-      if (rb < rows) xb = gmf[rb * gx + i];
+      if (ra < rows) xa = sub ? (T)((double)gmf[ra * gx + i] - mu) : gmf[ra * gx + i];
+      if (rb < rows) xb = sub ? (T)((double)gmf[rb * gx + i] - mu) : gmf[rb * gx + i];
     }
     line[swz<L>(i)] = mk<T>(xa, xb);
   }

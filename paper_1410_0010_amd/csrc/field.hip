@@ -1,5 +1,7 @@
 // Level composition (Sec. 2.2: the parent's field interpolated onto the refined grid
 // and added to its own mesh force), FP64 totals and fill kernels.
+#include <algorithm>
+
 #include "apm_kernels.hpp"
 
 namespace apm {
@@ -100,6 +102,50 @@ __global__ void __launch_bounds__(kBlock) k_sum_parts(const double* __restrict__
 hipError_t launch_sum_parts(const double* part, int nparts, int nq, double scale, double* out,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kBlock), 0, s, part, nparts, nq, scale, out);
+  return hipGetLastError();
+}
+
+// Average density of a periodic system (the sine wave test, Sec. 3: the solve needs
+// zero net mass): in-domain particle masses (NaN or outside [0, 1) excluded, as in
+// the deposit) plus the root gas mass, over the unit box.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mean_parts(const T* __restrict__ x, const T* __restrict__ y,
+                                                       const T* __restrict__ z, const T* __restrict__ m,
+                                                       int64_t npart, const T* __restrict__ gas,
+                                                       int64_t ngas, double vol,
+                                                       double* __restrict__ part) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  double pm = 0.0, gm = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npart; i += stride) {
+    const T px = x[i], py = y[i], pz = z[i];
+    if (px >= (T)0 && px < (T)1 && py >= (T)0 && py < (T)1 && pz >= (T)0 && pz < (T)1)
+      pm += (double)m[i];
+  }
+  if (gas)
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ngas; i += stride)
+      gm += (double)gas[i];
+  const double r = block_sum(pm + gm * vol);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_mean_finish(const double* __restrict__ part, int nparts,
+                                                        double* __restrict__ out) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += kBlock) acc += part[b];
+  const double r = block_sum(acc);
+  if (threadIdx.x == 0) out[0] = r;
+}
+
+static int nparts_for(int64_t n);
+
+template <typename T>
+hipError_t launch_mean_density(const T* x, const T* y, const T* z, const T* m, int64_t npart,
+                               const T* gas, int64_t ngas, double vol, double* part, double* out,
+                               hipStream_t s) {
+  const int nb = nparts_for(std::max<int64_t>(npart, gas ? ngas : 0));
+  hipLaunchKernelGGL((k_mean_parts<T>), dim3(nb), dim3(kBlock), 0, s, x, y, z, m, npart, gas, ngas,
+                     vol, part);
+  hipLaunchKernelGGL(k_mean_finish, dim3(1), dim3(kBlock), 0, s, (const double*)part, nb, out);
   return hipGetLastError();
 }
 
@@ -253,6 +299,9 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
 #define APM_INST_F(T)                                                                          \
   template hipError_t launch_compose<T>(const GridDesc*, const int64_t*, int32_t, const V4<T>*,  \
                                         const V4<T>*, V4<T>*, int64_t, hipStream_t);             \
+  template hipError_t launch_mean_density<T>(const T*, const T*, const T*, const T*, int64_t,     \
+                                             const T*, int64_t, double, double*, double*,         \
+                                             hipStream_t);                                        \
   template hipError_t launch_sum_scaled<T>(const T*, int64_t, double, double*, double*,          \
                                           hipStream_t);                                         \
   template hipError_t launch_totals<T>(const TotalsIO<T>&, hipStream_t);                        \

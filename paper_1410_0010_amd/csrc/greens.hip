@@ -8,7 +8,8 @@
 // a_l = a_cells dx_l).  The potential uses the same construction with the gradient
 // replaced by the identity: Gp = -4 pi G sum_n U^2 f_l(k_n) / [sum U^2]^2.
 // Root (level 0, isolated): the level-0 kernels (reference S_0^2) made isolated as
-// the doubled-mesh reference potential (James) plus optimal - reference.
+// the doubled-mesh reference potential (James) plus optimal - reference.  Periodic
+// root (Sec. 2.1): the level-0 kernels on the root's own mesh, zero at k = 0.
 // Tables hold the octant |m_i| <= M_i/2 (both kernels are even in every axis),
 // scaled by 1/(Mx My Mz) for the unnormalised transforms, at ((|my| Ox) + |mx|) Oz
 // + |mz| (Ox = Mx/2 + 1, Oz = Mz/2 + 1).
@@ -121,10 +122,14 @@ __global__ void k_influence(InfluenceParams p, double2* __restrict__ out) {
   const double g4 = -4.0 * kPi * p.G;
   double gf = s2 > 0.0 ? g4 * numf / (s2 * c2) : 0.0;
   double gp = g4 * nump / c2;
-  if (p.a_lm1 < 0.0) {
-    // root: James reference + (optimal - reference)
+  const double k2 = kx * kx + ky * ky + kz * kz;
+  if (p.a_lm1 < 0.0 && !p.james) {
+    // periodic root: the level-0 kernels themselves; zero at k = 0 (the mean
+    // density carries no potential)
+    if (k2 == 0.0) gf = gp = 0.0;
+  } else if (p.a_lm1 < 0.0) {
+    // isolated root: James reference + (optimal - reference)
     const double jm = p.james[((int64_t)mz * Oy + my) * Ox + mx];
-    const double k2 = kx * kx + ky * ky + kz * kz;
     if (k2 == 0.0) {
       gf = jm;
       gp = jm - kPi * p.G * dx * dx;

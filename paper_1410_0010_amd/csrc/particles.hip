@@ -41,18 +41,28 @@ __device__ __forceinline__ int batch_level(const int64_t* blk0, int nlev, int64_
   return b;
 }
 
+// Cell c of a periodic axis of n cells, for c in [-1, n].
+__device__ __forceinline__ int wrap_cell(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
 // TSC gather of the 27 cells around cell (ix, iy, iz) (box-relative) of a field box of
 // dims n, with offsets t from the cell centre.  Branch-free: a cell outside the box
 // gets weight 0 and a clamped (valid) address, so all 27 loads are issued together.
+// wrap != 0 (a periodic root, whose field box is the whole domain): the stencil wraps
+// around the box edges instead.
 template <typename T>
 __device__ __forceinline__ V4<T> tsc_gather(const V4<T>* __restrict__ F, int nx, int ny, int nz,
-                                            int ix, int iy, int iz, T tx, T ty, T tz) {
+                                            int ix, int iy, int iz, T tx, T ty, T tz, int wrap) {
   const int n[3] = {nx, ny, nz};
   int cx[3], cy[3], cz[3];
   T wx[3], wy[3], wz[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int x = ix + d - 1, y = iy + d - 1, z = iz + d - 1;
+    int x = ix + d - 1, y = iy + d - 1, z = iz + d - 1;
+    if (wrap) {
+      x = wrap_cell(x, nx);
+      y = wrap_cell(y, ny);
+      z = wrap_cell(z, nz);
+    }
     const bool okx = (x >= 0) & (x < nx), oky = (y >= 0) & (y < ny), okz = (z >= 0) & (z < nz);
     cx[d] = okx ? x : 0;
     cy[d] = oky ? y : 0;
@@ -518,12 +528,18 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
   }
   __syncthreads();
   // flush: consecutive threads take consecutive halo-tile cells, so a wave's atomics
-  // fall on a few rows of the key-box grid
+  // fall on a few rows of the key-box grid; on a periodic root the cells one past the
+  // box edges (-1 and N) are cells N - 1 and 0
   const int tx0 = ox - 1, ty0 = oy - 1, tz0 = oz - 1;
   for (int c = threadIdx.x; c < kTH3; c += kBlock) {
     const double v = acc[c];
     if (v == 0.0) continue;
-    const int gx = tx0 + c % kTH, gy = ty0 + (c / kTH) % kTH, gz = tz0 + c / (kTH * kTH);
+    int gx = tx0 + c % kTH, gy = ty0 + (c / kTH) % kTH, gz = tz0 + c / (kTH * kTH);
+    if (L.wrap) {
+      gx = wrap_cell(gx + L.key_lo[0], L.wrap) - L.key_lo[0];
+      gy = wrap_cell(gy + L.key_lo[1], L.wrap) - L.key_lo[1];
+      gz = wrap_cell(gz + L.key_lo[2], L.wrap) - L.key_lo[2];
+    }
     if (gx < 0 || gx >= L.key_n[0] || gy < 0 || gy >= L.key_n[1] || gz < 0 || gz >= L.key_n[2])
       continue;
     global_add(as_global_mut<double>(L.accum) + ((int64_t)gz * L.key_n[1] + gy) * L.key_n[0] + gx, v);
@@ -629,7 +645,7 @@ __global__ void k_interp(const GridDesc* __restrict__ grids, int32_t level,
   const int nx = g.fld_n[0], ny = g.fld_n[1], nz = g.fld_n[2];
   const V4<T> a = tsc_gather<T>(field + off, nx, ny, nz, (int)fx - g.fld_lo[0],
                                 (int)fy - g.fld_lo[1], (int)fz - g.fld_lo[2], sx - fx - (T)0.5,
-                                sy - fy - (T)0.5, sz - fz - (T)0.5);
+                                sy - fy - (T)0.5, sz - fz - (T)0.5, g.wrap);
   ax[i] = a.x; ay[i] = a.y; az[i] = a.z;
   if (pot) pot[i] = a.w;
 }
@@ -665,7 +681,7 @@ __global__ void __launch_bounds__(kBlock) k_interp_sorted(InterpIO<T> io, const 
   const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
   const V4<T> a = tsc_gather<T>(io.fld[lb] + off, nx, ny, nz, (int)fx - lx, (int)fy - ly,
                                 (int)fz - lz, v.x - fx - (T)0.5, v.y - fy - (T)0.5,
-                                v.z - fz - (T)0.5);
+                                v.z - fz - (T)0.5, g.wrap);
   io.res[lb][q] = a;                                 // sorted position: a coalesced store
 }
 

@@ -8,8 +8,9 @@
 //    subgrid's active box grown by `ghost` cells, filled from its parent;
 //  * field box (where accelerations and potential are produced): the root's active
 //    box; a subgrid's active box grown by one cell (TSC interpolation stencil);
-//  * FFT box: root 2 root_n per axis (James doubling for the isolated boundary);
-//    subgrid: the power of two >= GMF extent + p, p = ceil(pad_factor 2 a_cells)
+//  * FFT box: root 2 root_n per axis (James doubling for the isolated boundary) or
+//    root_n (periodic boundary, Sec. 2.1: no padding needed); subgrid: the power of
+//    two >= GMF extent + p, p = ceil(pad_factor 2 a_cells)
 //    (the 0.65 R a/dx cells of zero padding, Sec. 2.2).
 #include <cmath>
 #include <cstring>
@@ -38,10 +39,14 @@ apm_status build_plan(const apm_config& cfg, const apm_grid* grids, int32_t ngri
   std::ostringstream e;
   if (!grids || ngrids < 1) return fail(APM_ERR_INVALID, "apm_plan_create: no grids");
   if (!(cfg.G > 0.0) || !std::isfinite(cfg.G)) return fail(APM_ERR_INVALID, "G must be > 0");
+  if (cfg.boundary != APM_BC_ISOLATED && cfg.boundary != APM_BC_PERIODIC)
+    return fail(APM_ERR_INVALID, "unknown boundary");
+  const bool periodic = cfg.boundary == APM_BC_PERIODIC;
   if (!is_pow2(cfg.root_n) || cfg.root_n < 8)
     return fail(APM_ERR_INVALID, "root_n must be a power of two >= 8");
-  if (2 * cfg.root_n > kMaxFFT)
-    return fail(APM_ERR_RANGE, "root_n > 512: doubled root FFT longer than 1024");
+  if ((periodic ? 1 : 2) * (int64_t)cfg.root_n > kMaxFFT)
+    return fail(APM_ERR_RANGE, periodic ? "root_n > 1024: root FFT longer than 1024"
+                                        : "root_n > 512: doubled root FFT longer than 1024");
   if (!(cfg.a_cells > 0.0) || !(cfg.pad_factor >= 0.0))
     return fail(APM_ERR_INVALID, "a_cells must be > 0 and pad_factor >= 0");
   if (cfg.ghost < 2) return fail(APM_ERR_INVALID, "ghost must be >= 2");
@@ -100,8 +105,9 @@ apm_status build_plan(const apm_config& cfg, const apm_grid* grids, int32_t ngri
       for (int a = 0; a < 3; ++a) {
         d.gmf_lo[a] = 0; d.gmf_n[a] = N;
         d.fld_lo[a] = 0; d.fld_n[a] = N;
-        d.M[a] = 2 * N;
+        d.M[a] = periodic ? N : 2 * N;
       }
+      d.wrap = periodic ? N : 0;
     } else {
       for (int a = 0; a < 3; ++a) {
         d.gmf_lo[a] = g.lo[a] - cfg.ghost;
@@ -192,6 +198,7 @@ void apm_config_default(apm_config* cfg) {
   cfg->brillouin = 1;
   cfg->gradient = APM_GRAD_SPECTRAL;
   cfg->workspace_limit = 0;
+  cfg->boundary = APM_BC_ISOLATED;
 }
 
 apm_status apm_plan_create(const apm_config* cfg, const apm_grid* grids, int32_t ngrids,

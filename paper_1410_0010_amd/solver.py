@@ -15,6 +15,7 @@ from . import _apm
 from ._apm import check
 
 _GRAD = {"spectral": _apm.APM_GRAD_SPECTRAL, "fd2": _apm.APM_GRAD_FD2}
+_BC = {"isolated": _apm.APM_BC_ISOLATED, "periodic": _apm.APM_BC_PERIODIC}
 
 
 def _dtype_code(t):
@@ -35,7 +36,7 @@ class Plan:
 
     def __init__(self, root_n: int, grids: Sequence, G: float = 1.0, gradient: str = "spectral",
                  a_cells: float = 3.4, pad_factor: float = 0.65, ghost: int = 3,
-                 brillouin: int = 1, workspace_limit: int = 0):
+                 brillouin: int = 1, workspace_limit: int = 0, boundary: str = "isolated"):
         L = _apm.lib()
         cfg = _apm.apm_config()
         L.apm_config_default(ctypes.byref(cfg))
@@ -47,6 +48,7 @@ class Plan:
         cfg.brillouin = brillouin
         cfg.gradient = _GRAD[gradient]
         cfg.workspace_limit = workspace_limit
+        cfg.boundary = _BC[boundary]
         arr = (_apm.apm_grid * len(grids))()
         for i, g in enumerate(grids):
             arr[i].level = g.level

@@ -45,11 +45,13 @@ def test_library_is_gfx950_code_object():
     lambda: W.workload_plummer_nested(root_n=128, sub_n=64, nlevels=2, npart=10),
     lambda: W.workload_clumps(ngrids=12, per_clump=10),
     lambda: W.workload_large_nested(npart=10, with_velocities=False),
+    lambda: W.workload_sine_wave(ntracer=10),
+    lambda: W.workload_plummer_periodic(npart=10),
 ])
 def test_layout_matches_oracle_plan(wl):
     w = wl()
-    plan = P.Plan(w.root_n, w.grids)
-    op = O.OraclePlan(w.root_n, w.grids)
+    plan = P.Plan(w.root_n, w.grids, boundary=w.boundary)
+    op = O.OraclePlan(w.root_n, w.grids, boundary=w.boundary)
     assert plan.ngrids == len(op.grids)
     assert plan.nlevels == op.nlevels
     for g, og in zip(plan.grids, op.grids):
@@ -69,6 +71,28 @@ def test_bench_workload_fft_sizes():
     plan = P.Plan(128, W.centred_nested_grids(128, 64, 2))
     assert plan.grids[0]["fft_n"] == [256] * 3
     assert plan.grids[1]["fft_n"] == [128] * 3 and plan.grids[1]["gmf_n"] == [70] * 3
+
+
+def test_periodic_root_fft_is_not_doubled():
+    """A periodic root needs no zero padding (Sec. 2.1): its FFT is root_n long, so a
+    1024^3 periodic root is accepted while an isolated one (2048) is not."""
+    plan = P.Plan(128, W.centred_nested_grids(128, 64, 2), boundary="periodic")
+    assert plan.grids[0]["fft_n"] == [128] * 3
+    assert plan.grids[1]["fft_n"] == [128] * 3
+    big = P.Plan(1024, [GridSpec(0, -1, (0, 0, 0), (1024,) * 3)], boundary="periodic")
+    assert big.grids[0]["fft_n"] == [1024] * 3
+    assert _bad([GridSpec(0, -1, (0, 0, 0), (1024,) * 3)], root_n=1024) == _apm.APM_ERR_RANGE
+    cfg = _apm.apm_config()
+    P.lib().apm_config_default(ctypes.byref(cfg))
+    assert cfg.boundary == _apm.APM_BC_ISOLATED
+    cfg.root_n = 16
+    cfg.boundary = 7
+    arr = (_apm.apm_grid * 1)()
+    arr[0].level, arr[0].parent = 0, -1
+    for a in range(3):
+        arr[0].n[a] = 16
+    h = ctypes.c_void_p()
+    assert P.lib().apm_plan_create(ctypes.byref(cfg), arr, 1, ctypes.byref(h)) == _apm.APM_ERR_INVALID
 
 
 def _bad(grids, root_n=16, **kw):

@@ -169,3 +169,77 @@ def test_kick_drift_kinetic(dtype):
     vv = [v.cpu().numpy().astype(np.float64) for v in (vx, vy, vz)]
     k_ref = 0.5 * np.sum(r[9] * (vv[0] ** 2 + vv[1] ** 2 + vv[2] ** 2))
     assert abs(k - k_ref) <= 1e-12 * abs(k_ref)
+
+
+def _periodic_rel(a, b):
+    """Relative L2 of position differences taken across the periodic box (a particle
+    that wrapped on one side and not, by a rounding, on the other counts its true
+    distance)."""
+    d = (np.asarray(a, np.float64) - b + 0.5) % 1.0 - 0.5
+    return np.linalg.norm(d) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_leapfrog_periodic_matches_oracle(dtype):
+    """Periodic root (sine wave geometry, 32^3, P = 0.2, two levels) with massive
+    particles whose velocities carry many of them across the box edges: the drift
+    wraps them on both sides, and positions, velocities, accelerations and energies
+    follow the oracle."""
+    w = W.workload_sine_wave(period=0.2, root_n=32, ntracer=2000)
+    rng = np.random.default_rng(4343)
+    w.m = rng.lognormal(0.0, 1.0, w.npart) * 1e-4
+    w.x[:400] = rng.uniform(0.98, 1.0, 400)          # next to the x = 1 face, moving out
+    w.vx, w.vy, w.vz = (rng.normal(0.0, 1.0, w.npart) for _ in range(3))
+    w.vx[:400] = np.abs(w.vx[:400]) + 1.0
+    nsteps, h = 5, 0.01
+    say(f"[dynamics] periodic leapfrog dtype={dtype.__name__} npart={w.npart} steps={nsteps}")
+    x64, y64, z64, m64, gas64 = rounded(w, dtype)
+    v64 = [np.asarray(v, dtype).astype(np.float64) for v in (w.vx, w.vy, w.vz)]
+    plan_o = O.OraclePlan(w.root_n, w.grids, boundary="periodic")
+    ref = O.leapfrog(plan_o, x64, y64, z64, *v64, m64, h, nsteps, gas=gas64)
+    last = O.solve(plan_o, ref["x"], ref["y"], ref["z"], m64, gas64)
+
+    plan = P.Plan(w.root_n, w.grids, boundary="periodic")
+    ctx = P.Context(plan, 0)
+    x, y, z, m, vx, vy, vz = (dev(a, dtype) for a in (w.x, w.y, w.z, w.m, w.vx, w.vy, w.vz))
+    gas = [ctx.pack_gas(l, w.gas, x.dtype) for l in range(plan.nlevels)]
+    ax, ay, az, pot, energy = ctx.leapfrog(x, y, z, vx, vy, vz, m, h, nsteps, gas=gas)
+    torch.cuda.synchronize()
+    got = lambda t: t.cpu().numpy().astype(np.float64)
+    pos = np.stack([got(x), got(y), got(z)], 1)
+    pos_ref = np.stack([ref["x"], ref["y"], ref["z"]], 1)
+    assert (pos >= 0).all() and (pos < 1).all()
+    assert (pos_ref[:400, 0] < 0.2).mean() > 0.9      # most crossed the x = 1 face
+    vel = np.stack([got(vx), got(vy), got(vz)], 1)
+    vel_ref = np.stack([ref["vx"], ref["vy"], ref["vz"]], 1)
+    acc = np.stack([got(ax), got(ay), got(az)], 1)
+    if dtype == np.float64:
+        tp, tv, ta, te = 1e-13, 1e-11, 1e-11, 1e-11
+    else:
+        tp, tv, ta, te = 1e-6, 1e-5, 2e-5, 1e-5
+    assert _periodic_rel(pos, pos_ref) <= tp
+    assert rel(vel, vel_ref) <= tv
+    assert rel(acc, last["acc"]) <= ta
+    assert rel(energy, ref["energy"]) <= te, (energy, ref["energy"])
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_drift_wraps_on_periodic_plans(dtype):
+    rng = np.random.default_rng(8)
+    n = 10007
+    p = [rng.uniform(0.0, 1.0, n) for _ in range(3)]
+    v = [rng.normal(0.0, 3.0, n) for _ in range(3)]
+    p[0][:5] = 0.0
+    v[0][:5] = -1e-30                                  # rounds to 1 - tiny: must give 0
+    plan = P.Plan(16, [W.GridSpec(0, -1, (0, 0, 0), (16,) * 3)], boundary="periodic")
+    ctx = P.Context(plan, 0)
+    x, y, z, vx, vy, vz = (dev(a, dtype) for a in p + v)
+    ctx.drift(x, y, z, vx, vy, vz, 0.7)
+    torch.cuda.synchronize()
+    tol = 1e-15 if dtype == np.float64 else 1e-6
+    for c, (q, u) in zip((x, y, z), zip(p, v)):
+        g = c.cpu().numpy().astype(np.float64)
+        r = np.asarray(q, dtype).astype(np.float64) + 0.7 * np.asarray(u, dtype).astype(np.float64)
+        assert (g >= 0).all() and (g < 1).all()
+        assert _periodic_rel(g, O.wrap_unit(r)) <= tol
+    assert (x.cpu().numpy()[:5] == 0).all()

@@ -44,7 +44,7 @@ def dev(a, dtype):
 
 
 def run_staged(w, dtype, gradient="spectral"):
-    plan = P.Plan(w.root_n, w.grids, gradient=gradient)
+    plan = P.Plan(w.root_n, w.grids, gradient=gradient, boundary=w.boundary)
     ctx = P.Context(plan, 0)
     x, y, z, m = (dev(a, dtype) for a in (w.x, w.y, w.z, w.m))
     tdt = x.dtype
@@ -74,7 +74,7 @@ def run_staged(w, dtype, gradient="spectral"):
 
 def run_oracle(w, dtype, gradient="spectral", cache=None):
     cast = lambda a: None if a is None else np.asarray(a, dtype).astype(np.float64)
-    plan = O.OraclePlan(w.root_n, w.grids, gradient=gradient)
+    plan = O.OraclePlan(w.root_n, w.grids, gradient=gradient, boundary=w.boundary)
     return O.solve(plan, cast(w.x), cast(w.y), cast(w.z), cast(w.m),
                    [cast(g) for g in w.gas], cache=cache)
 
@@ -151,7 +151,44 @@ def edge_workload():
     return W.Workload("edge", 16, grids, x, y, z, m, [None] * 2)
 
 
+def periodic_edge_workload(seed=78):
+    """Periodic root 16^3 with one subgrid: particles within a cell of every face and
+    corner (clouds and stencils that wrap), exactly at 0, just below 1, outside the
+    box and NaN, plus a clump on the subgrid; gas on both grids."""
+    grids = W.centred_nested_grids(16, 8, 1)
+    rng = np.random.default_rng(seed)
+    d = 1.0 / 16
+    near = np.where(rng.uniform(0, 1, (600, 3)) < 0.5, rng.uniform(0, d, (600, 3)),
+                    rng.uniform(1 - d, 1, (600, 3)))
+    mix = rng.uniform(0, 1, (600, 3))
+    pick = rng.uniform(0, 1, (600, 3)) < 0.6
+    p = np.concatenate([np.where(pick, near, mix), rng.uniform(0.45, 0.55, (300, 3)),
+                        np.array([[0.0, 0.0, 0.0], [np.nextafter(1.0, 0.0), 0.5, 0.0],
+                                  [0.0, np.nextafter(np.float32(1.0), np.float32(0.0)), 0.5],
+                                  [-0.01, 0.5, 0.5], [np.nan, 0.5, 0.5], [1.0, 0.2, 0.2]])])
+    m = rng.uniform(0.5, 1.5, p.shape[0]) / p.shape[0]
+    gas = [W.root_uniform_gas(16, lambda x, y, z: 1.0 + 0.5 * np.sin(2 * np.pi * (x + 2 * y))),
+           None]
+    gas[1] = W.inject_gas(gas[0], grids[0], grids[1]) * 1.1
+    return W.Workload("periodic_edges", 16, grids, p[:, 0].copy(), p[:, 1].copy(),
+                      p[:, 2].copy(), m, gas, boundary="periodic")
+
+
+def periodic_sine_particles():
+    """The sine wave geometry on a 32^3 periodic root (P = 0.2) with 3000 massive
+    particles uniform in the box besides the gas."""
+    w = W.workload_sine_wave(period=0.2, root_n=32, ntracer=3000)
+    rng = np.random.default_rng(79)
+    w.m = rng.lognormal(0.0, 1.0, w.npart) * 1e-4
+    return w
+
+
 CASES = {
+    "periodic_edges16": periodic_edge_workload,
+    "periodic_sine32_P0.2": periodic_sine_particles,
+    "periodic_sine64_tracers": lambda: W.workload_sine_wave(period=1.0, ntracer=2000),
+    "periodic_plummer32": lambda: W.workload_plummer_periodic(root_n=32, sub_n=16, nlevels=2,
+                                                              npart=20000),
     "root32_gas_4096": W.workload_root32_uniform_gas,
     "nested32_2x16_plummer": lambda: W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=2,
                                                                 npart=20000),
@@ -183,9 +220,13 @@ def test_parity_fd2_gradient(dtype):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
-def test_one_call_solve_matches_staged(dtype):
-    w = W.workload_plummer_gas(root_n=32, sub_n=16, nlevels=2, npart=5000)
-    say(f"[parity] apm_solve vs staged dtype={dtype.__name__}")
+@pytest.mark.parametrize("boundary", ["isolated", "periodic"])
+def test_one_call_solve_matches_staged(dtype, boundary):
+    if boundary == "isolated":
+        w = W.workload_plummer_gas(root_n=32, sub_n=16, nlevels=2, npart=5000)
+    else:
+        w = periodic_sine_particles()
+    say(f"[parity] apm_solve vs staged boundary={boundary} dtype={dtype.__name__}")
     got = run_staged(w, dtype)
     ctx = got["ctx"]
     x, y, z, m, gas = got["tensors"]
@@ -220,6 +261,54 @@ def test_parity_bench_workload_full_size(bench_oracle, dtype):
     ref = run_oracle(w, dtype, cache=cache)
     got = run_staged(w, dtype)
     compare("bench_full", w, dtype, got, ref)
+
+
+# ---- periodic root at full size: 128^3 periodic + 2 x 64^3, 2^20 Plummer -------------
+
+@pytest.fixture(scope="module")
+def periodic_oracle():
+    w = W.workload_plummer_periodic()
+    say("[parity] building oracle kernels for the full periodic workload")
+    plan = O.OraclePlan(w.root_n, w.grids, boundary="periodic")
+    cache = {g.index: O.greens(plan, g) for g in plan.grids}
+    return w, cache
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_parity_periodic_workload_full_size(periodic_oracle, dtype):
+    w, cache = periodic_oracle
+    say(f"[parity] full periodic workload dtype={dtype.__name__} npart={w.npart}")
+    ref = run_oracle(w, dtype, cache=cache)
+    got = run_staged(w, dtype)
+    compare("periodic_full", w, dtype, got, ref)
+
+
+def test_periodic_state_and_unsupported_paths():
+    """A periodic subgrid level cannot be solved before a level-0 deposit has recorded
+    the average density; the reverse sweep is not offered for periodic plans."""
+    import ctypes
+    from paper_1410_0010_amd import _apm
+    w = W.workload_sine_wave(period=1.0, root_n=32, ntracer=100)
+    plan = P.Plan(w.root_n, w.grids, boundary="periodic")
+    ctx = P.Context(plan, 0)
+    lib = P.lib()
+    gmf = ctx.empty_gmf(1, torch.float32)
+    fld = ctx.empty_field(1, torch.float32)
+    st = lib.apm_solve_level(ctx.handle, _apm.APM_F32, 1, ctypes.c_void_p(gmf.data_ptr()),
+                             ctypes.c_void_p(fld.data_ptr()))
+    assert st == _apm.APM_ERR_STATE
+    x, y, z, m = (dev(a, np.float32) for a in (w.x, w.y, w.z, w.m))
+    gas = [ctx.pack_gas(l, w.gas, torch.float32) for l in range(plan.nlevels)]
+    ctx.solve(x, y, z, m, gas)
+    torch.cuda.synchronize()
+    st = lib.apm_solve_level(ctx.handle, _apm.APM_F32, 1, ctypes.c_void_p(gmf.data_ptr()),
+                             ctypes.c_void_p(fld.data_ptr()))
+    assert st == _apm.APM_OK
+    with pytest.raises(P.APMError) as e:
+        ctx.solve_adjoint(x, y, z, m, gas, wbar=1.0)
+    assert e.value.status == _apm.APM_ERR_UNSUPPORTED
+    torch.cuda.synchronize()
 
 
 # ---- error paths through the device entry points ------------------------------------
