@@ -50,7 +50,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(plan, npart, npart_level, esize):
+def kernel_bytes(plan, npart, npart_level, esize, root_gas=False):
     """Algorithmic HBM bytes per step of each kernel name: what the method must move
     at least once (c = complex bytes = 2 esize)."""
     c = 2 * esize
@@ -94,9 +94,59 @@ def kernel_bytes(plan, npart, npart_level, esize):
     b["unpack"] = npart * (4 * esize + 4 + 4 * esize)   # (a, Phi) records + owner in, 4 arrays out
     if plan.cfg.boundary == 1:                          # periodic: the average density
         N = plan.grids[0]["n"][0]
-        b["mean_density"] = npart * 4 * esize + N ** 3 * esize
+        b["mean_density"] = npart * 4 * esize + (N ** 3 * esize if root_gas else 0)
     b["adj_interp"] = binned * (4 * esize + 8) + npart * (esize + 3 * 8)
+    b["owner"] = npart * (3 * esize + 4)                # positions in, owner out
+    b["totals"] = (sum(L["gmf_elems"] for L in plan.levels) * esize
+                   + npart * (5 * esize + 4))           # GMFs, m, a, Phi, owner
+    b["bin_clear"] = b["bin_scan"] = 0.0
+    for l in range(nl):                                 # per level: tile counters, mass grid
+        gs = plan.level_grids(l)
+        kn = [max(g["gmf_lo"][a] + g["gmf_n"][a] for g in gs) + 1 -
+              (min(g["gmf_lo"][a] for g in gs) - 1) for a in range(3)]
+        ntiles = int(np.prod([(k + 7) // 8 for k in kn]))
+        rep = 1
+        while rep < 16 and ntiles * rep * 2 <= 1 << 18:
+            rep *= 2
+        b["bin_clear"] += (ntiles * rep + 1) * 4 + int(np.prod(kn)) * 8
+        b["bin_scan"] += 2 * ntiles * rep * 4 + ntiles * 8   # counters in and out, items
     return b
+
+
+def sine_wave_accuracy(Context, Plan, dev):
+    """The sine wave test's accuracy (Sec. 3): per level, the largest deviation over the
+    active cells of a_x and Phi from the continuum solution -4 pi (P / 2 pi)^2
+    sin(2 pi x / P), relative to its amplitude, for P = 1 and 0.2: FP32 and FP64 with
+    the spectral gradient, and FP64 with the two-point one (Sec. 2.2 names both)."""
+    import torch
+    import apm_workloads as W
+    out = {}
+    for P, grad, dt in [(P, g, d) for P in (1.0, 0.2)
+                        for g, d in (("spectral", torch.float32), ("spectral", torch.float64),
+                                     ("fd2", torch.float64))]:
+        w = W.workload_sine_wave(period=P)
+        plan = Plan(w.root_n, w.grids, boundary="periodic", gradient=grad)
+        ctx = Context(plan, 0)
+        k = 2 * np.pi / P
+        amp_a, amp_p = 4 * np.pi / k, 4 * np.pi / k ** 2
+        x, y, z, m = (torch.from_numpy(np.asarray(a, np.float64)).to(dev).to(dt)
+                      for a in (w.x, w.y, w.z, w.m))
+        gas = [ctx.pack_gas(l, w.gas, dt) for l in range(plan.nlevels)]
+        ctx.solve(x, y, z, m, gas)
+        torch.cuda.synchronize()
+        lv = []
+        for l in range(plan.nlevels):
+            F = ctx.solved_field(l, dt)
+            g = plan.level_grids(l)[0]
+            f = ctx.field_view(F, g["index"]).cpu().numpy().astype(np.float64)
+            a0 = [g["lo"][i] - g["fld_lo"][i] for i in range(3)]
+            f = f[a0[2]:a0[2] + g["n"][2], a0[1]:a0[1] + g["n"][1], a0[0]:a0[0] + g["n"][0]]
+            xc = (g["lo"][0] + np.arange(g["n"][0]) + 0.5) * g["dx"]
+            ea = float(np.abs(f[..., 0] - amp_a * np.cos(k * xc)).max() / amp_a)
+            ep = float(np.abs(f[..., 3] + amp_p * np.sin(k * xc)).max() / amp_p)
+            lv.append({"level": l, "max_rel_err_ax": ea, "max_rel_err_phi": ep})
+        out[f"P={P:g}/{grad}/{'f32' if dt == torch.float32 else 'f64'}"] = lv
+    return out
 
 
 def measured_traffic(kernel, workload):
@@ -278,7 +328,7 @@ def main():
         cx = np.floor(pos * (1.0 / plan.levels[l]["dx"]))
         inside = np.all((cx >= lo) & (cx < hi), axis=1) & np.all((pos >= 0) & (pos < 1), axis=1)
         npl.append(int(inside.sum()))
-    kb = kernel_bytes(plan, n, npl, 4)
+    kb = kernel_bytes(plan, n, npl, 4, root_gas=w.gas[0] is not None)
     per_kernel = {k: dict(ms_per_step=v[0] / psteps, launches_per_step=v[1] / psteps)
                   for k, v in p32["prof"].items()}
     forward_names = [k for k in per_kernel if not k.startswith("adj")]
@@ -404,6 +454,13 @@ def main():
             cpu["fwd_adjoint"] = {"value": n / (t_fwd + t_adj), "unit": "particles/s",
                                   "seconds": t_fwd + t_adj}
 
+    sw_acc = None
+    if args.workload == "sine_wave":
+        sw_acc = sine_wave_accuracy(Context, Plan, dev)
+        log("sine wave vs the continuum solution: " + "; ".join(
+            f"{k}: " + ", ".join(f"L{v['level']} {v['max_rel_err_ax']:.2e}" for v in lv)
+            for k, lv in sw_acc.items()))
+
     value = n / (r32["ms"] * 1e-3)
     step_info = lambda r: None if r is None else {
         "particles_per_s": n / (r["ms"] * 1e-3), "cells_per_s": active / (r["ms"] * 1e-3),
@@ -435,6 +492,7 @@ def main():
                         "energy": r32["totals"][plan.nlevels],
                         "net_force": list(r32["totals"][plan.nlevels + 1:plan.nlevels + 4])},
         "leapfrog_fp32": lf,
+        "sine_wave_vs_analytic": sw_acc,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, args.workload),
