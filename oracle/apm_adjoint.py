@@ -29,6 +29,11 @@ step's transpose in reverse order:
 
 Owner grids are piecewise constant in the positions and are held fixed (the loss
 is not differentiable where a particle crosses an ownership boundary).
+
+Periodic plans: the root's transposes wrap like its forward stencils, and the
+subtraction of the average density rho_bar from every GMF (apm_oracle R24) adds
+rho_bar's cotangent, minus the sum of every GMF cotangent, to the mass of every
+in-domain particle and (times dx_0^3) to every root gas cell.
 """
 
 from __future__ import annotations
@@ -63,14 +68,21 @@ def interp_adjoint(plan, fields: List[np.ndarray], own: np.ndarray, x, y, z, cot
         if sel.size == 0:
             continue
         F = fields[g.index]
+        wrap = plan.periodic and g.level == 0
         (ix, iy, iz), (wx, wy, wz), (dwx, dwy, dwz) = _stencil(g, x[sel], y[sel], z[sel])
         c = cot[sel]
         for dz in (-1, 0, 1):
             cz = iz + dz - g.fld_lo[2]
+            if wrap:
+                cz = cz % g.fld_n[2]
             for dy in (-1, 0, 1):
                 cy = iy + dy - g.fld_lo[1]
+                if wrap:
+                    cy = cy % g.fld_n[1]
                 for dxo in (-1, 0, 1):
                     cx = ix + dxo - g.fld_lo[0]
+                    if wrap:
+                        cx = cx % g.fld_n[0]
                     ins = ((cx >= 0) & (cx < g.fld_n[0]) & (cy >= 0) & (cy < g.fld_n[1])
                            & (cz >= 0) & (cz < g.fld_n[2]))
                     a, b, e = wx[dxo + 1], wy[dy + 1], wz[dz + 1]
@@ -147,13 +159,20 @@ def deposit_adjoint(plan, x, y, z, m, gmf_bar: List[np.ndarray], gas):
     for g in plan.grids:
         gb = gmf_bar[g.index] / g.dx ** 3
         gx, gy, gz = (int(v) for v in g.gmf_n)
+        wrap = plan.periodic and g.level == 0
         (ix, iy, iz), (wx, wy, wz), (dwx, dwy, dwz) = _stencil(g, x[ok], y[ok], z[ok])
         for dz in (-1, 0, 1):
             cz = iz + dz - g.gmf_lo[2]
+            if wrap:
+                cz = cz % gz
             for dy in (-1, 0, 1):
                 cy = iy + dy - g.gmf_lo[1]
+                if wrap:
+                    cy = cy % gy
                 for dxo in (-1, 0, 1):
                     cx = ix + dxo - g.gmf_lo[0]
+                    if wrap:
+                        cx = cx % gx
                     ins = (cx >= 0) & (cx < gx) & (cy >= 0) & (cy < gy) & (cz >= 0) & (cz < gz)
                     v = np.zeros(ok.size)
                     v[ins] = gb[cz[ins], cy[ins], cx[ins]]
@@ -230,6 +249,12 @@ def adjoint(plan, x, y, z, m, gas=None, abar=None, phibar=None, wbar: float = 0.
             cache[g.index] = O.greens(plan, g)
     gmf_bar = [convolve_adjoint(plan, g, sbar[g.index], cache[g.index]) for g in plan.grids]
     mbar, xbar2, gas_bar = deposit_adjoint(plan, x, y, z, m, gmf_bar, gas)
+    if plan.periodic:
+        # every GMF was convolved minus rho_bar = sum of in-domain masses + root gas dx^3
+        rho_bar_bar = -sum(float(np.sum(b)) for b in gmf_bar)
+        mbar = mbar + rho_bar_bar * O.valid_particles(x, y, z)
+        if gas_bar[0] is not None:
+            gas_bar[0] = gas_bar[0] + rho_bar_bar * plan.grids[0].dx ** 3
     mbar = mbar + wbar * 0.5 * fwd["pot"] * owned
     gas_bar = [None if a is None else a + d for a, d in zip(gas_bar, gas_direct)]
     return dict(x=xbar + xbar2, m=mbar, gas=gas_bar, fbar=fbar, sbar=sbar, gmf_bar=gmf_bar,

@@ -12,7 +12,11 @@ something other than the adjoint itself:
   rounding);
 * the symmetry closed form dW/dm_p = Phi_p on a single root grid (the potential
   operator, interpolation after deposition with the same weights and an even
-  kernel, is symmetric for particles whose clouds lie inside the grid)."""
+  kernel, is symmetric for particles whose clouds lie inside the grid).
+
+The transposes and gradients are checked on the isolated and on the periodic root
+(particles over the whole box, clouds across its edges, the average density
+subtracted from every GMF)."""
 
 import numpy as np
 import pytest
@@ -23,25 +27,38 @@ from oracle import apm_oracle as O
 from oracle import apm_adjoint as A
 
 
-def nested_case(npart=300, seed=5, gas=True):
-    """Root 16^3 + one centred 8^3 level (+ gas on both), particles in the centre."""
+def nested_case(npart=300, seed=5, gas=True, boundary="isolated"):
+    """Root 16^3 + one centred 8^3 level (+ gas on both); particles in the centre, or,
+    on a periodic root, a third of them within a cell of the box faces and the rest
+    anywhere."""
     rng = np.random.default_rng(seed)
     grids = [GridSpec(0, -1, (0, 0, 0), (16,) * 3), GridSpec(1, 0, (12, 12, 12), (8,) * 3)]
-    p = rng.uniform(0.3, 0.7, (npart, 3))
+    if boundary == "periodic":
+        p = rng.uniform(0.0, 1.0, (npart, 3))
+        k = npart // 3
+        p[:k] = np.where(rng.uniform(0, 1, (k, 3)) < 0.5, rng.uniform(0, 1 / 16, (k, 3)),
+                         rng.uniform(1 - 1 / 16, 1, (k, 3)))
+    else:
+        p = rng.uniform(0.3, 0.7, (npart, 3))
     m = rng.uniform(0.5, 1.5, npart) / npart
     g = None
     if gas:
         g0 = 0.3 + rng.uniform(0.0, 1.0, (16, 16, 16))
         g = [g0, W.inject_gas(g0, grids[0], grids[1])]
-    return O.OraclePlan(16, grids), p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy(), m, g
+    return (O.OraclePlan(16, grids, boundary=boundary), p[:, 0].copy(), p[:, 1].copy(),
+            p[:, 2].copy(), m, g)
+
+
+BCS = ["isolated", "periodic"]
 
 
 def dot(a, b):
     return float(sum(np.sum(u * v) for u, v in zip(a, b) if u is not None))
 
 
-def test_convolution_transpose():
-    plan, *_ = nested_case()
+@pytest.mark.parametrize("bc", BCS)
+def test_convolution_transpose(bc):
+    plan, *_ = nested_case(boundary=bc)
     rng = np.random.default_rng(1)
     for g in plan.grids:
         k = O.greens(plan, g)
@@ -66,8 +83,9 @@ def test_composition_transpose():
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
-def test_interpolation_transpose_and_position_derivative():
-    plan, x, y, z, m, _ = nested_case()
+@pytest.mark.parametrize("bc", BCS)
+def test_interpolation_transpose_and_position_derivative(bc):
+    plan, x, y, z, m, _ = nested_case(boundary=bc)
     rng = np.random.default_rng(3)
     F = [rng.standard_normal(tuple(int(v) for v in g.fld_n[::-1]) + (4,)) for g in plan.grids]
     own = O.owner_of(plan, x, y, z)
@@ -88,8 +106,9 @@ def test_interpolation_transpose_and_position_derivative():
             assert abs(fd - xbar[i, axis]) <= 1e-5 * (abs(xbar[i, axis]) + 1.0), (axis, i)
 
 
-def test_deposit_transpose_and_position_derivative():
-    plan, x, y, z, m, gas = nested_case()
+@pytest.mark.parametrize("bc", BCS)
+def test_deposit_transpose_and_position_derivative(bc):
+    plan, x, y, z, m, gas = nested_case(boundary=bc)
     rng = np.random.default_rng(4)
     gb = [rng.standard_normal(tuple(int(v) for v in g.gmf_n[::-1])) for g in plan.grids]
     mbar, xbar, gas_bar = A.deposit_adjoint(plan, x, y, z, m, gb, gas)
@@ -123,9 +142,9 @@ def test_energy_mass_gradient_is_potential_on_single_grid():
     assert np.max(np.abs(gr["m"] - phi)) <= 1e-12 * np.max(np.abs(phi))
 
 
-@pytest.fixture(scope="module")
-def energy_case():
-    plan, x, y, z, m, gas = nested_case(npart=200, seed=9)
+@pytest.fixture(scope="module", params=BCS)
+def energy_case(request):
+    plan, x, y, z, m, gas = nested_case(npart=200, seed=9, boundary=request.param)
     cache = {}
     gr = A.energy_gradient(plan, x, y, z, m, gas, cache=cache)
     return plan, x, y, z, m, gas, cache, gr
@@ -162,8 +181,9 @@ def test_energy_gradient_positions_fd(energy_case):
     assert abs(fd - an) <= 1e-6 * np.sum(np.abs(gr["x"] * v)), (fd, an)
 
 
-def test_general_loss_gradient_fd():
-    plan, x, y, z, m, gas = nested_case(npart=150, seed=12)
+@pytest.mark.parametrize("bc", BCS)
+def test_general_loss_gradient_fd(bc):
+    plan, x, y, z, m, gas = nested_case(npart=150, seed=12, boundary=bc)
     rng = np.random.default_rng(13)
     ab = rng.standard_normal((x.size, 3))
     pb = rng.standard_normal(x.size)
