@@ -18,10 +18,10 @@ Workloads (synthetic and seeded, shaped like the paper's tests):
   large_nested    root 512^3 + 3 nested 256^3 levels, 2^24 Plummer particles plus two
                   orbiting point masses; also 100 leapfrog steps and the energy drift;
   plummer_periodic  the plummer_nested geometry with a periodic root (root FFT 128^3,
-                  not 256^3), 2^20 Plummer particles reaching the box edges (forward);
+                  not 256^3), 2^20 Plummer particles reaching the box edges;
   sine_wave       the sine wave test: periodic root 64^3 + levels over
                   [0.34375, 0.65625)^3 and [0.421875, 0.578125)^3, gas 2 + sin(2 pi x),
-                  4096 massless tracer particles (forward).
+                  4096 massless tracer particles.
 
 Prints one JSON line: value = particles/s of the FP32 forward step (inputs resident in
 HBM), with cells/s, the forward+adjoint step, the FP64 steps, errors against the FP64
@@ -244,7 +244,7 @@ def main():
     n = w.npart
     log(f"workload {w.name}: {n} particles, {len(w.grids)} grids, {active} active cells")
     fp64_ok = not args.no_fp64 and args.workload != "large_nested"
-    do_adj = not args.no_adjoint and w.boundary == "isolated"   # no periodic reverse sweep
+    do_adj = not args.no_adjoint
 
     def tens(dtype):
         return [torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype))).to(dev)

@@ -289,7 +289,10 @@ apm_status apm_gas_energy(apm_ctx ctx, apm_dtype dtype, int32_t level, const voi
  * xbar, ybar, zbar, mbar: npart outputs (any may be NULL).  gas_bar: NULL or host
  * array of nlevels device pointers, a packed active-gas cotangent of a level for
  * each level with gas (NULL entries skipped).  Asynchronous.
- * APM_ERR_UNSUPPORTED for periodic plans. */
+ * Periodic plans: the root's transposes wrap like its stencils, and the average
+ * density's cotangent (minus the sum of the subgrids' GMF cotangents) is added to
+ * the mass cotangent of every in-domain particle and, times dx_0^3, to the root's
+ * gas cotangent. */
 apm_status apm_solve_adjoint(apm_ctx ctx, apm_dtype dtype, const void* x, const void* y,
                              const void* z, const void* m, int64_t npart, const void* const* gas,
                              const void* pot, const void* abar_x, const void* abar_y,

@@ -134,12 +134,18 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
     const int ix = min(max((int)fx - L.key_lo[0] - ox, 0), kTile - 1),
               iy = min(max((int)fy - L.key_lo[1] - oy, 0), kTile - 1),
               iz = min(max((int)fz - L.key_lo[2] - oz, 0), kTile - 1);
-    // per-axis cells (clamped into the box, weight 0 outside) and weights
+    // per-axis cells (clamped into the box, weight 0 outside; wrapped on a periodic
+    // root) and weights
     int ax_[3], ay_[3], az_[3];
     double wx[3], wy[3], wz[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
+      int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
+      if (g.wrap) {
+        xx = wrap_cell(xx, nx);
+        yy = wrap_cell(yy, ny);
+        zz = wrap_cell(zz, nz);
+      }
       const bool ox_ = (xx >= 0) & (xx < nx), oy_ = (yy >= 0) & (yy < ny), oz_ = (zz >= 0) & (zz < nz);
       ax_[d] = ox_ ? xx : 0; ay_[d] = oy_ ? yy : 0; az_[d] = oz_ ? zz : 0;
       wx[d] = ox_ ? (double)tsc_w_a(d - 1, tx) : 0.0;
@@ -178,9 +184,14 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
       for (int cc = 0; cc < NC; ++cc) any |= a[cc] != 0.0;
       if (!any) continue;
       const int lx = c % 10, ly = (c / 10) % 10, lz = c / 100;
-      const int xx = L.key_lo[0] + ox + lx - 1 - g.fld_lo[0];
-      const int yy = L.key_lo[1] + oy + ly - 1 - g.fld_lo[1];
-      const int zz = L.key_lo[2] + oz + lz - 1 - g.fld_lo[2];
+      int xx = L.key_lo[0] + ox + lx - 1 - g.fld_lo[0];
+      int yy = L.key_lo[1] + oy + ly - 1 - g.fld_lo[1];
+      int zz = L.key_lo[2] + oz + lz - 1 - g.fld_lo[2];
+      if (g.wrap) {                                 // periodic root: cells -1 and N
+        xx = wrap_cell(xx, g.fld_n[0]);
+        yy = wrap_cell(yy, g.fld_n[1]);
+        zz = wrap_cell(zz, g.fld_n[2]);
+      }
       if (xx < 0 || xx >= g.fld_n[0] || yy < 0 || yy >= g.fld_n[1] || zz < 0 || zz >= g.fld_n[2])
         continue;                                   // cannot hold weight (owned stencils lie inside)
       double* f = fbar + 4 * (g.fld_offset + ((int64_t)zz * g.fld_n[1] + yy) * g.fld_n[0] + xx);
@@ -214,12 +225,18 @@ k_adj_interp_grad(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc*
   const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
   const int cx = (int)fx - g.fld_lo[0], cy = (int)fy - g.fld_lo[1], cz = (int)fz - g.fld_lo[2];
   const int nx = g.fld_n[0], ny = g.fld_n[1], nz = g.fld_n[2];
-  // per-axis cells (clamped into the box, weight 0 outside: the loads issue together)
+  // per-axis cells (clamped into the box, weight 0 outside: the loads issue together;
+  // wrapped on a periodic root)
   int ax_[3], ay_[3], az_[3];
   double wx[3], wy[3], wz[3], dwx[3], dwy[3], dwz[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
+    int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
+    if (g.wrap) {
+      xx = wrap_cell(xx, nx);
+      yy = wrap_cell(yy, ny);
+      zz = wrap_cell(zz, nz);
+    }
     const bool ox_ = (xx >= 0) & (xx < nx), oy_ = (yy >= 0) & (yy < ny), oz_ = (zz >= 0) & (zz < nz);
     ax_[d] = ox_ ? xx : 0; ay_[d] = oy_ ? yy : 0; az_[d] = oz_ ? zz : 0;
     wx[d] = ox_ ? (double)tsc_w_a(d - 1, tx) : 0.0;
@@ -472,7 +489,12 @@ k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
   double wx[3], wy[3], wz[3], dwx[3], dwy[3], dwz[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
+    int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
+    if (L.wrap) {                                    // periodic root: cells -1 and N
+      xx = wrap_cell(xx + L.key_lo[0], L.wrap) - L.key_lo[0];
+      yy = wrap_cell(yy + L.key_lo[1], L.wrap) - L.key_lo[1];
+      zz = wrap_cell(zz + L.key_lo[2], L.wrap) - L.key_lo[2];
+    }
     const bool ox_ = (xx >= 0) & (xx < nx), oy_ = (yy >= 0) & (yy < ny), oz_ = (zz >= 0) & (zz < nz);
     ax_[d] = ox_ ? xx : 0; ay_[d] = oy_ ? yy : 0; az_[d] = oz_ ? zz : 0;
     wx[d] = ox_ ? (double)tsc_w_a(d - 1, tx) : 0.0;
@@ -544,11 +566,27 @@ k_adj_finish(AdjIO<T> io, const DepLevel* __restrict__ tab, const int32_t* __res
   }
   if (og >= 0) {
     if (io.wbar != 0.0 && pot) s0 += io.wbar * 0.5 * (double)pot[i];
+    if (io.rbar) s0 += as_global<double>(io.rbar)[0];   // periodic: the average density's
   }
   if (mb) mb[i] = (T)s0;
   if (xb) xb[i] = (T)s1;
   if (yb) yb[i] = (T)s2;
   if (zb) zb[i] = (T)s3;
+}
+
+// a[i] += scale * s[0] for i < n (a periodic root's gas cotangent: the average
+// density's cotangent times dx_0^3 on every cell)
+__global__ void __launch_bounds__(kBlock) k_add_scalar(double* __restrict__ a, int64_t n,
+                                                       const double* __restrict__ s, double scale) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) a[i] += scale * as_global<double>(s)[0];
+}
+
+hipError_t launch_add_scalar(double* a, int64_t n, const double* s, double scale, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_scalar, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                     a, n, s, scale);
+  return hipGetLastError();
 }
 
 template <typename T>

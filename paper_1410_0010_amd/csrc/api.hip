@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -42,8 +43,9 @@ struct apm_ctx_s {
   std::vector<DevBuf> adj_fbar, adj_gas, adj_gmf[3];
   DevBuf adj_pacc;
   std::vector<uintptr_t> last_solve;                               // (dtype, n, x, y, z, m)
-  // periodic plans: the average density (partials, then the value at kMaxParts), set
-  // by a level-0 deposit or a solve; allocated once, so job tables may hold it
+  // periodic plans: the average density (partials, then the value at kMaxParts and the
+  // reverse sweep's cotangent of it at kMaxParts + 1), set by a level-0 deposit or a
+  // solve; allocated once, so job tables may hold it
   DevBuf meanbuf;
   bool mean_set = false;
   std::map<std::pair<int, int>, void*> tw;                        // (dtype, L)
@@ -438,9 +440,19 @@ std::vector<int> pass_lengths(apm_ctx c, int pass, int level) {
   return Ls;
 }
 
-// Own fields of the grid set: the five passes, one launch per (pass, L).
+// One launch (or a fixed group of launches) on the context's current stream; a list of
+// them is one branch of a solve, so two branches can be enqueued interleaved.
+using Step = std::function<apm_status()>;
+
+apm_status run_steps(const std::vector<Step>& steps) {
+  for (const Step& f : steps) APM_TRY(f());
+  return APM_OK;
+}
+
+// Own fields of the grid set: the five passes, one launch per (pass, L), as steps.
+// Tables, buffers and job lists are resolved here on the host.
 template <typename T>
-apm_status convolve_t(apm_ctx c, int level, const LevelPtrs<T>& lp) {
+apm_status convolve_steps_t(apm_ctx c, int level, const LevelPtrs<T>& lp, std::vector<Step>& out) {
   const std::vector<int> set = grid_set(c, level);
   APM_TRY(prepare_tables<T>(c, set));
   APM_TRY(ensure(c, c->spec, c->spec_elems * sizeof(C2<T>), "spectrum buffer"));
@@ -453,14 +465,26 @@ apm_status convolve_t(apm_ctx c, int level, const LevelPtrs<T>& lp) {
       APM_TRY(job_list<T>(c, pass, L, level, nl, &jl));
       const void* tw = nullptr;
       APM_TRY(twiddles<T>(c, L, &tw));
-      HIP_TRY(timed(c, pass_name(pass), [&] {
-                return launch_pass<T>(pass, L, nl, jl->d, jl->n, jl->blocks, lp,
-                                      (C2<T>*)c->spec.p, (C2<T>*)c->zbuf.p, (C2<T>*)c->ybuf.p,
-                                      tw, c->stream);
-              }), pass_name(pass));
+      const ConvJob* jobs = jl->d;
+      const int njobs = jl->n;
+      const int64_t blocks = jl->blocks;
+      out.push_back([c, pass, L, nl, jobs, njobs, blocks, lp, tw]() -> apm_status {
+        HIP_TRY(timed(c, pass_name(pass), [&] {
+                  return launch_pass<T>(pass, L, nl, jobs, njobs, blocks, lp, (C2<T>*)c->spec.p,
+                                        (C2<T>*)c->zbuf.p, (C2<T>*)c->ybuf.p, tw, c->stream);
+                }), pass_name(pass));
+        return APM_OK;
+      });
     }
   }
   return APM_OK;
+}
+
+template <typename T>
+apm_status convolve_t(apm_ctx c, int level, const LevelPtrs<T>& lp) {
+  std::vector<Step> steps;
+  APM_TRY(convolve_steps_t<T>(c, level, lp, steps));
+  return run_steps(steps);
 }
 
 // The second stream and the fork / join events of a two-branch solve (created once).
@@ -602,28 +626,55 @@ apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y
   return APM_OK;
 }
 
-// TSC deposit of a prepared batch (Sec. 2), on the context's stream: eight launches --
-// clear, tile count, three scan launches, scatter, tile deposit, finalize.
+// TSC deposit of a prepared batch (Sec. 2) as six steps of eight launches -- clear,
+// tile count, three scan launches, scatter, tile deposit, finalize -- on the
+// context's stream at the time each step runs.  The level table must be uploaded
+// (sync_dep_table) before the steps are built.
 template <typename T>
-apm_status deposit_launch_t(apm_ctx c, const DepBatch<T>& d) {
-  const DepIO<T>& io = d.io;
+void deposit_steps_t(apm_ctx c, const DepBatch<T>& d, std::vector<Step>& out) {
+  const DepIO<T> io = d.io;
   const int nlev = d.nlev;
   const int64_t max_elems = d.max_elems;
   const int32_t max_tiles = d.max_tiles;
   const DepLevel* tab = (const DepLevel*)c->dep_tab.p + d.l0;
-  HIP_TRY(timed(c, "bin_clear", [&] { return launch_dep_clear(tab, nlev, max_elems, c->stream); }),
-          "clear");
-  HIP_TRY(timed(c, "bin_count", [&] { return launch_bin_count<T>(io, tab, c->stream); }), "bin count");
-  HIP_TRY(timed(c, "bin_scan", [&] { return launch_bin_scan(tab, nlev, max_tiles, c->stream); }),
-          "bin scan");
-  HIP_TRY(timed(c, "bin_scatter", [&] { return launch_bin_scatter<T>(io, tab, c->stream); }),
-          "bin scatter");
-  HIP_TRY(timed(c, "deposit_tiles", [&] { return launch_deposit_tiles<T>(io, tab, c->stream); }),
-          "deposit tiles");
-  HIP_TRY(timed(c, "deposit_finalize", [&] {
-            return launch_deposit_finalize<T>(io, tab, c->stream);
-          }), "deposit finalize");
-  return APM_OK;
+  out.push_back([=]() -> apm_status {
+    HIP_TRY(timed(c, "bin_clear", [&] { return launch_dep_clear(tab, nlev, max_elems, c->stream); }),
+            "clear");
+    return APM_OK;
+  });
+  out.push_back([=]() -> apm_status {
+    HIP_TRY(timed(c, "bin_count", [&] { return launch_bin_count<T>(io, tab, c->stream); }),
+            "bin count");
+    return APM_OK;
+  });
+  out.push_back([=]() -> apm_status {
+    HIP_TRY(timed(c, "bin_scan", [&] { return launch_bin_scan(tab, nlev, max_tiles, c->stream); }),
+            "bin scan");
+    return APM_OK;
+  });
+  out.push_back([=]() -> apm_status {
+    HIP_TRY(timed(c, "bin_scatter", [&] { return launch_bin_scatter<T>(io, tab, c->stream); }),
+            "bin scatter");
+    return APM_OK;
+  });
+  out.push_back([=]() -> apm_status {
+    HIP_TRY(timed(c, "deposit_tiles", [&] { return launch_deposit_tiles<T>(io, tab, c->stream); }),
+            "deposit tiles");
+    return APM_OK;
+  });
+  out.push_back([=]() -> apm_status {
+    HIP_TRY(timed(c, "deposit_finalize", [&] {
+              return launch_deposit_finalize<T>(io, tab, c->stream);
+            }), "deposit finalize");
+    return APM_OK;
+  });
+}
+
+template <typename T>
+apm_status deposit_launch_t(apm_ctx c, const DepBatch<T>& d) {
+  std::vector<Step> steps;
+  deposit_steps_t<T>(c, d, steps);
+  return run_steps(steps);
 }
 
 // TSC deposit of levels [l0, l0 + nlev) in one batch.  gas/pgas/gmf are indexed by
@@ -719,15 +770,27 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
                                    &d1));
       APM_TRY(sync_dep_table(c));
       APM_TRY(prepare_branch_stream(c));
+      std::vector<Step> root, sub;
+      deposit_steps_t<T>(c, d0, root);
+      APM_TRY(convolve_steps_t<T>(c, 0, lp, root));
+      deposit_steps_t<T>(c, d1, sub);
+      APM_TRY(convolve_steps_t<T>(c, kSubLevels, lp, sub));
       HIP_TRY(hipEventRecord(c->ev_fork, c->stream), "fork record");
       HIP_TRY(hipStreamWaitEvent(c->aux_stream, c->ev_fork, 0), "fork wait");
-      // the root's branch, the longer one, is enqueued (and captured) first
-      apm_status st = deposit_launch_t<T>(c, d0);
-      if (st == APM_OK) st = convolve_t<T>(c, 0, lp);
+      // the two branches' launches are enqueued (and captured) alternately, so both
+      // branches start at once
       hipStream_t main = c->stream;
-      c->stream = c->aux_stream;
-      if (st == APM_OK) st = deposit_launch_t<T>(c, d1);
-      if (st == APM_OK) st = convolve_t<T>(c, kSubLevels, lp);
+      apm_status st = APM_OK;
+      for (size_t i = 0; st == APM_OK && i < std::max(root.size(), sub.size()); ++i) {
+        if (i < root.size()) {
+          c->stream = main;
+          st = root[i]();
+        }
+        if (st == APM_OK && i < sub.size()) {
+          c->stream = c->aux_stream;
+          st = sub[i]();
+        }
+      }
       c->stream = main;
       // join in every case, so a capture never ends with the branch left open
       HIP_TRY(hipEventRecord(c->ev_join, c->aux_stream), "join record");
@@ -1130,8 +1193,26 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
     ap.fbar[l] = io.fbar[l];
   }
   APM_TRY(adj_convolve_branches_t<T>(c, ap, pot_only));
+  if (P.cfg.boundary == APM_BC_PERIODIC) {
+    // the subgrids convolved GMF - rho_bar: rho_bar's cotangent is minus the sum of
+    // their GMF cotangents (the root's kernel is zero at k = 0, so the root's sums to 0)
+    double* mb_ = (double*)c->meanbuf.p;
+    double* rb = mb_ + kMaxParts + 1;
+    HIP_TRY(launch_fill_f64(rb, 1, 0.0, c->stream), "mean cotangent clear");
+    for (int l = 1; l < nl; ++l)
+      HIP_TRY(timed(c, "adj_mean", [&] {
+                return launch_sum_scaled<T>((const T*)c->adj_gmf[di][l].p, P.levels[l].gmf_elems,
+                                            -1.0, mb_, rb, c->stream);
+              }), "mean cotangent");
+    io.rbar = rb;
+  }
   HIP_TRY(timed(c, "adj_deposit_grid", [&] { return launch_adj_deposit_grid<T>(io, tab, c->stream); }),
           "deposit transpose (grids)");
+  if (io.rbar && io.gas_bar[0]) {
+    const double vol = P.levels[0].dx * P.levels[0].dx * P.levels[0].dx;
+    HIP_TRY(launch_add_scalar(io.gas_bar[0], P.levels[0].gas_elems, io.rbar, vol, c->stream),
+            "root gas: mean cotangent");
+  }
   HIP_TRY(timed(c, "adj_deposit_particles", [&] {
             return launch_adj_deposit_particles<T>(io, tab, c->stream);
           }), "deposit transpose (particles)");
@@ -1239,7 +1320,7 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
   apm_status st = upload(c, (void**)&c->d_grids, P.grids.data(), sizeof(GridDesc) * P.grids.size(),
                          "grid table");
   if (st == APM_OK && P.cfg.boundary == APM_BC_PERIODIC)
-    st = ensure(c, c->meanbuf, (size_t)(kMaxParts + 1) * 8, "average density");
+    st = ensure(c, c->meanbuf, (size_t)(kMaxParts + 2) * 8, "average density");
   if (st != APM_OK) { apm_destroy(c); return st; }
   for (const LevelDesc& L : P.levels) {
     std::vector<int64_t> dep(L.count + 1), cmp(L.count + 1), act(L.count + 1), foot(L.count + 1);
@@ -1741,8 +1822,6 @@ apm_status apm_solve_adjoint(apm_ctx c, apm_dtype dt, const void* x, const void*
                              void* ybar, void* zbar, void* mbar, void* const* gas_bar) {
   APM_TRY(check_ctx(c));
   APM_TRY(check_dtype(dt));
-  if (c->plan.cfg.boundary == APM_BC_PERIODIC)
-    return fail(APM_ERR_UNSUPPORTED, "apm_solve_adjoint: periodic plans have no reverse sweep");
   if (npart < 0 || npart > INT32_MAX) return fail(APM_ERR_RANGE, "apm_solve_adjoint: npart out of range");
   if (npart > 0 && (!x || !y || !z || !m))
     return fail(APM_ERR_INVALID, "apm_solve_adjoint: NULL particle array");

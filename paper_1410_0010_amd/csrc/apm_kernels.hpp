@@ -238,6 +238,9 @@ template <typename T> struct AdjIO {
                                        // position gradient (x, y, z; owned entries)
   V4<T>* plev[kMaxLevels];             // per level: the deposit transpose's
                                        // (mbar, xbar, ybar, zbar) (binned entries)
+  const double* rbar;                  // periodic: device scalar, the cotangent of the
+                                       // average density (added to every in-domain
+                                       // particle's mass cotangent); else null
 };
 template <typename T> hipError_t launch_adj_interp(const AdjIO<T>& io, const DepLevel* tab,
                                                    const GridDesc* grids, hipStream_t s);
@@ -258,6 +261,7 @@ template <typename T> hipError_t launch_adj_finish(const AdjIO<T>& io, const Dep
                                                    const int32_t* owner, const T* pot, T* xb,
                                                    T* yb, T* zb, T* mb, hipStream_t s);
 template <typename T> hipError_t launch_to_t(const double* a, T* b, int64_t n, hipStream_t s);
+hipError_t launch_add_scalar(double* a, int64_t n, const double* s, double scale, hipStream_t st);
 
 template <typename T> hipError_t launch_compose(const GridDesc* grids, const int64_t* block_begin,
                                                 int32_t ngrids, const V4<T>* own,

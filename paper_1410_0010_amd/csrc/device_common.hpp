@@ -43,6 +43,9 @@ template <typename V> __device__ __forceinline__ void pin4(V& v) {
   asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
 }
 
+// Cell c of a periodic axis of n cells, for c in [-1, n] (a periodic root's stencils).
+__device__ __forceinline__ int wrap_cell(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
 // complex element i of a global table reached through a job record
 template <typename T> __device__ __forceinline__ C2<T> load_c2(const void* base, int64_t i) {
   const nvec2<T> v = as_global<nvec2<T>>(base)[i];

@@ -64,11 +64,24 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
   // GMF box only; the padding stays zero), the difference formed in FP64
   const bool sub = J.mean != nullptr;
   const double mu = sub ? as_global<double>(J.mean)[0] : 0.0;
-  for (int i = w; i < L; i += L / 8) {
+  // loads first, from clamped (valid) addresses, then the zero padding is selected
+  const bool hra = ra < rows, hrb = rb < rows;
+  const T* rowa = gmf + (hra ? ra : 0) * gx;
+  const T* rowb = gmf + (hrb ? rb : 0) * gx;
+  T va[8], vb[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int i = min(w + j * (L / 8), gx - 1);
+    va[j] = rowa[i];
+    vb[j] = rowb[i];
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int i = w + j * (L / 8);
     T xa = 0, xb = 0;
     if (i < gx) {
-      if (ra < rows) xa = sub ? (T)((double)gmf[ra * gx + i] - mu) : gmf[ra * gx + i];
-      if (rb < rows) xb = sub ? (T)((double)gmf[rb * gx + i] - mu) : gmf[rb * gx + i];
+      if (hra) xa = sub ? (T)((double)va[j] - mu) : va[j];
+      if (hrb) xb = sub ? (T)((double)vb[j] - mu) : vb[j];
     }
     line[swz<L>(i)] = mk<T>(xa, xb);
   }
@@ -322,11 +335,25 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
     const C2<T>* A = ybuf + cs + ra * P;
     const bool hb = rb < rows;
     const C2<T>* B = ybuf + cs + (hb ? rb : ra) * P;
-    for (int i = w; i < L; i += L / 8) {
+    // all eight elements' loads are issued before any is used (a loop that stores to
+    // LDS after each load waits out one HBM round trip per element)
+    C2<T> av[8], bv[8];
+    T dv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = w + j * (L / 8);
       const int k = i <= L / 2 ? i : L - i;
-      C2<T> a = A[k], bq = hb ? B[k] : mk<T>(0, 0);
+      av[j] = A[k];
+      bv[j] = B[k];
+      dv[j] = dxs[k];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = w + j * (L / 8);
+      const int k = i <= L / 2 ? i : L - i;
+      C2<T> a = av[j], bq = hb ? bv[j] : mk<T>(0, 0);
       if (c == 0) {
-        const T d = dxs[k];
+        const T d = dv[j];
         a = mk<T>(d * a.y, -d * a.x);
         bq = mk<T>(d * bq.y, -d * bq.x);
       }

@@ -64,20 +64,35 @@ k_adj_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   const int64_t rows = (int64_t)fz * fy;
   constexpr int LS = line_stride(L);
   for (int i = t; i < nl * LS; i += nt) lds[i] = mk<T>(0, 0);
-  __syncthreads();
-  for (int idx = t; idx < G * 2 * fx; idx += nt) {
-    const int gg = idx / (2 * fx), rem = idx % (2 * fx);
-    const int half = rem / fx, x = rem % fx;
-    const int64_t r = 2 * (blk * G + gg) + half;
-    if (r < rows) {
-      const double* cell = fb + 4 * (r * fx + x);
-      const int xi = swz<L>((ox + x) & (L - 1));
-      C2<T>* L0 = lds + (4 * gg) * LS + xi;
+  // each thread takes at most four cells (G 2 fx <= 4 nt since fx <= L); their 32 B
+  // cotangent loads are all issued before the LDS stores
+  V4<double> cv[4];
+  int slot[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if (half == 0) L0[c * LS].x = (T)cell[c];
-        else L0[c * LS].y = (T)cell[c];
+  for (int j = 0; j < 4; ++j) {
+    const int idx = t + j * nt;
+    slot[j] = -1;
+    int64_t cell = 0;
+    if (idx < G * 2 * fx) {
+      const int gg = idx / (2 * fx), rem = idx % (2 * fx);
+      const int half = rem / fx, x = rem % fx;
+      const int64_t r = 2 * (blk * G + gg) + half;
+      if (r < rows) {
+        cell = r * fx + x;
+        slot[j] = ((4 * gg) * LS + swz<L>((ox + x) & (L - 1))) * 2 + half;
       }
+    }
+    cv[j] = load_v4<double>(fb, cell);               // cell 0 when unused: a valid address
+  }
+  __syncthreads();                                   // the zeroing is done
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (slot[j] >= 0) {
+      T* L0 = reinterpret_cast<T*>(lds) + slot[j];  // .x or .y of the line element
+      L0[0] = (T)cv[j].x;
+      L0[2 * LS] = (T)cv[j].y;
+      L0[4 * LS] = (T)cv[j].z;
+      L0[6 * LS] = (T)cv[j].w;
     }
   }
   __syncthreads();
@@ -323,9 +338,19 @@ k_adj_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
     const int64_t za = ra / gy, ya = ra % gy, zb = hb ? rb / gy : za, yb = hb ? rb % gy : ya;
     const C2<T>* A = spec + (za * My + ya) * P;
     const C2<T>* B = spec + (zb * My + yb) * P;
-    for (int i = w; i < L; i += L / 8) {
+    C2<T> av[8], bv[8];                              // all loads first
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = w + j * (L / 8);
       const int k = i <= L / 2 ? i : L - i;
-      C2<T> a = A[k], bq = hb ? B[k] : mk<T>(0, 0);
+      av[j] = A[k];
+      bv[j] = B[k];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = w + j * (L / 8);
+      const int k = i <= L / 2 ? i : L - i;
+      C2<T> a = av[j], bq = hb ? bv[j] : mk<T>(0, 0);
       if (k == 0 || k == L / 2) { a.y = 0; bq.y = 0; }
       line[swz<L>(i)] = i <= L / 2 ? mk<T>(a.x - bq.y, a.y + bq.x) : mk<T>(a.x + bq.y, bq.x - a.y);
     }
@@ -369,12 +394,24 @@ k_adjp_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   const int64_t rows = (int64_t)fz * fy;
   const int64_t q = blk * nl + b;
   const int64_t ra = 2 * q, rb = 2 * q + 1;
-  for (int i = w; i < L; i += L / 8) {
+  const bool hra = ra < rows, hrb = rb < rows;
+  const double* fa = fb + 4 * (hra ? ra : 0) * fx + 3;
+  const double* fc = fb + 4 * (hrb ? rb : 0) * fx + 3;
+  double va[8], vb[8];                               // all loads first, clamped addresses
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int x = min((w + j * (L / 8) - ox) & (L - 1), fx - 1);
+    va[j] = fa[4 * x];
+    vb[j] = fc[4 * x];
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int i = w + j * (L / 8);
     const int x = (i - ox) & (L - 1);                // field cell landing at position i
     T xa = 0, xb = 0;
     if (x < fx) {
-      if (ra < rows) xa = (T)fb[4 * (ra * fx + x) + 3];
-      if (rb < rows) xb = (T)fb[4 * (rb * fx + x) + 3];
+      if (hra) xa = (T)va[j];
+      if (hrb) xb = (T)vb[j];
     }
     line[swz<L>(i)] = mk<T>(xa, xb);
   }

@@ -41,9 +41,6 @@ __device__ __forceinline__ int batch_level(const int64_t* blk0, int nlev, int64_
   return b;
 }
 
-// Cell c of a periodic axis of n cells, for c in [-1, n].
-__device__ __forceinline__ int wrap_cell(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
-
 // TSC gather of the 27 cells around cell (ix, iy, iz) (box-relative) of a field box of
 // dims n, with offsets t from the cell centre.  Branch-free: a cell outside the box
 // gets weight 0 and a clamped (valid) address, so all 27 loads are issued together.

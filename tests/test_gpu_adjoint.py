@@ -56,7 +56,35 @@ def gas_clumps():
     return dataclasses.replace(w, gas=gas)
 
 
+def periodic_edges():
+    """Periodic root 16^3 + a centred 8^3 level with gas on both; particles within a
+    cell of the box faces (clouds and stencils across the edges), anywhere in the box,
+    on the subgrid, and a few outside the box."""
+    grids = W.centred_nested_grids(16, 8, 1)
+    rng = np.random.default_rng(81)
+    d = 1.0 / 16
+    near = np.where(rng.uniform(0, 1, (800, 3)) < 0.5, rng.uniform(0, d, (800, 3)),
+                    rng.uniform(1 - d, 1, (800, 3)))
+    p = np.concatenate([near, rng.uniform(0, 1, (800, 3)), rng.uniform(0.45, 0.55, (400, 3)),
+                        np.array([[-0.01, 0.5, 0.5], [0.5, 1.0, 0.5]])])
+    m = rng.uniform(0.5, 1.5, p.shape[0]) / p.shape[0]
+    g0 = 0.3 + rng.uniform(0.0, 1.0, (16, 16, 16))
+    gas = [g0, W.inject_gas(g0, grids[0], grids[1])]
+    return W.Workload("periodic_edges", 16, grids, p[:, 0].copy(), p[:, 1].copy(),
+                      p[:, 2].copy(), m, gas, boundary="periodic")
+
+
+def periodic_sine():
+    w = W.workload_sine_wave(period=0.2, root_n=32, ntracer=3000)
+    w.m = np.random.default_rng(82).lognormal(0.0, 1.0, w.npart) * 1e-4
+    return w
+
+
 CASES = {
+    "periodic_edges16_gas": periodic_edges,
+    "periodic_sine32": periodic_sine,
+    "periodic_plummer32": lambda: W.workload_plummer_periodic(root_n=32, sub_n=16, nlevels=2,
+                                                              npart=8000),
     "gas_nested32": lambda: W.workload_plummer_gas(root_n=32, sub_n=16, nlevels=2, npart=6000),
     "plummer_nested32_3lev": lambda: W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=3,
                                                                 npart=8000),
@@ -66,7 +94,7 @@ CASES = {
 
 
 def gpu_adjoint(w, dtype, abar=None, phibar=None, wbar=0.0):
-    plan = P.Plan(w.root_n, w.grids)
+    plan = P.Plan(w.root_n, w.grids, boundary=w.boundary)
     ctx = P.Context(plan, 0)
     x, y, z, m = (dev(a, dtype) for a in (w.x, w.y, w.z, w.m))
     gas = [ctx.pack_gas(l, w.gas, x.dtype) for l in range(plan.nlevels)]
@@ -111,12 +139,14 @@ def test_energy_gradient_matches_oracle(case, dtype):
     w = CASES[case]()
     say(f"[adjoint] energy gradient case={case} dtype={dtype.__name__} npart={w.npart}")
     x, y, z, m, gas = rounded(w, dtype)
-    ref = A.energy_gradient(O.OraclePlan(w.root_n, w.grids), x, y, z, m, gas)
+    ref = A.energy_gradient(O.OraclePlan(w.root_n, w.grids, boundary=w.boundary), x, y, z, m,
+                            gas)
     check(case, dtype, gpu_adjoint(w, dtype, wbar=1.0), ref, w)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("case", ["gas_nested32", "clumps32_24grids_gas"])
+@pytest.mark.parametrize("case", ["gas_nested32", "clumps32_24grids_gas", "periodic_edges16_gas",
+                                  "periodic_sine32"])
 def test_general_loss_gradient_matches_oracle(case, dtype):
     w = CASES[case]()
     rng = np.random.default_rng(3)
@@ -124,8 +154,8 @@ def test_general_loss_gradient_matches_oracle(case, dtype):
     pb = np.asarray(rng.standard_normal(w.npart), dtype).astype(np.float64)
     say(f"[adjoint] general loss case={case} dtype={dtype.__name__}")
     x, y, z, m, gas = rounded(w, dtype)
-    ref = A.adjoint(O.OraclePlan(w.root_n, w.grids), x, y, z, m, gas, abar=ab, phibar=pb,
-                    wbar=0.5)
+    ref = A.adjoint(O.OraclePlan(w.root_n, w.grids, boundary=w.boundary), x, y, z, m, gas,
+                    abar=ab, phibar=pb, wbar=0.5)
     check(case, dtype, gpu_adjoint(w, dtype, ab, pb, 0.5), ref, w)
 
 
