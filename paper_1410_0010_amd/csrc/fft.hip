@@ -192,30 +192,28 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int kx = c0 + b;
   const int kxc = kx < W ? kx : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
-  // this column's multipliers: one contiguous run of L/2 + 1 in the table
+  // this column's multipliers: one contiguous run of L/2 + 1 in the table, read for
+  // each product where it is used (holding all three sets for the whole kernel cost
+  // 24 registers, and the register count bounds the waves per SIMD)
   const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)(kyo * W + kxc) * (L / 2 + 1);
-  T gf[8], gp[8], gz_[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int kz = w + q * (L / 8);
-    const int kzo = kz <= L / 2 ? kz : L - kz;
-    const nvec2<T> gv = gcol[kzo];
-    const C2<T> G = mk<T>(gv.x, gv.y);
-    gf[q] = G.x;
-    gp[q] = G.y;
-    gz_[q] = dzs[kz] * G.x;
-  }
   fft_line<T, L, false>(line, w, tw);
   C2<T> X[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) X[q] = line[swz<L>(w + q * (L / 8))];
+#pragma unroll 1
   for (int s = 0; s < 3; ++s) {
+    T mul[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      C2<T> v;
-      if (s == 0) v = mk<T>(gf[q] * X[q].x, gf[q] * X[q].y);
-      else if (s == 1) v = mk<T>(gz_[q] * X[q].y, -gz_[q] * X[q].x);   // -i d_z Gf X
-      else v = mk<T>(gp[q] * X[q].x, gp[q] * X[q].y);
+      const int kz = w + q * (L / 8);
+      const int kzo = kz <= L / 2 ? kz : L - kz;
+      const nvec2<T> gv = gcol[kzo];
+      mul[q] = s == 0 ? gv.x : (s == 1 ? dzs[kz] * gv.x : gv.y);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const C2<T> v = s == 1 ? mk<T>(mul[q] * X[q].y, -mul[q] * X[q].x)   // -i d_z Gf X
+                             : mk<T>(mul[q] * X[q].x, mul[q] * X[q].y);
       line[swz<L>(w + q * (L / 8))] = v;
     }
     __syncthreads();

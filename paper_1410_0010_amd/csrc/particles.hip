@@ -682,6 +682,101 @@ __global__ void __launch_bounds__(kBlock) k_interp_sorted(InterpIO<T> io, const 
   io.res[lb][q] = a;                                 // sorted position: a coalesced store
 }
 
+// Tile-staged interpolation, one block per deposit work item (a tile's chunk of at most
+// kChunk sorted entries): on a level of one grid, for chunks of 64 entries or more, the
+// 10^3 field cells around the tile (zero outside the field box; wrapped on a periodic
+// root) are read into LDS once and every entry's 27-cell gather reads LDS.  The sums
+// run in the same order as tsc_gather's, over the same values (a cell outside the box
+// contributes an exact zero either way).  Other chunks gather from global memory as
+// k_interp_sorted does.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_interp_tiles(InterpIO<T> io, const DepLevel* __restrict__ tab,
+                                                         const GridDesc* __restrict__ grids) {
+  __shared__ V4<T> tf[kTH3];
+  const int lb = batch_level(io.item_blk0, io.nlev, blockIdx.x);
+  const DepLevel& L = tab[lb];
+  const int64_t item = blockIdx.x - io.item_blk0[lb];
+  const int32_t total = L.items[L.ntiles];
+  const int4 wk = L.work[item];                     // in the table's room; read with the count
+  if (item >= total) return;                        // uniform for the block
+  const int tile = wk.x;
+  const int64_t begin = wk.y, end = wk.z;
+  const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
+            oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;
+  // staged when the level has one grid and the chunk is not sparse (a few entries
+  // read fewer bytes with their own gathers than the 10^3 tile)
+  const bool staged = L.ngrids == 1 && end - begin >= 64;   // uniform for the block
+  const V4<T>* F = io.fld[lb];
+  if (staged) {
+    const GridDesc& g = grids[L.first];
+    const V4<T>* Fg = F + g.fld_offset;
+    // halo cell (lx, ly, lz) of the tile is level cell key_lo + o + l - 1
+    for (int c = threadIdx.x; c < kTH3; c += kBlock) {
+      int x = L.key_lo[0] + ox + c % kTH - 1 - g.fld_lo[0];
+      int y = L.key_lo[1] + oy + (c / kTH) % kTH - 1 - g.fld_lo[1];
+      int z = L.key_lo[2] + oz + c / (kTH * kTH) - 1 - g.fld_lo[2];
+      if (g.wrap) {
+        x = wrap_cell(x, g.fld_n[0]);
+        y = wrap_cell(y, g.fld_n[1]);
+        z = wrap_cell(z, g.fld_n[2]);
+      }
+      const bool in = x >= 0 && x < g.fld_n[0] && y >= 0 && y < g.fld_n[1] && z >= 0 &&
+                      z < g.fld_n[2];
+      V4<T> v = load_v4<T>(Fg, in ? ((int64_t)z * g.fld_n[1] + y) * g.fld_n[0] + x : 0);
+      if (!in) v = V4<T>{0, 0, 0, 0};
+      tf[c] = v;
+    }
+    __syncthreads();
+  }
+  const int bx = L.key_lo[0] + ox, by = L.key_lo[1] + oy, bz = L.key_lo[2] + oz;
+  for (int k = 0; k < 8; ++k) {
+    const int64_t q = begin + threadIdx.x + (int64_t)k * kBlock;
+    if (q >= end) break;
+    const int2 r = load_i2(L.sref, q);
+    if (r.y < 0) continue;
+    const V4<T> v = load_v4<T>(L.sorted, q);
+    const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
+    const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
+    V4<T> a;
+    if (staged) {
+      // the entry's cell inside the tile (binned there; clamped defensively)
+      const int ix = min(max((int)fx - bx, 0), kTile - 1), iy = min(max((int)fy - by, 0), kTile - 1),
+                iz = min(max((int)fz - bz, 0), kTile - 1);
+      const T wx[3] = {tsc_w(-1, tx), tsc_w(0, tx), tsc_w(1, tx)};
+      const T wy[3] = {tsc_w(-1, ty), tsc_w(0, ty), tsc_w(1, ty)};
+      const T wz[3] = {tsc_w(-1, tz), tsc_w(0, tz), tsc_w(1, tz)};
+      a.x = 0; a.y = 0; a.z = 0; a.w = 0;
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const T wzy = wz[dz] * wy[dy];
+          const V4<T>* row = tf + ((iz + dz) * kTH + iy + dy) * kTH + ix;
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            const V4<T> f = row[dx];
+            const T w = wzy * wx[dx];
+            a.x += w * f.x; a.y += w * f.y; a.z += w * f.z; a.w += w * f.w;
+          }
+        }
+    } else {
+      const GridDesc& g = grids[r.y];
+      a = tsc_gather<T>(F + g.fld_offset, g.fld_n[0], g.fld_n[1], g.fld_n[2], (int)fx - g.fld_lo[0],
+                        (int)fy - g.fld_lo[1], (int)fz - g.fld_lo[2], tx, ty, tz, g.wrap);
+    }
+    io.res[lb][q] = a;                               // sorted position: a coalesced store
+  }
+}
+
+template <typename T>
+hipError_t launch_interp_tiles(const InterpIO<T>& io, const DepLevel* tab, const GridDesc* grids,
+                               hipStream_t s) {
+  const int64_t nb = io.item_blk0[io.nlev];
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_interp_tiles<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab, grids);
+  return hipGetLastError();
+}
+
 // Records -> the four output arrays (coalesced stores): particle i's record is read
 // at its sorted position count[key] + rank on its owner's level.
 template <typename T>
@@ -733,6 +828,8 @@ hipError_t launch_interp_sorted(const InterpIO<T>& io, const DepLevel* tab, cons
                                       int64_t, int32_t*, T*, T*, T*, T*, hipStream_t);          \
   template hipError_t launch_interp_sorted<T>(const InterpIO<T>&, const DepLevel*,              \
                                               const GridDesc*, hipStream_t);                    \
+  template hipError_t launch_interp_tiles<T>(const InterpIO<T>&, const DepLevel*,               \
+                                             const GridDesc*, hipStream_t);                     \
   template hipError_t launch_unpack<T>(const InterpIO<T>&, const DepLevel*, const int32_t*,     \
                                        int64_t, T*, T*, T*, T*, hipStream_t);                   \
   template hipError_t launch_interp<T>(const GridDesc*, int32_t, const V4<T>*, const T*,       \
