@@ -471,68 +471,115 @@ hipError_t launch_adj_deposit_grid(const AdjIO<T>& io, const DepLevel* tab, hipS
 // ---- deposit transpose, particle side --------------------------------------------------
 // Entry q of a level's sorted list: (sum_c w(c) A(c), m sum_c grad w(c) A(c)), A the
 // level's key-box cotangent, stored in the level's per-particle slot (the levels are
-// summed per particle at the end, so no atomics).
+// summed per particle at the end, so no atomics).  One block per deposit work item; a
+// chunk of 64 entries or more reads the 10^3 key-box cells around its tile into LDS
+// (zero outside the box, wrapped on a periodic root) and gathers from there.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
-  const int lb = batch_of(io.part_blk0, io.nlev, blockIdx.x);
+  __shared__ double ta[kTH3];
+  constexpr int kTH = kTile + 2;
+  const int lb = batch_of(io.item_blk0, io.nlev, blockIdx.x);
   const DepLevel& L = tab[lb];
-  const int64_t q = (blockIdx.x - io.part_blk0[lb]) * (int64_t)kBlock + threadIdx.x;
-  if (q >= *L.binned) return;
-  const int2 r = load_i2(L.sref, q);
-  const V4<T> v = load_v4<T>(L.sorted, q);
-  const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
-  const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
-  const int cx = (int)fx - L.key_lo[0], cy = (int)fy - L.key_lo[1], cz = (int)fz - L.key_lo[2];
+  const int64_t item = blockIdx.x - io.item_blk0[lb];
+  const int32_t total = L.items[L.ntiles];
+  const int4 wk = L.work[item];                     // in the table's room; read with the count
+  if (item >= total) return;                        // uniform for the block
+  const int tile = wk.x;
+  const int64_t begin = wk.y, end = wk.z;
+  const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
+            oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;
   const int nx = L.key_n[0], ny = L.key_n[1], nz = L.key_n[2];
-  int ax_[3], ay_[3], az_[3];
-  double wx[3], wy[3], wz[3], dwx[3], dwy[3], dwz[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
-    if (L.wrap) {                                    // periodic root: cells -1 and N
-      xx = wrap_cell(xx + L.key_lo[0], L.wrap) - L.key_lo[0];
-      yy = wrap_cell(yy + L.key_lo[1], L.wrap) - L.key_lo[1];
-      zz = wrap_cell(zz + L.key_lo[2], L.wrap) - L.key_lo[2];
-    }
-    const bool ox_ = (xx >= 0) & (xx < nx), oy_ = (yy >= 0) & (yy < ny), oz_ = (zz >= 0) & (zz < nz);
-    ax_[d] = ox_ ? xx : 0; ay_[d] = oy_ ? yy : 0; az_[d] = oz_ ? zz : 0;
-    wx[d] = ox_ ? (double)tsc_w_a(d - 1, tx) : 0.0;
-    wy[d] = oy_ ? (double)tsc_w_a(d - 1, ty) : 0.0;
-    wz[d] = oz_ ? (double)tsc_w_a(d - 1, tz) : 0.0;
-    dwx[d] = ox_ ? (double)tsc_dw_a(d - 1, tx) : 0.0;
-    dwy[d] = oy_ ? (double)tsc_dw_a(d - 1, ty) : 0.0;
-    dwz[d] = oz_ ? (double)tsc_dw_a(d - 1, tz) : 0.0;
-  }
   const gptr<double> acc_g = as_global<double>(L.accum);
-  double a27[27];
-#pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx)
-        a27[(dz * 3 + dy) * 3 + dx] = acc_g[((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]];
-  double sm = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-#pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const double a = a27[(dz * 3 + dy) * 3 + dx];
-        sm += wx[dx] * wy[dy] * wz[dz] * a;
-        gx += dwx[dx] * wy[dy] * wz[dz] * a;
-        gy += wx[dx] * dwy[dy] * wz[dz] * a;
-        gz += wx[dx] * wy[dy] * dwz[dz] * a;
+  const bool staged = end - begin >= 64;            // uniform for the block
+  if (staged) {
+    for (int c = threadIdx.x; c < kTH3; c += kBlock) {
+      int x = ox + c % kTH - 1, y = oy + (c / kTH) % kTH - 1, z = oz + c / (kTH * kTH) - 1;
+      if (L.wrap) {                                  // periodic root: cells -1 and N
+        x = wrap_cell(x + L.key_lo[0], L.wrap) - L.key_lo[0];
+        y = wrap_cell(y + L.key_lo[1], L.wrap) - L.key_lo[1];
+        z = wrap_cell(z + L.key_lo[2], L.wrap) - L.key_lo[2];
       }
-  const double m = (double)v.w * L.inv_dx;
-  io.plev[lb][q] = V4<T>{(T)sm, (T)(m * gx), (T)(m * gy), (T)(m * gz)};   // sorted position
+      const bool in = x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz;
+      const double a = acc_g[in ? ((int64_t)z * ny + y) * nx + x : 0];
+      ta[c] = in ? a : 0.0;
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < 8; ++k) {
+    const int64_t q = begin + threadIdx.x + (int64_t)k * kBlock;
+    if (q >= end) break;
+    const V4<T> v = load_v4<T>(L.sorted, q);
+    const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
+    const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
+    double wx[3], wy[3], wz[3], dwx[3], dwy[3], dwz[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      wx[d] = (double)tsc_w_a(d - 1, tx);
+      wy[d] = (double)tsc_w_a(d - 1, ty);
+      wz[d] = (double)tsc_w_a(d - 1, tz);
+      dwx[d] = (double)tsc_dw_a(d - 1, tx);
+      dwy[d] = (double)tsc_dw_a(d - 1, ty);
+      dwz[d] = (double)tsc_dw_a(d - 1, tz);
+    }
+    double a27[27];
+    if (staged) {
+      const int ix = min(max((int)fx - L.key_lo[0] - ox, 0), kTile - 1),
+                iy = min(max((int)fy - L.key_lo[1] - oy, 0), kTile - 1),
+                iz = min(max((int)fz - L.key_lo[2] - oz, 0), kTile - 1);
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx)
+            a27[(dz * 3 + dy) * 3 + dx] = ta[((iz + dz) * kTH + iy + dy) * kTH + ix + dx];
+    } else {
+      const int cx = (int)fx - L.key_lo[0], cy = (int)fy - L.key_lo[1], cz = (int)fz - L.key_lo[2];
+      int ax_[3], ay_[3], az_[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        int xx = cx + d - 1, yy = cy + d - 1, zz = cz + d - 1;
+        if (L.wrap) {                                // periodic root: cells -1 and N
+          xx = wrap_cell(xx + L.key_lo[0], L.wrap) - L.key_lo[0];
+          yy = wrap_cell(yy + L.key_lo[1], L.wrap) - L.key_lo[1];
+          zz = wrap_cell(zz + L.key_lo[2], L.wrap) - L.key_lo[2];
+        }
+        const bool ox_ = (xx >= 0) & (xx < nx), oy_ = (yy >= 0) & (yy < ny), oz_ = (zz >= 0) & (zz < nz);
+        ax_[d] = ox_ ? xx : 0; ay_[d] = oy_ ? yy : 0; az_[d] = oz_ ? zz : 0;
+        if (!ox_) { wx[d] = 0.0; dwx[d] = 0.0; }
+        if (!oy_) { wy[d] = 0.0; dwy[d] = 0.0; }
+        if (!oz_) { wz[d] = 0.0; dwz[d] = 0.0; }
+      }
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx)
+            a27[(dz * 3 + dy) * 3 + dx] = acc_g[((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]];
+    }
+    double sm = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const double a = a27[(dz * 3 + dy) * 3 + dx];
+          sm += wx[dx] * wy[dy] * wz[dz] * a;
+          gx += dwx[dx] * wy[dy] * wz[dz] * a;
+          gy += wx[dx] * dwy[dy] * wz[dz] * a;
+          gz += wx[dx] * wy[dy] * dwz[dz] * a;
+        }
+    const double m = (double)v.w * L.inv_dx;
+    io.plev[lb][q] = V4<T>{(T)sm, (T)(m * gx), (T)(m * gy), (T)(m * gz)};   // sorted position
+  }
 }
 
 template <typename T>
 hipError_t launch_adj_deposit_particles(const AdjIO<T>& io, const DepLevel* tab, hipStream_t s) {
-  const int64_t nb = io.part_blk0[io.nlev];
+  const int64_t nb = io.item_blk0[io.nlev];
   if (nb <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_adj_deposit_particles<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab);
   return hipGetLastError();
