@@ -536,7 +536,8 @@ template <typename T> struct DepBatch {
 template <typename T>
 apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y, const T* z,
                              const T* m, int64_t npart, const int32_t* owner, const T* const* gas,
-                             const T* const* pgas, T* const* gmf, DepBatch<T>* out) {
+                             const T* const* pgas, T* const* gmf, DepBatch<T>* out,
+                             bool find_owner = false) {
   const Plan& P = c->plan;
   const int nl = (int)P.levels.size();
   c->lvb.resize(nl);
@@ -549,6 +550,12 @@ apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y
   DepIO<T> io{};
   io.x = x; io.y = y; io.z = z; io.m = m;
   io.owner = owner;
+  if (find_owner) {                                  // the scatter finds (and, for the
+    io.owner = nullptr;                              // root level, writes) the owners
+    io.om = c->d_owner_map;
+    io.om_nlev = nl;
+    io.owner_out = l0 == 0 ? (int32_t*)owner : nullptr;
+  }
   io.npart = npart;
   io.nlev = nlev;
   int64_t max_elems = 0, iblk = 0, fblk = 0;
@@ -682,9 +689,10 @@ apm_status deposit_launch_t(apm_ctx c, const DepBatch<T>& d) {
 template <typename T>
 apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y, const T* z,
                             const T* m, int64_t npart, const int32_t* owner, const T* const* gas,
-                            const T* const* pgas, T* const* gmf) {
+                            const T* const* pgas, T* const* gmf, bool find_owner = false) {
   DepBatch<T> d;
-  APM_TRY(deposit_prepare_t<T>(c, l0, nlev, x, y, z, m, npart, owner, gas, pgas, gmf, &d));
+  APM_TRY(deposit_prepare_t<T>(c, l0, nlev, x, y, z, m, npart, owner, gas, pgas, gmf, &d,
+                               find_owner));
   APM_TRY(sync_dep_table(c));
   return deposit_launch_t<T>(c, d);
 }
@@ -734,10 +742,7 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
   }
   APM_TRY(ensure(c, c->owner, (size_t)std::max<int64_t>(npart, 1) * 4, "owner"));
   int32_t* own = (int32_t*)c->owner.p;
-  HIP_TRY(timed(c, "owner", [&] {
-            return launch_owner<T>(c->d_owner_map, (int32_t)P.levels.size(), x, y, z, npart, own,
-                                   (T*)nullptr, (T*)nullptr, (T*)nullptr, (T*)nullptr, c->stream);
-          }), "owner");
+  // owner grids: found by the binning scatter (the root level's blocks write them)
   if (P.cfg.boundary == APM_BC_PERIODIC) APM_TRY(mean_density_t<T>(c, x, y, z, m, npart,
                                                                    gas ? (const T*)gas[0] : nullptr));
   {
@@ -757,7 +762,7 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
       lp.fld[l] = (V4<T>*)c->fld[di][l].p;
     }
     if (c->prof_on || nl < 2) {                      // one stream (kernels timed one by one)
-      APM_TRY(deposit_levels_t<T>(c, 0, nl, x, y, z, m, npart, own, gl, pg, gm));
+      APM_TRY(deposit_levels_t<T>(c, 0, nl, x, y, z, m, npart, own, gl, pg, gm, true));
       APM_TRY(convolve_t<T>(c, kAllLevels, lp));
     } else {
       // The root's deposit and transforms, and those of the subgrid levels, touch
@@ -765,9 +770,9 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
       // stream, forked from and joined back to the context's stream (two branches of
       // the captured graph).
       DepBatch<T> d0, d1;
-      APM_TRY(deposit_prepare_t<T>(c, 0, 1, x, y, z, m, npart, own, gl, pg, gm, &d0));
+      APM_TRY(deposit_prepare_t<T>(c, 0, 1, x, y, z, m, npart, own, gl, pg, gm, &d0, true));
       APM_TRY(deposit_prepare_t<T>(c, 1, nl - 1, x, y, z, m, npart, own, gl + 1, pg + 1, gm + 1,
-                                   &d1));
+                                   &d1, true));
       APM_TRY(sync_dep_table(c));
       APM_TRY(prepare_branch_stream(c));
       std::vector<Step> root, sub;

@@ -101,6 +101,29 @@ hipError_t launch_james(int N, double dx, double a0, double G, const double* cos
                         double* buf0, double* buf1, double** result, hipStream_t s);
 hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 
+// Owner lookup (finest grid whose active box holds a point, lowest index on that level):
+// per level either its single grid's active box or, for several grids, a table over
+// the bounding box of their active boxes with the lowest-index grid of every cell.
+struct OwnerLevel {
+  double inv_dx;
+  int32_t lo[3], n[3];             // box (level cells)
+  int32_t single;                  // the grid if the level has one, else -1
+  const int32_t* table;            // n[0] n[1] n[2] grid indices (-1: none), or null
+};
+__device__ __forceinline__ int owner_lookup(const OwnerLevel* __restrict__ om, int nlev, double px,
+                                            double py, double pz) {
+  for (int l = nlev - 1; l >= 0; --l) {
+    const OwnerLevel& o = om[l];
+    const int cx = (int)floor(px * o.inv_dx) - o.lo[0];
+    const int cy = (int)floor(py * o.inv_dx) - o.lo[1];
+    const int cz = (int)floor(pz * o.inv_dx) - o.lo[2];
+    if (cx < 0 || cx >= o.n[0] || cy < 0 || cy >= o.n[1] || cz < 0 || cz >= o.n[2]) continue;
+    const int g = o.single >= 0 ? o.single : o.table[((int64_t)cz * o.n[1] + cy) * o.n[0] + cx];
+    if (g >= 0) return g;
+  }
+  return -1;
+}
+
 // Particles: binning by 8^3 tile of the particle's cell i0 = floor(x/dx) inside the
 // level's binning box (union of GMF boxes grown by one cell), then the tile-wise
 // TSC deposit.  Every stage is one launch over a batch of consecutive levels.
@@ -140,6 +163,9 @@ struct DepLevel {
 template <typename T> struct DepIO {
   const T* x; const T* y; const T* z; const T* m;
   const int32_t* owner;                // owner grid per particle, or null (no owners)
+  const OwnerLevel* om;                // or the owner lookup of every level (om_nlev), the
+  int32_t om_nlev;                     // owner computed in the scatter, and written to
+  int32_t* owner_out;                  // owner_out (if not null) by the root level's blocks
   int64_t npart;
   int32_t nlev;
   int64_t item_blk0[kMaxLevels + 1];   // deposit-tile blocks of level b: [item_blk0[b], [b+1])
@@ -158,29 +184,6 @@ template <typename T> hipError_t launch_deposit_tiles(const DepIO<T>& io, const 
                                                       hipStream_t s);
 template <typename T> hipError_t launch_deposit_finalize(const DepIO<T>& io, const DepLevel* tab,
                                                          hipStream_t s);
-
-// Owner lookup (finest grid whose active box holds a point, lowest index on that level):
-// per level either its single grid's active box or, for several grids, a table over
-// the bounding box of their active boxes with the lowest-index grid of every cell.
-struct OwnerLevel {
-  double inv_dx;
-  int32_t lo[3], n[3];             // box (level cells)
-  int32_t single;                  // the grid if the level has one, else -1
-  const int32_t* table;            // n[0] n[1] n[2] grid indices (-1: none), or null
-};
-__device__ __forceinline__ int owner_lookup(const OwnerLevel* __restrict__ om, int nlev, double px,
-                                            double py, double pz) {
-  for (int l = nlev - 1; l >= 0; --l) {
-    const OwnerLevel& o = om[l];
-    const int cx = (int)floor(px * o.inv_dx) - o.lo[0];
-    const int cy = (int)floor(py * o.inv_dx) - o.lo[1];
-    const int cz = (int)floor(pz * o.inv_dx) - o.lo[2];
-    if (cx < 0 || cx >= o.n[0] || cy < 0 || cy >= o.n[1] || cz < 0 || cz >= o.n[2]) continue;
-    const int g = o.single >= 0 ? o.single : o.table[((int64_t)cz * o.n[1] + cy) * o.n[0] + cx];
-    if (g >= 0) return g;
-  }
-  return -1;
-}
 
 // owner grid of every particle; where the outputs are given, particles outside the
 // domain (owner -1) get zero acceleration and potential there

@@ -335,15 +335,26 @@ __global__ void __launch_bounds__(kBlock) k_bin_scatter(DepIO<T> io, const DepLe
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= io.npart) return;
   const int32_t key = as_global<int32_t>(L.key)[i];
-  if (key < 0) return;
+  // the root level bins every in-domain particle (key >= 0 exactly for those), so its
+  // blocks write the owner of every particle
+  const bool root = io.owner_out != nullptr && L.first == 0;
+  if (key < 0) {
+    if (root) io.owner_out[i] = -1;
+    return;
+  }
+  const T px = io.x[i], py = io.y[i], pz = io.z[i];
   const T sc = (T)L.inv_dx;
   V4<T> r;
-  r.x = io.x[i] * sc;                                // exact: dx is a power of two
-  r.y = io.y[i] * sc;
-  r.z = io.z[i] * sc;
+  r.x = px * sc;                                     // exact: dx is a power of two
+  r.y = py * sc;
+  r.z = pz * sc;
   r.w = io.m[i];
   int32_t og = -1;
-  if (io.owner) {
+  if (io.om) {                                       // as k_owner (in-domain: key >= 0)
+    const int32_t o = owner_lookup(io.om, io.om_nlev, px, py, pz);
+    if (root) io.owner_out[i] = o;
+    if (o >= L.first && o < L.first + L.ngrids) og = o;
+  } else if (io.owner) {
     const int32_t o = io.owner[i];
     if (o >= L.first && o < L.first + L.ngrids) og = o;
   }
