@@ -430,7 +430,9 @@ def main():
             t_adj = time.perf_counter() - t0
         log(f"oracle forward {t_fwd:.1f} s" + (f", reverse sweep {t_adj:.1f} s" if t_adj else ""))
         own = ref32["owner"] >= 0
-        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        def rel(a, b):
+            nb = float(np.linalg.norm(b))
+            return float(np.linalg.norm(a - b)) / nb if nb > 0 else None   # e.g. massless tracers
         err["fp32_acc_rel_l2"] = rel(r32["acc"][own], ref32["acc"][own])
         err["fp32_pot_rel_l2"] = rel(r32["pot"][own], ref32["pot"][own])
         if a32 is not None:
