@@ -224,6 +224,82 @@ __device__ __forceinline__ void fft_line(C2<T>* line, int w, const C2<T>* tw) {
   }
 }
 
+// ---- Stockham transform with the line in registers at both ends ------------------
+// Worker w of a line holds elements w + m L/8 (m = 0..7) in v[] before and after the
+// transform.  The first stage reads its butterflies' inputs from v (butterfly q of a
+// stage of radix R takes elements w + (q + r B) L/8, B = 8/R) and the last stage
+// writes its outputs back to the same places, so only the stages in between go
+// through LDS.  The workers of a line may sit in different wavefronts (columns
+// fastest across lanes, the layout of coalesced column loads), so the LDS exchanges
+// use block barriers and every thread of the block must call this.  On entry no
+// thread may still read the line's LDS; on exit reads of it may still be in flight:
+// the caller puts a block barrier before the line's LDS is written again.
+template <typename T, int L, int R, int NS, bool INV, bool FIRST>
+__device__ __forceinline__ void regs_stage(C2<T>* line, int w, C2<T> (&v)[8],
+                                           const C2<T>* __restrict__ tw) {
+  constexpr int B = 8 / R;
+  constexpr int W8 = L / 8;
+  constexpr bool LAST = NS * R == L;
+  C2<T> u[B][R];
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    const int j = w + q * W8;
+    const int k = j % NS;
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[q][r] = FIRST ? v[q + r * B] : line[swz<L>(j + r * (L / R))];
+    if (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C2<T> t = tw[(r * k) * (L / (NS * R))];
+        u[q][r] = INV ? cmulc(u[q][r], t) : cmul(u[q][r], t);
+      }
+    }
+    if (R == 8) dft8<INV, T>(u[q]);
+    else if (R == 4) dft4<INV>(u[q]);
+    else dft2<INV>(u[q]);
+  }
+  if constexpr (LAST) {
+    // j < NS here, so output r of butterfly q is element j + r NS = w + (q + r B) L/8
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q + r * B] = u[q][r];
+  } else {
+    if constexpr (!FIRST) __syncthreads();           // this stage's reads are done
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int j = w + q * W8;
+      const int base = (j / NS) * NS * R + j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) line[swz<L>(base + r * NS)] = u[q][r];
+    }
+    __syncthreads();                                 // writes seen by the next stage
+  }
+}
+
+template <typename T, int L, int NS, bool INV, bool FIRST>
+__device__ __forceinline__ void regs_radix8(C2<T>* line, int w, C2<T> (&v)[8], const C2<T>* tw) {
+  if constexpr (NS < L) {
+    regs_stage<T, L, 8, NS, INV, FIRST>(line, w, v, tw);
+    regs_radix8<T, L, NS * 8, INV, false>(line, w, v, tw);
+  }
+}
+
+// Unnormalised; INV: exp(+2 pi i ...).  Same stage sequence as fft_line.
+template <typename T, int L, bool INV>
+__device__ __forceinline__ void fft_regs(C2<T>* line, int w, C2<T> (&v)[8], const C2<T>* tw) {
+  constexpr int r0 = Log2<L>::v % 3;
+  if constexpr (r0 == 1) {
+    regs_stage<T, L, 2, 1, INV, true>(line, w, v, tw);
+    regs_radix8<T, L, 2, INV, false>(line, w, v, tw);
+  } else if constexpr (r0 == 2) {
+    regs_stage<T, L, 4, 1, INV, true>(line, w, v, tw);
+    regs_radix8<T, L, 4, INV, false>(line, w, v, tw);
+  } else {
+    regs_radix8<T, L, 1, INV, true>(line, w, v, tw);
+  }
+}
+
 // Lines per block for a given element type and length: 4096 (FP32) or 2048
 // (FP64) complex values per block -> 32-33 KB of LDS, 256 or 512 threads.
 template <typename T, int L> struct FFTShape {

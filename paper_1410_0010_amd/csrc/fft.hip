@@ -149,7 +149,10 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
 //   s = 0: Gf(k) rho_hat            (the x and y derivatives follow in later passes)
 //   s = 1: -i d_z(k_z) Gf(k) rho_hat
 //   s = 2: Gp(k) rho_hat
-// kern: octant table of (Gf, Gp), index ((|ky| W) + kx) Oz + |kz|, already scaled.
+// kern: octant table of (Gf, Gp), index ((|kz| Oy) + |ky|) W + kx, already scaled.
+// Thread t works on column t mod nl as worker t / nl of its line: the column loads
+// and stores are coalesced across lanes and go straight to and from the registers
+// the transforms start and end in (only the middle Stockham stages use LDS).
 
 template <typename T, int L>
 __global__ void __launch_bounds__(kZConvMaxThreads)
@@ -172,62 +175,47 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int64_t pstride = (int64_t)My * P;
   const int64_t qstride = (int64_t)(L / 8) * pstride;   // uniform: q steps by a scalar
   const int t = threadIdx.x;
-  const int cb = t % nl, r0 = t / nl;                // column-wise mapping, as in y_fwd
+  const int cb = t % nl, w = t / nl;
   const bool col_ok = c0 + cb < W;
+  C2<T>* line = lds + cb * ls;
+  C2<T> X[8];
   {
-    const C2<T>* src = spec + (int64_t)ky * P + c0 + cb + r0 * pstride;
-    C2<T> v[8];
+    const C2<T>* src = spec + (int64_t)ky * P + c0 + cb + w * pstride;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int z = r0 + q * (L / 8);
-      v[q] = (z < gz && col_ok) ? src[q * qstride] : mk<T>(0, 0);
+      const int z = w + q * (L / 8);
+      X[q] = (z < gz && col_ok) ? src[q * qstride] : mk<T>(0, 0);
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
   }
-  __syncthreads();
-  const int b = t / (L / 8), w = t % (L / 8);
-  C2<T>* line = lds + b * ls;
-  // this worker's multipliers, loaded while the forward transform runs
-  const int kx = c0 + b;
-  const int kxc = kx < W ? kx : 0;
+  fft_regs<T, L, false>(line, w, X, tw);
+  // multipliers of this column: kx fastest in the table, so lanes read neighbours
+  const int kxc = col_ok ? c0 + cb : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
-  // this column's multipliers: one contiguous run of L/2 + 1 in the table, read for
-  // each product where it is used (holding all three sets for the whole kernel cost
-  // 24 registers, and the register count bounds the waves per SIMD)
-  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)(kyo * W + kxc) * (L / 2 + 1);
-  fft_line<T, L, false>(line, w, tw);
-  C2<T> X[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) X[q] = line[swz<L>(w + q * (L / 8))];
+  // 32-bit offsets from block-uniform bases (an octant table has < 2^31 entries)
+  const uint32_t ostride = (uint32_t)((My / 2 + 1) * W);
+  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)kyo * W;
+  C2<T>* dst = zo + (int64_t)ky * P + c0 + cb;
 #pragma unroll 1
   for (int s = 0; s < 3; ++s) {
-    T mul[8];
+    C2<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int kz = w + q * (L / 8);
       const int kzo = kz <= L / 2 ? kz : L - kz;
-      const nvec2<T> gv = gcol[kzo];
-      mul[q] = s == 0 ? gv.x : (s == 1 ? dzs[kz] * gv.x : gv.y);
+      const nvec2<T> gv = gcol[(uint32_t)kzo * ostride + (uint32_t)kxc];
+      const T mul = s == 0 ? gv.x : (s == 1 ? dzs[kz] * gv.x : gv.y);
+      v[q] = s == 1 ? mk<T>(mul * X[q].y, -mul * X[q].x)   // -i d_z Gf X
+                    : mk<T>(mul * X[q].x, mul * X[q].y);
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const C2<T> v = s == 1 ? mk<T>(mul[q] * X[q].y, -mul[q] * X[q].x)   // -i d_z Gf X
-                             : mk<T>(mul[q] * X[q].x, mul[q] * X[q].y);
-      line[swz<L>(w + q * (L / 8))] = v;
-    }
-    __syncthreads();
-    fft_line<T, L, true>(line, w, tw);
-    __syncthreads();                                 // stores use another mapping
+    __syncthreads();                                 // the previous transform's reads
+    fft_regs<T, L, true>(line, w, v, tw);
     if (col_ok) {
-      C2<T>* dst = zo + ((int64_t)s * fz + r0) * pstride + (int64_t)ky * P + c0 + cb;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int j = r0 + q * (L / 8);
-        if (j < fz) dst[q * qstride] = lds[cb * ls + swz<L>((oz + j) & (L - 1))];
+        const int j = (w + q * (L / 8) - oz) & (L - 1);  // field plane of element w + q L/8
+        if (j < fz) dst[((int64_t)s * fz + j) * pstride] = v[q];
       }
     }
-    __syncthreads();
   }
 }
 

@@ -186,7 +186,8 @@ k_adj_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 // Block = (ky, nl columns), one line per column: the three z-buffer arrays in turn
 // (planes j < fz at positions (oz + j) mod L) -> forward FFT -> accumulated into
 // S = Gf (U + i d_z V) + Gp P in registers; then the inverse FFT of S and the gz GMF
-// planes into the spectrum buffer.
+// planes into the spectrum buffer.  Thread t is worker t / nl of column t mod nl,
+// as in the forward z pass: loads and stores go straight to the transform registers.
 template <typename T, int L>
 __global__ void __launch_bounds__(kZConvMaxThreads)
 k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
@@ -207,65 +208,53 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   C2<T>* spec = specb + J.spec_off + (int64_t)ky * P + c0;
   const gptr<T> dzs = as_global<T>(J.dsym[2]);
   const int t = threadIdx.x;
-  const int cb = t % nl, r0 = t / nl;
+  const int cb = t % nl, w = t / nl;
   const bool col_ok = c0 + cb < W;
-  const int b = t / (L / 8), w = t % (L / 8);
-  C2<T>* line = lds + b * ls;
-  const int kx = c0 + b;
-  const int kxc = kx < W ? kx : 0;
+  C2<T>* line = lds + cb * ls;
+  const int kxc = col_ok ? c0 + cb : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
   // 24-bit multiplies: jz < 2^11, My P < 2^24, every product < 2^31
   const uint32_t ps32 = (uint32_t)pstride;
-  // this column's multipliers: one contiguous run of L/2 + 1 in the table
-  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)(kyo * W + kxc) * (L / 2 + 1);
-  T gf[8], gp[8], dz[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int kz = w + q * (L / 8);
-    const int kzo = kz <= L / 2 ? kz : L - kz;
-    const nvec2<T> gv = gcol[kzo];
-    const C2<T> G = mk<T>(gv.x, gv.y);
-    gf[q] = G.x;
-    gp[q] = G.y;
-    dz[q] = dzs[kz];
-  }
+  // multipliers of this column: kx fastest in the table, so lanes read neighbours;
+  // each product's set is read where it is used (holding all three for the whole
+  // kernel spills FP64 registers)
+  const int64_t ostride = (int64_t)(My / 2 + 1) * W;
+  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)kyo * W + kxc;
   C2<T> S[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) S[q] = mk<T>(0, 0);
+#pragma unroll 1
   for (int s = 0; s < 3; ++s) {
     const C2<T>* zs_in = zin + s * zs;
     C2<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int r = r0 + q * (L / 8);                // transform position
+      const int r = w + q * (L / 8);                 // transform position
       const int jz = (r - oz) & (L - 1);             // field plane landing there
       v[q] = (col_ok && jz < fz) ? zs_in[__umul24((uint32_t)jz, ps32) + cb] : mk<T>(0, 0);
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
-    __syncthreads();
-    fft_line<T, L, false>(line, w, tw);
+    if (s > 0) __syncthreads();                      // the previous transform's reads
+    fft_regs<T, L, false>(line, w, v, tw);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const C2<T> X = line[swz<L>(w + q * (L / 8))];
-      if (s == 0) S[q] = cadd(S[q], mk<T>(gf[q] * X.x, gf[q] * X.y));
-      else if (s == 1) S[q] = cadd(S[q], mul_id<T>(gf[q] * dz[q], X));
-      else S[q] = cadd(S[q], mk<T>(gp[q] * X.x, gp[q] * X.y));
+      const int kz = w + q * (L / 8);
+      const int kzo = kz <= L / 2 ? kz : L - kz;
+      const nvec2<T> gv = gcol[kzo * ostride];
+      const C2<T> X = v[q];
+      if (s == 0) S[q] = cadd(S[q], mk<T>(gv.x * X.x, gv.x * X.y));
+      else if (s == 1) S[q] = cadd(S[q], mul_id<T>(gv.x * dzs[kz], X));
+      else S[q] = cadd(S[q], mk<T>(gv.y * X.x, gv.y * X.y));
     }
-    __syncthreads();                                 // the line is reloaded next
   }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) line[swz<L>(w + q * (L / 8))] = S[q];
   __syncthreads();
-  fft_line<T, L, true>(line, w, tw);
-  __syncthreads();                                   // stores use another mapping
+  fft_regs<T, L, true>(line, w, S, tw);
   if (col_ok) {
-    C2<T>* dst = spec + r0 * pstride + cb;
+    C2<T>* dst = spec + w * pstride + cb;
     const int64_t qstride = (int64_t)(L / 8) * pstride;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int z = r0 + q * (L / 8);
-      if (z < gz) dst[q * qstride] = lds[cb * ls + swz<L>(z)];
+      const int z = w + q * (L / 8);
+      if (z < gz) dst[q * qstride] = S[q];
     }
   }
 }
@@ -488,53 +477,41 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int64_t pstride = (int64_t)My * P;
   C2<T>* spec = specb + J.spec_off + (int64_t)ky * P + c0;
   const int t = threadIdx.x;
-  const int cb = t % nl, r0 = t / nl;
+  const int cb = t % nl, w = t / nl;
   const bool col_ok = c0 + cb < W;
-  const int b = t / (L / 8), w = t % (L / 8);
-  C2<T>* line = lds + b * ls;
-  const int kx = c0 + b;
-  const int kxc = kx < W ? kx : 0;
+  C2<T>* line = lds + cb * ls;
+  const int kxc = col_ok ? c0 + cb : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
   // 24-bit multiplies: jz < 2^11, My P < 2^24, every product < 2^31
   const uint32_t ps32 = (uint32_t)pstride;
-  // this column's multipliers: one contiguous run of L/2 + 1 in the table
-  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)(kyo * W + kxc) * (L / 2 + 1);
+  const int64_t ostride = (int64_t)(My / 2 + 1) * W;
+  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)kyo * W + kxc;
+  C2<T> v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int r = w + q * (L / 8);
+    const int jz = (r - oz) & (L - 1);
+    v[q] = (col_ok && jz < fz) ? zin[__umul24((uint32_t)jz, ps32) + cb] : mk<T>(0, 0);
+  }
   T gp[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int kz = w + q * (L / 8);
     const int kzo = kz <= L / 2 ? kz : L - kz;
-    gp[q] = gcol[kzo].y;
+    gp[q] = gcol[kzo * ostride].y;
   }
-  {
-    C2<T> v[8];
+  fft_regs<T, L, false>(line, w, v, tw);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int r = r0 + q * (L / 8);
-      const int jz = (r - oz) & (L - 1);
-      v[q] = (col_ok && jz < fz) ? zin[__umul24((uint32_t)jz, ps32) + cb] : mk<T>(0, 0);
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
-  }
+  for (int q = 0; q < 8; ++q) v[q] = mk<T>(gp[q] * v[q].x, gp[q] * v[q].y);
   __syncthreads();
-  fft_line<T, L, false>(line, w, tw);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int k = swz<L>(w + q * (L / 8));
-    const C2<T> X = line[k];
-    line[k] = mk<T>(gp[q] * X.x, gp[q] * X.y);
-  }
-  __syncthreads();
-  fft_line<T, L, true>(line, w, tw);
-  __syncthreads();
+  fft_regs<T, L, true>(line, w, v, tw);
   if (col_ok) {
-    C2<T>* dst = spec + r0 * pstride + cb;
+    C2<T>* dst = spec + w * pstride + cb;
     const int64_t qstride = (int64_t)(L / 8) * pstride;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int z = r0 + q * (L / 8);
-      if (z < gz) dst[q * qstride] = lds[cb * ls + swz<L>(z)];
+      const int z = w + q * (L / 8);
+      if (z < gz) dst[q * qstride] = v[q];
     }
   }
 }

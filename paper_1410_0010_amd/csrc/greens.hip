@@ -11,8 +11,8 @@
 // the doubled-mesh reference potential (James) plus optimal - reference.  Periodic
 // root (Sec. 2.1): the level-0 kernels on the root's own mesh, zero at k = 0.
 // Tables hold the octant |m_i| <= M_i/2 (both kernels are even in every axis),
-// scaled by 1/(Mx My Mz) for the unnormalised transforms, at ((|my| Ox) + |mx|) Oz
-// + |mz| (Ox = Mx/2 + 1, Oz = Mz/2 + 1).
+// scaled by 1/(Mx My Mz) for the unnormalised transforms, at ((|mz| Oy) + |my|) Ox
+// + |mx| (Ox = Mx/2 + 1, Oy = My/2 + 1).
 #include <cmath>
 
 #include "apm_kernels.hpp"
@@ -140,9 +140,9 @@ __global__ void k_influence(InfluenceParams p, double2* __restrict__ out) {
       gp = jm + (gp - gref);
     }
   }
-  // stored kz-fastest, ((my Ox) + mx) Oz + mz: the z pass reads each column's
-  // multipliers as one contiguous run
-  out[((int64_t)my * Ox + mx) * Oz + mz] = make_double2(gf * p.norm, gp * p.norm);
+  // stored kx-fastest, ((mz Oy) + my) Ox + mx: in the z passes neighbouring lanes
+  // work on neighbouring kx columns
+  out[((int64_t)mz * Oy + my) * Ox + mx] = make_double2(gf * p.norm, gp * p.norm);
 }
 
 hipError_t launch_influence(const InfluenceParams& p, double2* out, hipStream_t s) {

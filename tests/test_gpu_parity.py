@@ -371,6 +371,45 @@ def test_graph_replays_match_eager(dtype):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_graph_replays_periodic_recompute_the_mean(dtype):
+    """A periodic solve with root and subgrid gas under graph replay: the average
+    density is taken inside the graph, so rewriting the masses in place between
+    replays changes the result exactly as an eager solve on the new masses does."""
+    w = periodic_sine_particles()
+    say(f"[graph] periodic sine32 dtype={dtype.__name__}")
+    plan = P.Plan(w.root_n, w.grids, boundary="periodic")
+    ctx = P.Context(plan, 0)
+    t = [dev(a, dtype) for a in (w.x, w.y, w.z, w.m)]
+    gas = [ctx.pack_gas(l, w.gas, t[0].dtype) for l in range(plan.nlevels)]
+    ctx.set_graph(False)
+    ref1 = _solve_np(ctx, t, gas)
+    m2 = np.asarray(w.m) * 3.0 + 1e-4
+    eager2 = P.Context(plan, 0)
+    eager2.set_graph(False)
+    ref2 = _solve_np(eager2, t[:3] + [dev(m2, dtype)], gas)
+    ctx.set_graph(True)
+    tol = 1e-12 if dtype == np.float64 else 2e-6
+    outs = [torch.empty(w.npart, dtype=t[0].dtype, device=DEV) for _ in range(4)]
+    m1 = t[3].clone()
+    for rep in range(6):
+        ref = ref1 if rep % 2 == 0 else ref2
+        t[3].copy_(m1 if rep % 2 == 0 else dev(m2, dtype))
+        ctx.solve(*t, gas, *outs)
+        torch.cuda.synchronize()
+        got = np.stack([o.cpu().numpy() for o in outs], 1).astype(np.float64)
+        e = rel(got, ref)
+        assert e <= tol, f"replay {rep}: rel {e:.3e}"
+        for o in outs:
+            o.fill_(np.nan)
+    assert rel(ref1, ref2) > 0.1                 # the two mass sets differ in the result
+    w2 = periodic_sine_particles()
+    w2.m = m2
+    oref = run_oracle(w2, dtype)
+    own = oref["owner"] >= 0
+    assert rel(ref2[own, :3], oref["acc"][own]) <= TOL[dtype]["acc"]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
 def test_autotune_keeps_parity(dtype):
     w = W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=2, npart=20000)
     say(f"[autotune] nested32 dtype={dtype.__name__}")
