@@ -234,25 +234,48 @@ __device__ __forceinline__ void fft_line(C2<T>* line, int w, const C2<T>* tw) {
 // use block barriers and every thread of the block must call this.  On entry no
 // thread may still read the line's LDS; on exit reads of it may still be in flight:
 // the caller puts a block barrier before the line's LDS is written again.
+//
+// Twiddles: every stage after the first is radix 8 with one butterfly per worker,
+// k = w mod NS, and needs w_{8 NS}^{r k} for r = 1..7.  Only the base w_{8 NS}^k is
+// read (once per kernel, with the data loads, so no table read waits behind a
+// barrier); the other powers are products of it, at most three deep.
+template <typename T, int L> struct Twid {
+  static constexpr int r0 = Log2<L>::v % 3;
+  static constexpr int first_ns = r0 == 1 ? 2 : (r0 == 2 ? 4 : 8);   // NS of the first twiddled stage
+  static constexpr int count() { int n = 0; for (int ns = first_ns; ns < L; ns *= 8) ++n; return n; }
+  static constexpr int index(int ns) { int i = 0; for (int n = first_ns; n < ns; n *= 8) ++i; return i; }
+  static constexpr int N = count();
+  C2<T> t[N > 0 ? N : 1];
+  __device__ __forceinline__ Twid(int w, const C2<T>* __restrict__ tw) {
+    int ns = first_ns;
+#pragma unroll
+    for (int i = 0; i < N; ++i, ns *= 8) t[i] = tw[(w % ns) * (L / (ns * 8))];
+  }
+};
+
 template <typename T, int L, int R, int NS, bool INV, bool FIRST>
-__device__ __forceinline__ void regs_stage(C2<T>* line, int w, C2<T> (&v)[8],
-                                           const C2<T>* __restrict__ tw) {
+__device__ __forceinline__ void regs_stage(C2<T>* line, int w, C2<T> (&v)[8], const Twid<T, L>& tb) {
   constexpr int B = 8 / R;
   constexpr int W8 = L / 8;
   constexpr bool LAST = NS * R == L;
+  static_assert(NS == 1 || R == 8, "only a first stage has radix 2 or 4");
   C2<T> u[B][R];
 #pragma unroll
   for (int q = 0; q < B; ++q) {
     const int j = w + q * W8;
-    const int k = j % NS;
 #pragma unroll
     for (int r = 0; r < R; ++r) u[q][r] = FIRST ? v[q + r * B] : line[swz<L>(j + r * (L / R))];
-    if (NS > 1) {
+    if constexpr (NS > 1) {
+      C2<T> p[8];
+      p[1] = tb.t[Twid<T, L>::index(NS)];
+      p[2] = cmul(p[1], p[1]);
+      p[3] = cmul(p[2], p[1]);
+      p[4] = cmul(p[2], p[2]);
+      p[5] = cmul(p[4], p[1]);
+      p[6] = cmul(p[3], p[3]);
+      p[7] = cmul(p[4], p[3]);
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        C2<T> t = tw[(r * k) * (L / (NS * R))];
-        u[q][r] = INV ? cmulc(u[q][r], t) : cmul(u[q][r], t);
-      }
+      for (int r = 1; r < 8; ++r) u[q][r] = INV ? cmulc(u[q][r], p[r]) : cmul(u[q][r], p[r]);
     }
     if (R == 8) dft8<INV, T>(u[q]);
     else if (R == 4) dft4<INV>(u[q]);
@@ -278,25 +301,26 @@ __device__ __forceinline__ void regs_stage(C2<T>* line, int w, C2<T> (&v)[8],
 }
 
 template <typename T, int L, int NS, bool INV, bool FIRST>
-__device__ __forceinline__ void regs_radix8(C2<T>* line, int w, C2<T> (&v)[8], const C2<T>* tw) {
+__device__ __forceinline__ void regs_radix8(C2<T>* line, int w, C2<T> (&v)[8], const Twid<T, L>& tb) {
   if constexpr (NS < L) {
-    regs_stage<T, L, 8, NS, INV, FIRST>(line, w, v, tw);
-    regs_radix8<T, L, NS * 8, INV, false>(line, w, v, tw);
+    regs_stage<T, L, 8, NS, INV, FIRST>(line, w, v, tb);
+    regs_radix8<T, L, NS * 8, INV, false>(line, w, v, tb);
   }
 }
 
-// Unnormalised; INV: exp(+2 pi i ...).  Same stage sequence as fft_line.
+// Unnormalised; INV: exp(+2 pi i ...).  Same stage sequence as fft_line; tb from
+// Twid<T, L>(w, tw) of the same worker.
 template <typename T, int L, bool INV>
-__device__ __forceinline__ void fft_regs(C2<T>* line, int w, C2<T> (&v)[8], const C2<T>* tw) {
+__device__ __forceinline__ void fft_regs(C2<T>* line, int w, C2<T> (&v)[8], const Twid<T, L>& tb) {
   constexpr int r0 = Log2<L>::v % 3;
   if constexpr (r0 == 1) {
-    regs_stage<T, L, 2, 1, INV, true>(line, w, v, tw);
-    regs_radix8<T, L, 2, INV, false>(line, w, v, tw);
+    regs_stage<T, L, 2, 1, INV, true>(line, w, v, tb);
+    regs_radix8<T, L, 2, INV, false>(line, w, v, tb);
   } else if constexpr (r0 == 2) {
-    regs_stage<T, L, 4, 1, INV, true>(line, w, v, tw);
-    regs_radix8<T, L, 4, INV, false>(line, w, v, tw);
+    regs_stage<T, L, 4, 1, INV, true>(line, w, v, tb);
+    regs_radix8<T, L, 4, INV, false>(line, w, v, tb);
   } else {
-    regs_radix8<T, L, 1, INV, true>(line, w, v, tw);
+    regs_radix8<T, L, 1, INV, true>(line, w, v, tb);
   }
 }
 

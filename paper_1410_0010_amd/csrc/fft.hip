@@ -102,6 +102,8 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
 
 // ------------------------------------------------------ y forward (columns) --
 // Lines along y of the gz spectrum planes: rows [0, gy) in, all My rows out, in place.
+// Thread t is worker t / nl of column t mod nl: the coalesced column loads and
+// stores go straight to and from the transform's registers.
 template <typename T, int L>
 __global__ void __launch_bounds__(1024)
 k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* __restrict__ specb,
@@ -117,28 +119,19 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
   const int c0 = (int)(blk % nbw) * nl;
   C2<T>* base = specb + J.spec_off + p * ((int64_t)My * P) + c0;
   const int t = threadIdx.x;
-  // column-wise mapping: thread t holds column t mod nl, rows t/nl + q L/8 (nl L/8
-  // threads, 8 elements each; all loads issued before the first LDS write)
-  const int cb = t % nl, r0 = t / nl;
+  const int cb = t % nl, w = t / nl;
+  const Twid<T, L> tb(w, tw);
   const bool col_ok = c0 + cb < W;
   C2<T> v[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int r = r0 + q * (L / 8);
+    const int r = w + q * (L / 8);
     v[q] = (r < gy && col_ok) ? base[(int64_t)r * P + cb] : mk<T>(0, 0);
   }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
-  __syncthreads();
-  const int b = t / (L / 8), w = t % (L / 8);
-  fft_line<T, L, false>(lds + b * ls, w, tw);
-  __syncthreads();                                   // stores use another mapping
+  fft_regs<T, L, false>(lds + cb * ls, w, v, tb);
   if (col_ok) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int j = r0 + q * (L / 8);
-      base[(int64_t)j * P + cb] = lds[cb * ls + swz<L>(j)];
-    }
+    for (int q = 0; q < 8; ++q) base[(int64_t)(w + q * (L / 8)) * P + cb] = v[q];
   }
 }
 
@@ -176,6 +169,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int64_t qstride = (int64_t)(L / 8) * pstride;   // uniform: q steps by a scalar
   const int t = threadIdx.x;
   const int cb = t % nl, w = t / nl;
+  const Twid<T, L> tb(w, tw);
   const bool col_ok = c0 + cb < W;
   C2<T>* line = lds + cb * ls;
   C2<T> X[8];
@@ -187,7 +181,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       X[q] = (z < gz && col_ok) ? src[q * qstride] : mk<T>(0, 0);
     }
   }
-  fft_regs<T, L, false>(line, w, X, tw);
+  fft_regs<T, L, false>(line, w, X, tb);
   // multipliers of this column: kx fastest in the table, so lanes read neighbours
   const int kxc = col_ok ? c0 + cb : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
@@ -208,7 +202,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
                     : mk<T>(mul * X[q].x, mul * X[q].y);
     }
     __syncthreads();                                 // the previous transform's reads
-    fft_regs<T, L, true>(line, w, v, tw);
+    fft_regs<T, L, true>(line, w, v, tb);
     if (col_ok) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -224,7 +218,10 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 // the three z arrays: a_x <- Gf rho (its x derivative follows in the x pass),
 // a_y <- -i d_y(k_y) Gf rho, a_z <- array 1, Phi <- array 2; inverse FFT along y;
 // rows j' < fy written from transform index (off_y + j') mod L into the y buffer
-// (planes c fz + j, fy rows, W columns).
+// (planes c fz + j, fy rows, W columns).  Thread t is worker t / (4 nl) of line
+// (component (t / nl) mod 4, column t mod nl): its column loads and stores go
+// straight to and from the transform's registers (the a_x and a_y lines of a column
+// read the same array 0 elements; the second read hits the cache).
 template <typename T, int L>
 __global__ void __launch_bounds__(1024)
 k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
@@ -240,45 +237,33 @@ k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int j = (int)(blk / nbw);
   const int c0 = (int)(blk % nbw) * nl;
   const gptr<T> dys = as_global<T>(J.dsym[1]);
-  const C2<T>* zin = zb + J.z_off + (int64_t)j * My * P + c0;
-  const int64_t zs = (int64_t)fz * My * P;             // stride between z arrays
-  C2<T>* yout = yb + J.y_off + (int64_t)j * fy * P + c0;
-  const int64_t ys = (int64_t)fz * fy * P;             // stride between components
   const int t = threadIdx.x;
-  // lines: component c of column cb at lds[(c nl + cb) ls]; loads are column-wise,
-  // thread t: column t mod nl, rows t/nl + q L/2 (4 nl L/8 threads, 2 rows each)
-  const int cb = t % nl, r0 = t / nl;
+  const int cb = t % nl, c = (t / nl) & 3, w = t / (4 * nl);
+  const Twid<T, L> tb(w, tw);
   const bool col_ok = c0 + cb < W;
-  C2<T> v[2][3];
+  const int64_t zs = (int64_t)fz * My * P;             // stride between z arrays
+  const C2<T>* zin = zb + J.z_off + (c == 0 ? 0 : c - 1) * zs + (int64_t)j * My * P + c0 + cb;
+  C2<T> v[8];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int64_t o = (int64_t)(r0 + q * (L / 2)) * P + cb;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) v[q][a] = col_ok ? zin[a * zs + o] : mk<T>(0, 0);
+  for (int q = 0; q < 8; ++q) {
+    const int r = w + q * (L / 8);
+    v[q] = col_ok ? zin[(int64_t)r * P] : mk<T>(0, 0);
   }
+  if (c == 1) {                                      // -i d_y Gf rho
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int r = r0 + q * (L / 2);
-    const T d = dys[r];
-    const int rs = swz<L>(r);
-    lds[(0 * nl + cb) * ls + rs] = v[q][0];
-    lds[(1 * nl + cb) * ls + rs] = mk<T>(d * v[q][0].y, -d * v[q][0].x);   // -i d_y Gf rho
-    lds[(2 * nl + cb) * ls + rs] = v[q][1];
-    lds[(3 * nl + cb) * ls + rs] = v[q][2];
+    for (int q = 0; q < 8; ++q) {
+      const T d = dys[w + q * (L / 8)];
+      v[q] = mk<T>(d * v[q].y, -d * v[q].x);
+    }
   }
-  __syncthreads();
-  const int b = t / (L / 8), w = t % (L / 8);
-  fft_line<T, L, true>(lds + b * ls, w, tw);
-  __syncthreads();                                   // stores use another mapping
+  fft_regs<T, L, true>(lds + (c * nl + cb) * ls, w, v, tb);
   if (col_ok) {
+    const int64_t ys = (int64_t)fz * fy * P;           // stride between components
+    C2<T>* yout = yb + J.y_off + c * ys + (int64_t)j * fy * P + c0 + cb;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int jj = r0 + q * (L / 2);
-      if (jj < fy) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          yout[c * ys + (int64_t)jj * P + cb] = lds[(c * nl + cb) * ls + swz<L>((oy + jj) & (L - 1))];
-      }
+    for (int q = 0; q < 8; ++q) {
+      const int jj = (w + q * (L / 8) - oy) & (L - 1);  // field row of this element
+      if (jj < fy) yout[(int64_t)jj * P] = v[q];
     }
   }
 }

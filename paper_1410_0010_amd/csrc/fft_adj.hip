@@ -209,6 +209,7 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const gptr<T> dzs = as_global<T>(J.dsym[2]);
   const int t = threadIdx.x;
   const int cb = t % nl, w = t / nl;
+  const Twid<T, L> tb(w, tw);
   const bool col_ok = c0 + cb < W;
   C2<T>* line = lds + cb * ls;
   const int kxc = col_ok ? c0 + cb : 0;
@@ -234,7 +235,7 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       v[q] = (col_ok && jz < fz) ? zs_in[__umul24((uint32_t)jz, ps32) + cb] : mk<T>(0, 0);
     }
     if (s > 0) __syncthreads();                      // the previous transform's reads
-    fft_regs<T, L, false>(line, w, v, tw);
+    fft_regs<T, L, false>(line, w, v, tb);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int kz = w + q * (L / 8);
@@ -247,7 +248,7 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
     }
   }
   __syncthreads();
-  fft_regs<T, L, true>(line, w, S, tw);
+  fft_regs<T, L, true>(line, w, S, tb);
   if (col_ok) {
     C2<T>* dst = spec + w * pstride + cb;
     const int64_t qstride = (int64_t)(L / 8) * pstride;
@@ -261,7 +262,7 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 
 // ------------------------------------------------------------------ ayi ---------
 // Block = (plane z < gz, nl columns): inverse FFT along y of all My rows, rows
-// [0, gy) written back in place.
+// [0, gy) written back in place; thread t is worker t / nl of column t mod nl.
 template <typename T, int L>
 __global__ void __launch_bounds__(1024)
 k_adj_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* __restrict__ specb,
@@ -277,25 +278,21 @@ k_adj_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
   const int c0 = (int)(blk % nbw) * nl;
   C2<T>* base = specb + J.spec_off + p * ((int64_t)My * P) + c0;
   const int t = threadIdx.x;
-  const int cb = t % nl, r0 = t / nl;
+  const int cb = t % nl, w = t / nl;
+  const Twid<T, L> tb(w, tw);
   const bool col_ok = c0 + cb < W;
   C2<T> v[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int r = r0 + q * (L / 8);
+    const int r = w + q * (L / 8);
     v[q] = col_ok ? base[(int64_t)r * P + cb] : mk<T>(0, 0);
   }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
-  __syncthreads();
-  const int b = t / (L / 8), w = t % (L / 8);
-  fft_line<T, L, true>(lds + b * ls, w, tw);
-  __syncthreads();
+  fft_regs<T, L, true>(lds + cb * ls, w, v, tb);
   if (col_ok) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int r = r0 + q * (L / 8);
-      if (r < gy) base[(int64_t)r * P + cb] = lds[cb * ls + swz<L>(r)];
+      const int r = w + q * (L / 8);
+      if (r < gy) base[(int64_t)r * P + cb] = v[q];
     }
   }
 }
@@ -435,27 +432,20 @@ k_adjp_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const C2<T>* yin = yb + J.y_off + (int64_t)j * fy * P + c0;
   C2<T>* zout = zb + J.z_off + (int64_t)j * My * P + c0;
   const int t = threadIdx.x;
-  const int cb = t % nl, r0 = t / nl;
+  const int cb = t % nl, w = t / nl;
+  const Twid<T, L> tb(w, tw);
   const bool col_ok = c0 + cb < W;
   C2<T> v[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int r = r0 + q * (L / 8);
+    const int r = w + q * (L / 8);
     const int y = (r - oy) & (L - 1);
     v[q] = (col_ok && y < fy) ? yin[(int64_t)y * P + cb] : mk<T>(0, 0);
   }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) lds[cb * ls + swz<L>(r0 + q * (L / 8))] = v[q];
-  __syncthreads();
-  const int b = t / (L / 8), w = t % (L / 8);
-  fft_line<T, L, false>(lds + b * ls, w, tw);
-  __syncthreads();
+  fft_regs<T, L, false>(lds + cb * ls, w, v, tb);
   if (col_ok) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int k = r0 + q * (L / 8);
-      zout[(int64_t)k * P + cb] = lds[cb * ls + swz<L>(k)];
-    }
+    for (int q = 0; q < 8; ++q) zout[(int64_t)(w + q * (L / 8)) * P + cb] = v[q];
   }
 }
 
@@ -478,6 +468,7 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   C2<T>* spec = specb + J.spec_off + (int64_t)ky * P + c0;
   const int t = threadIdx.x;
   const int cb = t % nl, w = t / nl;
+  const Twid<T, L> tb(w, tw);
   const bool col_ok = c0 + cb < W;
   C2<T>* line = lds + cb * ls;
   const int kxc = col_ok ? c0 + cb : 0;
@@ -500,11 +491,11 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
     const int kzo = kz <= L / 2 ? kz : L - kz;
     gp[q] = gcol[kzo * ostride].y;
   }
-  fft_regs<T, L, false>(line, w, v, tw);
+  fft_regs<T, L, false>(line, w, v, tb);
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = mk<T>(gp[q] * v[q].x, gp[q] * v[q].y);
   __syncthreads();
-  fft_regs<T, L, true>(line, w, v, tw);
+  fft_regs<T, L, true>(line, w, v, tb);
   if (col_ok) {
     C2<T>* dst = spec + w * pstride + cb;
     const int64_t qstride = (int64_t)(L / 8) * pstride;
