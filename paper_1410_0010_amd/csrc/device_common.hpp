@@ -157,29 +157,58 @@ __host__ __device__ constexpr int line_stride(int L) {
        : L == 512 ? 517 : L + 5;
 }
 
+// ---- twiddles ---------------------------------------------------------------------
+// Every Stockham stage after the first is radix 8 with one butterfly per worker,
+// k = w mod NS, and needs w_{8 NS}^{r k} for r = 1..7.  Only the base w_{8 NS}^k is
+// read (once per kernel, beside the data loads, so no table read waits behind a
+// barrier); the other powers are products of it, at most three deep.
+template <typename T, int L> struct Twid {
+  static constexpr int r0 = Log2<L>::v % 3;
+  static constexpr int first_ns = r0 == 1 ? 2 : (r0 == 2 ? 4 : 8);   // NS of the first twiddled stage
+  static constexpr int count() { int n = 0; for (int ns = first_ns; ns < L; ns *= 8) ++n; return n; }
+  static constexpr int index(int ns) { int i = 0; for (int n = first_ns; n < ns; n *= 8) ++i; return i; }
+  static constexpr int N = count();
+  C2<T> t[N > 0 ? N : 1];
+  __device__ __forceinline__ Twid(int w, const C2<T>* __restrict__ tw) {
+    int ns = first_ns;
+#pragma unroll
+    for (int i = 0; i < N; ++i, ns *= 8) t[i] = tw[(w % ns) * (L / (ns * 8))];
+  }
+};
+
+template <typename C>
+__device__ __forceinline__ void twiddle_powers(C (&p)[8], C t1) {
+  p[1] = t1;
+  p[2] = cmul(p[1], p[1]);
+  p[3] = cmul(p[2], p[1]);
+  p[4] = cmul(p[2], p[2]);
+  p[5] = cmul(p[4], p[1]);
+  p[6] = cmul(p[3], p[3]);
+  p[7] = cmul(p[4], p[3]);
+}
+
 // ---- Stockham auto-sort radix stages on one line held in LDS --------------------
 // A line of L complex values; L/8 workers per line; each worker always handles
 // 8 values per stage: one radix-8, two radix-4 or four radix-2 butterflies.
 // Butterfly j of a stage with span NS reads line[j + r L/R], twiddles element r
 // by w_{NS R}^{r (j mod NS)}, transforms, and writes line[(j/NS) NS R + j mod NS
-// + r NS].  tw[q] = exp(-2 pi i q / L).
+// + r NS].  Twiddle bases in tb (Twid).
 template <typename T, int L, int R, int NS, bool INV>
-__device__ __forceinline__ void stockham_stage(C2<T>* line, int w, const C2<T>* __restrict__ tw) {
+__device__ __forceinline__ void stockham_stage(C2<T>* line, int w, const Twid<T, L>& tb) {
   constexpr int B = 8 / R;
   constexpr int W8 = L / 8;
+  static_assert(NS == 1 || R == 8, "only a first stage has radix 2 or 4");
   C2<T> v[B][R];
 #pragma unroll
   for (int q = 0; q < B; ++q) {
     const int j = w + q * W8;
-    const int k = j % NS;
 #pragma unroll
     for (int r = 0; r < R; ++r) v[q][r] = line[swz<L>(j + r * (L / R))];
-    if (NS > 1) {
+    if constexpr (NS > 1) {
+      C2<T> p[8];
+      twiddle_powers(p, tb.t[Twid<T, L>::index(NS)]);
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        C2<T> t = tw[(r * k) * (L / (NS * R))];
-        v[q][r] = INV ? cmulc(v[q][r], t) : cmul(v[q][r], t);
-      }
+      for (int r = 1; r < 8; ++r) v[q][r] = INV ? cmulc(v[q][r], p[r]) : cmul(v[q][r], p[r]);
     }
     if (R == 8) dft8<INV, T>(v[q]);
     else if (R == 4) dft4<INV>(v[q]);
@@ -198,10 +227,10 @@ __device__ __forceinline__ void stockham_stage(C2<T>* line, int w, const C2<T>* 
 }
 
 template <typename T, int L, int NS, bool INV>
-__device__ __forceinline__ void radix8_stages(C2<T>* line, int w, const C2<T>* tw) {
+__device__ __forceinline__ void radix8_stages(C2<T>* line, int w, const Twid<T, L>& tb) {
   if constexpr (NS < L) {
-    stockham_stage<T, L, 8, NS, INV>(line, w, tw);
-    radix8_stages<T, L, NS * 8, INV>(line, w, tw);
+    stockham_stage<T, L, 8, NS, INV>(line, w, tb);
+    radix8_stages<T, L, NS * 8, INV>(line, w, tb);
   }
 }
 
@@ -210,17 +239,17 @@ __device__ __forceinline__ void radix8_stages(C2<T>* line, int w, const C2<T>* t
 // The caller orders the line's LDS contents before (block barrier after a load
 // with another thread mapping) and after it.  Unnormalised; INV: exp(+2 pi i ...).
 template <typename T, int L, bool INV>
-__device__ __forceinline__ void fft_line(C2<T>* line, int w, const C2<T>* tw) {
+__device__ __forceinline__ void fft_line(C2<T>* line, int w, const Twid<T, L>& tb) {
   constexpr int p = Log2<L>::v;
   constexpr int r0 = p % 3;
   if constexpr (r0 == 1) {
-    stockham_stage<T, L, 2, 1, INV>(line, w, tw);
-    radix8_stages<T, L, 2, INV>(line, w, tw);
+    stockham_stage<T, L, 2, 1, INV>(line, w, tb);
+    radix8_stages<T, L, 2, INV>(line, w, tb);
   } else if constexpr (r0 == 2) {
-    stockham_stage<T, L, 4, 1, INV>(line, w, tw);
-    radix8_stages<T, L, 4, INV>(line, w, tw);
+    stockham_stage<T, L, 4, 1, INV>(line, w, tb);
+    radix8_stages<T, L, 4, INV>(line, w, tb);
   } else {
-    radix8_stages<T, L, 1, INV>(line, w, tw);
+    radix8_stages<T, L, 1, INV>(line, w, tb);
   }
 }
 
@@ -234,24 +263,6 @@ __device__ __forceinline__ void fft_line(C2<T>* line, int w, const C2<T>* tw) {
 // use block barriers and every thread of the block must call this.  On entry no
 // thread may still read the line's LDS; on exit reads of it may still be in flight:
 // the caller puts a block barrier before the line's LDS is written again.
-//
-// Twiddles: every stage after the first is radix 8 with one butterfly per worker,
-// k = w mod NS, and needs w_{8 NS}^{r k} for r = 1..7.  Only the base w_{8 NS}^k is
-// read (once per kernel, with the data loads, so no table read waits behind a
-// barrier); the other powers are products of it, at most three deep.
-template <typename T, int L> struct Twid {
-  static constexpr int r0 = Log2<L>::v % 3;
-  static constexpr int first_ns = r0 == 1 ? 2 : (r0 == 2 ? 4 : 8);   // NS of the first twiddled stage
-  static constexpr int count() { int n = 0; for (int ns = first_ns; ns < L; ns *= 8) ++n; return n; }
-  static constexpr int index(int ns) { int i = 0; for (int n = first_ns; n < ns; n *= 8) ++i; return i; }
-  static constexpr int N = count();
-  C2<T> t[N > 0 ? N : 1];
-  __device__ __forceinline__ Twid(int w, const C2<T>* __restrict__ tw) {
-    int ns = first_ns;
-#pragma unroll
-    for (int i = 0; i < N; ++i, ns *= 8) t[i] = tw[(w % ns) * (L / (ns * 8))];
-  }
-};
 
 template <typename T, int L, int R, int NS, bool INV, bool FIRST>
 __device__ __forceinline__ void regs_stage(C2<T>* line, int w, C2<T> (&v)[8], const Twid<T, L>& tb) {
@@ -267,13 +278,7 @@ __device__ __forceinline__ void regs_stage(C2<T>* line, int w, C2<T> (&v)[8], co
     for (int r = 0; r < R; ++r) u[q][r] = FIRST ? v[q + r * B] : line[swz<L>(j + r * (L / R))];
     if constexpr (NS > 1) {
       C2<T> p[8];
-      p[1] = tb.t[Twid<T, L>::index(NS)];
-      p[2] = cmul(p[1], p[1]);
-      p[3] = cmul(p[2], p[1]);
-      p[4] = cmul(p[2], p[2]);
-      p[5] = cmul(p[4], p[1]);
-      p[6] = cmul(p[3], p[3]);
-      p[7] = cmul(p[4], p[3]);
+      twiddle_powers(p, tb.t[Twid<T, L>::index(NS)]);
 #pragma unroll
       for (int r = 1; r < 8; ++r) u[q][r] = INV ? cmulc(u[q][r], p[r]) : cmul(u[q][r], p[r]);
     }
@@ -322,6 +327,33 @@ __device__ __forceinline__ void fft_regs(C2<T>* line, int w, C2<T> (&v)[8], cons
   } else {
     regs_radix8<T, L, 1, INV, true>(line, w, v, tb);
   }
+}
+
+// fft_line with the line's elements w + m L/8 arriving in v[] (m = 0..7) instead of
+// LDS: the first stage takes its inputs from the registers; the output is in LDS as
+// for fft_line.  Same synchronisation as fft_line; the caller orders the LDS
+// contents after it.
+template <typename T, int L, bool INV>
+__device__ __forceinline__ void fft_line_rin(C2<T>* line, int w, C2<T> (&v)[8], const Twid<T, L>& tb) {
+  constexpr int r0 = Log2<L>::v % 3;
+  constexpr int R = r0 == 1 ? 2 : (r0 == 2 ? 4 : 8);
+  constexpr int B = 8 / R;
+  constexpr int W8 = L / 8;
+  static_assert(L > 8, "a single-stage line has no LDS stage");
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    C2<T> u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = v[q + r * B];
+    if (R == 8) dft8<INV, T>(u);
+    else if (R == 4) dft4<INV>(u);
+    else dft2<INV>(u);
+    const int j = w + q * W8;
+#pragma unroll
+    for (int r = 0; r < R; ++r) line[swz<L>(j * R + r)] = u[r];
+  }
+  stage_sync<L>();
+  radix8_stages<T, L, R, INV>(line, w, tb);
 }
 
 // Lines per block for a given element type and length: 4096 (FP32) or 2048

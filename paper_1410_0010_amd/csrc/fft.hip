@@ -55,6 +55,7 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
   const T* __restrict__ gmf = lp.gmf[J.level] + J.gmf_off;
   C2<T>* __restrict__ spec = specb + J.spec_off;
   const int t = threadIdx.x;
+  const Twid<T, L> tb(t % (L / 8), tw);   // line worker t mod L/8
   const int b = t / (L / 8), w = t % (L / 8);
   C2<T>* line = lds + b * line_stride(L);
   const int64_t rows = (int64_t)gy * gz;
@@ -75,6 +76,7 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
     va[j] = rowa[i];
     vb[j] = rowb[i];
   }
+  C2<T> v[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int i = w + j * (L / 8);
@@ -83,10 +85,9 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
       if (hra) xa = sub ? (T)((double)va[j] - mu) : va[j];
       if (hrb) xb = sub ? (T)((double)vb[j] - mu) : vb[j];
     }
-    line[swz<L>(i)] = mk<T>(xa, xb);
+    v[j] = mk<T>(xa, xb);
   }
-  __syncthreads();
-  fft_line<T, L, false>(line, w, tw);
+  fft_line_rin<T, L, false>(line, w, v, tb);
   if (ra < rows) {
     const int64_t za = ra / gy, ya = ra % gy, zb = rb / gy, yb = rb % gy;
     C2<T>* outa = spec + (za * My + ya) * P;
@@ -294,6 +295,7 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
   const int G = nl / 4;
   const int nt = nl * (L / 8);
   const int t = threadIdx.x;
+  const Twid<T, L> tb(t % (L / 8), tw);   // line worker t mod L/8
   const int b = t / (L / 8), w = t % (L / 8);
   const int64_t rows = (int64_t)fz * fy;
   const int64_t q = blk * G + b / 4;
@@ -301,6 +303,7 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
   const int64_t ra = 2 * q, rb = 2 * q + 1;
   constexpr int LS = line_stride(L);
   C2<T>* line = lds + b * LS;
+  C2<T> v[8];
   if (ra < rows) {
     const int64_t cs = (int64_t)c * rows * P;         // component stride
     const C2<T>* A = ybuf + cs + ra * P;
@@ -329,13 +332,13 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
         bq = mk<T>(d * bq.y, -d * bq.x);
       }
       if (k == 0 || k == L / 2) { a.y = 0; bq.y = 0; }
-      line[swz<L>(i)] = i <= L / 2 ? mk<T>(a.x - bq.y, a.y + bq.x) : mk<T>(a.x + bq.y, bq.x - a.y);
+      v[j] = i <= L / 2 ? mk<T>(a.x - bq.y, a.y + bq.x) : mk<T>(a.x + bq.y, bq.x - a.y);
     }
   } else {
-    for (int i = w; i < L; i += L / 8) line[swz<L>(i)] = mk<T>(0, 0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = mk<T>(0, 0);
   }
-  __syncthreads();
-  fft_line<T, L, true>(line, w, tw);
+  fft_line_rin<T, L, true>(line, w, v, tb);
   __syncthreads();                                   // stores read four lines
   for (int idx = t; idx < G * 2 * fx; idx += nt) {
     const int gg = idx / (2 * fx), rem = idx % (2 * fx);

@@ -60,6 +60,7 @@ k_adj_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   const int G = nl / 4;
   const int nt = nl * (L / 8);
   const int t = threadIdx.x;
+  const Twid<T, L> tb(t % (L / 8), tw);   // line worker t mod L/8
   const int b = t / (L / 8), w = t % (L / 8);
   const int64_t rows = (int64_t)fz * fy;
   constexpr int LS = line_stride(L);
@@ -97,7 +98,7 @@ k_adj_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   }
   __syncthreads();
   C2<T>* line = lds + b * LS;
-  fft_line<T, L, false>(line, w, tw);
+  fft_line<T, L, false>(line, w, tb);
   const int64_t q = blk * G + b / 4;
   const int c = b & 3;
   const int64_t ra = 2 * q, rb = 2 * q + 1;
@@ -145,6 +146,7 @@ k_adj_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   C2<T>* zout = zb + J.z_off + (int64_t)j * My * P + c0;
   const int64_t zs = (int64_t)fz * My * P;
   const int t = threadIdx.x;
+  const Twid<T, L> tb(t % (L / 8), tw);   // line worker t mod L/8
   const int cb = t % nl, r0 = t / nl;                // column-wise: rows r0 + q L/2
   const bool col_ok = c0 + cb < W;
   C2<T> v[2][4];
@@ -165,7 +167,7 @@ k_adj_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   }
   __syncthreads();
   const int b = t / (L / 8), w = t % (L / 8);
-  fft_line<T, L, false>(lds + b * ls, w, tw);
+  fft_line<T, L, false>(lds + b * ls, w, tb);
   __syncthreads();                                   // stores read four lines
   if (col_ok) {
 #pragma unroll
@@ -314,6 +316,7 @@ k_adj_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   const C2<T>* __restrict__ spec = specb + J.spec_off;
   T* __restrict__ out = ap.gmf[J.level] + J.gmf_off;
   const int t = threadIdx.x;
+  const Twid<T, L> tb(t % (L / 8), tw);   // line worker t mod L/8
   const int b = t / (L / 8), w = t % (L / 8);
   C2<T>* line = lds + b * line_stride(L);
   const int64_t rows = (int64_t)gy * gz;
@@ -344,7 +347,7 @@ k_adj_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
     for (int i = w; i < L; i += L / 8) line[swz<L>(i)] = mk<T>(0, 0);
   }
   __syncthreads();
-  fft_line<T, L, true>(line, w, tw);
+  fft_line<T, L, true>(line, w, tb);
   if (ra < rows) {
     for (int x = w; x < gx; x += L / 8) {
       const C2<T> v = line[swz<L>(x)];
@@ -375,6 +378,7 @@ k_adjp_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   C2<T>* __restrict__ ybuf = yb + J.y_off;
   const double* __restrict__ fb = ap.fbar[J.level] + 4 * J.fld_off;
   const int t = threadIdx.x;
+  const Twid<T, L> tb(t % (L / 8), tw);   // line worker t mod L/8
   const int b = t / (L / 8), w = t % (L / 8);
   C2<T>* line = lds + b * line_stride(L);
   const int64_t rows = (int64_t)fz * fy;
@@ -402,7 +406,7 @@ k_adjp_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
     line[swz<L>(i)] = mk<T>(xa, xb);
   }
   __syncthreads();
-  fft_line<T, L, false>(line, w, tw);
+  fft_line<T, L, false>(line, w, tb);
   if (ra < rows) {
     C2<T>* outa = ybuf + ra * P;
     C2<T>* outb = ybuf + rb * P;
