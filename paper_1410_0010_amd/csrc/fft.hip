@@ -183,6 +183,13 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
     }
   }
   fft_regs<T, L, false>(line, w, X, tb);
+  // the forward result waits in LDS, each thread's own values in its own slots (no
+  // barrier: the same thread reads them back), so the inverse transforms do not
+  // hold it in registers
+  C2<T>* xs = lds + (int64_t)nl * ls + t;
+  const int nt = (int)blockDim.x;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) xs[q * nt] = X[q];
   // multipliers of this column: kx fastest in the table, so lanes read neighbours
   const int kxc = col_ok ? c0 + cb : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
@@ -199,8 +206,9 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       const int kzo = kz <= L / 2 ? kz : L - kz;
       const nvec2<T> gv = gcol[(uint32_t)kzo * ostride + (uint32_t)kxc];
       const T mul = s == 0 ? gv.x : (s == 1 ? dzs[kz] * gv.x : gv.y);
-      v[q] = s == 1 ? mk<T>(mul * X[q].y, -mul * X[q].x)   // -i d_z Gf X
-                    : mk<T>(mul * X[q].x, mul * X[q].y);
+      const C2<T> x = xs[q * nt];
+      v[q] = s == 1 ? mk<T>(mul * x.y, -mul * x.x)   // -i d_z Gf X
+                    : mk<T>(mul * x.x, mul * x.y);
     }
     __syncthreads();                                 // the previous transform's reads
     fft_regs<T, L, true>(line, w, v, tb);
@@ -402,7 +410,9 @@ template <typename T> size_t pass_lds(int pass, int L, int nl) {
   pass = mirror_pass(pass);
   if (nl < 1) return 0;
   const int lines = pass_lines_per_block(pass, nl);
-  const size_t bytes = (size_t)lines * pass_ls<T>(pass, L, nl) * sizeof(C2<T>);
+  // the z pass also parks each thread's eight forward-transform values (nl L values)
+  const size_t bytes = ((size_t)lines * pass_ls<T>(pass, L, nl) + (pass == PASS_Z_CONV ? (size_t)nl * L : 0)) *
+                       sizeof(C2<T>);
   const int max_threads = pass == PASS_Z_CONV ? kZConvMaxThreads : 1024;
   if (lines * (L / 8) > max_threads || bytes > (size_t)kMaxLDS) return 0;
   if (pass == PASS_X_INV && (nl % 4) != 0) return 0;

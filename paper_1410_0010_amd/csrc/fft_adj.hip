@@ -223,9 +223,10 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   // kernel spills FP64 registers)
   const int64_t ostride = (int64_t)(My / 2 + 1) * W;
   const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)kyo * W + kxc;
-  C2<T> S[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) S[q] = mk<T>(0, 0);
+  // S accumulates in LDS, each thread's values in its own slots (no barrier: the same
+  // thread reads them back), so the forward transforms do not hold it in registers
+  C2<T>* ss = lds + (int64_t)nl * ls + t;
+  const int nt = (int)blockDim.x;
 #pragma unroll 1
   for (int s = 0; s < 3; ++s) {
     const C2<T>* zs_in = zin + s * zs;
@@ -244,11 +245,14 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       const int kzo = kz <= L / 2 ? kz : L - kz;
       const nvec2<T> gv = gcol[kzo * ostride];
       const C2<T> X = v[q];
-      if (s == 0) S[q] = cadd(S[q], mk<T>(gv.x * X.x, gv.x * X.y));
-      else if (s == 1) S[q] = cadd(S[q], mul_id<T>(gv.x * dzs[kz], X));
-      else S[q] = cadd(S[q], mk<T>(gv.y * X.x, gv.y * X.y));
+      if (s == 0) ss[q * nt] = mk<T>(gv.x * X.x, gv.x * X.y);
+      else if (s == 1) ss[q * nt] = cadd(ss[q * nt], mul_id<T>(gv.x * dzs[kz], X));
+      else ss[q * nt] = cadd(ss[q * nt], mk<T>(gv.y * X.x, gv.y * X.y));
     }
   }
+  C2<T> S[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) S[q] = ss[q * nt];
   __syncthreads();
   fft_regs<T, L, true>(line, w, S, tb);
   if (col_ok) {
