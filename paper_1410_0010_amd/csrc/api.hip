@@ -814,21 +814,16 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
   }
   InterpIO<T> io{};
   io.nlev = nl;
-  const int64_t nbp = (npart + kBlock - 1) / kBlock;
-  for (int l = 0; l < nl; ++l) {
-    io.blk0[l] = l * nbp;
-    io.fld[l] = (const V4<T>*)c->fld[di][l].p;
-  }
-  io.blk0[nl] = nl * nbp;
+  for (int l = 0; l < nl; ++l) io.fld[l] = (const V4<T>*)c->fld[di][l].p;
   int64_t iblk = 0;                                  // one block per deposit work item
   for (int l = 0; l < nl; ++l) {
     io.item_blk0[l] = iblk;
     iblk += (int64_t)c->dep_host[l].ntiles + (npart + kChunk - 1) / kChunk;
   }
   io.item_blk0[nl] = iblk;
-  APM_TRY(ensure(c, c->pres, (size_t)std::max<int64_t>(npart, 1) * sizeof(V4<T>) * nl,
-                 "particle results"));
-  for (int l = 0; l < nl; ++l) io.res[l] = (V4<T>*)c->pres.p + (int64_t)std::max<int64_t>(npart, 1) * l;
+  // one record per particle, written by its owner level's interpolation
+  APM_TRY(ensure(c, c->pres, (size_t)std::max<int64_t>(npart, 1) * sizeof(V4<T>), "particle results"));
+  io.res = (V4<T>*)c->pres.p;
   HIP_TRY(timed(c, "interp", [&] {
             return launch_interp_tiles<T>(io, (const DepLevel*)c->dep_tab.p, c->d_grids, c->stream);
           }), "interp");

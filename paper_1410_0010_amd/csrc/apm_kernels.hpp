@@ -200,19 +200,17 @@ template <typename T> hipError_t launch_interp(const GridDesc* grids, int32_t le
 // grid when that grid is on level b, and written to the particle's original slot.
 template <typename T> struct InterpIO {
   int32_t nlev;
-  int64_t blk0[kMaxLevels + 1];        // blocks of level b: [blk0[b], blk0[b + 1])
   int64_t item_blk0[kMaxLevels + 1];   // work-item blocks of level b (the deposit's items)
   const V4<T>* fld[kMaxLevels];
-  V4<T>* res[kMaxLevels];              // per level: (a_x, a_y, a_z, Phi) of each owned
-                                       // entry at its tile-sorted position (coalesced)
+  V4<T>* res;                          // (a_x, a_y, a_z, Phi) of every owned particle,
+                                       // at its own index
 };
-template <typename T> hipError_t launch_interp_sorted(const InterpIO<T>& io, const DepLevel* tab,
-                                                      const GridDesc* grids, hipStream_t s);
-// the same results, one block per deposit work item with the tile's field in LDS
+// interpolation of every level's owned particles, one block per deposit work item
+// (the tile's field in LDS where it pays)
 template <typename T> hipError_t launch_interp_tiles(const InterpIO<T>& io, const DepLevel* tab,
                                                      const GridDesc* grids, hipStream_t s);
-// the records -> the four per-particle output arrays, each particle's read at its
-// sorted position on its owner's level (zero where owner < 0); pot may be null
+// the records (res, particle order) -> the four per-particle output arrays (zero
+// where owner < 0); pot may be null
 template <typename T> hipError_t launch_unpack(const InterpIO<T>& io, const DepLevel* tab,
                                                const int32_t* owner, int64_t npart, T* ax, T* ay,
                                                T* az, T* pot, hipStream_t s);

@@ -669,37 +669,13 @@ hipError_t launch_interp(const GridDesc* grids, int32_t level, const V4<T>* fiel
   return hipGetLastError();
 }
 
-// Sorted-order interpolation: consecutive lanes hold particles of one tile, so their
-// 27-cell gathers share cache lines; each entry owned on this level writes its
-// particle's outputs in the original order.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_interp_sorted(InterpIO<T> io, const DepLevel* __restrict__ tab,
-                                                          const GridDesc* __restrict__ grids) {
-  const int lb = batch_level(io.blk0, io.nlev, blockIdx.x);
-  const DepLevel& L = tab[lb];
-  const int64_t q = (blockIdx.x - io.blk0[lb]) * (int64_t)kBlock + threadIdx.x;
-  if (q >= *L.binned) return;
-  const int2 r = load_i2(L.sref, q);
-  const V4<T> v = load_v4<T>(L.sorted, q);
-  if (r.y < 0) return;
-  const GridDesc& g = grids[r.y];
-  const int64_t off = g.fld_offset;
-  const int nx = g.fld_n[0], ny = g.fld_n[1], nz = g.fld_n[2];
-  const int lx = g.fld_lo[0], ly = g.fld_lo[1], lz = g.fld_lo[2];
-  const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
-  const V4<T> a = tsc_gather<T>(io.fld[lb] + off, nx, ny, nz, (int)fx - lx, (int)fy - ly,
-                                (int)fz - lz, v.x - fx - (T)0.5, v.y - fy - (T)0.5,
-                                v.z - fz - (T)0.5, g.wrap);
-  io.res[lb][q] = a;                                 // sorted position: a coalesced store
-}
-
 // Tile-staged interpolation, one block per deposit work item (a tile's chunk of at most
 // kChunk sorted entries): on a level of one grid, for chunks of 64 entries or more, the
 // 10^3 field cells around the tile (zero outside the field box; wrapped on a periodic
 // root) are read into LDS once and every entry's 27-cell gather reads LDS.  The sums
 // run in the same order as tsc_gather's, over the same values (a cell outside the box
-// contributes an exact zero either way).  Other chunks gather from global memory as
-// k_interp_sorted does.
+// contributes an exact zero either way).  Other chunks gather from global memory
+// (tsc_gather).  Each owned entry writes one 16 B record at its particle's index.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_interp_tiles(InterpIO<T> io, const DepLevel* __restrict__ tab,
                                                          const GridDesc* __restrict__ grids) {
@@ -775,7 +751,7 @@ __global__ void __launch_bounds__(kBlock) k_interp_tiles(InterpIO<T> io, const D
       a = tsc_gather<T>(F + g.fld_offset, g.fld_n[0], g.fld_n[1], g.fld_n[2], (int)fx - g.fld_lo[0],
                         (int)fy - g.fld_lo[1], (int)fz - g.fld_lo[2], tx, ty, tz, g.wrap);
     }
-    io.res[lb][q] = a;                               // sorted position: a coalesced store
+    io.res[r.x] = a;                              // one 16 B record at the particle's index
   }
 }
 
@@ -788,25 +764,19 @@ hipError_t launch_interp_tiles(const InterpIO<T>& io, const DepLevel* tab, const
   return hipGetLastError();
 }
 
-// Records -> the four output arrays (coalesced stores): particle i's record is read
-// at its sorted position count[key] + rank on its owner's level.
+// Records -> the four output arrays: particle i's record, written at index i by its
+// owner level's interpolation, is read coalesced (zero where owner < 0).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_unpack(InterpIO<T> io, const DepLevel* __restrict__ tab,
                                                    const int32_t* __restrict__ owner, int64_t npart,
                                                    T* __restrict__ ax, T* __restrict__ ay,
                                                    T* __restrict__ az, T* __restrict__ pot) {
+  (void)tab;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= npart) return;
   const int32_t og = owner[i];
-  V4<T> v = V4<T>{0, 0, 0, 0};
-  if (og >= 0) {
-    int l = 0;
-    while (l + 1 < io.nlev && og >= tab[l + 1].first) ++l;   // levels hold ascending grids
-    const DepLevel& L = tab[l];
-    const int32_t q = as_global<int32_t>(L.count)[as_global<int32_t>(L.key)[i]] +
-                      as_global<int32_t>(L.rank)[i];
-    v = load_v4<T>(io.res[l], q);
-  }
+  const V4<T> r = load_v4<T>(io.res, i);
+  const V4<T> v = og >= 0 ? r : V4<T>{0, 0, 0, 0};
   ax[i] = v.x; ay[i] = v.y; az[i] = v.z;
   if (pot) pot[i] = v.w;
 }
@@ -821,14 +791,6 @@ hipError_t launch_unpack(const InterpIO<T>& io, const DepLevel* tab, const int32
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_interp_sorted(const InterpIO<T>& io, const DepLevel* tab, const GridDesc* grids,
-                                hipStream_t s) {
-  const int64_t nb = io.blk0[io.nlev];
-  if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_interp_sorted<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab, grids);
-  return hipGetLastError();
-}
 
 #define APM_INST(T)                                                                          \
   template hipError_t launch_bin_count<T>(const DepIO<T>&, const DepLevel*, hipStream_t);      \
@@ -837,8 +799,6 @@ hipError_t launch_interp_sorted(const InterpIO<T>& io, const DepLevel* tab, cons
   template hipError_t launch_deposit_finalize<T>(const DepIO<T>&, const DepLevel*, hipStream_t); \
   template hipError_t launch_owner<T>(const OwnerLevel*, int32_t, const T*, const T*, const T*, \
                                       int64_t, int32_t*, T*, T*, T*, T*, hipStream_t);          \
-  template hipError_t launch_interp_sorted<T>(const InterpIO<T>&, const DepLevel*,              \
-                                              const GridDesc*, hipStream_t);                    \
   template hipError_t launch_interp_tiles<T>(const InterpIO<T>&, const DepLevel*,               \
                                              const GridDesc*, hipStream_t);                     \
   template hipError_t launch_unpack<T>(const InterpIO<T>&, const DepLevel*, const int32_t*,     \
