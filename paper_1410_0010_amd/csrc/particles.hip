@@ -393,7 +393,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
   constexpr int kCells = kTile * kTile * kTile;
   __shared__ double acc[kTH3];
   __shared__ int32_t cstart[kCells];                 // per-cell counts, then starts
-  __shared__ nvec4<T> srec[kChunk];                  // the chunk, sorted by cell
+  __shared__ uint16_t sidx[kChunk];                  // the chunk's entries, sorted by cell
   const int lb = batch_level(io.item_blk0, io.nlev, blockIdx.x);
   const DepLevel& L = tab[lb];
   const int64_t item = blockIdx.x - io.item_blk0[lb];
@@ -482,7 +482,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (cell[k] >= 0) srec[cstart[cell[k]] + rk[k]] = nvec4<T>{rec[k].x, rec[k].y, rec[k].z, rec[k].w};
+      if (cell[k] >= 0) sidx[cstart[cell[k]] + rk[k]] = (uint16_t)(threadIdx.x + k * kBlock);
     __syncthreads();
     // eight consecutive sorted records per thread: a run of one cell accumulates its
     // 27 weighted masses in registers and adds them to the tile once
@@ -503,10 +503,18 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
             a27[(dz * 3 + dy) * 3 + dx] = 0.0;
           }
     };
+    // this thread's eight sorted entries, re-read from the chunk's records (cache
+    // hits: the block read them above) so the LDS holds 2 B per entry, not a record
+    V4<T> sv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = min((int)threadIdx.x * 8 + j, n - 1);
+      sv[j] = load_v4<T>(L.sorted, begin + sidx[e]);
+    }
     for (int j = 0; j < 8; ++j) {
       const int e = (int)threadIdx.x * 8 + j;
       if (e >= n) break;
-      const nvec4<T> v = srec[e];
+      const V4<T> v = sv[j];
       const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
       const int ix = min(max((int)fx - bx, 0), kTile - 1), iy = min(max((int)fy - by, 0), kTile - 1),
                 iz = min(max((int)fz - bz, 0), kTile - 1);
