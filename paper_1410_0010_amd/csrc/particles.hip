@@ -583,9 +583,13 @@ __global__ void __launch_bounds__(kBlock) k_deposit_finalize(DepIO<T> io, const 
   const int64_t cells = (int64_t)g.gmf_n[0] * g.gmf_n[1] * g.gmf_n[2];
   const int64_t local = (blk - L.block_begin[gi]) * (int64_t)kBlock + threadIdx.x;
   if (local >= cells) return;
-  const int lx = (int)(local % g.gmf_n[0]);
-  const int ly = (int)((local / g.gmf_n[0]) % g.gmf_n[1]);
-  const int lz = (int)(local / ((int64_t)g.gmf_n[0] * g.gmf_n[1]));
+  // a GMF box has fewer than 2^31 cells: 32-bit index arithmetic (64-bit division is
+  // a long software sequence)
+  const uint32_t loc = (uint32_t)local, nx = (uint32_t)g.gmf_n[0], ny = (uint32_t)g.gmf_n[1];
+  const uint32_t row = loc / nx;
+  const int lx = (int)(loc - row * nx);
+  const int lz = (int)(row / ny);
+  const int ly = (int)(row - (uint32_t)lz * ny);
   const int cx = g.gmf_lo[0] + lx, cy = g.gmf_lo[1] + ly, cz = g.gmf_lo[2] + lz;
   const double mass = as_global<double>(L.accum)[((int64_t)(cz - L.key_lo[2]) * L.key_n[1] +
                                                   (cy - L.key_lo[1])) * L.key_n[0] + (cx - L.key_lo[0])];
