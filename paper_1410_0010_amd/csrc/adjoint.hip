@@ -164,9 +164,11 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc) atomicAdd(a + cc, w * cot[c0 + cc]);
           } else {
-            double* a = fbar + 4 * (g.fld_offset + ((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]);
+            // 4 components per cell, or the Phi component alone, densely (NC == 1)
+            double* a = fbar + (NC == 1 ? 1 : 4) *
+                                   (g.fld_offset + ((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]);
 #pragma unroll
-            for (int cc = 0; cc < NC; ++cc) atomicAdd(a + c0 + cc, w * cot[c0 + cc]);
+            for (int cc = 0; cc < NC; ++cc) atomicAdd(a + (NC == 1 ? 0 : c0 + cc), w * cot[c0 + cc]);
           }
         }
       }
@@ -194,9 +196,10 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
       }
       if (xx < 0 || xx >= g.fld_n[0] || yy < 0 || yy >= g.fld_n[1] || zz < 0 || zz >= g.fld_n[2])
         continue;                                   // cannot hold weight (owned stencils lie inside)
-      double* f = fbar + 4 * (g.fld_offset + ((int64_t)zz * g.fld_n[1] + yy) * g.fld_n[0] + xx);
+      double* f = fbar + (NC == 1 ? 1 : 4) *
+                             (g.fld_offset + ((int64_t)zz * g.fld_n[1] + yy) * g.fld_n[0] + xx);
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) atomicAdd(f + c0 + cc, a[cc]);
+      for (int cc = 0; cc < NC; ++cc) atomicAdd(f + (NC == 1 ? 0 : c0 + cc), a[cc]);
     }
   }
 }
@@ -298,7 +301,7 @@ __global__ void __launch_bounds__(kBlock)
 k_adj_gas_seed(const GridDesc* __restrict__ grids, const OwnerLevel* __restrict__ om, int32_t nlev,
                int32_t first, int32_t count, const int64_t* __restrict__ begin,
                const T* __restrict__ gas, const V4<T>* __restrict__ field, double wbar,
-               double* __restrict__ fbar, double* __restrict__ gas_bar) {
+               double* __restrict__ fbar, int fs, double* __restrict__ gas_bar) {
   const int64_t b = blockIdx.x;
   int lo = 0, hi = count - 1;
   while (lo < hi) {
@@ -319,7 +322,7 @@ k_adj_gas_seed(const GridDesc* __restrict__ grids, const OwnerLevel* __restrict_
                                      (g.lo[1] + ly - g.fld_lo[1])) * g.fld_n[0] +
                      (g.lo[0] + lx - g.fld_lo[0]);
   const double v = g.dx * g.dx * g.dx * 0.5 * wbar;
-  fbar[4 * fc + 3] += v * (double)gas[g.gas_offset + local];
+  fbar[fs * fc + fs - 1] += v * (double)gas[g.gas_offset + local];   // the Phi component
   gas_bar[g.gas_offset + local] += v * (double)field[fc].w;
 }
 
@@ -327,10 +330,10 @@ template <typename T>
 hipError_t launch_adj_gas_seed(const GridDesc* grids, const OwnerLevel* om, int32_t nlev,
                                int32_t first, int32_t count, const int64_t* begin, int64_t nblocks,
                                const T* gas, const V4<T>* field, double wbar, double* fbar,
-                               double* gas_bar, hipStream_t s) {
+                               int fs, double* gas_bar, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
   hipLaunchKernelGGL((k_adj_gas_seed<T>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, grids, om,
-                     nlev, first, count, begin, gas, field, wbar, fbar, gas_bar);
+                     nlev, first, count, begin, gas, field, wbar, fbar, fs, gas_bar);
   return hipGetLastError();
 }
 
@@ -338,6 +341,7 @@ hipError_t launch_adj_gas_seed(const GridDesc* grids, const OwnerLevel* om, int3
 // Thread = parent field cell q in the footprint of one child grid; it gathers the child
 // cells 2q-1, 2q, 2q+1, 2q+2 per axis (weights 1/4, 3/4, 3/4, 1/4: the trilinear
 // prolongation between cell centres, transposed) and adds the sum to the parent.
+template <int FS>
 __global__ void __launch_bounds__(kBlock)
 k_adj_restrict(const GridDesc* __restrict__ grids, int32_t first, int32_t count,
                const int64_t* __restrict__ begin, const double* __restrict__ child_bar,
@@ -375,41 +379,66 @@ k_adj_restrict(const GridDesc* __restrict__ grids, int32_t first, int32_t count,
       ci[a][k] = ok ? c : 0;
       cw[a][k] = ok ? wts[k] : 0.0;
     }
-  const V4<double>* cb = reinterpret_cast<const V4<double>*>(child_bar) + g.fld_offset;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const int64_t pc = g.parent_fld_offset +
+                     ((int64_t)(q[2] - g.parent_fld_lo[2]) * g.parent_fld_n[1] +
+                      (q[1] - g.parent_fld_lo[1])) * g.parent_fld_n[0] +
+                     (q[0] - g.parent_fld_lo[0]);
+  if constexpr (FS == 4) {
+    const V4<double>* cb = reinterpret_cast<const V4<double>*>(child_bar) + g.fld_offset;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-  for (int kz = 0; kz < 4; ++kz) {
+    for (int kz = 0; kz < 4; ++kz) {
 #pragma unroll
-    for (int ky = 0; ky < 4; ++ky) {
-      const int64_t row = ((int64_t)ci[2][kz] * g.fld_n[1] + ci[1][ky]) * g.fld_n[0];
-      V4<double> v[4];
+      for (int ky = 0; ky < 4; ++ky) {
+        const int64_t row = ((int64_t)ci[2][kz] * g.fld_n[1] + ci[1][ky]) * g.fld_n[0];
+        V4<double> v[4];
 #pragma unroll
-      for (int kx = 0; kx < 4; ++kx) v[kx] = load_v4<double>(cb, row + ci[0][kx]);
-      const double wzy = cw[2][kz] * cw[1][ky];
+        for (int kx = 0; kx < 4; ++kx) v[kx] = load_v4<double>(cb, row + ci[0][kx]);
+        const double wzy = cw[2][kz] * cw[1][ky];
 #pragma unroll
-      for (int kx = 0; kx < 4; ++kx) {
-        const double w = wzy * cw[0][kx];
-        s0 += w * v[kx].x; s1 += w * v[kx].y; s2 += w * v[kx].z; s3 += w * v[kx].w;
+        for (int kx = 0; kx < 4; ++kx) {
+          const double w = wzy * cw[0][kx];
+          s0 += w * v[kx].x; s1 += w * v[kx].y; s2 += w * v[kx].z; s3 += w * v[kx].w;
+        }
       }
     }
+    if (s0 == 0.0 && s1 == 0.0 && s2 == 0.0 && s3 == 0.0) return;
+    double* p = parent_bar + 4 * pc;
+    atomicAdd(p + 0, s0);
+    atomicAdd(p + 1, s1);
+    atomicAdd(p + 2, s2);
+    atomicAdd(p + 3, s3);
+  } else {                                           // the Phi component alone, dense
+    const gptr<double> cb = as_global<double>(child_bar + g.fld_offset);
+    double s3 = 0.0;
+#pragma unroll
+    for (int kz = 0; kz < 4; ++kz) {
+#pragma unroll
+      for (int ky = 0; ky < 4; ++ky) {
+        const int64_t row = ((int64_t)ci[2][kz] * g.fld_n[1] + ci[1][ky]) * g.fld_n[0];
+        double v[4];
+#pragma unroll
+        for (int kx = 0; kx < 4; ++kx) v[kx] = cb[row + ci[0][kx]];
+        const double wzy = cw[2][kz] * cw[1][ky];
+#pragma unroll
+        for (int kx = 0; kx < 4; ++kx) s3 += wzy * cw[0][kx] * v[kx];
+      }
+    }
+    if (s3 == 0.0) return;
+    atomicAdd(parent_bar + pc, s3);
   }
-  if (s0 == 0.0 && s1 == 0.0 && s2 == 0.0 && s3 == 0.0) return;
-  double* p = parent_bar + 4 * (g.parent_fld_offset +
-                                ((int64_t)(q[2] - g.parent_fld_lo[2]) * g.parent_fld_n[1] +
-                                 (q[1] - g.parent_fld_lo[1])) * g.parent_fld_n[0] +
-                                (q[0] - g.parent_fld_lo[0]));
-  atomicAdd(p + 0, s0);
-  atomicAdd(p + 1, s1);
-  atomicAdd(p + 2, s2);
-  atomicAdd(p + 3, s3);
 }
 
 hipError_t launch_adj_restrict(const GridDesc* grids, int32_t first, int32_t count,
                                const int64_t* begin, int64_t nblocks, const double* child_bar,
-                               double* parent_bar, hipStream_t s) {
+                               double* parent_bar, int fs, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adj_restrict, dim3((unsigned)nblocks), dim3(kBlock), 0, s, grids, first,
-                     count, begin, child_bar, parent_bar);
+  if (fs == 1)
+    hipLaunchKernelGGL(k_adj_restrict<1>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, grids, first,
+                       count, begin, child_bar, parent_bar);
+  else
+    hipLaunchKernelGGL(k_adj_restrict<4>, dim3((unsigned)nblocks), dim3(kBlock), 0, s, grids, first,
+                       count, begin, child_bar, parent_bar);
   return hipGetLastError();
 }
 
@@ -664,8 +693,8 @@ hipError_t launch_to_t(const double* a, T* b, int64_t n, hipStream_t s) {
                                            hipStream_t);                                       \
   template hipError_t launch_adj_gas_seed<T>(const GridDesc*, const OwnerLevel*, int32_t,       \
                                              int32_t, int32_t, const int64_t*, int64_t,        \
-                                             const T*, const V4<T>*, double, double*, double*, \
-                                             hipStream_t);                                     \
+                                             const T*, const V4<T>*, double, double*, int,     \
+                                             double*, hipStream_t);                            \
   template hipError_t launch_adj_deposit_grid<T>(const AdjIO<T>&, const DepLevel*, hipStream_t); \
   template hipError_t launch_adj_deposit_particles<T>(const AdjIO<T>&, const DepLevel*,        \
                                                       hipStream_t);                            \

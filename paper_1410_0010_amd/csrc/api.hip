@@ -1136,6 +1136,8 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
   io.abx = abx; io.aby = aby; io.abz = abz; io.phib = phib;
   const bool pot_only = !abx && !aby && !abz;       // the Phi cotangent alone flows back
   io.c0 = pot_only ? 3 : 0;
+  // field cotangents per cell: all four components, or the Phi one alone, densely
+  const int fs = pot_only ? 1 : 4;
   V4<T>* pacc = (V4<T>*)c->adj_pacc.p;
   for (int l = 0; l < nl; ++l) {
     io.plev[l] = pacc + (int64_t)n * (2 * l);
@@ -1156,7 +1158,7 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
     io.gmf_bar[l] = (const T*)c->adj_gmf[di][l].p;
     io.gas_bar[l] = (gas && gas[l]) ? (double*)c->adj_gas[l].p : nullptr;
     io.pgas_bar[l] = (l > 0 && gas && gas[l - 1]) ? (double*)c->adj_gas[l - 1].p : nullptr;
-    add(io.fbar[l], P.levels[l].fld_cells * 4);
+    add(io.fbar[l], P.levels[l].fld_cells * fs);
     add(c->lvb[l].accum.p, P.levels[l].key_cells);
     if (io.gas_bar[l]) add(io.gas_bar[l], P.levels[l].gas_elems);
   }
@@ -1176,7 +1178,7 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
                 return launch_adj_gas_seed<T>(c->d_grids, c->d_owner_map, (int32_t)P.levels.size(),
                                               L.first, L.count, c->d_act_begin[l],
                                               c->act_blocks[l], (const T*)gas[l], io.fld[l],
-                                              wbar, io.fbar[l], io.gas_bar[l], c->stream);
+                                              wbar, io.fbar[l], fs, io.gas_bar[l], c->stream);
               }), "gas energy seeds");
     }
   }
@@ -1184,7 +1186,8 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
     const LevelDesc& L = P.levels[l];
     HIP_TRY(timed(c, "adj_restrict", [&] {
               return launch_adj_restrict(c->d_grids, L.first, L.count, c->d_foot_begin[l],
-                                         c->foot_blocks[l], io.fbar[l], io.fbar[l - 1], c->stream);
+                                         c->foot_blocks[l], io.fbar[l], io.fbar[l - 1], fs,
+                                         c->stream);
             }), "composition transpose");
   }
   // transposed convolution of every grid of every level

@@ -77,7 +77,8 @@ hipError_t launch_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, 
                        const void* tw, hipStream_t s);
 
 // Buffers of the transposed convolution: GMF cotangents out (working precision) and
-// FP64 field-box cotangents in (4 per cell, field layout), per level.
+// FP64 field-box cotangents in (field layout: 4 per cell, or the Phi one alone for the
+// potential-only passes), per level.
 template <typename T> struct AdjPtrs {
   T* gmf[kMaxLevels];
   const double* fbar[kMaxLevels];
@@ -232,7 +233,8 @@ template <typename T> struct AdjIO {
   int64_t fin_blk0[kMaxLevels + 1];    // GMF-cell blocks
   int64_t part_blk0[kMaxLevels + 1];   // sorted-list blocks
   const V4<T>* fld[kMaxLevels];        // forward composed fields
-  double* fbar[kMaxLevels];            // field cotangents, FP64, 4 per field cell
+  double* fbar[kMaxLevels];            // field cotangents, FP64: 4 per field cell, or
+                                       // the Phi one alone (dense) when c0 == 3
   const T* gmf_bar[kMaxLevels];        // GMF cotangents
   double* gas_bar[kMaxLevels];         // own-gas cotangent of the level, or null
   double* pgas_bar[kMaxLevels];        // the parent level's gas cotangent, or null
@@ -253,11 +255,11 @@ template <typename T> hipError_t launch_adj_gas_seed(const GridDesc* grids, cons
                                                      int32_t nlev, int32_t first, int32_t count,
                                                      const int64_t* begin, int64_t nblocks,
                                                      const T* gas, const V4<T>* field, double wbar,
-                                                     double* fbar, double* gas_bar,
+                                                     double* fbar, int fs, double* gas_bar,
                                                      hipStream_t s);
 hipError_t launch_adj_restrict(const GridDesc* grids, int32_t first, int32_t count,
                                const int64_t* begin, int64_t nblocks, const double* child_bar,
-                               double* parent_bar, hipStream_t s);
+                               double* parent_bar, int fs, hipStream_t s);   // fs: 4 or 1 per cell
 template <typename T> hipError_t launch_adj_deposit_grid(const AdjIO<T>& io, const DepLevel* tab,
                                                          hipStream_t s);
 template <typename T> hipError_t launch_adj_deposit_particles(const AdjIO<T>& io,

@@ -380,7 +380,7 @@ k_adjp_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   const int P = J.pitch;
   const int fx = J.f[0], fy = J.f[1], fz = J.f[2], ox = J.off[0];
   C2<T>* __restrict__ ybuf = yb + J.y_off;
-  const double* __restrict__ fb = ap.fbar[J.level] + 4 * J.fld_off;
+  const double* __restrict__ fb = ap.fbar[J.level] + J.fld_off;   // the Phi cotangent, dense
   const int t = threadIdx.x;
   const Twid<T, L> tb(t % (L / 8), tw);   // line worker t mod L/8
   const int b = t / (L / 8), w = t % (L / 8);
@@ -389,14 +389,14 @@ k_adjp_x(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   const int64_t q = blk * nl + b;
   const int64_t ra = 2 * q, rb = 2 * q + 1;
   const bool hra = ra < rows, hrb = rb < rows;
-  const double* fa = fb + 4 * (hra ? ra : 0) * fx + 3;
-  const double* fc = fb + 4 * (hrb ? rb : 0) * fx + 3;
+  const double* fa = fb + (hra ? ra : 0) * fx;
+  const double* fc = fb + (hrb ? rb : 0) * fx;
   double va[8], vb[8];                               // all loads first, clamped addresses
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int x = min((w + j * (L / 8) - ox) & (L - 1), fx - 1);
-    va[j] = fa[4 * x];
-    vb[j] = fc[4 * x];
+    va[j] = fa[x];
+    vb[j] = fc[x];
   }
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
