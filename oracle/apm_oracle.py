@@ -43,9 +43,16 @@ Readings of the paper used here (each one also listed in the design notes):
       the derivative symbol is 0 at the Nyquist index.
   R7  Conjugate D* in Eq. 5; where |D|^2 = 0 the force kernel is 0 (the force
       multiplier D vanishes there too).
-  R21 Potential: HE's potential-optimal influence function (Eq. 5 with D -> 1 and
-      the reference potential); the force-optimal one is unbounded near the
-      Nyquist corners for the two-point gradient.
+  R21 Potential: Sec. 2.2 takes the potential from Eq. 2 with Eq. 5's G, and the
+      force from the potential differenced in Fourier space.  With the spectral
+      gradient (the default) that is done literally: one kernel, Eq. 5's G, whose
+      removable singularity at k = 0 is filled by its limit (only the n = 0 alias
+      term survives there: -4 pi G (a_{l-1}^2 - a_l^2)/30 on a subgrid; on the
+      isolated root the limit of the short-range difference, -pi G dx^2, is added
+      to the James part).  With the two-point gradient Eq. 5's G grows without
+      bound next to the Nyquist corners where |D| -> 0, so there the potential
+      uses HE's potential-optimal influence function (Eq. 5 with D -> 1 and the
+      reference potential) instead.
   R22 Root kernel: optimal influence function of level 0 made isolated as the
       James doubled-mesh reference potential plus the (short-ranged) difference
       optimal - reference on the doubled mesh.
@@ -429,7 +436,7 @@ def _sinc6(k: np.ndarray, dx: float) -> np.ndarray:
 
 
 def influence(kx, ky, kz, dx: float, a_l: float, a_lm1: Optional[float], G: float,
-              dsym, bz: int = 1):
+              dsym, bz: int = 1, ref=None):
     """The two optimal influence functions at wavenumbers (kx, ky, kz) (broadcastable
     1-D axes), both times -4 pi G (R1):
 
@@ -444,9 +451,10 @@ def influence(kx, ky, kz, dx: float, a_l: float, a_lm1: Optional[float], G: floa
                 sum_n U^2(k_n) f_l(|k_n|) / [sum_n U^2(k_n)]^2.  (With the
                 two-point gradient the force kernel grows without bound next to
                 the Nyquist corners where |d| -> 0, so it cannot give the potential.)
-    The mesh force is IDFT(-i d_i force rho_hat) and the potential IDFT(pot rho_hat).
-    With a_lm1 None (the root, S_{-1} = 0) the k = 0 values are infinite and are
-    replaced by the caller."""
+    The mesh force is IDFT(-i d_i force rho_hat); which kernel gives the potential
+    is decided by the caller (R21).  With a_lm1 None (the root, S_{-1} = 0) the
+    k = 0 values are infinite and are replaced by the caller.  ``ref``, if given,
+    replaces f_l(|q|) (a function of the alias wavenumber magnitude q alone)."""
     kx, ky, kz = (np.asarray(v, dtype=np.float64) for v in (kx, ky, kz))
     sx, sy, sz = (np.asarray(v, dtype=np.float64) for v in dsym)
     s2 = sx * sx + sy * sy + sz * sz
@@ -466,9 +474,12 @@ def influence(kx, ky, kz, dx: float, a_l: float, a_lm1: Optional[float], G: floa
                 ux = _sinc6(qx, dx)
                 q = np.sqrt(qx * qx + qy * qy + qz * qz)
                 with np.errstate(divide="ignore", invalid="ignore"):
-                    f = ref_force_factor(q, a_l, a_lm1)
-                if a_lm1 is not None:
-                    f = np.where(q == 0.0, (a_lm1 ** 2 - a_l ** 2) / 30.0, f)
+                    if ref is not None:
+                        f = ref(q)
+                    else:
+                        f = ref_force_factor(q, a_l, a_lm1)
+                        if a_lm1 is not None:
+                            f = np.where(q == 0.0, (a_lm1 ** 2 - a_l ** 2) / 30.0, f)
                 u2f = ux * uy * uz * f
                 num_p += u2f
                 num_f += np.where(np.isfinite(u2f), u2f, 0.0) * (sx * qx + sy * qy + sz * qz)
@@ -498,10 +509,19 @@ def _rfft_d(M, dx, mode):
 
 def greens_sub(plan: OraclePlan, g: OGrid):
     """(force kernel, potential kernel) of subgrid g on its padded rfft grid
-    (Mz, My, Mx//2+1); short-range reference S_l^2 - S_{l-1}^2 (Eq. 9)."""
+    (Mz, My, Mx//2+1); short-range reference S_l^2 - S_{l-1}^2 (Eq. 9).
+
+    Spectral gradient (R21): both are Eq. 5's G, with the value at k = 0 set to its
+    limit -4 pi G (a_{l-1}^2 - a_l^2)/30 (the force multiplier -i d is 0 there, so
+    the forces do not see it).  Two-point gradient: the potential-optimal kernel."""
     kx, ky, kz = _rfft_k(g.M, g.dx)
     al, alm1 = plan.a_soft(g.level), plan.a_soft(g.level - 1)
-    return influence(kx, ky, kz, g.dx, al, alm1, plan.G, _rfft_d(g.M, g.dx, plan.gradient))
+    gf, gpo = influence(kx, ky, kz, g.dx, al, alm1, plan.G, _rfft_d(g.M, g.dx, plan.gradient))
+    if plan.gradient == "fd2":
+        return gf, gpo
+    gf = gf.copy()
+    gf[0, 0, 0] = -4.0 * math.pi * plan.G * (alm1 ** 2 - al ** 2) / 30.0
+    return gf, gf
 
 
 def greens_root(plan: OraclePlan):
@@ -512,8 +532,12 @@ def greens_root(plan: OraclePlan):
     isolated form comes from the doubled-mesh James construction, plus the
     difference optimal - reference, which only corrects the TSC smoothing and the
     finite difference at short range and is added on the doubled mesh as is.
-    k = 0 of the potential difference: its limit -pi G dx^2 (the n = 0 alias term
-    gives f (U^2/C^2 - 1) -> dx^2/4 in unit-charge units)."""
+    k = 0 of the short-range difference: its limit -pi G dx^2 (the n = 0 alias term
+    gives f (U^2/C^2 - 1) -> dx^2/4 in unit-charge units; the other terms vanish like
+    k^5).  The limit is the same for the force kernel with the spectral gradient
+    (there d . k_0 / |d|^2 = 1), whose k = 0 value the forces never see (d = 0).
+    Spectral gradient: the potential kernel is the force kernel (R21); two-point
+    gradient: the potential-optimal kernel."""
     g = plan.grids[0]
     kx, ky, kz = _rfft_k(g.M, g.dx)
     a0 = plan.a_soft(0)
@@ -526,16 +550,18 @@ def greens_root(plan: OraclePlan):
                            _rfft_d(g.M, g.dx, plan.gradient))
         dF = fo - gref
         dP = po - gref
-    dF[0, 0, 0] = 0.0
+    dF[0, 0, 0] = -math.pi * plan.G * g.dx ** 2 if plan.gradient == "spectral" else 0.0
     dP[0, 0, 0] = -math.pi * plan.G * g.dx ** 2
-    return gj + dF, gj + dP
+    gf = gj + dF
+    return (gf, gf) if plan.gradient == "spectral" else (gf, gj + dP)
 
 
 def greens_root_periodic(plan: OraclePlan):
     """(force kernel, potential kernel) of the periodic root on its N^3 rfft grid
     (R23): the level-0 optimal influence functions of Eq. 5 taken directly in
     Fourier space, zero at k = 0 (there the force multiplier vanishes and the
-    mean density carries no potential)."""
+    mean density carries no potential).  Spectral gradient: the potential kernel
+    is the force kernel (R21); two-point gradient: the potential-optimal one."""
     g = plan.grids[0]
     kx, ky, kz = _rfft_k(g.M, g.dx)
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -543,7 +569,7 @@ def greens_root_periodic(plan: OraclePlan):
                            _rfft_d(g.M, g.dx, plan.gradient))
     fo[0, 0, 0] = 0.0
     po[0, 0, 0] = 0.0
-    return fo, po
+    return (fo, fo) if plan.gradient == "spectral" else (fo, po)
 
 
 def greens(plan: OraclePlan, g: OGrid):

@@ -180,6 +180,66 @@ def test_eq8_is_alias_sum_of_sinc6():
     assert np.max(np.abs(closed - brute12)) > 0.1        # the printed sinc^6 as U would not match
 
 
+def _tail_sum(h, power, nmax=4000):
+    """sum over |n| >= 2 of sinc^power(h + pi n) (power 6) or (h + pi n)^-5 (power -5),
+    by brute force; h is an array of half-angles k dx / 2."""
+    n = np.concatenate([np.arange(-nmax, -1), np.arange(2, nmax + 1)]).astype(np.float64)
+    a = h[:, None] + math.pi * n[None, :]
+    if power == 6:
+        return ((np.sin(a) / a) ** 6).sum(1)
+    return (a ** -5).sum(1)
+
+
+@pytest.mark.parametrize("gradient", ["spectral", "fd2"])
+def test_eq6_brillouin_zone_sum(gradient):
+    """Pins the alias loop of Eq. 5 over the zones n in [-1, 1]^3 (Eq. 6).  With the
+    reference factor replaced by 1, the numerators are sums over a product set of
+    products of per-axis terms, so they factor:
+      potential  sum_n U^2(k_n)       = prod_i S_i,
+      force      sum_n U^2(k_n) d.k_n = sum_i d_i T_i prod_{j != i} S_j,
+    S_i = sum_{|n| <= 1} sinc^6(h_i + pi n) and T_i = sum_{|n| <= 1} sinc^6(h_i + pi n)
+    (k_i + 2 pi n / dx), h_i = k_i dx / 2.  Each axis sum is the infinite one minus its
+    |n| >= 2 tail (brute force): for S_i the infinite sum is Eq. 8's closed form, and
+    for T_i it is (2/dx) sin^6 h sum_n (h + pi n)^-5 = (2/dx) sin^6 h D4(h) / 24 with
+    D4 the fourth derivative of cot, 8 c (1 + c^2)(2 + 3 c^2), c = cot h
+    (differentiating sum_n 1/(x + pi n) = cot x four times).  The kernels'
+    denominators are taken off with Eq. 8 written out here."""
+    dx = 1.0 / 64
+    rng = np.random.default_rng(61)
+    # random wavenumbers in the first zone plus the Nyquist corner and edges
+    m = rng.uniform(-32, 32, (200, 3))
+    m[:4] = [[32, 32, 32], [32, 0.5, -7.25], [0.25, 32, 1.5], [-31.9, 3.1, 32]]
+    k = 2 * math.pi * m / (64 * dx)
+    if gradient == "spectral":
+        d = k.copy()
+    else:
+        d = np.sin(k * dx) / dx
+    G = -1.0 / (4 * math.pi)                            # -4 pi G = 1
+    one = lambda q: np.ones_like(q)
+    kern_f, kern_p = O.influence(k[:, 0], k[:, 1], k[:, 2], dx, 3.4 * dx, 6.8 * dx, G,
+                                 (d[:, 0], d[:, 1], d[:, 2]), ref=one)
+    h = k * dx / 2
+    eq8 = 1.0 - np.sin(h) ** 2 + (2.0 / 15.0) * np.sin(h) ** 4           # per axis
+    S = np.stack([eq8[:, i] - _tail_sum(h[:, i], 6) for i in range(3)], 1)
+    cot = np.cos(h) / np.sin(h)
+    d4cot = 8 * cot * (1 + cot ** 2) * (2 + 3 * cot ** 2)
+    T = np.stack([(2 / dx) * np.sin(h[:, i]) ** 6 * (d4cot[:, i] / 24 - _tail_sum(h[:, i], -5))
+                  for i in range(3)], 1)
+    den = np.prod(eq8, 1) ** 2
+    num_p = kern_p * den
+    assert np.allclose(num_p, np.prod(S, 1), rtol=1e-11, atol=0)
+    num_f_ref = (d[:, 0] * T[:, 0] * S[:, 1] * S[:, 2] + d[:, 1] * T[:, 1] * S[:, 0] * S[:, 2]
+                 + d[:, 2] * T[:, 2] * S[:, 0] * S[:, 1])
+    s2 = (d * d).sum(1)
+    num_f = kern_f * s2 * den
+    scale = np.abs(d).sum(1) * np.abs(T).max(1) + 1e-300
+    assert np.all(np.abs(num_f - num_f_ref) <= 1e-10 * scale)
+    # the zones matter: one zone (n = 0 only) misses by O(1) at the Nyquist corner
+    f0, p0 = O.influence(k[:1, 0], k[:1, 1], k[:1, 2], dx, 3.4 * dx, 6.8 * dx, G,
+                         (d[:1, 0], d[:1, 1], d[:1, 2]), bz=0, ref=one)
+    assert abs(p0[0] * den[0] / np.prod(S[0]) - 1) > 0.5
+
+
 # ---------------------------------------------------------------------------
 # P4: S2-S2 reference potential
 # ---------------------------------------------------------------------------
@@ -346,17 +406,48 @@ def test_green_functions_real_even_and_cube_symmetric():
 
 def test_point_mass_far_field():
     """Single particle on an isolated root: Phi -> -GM/r and a -> -GM r_hat/r^2 away
-    from the softening scale (the cloud quadrupole vanishes, so O((dx/r)^4))."""
+    from the softening scale.
+
+    Bound on the potential, from the kernel's construction: the root kernel is the
+    James reference potential (exactly -G/r beyond a_0, P4-P5) plus the short-range
+    difference optimal - reference (its real-space form cK on the doubled mesh).  At
+    a mesh point x whose distance to every cloud cell exceeds a_0,
+        Phi(x) = -G sum_c w_c / |x - x_c| + sum_c w_c cK(x - x_c),
+    so |Phi d + 1| <= |d sum_c w_c / |x - x_c| - 1| + d max_c |cK(x - x_c)|: the
+    cloud's multipole error (brute force with the textbook TSC kernel) plus the size
+    of the optimal - reference correction.  Checked point by point beyond 2.5 a_0."""
     N = 32
     plan = _root_plan(N)
     x, y, z = np.array([0.5 + 0.27 / N]), np.array([0.5 - 0.11 / N]), np.array([0.5 + 0.4 / N])
     r = O.solve(plan, x, y, z, np.array([1.0]))
     F = r["field"][0]
+    g = plan.grids[0]
+    dx, M = g.dx, 2 * N
     c = (np.arange(N) + 0.5) / N
     Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
     d = np.sqrt((X - x[0]) ** 2 + (Y - y[0]) ** 2 + (Z - z[0]) ** 2)
     far = d > 2.5 * plan.a_soft(0)
-    assert np.abs(F[..., 3][far] * d[far] + 1.0).max() < 2e-4
+    # correction kernel: potential of a unit point mass at a mesh offset
+    cK = np.fft.irfftn(O.greens(plan, g)[1] - O.greens_root_james(plan), s=(M, M, M),
+                       axes=(0, 1, 2)) / dx ** 3
+    p = np.array([x[0], y[0], z[0]]) / dx
+    i0 = np.floor(p).astype(int)
+    cloud = [(i0 + np.array(o), float(np.prod(_tsc_kernel_1d(i0 + np.array(o) + 0.5 - p))))
+             for o in np.ndindex(3, 3, 3) for o in [np.array(o) - 1]]
+    assert abs(sum(w for _, w in cloud) - 1.0) < 1e-14
+    idx = np.argwhere(far)
+    xm = idx[:, ::-1]                                   # (x, y, z) cell indices
+    multipole = np.zeros(len(idx))
+    corr = np.zeros(len(idx))
+    for cc, w in cloud:
+        multipole += w / (np.linalg.norm(xm - cc, axis=1) * dx)
+        off = (xm - cc) % M
+        corr = np.maximum(corr, np.abs(cK[off[:, 2], off[:, 1], off[:, 0]]))
+    dd = d[far]
+    bound = np.abs(dd * multipole - 1.0) + dd * corr
+    err = np.abs(F[..., 3][far] * dd + 1.0)
+    assert np.all(err <= bound * (1 + 1e-9) + 1e-12)
+    assert bound.max() < 2e-3                           # the far field is -GM/r to 0.2%
     # pair force on TSC-interpolated test particles (what the optimal kernel targets)
     src = np.array([x[0], y[0], z[0]])
     rr, lev, erad, etan, pr = _radial_errors(plan, r["field"], src, 2.5 * plan.a_soft(0),
