@@ -190,10 +190,12 @@ apm_status apm_deposit(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* 
                        const void* gas, const void* parent_gas, void* gmf);
 
 /* Own field of every grid of `level` (Sec. 2.2, Eq. 2, 5-9): the GMF zero-padded to
- * the FFT box, transformed, multiplied by the level's influence functions and
- * transformed back, the three acceleration components differenced in Fourier
- * space (a_i = IDFT(-i d_i G_force rho_hat)) and the potential with the
- * potential-optimal kernel (Phi = IDFT(G_pot rho_hat)).  Root: isolated boundary
+ * the FFT box, transformed, multiplied by the level's influence function and
+ * transformed back, the potential Phi = IDFT(G rho_hat) with Eq. 5's kernel G and
+ * the three acceleration components differenced in Fourier space
+ * (a_i = IDFT(-i d_i G rho_hat)).  With APM_GRAD_FD2, where Eq. 5's kernel is
+ * unbounded next to the Nyquist corners, the potential takes Hockney and
+ * Eastwood's potential-optimal kernel instead.  Root: isolated boundary
  * on the doubled mesh, or periodic (kernel zero at k = 0); subgrids: short-range
  * reference S_l^2 - S_{l-1}^2.  Periodic plans: a subgrid level's GMF is convolved
  * minus the average density recorded by the last level-0 apm_deposit or apm_solve
@@ -212,10 +214,15 @@ apm_status apm_solve_level(apm_ctx ctx, apm_dtype dtype, int32_t level, const vo
 apm_status apm_accel(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* own,
                      const void* parent_field, void* field);
 
-/* TSC interpolation (same weights as the deposit; wrapping at the box edges on a
- * periodic root) of the composed field of
- * `level` to the particles whose owner grid is on `level`; writes a_x, a_y, a_z
- * and Phi of those particles only (others untouched).  pot may be NULL. */
+/* TSC interpolation of the composed field of `level` to the particles whose owner
+ * grid is on `level` (Sec. 2: particles take their acceleration from the mesh with
+ * the assignment's own TSC weights, which gives no self-force on one level, as the
+ * self-force test of Sec. 3.1 relies on; Sec. 3.2: the force on a particle is that
+ * of the finest grid it lies on).  Stencils wrap at the box edges on a periodic
+ * root.  field: the level's composed field (apm_accel output layout); x, y, z:
+ * npart positions; owner: npart owner grids (apm_owner); writes a_x, a_y, a_z and
+ * Phi of those particles only (others untouched); pot may be NULL.  Errors:
+ * APM_ERR_INVALID for a NULL array, APM_ERR_RANGE for npart outside [0, 2^31). */
 apm_status apm_interp(apm_ctx ctx, apm_dtype dtype, int32_t level, const void* field,
                       const void* x, const void* y, const void* z, const int32_t* owner,
                       int64_t npart, void* ax, void* ay, void* az, void* pot);
@@ -271,8 +278,9 @@ apm_status apm_gas_energy(apm_ctx ctx, apm_dtype dtype, int32_t level, const voi
 
 /* ------------------------------------------------------------- adjoint ------ */
 
-/* Reverse sweep of the last apm_solve on this context (same dtype, npart and x, y, z,
- * m pointers, with unchanged contents; APM_ERR_STATE otherwise): the gradient of
+/* Reverse sweep of the last apm_solve on this context (same dtype, npart, x, y, z, m
+ * pointers and gas pointers of every level, with unchanged contents; APM_ERR_STATE
+ * otherwise): the gradient of
  *     L = wbar W + sum_p abar_p . a_p + sum_p phibar_p Phi_p
  * (W as in apm_solve_totals, a and Phi the solve's outputs) with respect to the
  * particle positions, masses and the gas.  Each forward step is transposed in

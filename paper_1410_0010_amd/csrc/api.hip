@@ -42,7 +42,8 @@ struct apm_ctx_s {
   // FP64 per-particle accumulators; the forward state it needs is the last apm_solve's
   std::vector<DevBuf> adj_fbar, adj_gas, adj_gmf[3];
   DevBuf adj_pacc;
-  std::vector<uintptr_t> last_solve;                               // (dtype, n, x, y, z, m)
+  std::vector<uintptr_t> last_solve;                               // (dtype, n, x, y, z, m,
+                                                                  // gas pointer per level)
   // periodic plans: the average density (partials, then the value at kMaxParts and the
   // reverse sweep's cotangent of it at kMaxParts + 1), set by a level-0 deposit or a
   // solve; allocated once, so job tables may hold it
@@ -834,6 +835,16 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
   return APM_OK;
 }
 
+// What the library-owned state of a solve belongs to: the particles and, since the
+// composed fields depend on it, the gas of every level.
+std::vector<uintptr_t> solve_key(apm_ctx c, apm_dtype dt, int64_t n, const void* x, const void* y,
+                                 const void* z, const void* m, const void* const* gas) {
+  std::vector<uintptr_t> k = {(uintptr_t)dt, (uintptr_t)n, (uintptr_t)x, (uintptr_t)y,
+                              (uintptr_t)z, (uintptr_t)m};
+  for (size_t l = 0; l < c->plan.levels.size(); ++l) k.push_back(gas ? (uintptr_t)gas[l] : 0);
+  return k;
+}
+
 void drop_graph(apm_ctx c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   c->gexec = nullptr;
@@ -853,9 +864,7 @@ apm_status solve_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z, 
                    int64_t npart, const void* const* gas, T* ax, T* ay, T* az, T* pot) {
   c->last_solve.clear();
   apm_status st = solve_graph_t<T>(c, dt, x, y, z, m, npart, gas, ax, ay, az, pot);
-  if (st == APM_OK)
-    c->last_solve = {(uintptr_t)dt, (uintptr_t)npart, (uintptr_t)x, (uintptr_t)y, (uintptr_t)z,
-                     (uintptr_t)m};
+  if (st == APM_OK) c->last_solve = solve_key(c, dt, npart, x, y, z, m, gas);
   return st;
 }
 
@@ -1099,11 +1108,10 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
   const Plan& P = c->plan;
   const int nl = (int)P.levels.size();
   const int di = (int)dt;
-  const std::vector<uintptr_t> key = {(uintptr_t)dt, (uintptr_t)n, (uintptr_t)x, (uintptr_t)y,
-                                      (uintptr_t)z, (uintptr_t)m};
-  if (c->last_solve != key || (int)c->fld[di].size() != nl || (int)c->lvb.size() != nl)
-    return fail(APM_ERR_STATE, "apm_solve_adjoint: needs the apm_solve of the same particles "
-                               "and dtype as the last solve on this context");
+  if (c->last_solve != solve_key(c, dt, n, x, y, z, m, gas) || (int)c->fld[di].size() != nl ||
+      (int)c->lvb.size() != nl)
+    return fail(APM_ERR_STATE, "apm_solve_adjoint: needs the apm_solve of the same particles, "
+                               "gas and dtype as the last solve on this context");
   c->adj_fbar.resize(nl);
   c->adj_gas.resize(nl);
   c->adj_gmf[di].resize(nl);

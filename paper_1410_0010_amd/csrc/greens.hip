@@ -10,6 +10,14 @@
 // Root (level 0, isolated): the level-0 kernels (reference S_0^2) made isolated as
 // the doubled-mesh reference potential (James) plus optimal - reference.  Periodic
 // root (Sec. 2.1): the level-0 kernels on the root's own mesh, zero at k = 0.
+// Which kernel gives the potential: Sec. 2.2 takes it from Eqs. 2 and 5 and
+// differences it in Fourier space.  With the spectral gradient D = -i k that holds
+// literally, Gp = Gf, with Gf's removable singularity at k = 0 filled by its limit
+// (the n = 0 alias term alone: -4 pi G (a_{l-1}^2 - a_l^2)/30 on a subgrid, the
+// James value - pi G dx^2 on the isolated root, 0 on the periodic root); the force
+// multipliers -i d vanish at k = 0, so the forces do not see it.  With the two-point
+// gradient Eq. 5's kernel is unbounded next to the Nyquist corners (|D| -> 0), and
+// the potential takes the potential-optimal Gp above.
 // Tables hold the octant |m_i| <= M_i/2 (both kernels are even in every axis),
 // scaled by 1/(Mx My Mz) for the unnormalised transforms, at ((|mz| Oy) + |my|) Ox
 // + |mx| (Ox = Mx/2 + 1, Oy = My/2 + 1).
@@ -123,23 +131,28 @@ __global__ void k_influence(InfluenceParams p, double2* __restrict__ out) {
   double gf = s2 > 0.0 ? g4 * numf / (s2 * c2) : 0.0;
   double gp = g4 * nump / c2;
   const double k2 = kx * kx + ky * ky + kz * kz;
+  const bool spectral = p.grad != APM_GRAD_FD2;
   if (p.a_lm1 < 0.0 && !p.james) {
     // periodic root: the level-0 kernels themselves; zero at k = 0 (the mean
     // density carries no potential)
     if (k2 == 0.0) gf = gp = 0.0;
   } else if (p.a_lm1 < 0.0) {
-    // isolated root: James reference + (optimal - reference)
+    // isolated root: James reference + (optimal - reference); the difference tends
+    // to -pi G dx^2 at k = 0 (for Gp, and for Gf with the spectral gradient)
     const double jm = p.james[((int64_t)mz * Oy + my) * Ox + mx];
     if (k2 == 0.0) {
-      gf = jm;
       gp = jm - kPi * p.G * dx * dx;
+      gf = spectral ? gp : jm;
     } else {
       const double sl = s2hat(0.5 * sqrt(k2) * p.a_l);
       const double gref = g4 * sl * sl / k2;
       gf = jm + (gf - gref);
       gp = jm + (gp - gref);
     }
+  } else if (k2 == 0.0 && spectral) {
+    gf = gp;                                         // subgrid: the k -> 0 limit
   }
+  if (spectral) gp = gf;                             // Eq. 2 with Eq. 5's kernel
   // stored kx-fastest, ((mz Oy) + my) Ox + mx: in the z passes neighbouring lanes
   // work on neighbouring kx columns
   out[((int64_t)mz * Oy + my) * Ox + mx] = make_double2(gf * p.norm, gp * p.norm);

@@ -28,12 +28,12 @@ FAMILY = {
     "k_adj_z": "adj_fft_z", "k_adjp_z": "adj_fft_z", "k_adj_y_inv": "adj_fft_y_inv",
     "k_adj_x_inv": "adj_fft_x_inv",
     "k_dep_clear": "bin_clear", "k_bin_count": "bin_count", "k_scan_tiles": "bin_scan",
-    "k_scan_blocks": "bin_scan", "k_scan_emit": "bin_scan", "k_deposit_sparse": "deposit_sparse",
+    "k_scan_blocks": "bin_scan", "k_scan_emit": "bin_scan",
     "k_adj_interp_grad": "adj_interp", "k_totals_parts": "totals", "k_particle_totals": "totals",
     "k_totals_finish": "totals",
     "k_bin_scatter": "bin_scatter", "k_deposit_tiles": "deposit_tiles",
     "k_deposit_finalize": "deposit_finalize", "k_owner": "owner", "k_compose": "compose",
-    "k_interp_sorted": "interp", "k_unpack": "unpack",
+    "k_interp_tiles": "interp", "k_interp": "interp", "k_unpack": "unpack",
     "k_adj_interp": "adj_interp", "k_adj_deposit_particles": "adj_deposit_particles",
     "k_adj_deposit_grid": "adj_deposit_grid", "k_adj_restrict": "adj_restrict",
     "k_adj_finish": "adj_finish", "k_zero_ranges": "adj_clear",

@@ -103,6 +103,7 @@ class Context:
         check(_apm.lib().apm_create(plan.handle, device, ctypes.c_void_p(stream), ctypes.byref(h)),
               "apm_create")
         self.handle = h
+        self.solve_count = 0         # solves run on this context (the autograd wrappers check it)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -154,6 +155,7 @@ class Context:
         return out
 
     def deposit(self, level, x, y, z, m, gas=None, parent_gas=None, out=None):
+        self.solve_count += 1          # the library's forward state is replaced
         if out is None:
             out = self.empty_gmf(level, x.dtype)
         check(_apm.lib().apm_deposit(self.handle, _dtype_code(x), level, _ptr(x), _ptr(y), _ptr(z),
@@ -202,6 +204,7 @@ class Context:
         if gas is not None:
             garr = (ctypes.c_void_p * self.plan.nlevels)(
                 *[None if g is None else g.data_ptr() for g in gas])
+        self.solve_count += 1
         check(_apm.lib().apm_solve(self.handle, _dtype_code(x), _ptr(x), _ptr(y), _ptr(z), _ptr(m),
                                    n, garr, _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot)), "apm_solve")
         return ax, ay, az, pot
@@ -282,6 +285,7 @@ class Context:
                  pot=None, energy=True):
         """nsteps KDK steps in place (apm_leapfrog); returns (ax, ay, az, pot, energies)
         with energies an (nsteps + 1) array of K + W, or None."""
+        self.solve_count += 1          # the library's forward state is replaced
         n = x.shape[0]
         mk = lambda: self.torch.empty(n, dtype=x.dtype, device=self.device)
         ax = mk() if ax is None else ax
@@ -300,6 +304,7 @@ class Context:
     def autotune(self, dtype, reps: int = 5):
         """Pick launch shapes for every transform pass (after one solve() of dtype);
         returns the autotuner's JSON report as a dict."""
+        self.solve_count += 1          # the library's forward state is replaced
         import json
         code = _apm.APM_F32 if dtype == self.torch.float32 else _apm.APM_F64
         buf = ctypes.create_string_buffer(1 << 16)

@@ -80,7 +80,28 @@ def periodic_sine():
     return w
 
 
+def slab_chain(axis):
+    """Root 64^3 and a chain of thin slab grids reaching level 4, FFT lengths 256, 512
+    and 1024 along `axis` (the transposed row passes for axis 0, the y column passes
+    for 1, the z pass for 2), 32 across."""
+    grids = [W.GridSpec(0, -1, (0, 0, 0), (64,) * 3)]
+    for lev, (lo, n) in enumerate([(4, 120), (12, 232), (28, 456), (60, 904)], start=1):
+        c = 32 * 2 ** lev
+        los, ns = [c - 4] * 3, [8] * 3
+        los[axis], ns[axis] = lo, n
+        grids.append(W.GridSpec(lev, lev - 1, tuple(los), tuple(ns)))
+    rng = np.random.default_rng(90 + axis)
+    p = [0.5 + rng.normal(0, 0.002, 2500) for _ in range(3)]
+    p[axis] = rng.uniform(0.08, 0.92, 2500)
+    m = rng.uniform(0.5, 1.5, 2500) / 2500
+    return W.Workload(f"slab_chain_axis{axis}", 64, grids, p[0], p[1], p[2], m,
+                      [None] * len(grids))
+
+
 CASES = {
+    "slab_chain_L1024_x": lambda: slab_chain(0),
+    "slab_chain_L1024_y": lambda: slab_chain(1),
+    "slab_chain_L1024_z": lambda: slab_chain(2),
     "periodic_edges16_gas": periodic_edges,
     "periodic_sine32": periodic_sine,
     "periodic_plummer32": lambda: W.workload_plummer_periodic(root_n=32, sub_n=16, nlevels=2,
@@ -146,7 +167,7 @@ def test_energy_gradient_matches_oracle(case, dtype):
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
 @pytest.mark.parametrize("case", ["gas_nested32", "clumps32_24grids_gas", "periodic_edges16_gas",
-                                  "periodic_sine32"])
+                                  "periodic_sine32", "slab_chain_L1024_y", "slab_chain_L1024_z"])
 def test_general_loss_gradient_matches_oracle(case, dtype):
     w = CASES[case]()
     rng = np.random.default_rng(3)
@@ -180,6 +201,32 @@ def test_adjoint_needs_matching_solve():
     ctx.deposit(0, x, y, z, m)
     with pytest.raises(P.APMError):
         ctx.solve_adjoint(x, y, z, m, wbar=1.0, pot=pot)
+
+
+def test_adjoint_needs_the_gas_of_the_last_solve():
+    """The composed fields the reverse sweep reads depend on the gas: after a second
+    solve with other gas, the reverse sweep of the first (its gas pointers) is refused,
+    by the library and, through autograd, by the context's solve count."""
+    w = W.workload_plummer_gas(root_n=32, sub_n=16, nlevels=1, npart=2000)
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    x, y, z, m = (dev(a, np.float64) for a in (w.x, w.y, w.z, w.m))
+    gas_a = [ctx.pack_gas(l, w.gas, x.dtype) for l in range(plan.nlevels)]
+    gas_b = [None if g is None else 2.0 * g for g in gas_a]
+    _, _, _, pot_a = ctx.solve(x, y, z, m, gas_a)
+    ctx.solve(x, y, z, m, gas_b)
+    with pytest.raises(P.APMError) as e:
+        ctx.solve_adjoint(x, y, z, m, gas_a, pot_a, wbar=1.0)
+    assert e.value.status == P._apm.APM_ERR_STATE
+    xr, yr, zr, mr = (t.clone().requires_grad_() for t in (x, y, z, m))
+    ga = [None if g is None else g.clone().requires_grad_() for g in gas_a]
+    gb = [None if g is None else g.clone().requires_grad_() for g in gas_b]
+    e1 = AG.potential_energy(ctx, xr, yr, zr, mr, ga)
+    e2 = AG.potential_energy(ctx, xr, yr, zr, mr, gb)
+    with pytest.raises(RuntimeError):
+        torch.autograd.grad(e1, [xr])
+    g2 = torch.autograd.grad(e2, [xr])[0]             # the most recent one still works
+    assert torch.isfinite(g2).all()
 
 
 def test_gas_totals_need_a_current_solve():

@@ -113,20 +113,23 @@ def compare(name, w, dtype, got, ref):
         assert np.abs(got["totals"][nl + 1:nl + 4] - fref).max() <= 10 * t["acc"] * scale
 
 
-def slab_workload(npart=3000, seed=77):
+def slab_workload(npart=3000, seed=77, axis=0):
     """Root 64^3 and a chain of thin slab grids (8 cells thick) reaching level 4 with
-    FFT lengths 256, 512 and 1024 along x and 32 across."""
+    FFT lengths 256, 512 and 1024 along `axis` and 32 across: axis 0 runs the row
+    passes at those lengths, axis 1 the y column passes, axis 2 the z pass."""
     grids = [GridSpec(0, -1, (0, 0, 0), (64,) * 3)]
-    xs = [(4, 120), (12, 232), (28, 456), (60, 904)]
-    for lev, (lo, n) in enumerate(xs, start=1):
+    spans = [(4, 120), (12, 232), (28, 456), (60, 904)]
+    for lev, (lo, n) in enumerate(spans, start=1):
         c = 32 * 2 ** lev
-        grids.append(GridSpec(lev, lev - 1, (lo, c - 4, c - 4), (n, 8, 8)))
+        los, ns = [c - 4] * 3, [8] * 3
+        los[axis], ns[axis] = lo, n
+        grids.append(GridSpec(lev, lev - 1, tuple(los), tuple(ns)))
     rng = np.random.default_rng(seed)
-    x = rng.uniform(0.08, 0.92, npart)
-    y = 0.5 + rng.normal(0, 0.002, npart)
-    z = 0.5 + rng.normal(0, 0.002, npart)
+    p = [0.5 + rng.normal(0, 0.002, npart) for _ in range(3)]
+    p[axis] = rng.uniform(0.08, 0.92, npart)
     m = rng.uniform(0.5, 1.5, npart) / npart
-    return W.Workload("slab_chain", 64, grids, x, y, z, m, [None] * len(grids))
+    return W.Workload(f"slab_chain_axis{axis}", 64, grids, p[0], p[1], p[2], m,
+                      [None] * len(grids))
 
 
 def tiny_grid_workload():
@@ -196,6 +199,8 @@ CASES = {
                                                    side_lo=4, side_hi=20),
     "gas_nested32": lambda: W.workload_plummer_gas(root_n=32, sub_n=16, nlevels=2, npart=5000),
     "slab_chain_L1024": slab_workload,
+    "slab_chain_L1024_y": lambda: slab_workload(axis=1),
+    "slab_chain_L1024_z": lambda: slab_workload(axis=2),
     "tiny_grids_L16": tiny_grid_workload,
     "edge_particles": edge_workload,
     "uniform_sphere_gas_only": W.workload_uniform_sphere,
@@ -261,6 +266,57 @@ def test_parity_bench_workload_full_size(bench_oracle, dtype):
     ref = run_oracle(w, dtype, cache=cache)
     got = run_staged(w, dtype)
     compare("bench_full", w, dtype, got, ref)
+
+
+# ---- batched level at full size: root 64^3 + 256 uneven level-1 grids, 2^21 particles --
+# The oracle deposits every particle once per grid, so it is run on the root and on a
+# sample of the 256 grids (each sampled grid in full: GMF, own and composed field, and
+# every particle it owns); the owner grid of every particle is compared exactly.
+
+CLUMP_SAMPLE = (0, 1, 37, 101, 128, 200, 254, 255)
+
+
+@pytest.fixture(scope="module")
+def clumps_oracle():
+    w = W.workload_clumps()
+    return w, O.OraclePlan(w.root_n, w.grids)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_parity_clumps_workload_full_size(clumps_oracle, dtype):
+    w, oplan = clumps_oracle
+    say(f"[parity] full clumps workload dtype={dtype.__name__} npart={w.npart} "
+        f"grids={len(w.grids)}")
+    got = run_staged(w, dtype)
+    t = TOL[dtype]
+    cast = lambda a: np.asarray(a, dtype).astype(np.float64)
+    x, y, z, m = (cast(a) for a in (w.x, w.y, w.z, w.m))
+    say("[parity] oracle: owners of the rounded positions, root and sampled grids")
+    own_ref = O.owner_of(oplan, x, y, z)
+    assert np.array_equal(got["owner"], own_ref), "owner grids differ"
+    gas = [None] * len(w.grids)
+    root = oplan.grids[0]
+    rho0 = O.deposit_grid(oplan, root, x, y, z, m, gas)
+    f0 = O.compose(oplan, root, O.convolve(oplan, root, rho0), None)
+    sample = [1 + (i % (len(w.grids) - 1)) for i in CLUMP_SAMPLE]
+    fields = {0: f0}
+    for gi in sample:
+        g = oplan.grids[gi]
+        rho = O.deposit_grid(oplan, g, x, y, z, m, gas)
+        short = O.convolve(oplan, g, rho)
+        fields[gi] = O.compose(oplan, g, short, f0)
+        for key, ref in (("gmf", rho), ("own", short), ("field", fields[gi])):
+            e = rel(got[key][gi], ref)
+            assert e <= (t["gmf"] if key == "gmf" else t["field"]), \
+                f"grid {gi} {key} rel L2 {e:.3e}"
+    assert rel(got["gmf"][0], rho0) <= t["gmf"] and rel(got["field"][0], f0) <= t["field"]
+    sel = np.nonzero(np.isin(own_ref, list(fields)))[0]
+    flist = [fields.get(i, np.zeros((1, 1, 1, 4))) for i in range(len(w.grids))]
+    pa = O.interp(oplan, flist, own_ref[sel], x[sel], y[sel], z[sel])
+    say(f"[parity] clumps: {sel.size} particles on the root and the sampled grids")
+    assert rel(got["acc"][sel], pa[:, :3]) <= t["acc"]
+    assert rel(got["pot"][sel], pa[:, 3]) <= t["pot"]
 
 
 # ---- periodic root at full size: 128^3 periodic + 2 x 64^3, 2^20 Plummer -------------
