@@ -237,6 +237,21 @@ apm_status apm_totals(apm_ctx ctx, apm_dtype dtype, const void* const* gmf, cons
                       const int32_t* owner, int64_t npart, const void* ax, const void* ay,
                       const void* az, const void* pot, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): apm_totals with its results
+ * written to out_dev (nlevels + 4 FP64 values, a device array the caller owns, same
+ * layout as apm_totals' out) in stream order, without synchronising and without any
+ * allocation: the reduction partials live in a fixed device array of the library,
+ * (21 + 4) * 1024 doubles (200 KiB), one per device, held until the process ends and
+ * shared by every call on that device.  Each call rewrites every partial it reads,
+ * so nothing carries over between calls; calls that overlap on one device (other
+ * streams, other contexts, other threads) race on the array and must be ordered by
+ * the caller.  Arguments as in apm_totals.  Errors: APM_ERR_INVALID for NULL
+ * arguments, APM_ERR_RANGE for npart < 0 or more levels than the array holds. */
+apm_status apm_totals_noalloc(apm_ctx ctx, apm_dtype dtype, const void* const* gmf,
+                              const void* m, const int32_t* owner, int64_t npart, const void* ax,
+                              const void* ay, const void* az, const void* pot, double* out_dev);
+
 /* The whole forward solve in one call: owner, deposit, solve, composition and
  * interpolation of every level, in the paper's order, into library-owned level
  * buffers (periodic plans: the average density is computed from the particles and

@@ -84,6 +84,8 @@ SIGNATURES = {
     "apm_interp": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "apm_totals": (_st, [_vp, _st, ctypes.POINTER(_vp), _vp, _vp, _i64, _vp, _vp, _vp, _vp,
                          ctypes.POINTER(ctypes.c_double)]),
+    "apm_totals_noalloc": (_st, [_vp, _st, ctypes.POINTER(_vp), _vp, _vp, _i64, _vp, _vp, _vp,
+                                 _vp, _vp]),
     "apm_solve": (_st, [_vp, _st, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_vp), _vp, _vp, _vp,
                         _vp]),
     "apm_solve_totals": (_st, [_vp, _st, _vp, _i64, ctypes.POINTER(_vp), _vp, _vp, _vp, _vp,

@@ -16,6 +16,13 @@
 
 using namespace apm;
 
+// Fixed scratch of apm_totals_noalloc: the FP64 reduction partials, one row of
+// kMaxParts per quantity (a level's mass, then W_p and sum m a), for callers that
+// cannot allocate.  Each device holds its own copy for the life of the process; host
+// code reaches it only through the per-device address taken in apm_create.
+constexpr int64_t kNoAllocScratch = (int64_t)(apm::kMaxLevels + 4) * apm::kMaxParts;
+static __device__ __align__(256) double scratch[kNoAllocScratch];
+
 namespace {
 
 struct DevBuf {
@@ -92,6 +99,19 @@ struct apm_ctx_s {
 };
 
 namespace {
+
+std::mutex& device_setup_mutex() {
+  static std::mutex m;
+  return m;
+}
+std::vector<int>& setup_done() {                    // devices set up (under the mutex)
+  static std::vector<int> v;
+  return v;
+}
+std::map<int, double*>& scratch_ptrs() {            // device -> address of `scratch`
+  static std::map<int, double*> v;
+  return v;
+}
 
 apm_status hip_fail(hipError_t e, const char* where) {
   std::ostringstream s;
@@ -1253,6 +1273,30 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
 // synchronous entry points' results, [kTotPart ..) reduction partials.
 constexpr int64_t kTotOut = 8, kTotPart = 64;
 
+// Launch arguments of the totals: GMF sums of every level and the particle sums,
+// partials at `part` ((nlev + 4) kMaxParts doubles), results at out_dev.
+template <typename T>
+apm_status totals_io_t(apm_ctx c, const void* const* gmf, const T* m, const int32_t* owner,
+                       int64_t npart, const T* ax, const T* ay, const T* az, const T* pot,
+                       double* part, double* out_dev, TotalsIO<T>* out) {
+  const Plan& P = c->plan;
+  const int nl = (int)P.levels.size();
+  TotalsIO<T>& io = *out;
+  io.nlev = nl;
+  for (int l = 0; l < nl; ++l) {
+    if (!gmf[l]) return fail(APM_ERR_INVALID, "totals: NULL gmf pointer");
+    io.gmf[l] = (const T*)gmf[l];
+    io.gmf_n[l] = P.levels[l].gmf_elems;
+    io.vol[l] = P.levels[l].dx * P.levels[l].dx * P.levels[l].dx;
+  }
+  io.m = m; io.owner = owner; io.npart = npart;
+  io.ax = ax; io.ay = ay; io.az = az; io.pot = pot;
+  io.gas_w = nullptr;
+  io.part = part;
+  io.out = out_dev;
+  return APM_OK;
+}
+
 // A9 totals on the stream into out_dev (nlev + 5 doubles, device): two launches, plus
 // the gas-energy passes when gas is given (they read the composed fields of the last
 // solve of this dtype).
@@ -1265,17 +1309,7 @@ apm_status totals_t(apm_ctx c, apm_dtype dt, const void* const* gmf, const T* m,
   APM_TRY(ensure(c, c->totals, (size_t)(kTotPart + (kMaxLevels + 4) * kMaxParts) * 8, "totals"));
   double* d = (double*)c->totals.p;
   TotalsIO<T> io{};
-  io.nlev = nl;
-  for (int l = 0; l < nl; ++l) {
-    if (!gmf[l]) return fail(APM_ERR_INVALID, "totals: NULL gmf pointer");
-    io.gmf[l] = (const T*)gmf[l];
-    io.gmf_n[l] = P.levels[l].gmf_elems;
-    io.vol[l] = P.levels[l].dx * P.levels[l].dx * P.levels[l].dx;
-  }
-  io.m = m; io.owner = owner; io.npart = npart;
-  io.ax = ax; io.ay = ay; io.az = az; io.pot = pot;
-  io.part = d + kTotPart;
-  io.out = out_dev;
+  APM_TRY(totals_io_t<T>(c, gmf, m, owner, npart, ax, ay, az, pot, d + kTotPart, out_dev, &io));
   bool any_gas = false;
   for (int l = 0; gas && l < nl; ++l) any_gas = any_gas || gas[l];
   if (any_gas) {
@@ -1318,19 +1352,26 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
   c->device = device;
   c->stream = (hipStream_t)stream;
   {
-    // transform kernels may use up to the device's LDS per workgroup (once per
-    // process and device, before any launch or capture)
-    static std::mutex lds_mutex;
-    static std::vector<int> lds_done;
-    std::lock_guard<std::mutex> lock(lds_mutex);
-    if (std::find(lds_done.begin(), lds_done.end(), device) == lds_done.end()) {
+    // once per process and device, with the device current, before any launch or
+    // capture: transform kernels may use up to the device's LDS per workgroup, and the
+    // device address of the fixed totals scratch is taken
+    std::lock_guard<std::mutex> lock(device_setup_mutex());
+    if (std::find(setup_done().begin(), setup_done().end(), device) == setup_done().end()) {
       hipError_t e = allow_lds_forward();
       if (e == hipSuccess) e = allow_lds_adjoint();
       if (e != hipSuccess) {
         apm_destroy(c);
         return hip_fail(e, "apm_create: LDS limit");
       }
-      lds_done.push_back(device);
+      void* sp = nullptr;
+      e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !sp) {
+        apm_destroy(c);
+        return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                        "apm_create: address of the fixed totals scratch");
+      }
+      scratch_ptrs()[device] = (double*)sp;
+      setup_done().push_back(device);
     }
   }
   const Plan& P = c->plan;
@@ -1584,6 +1625,42 @@ apm_status apm_totals(apm_ctx c, apm_dtype dt, const void* const* gmf, const voi
   HIP_TRY(hipMemcpyAsync(out, res, (size_t)(nl + 4) * 8, hipMemcpyDeviceToHost, c->stream),
           "totals copy");
   HIP_TRY(hipStreamSynchronize(c->stream), "totals sync");
+  return APM_OK;
+}
+
+apm_status apm_totals_noalloc(apm_ctx c, apm_dtype dt, const void* const* gmf, const void* m,
+                              const int32_t* owner, int64_t npart, const void* ax, const void* ay,
+                              const void* az, const void* pot, double* out_dev) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (!out_dev || !gmf) return fail(APM_ERR_INVALID, "apm_totals_noalloc: NULL argument");
+  if (npart < 0) return fail(APM_ERR_RANGE, "apm_totals_noalloc: npart < 0");
+  if (npart > 0 && (!m || !owner || !ax || !ay || !az))
+    return fail(APM_ERR_INVALID, "apm_totals_noalloc: NULL particle array");
+  const int nl = (int)c->plan.levels.size();
+  if ((int64_t)(nl + 4) * kMaxParts > kNoAllocScratch)
+    return fail(APM_ERR_RANGE, "apm_totals_noalloc: more levels than the fixed scratch holds");
+  double* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(device_setup_mutex());
+    auto it = scratch_ptrs().find(c->device);
+    if (it != scratch_ptrs().end()) part = it->second;
+  }
+  if (!part) return fail(APM_ERR_STATE, "apm_totals_noalloc: no fixed scratch on this device");
+  // the same two launches as apm_totals, with the partials in the fixed scratch
+  if (dt == APM_F32) {
+    TotalsIO<float> io{};
+    APM_TRY(totals_io_t<float>(c, gmf, (const float*)m, owner, npart, (const float*)ax,
+                               (const float*)ay, (const float*)az, (const float*)pot, part,
+                               out_dev, &io));
+    HIP_TRY(launch_totals<float>(io, c->stream), "apm_totals_noalloc");
+  } else {
+    TotalsIO<double> io{};
+    APM_TRY(totals_io_t<double>(c, gmf, (const double*)m, owner, npart, (const double*)ax,
+                                (const double*)ay, (const double*)az, (const double*)pot, part,
+                                out_dev, &io));
+    HIP_TRY(launch_totals<double>(io, c->stream), "apm_totals_noalloc");
+  }
   return APM_OK;
 }
 

@@ -191,6 +191,18 @@ class Context:
               "apm_totals")
         return np.array(out[:])
 
+    def totals_noalloc(self, gmfs: List, m, owner, ax, ay, az, pot=None, out=None):
+        """apm_totals into a float64 device tensor (nlevels + 4 values), no allocation in
+        the library and no synchronisation; returns `out`."""
+        nl = self.plan.nlevels
+        if out is None:
+            out = self.torch.empty(nl + 4, dtype=self.torch.float64, device=self.device)
+        arr = (ctypes.c_void_p * nl)(*[g.data_ptr() for g in gmfs])
+        check(_apm.lib().apm_totals_noalloc(self.handle, _dtype_code(m), arr, _ptr(m), _ptr(owner),
+                                            m.shape[0], _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot),
+                                            _ptr(out)), "apm_totals_noalloc")
+        return out
+
     def solve(self, x, y, z, m, gas: Optional[List] = None, ax=None, ay=None, az=None, pot=None,
               with_pot=True):
         n = x.shape[0]
