@@ -507,25 +507,37 @@ def _rfft_d(M, dx, mode):
             grad_symbol(mz, Mz, dx, mode)[:, None, None])
 
 
-def greens_sub(plan: OraclePlan, g: OGrid):
+def _planes(k3, d3, planes):
+    """The rfft-grid axes restricted to the kz planes [p0, p1) (all planes if None)."""
+    if planes is None:
+        return k3, d3
+    p0, p1 = planes
+    return (k3[0], k3[1], k3[2][p0:p1]), (d3[0], d3[1], d3[2][p0:p1])
+
+
+def greens_sub(plan: OraclePlan, g: OGrid, planes=None):
     """(force kernel, potential kernel) of subgrid g on its padded rfft grid
-    (Mz, My, Mx//2+1); short-range reference S_l^2 - S_{l-1}^2 (Eq. 9).
+    (Mz, My, Mx//2+1), or on its kz planes [p0, p1) only; short-range reference
+    S_l^2 - S_{l-1}^2 (Eq. 9).
 
     Spectral gradient (R21): both are Eq. 5's G, with the value at k = 0 set to its
     limit -4 pi G (a_{l-1}^2 - a_l^2)/30 (the force multiplier -i d is 0 there, so
     the forces do not see it).  Two-point gradient: the potential-optimal kernel."""
-    kx, ky, kz = _rfft_k(g.M, g.dx)
+    (kx, ky, kz), dsym = _planes(_rfft_k(g.M, g.dx), _rfft_d(g.M, g.dx, plan.gradient), planes)
     al, alm1 = plan.a_soft(g.level), plan.a_soft(g.level - 1)
-    gf, gpo = influence(kx, ky, kz, g.dx, al, alm1, plan.G, _rfft_d(g.M, g.dx, plan.gradient))
+    gf, gpo = influence(kx, ky, kz, g.dx, al, alm1, plan.G, dsym)
     if plan.gradient == "fd2":
         return gf, gpo
     gf = gf.copy()
-    gf[0, 0, 0] = -4.0 * math.pi * plan.G * (alm1 ** 2 - al ** 2) / 30.0
+    if planes is None or planes[0] == 0:
+        gf[0, 0, 0] = -4.0 * math.pi * plan.G * (alm1 ** 2 - al ** 2) / 30.0
     return gf, gf
 
 
-def greens_root(plan: OraclePlan):
-    """(force kernel, potential kernel) of the isolated root on the (2N)^3 rfft grid.
+def greens_root(plan: OraclePlan, planes=None, james=None):
+    """(force kernel, potential kernel) of the isolated root on the (2N)^3 rfft grid
+    (or on its kz planes [p0, p1) only; ``james``, if given, is greens_root_james on
+    those planes).
 
     The optimal influence functions of level 0 (reference S_0^2, R3) are periodic.
     They are made isolated by splitting them into the reference potential, whose
@@ -539,19 +551,24 @@ def greens_root(plan: OraclePlan):
     Spectral gradient: the potential kernel is the force kernel (R21); two-point
     gradient: the potential-optimal kernel."""
     g = plan.grids[0]
-    kx, ky, kz = _rfft_k(g.M, g.dx)
+    (kx, ky, kz), dsym = _planes(_rfft_k(g.M, g.dx), _rfft_d(g.M, g.dx, plan.gradient), planes)
     a0 = plan.a_soft(0)
-    gj = greens_root_james(plan)
+    if james is not None:
+        gj = james
+    else:
+        gj = greens_root_james(plan)
+        if planes is not None:
+            gj = gj[planes[0]:planes[1]]
     KX, KY, KZ = np.broadcast_arrays(kx, ky, kz)
     k = np.sqrt(KX * KX + KY * KY + KZ * KZ)
     with np.errstate(divide="ignore", invalid="ignore"):
         gref = -4.0 * math.pi * plan.G * s2_hat(k * a0 / 2) ** 2 / (k * k)
-        fo, po = influence(kx, ky, kz, g.dx, a0, None, plan.G,
-                           _rfft_d(g.M, g.dx, plan.gradient))
+        fo, po = influence(kx, ky, kz, g.dx, a0, None, plan.G, dsym)
         dF = fo - gref
         dP = po - gref
-    dF[0, 0, 0] = -math.pi * plan.G * g.dx ** 2 if plan.gradient == "spectral" else 0.0
-    dP[0, 0, 0] = -math.pi * plan.G * g.dx ** 2
+    if planes is None or planes[0] == 0:
+        dF[0, 0, 0] = -math.pi * plan.G * g.dx ** 2 if plan.gradient == "spectral" else 0.0
+        dP[0, 0, 0] = -math.pi * plan.G * g.dx ** 2
     gf = gj + dF
     return (gf, gf) if plan.gradient == "spectral" else (gf, gj + dP)
 
@@ -572,10 +589,15 @@ def greens_root_periodic(plan: OraclePlan):
     return (fo, fo) if plan.gradient == "spectral" else (fo, po)
 
 
-def greens(plan: OraclePlan, g: OGrid):
+def greens(plan: OraclePlan, g: OGrid, planes=None):
+    """(force, potential) kernels of grid g on its rfft grid, or on its kz planes
+    [p0, p1) only (the same values: each plane depends on its own wavenumbers)."""
     if g.level > 0:
-        return greens_sub(plan, g)
-    return greens_root_periodic(plan) if plan.periodic else greens_root(plan)
+        return greens_sub(plan, g, planes)
+    if plan.periodic:
+        fo, fp = greens_root_periodic(plan)
+        return (fo, fp) if planes is None else (fo[planes[0]:planes[1]], fp[planes[0]:planes[1]])
+    return greens_root(plan, planes)
 
 
 # --------------------------------------------------------------------------

@@ -726,3 +726,19 @@ def test_mesh_forces_match_direct_pp_sum():
     ref = O.pp_reference_accel(p[:, 0], p[:, 1], p[:, 2], m, plan.a_soft(2))
     err = np.linalg.norm(r["acc"] - ref, axis=1) / np.linalg.norm(ref, axis=1)
     assert np.median(err) < 0.02 and err.max() < 0.08
+
+
+def test_greens_on_plane_ranges_equal_whole_grid():
+    """The kernels of a range of kz planes are those planes of the whole grid's kernels
+    (subgrid and isolated root; both gradients)."""
+    grids = [GridSpec(0, -1, (0, 0, 0), (8,) * 3), GridSpec(1, 0, (4, 4, 6), (8, 6, 4))]
+    for grad in ("spectral", "fd2"):
+        plan = O.OraclePlan(8, grids, gradient=grad)
+        for g in plan.grids:
+            whole = O.greens(plan, g)
+            Mz = int(g.M[2])
+            cuts = [0, 3, Mz // 2, Mz // 2 + 1, Mz]
+            for p0, p1 in zip(cuts[:-1], cuts[1:]):
+                part = O.greens(plan, g, planes=(p0, p1))
+                for a, b in zip(part, whole):
+                    assert np.array_equal(a, b[p0:p1])
