@@ -8,15 +8,17 @@ A step is one pass of the whole hot path over the workload:
   adjoint  the reverse sweep for the gradient of the potential energy W with respect
            to positions and masses (and gas), after the forward solve.
 Workloads (synthetic and seeded, shaped like the paper's tests):
+  large_nested    root 512^3 (1024^3 padded FFT) + 3 nested 256^3 levels, 2^24 Plummer
+                  particles (b = 0.02) plus two orbiting point masses -- the default:
+                  the largest configuration, on one GPU; also 100 leapfrog steps and
+                  the energy drift;
   plummer_nested  root 128^3 + 2 nested 64^3 levels, 2^20 Plummer particles
-                  (b = 0.05), no gas -- the default and the headline line;
+                  (b = 0.05), no gas;
   root32_gas      single isolated root 32^3, 4096 particles + Gaussian gas blob;
   clumps          root 64^3 + 256 non-cubic level-1 grids (sides 8..48) on 256
                   Plummer clumps, 2^21 particles, lognormal masses;
   plummer_gas     root 256^3 + 2 nested 128^3 levels, 2^22 Plummer particles plus a
                   lognormal k^-2 random gas field (forward + adjoint);
-  large_nested    root 512^3 + 3 nested 256^3 levels, 2^24 Plummer particles plus two
-                  orbiting point masses; also 100 leapfrog steps and the energy drift;
   plummer_periodic  the plummer_nested geometry with a periodic root (root FFT 128^3,
                   not 256^3), 2^20 Plummer particles reaching the box edges;
   sine_wave       the sine wave test: periodic root 64^3 + levels over
@@ -24,16 +26,25 @@ Workloads (synthetic and seeded, shaped like the paper's tests):
                   4096 massless tracer particles.
 
 Prints one JSON line: value = particles/s of the FP32 forward step (inputs resident in
-HBM), with cells/s, the forward+adjoint step, the FP64 steps, errors against the FP64
-oracle, the roofline of the dominant kernel (HIP events on the library stream) and the
-oracle timed on the host as the CPU baseline.
+HBM), with cells/s, the forward+adjoint step, the FP64 steps, the staged per-level FP64
+path, errors against the FP64 oracle, the roofline of the dominant kernel (HIP events
+on the library stream) and the oracle timed on the host as the CPU baseline.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload plummer_nested]
-                    [--no-cpu-baseline] [--no-fp64] [--no-adjoint]
+The oracle leg runs first, before the GPU is touched, in a pool of worker processes
+(the unchanged oracle functions over particle chunks and kz-plane ranges).  On the
+large workload it is staged (a full oracle solve of the 1024^3 root takes many
+minutes): the GMF of every grid at sampled cells and the level masses, and the own
+field of the finest grid (deposit, Green's function, 512^3 convolution) at sampled
+cells; --oracle-full runs the whole oracle solve instead (every grid, composition,
+every particle), for a one-off check.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload large_nested]
+                    [--no-cpu-baseline] [--oracle-full] [--no-fp64] [--no-adjoint]
 """
 
 import argparse
 import json
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -50,16 +61,45 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(plan, npart, npart_level, esize, root_gas=False):
+# --------------------------------------------------------------------------------------
+# algorithmic bytes
+# --------------------------------------------------------------------------------------
+
+def pass_b_floor(plan, esize):
+    """Bytes per step of the survey's three-pass floor for the z pass (pass B): read and
+    write the gz My (Mx/2+1) complex intermediate and read the (M/2+1)^3 kernel octant
+    (one real per entry), summed over the grids."""
+    b = 0.0
+    for g in plan.grids:
+        gz = g["gmf_n"][2]
+        Mx, My, Mz = g["fft_n"]
+        W = Mx // 2 + 1
+        b += 2 * gz * My * W * 2 * esize + (Mx // 2 + 1) * (My // 2 + 1) * (Mz // 2 + 1) * esize
+    return b
+
+
+def conv_arrays(plan):
+    """(z-pass output arrays, y-pass output arrays, kernel-table values per octant
+    entry) of the library's transform passes for this plan: with the spectral gradient
+    one kernel serves force and potential (two z arrays, three y arrays, one value),
+    with the two-point gradient the potential has its own (three, four, a pair)."""
+    return (3, 4, 2) if plan.cfg.gradient == 1 else (2, 3, 1)
+
+
+def kernel_bytes(plan, npart, npart_level, esize, root_gas=False, pot_only_adjoint=True):
     """Algorithmic HBM bytes per step of each kernel name: what the method must move
-    at least once (c = complex bytes = 2 esize)."""
+    at least once with the arrays each pass reads and writes (c = complex bytes =
+    2 esize).  The reverse sweep benchmarked is the gradient of W, whose transposed
+    convolution carries the potential's cotangent alone (one FP64 value per field
+    cell, one complex array per pass until the z pass)."""
     c = 2 * esize
+    fs = 1 if pot_only_adjoint else 4
     names = ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv", "deposit_tiles",
              "deposit_finalize", "compose", "interp", "unpack", "bin_count", "bin_scatter",
-             "adj_fft_x",
-             "adj_fft_y", "adj_fft_z", "adj_fft_y_inv", "adj_fft_x_inv", "adj_interp",
-             "adj_deposit_grid", "adj_deposit_particles", "adj_restrict")
+             "adj_fft_x", "adj_fft_y", "adj_fft_z", "adj_fft_y_inv", "adj_fft_x_inv",
+             "adj_interp", "adj_deposit_grid", "adj_deposit_particles", "adj_restrict")
     b = {k: 0.0 for k in names}
+    nz, ny, tv = conv_arrays(plan)
     for g in plan.grids:
         gx, gy, gz = g["gmf_n"]
         fx, fy, fz = g["fld_n"]
@@ -68,21 +108,22 @@ def kernel_bytes(plan, npart, npart_level, esize, root_gas=False):
         oct_ = (Mx // 2 + 1) * (My // 2 + 1) * (Mz // 2 + 1)
         b["fft_x_fwd"] += gx * gy * gz * esize + gy * gz * W * c
         b["fft_y_fwd"] += gz * gy * W * c + gz * My * W * c
-        b["fft_z_conv"] += gz * My * W * c + oct_ * c + 3 * fz * My * W * c
-        b["fft_y_inv"] += 3 * fz * My * W * c + 4 * fz * fy * W * c
-        b["fft_x_inv"] += 4 * fz * fy * W * c + fx * fy * fz * 4 * esize
+        b["fft_z_conv"] += gz * My * W * c + oct_ * tv * esize + nz * fz * My * W * c
+        b["fft_y_inv"] += nz * fz * My * W * c + ny * fz * fy * W * c
+        b["fft_x_inv"] += ny * fz * fy * W * c + fx * fy * fz * 4 * esize
         # the transposed passes move the same arrays in the other direction; their
-        # field-box input is the FP64 cotangent
-        b["adj_fft_x"] += fx * fy * fz * 4 * 8 + 4 * fz * fy * W * c
-        b["adj_fft_y"] += 4 * fz * fy * W * c + 3 * fz * My * W * c
-        b["adj_fft_z"] += 3 * fz * My * W * c + oct_ * c + gz * My * W * c
+        # field-box input is the FP64 cotangent (fs values per cell)
+        b["adj_fft_x"] += fx * fy * fz * fs * 8 + fs * fz * fy * W * c
+        b["adj_fft_y"] += fs * fz * fy * W * c + min(fs, 3) * fz * My * W * c
+        b["adj_fft_z"] += (min(fs, 3) * fz * My * W * c + oct_ * tv * esize
+                           + gz * My * W * c)
         b["adj_fft_y_inv"] += gz * My * W * c + gz * gy * W * c
         b["adj_fft_x_inv"] += gy * gz * W * c + gx * gy * gz * esize
         b["deposit_finalize"] += gx * gy * gz * (8 + esize)     # FP64 mass in, GMF out
         b["adj_deposit_grid"] += gx * gy * gz * (esize + 8)     # GMF cotangent in, FP64 out
         if g["level"] > 0:      # own field read and rewritten in place, parent at 1/8 density
             b["compose"] += fx * fy * fz * 4 * esize * (2 + 1 / 8)
-            b["adj_restrict"] += fx * fy * fz * 4 * 8 * (1 + 2 / 8)
+            b["adj_restrict"] += fx * fy * fz * fs * 8 * (1 + 2 / 8)
     binned = sum(npart_level)
     for nb in npart_level:
         b["deposit_tiles"] += nb * 4 * esize           # sorted (x/dx, y/dx, z/dx, m) records
@@ -113,40 +154,15 @@ def kernel_bytes(plan, npart, npart_level, esize, root_gas=False):
     return b
 
 
-def sine_wave_accuracy(Context, Plan, dev):
-    """The sine wave test's accuracy (Sec. 3): per level, the largest deviation over the
-    active cells of a_x and Phi from the continuum solution -4 pi (P / 2 pi)^2
-    sin(2 pi x / P), relative to its amplitude, for P = 1 and 0.2: FP32 and FP64 with
-    the spectral gradient, and FP64 with the two-point one (Sec. 2.2 names both)."""
-    import torch
-    import apm_workloads as W
-    out = {}
-    for P, grad, dt in [(P, g, d) for P in (1.0, 0.2)
-                        for g, d in (("spectral", torch.float32), ("spectral", torch.float64),
-                                     ("fd2", torch.float64))]:
-        w = W.workload_sine_wave(period=P)
-        plan = Plan(w.root_n, w.grids, boundary="periodic", gradient=grad)
-        ctx = Context(plan, 0)
-        k = 2 * np.pi / P
-        amp_a, amp_p = 4 * np.pi / k, 4 * np.pi / k ** 2
-        x, y, z, m = (torch.from_numpy(np.asarray(a, np.float64)).to(dev).to(dt)
-                      for a in (w.x, w.y, w.z, w.m))
-        gas = [ctx.pack_gas(l, w.gas, dt) for l in range(plan.nlevels)]
-        ctx.solve(x, y, z, m, gas)
-        torch.cuda.synchronize()
-        lv = []
-        for l in range(plan.nlevels):
-            F = ctx.solved_field(l, dt)
-            g = plan.level_grids(l)[0]
-            f = ctx.field_view(F, g["index"]).cpu().numpy().astype(np.float64)
-            a0 = [g["lo"][i] - g["fld_lo"][i] for i in range(3)]
-            f = f[a0[2]:a0[2] + g["n"][2], a0[1]:a0[1] + g["n"][1], a0[0]:a0[0] + g["n"][0]]
-            xc = (g["lo"][0] + np.arange(g["n"][0]) + 0.5) * g["dx"]
-            ea = float(np.abs(f[..., 0] - amp_a * np.cos(k * xc)).max() / amp_a)
-            ep = float(np.abs(f[..., 3] + amp_p * np.sin(k * xc)).max() / amp_p)
-            lv.append({"level": l, "max_rel_err_ax": ea, "max_rel_err_phi": ep})
-        out[f"P={P:g}/{grad}/{'f32' if dt == torch.float32 else 'f64'}"] = lv
-    return out
+def survey_floor_bytes(kernel, plan, npart_level, esize):
+    """Bytes per step of the survey's floor for a kernel family (the roofline's
+    `achieved`): pass B for the z pass, 4 esize per binned particle + esize per GMF
+    cell for the deposit, else None (the kernel's own algorithmic bytes are used)."""
+    if kernel == "fft_z_conv":
+        return pass_b_floor(plan, esize)
+    if kernel == "deposit_tiles":
+        return sum(npart_level) * 4 * esize + sum(L["gmf_elems"] for L in plan.levels) * esize
+    return None
 
 
 def measured_traffic(kernel, workload):
@@ -163,7 +179,13 @@ def measured_traffic(kernel, workload):
                      float(rec["write_kib"]) * float(rec["write_scale"]))
 
 
+# --------------------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------------------
+
 WORKLOADS = {
+    "large_nested": ("large_nested: root 512^3 (1024^3 padded FFT) + 3 nested 256^3 levels, "
+                     "2^24 Plummer particles (b=0.02) + 2 orbiting point masses m=0.1"),
     "plummer_nested": ("plummer_nested: root 128^3 + 2 nested 64^3 levels, 2^20 Plummer "
                        "particles (b=0.05), no gas"),
     "root32_gas": ("root32_gas: single isolated root 32^3, 4096 particles uniform in the "
@@ -173,8 +195,6 @@ WORKLOADS = {
                "clumps (b=0.01), lognormal masses"),
     "plummer_gas": ("plummer_gas: root 256^3 + 2 nested 128^3 levels, 2^22 Plummer particles "
                     "(b=0.05) + lognormal k^-2 random gas field"),
-    "large_nested": ("large_nested: root 512^3 (1024^3 padded FFT) + 3 nested 256^3 levels, "
-                     "2^24 Plummer particles (b=0.02) + 2 orbiting point masses m=0.1"),
     "plummer_periodic": ("plummer_periodic: periodic root 128^3 (128^3 FFT) + 2 nested 64^3 "
                          "levels, 2^20 Plummer particles (b=0.05) over the whole box, no gas"),
     "sine_wave": ("sine_wave: the sine wave test, periodic root 64^3 + levels over "
@@ -182,37 +202,245 @@ WORKLOADS = {
                   "2 + sin(2 pi x), 4096 massless tracers"),
 }
 
+# the oracle solves these whole (in seconds to a minute); the others are staged
+FULL_ORACLE = ("plummer_nested", "root32_gas", "plummer_periodic", "sine_wave")
+
 
 def make_workload(name):
     import apm_workloads as W
-    if name == "plummer_nested":
-        return W.workload_plummer_nested()
-    if name == "root32_gas":
-        return W.workload_root32_uniform_gas()
-    if name == "clumps":
-        return W.workload_clumps()
-    if name == "plummer_gas":
-        return W.workload_plummer_gas()
-    if name == "large_nested":
-        return W.workload_large_nested()
-    if name == "plummer_periodic":
-        return W.workload_plummer_periodic()
-    if name == "sine_wave":
-        return W.workload_sine_wave()
-    raise ValueError(name)
+    return {"plummer_nested": W.workload_plummer_nested, "root32_gas": W.workload_root32_uniform_gas,
+            "clumps": W.workload_clumps, "plummer_gas": W.workload_plummer_gas,
+            "large_nested": W.workload_large_nested,
+            "plummer_periodic": W.workload_plummer_periodic,
+            "sine_wave": W.workload_sine_wave}[name]()
 
+
+# --------------------------------------------------------------------------------------
+# the staged oracle on the host cores (worker processes forked before any GPU use)
+# --------------------------------------------------------------------------------------
+
+_OW = {}          # what forked workers read: plan, particles, James planes, fields
+
+
+def _w_deposit(args):
+    """Oracle deposit of particles [lo, hi) onto grid gi: the whole GMF array, or only
+    its values at `idx` (flat) plus its sum."""
+    from oracle import apm_oracle as O
+    gi, lo, hi, idx = args
+    plan, (x, y, z, m) = _OW["plan"], _OW["p"]
+    rho = O.deposit_particles(plan, plan.grids[gi], x[lo:hi], y[lo:hi], z[lo:hi], m[lo:hi])
+    if idx is None:
+        return gi, rho, float(rho.sum())
+    return gi, rho.reshape(-1)[idx], float(rho.sum())
+
+
+def _w_greens(args):
+    from oracle import apm_oracle as O
+    gi, p0, p1 = args
+    plan = _OW["plan"]
+    g = plan.grids[gi]
+    if g.level == 0 and not plan.periodic:
+        return gi, p0, O.greens_root(plan, planes=(p0, p1), james=_OW["james"][p0:p1])
+    return gi, p0, O.greens(plan, g, planes=(p0, p1))
+
+
+def _w_interp(args):
+    from oracle import apm_oracle as O
+    lo, hi = args
+    plan, (x, y, z, m) = _OW["plan"], _OW["p"]
+    return lo, O.interp(plan, _OW["fields"], _OW["owner"][lo:hi], x[lo:hi], y[lo:hi], z[lo:hi])
+
+
+def _pool(workers):
+    return mp.get_context("fork").Pool(workers)
+
+
+def _chunks(n, k):
+    e = np.linspace(0, n, k + 1).astype(np.int64)
+    return [(int(a), int(b)) for a, b in zip(e[:-1], e[1:]) if b > a]
+
+
+def _deposit_grids(plan, npart, grids, workers, samples):
+    """GMF of each grid in `grids` (the whole array where samples[gi] is None, else the
+    values at samples[gi]) and its sum, from particle chunks deposited in parallel."""
+    def nchunks(gi):                    # whole arrays of a 512^3 root: fewer, larger chunks
+        big = samples.get(gi) is None and np.prod(plan.grids[gi].gmf_n) > (1 << 26)
+        return max(4, workers // 4) if big else workers
+    tasks = [(gi, lo, hi, samples.get(gi)) for gi in grids for lo, hi in _chunks(npart, nchunks(gi))]
+    out, tot = {}, {gi: 0.0 for gi in grids}
+    with _pool(workers) as pool:
+        for gi, v, s in pool.imap_unordered(_w_deposit, tasks):
+            out[gi] = v if gi not in out else out[gi] + v
+            tot[gi] += s
+    return out, tot
+
+
+def _greens_parallel(plan, gi, workers):
+    g = plan.grids[gi]
+    Mz = int(g.M[2])
+    tasks = [(gi, a, b) for a, b in _chunks(Mz, 4 * workers)]
+    parts = {}
+    with _pool(workers) as pool:
+        for _, p0, k in pool.imap_unordered(_w_greens, tasks):
+            parts[p0] = k
+    keys = sorted(parts)
+    gf = np.concatenate([parts[k][0] for k in keys], axis=0)
+    same = all(parts[k][0] is parts[k][1] for k in keys)
+    gp = gf if same else np.concatenate([parts[k][1] for k in keys], axis=0)
+    return gf, gp
+
+
+def staged_oracle(w, full, workers, seed=1410):
+    """The FP64 oracle on the FP32-rounded inputs of the workload, on `workers` host
+    processes.  Staged (full = False): every grid's GMF at 4096 sampled cells and its
+    mass; the finest grid's deposit, Green's function and convolution, its own field at
+    64 sampled field cells.  Full: the whole solve (every grid's GMF, own and composed
+    field, owner grids, every particle's acceleration and potential)."""
+    from oracle import apm_oracle as O
+    rd = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    x, y, z, m = (rd(a) for a in (w.x, w.y, w.z, w.m))
+    if any(g is not None for g in w.gas):
+        raise ValueError("the staged oracle covers particle-only workloads")
+    plan = O.OraclePlan(w.root_n, w.grids)
+    _OW.clear()
+    _OW.update(plan=plan, p=(x, y, z, m))
+    rng = np.random.default_rng(seed)
+    res = {"mode": "full" if full else "staged", "workers": workers}
+    t_all = time.perf_counter()
+    fin = len(plan.grids) - 1
+    if not full:
+        samples = {g.index: rng.choice(int(np.prod(g.gmf_n)), min(4096, int(np.prod(g.gmf_n))),
+                                       replace=False) for g in plan.grids}
+        t0 = time.perf_counter()
+        gmf, tot = _deposit_grids(plan, w.npart, [fin], workers, {})
+        t_dep_fin = time.perf_counter() - t0
+        rest, tot2 = _deposit_grids(plan, w.npart, list(range(fin)), workers, samples)
+        tot.update(tot2)
+        g = plan.grids[fin]
+        rho = gmf[fin]
+        res["gmf_samples"] = {gi: (samples[gi], rest[gi]) for gi in range(fin)}
+        res["gmf_samples"][fin] = (samples[fin], rho.reshape(-1)[samples[fin]])
+        log(f"oracle: GMFs ({t_dep_fin:.1f} s for the finest grid's deposit)")
+        t0 = time.perf_counter()
+        kern = _greens_parallel(plan, fin, workers)
+        log(f"oracle: finest grid's Green's function {time.perf_counter() - t0:.1f} s")
+        t0 = time.perf_counter()
+        short = O.convolve(plan, g, rho, kern)
+        t_conv = time.perf_counter() - t0
+        cells = rng.choice(int(np.prod(g.fld_n)), min(64, int(np.prod(g.fld_n))), replace=False)
+        res["own_samples"] = {fin: (cells, short.reshape(-1, 4)[cells])}
+        res["mass"] = {gi: tot[gi] * plan.grids[gi].dx ** 3 for gi in tot}
+        res["sample_seconds"] = t_dep_fin + t_conv
+        res["sample_desc"] = (f"the forward solve of the finest grid alone: TSC deposit of all "
+                              f"{w.npart} particles onto its GMF ({workers} processes) and its "
+                              f"{'x'.join(str(int(v)) for v in g.M)} convolution (one core), "
+                              f"Green's function precomputed as on the GPU")
+        res["sample_cells"] = int(np.prod(g.n))
+        log(f"oracle: finest grid's convolution {t_conv:.1f} s")
+    else:
+        if not plan.periodic:
+            t0 = time.perf_counter()
+            _OW["james"] = O.greens_root_james(plan)
+            log(f"oracle: James root kernel {time.perf_counter() - t0:.1f} s")
+        kerns = {}
+        t0 = time.perf_counter()
+        for g in plan.grids:
+            kerns[g.index] = _greens_parallel(plan, g.index, workers)
+        _OW.pop("james", None)
+        log(f"oracle: Green's functions {time.perf_counter() - t0:.1f} s")
+        t_solve = time.perf_counter()
+        gmf, tot = _deposit_grids(plan, w.npart, [g.index for g in plan.grids], workers, {})
+        log(f"oracle: deposits {time.perf_counter() - t_solve:.1f} s")
+        short, fld = {}, {}
+        for g in plan.grids:
+            t0 = time.perf_counter()
+            short[g.index] = O.convolve(plan, g, gmf[g.index], kerns.pop(g.index))
+            log(f"oracle: convolution of grid {g.index} {time.perf_counter() - t0:.1f} s")
+        for lev in range(plan.nlevels):
+            for g in plan.level_grids(lev):
+                fld[g.index] = O.compose(plan, g, short[g.index],
+                                         fld[g.parent] if g.parent >= 0 else None)
+        own = O.owner_of(plan, x, y, z)
+        _OW.update(fields=[fld[g.index] for g in plan.grids], owner=own)
+        pa = np.zeros((w.npart, 4))
+        with _pool(workers) as pool:
+            for lo, v in pool.imap_unordered(_w_interp, _chunks(w.npart, 4 * workers)):
+                pa[lo:lo + v.shape[0]] = v
+        res["solve_seconds"] = time.perf_counter() - t_solve
+        res.update(gmf=gmf, short=short, field=fld, owner=own, acc=pa[:, :3], pot=pa[:, 3],
+                   mass={gi: tot[gi] * plan.grids[gi].dx ** 3 for gi in tot})
+        res["sample_seconds"] = res["solve_seconds"]
+        res["sample_desc"] = (f"the whole forward solve ({workers} processes for deposits, "
+                              f"Green's functions and interpolation; convolutions on one core), "
+                              f"Green's functions precomputed as on the GPU")
+        res["sample_cells"] = w.active_cells()
+    _OW.clear()
+    res["oracle_seconds"] = time.perf_counter() - t_all
+    return res
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / nb if nb > 0 else None
+
+
+def staged_errors(ref, got, plan_grids):
+    """Errors of GPU outputs against the staged oracle results (relative L2 over the
+    compared values)."""
+    e = {}
+    for gi, (idx, vals) in ref.get("gmf_samples", {}).items():
+        e[f"gmf_grid{gi}_sampled"] = rel(got["gmf"][gi].reshape(-1)[idx], vals)
+    for gi, (cells, vals) in ref.get("own_samples", {}).items():
+        f = got["own"][gi].reshape(-1, 4)[cells]
+        e[f"own_acc_grid{gi}_sampled"] = rel(f[:, :3], vals[:, :3])
+        e[f"own_pot_grid{gi}_sampled"] = rel(f[:, 3], vals[:, 3])
+    if "field" in ref:
+        for gi in ref["field"]:
+            e[f"gmf_grid{gi}"] = rel(got["gmf"][gi], ref["gmf"][gi])
+            e[f"own_acc_grid{gi}"] = rel(got["own"][gi][..., :3], ref["short"][gi][..., :3])
+            e[f"own_pot_grid{gi}"] = rel(got["own"][gi][..., 3], ref["short"][gi][..., 3])
+            e[f"field_acc_grid{gi}"] = rel(got["field"][gi][..., :3], ref["field"][gi][..., :3])
+            e[f"field_pot_grid{gi}"] = rel(got["field"][gi][..., 3], ref["field"][gi][..., 3])
+        own = ref["owner"] >= 0
+        e["owner_mismatches"] = int(np.sum(got["owner"] != ref["owner"]))
+        e["acc_rel_l2"] = rel(got["acc"][own], ref["acc"][own])
+        e["pot_rel_l2"] = rel(got["pot"][own], ref["pot"][own])
+    lev_mass = {}
+    for gi, mref in ref["mass"].items():
+        lev = plan_grids[gi]["level"]
+        lev_mass[lev] = lev_mass.get(lev, 0.0) + mref
+    for lev, mref in sorted(lev_mass.items()):
+        e[f"mass_level{lev}_rel"] = abs(got["mass"][lev] - mref) / abs(mref)
+    return e
+
+
+# --------------------------------------------------------------------------------------
+# main
+# --------------------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plummer_nested", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large_nested", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="large workloads: run the whole oracle solve (many minutes) instead "
+                         "of the staged one")
+    ap.add_argument("--oracle-workers", type=int, default=0,
+                    help="host processes of the oracle leg (0: the CPUs this process may use, "
+                         "at most 16)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-staged", action="store_true",
+                    help="skip the staged per-level FP64 timing")
     ap.add_argument("--leapfrog-steps", type=int, default=100,
                     help="KDK steps timed for large_nested (energy drift)")
+    ap.add_argument("--leapfrog-dt-div", type=int, default=400,
+                    help="large_nested: the leapfrog step is the point masses' period over this")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB a few times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -221,6 +449,18 @@ def main():
         print("bench.py: this build runs on one GPU only (no multi-GPU path); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+
+    w = None
+    ref = None
+    if not args.calibrate_copy:
+        w = make_workload(args.workload)
+        log(f"workload {w.name}: {w.npart} particles, {len(w.grids)} grids, "
+            f"{w.active_cells()} active cells")
+    if w is not None and not args.no_cpu_baseline and args.workload not in FULL_ORACLE:
+        workers = args.oracle_workers or min(16, len(os.sched_getaffinity(0)))
+        log(f"oracle leg ({'full' if args.oracle_full else 'staged'}) on {workers} processes")
+        ref = staged_oracle(w, args.oracle_full, workers)
+        log(f"oracle leg done in {ref['oracle_seconds']:.1f} s")
 
     import torch
     dev = torch.device("cuda", 0)
@@ -237,18 +477,16 @@ def main():
 
     from paper_1410_0010_amd import Context, Plan
 
-    w = make_workload(args.workload)
     plan = Plan(w.root_n, w.grids, boundary=w.boundary)
     ctx = Context(plan, 0)
     active = w.active_cells()
     n = w.npart
-    log(f"workload {w.name}: {n} particles, {len(w.grids)} grids, {active} active cells")
-    fp64_ok = not args.no_fp64 and args.workload != "large_nested"
+    fp64_ok = not args.no_fp64
     do_adj = not args.no_adjoint
 
-    def tens(dtype):
-        return [torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype))).to(dev)
-                for a in (w.x, w.y, w.z, w.m)]
+    def tens(dtype, src=None):
+        src = src or (w.x, w.y, w.z, w.m)
+        return [torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype))).to(dev) for a in src]
 
     def gas_for(tdt):
         g = [ctx.pack_gas(l, w.gas, tdt) for l in range(plan.nlevels)]
@@ -293,30 +531,81 @@ def main():
         if profile:
             ctx.profile(False)
             prof = ctx.profile_read()
-        res = dict(ms=ms, wall_ms=1000 * wall / steps, totals=tot.cpu().numpy(), prof=prof,
-                   acc=np.stack([o.cpu().numpy().astype(np.float64) for o in out[:3]], 1),
-                   pot=out[3].cpu().numpy().astype(np.float64))
+        res = dict(ms=ms, wall_ms=1000 * wall / steps, totals=tot.cpu().numpy(), prof=prof)
         if grads is not None:
             res["gx"] = np.stack([t.cpu().numpy().astype(np.float64) for t in grads[:3]], 1)
             res["gm"] = grads[3].cpu().numpy().astype(np.float64)
+        res["acc"] = np.stack([o.cpu().numpy().astype(np.float64) for o in out[:3]], 1)
+        res["pot"] = out[3].cpu().numpy().astype(np.float64)
+        del x, y, z, m, out
+        return res
+
+    def staged_path(dtype, steps, src=None, outputs=False):
+        """The plain per-level path through the staged entry points (owner, deposit,
+        solve_level, accel, interp per level, totals), eager: ms per step, and the
+        outputs of the last step when asked."""
+        x, y, z, m = tens(dtype, src)
+        gas = [ctx.pack_gas(l, w.gas, x.dtype) for l in range(plan.nlevels)]
+        ax, ay, az, pot = (torch.zeros(n, dtype=x.dtype, device=dev) for _ in range(4))
+        gmf = [ctx.empty_gmf(l, x.dtype) for l in range(plan.nlevels)]
+        own = [ctx.empty_field(l, x.dtype) for l in range(plan.nlevels)]
+        fld = [ctx.empty_field(l, x.dtype) for l in range(plan.nlevels)]
+        owner = torch.empty(n, dtype=torch.int32, device=dev)
+
+        def step():
+            ctx.owner(x, y, z, out=owner)
+            for l in range(plan.nlevels):
+                ctx.deposit(l, x, y, z, m, gas[l], gas[l - 1] if l > 0 else None, out=gmf[l])
+            for l in range(plan.nlevels):
+                ctx.solve_level(l, gmf[l], out=own[l])
+            for l in range(plan.nlevels):
+                ctx.accel(l, own[l], fld[l - 1] if l > 0 else None, out=fld[l])
+            for l in range(plan.nlevels):
+                ctx.interp(l, fld[l], x, y, z, owner, ax, ay, az, pot)
+            return ctx.totals(gmf, m, owner, ax, ay, az, pot)
+
+        step()
+        torch.cuda.synchronize()
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record()
+        for _ in range(steps):
+            tot = step()
+        s1.record()
+        torch.cuda.synchronize()
+        res = {"ms": s0.elapsed_time(s1) / steps}
+        if outputs:
+            # own fields: the staged solve_level outputs (the composed ones are fld)
+            cpu = lambda t: t.cpu().numpy().astype(np.float64)
+            res.update(
+                gmf=[ctx.gmf_view(gmf[g["level"]], g["index"]).cpu().numpy().astype(np.float64)
+                     for g in plan.grids],
+                own=[cpu(ctx.field_view(own[g["level"]], g["index"])) for g in plan.grids],
+                field=[cpu(ctx.field_view(fld[g["level"]], g["index"])) for g in plan.grids],
+                owner=owner.cpu().numpy(), acc=np.stack([cpu(ax), cpu(ay), cpu(az)], 1),
+                pot=cpu(pot), mass=list(tot[:plan.nlevels]))
+        del x, y, z, m, gmf, own, fld
         return res
 
     log(f"FP32 forward: warmup {args.warmup}, {args.steps} timed steps")
     r32 = run(np.float32, args.steps, args.warmup)
     log(f"FP32 forward: {r32['ms']:.3f} ms/step")
-    a32 = a64 = r64 = None
+    a32 = a64 = r64 = s64 = None
     if do_adj:
         a32 = run(np.float32, args.steps, 1, adjoint=True)
         log(f"FP32 forward+adjoint: {a32['ms']:.3f} ms/step")
-    log("FP32: profiled pass (HIP events around every kernel)")
-    psteps = max(3, args.steps // 4)
+    log("FP32: profiled pass (HIP events around every kernel, one stream, no graph)")
+    psteps = max(3, args.steps // 3)
     p32 = run(np.float32, psteps, 1, adjoint=do_adj, profile=True)
     if fp64_ok:
         r64 = run(np.float64, args.steps, args.warmup)
         log(f"FP64 forward: {r64['ms']:.3f} ms/step")
         if do_adj:
-            a64 = run(np.float64, args.steps, 1, adjoint=True)
+            a64 = run(np.float64, max(3, args.steps // 2), 1, adjoint=True)
             log(f"FP64 forward+adjoint: {a64['ms']:.3f} ms/step")
+        if not args.no_staged:
+            s64 = staged_path(np.float64, max(3, args.steps // 2))
+            log(f"FP64 staged per-level path: {s64['ms']:.3f} ms/step")
 
     # per-kernel times of the FP32 step, the dominant forward kernel and its roofline
     npl = []
@@ -328,6 +617,7 @@ def main():
         cx = np.floor(pos * (1.0 / plan.levels[l]["dx"]))
         inside = np.all((cx >= lo) & (cx < hi), axis=1) & np.all((pos >= 0) & (pos < 1), axis=1)
         npl.append(int(inside.sum()))
+    del pos
     kb = kernel_bytes(plan, n, npl, 4, root_gas=w.gas[0] is not None)
     per_kernel = {k: dict(ms_per_step=v[0] / psteps, launches_per_step=v[1] / psteps)
                   for k, v in p32["prof"].items()}
@@ -336,13 +626,16 @@ def main():
     dom_ms = per_kernel[dom]["ms_per_step"]
     dom_launches = per_kernel[dom]["launches_per_step"]
     dom_launch_ms = dom_ms / dom_launches
-    achieved = kb.get(dom, 0.0) / (dom_ms * 1e-3) / 1e9
+    floor_b = survey_floor_bytes(dom, plan, npl, 4)
+    ach_b = floor_b if floor_b is not None else kb.get(dom, 0.0)
+    achieved = ach_b / (dom_ms * 1e-3) / 1e9
     for k in per_kernel:
         if kb.get(k):
             per_kernel[k]["gbs"] = kb[k] / (per_kernel[k]["ms_per_step"] * 1e-3) / 1e9
     log("per-kernel (FP32): " + ", ".join(
         f"{k} {v['ms_per_step'] * 1e3:.1f}us" + (f" {v['gbs']:.0f}GB/s" if 'gbs' in v else "")
         for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1]['ms_per_step'])))
+    fwd_kernels_ms = sum(v["ms_per_step"] for k, v in per_kernel.items() if not k.startswith("adj"))
 
     # leapfrog (large nested run): KDK steps, energy drift.  The two point masses'
     # self-energy (1/2 m Phi_self, Phi_self from a solve of the mass alone) depends on
@@ -356,7 +649,7 @@ def main():
                       for v in (w.vx, w.vy, w.vz))
         r, b = 0.036, 0.02
         v = np.sqrt(r * (0.1 / (2 * r) ** 2 + r ** 3 / (r * r + b * b) ** 1.5 / r ** 2))
-        h = 2 * np.pi * r / v / 400
+        h = 2 * np.pi * r / v / args.leapfrog_dt_div
         nst = args.leapfrog_steps
         nseg = 10 if nst % 10 == 0 else 1
         pot = torch.empty_like(x)
@@ -385,7 +678,6 @@ def main():
             if seg == 0:
                 energies.append(float(e[0]))
                 xs = [t.clone() for t in (x, y, z)]
-                # self-energy at the initial positions
                 x.copy_(x0); y.copy_(y0); z.copy_(z0)
                 selfs.append(self_energy())
                 x.copy_(xs[0]); y.copy_(xs[1]); z.copy_(xs[2])
@@ -394,7 +686,8 @@ def main():
         E = np.array(energies)
         Ec = E - np.array(selfs)
         dev_ = lambda a: float(np.max(np.abs(a - a[0])) / abs(a[0]))
-        lf = {"steps": nst, "dt": h, "seconds": sec, "ms_per_step": 1000 * sec / nst,
+        lf = {"steps": nst, "dt": h, "dt_divisor": args.leapfrog_dt_div, "seconds": sec,
+              "ms_per_step": 1000 * sec / nst,
               "particle_steps_per_s": n * nst / sec, "energy_checkpoints": E.tolist(),
               "point_mass_self_energy": selfs,
               "energy_drift": float(abs(E[-1] - E[0]) / abs(E[0])),
@@ -405,21 +698,38 @@ def main():
             f"{lf['energy_drift']:.3e} (max {lf['energy_max_rel_dev']:.3e}); without the point "
             f"masses' self-energy {lf['energy_drift_excl_point_mass_self']:.3e} "
             f"(max {lf['energy_max_rel_dev_excl_point_mass_self']:.3e})")
+        del x, y, z, m, vx, vy, vz, x0, y0, z0, vx0, vy0, vz0, pot, ctx_self
 
-    # errors against the FP64 oracle and the oracle's own time (CPU baseline)
+    # errors against the FP64 oracle, and the oracle's own time (CPU baseline)
     cpu = None
     err = {}
-    if not args.no_cpu_baseline and args.workload in ("plummer_nested", "root32_gas",
-                                                      "plummer_periodic", "sine_wave"):
+    if ref is not None:
+        rd = [np.asarray(a, np.float32) for a in (w.x, w.y, w.z, w.m)]
+        for name, dt in (("fp32", np.float32), ("fp64", np.float64)):
+            if dt == np.float64 and not fp64_ok:
+                continue
+            got = staged_path(dt, 1, src=rd, outputs=True)
+            e = staged_errors(ref, got, plan.grids)
+            err.update({f"{name}_{k}": v for k, v in e.items()})
+            del got
+        log("errors vs the oracle: " + ", ".join(f"{k} {v:.2e}" for k, v in err.items()
+                                                  if isinstance(v, float)))
+        cpu = {"value": ref["sample_cells"] / ref["sample_seconds"], "unit": "cells/s",
+               "cores": ref["workers"], "kind": "oracle", "sample": ref["sample_desc"],
+               "seconds": ref["sample_seconds"], "oracle_leg_seconds": ref["oracle_seconds"],
+               "mode": ref["mode"]}
+        if ref["mode"] == "full":
+            cpu["particles_per_s"] = n / ref["sample_seconds"]
+    elif not args.no_cpu_baseline and args.workload in FULL_ORACLE:
         from oracle import apm_oracle as O
         from oracle import apm_adjoint as A
         log("oracle: Green's functions (cached, as on the GPU), then one timed forward solve "
             "and one timed reverse sweep")
         op = O.OraclePlan(w.root_n, w.grids, boundary=w.boundary)
         cache = {g.index: O.greens(op, g) for g in op.grids}
-        rd = lambda a: None if a is None else np.asarray(a, np.float32).astype(np.float64)
-        x32 = [rd(a) for a in (w.x, w.y, w.z, w.m)]
-        g32 = [rd(a) for a in w.gas]
+        rdn = lambda a: None if a is None else np.asarray(a, np.float32).astype(np.float64)
+        x32 = [rdn(a) for a in (w.x, w.y, w.z, w.m)]
+        g32 = [rdn(a) for a in w.gas]
         t0 = time.perf_counter()
         ref32 = O.solve(op, *x32, g32, cache=cache)
         t_fwd = time.perf_counter() - t0
@@ -430,9 +740,6 @@ def main():
             t_adj = time.perf_counter() - t0
         log(f"oracle forward {t_fwd:.1f} s" + (f", reverse sweep {t_adj:.1f} s" if t_adj else ""))
         own = ref32["owner"] >= 0
-        def rel(a, b):
-            nb = float(np.linalg.norm(b))
-            return float(np.linalg.norm(a - b)) / nb if nb > 0 else None   # e.g. massless tracers
         err["fp32_acc_rel_l2"] = rel(r32["acc"][own], ref32["acc"][own])
         err["fp32_pot_rel_l2"] = rel(r32["pot"][own], ref32["pot"][own])
         if a32 is not None:
@@ -489,6 +796,7 @@ def main():
         "fwd_adjoint_fp32": step_info(a32),
         "fp64": step_info(r64),
         "fwd_adjoint_fp64": step_info(a64),
+        "staged_per_level_fp64": step_info(s64),
         "error_vs_fp64_oracle": err,
         "totals_fp32": {"mass_per_level": list(r32["totals"][:plan.nlevels]),
                         "energy": r32["totals"][plan.nlevels],
@@ -499,9 +807,13 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, args.workload),
                      "avg_launch_ms": dom_launch_ms,
-                     "algorithmic_bytes_per_launch": kb.get(dom, 0.0) / dom_launches,
-                     "algorithmic_bytes_per_step": kb.get(dom, 0.0),
-                     "profiled_ms_per_step": p32["ms"]},
+                     "bytes_basis": ("survey floor (pass B for the z pass)" if floor_b is not None
+                                     else "kernel's algorithmic bytes"),
+                     "algorithmic_bytes_per_launch": ach_b / dom_launches,
+                     "algorithmic_bytes_per_step": ach_b,
+                     "kernel_array_bytes_per_step": kb.get(dom, 0.0),
+                     "profiled_ms_per_step": p32["ms"],
+                     "forward_kernels_ms_per_step": fwd_kernels_ms},
         "kernels_fp32": per_kernel,
         "launch": {"graph": "apm_solve captured once, replayed per step",
                    "autotuned_lines_per_block": {k: v["lines"] for d in tuned.values()
@@ -509,6 +821,42 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
+
+
+def sine_wave_accuracy(Context, Plan, dev):
+    """The sine wave test's accuracy (Sec. 3): per level, the largest deviation over the
+    active cells of a_x and Phi from the continuum solution -4 pi (P / 2 pi)^2
+    sin(2 pi x / P), relative to its amplitude, for P = 1 and 0.2: FP32 and FP64 with
+    the spectral gradient, and FP64 with the two-point one (Sec. 2.2 names both)."""
+    import torch
+    import apm_workloads as W
+    out = {}
+    for P, grad, dt in [(P, g, d) for P in (1.0, 0.2)
+                        for g, d in (("spectral", torch.float32), ("spectral", torch.float64),
+                                     ("fd2", torch.float64))]:
+        w = W.workload_sine_wave(period=P)
+        plan = Plan(w.root_n, w.grids, boundary="periodic", gradient=grad)
+        ctx = Context(plan, 0)
+        k = 2 * np.pi / P
+        amp_a, amp_p = 4 * np.pi / k, 4 * np.pi / k ** 2
+        x, y, z, m = (torch.from_numpy(np.asarray(a, np.float64)).to(dev).to(dt)
+                      for a in (w.x, w.y, w.z, w.m))
+        gas = [ctx.pack_gas(l, w.gas, dt) for l in range(plan.nlevels)]
+        ctx.solve(x, y, z, m, gas)
+        torch.cuda.synchronize()
+        lv = []
+        for l in range(plan.nlevels):
+            F = ctx.solved_field(l, dt)
+            g = plan.level_grids(l)[0]
+            f = ctx.field_view(F, g["index"]).cpu().numpy().astype(np.float64)
+            a0 = [g["lo"][i] - g["fld_lo"][i] for i in range(3)]
+            f = f[a0[2]:a0[2] + g["n"][2], a0[1]:a0[1] + g["n"][1], a0[0]:a0[0] + g["n"][0]]
+            xc = (g["lo"][0] + np.arange(g["n"][0]) + 0.5) * g["dx"]
+            ea = float(np.abs(f[..., 0] - amp_a * np.cos(k * xc)).max() / amp_a)
+            ep = float(np.abs(f[..., 3] + amp_p * np.sin(k * xc)).max() / amp_p)
+            lv.append({"level": l, "max_rel_err_ax": ea, "max_rel_err_phi": ep})
+        out[f"P={P:g}/{grad}/{'f32' if dt == torch.float32 else 'f64'}"] = lv
+    return out
 
 
 if __name__ == "__main__":

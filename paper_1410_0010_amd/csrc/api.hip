@@ -285,13 +285,21 @@ apm_status grad_symbols(apm_ctx c, int level, int M, double dx, const T** out) {
   return APM_OK;
 }
 
-// FP64 octant table (Gf, Gp)/(Mx My Mz) of a grid shape; FP32 copy on request.
+// One kernel for force and potential (the spectral gradient: the potential is taken
+// with Eq. 5's kernel itself); with the two-point gradient the tables hold pairs.
+bool single_kernel(apm_ctx c) { return c->plan.cfg.gradient != APM_GRAD_FD2; }
+int y_lines(apm_ctx c) { return single_kernel(c) ? 3 : 4; }   // y inverse lines per column
+
+// Octant table of a grid shape in the working precision, scaled by 1/(Mx My Mz):
+// (Gf, Gp) pairs, or Gf alone with one kernel.  Generated once as FP64 pairs (cached);
+// the working table is derived from those.
 apm_status kernel_table(apm_ctx c, apm_dtype dt, const GridDesc& g, const void** out) {
   const int Mx = g.M[0], My = g.M[1], Mz = g.M[2];
-  auto k64 = std::make_tuple(8, g.level, Mx, My, Mz);
-  auto k32 = std::make_tuple(4, g.level, Mx, My, Mz);
-  if (dt == APM_F32) {
-    auto it = c->kern.find(k32);
+  const bool single = single_kernel(c);
+  auto k64 = std::make_tuple(8, g.level, Mx, My, Mz);                   // FP64 pairs
+  auto kw = std::make_tuple((dt == APM_F32 ? 4 : 8) + (single ? 1 : 0), g.level, Mx, My, Mz);
+  {
+    auto it = c->kern.find(kw);
     if (it != c->kern.end()) { *out = it->second; return APM_OK; }
   }
   auto it64 = c->kern.find(k64);
@@ -342,13 +350,19 @@ apm_status kernel_table(apm_ctx c, apm_dtype dt, const GridDesc& g, const void**
     }
     c->kern[k64] = t64;
   }
-  if (dt == APM_F64) { *out = t64; return APM_OK; }
-  void* p32 = nullptr;
-  APM_TRY(dev_alloc(c, &p32, sizeof(float2) * oct, "green's function table (fp32)"));
-  c->owned.push_back(p32);
-  HIP_TRY(launch_to_f32((const double*)t64, (float*)p32, 2 * oct, c->stream), "table to fp32");
-  c->kern[k32] = p32;
-  *out = p32;
+  if (dt == APM_F64 && !single) { *out = t64; return APM_OK; }
+  const size_t es = dt == APM_F32 ? 4 : 8;
+  void* pw = nullptr;
+  APM_TRY(dev_alloc(c, &pw, es * (single ? 1 : 2) * oct, "green's function table (working)"));
+  c->owned.push_back(pw);
+  if (!single)
+    HIP_TRY(launch_to_f32((const double*)t64, (float*)pw, 2 * oct, c->stream), "table to fp32");
+  else if (dt == APM_F32)
+    HIP_TRY(launch_table_pick<float>((const double*)t64, (float*)pw, oct, 0, c->stream), "table");
+  else
+    HIP_TRY(launch_table_pick<double>((const double*)t64, (double*)pw, oct, 0, c->stream), "table");
+  c->kern[kw] = pw;
+  *out = pw;
   return APM_OK;
 }
 
@@ -430,6 +444,8 @@ apm_status job_list(apm_ctx c, int pass, int L, int level, int nl, const apm_ctx
     j.z_off = c->z_off[gi];
     j.y_off = c->y_off[gi];
     APM_TRY(kernel_table(c, dt, g, &j.kern));
+    j.kstride = single_kernel(c) ? 1 : 2;
+    j.kpot = single_kernel(c) ? 0 : 1;
     for (int a = 0; a < 3; ++a) {
       const T* d = nullptr;
       APM_TRY(grad_symbols<T>(c, g.level, g.M[a], g.dx, &d));
@@ -489,9 +505,10 @@ apm_status convolve_steps_t(apm_ctx c, int level, const LevelPtrs<T>& lp, std::v
       const ConvJob* jobs = jl->d;
       const int njobs = jl->n;
       const int64_t blocks = jl->blocks;
-      out.push_back([c, pass, L, nl, jobs, njobs, blocks, lp, tw]() -> apm_status {
+      const int nc = y_lines(c);
+      out.push_back([c, pass, L, nl, nc, jobs, njobs, blocks, lp, tw]() -> apm_status {
         HIP_TRY(timed(c, pass_name(pass), [&] {
-                  return launch_pass<T>(pass, L, nl, jobs, njobs, blocks, lp, (C2<T>*)c->spec.p,
+                  return launch_pass<T>(pass, L, nl, nc, jobs, njobs, blocks, lp, (C2<T>*)c->spec.p,
                                         (C2<T>*)c->zbuf.p, (C2<T>*)c->ybuf.p, tw, c->stream);
                 }), pass_name(pass));
         return APM_OK;
@@ -962,15 +979,17 @@ apm_status autotune_t(apm_ctx c, apm_dtype dt, int reps) {
       float best_ms = 1e30f;
       std::ostringstream cand;
       for (int nlc : {d0 / 4, d0 / 2, d0, d0 * 2, d0 * 4}) {
-        if (pass_lds<T>(pass, L, nlc) == 0) continue;
+        if (pass_lds<T>(pass, L, nlc, y_lines(c)) == 0) continue;
         const apm_ctx_s::JobList* jl = nullptr;
         APM_TRY(job_list<T>(c, pass, L, -1, nlc, &jl));
-        HIP_TRY(launch_pass<T>(pass, L, nlc, jl->d, jl->n, jl->blocks, lp, (C2<T>*)c->spec.p,
+        HIP_TRY(launch_pass<T>(pass, L, nlc, y_lines(c), jl->d, jl->n, jl->blocks, lp,
+                               (C2<T>*)c->spec.p,
                                (C2<T>*)c->zbuf.p, (C2<T>*)c->ybuf.p, tw, c->stream),
                 "autotune warm-up");
         HIP_TRY(hipEventRecord(e0, c->stream), "event");
         for (int r = 0; r < reps; ++r)
-          HIP_TRY(launch_pass<T>(pass, L, nlc, jl->d, jl->n, jl->blocks, lp, (C2<T>*)c->spec.p,
+          HIP_TRY(launch_pass<T>(pass, L, nlc, y_lines(c), jl->d, jl->n, jl->blocks, lp,
+                               (C2<T>*)c->spec.p,
                                  (C2<T>*)c->zbuf.p, (C2<T>*)c->ybuf.p, tw, c->stream),
                   "autotune launch");
         HIP_TRY(hipEventRecord(e1, c->stream), "event");

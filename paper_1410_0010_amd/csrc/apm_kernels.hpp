@@ -57,7 +57,11 @@ struct ConvJob {
   int32_t pitch;                   // complex values per row of the spectrum, z and y
                                    // buffers: W = Mx/2 + 1 rounded up to kRowAlign
   int64_t gmf_off, fld_off, spec_off, z_off, y_off;
-  const void* kern;                // octant (Gf, Gp) table
+  const void* kern;                // octant table: kstride values per entry, Gf first
+  int32_t kstride;                 // 2: (Gf, Gp) pairs; 1: Gf alone, the potential's kernel
+                                   // too (spectral gradient): then the z pass writes two
+                                   // arrays and the y inverse pass three lines per column
+  int32_t kpot;                    // offset of the potential's kernel in an entry (1 or 0)
   const void* dsym[3];             // gradient symbols per axis index
   const double* mean;              // periodic plans, subgrids: device scalar, the average
                                    // density subtracted from the GMF; else null
@@ -68,13 +72,17 @@ constexpr int kZConvMaxThreads = 512;     // keeps the FP64 z passes free of spi
 constexpr int kMaxLDS = 163840;           // dynamic LDS per workgroup on gfx950
 hipError_t allow_lds_forward();           // raise every transform kernel's LDS limit
 hipError_t allow_lds_adjoint();
-template <typename T> size_t pass_lds(int pass, int L, int nl);   // 0: not launchable
+// nc: lines per column of the y inverse pass (4, or 3 with a single-kernel table)
+template <typename T> size_t pass_lds(int pass, int L, int nl, int nc = 4);  // 0: not launchable
 template <typename T> int pass_row_stride(int pass, int L, int nl); // LDS line stride
-int pass_threads(int pass, int L, int nl);
+int pass_threads(int pass, int L, int nl, int nc = 4);
 template <typename T>
-hipError_t launch_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, int64_t nblocks,
-                       const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* zbuf, C2<T>* ybuf,
-                       const void* tw, hipStream_t s);
+hipError_t launch_pass(int pass, int L, int nl, int nc, const ConvJob* jobs, int njobs,
+                       int64_t nblocks, const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* zbuf,
+                       C2<T>* ybuf, const void* tw, hipStream_t s);
+// one value of every octant pair (comp 0: Gf) in the working precision
+template <typename T> hipError_t launch_table_pick(const double* pairs, T* out, int64_t n, int comp,
+                                                   hipStream_t s);
 
 // Buffers of the transposed convolution: GMF cotangents out (working precision) and
 // FP64 field-box cotangents in (field layout: 4 per cell, or the Phi one alone for the

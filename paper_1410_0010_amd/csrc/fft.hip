@@ -16,6 +16,10 @@
 //           line: in the x and y inverse passes; along z they are constants)
 //   x_inv   two rows of one component per complex inverse FFT, Hermitian rows ->
 //           real field-box rows, written as 4-vectors per cell (fy*fz rows)
+// With one kernel for force and potential (spectral gradient: Gp = Gf) the potential
+// is the a_x line before its x derivative: the z pass writes two arrays (Gf rho,
+// -i d_z Gf rho), the y inverse pass three lines per column (a_x / Phi, a_y, a_z),
+// and the x inverse pass takes both a_x (with -i d_x) and Phi from the first.
 // Zero planes/rows of the padding are never read or transformed twice: y_fwd reads
 // only gy rows, z_conv only gz planes, and the inverse passes write only the field
 // box.  Unnormalised transforms; 1/(Mx My Mz) is folded into the kernel table.
@@ -193,19 +197,21 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   // multipliers of this column: kx fastest in the table, so lanes read neighbours
   const int kxc = col_ok ? c0 + cb : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
-  // 32-bit offsets from block-uniform bases (an octant table has < 2^31 entries)
+  // 32-bit offsets from block-uniform bases (an octant table has < 2^30 values)
+  const uint32_t ks = (uint32_t)J.kstride;
   const uint32_t ostride = (uint32_t)((My / 2 + 1) * W);
-  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)kyo * W;
+  const gptr<T> gcol = as_global<T>(J.kern) + (int64_t)kyo * W * ks;
   C2<T>* dst = zo + (int64_t)ky * P + c0 + cb;
+  const int nzs = ks == 1 ? 2 : 3;                  // products written
 #pragma unroll 1
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < nzs; ++s) {
     C2<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int kz = w + q * (L / 8);
       const int kzo = kz <= L / 2 ? kz : L - kz;
-      const nvec2<T> gv = gcol[(uint32_t)kzo * ostride + (uint32_t)kxc];
-      const T mul = s == 0 ? gv.x : (s == 1 ? dzs[kz] * gv.x : gv.y);
+      const uint32_t e = ((uint32_t)kzo * ostride + (uint32_t)kxc) * ks;
+      const T mul = s == 0 ? gcol[e] : (s == 1 ? dzs[kz] * gcol[e] : gcol[e + 1]);
       const C2<T> x = xs[q * nt];
       v[q] = s == 1 ? mk<T>(mul * x.y, -mul * x.x)   // -i d_z Gf X
                     : mk<T>(mul * x.x, mul * x.y);
@@ -223,15 +229,16 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 }
 
 // -------------------------------------------------------- y inverse (columns) --
-// Block = (plane j < fz, nl columns): 4 lines per column built from one read of
-// the three z arrays: a_x <- Gf rho (its x derivative follows in the x pass),
-// a_y <- -i d_y(k_y) Gf rho, a_z <- array 1, Phi <- array 2; inverse FFT along y;
-// rows j' < fy written from transform index (off_y + j') mod L into the y buffer
-// (planes c fz + j, fy rows, W columns).  Thread t is worker t / (4 nl) of line
-// (component (t / nl) mod 4, column t mod nl): its column loads and stores go
-// straight to and from the transform's registers (the a_x and a_y lines of a column
-// read the same array 0 elements; the second read hits the cache).
-template <typename T, int L>
+// Block = (plane j < fz, nl columns): NC lines per column built from one read of
+// the z arrays: a_x <- Gf rho (its x derivative follows in the x pass),
+// a_y <- -i d_y(k_y) Gf rho, a_z <- array 1, and with NC = 4 Phi <- array 2 (with
+// NC = 3 the potential is the a_x line itself); inverse FFT along y; rows j' < fy
+// written from transform index (off_y + j') mod L into the y buffer (planes c fz + j,
+// fy rows, W columns).  Thread t is worker t / (NC nl) of line (component
+// (t / nl) mod NC, column t mod nl): its column loads and stores go straight to and
+// from the transform's registers (the a_x and a_y lines of a column read the same
+// array 0 elements; the second read hits the cache).
+template <typename T, int L, int NC>
 __global__ void __launch_bounds__(1024)
 k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
             const C2<T>* __restrict__ zb, C2<T>* __restrict__ yb, const C2<T>* __restrict__ tw) {
@@ -247,7 +254,7 @@ k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int c0 = (int)(blk % nbw) * nl;
   const gptr<T> dys = as_global<T>(J.dsym[1]);
   const int t = threadIdx.x;
-  const int cb = t % nl, c = (t / nl) & 3, w = t / (4 * nl);
+  const int cb = t % nl, c = (t / nl) % NC, w = t / (NC * nl);
   const Twid<T, L> tb(w, tw);
   const bool col_ok = c0 + cb < W;
   const int64_t zs = (int64_t)fz * My * P;             // stride between z arrays
@@ -313,7 +320,9 @@ k_fft_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, const C2<T>* __
   C2<T>* line = lds + b * LS;
   C2<T> v[8];
   if (ra < rows) {
-    const int64_t cs = (int64_t)c * rows * P;         // component stride
+    // with one kernel for force and potential, Phi is the a_x rows without d_x
+    const int src = (c == 3 && J.kstride == 1) ? 0 : c;
+    const int64_t cs = (int64_t)src * rows * P;       // component stride
     const C2<T>* A = ybuf + cs + ra * P;
     const bool hb = rb < rows;
     const C2<T>* B = ybuf + cs + (hb ? rb : ra) * P;
@@ -393,7 +402,9 @@ template <typename T> int default_lines(int pass, int L) {
   return nl;
 }
 
-static int pass_lines_per_block(int pass, int nl) {
+static int pass_lines_per_block(int pass, int nl, int nc) {
+  // the y inverse pass has nc lines per column; its transpose always four
+  if (pass == PASS_Y_INV) return nc * nl;
   return mirror_pass(pass) == PASS_Y_INV ? 4 * nl : nl;
 }
 
@@ -404,12 +415,14 @@ template <typename T> static int pass_ls(int pass, int L, int nl) {
 }
 
 template <typename T> int pass_row_stride(int pass, int L, int nl) { return pass_ls<T>(pass, L, nl); }
-int pass_threads(int pass, int L, int nl) { return pass_lines_per_block(pass, nl) * (L / 8); }
+int pass_threads(int pass, int L, int nl, int nc) {
+  return pass_lines_per_block(pass, nl, nc) * (L / 8);
+}
 
-template <typename T> size_t pass_lds(int pass, int L, int nl) {
+template <typename T> size_t pass_lds(int pass, int L, int nl, int nc) {
+  if (nl < 1 || (nc != 3 && nc != 4)) return 0;
+  const int lines = pass_lines_per_block(pass, nl, nc);
   pass = mirror_pass(pass);
-  if (nl < 1) return 0;
-  const int lines = pass_lines_per_block(pass, nl);
   // the z pass also parks each thread's eight forward-transform values (nl L values)
   const size_t bytes = ((size_t)lines * pass_ls<T>(pass, L, nl) + (pass == PASS_Z_CONV ? (size_t)nl * L : 0)) *
                        sizeof(C2<T>);
@@ -432,14 +445,14 @@ template <typename T> size_t pass_lds(int pass, int L, int nl) {
   }
 
 template <typename T>
-hipError_t launch_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, int64_t nblocks,
-                       const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* zbuf, C2<T>* ybuf,
-                       const void* tw, hipStream_t s) {
+hipError_t launch_pass(int pass, int L, int nl, int nc, const ConvJob* jobs, int njobs,
+                       int64_t nblocks, const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* zbuf,
+                       C2<T>* ybuf, const void* tw, hipStream_t s) {
   if (njobs == 0 || nblocks == 0) return hipSuccess;
-  const size_t shm = pass_lds<T>(pass, L, nl);
+  const size_t shm = pass_lds<T>(pass, L, nl, nc);
   if (shm == 0) return hipErrorInvalidConfiguration;
   const int ls = pass_ls<T>(pass, L, nl);
-  const dim3 grid((unsigned)nblocks), block((unsigned)(pass_lines_per_block(pass, nl) * (L / 8)));
+  const dim3 grid((unsigned)nblocks), block((unsigned)(pass_lines_per_block(pass, nl, nc) * (L / 8)));
   const C2<T>* twc = (const C2<T>*)tw;
   APM_FFT_DISPATCH(L, {
     switch (pass) {
@@ -454,8 +467,12 @@ hipError_t launch_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, 
                            (const C2<T>*)spec, zbuf, twc);
         break;
       case PASS_Y_INV:
-        hipLaunchKernelGGL((k_fft_y_inv<T, LL>), grid, block, shm, s, jobs, njobs, nl, ls,
-                           (const C2<T>*)zbuf, ybuf, twc);
+        if (nc == 3)
+          hipLaunchKernelGGL((k_fft_y_inv<T, LL, 3>), grid, block, shm, s, jobs, njobs, nl, ls,
+                             (const C2<T>*)zbuf, ybuf, twc);
+        else
+          hipLaunchKernelGGL((k_fft_y_inv<T, LL, 4>), grid, block, shm, s, jobs, njobs, nl, ls,
+                             (const C2<T>*)zbuf, ybuf, twc);
         break;
       case PASS_X_INV:
         hipLaunchKernelGGL((k_fft_x_inv<T, LL>), grid, block, shm, s, jobs, njobs, nl,
@@ -470,16 +487,16 @@ hipError_t launch_pass(int pass, int L, int nl, const ConvJob* jobs, int njobs, 
 
 template int default_lines<float>(int, int);
 template int default_lines<double>(int, int);
-template size_t pass_lds<float>(int, int, int);
-template size_t pass_lds<double>(int, int, int);
+template size_t pass_lds<float>(int, int, int, int);
+template size_t pass_lds<double>(int, int, int, int);
 template int pass_row_stride<float>(int, int, int);
 template int pass_row_stride<double>(int, int, int);
 // Every transform kernel may use up to kMaxLDS bytes of dynamic LDS (the gfx950 limit
 // per workgroup); set once per process, before any launch or graph capture.
 template <typename T, int L> static hipError_t allow_lds_fwd() {
   const void* f[] = {(const void*)&k_fft_x_fwd<T, L>, (const void*)&k_fft_y_fwd<T, L>,
-                     (const void*)&k_fft_z_conv<T, L>, (const void*)&k_fft_y_inv<T, L>,
-                     (const void*)&k_fft_x_inv<T, L>};
+                     (const void*)&k_fft_z_conv<T, L>, (const void*)&k_fft_y_inv<T, L, 3>,
+                     (const void*)&k_fft_y_inv<T, L, 4>, (const void*)&k_fft_x_inv<T, L>};
   for (const void* k : f) {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLDS);
     if (e != hipSuccess) return e;
@@ -498,11 +515,29 @@ hipError_t allow_lds_forward() {
   return e;
 }
 
-template hipError_t launch_pass<float>(int, int, int, const ConvJob*, int, int64_t,
+template hipError_t launch_pass<float>(int, int, int, int, const ConvJob*, int, int64_t,
                                        const LevelPtrs<float>&, C2<float>*, C2<float>*,
                                        C2<float>*, const void*, hipStream_t);
-template hipError_t launch_pass<double>(int, int, int, const ConvJob*, int, int64_t,
+template hipError_t launch_pass<double>(int, int, int, int, const ConvJob*, int, int64_t,
                                         const LevelPtrs<double>&, C2<double>*, C2<double>*,
                                         C2<double>*, const void*, hipStream_t);
+
+// ---------------------------------------------------------- kernel-table copies --
+template <typename T>
+__global__ void k_table_pick(const double* __restrict__ pairs, T* __restrict__ out, int64_t n,
+                             int comp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (T)pairs[2 * i + comp];
+}
+
+template <typename T>
+hipError_t launch_table_pick(const double* pairs, T* out, int64_t n, int comp, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_table_pick<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, pairs, out, n, comp);
+  return hipGetLastError();
+}
+template hipError_t launch_table_pick<float>(const double*, float*, int64_t, int, hipStream_t);
+template hipError_t launch_table_pick<double>(const double*, double*, int64_t, int, hipStream_t);
 
 }  // namespace apm

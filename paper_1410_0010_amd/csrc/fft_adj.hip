@@ -221,8 +221,9 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   // multipliers of this column: kx fastest in the table, so lanes read neighbours;
   // each product's set is read where it is used (holding all three for the whole
   // kernel spills FP64 registers)
-  const int64_t ostride = (int64_t)(My / 2 + 1) * W;
-  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)kyo * W + kxc;
+  const int64_t ks = J.kstride, kp = J.kpot;          // table values per entry, Gp's offset
+  const int64_t ostride = (int64_t)(My / 2 + 1) * W * ks;
+  const gptr<T> gcol = as_global<T>(J.kern) + ((int64_t)kyo * W + kxc) * ks;
   // S accumulates in LDS, each thread's values in its own slots (no barrier: the same
   // thread reads them back), so the forward transforms do not hold it in registers
   C2<T>* ss = lds + (int64_t)nl * ls + t;
@@ -243,11 +244,14 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
     for (int q = 0; q < 8; ++q) {
       const int kz = w + q * (L / 8);
       const int kzo = kz <= L / 2 ? kz : L - kz;
-      const nvec2<T> gv = gcol[kzo * ostride];
+      const T gf = gcol[kzo * ostride];
       const C2<T> X = v[q];
-      if (s == 0) ss[q * nt] = mk<T>(gv.x * X.x, gv.x * X.y);
-      else if (s == 1) ss[q * nt] = cadd(ss[q * nt], mul_id<T>(gv.x * dzs[kz], X));
-      else ss[q * nt] = cadd(ss[q * nt], mk<T>(gv.y * X.x, gv.y * X.y));
+      if (s == 0) ss[q * nt] = mk<T>(gf * X.x, gf * X.y);
+      else if (s == 1) ss[q * nt] = cadd(ss[q * nt], mul_id<T>(gf * dzs[kz], X));
+      else {
+        const T gp = gcol[kzo * ostride + kp];
+        ss[q * nt] = cadd(ss[q * nt], mk<T>(gp * X.x, gp * X.y));
+      }
     }
   }
   C2<T> S[8];
@@ -483,8 +487,9 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int kyo = ky <= My / 2 ? ky : My - ky;
   // 24-bit multiplies: jz < 2^11, My P < 2^24, every product < 2^31
   const uint32_t ps32 = (uint32_t)pstride;
-  const int64_t ostride = (int64_t)(My / 2 + 1) * W;
-  const gptr<nvec2<T>> gcol = as_global<nvec2<T>>(J.kern) + (int64_t)kyo * W + kxc;
+  const int64_t ks = J.kstride;                        // table values per entry
+  const int64_t ostride = (int64_t)(My / 2 + 1) * W * ks;
+  const gptr<T> gcol = as_global<T>(J.kern) + ((int64_t)kyo * W + kxc) * ks + J.kpot;
   C2<T> v[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
@@ -497,7 +502,7 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   for (int q = 0; q < 8; ++q) {
     const int kz = w + q * (L / 8);
     const int kzo = kz <= L / 2 ? kz : L - kz;
-    gp[q] = gcol[kzo * ostride].y;
+    gp[q] = gcol[kzo * ostride];
   }
   fft_regs<T, L, false>(line, w, v, tb);
 #pragma unroll
