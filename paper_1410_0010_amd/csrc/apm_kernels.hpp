@@ -44,6 +44,18 @@ inline int mirror_pass(int pass) {
   return pass;
 }
 
+// Spectrum and z-buffer rows are stored in tiles of kYT rows along ky: row (plane p,
+// ky) of a region of np planes sits kYT ((ky / kYT) np + p) + ky % kYT rows from the
+// region's start.  A column along the planes (the z pass) then steps kYT rows, so it
+// crosses a few memory pages instead of one per plane (a 1024-plane column of a
+// plane-major 1024^2 spectrum touched over a thousand pages per block, and the
+// address translation, not HBM, set the z pass's pace); a line along ky steps one row
+// within a tile and np kYT rows between tiles.  Every FFT length is a multiple of kYT.
+constexpr int kYT = 16;
+__host__ __device__ __forceinline__ int64_t tile_row(int p, int ky, int np) {
+  return ((int64_t)(ky / kYT) * np + p) * kYT + (ky % kYT);
+}
+
 // One grid in one pass: GMF (dims g) zero-padded into FFT box M, outputs on the field
 // box (dims f) whose first cell sits at transform index off (cyclic).  Offsets are
 // in elements of the level GMF buffer, the level field buffer (cells) and the
@@ -72,7 +84,8 @@ constexpr int kZConvMaxThreads = 512;     // keeps the FP64 z passes free of spi
 constexpr int kMaxLDS = 163840;           // dynamic LDS per workgroup on gfx950
 hipError_t allow_lds_forward();           // raise every transform kernel's LDS limit
 hipError_t allow_lds_adjoint();
-// nc: lines per column of the y inverse pass (4, or 3 with a single-kernel table)
+// nc: lines per column of the y inverse pass: 3 with single-kernel tables (kstride 1,
+// the z pass then writes two arrays), else 4
 template <typename T> size_t pass_lds(int pass, int L, int nl, int nc = 4);  // 0: not launchable
 template <typename T> int pass_row_stride(int pass, int L, int nl); // LDS line stride
 int pass_threads(int pass, int L, int nl, int nc = 4);

@@ -29,6 +29,8 @@
 // job table lists the grids with the index of their first block; a block finds its
 // grid by binary search.  Lines per block (nl) is a launch parameter, chosen by the
 // autotuner per (pass, L, precision).
+#include <type_traits>
+
 #include "apm_kernels.hpp"
 #include "device_common.hpp"
 
@@ -94,8 +96,8 @@ k_fft_x_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, LevelPtrs<T> lp
   fft_line_rin<T, L, false>(line, w, v, tb);
   if (ra < rows) {
     const int64_t za = ra / gy, ya = ra % gy, zb = rb / gy, yb = rb % gy;
-    C2<T>* outa = spec + (za * My + ya) * P;
-    C2<T>* outb = spec + (zb * My + yb) * P;
+    C2<T>* outa = spec + tile_row((int)za, (int)ya, gz) * P;
+    C2<T>* outb = spec + tile_row((int)zb, (int)yb, gz) * P;
     const T h = (T)0.5;
     for (int k = w; k <= L / 2; k += L / 8) {
       C2<T> z = line[swz<L>(k)], m = line[swz<L>((L - k) & (L - 1))];
@@ -118,11 +120,11 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
   const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
   const ConvJob& J = jobs[find_job(jobs, njobs, gb)];
   const int64_t blk = gb - J.blk0;
-  const int W = J.M[0] / 2 + 1, My = J.M[1], gy = J.g[1], P = J.pitch;
+  const int W = J.M[0] / 2 + 1, gy = J.g[1], gz = J.g[2], P = J.pitch;
   const int nbw = (W + nl - 1) / nl;
   const int64_t p = blk / nbw;
   const int c0 = (int)(blk % nbw) * nl;
-  C2<T>* base = specb + J.spec_off + p * ((int64_t)My * P) + c0;
+  C2<T>* base = specb + J.spec_off + c0;             // rows (p, r) at tile_row(p, r, gz)
   const int t = threadIdx.x;
   const int cb = t % nl, w = t / nl;
   const Twid<T, L> tb(w, tw);
@@ -131,12 +133,12 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int r = w + q * (L / 8);
-    v[q] = (r < gy && col_ok) ? base[(int64_t)r * P + cb] : mk<T>(0, 0);
+    v[q] = (r < gy && col_ok) ? base[tile_row((int)p, r, gz) * P + cb] : mk<T>(0, 0);
   }
   fft_regs<T, L, false>(lds + cb * ls, w, v, tb);
   if (col_ok) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) base[(int64_t)(w + q * (L / 8)) * P + cb] = v[q];
+    for (int q = 0; q < 8; ++q) base[tile_row((int)p, w + q * (L / 8), gz) * P + cb] = v[q];
   }
 }
 
@@ -152,7 +154,9 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
 // and stores are coalesced across lanes and go straight to and from the registers
 // the transforms start and end in (only the middle Stockham stages use LDS).
 
-template <typename T, int L>
+// KS: kernel-table values per octant entry (2: (Gf, Gp) pairs, 1: Gf alone, whose
+// potential product is then array 0 itself and is not written).
+template <typename T, int L, int KS>
 __global__ void __launch_bounds__(kZConvMaxThreads)
 k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
              const C2<T>* __restrict__ specb, C2<T>* __restrict__ zb,
@@ -170,7 +174,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const C2<T>* __restrict__ spec = specb + J.spec_off;
   C2<T>* __restrict__ zo = zb + J.z_off;
   const gptr<T> dzs = as_global<T>(J.dsym[2]);
-  const int64_t pstride = (int64_t)My * P;
+  const int64_t pstride = (int64_t)kYT * P;            // next plane, same ky (tiled rows)
   const int64_t qstride = (int64_t)(L / 8) * pstride;   // uniform: q steps by a scalar
   const int t = threadIdx.x;
   const int cb = t % nl, w = t / nl;
@@ -179,7 +183,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   C2<T>* line = lds + cb * ls;
   C2<T> X[8];
   {
-    const C2<T>* src = spec + (int64_t)ky * P + c0 + cb + w * pstride;
+    const C2<T>* src = spec + tile_row(0, ky, gz) * P + c0 + cb + w * pstride;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int z = w + q * (L / 8);
@@ -197,21 +201,24 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   // multipliers of this column: kx fastest in the table, so lanes read neighbours
   const int kxc = col_ok ? c0 + cb : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
-  // 32-bit offsets from block-uniform bases (an octant table has < 2^30 values)
-  const uint32_t ks = (uint32_t)J.kstride;
+  // 32-bit offsets from block-uniform bases (an octant table has < 2^31 entries)
+  using TV = typename std::conditional<KS == 2, nvec2<T>, T>::type;
   const uint32_t ostride = (uint32_t)((My / 2 + 1) * W);
-  const gptr<T> gcol = as_global<T>(J.kern) + (int64_t)kyo * W * ks;
-  C2<T>* dst = zo + (int64_t)ky * P + c0 + cb;
-  const int nzs = ks == 1 ? 2 : 3;                  // products written
+  const gptr<TV> gcol = as_global<TV>(J.kern) + (int64_t)kyo * W;
+  const int64_t zas = (int64_t)fz * My * P;            // stride between z arrays
+  C2<T>* dst = zo + tile_row(0, ky, fz) * P + c0 + cb;
+  constexpr int kProducts = KS == 1 ? 2 : 3;        // arrays written
 #pragma unroll 1
-  for (int s = 0; s < nzs; ++s) {
+  for (int s = 0; s < kProducts; ++s) {
     C2<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int kz = w + q * (L / 8);
       const int kzo = kz <= L / 2 ? kz : L - kz;
-      const uint32_t e = ((uint32_t)kzo * ostride + (uint32_t)kxc) * ks;
-      const T mul = s == 0 ? gcol[e] : (s == 1 ? dzs[kz] * gcol[e] : gcol[e + 1]);
+      const TV gv = gcol[(uint32_t)kzo * ostride + (uint32_t)kxc];
+      T mul;
+      if constexpr (KS == 2) mul = s == 0 ? gv.x : (s == 1 ? dzs[kz] * gv.x : gv.y);
+      else mul = s == 0 ? gv : dzs[kz] * gv;
       const C2<T> x = xs[q * nt];
       v[q] = s == 1 ? mk<T>(mul * x.y, -mul * x.x)   // -i d_z Gf X
                     : mk<T>(mul * x.x, mul * x.y);
@@ -222,7 +229,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int j = (w + q * (L / 8) - oz) & (L - 1);  // field plane of element w + q L/8
-        if (j < fz) dst[((int64_t)s * fz + j) * pstride] = v[q];
+        if (j < fz) dst[s * zas + j * pstride] = v[q];
       }
     }
   }
@@ -258,12 +265,12 @@ k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const Twid<T, L> tb(w, tw);
   const bool col_ok = c0 + cb < W;
   const int64_t zs = (int64_t)fz * My * P;             // stride between z arrays
-  const C2<T>* zin = zb + J.z_off + (c == 0 ? 0 : c - 1) * zs + (int64_t)j * My * P + c0 + cb;
+  const C2<T>* zin = zb + J.z_off + (c == 0 ? 0 : c - 1) * zs + c0 + cb;
   C2<T> v[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int r = w + q * (L / 8);
-    v[q] = col_ok ? zin[(int64_t)r * P] : mk<T>(0, 0);
+    v[q] = col_ok ? zin[tile_row(j, r, fz) * P] : mk<T>(0, 0);
   }
   if (c == 1) {                                      // -i d_y Gf rho
 #pragma unroll
@@ -462,9 +469,13 @@ hipError_t launch_pass(int pass, int L, int nl, int nc, const ConvJob* jobs, int
       case PASS_Y_FWD:
         hipLaunchKernelGGL((k_fft_y_fwd<T, LL>), grid, block, shm, s, jobs, njobs, nl, ls, spec, twc);
         break;
-      case PASS_Z_CONV:
-        hipLaunchKernelGGL((k_fft_z_conv<T, LL>), grid, block, shm, s, jobs, njobs, nl, ls,
-                           (const C2<T>*)spec, zbuf, twc);
+      case PASS_Z_CONV:                    // nc == 3: single-kernel tables
+        if (nc == 3)
+          hipLaunchKernelGGL((k_fft_z_conv<T, LL, 1>), grid, block, shm, s, jobs, njobs, nl, ls,
+                             (const C2<T>*)spec, zbuf, twc);
+        else
+          hipLaunchKernelGGL((k_fft_z_conv<T, LL, 2>), grid, block, shm, s, jobs, njobs, nl, ls,
+                             (const C2<T>*)spec, zbuf, twc);
         break;
       case PASS_Y_INV:
         if (nc == 3)
@@ -495,7 +506,8 @@ template int pass_row_stride<double>(int, int, int);
 // per workgroup); set once per process, before any launch or graph capture.
 template <typename T, int L> static hipError_t allow_lds_fwd() {
   const void* f[] = {(const void*)&k_fft_x_fwd<T, L>, (const void*)&k_fft_y_fwd<T, L>,
-                     (const void*)&k_fft_z_conv<T, L>, (const void*)&k_fft_y_inv<T, L, 3>,
+                     (const void*)&k_fft_z_conv<T, L, 1>, (const void*)&k_fft_z_conv<T, L, 2>,
+                     (const void*)&k_fft_y_inv<T, L, 3>,
                      (const void*)&k_fft_y_inv<T, L, 4>, (const void*)&k_fft_x_inv<T, L>};
   for (const void* k : f) {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLDS);

@@ -143,7 +143,7 @@ k_adj_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const gptr<T> dys = as_global<T>(J.dsym[1]);
   const C2<T>* yin = yb + J.y_off + (int64_t)j * fy * P + c0;
   const int64_t ys = (int64_t)fz * fy * P;
-  C2<T>* zout = zb + J.z_off + (int64_t)j * My * P + c0;
+  C2<T>* zout = zb + J.z_off + c0;                   // rows (j, k) at tile_row(j, k, fz)
   const int64_t zs = (int64_t)fz * My * P;
   const int t = threadIdx.x;
   const Twid<T, L> tb(t % (L / 8), tw);   // line worker t mod L/8
@@ -177,9 +177,10 @@ k_adj_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       const T d = dys[k];
       const C2<T> X0 = lds[(0 * nl + cb) * ls + ks], X1 = lds[(1 * nl + cb) * ls + ks];
       const C2<T> U = cadd(X0, mul_id<T>(d, X1));
-      zout[(int64_t)k * P + cb] = U;
-      zout[zs + (int64_t)k * P + cb] = lds[(2 * nl + cb) * ls + ks];
-      zout[2 * zs + (int64_t)k * P + cb] = lds[(3 * nl + cb) * ls + ks];
+      const int64_t o = tile_row(j, k, fz) * P + cb;
+      zout[o] = U;
+      zout[zs + o] = lds[(2 * nl + cb) * ls + ks];
+      zout[2 * zs + o] = lds[(3 * nl + cb) * ls + ks];
     }
   }
 }
@@ -204,10 +205,10 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int nbw = (W + nl - 1) / nl;
   const int ky = (int)(blk / nbw);
   const int c0 = (int)(blk % nbw) * nl;
-  const C2<T>* zin = zb + J.z_off + (int64_t)ky * P + c0;
-  const int64_t pstride = (int64_t)My * P;
-  const int64_t zs = (int64_t)fz * pstride;
-  C2<T>* spec = specb + J.spec_off + (int64_t)ky * P + c0;
+  const C2<T>* zin = zb + J.z_off + tile_row(0, ky, fz) * P + c0;
+  const int64_t pstride = (int64_t)kYT * P;            // next plane, same ky (tiled rows)
+  const int64_t zs = (int64_t)fz * My * P;
+  C2<T>* spec = specb + J.spec_off + tile_row(0, ky, gz) * P + c0;
   const gptr<T> dzs = as_global<T>(J.dsym[2]);
   const int t = threadIdx.x;
   const int cb = t % nl, w = t / nl;
@@ -216,7 +217,7 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   C2<T>* line = lds + cb * ls;
   const int kxc = col_ok ? c0 + cb : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
-  // 24-bit multiplies: jz < 2^11, My P < 2^24, every product < 2^31
+  // 24-bit multiplies: jz < 2^11, kYT P < 2^24, every product < 2^31
   const uint32_t ps32 = (uint32_t)pstride;
   // multipliers of this column: kx fastest in the table, so lanes read neighbours;
   // each product's set is read where it is used (holding all three for the whole
@@ -282,11 +283,11 @@ k_adj_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
   const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
   const ConvJob& J = jobs[find_job_a(jobs, njobs, gb)];
   const int64_t blk = gb - J.blk0;
-  const int W = J.M[0] / 2 + 1, My = J.M[1], gy = J.g[1], P = J.pitch;
+  const int W = J.M[0] / 2 + 1, gy = J.g[1], gz = J.g[2], P = J.pitch;
   const int nbw = (W + nl - 1) / nl;
   const int64_t p = blk / nbw;
   const int c0 = (int)(blk % nbw) * nl;
-  C2<T>* base = specb + J.spec_off + p * ((int64_t)My * P) + c0;
+  C2<T>* base = specb + J.spec_off + c0;             // rows (p, r) at tile_row(p, r, gz)
   const int t = threadIdx.x;
   const int cb = t % nl, w = t / nl;
   const Twid<T, L> tb(w, tw);
@@ -295,14 +296,14 @@ k_adj_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int r = w + q * (L / 8);
-    v[q] = col_ok ? base[(int64_t)r * P + cb] : mk<T>(0, 0);
+    v[q] = col_ok ? base[tile_row((int)p, r, gz) * P + cb] : mk<T>(0, 0);
   }
   fft_regs<T, L, true>(lds + cb * ls, w, v, tb);
   if (col_ok) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int r = w + q * (L / 8);
-      if (r < gy) base[(int64_t)r * P + cb] = v[q];
+      if (r < gy) base[tile_row((int)p, r, gz) * P + cb] = v[q];
     }
   }
 }
@@ -333,8 +334,8 @@ k_adj_x_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, AdjPtrs<T> ap,
   if (ra < rows) {
     const bool hb = rb < rows;
     const int64_t za = ra / gy, ya = ra % gy, zb = hb ? rb / gy : za, yb = hb ? rb % gy : ya;
-    const C2<T>* A = spec + (za * My + ya) * P;
-    const C2<T>* B = spec + (zb * My + yb) * P;
+    const C2<T>* A = spec + tile_row((int)za, (int)ya, gz) * P;
+    const C2<T>* B = spec + tile_row((int)zb, (int)yb, gz) * P;
     C2<T> av[8], bv[8];                              // all loads first
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -437,12 +438,12 @@ k_adjp_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const ConvJob& J = jobs[find_job_a(jobs, njobs, gb)];
   const int64_t blk = gb - J.blk0;
   const int W = J.M[0] / 2 + 1, My = J.M[1], P = J.pitch;
-  const int fy = J.f[1], oy = J.off[1];
+  const int fy = J.f[1], fz = J.f[2], oy = J.off[1];
   const int nbw = (W + nl - 1) / nl;
   const int j = (int)(blk / nbw);
   const int c0 = (int)(blk % nbw) * nl;
   const C2<T>* yin = yb + J.y_off + (int64_t)j * fy * P + c0;
-  C2<T>* zout = zb + J.z_off + (int64_t)j * My * P + c0;
+  C2<T>* zout = zb + J.z_off + c0;                   // rows (j, k) at tile_row(j, k, fz)
   const int t = threadIdx.x;
   const int cb = t % nl, w = t / nl;
   const Twid<T, L> tb(w, tw);
@@ -457,7 +458,7 @@ k_adjp_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   fft_regs<T, L, false>(lds + cb * ls, w, v, tb);
   if (col_ok) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) zout[(int64_t)(w + q * (L / 8)) * P + cb] = v[q];
+    for (int q = 0; q < 8; ++q) zout[tile_row(j, w + q * (L / 8), fz) * P + cb] = v[q];
   }
 }
 
@@ -475,9 +476,9 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int nbw = (W + nl - 1) / nl;
   const int ky = (int)(blk / nbw);
   const int c0 = (int)(blk % nbw) * nl;
-  const C2<T>* zin = zb + J.z_off + (int64_t)ky * P + c0;
-  const int64_t pstride = (int64_t)My * P;
-  C2<T>* spec = specb + J.spec_off + (int64_t)ky * P + c0;
+  const C2<T>* zin = zb + J.z_off + tile_row(0, ky, fz) * P + c0;
+  const int64_t pstride = (int64_t)kYT * P;            // next plane, same ky (tiled rows)
+  C2<T>* spec = specb + J.spec_off + tile_row(0, ky, gz) * P + c0;
   const int t = threadIdx.x;
   const int cb = t % nl, w = t / nl;
   const Twid<T, L> tb(w, tw);
@@ -485,7 +486,7 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   C2<T>* line = lds + cb * ls;
   const int kxc = col_ok ? c0 + cb : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
-  // 24-bit multiplies: jz < 2^11, My P < 2^24, every product < 2^31
+  // 24-bit multiplies: jz < 2^11, kYT P < 2^24, every product < 2^31
   const uint32_t ps32 = (uint32_t)pstride;
   const int64_t ks = J.kstride;                        // table values per entry
   const int64_t ostride = (int64_t)(My / 2 + 1) * W * ks;
