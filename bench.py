@@ -147,7 +147,7 @@ def kernel_bytes(plan, npart, npart_level, esize, root_gas=False, pot_only_adjoi
               (min(g["gmf_lo"][a] for g in gs) - 1) for a in range(3)]
         ntiles = int(np.prod([(k + 7) // 8 for k in kn]))
         rep = 1
-        while rep < 16 and ntiles * rep * 2 <= 1 << 18:
+        while rep < 16 and ntiles * rep * 2 <= 1 << 23:
             rep *= 2
         b["bin_clear"] += (ntiles * rep + 1) * 4 + int(np.prod(kn)) * 8
         b["bin_scan"] += 2 * ntiles * rep * 4 + ntiles * 8   # counters in and out, items

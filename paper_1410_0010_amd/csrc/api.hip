@@ -607,11 +607,12 @@ apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y
       tn[a] = (L.key_n[a] + kTile - 1) / kTile;
       ntiles *= tn[a];
     }
-    // counter replicas per tile (blocks pick one by index): up to kMaxRep, about 2^17
-    // counters in all; the many blocks of a dense core then spread their one atomic
-    // per (block, tile) over that many addresses
+    // counter replicas per tile (blocks pick one by index): kMaxRep while the counters
+    // stay under 2^23 (32 MB); the many blocks of a dense core then spread their one
+    // atomic per (block, tile) over that many addresses (with one counter per tile the
+    // 8192 blocks of a 2^24-particle Plummer core queued on the same few addresses)
     int32_t rep = 1;
-    while (rep < kMaxRep && ntiles * rep * 2 <= ((int64_t)1 << 18)) rep *= 2;
+    while (rep < kMaxRep && ntiles * rep * 2 <= ((int64_t)1 << 23)) rep *= 2;
     const int64_t ncount = ntiles * rep + 1;
     APM_TRY(ensure(c, B.count, (size_t)ncount * 4, "tile counts"));
     APM_TRY(ensure(c, B.items, (size_t)(ntiles + 1) * 4, "tile work items"));
