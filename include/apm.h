@@ -89,6 +89,11 @@ typedef struct {
   int32_t gradient;         /* apm_gradient [APM_GRAD_SPECTRAL]                   */
   int64_t workspace_limit;  /* bytes of device workspace allowed, 0 = no limit    */
   int32_t boundary;         /* apm_boundary of the root [APM_BC_ISOLATED]         */
+  int32_t strict;           /* [0] 1: apm_deposit and apm_solve return APM_ERR_RANGE
+                               (after writing their outputs, and synchronising) when
+                               a particle has a coordinate outside [0,1) or NaN;
+                               0: such particles are left out silently (see
+                               apm_dropped)                                        */
 } apm_config;
 
 /* One grid of the static hierarchy.  Grid 0 must be the root: level 0, parent
@@ -251,6 +256,15 @@ apm_status apm_totals(apm_ctx ctx, apm_dtype dtype, const void* const* gmf, cons
 apm_status apm_totals_noalloc(apm_ctx ctx, apm_dtype dtype, const void* const* gmf,
                               const void* m, const int32_t* owner, int64_t npart, const void* ax,
                               const void* ay, const void* az, const void* pot, double* out_dev);
+
+/* The particles a deposit leaves out: those with a coordinate outside [0,1) or NaN
+ * (Sec. 2 deposits the particles that lie on the grids; they get no acceleration).
+ * Their number into *count and their total mass (FP64) into *mass, from npart
+ * positions and masses (device arrays of dtype).  The deposited mass itself is the
+ * per-level sum of apm_totals / apm_solve_totals.  Synchronises.  Errors:
+ * APM_ERR_INVALID for NULL arguments, APM_ERR_RANGE for npart < 0. */
+apm_status apm_dropped(apm_ctx ctx, apm_dtype dtype, const void* x, const void* y, const void* z,
+                       const void* m, int64_t npart, int64_t* count, double* mass);
 
 /* The whole forward solve in one call: owner, deposit, solve, composition and
  * interpolation of every level, in the paper's order, into library-owned level

@@ -34,7 +34,7 @@ class apm_config(ctypes.Structure):
                 ("a_cells", ctypes.c_double), ("pad_factor", ctypes.c_double),
                 ("ghost", ctypes.c_int32), ("brillouin", ctypes.c_int32),
                 ("gradient", ctypes.c_int32), ("workspace_limit", ctypes.c_int64),
-                ("boundary", ctypes.c_int32)]
+                ("boundary", ctypes.c_int32), ("strict", ctypes.c_int32)]
 
 
 class apm_grid(ctypes.Structure):
@@ -84,6 +84,8 @@ SIGNATURES = {
     "apm_interp": (_st, [_vp, _st, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "apm_totals": (_st, [_vp, _st, ctypes.POINTER(_vp), _vp, _vp, _i64, _vp, _vp, _vp, _vp,
                          ctypes.POINTER(ctypes.c_double)]),
+    "apm_dropped": (_st, [_vp, _st, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64),
+                          ctypes.POINTER(ctypes.c_double)]),
     "apm_totals_noalloc": (_st, [_vp, _st, ctypes.POINTER(_vp), _vp, _vp, _i64, _vp, _vp, _vp,
                                  _vp, _vp]),
     "apm_solve": (_st, [_vp, _st, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_vp), _vp, _vp, _vp,

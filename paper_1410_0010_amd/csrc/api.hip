@@ -1353,7 +1353,60 @@ apm_status totals_any(apm_ctx c, apm_dtype dt, const void* const* gmf, const voi
                           (const double*)ay, (const double*)az, (const double*)pot, gas, out_dev);
 }
 
+// Number and mass of the particles outside the box or NaN (stream-ordered, then read).
+template <typename T>
+apm_status dropped_t(apm_ctx c, const T* x, const T* y, const T* z, const T* m, int64_t n,
+                     int64_t* count, double* mass) {
+  const int nl = (int)c->plan.levels.size();
+  APM_TRY(ensure(c, c->totals, (size_t)(kTotPart + (kMaxLevels + 4) * kMaxParts) * 8, "totals"));
+  (void)nl;
+  double* d = (double*)c->totals.p;
+  double h[2] = {0.0, 0.0};
+  if (n > 0) {
+    HIP_TRY(launch_fill_f64(d, 2, 0.0, c->stream), "dropped clear");
+    HIP_TRY(launch_dropped<T>(x, y, z, m, n, d + kTotPart, d, c->stream), "dropped particles");
+    HIP_TRY(hipMemcpyAsync(h, d, 16, hipMemcpyDeviceToHost, c->stream), "dropped copy");
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream), "dropped sync");
+  if (count) *count = (int64_t)h[0];
+  if (mass) *mass = h[1];
+  return APM_OK;
+}
+
+apm_status dropped_any(apm_ctx c, apm_dtype dt, const void* x, const void* y, const void* z,
+                       const void* m, int64_t n, int64_t* count, double* mass) {
+  if (dt == APM_F32)
+    return dropped_t<float>(c, (const float*)x, (const float*)y, (const float*)z, (const float*)m,
+                            n, count, mass);
+  return dropped_t<double>(c, (const double*)x, (const double*)y, (const double*)z,
+                           (const double*)m, n, count, mass);
+}
+
+// Strict mode: APM_ERR_RANGE (after the call's work) if any particle was left out.
+apm_status strict_check(apm_ctx c, apm_dtype dt, const void* x, const void* y, const void* z,
+                        const void* m, int64_t n, const char* where) {
+  if (!c->plan.cfg.strict || n <= 0) return APM_OK;
+  int64_t cnt = 0;
+  double mass = 0.0;
+  APM_TRY(dropped_any(c, dt, x, y, z, m, n, &cnt, &mass));
+  if (cnt == 0) return APM_OK;
+  std::ostringstream e;
+  e << where << ": strict mode: " << cnt << " particle(s) outside [0,1)^3 or NaN, mass " << mass
+    << " left out";
+  return fail(APM_ERR_RANGE, e.str());
+}
+
 extern "C" {
+
+apm_status apm_dropped(apm_ctx c, apm_dtype dt, const void* x, const void* y, const void* z,
+                       const void* m, int64_t npart, int64_t* count, double* mass) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (npart < 0) return fail(APM_ERR_RANGE, "apm_dropped: npart < 0");
+  if (!count || !mass || (npart > 0 && (!x || !y || !z || !m)))
+    return fail(APM_ERR_INVALID, "apm_dropped: NULL argument");
+  return dropped_any(c, dt, x, y, z, m, npart, count, mass);
+}
 
 apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out) {
   if (!plan || !out) return fail(APM_ERR_INVALID, "apm_create: NULL argument");
@@ -1566,7 +1619,7 @@ apm_status apm_deposit(apm_ctx c, apm_dtype dt, int32_t level, const void* x, co
     if (mean)
       APM_TRY(mean_density_t<float>(c, (const float*)x, (const float*)y, (const float*)z,
                                     (const float*)m, npart, g));
-    return APM_OK;
+    return strict_check(c, dt, x, y, z, m, npart, "apm_deposit");
   }
   const double* g = (const double*)gas;
   const double* pg = (const double*)parent_gas;
@@ -1577,7 +1630,7 @@ apm_status apm_deposit(apm_ctx c, apm_dtype dt, int32_t level, const void* x, co
   if (mean)
     APM_TRY(mean_density_t<double>(c, (const double*)x, (const double*)y, (const double*)z,
                                    (const double*)m, npart, g));
-  return APM_OK;
+  return strict_check(c, dt, x, y, z, m, npart, "apm_deposit");
 }
 
 apm_status apm_solve_level(apm_ctx c, apm_dtype dt, int32_t level, const void* gmf, void* field) {
@@ -1693,11 +1746,14 @@ apm_status apm_solve(apm_ctx c, apm_dtype dt, const void* x, const void* y, cons
   if (npart > 0 && (!x || !y || !z || !m || !ax || !ay || !az))
     return fail(APM_ERR_INVALID, "apm_solve: NULL array");
   if (dt == APM_F32)
-    return solve_t<float>(c, dt, (const float*)x, (const float*)y, (const float*)z, (const float*)m,
-                          npart, gas, (float*)ax, (float*)ay, (float*)az, (float*)pot);
-  return solve_t<double>(c, dt, (const double*)x, (const double*)y, (const double*)z,
-                         (const double*)m, npart, gas, (double*)ax, (double*)ay, (double*)az,
-                         (double*)pot);
+    APM_TRY(solve_t<float>(c, dt, (const float*)x, (const float*)y, (const float*)z,
+                           (const float*)m, npart, gas, (float*)ax, (float*)ay, (float*)az,
+                           (float*)pot));
+  else
+    APM_TRY(solve_t<double>(c, dt, (const double*)x, (const double*)y, (const double*)z,
+                            (const double*)m, npart, gas, (double*)ax, (double*)ay, (double*)az,
+                            (double*)pot));
+  return strict_check(c, dt, x, y, z, m, npart, "apm_solve");
 }
 
 static apm_status solve_totals_check(apm_ctx c, apm_dtype dt, const void* m, int64_t npart,

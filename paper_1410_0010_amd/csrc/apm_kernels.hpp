@@ -320,6 +320,11 @@ template <typename T> struct TotalsIO {
   double* out;                         // nlev + 5 doubles
 };
 template <typename T> hipError_t launch_totals(const TotalsIO<T>& io, hipStream_t s);
+// number and mass of the particles outside [0, 1)^3 or with a NaN coordinate, added to
+// out[0] (the count, as a double) and out[1]; partials in part (2 kMaxParts doubles)
+template <typename T> hipError_t launch_dropped(const T* x, const T* y, const T* z, const T* m,
+                                                int64_t npart, double* part, double* out,
+                                                hipStream_t s);
 // out[q] += scale * sum_{b < nparts} part[q * kMaxParts + b], q < nq (fixed order;
 // with nq = 1 any nparts)
 hipError_t launch_sum_parts(const double* part, int nparts, int nq, double scale, double* out,

@@ -138,6 +138,29 @@ __global__ void __launch_bounds__(kBlock) k_mean_finish(const double* __restrict
 
 static int nparts_for(int64_t n);
 
+// Particles the deposit leaves out (a coordinate outside [0, 1) or NaN): per-block
+// partial count and mass at part[b] and part[kMaxParts + b].
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dropped_parts(const T* __restrict__ x, const T* __restrict__ y,
+                                                          const T* __restrict__ z,
+                                                          const T* __restrict__ m, int64_t npart,
+                                                          double* __restrict__ part) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  double cnt = 0.0, mass = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < npart; i += stride) {
+    const T px = x[i], py = y[i], pz = z[i];
+    if (!(px >= (T)0 && px < (T)1 && py >= (T)0 && py < (T)1 && pz >= (T)0 && pz < (T)1)) {
+      cnt += 1.0;
+      mass += (double)m[i];
+    }
+  }
+  const double rc = block_sum(cnt), rm = block_sum(mass);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = rc;
+    part[kMaxParts + blockIdx.x] = rm;
+  }
+}
+
 template <typename T>
 hipError_t launch_mean_density(const T* x, const T* y, const T* z, const T* m, int64_t npart,
                                const T* gas, int64_t ngas, double vol, double* part, double* out,
@@ -152,6 +175,15 @@ hipError_t launch_mean_density(const T* x, const T* y, const T* z, const T* m, i
 static int nparts_for(int64_t n) {
   int64_t nb = (n + kBlock - 1) / kBlock;
   return (int)(nb > kMaxParts ? kMaxParts : (nb < 1 ? 1 : nb));
+}
+
+template <typename T>
+hipError_t launch_dropped(const T* x, const T* y, const T* z, const T* m, int64_t npart,
+                          double* part, double* out, hipStream_t s) {
+  const int nb = nparts_for(npart);
+  hipLaunchKernelGGL((k_dropped_parts<T>), dim3(nb), dim3(kBlock), 0, s, x, y, z, m, npart, part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kBlock), 0, s, (const double*)part, nb, 2, 1.0, out);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -305,6 +337,8 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
   template hipError_t launch_sum_scaled<T>(const T*, int64_t, double, double*, double*,          \
                                           hipStream_t);                                         \
   template hipError_t launch_totals<T>(const TotalsIO<T>&, hipStream_t);                        \
+  template hipError_t launch_dropped<T>(const T*, const T*, const T*, const T*, int64_t, double*,  \
+                                        double*, hipStream_t);                                   \
   template hipError_t launch_particle_totals<T>(const T*, const int32_t*, int64_t, const T*,     \
                                                 const T*, const T*, const T*, double*, double*,  \
                                                 hipStream_t);

@@ -54,6 +54,7 @@ apm_status build_plan(const apm_config& cfg, const apm_grid* grids, int32_t ngri
   if (cfg.gradient != APM_GRAD_SPECTRAL && cfg.gradient != APM_GRAD_FD2)
     return fail(APM_ERR_INVALID, "unknown gradient");
   if (cfg.workspace_limit < 0) return fail(APM_ERR_INVALID, "workspace_limit < 0");
+  if (cfg.strict != 0 && cfg.strict != 1) return fail(APM_ERR_INVALID, "strict must be 0 or 1");
 
   P.cfg = cfg;
   P.pad = (int32_t)std::ceil(cfg.pad_factor * 2.0 * cfg.a_cells - 1e-12);

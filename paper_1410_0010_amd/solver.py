@@ -36,7 +36,8 @@ class Plan:
 
     def __init__(self, root_n: int, grids: Sequence, G: float = 1.0, gradient: str = "spectral",
                  a_cells: float = 3.4, pad_factor: float = 0.65, ghost: int = 3,
-                 brillouin: int = 1, workspace_limit: int = 0, boundary: str = "isolated"):
+                 brillouin: int = 1, workspace_limit: int = 0, boundary: str = "isolated",
+                 strict: bool = False):
         L = _apm.lib()
         cfg = _apm.apm_config()
         L.apm_config_default(ctypes.byref(cfg))
@@ -49,6 +50,7 @@ class Plan:
         cfg.gradient = _GRAD[gradient]
         cfg.workspace_limit = workspace_limit
         cfg.boundary = _BC[boundary]
+        cfg.strict = 1 if strict else 0
         arr = (_apm.apm_grid * len(grids))()
         for i, g in enumerate(grids):
             arr[i].level = g.level
@@ -190,6 +192,15 @@ class Context:
                                     m.shape[0], _ptr(ax), _ptr(ay), _ptr(az), _ptr(pot), out),
               "apm_totals")
         return np.array(out[:])
+
+    def dropped(self, x, y, z, m):
+        """(count, mass) of the particles a deposit leaves out (outside [0, 1)^3 or NaN)."""
+        cnt = ctypes.c_int64()
+        mass = ctypes.c_double()
+        check(_apm.lib().apm_dropped(self.handle, _dtype_code(m), _ptr(x), _ptr(y), _ptr(z),
+                                     _ptr(m), m.shape[0], ctypes.byref(cnt), ctypes.byref(mass)),
+              "apm_dropped")
+        return cnt.value, mass.value
 
     def totals_noalloc(self, gmfs: List, m, owner, ax, ay, az, pot=None, out=None):
         """apm_totals into a float64 device tensor (nlevels + 4 values), no allocation in

@@ -93,6 +93,12 @@ def test_periodic_root_fft_is_not_doubled():
         arr[0].n[a] = 16
     h = ctypes.c_void_p()
     assert P.lib().apm_plan_create(ctypes.byref(cfg), arr, 1, ctypes.byref(h)) == _apm.APM_ERR_INVALID
+    cfg.boundary = _apm.APM_BC_ISOLATED
+    cfg.strict = 2
+    assert P.lib().apm_plan_create(ctypes.byref(cfg), arr, 1, ctypes.byref(h)) == _apm.APM_ERR_INVALID
+    cfg.strict = 1
+    assert P.lib().apm_plan_create(ctypes.byref(cfg), arr, 1, ctypes.byref(h)) == _apm.APM_OK
+    P.lib().apm_plan_destroy(h)
 
 
 def _bad(grids, root_n=16, **kw):

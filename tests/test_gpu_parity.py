@@ -481,3 +481,53 @@ def test_autotune_keeps_parity(dtype):
     own = ref["owner"] >= 0
     assert rel(got[own, :3], ref["acc"][own]) <= TOL[dtype]["acc"]
     assert rel(got[own, 3], ref["pot"][own]) <= TOL[dtype]["pot"]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_dropped_particles_and_strict_mode(dtype):
+    """apm_dropped counts the particles a deposit leaves out (outside [0, 1)^3 or NaN)
+    and their mass; in strict mode apm_solve and apm_deposit report them as
+    APM_ERR_RANGE, and accept the same hierarchy with those particles removed."""
+    w = edge_workload()
+    say(f"[dropped] edge particles dtype={dtype.__name__}")
+    cast = lambda a: np.asarray(a, dtype).astype(np.float64)
+    bad = ~O.valid_particles(cast(w.x), cast(w.y), cast(w.z))
+    assert bad.sum() == 3
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    x, y, z, m = (dev(a, dtype) for a in (w.x, w.y, w.z, w.m))
+    cnt, mass = ctx.dropped(x, y, z, m)
+    assert cnt == 3 and abs(mass - cast(w.m)[bad].sum()) <= 1e-12
+    assert ctx.dropped(x[:2], y[:2], z[:2], m[:2]) == (0, 0.0)
+    strict = P.Context(P.Plan(w.root_n, w.grids, strict=True), 0)
+    from paper_1410_0010_amd import _apm
+    for call in (lambda: strict.solve(x, y, z, m), lambda: strict.deposit(0, x, y, z, m)):
+        with pytest.raises(P.APMError) as e:
+            call()
+        assert e.value.status == _apm.APM_ERR_RANGE
+    ok = torch.from_numpy(np.nonzero(~bad)[0]).to(DEV)
+    sx, sy, sz, sm = (t[ok].contiguous() for t in (x, y, z, m))
+    got = strict.solve(sx, sy, sz, sm)
+    ref = ctx.solve(sx, sy, sz, sm)
+    torch.cuda.synchronize()
+    for a, b in zip(got, ref):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_repeat_runs_agree_within_rounding(dtype):
+    """The deposit sums with atomics in an order that varies between runs, so repeated
+    solves of the same input need not be bit-identical; they agree to the rounding of
+    the working precision (bound: 1e-6 relative L2 in FP32, 1e-14 in FP64, far inside
+    the parity tolerances)."""
+    w = W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=2, npart=50000)
+    say(f"[repeat] nested32 npart={w.npart} dtype={dtype.__name__}")
+    plan = P.Plan(w.root_n, w.grids)
+    ctx = P.Context(plan, 0)
+    ctx.set_graph(False)
+    t = [dev(a, dtype) for a in (w.x, w.y, w.z, w.m)]
+    runs = [_solve_np(ctx, t) for _ in range(4)]
+    bound = 1e-6 if dtype == np.float32 else 1e-14
+    worst = max(rel(r, runs[0]) for r in runs[1:])
+    say(f"[repeat] largest relative L2 difference between runs: {worst:.3e}")
+    assert worst <= bound
