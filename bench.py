@@ -95,7 +95,7 @@ def kernel_bytes(plan, npart, npart_level, esize, root_gas=False, pot_only_adjoi
     c = 2 * esize
     fs = 1 if pot_only_adjoint else 4
     names = ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv", "deposit_tiles",
-             "deposit_finalize", "compose", "interp", "unpack", "bin_count", "bin_scatter",
+             "deposit_finalize", "compose", "interp", "unpack", "sort", "tile_ranges",
              "adj_fft_x", "adj_fft_y", "adj_fft_z", "adj_fft_y_inv", "adj_fft_x_inv",
              "adj_interp", "adj_deposit_grid", "adj_deposit_particles", "adj_restrict")
     b = {k: 0.0 for k in names}
@@ -129,8 +129,16 @@ def kernel_bytes(plan, npart, npart_level, esize, root_gas=False, pot_only_adjoi
         b["deposit_tiles"] += nb * 4 * esize           # sorted (x/dx, y/dx, z/dx, m) records
         b["adj_deposit_particles"] += nb * (4 * esize + 8 + 4 * 8)
     nl = len(plan.levels)
-    b["bin_count"] = npart * 3 * esize + nl * npart * 8      # positions once, key + rank per level
-    b["bin_scatter"] = nl * npart * (4 * esize + 8) + binned * (4 * esize + 8)
+    # the particle sort: Morton bits of the finest level's 8^3 tiles, 8 a pass, keys of
+    # 4 bytes below 32 bits; keys + indices read and written each pass, the digit
+    # counts read with the keys; records packed, then gathered in sorted order
+    nbits = 3 * max(0, int(round(np.log2(plan.grids[0]["n"][0] << (nl - 1)))) - 3)
+    ks = 8 if nbits >= 32 else 4
+    passes = (nbits + 8) // 8
+    b["sort"] = (npart * (4 * esize) + npart * (ks + 4 + 4 * esize + 4)    # keys, owners, pack
+                 + passes * npart * (ks + 2 * (ks + 4))                   # digit counts, scatter
+                 + npart * (4 + 4 * esize + 4) + npart * (4 * esize + 8))  # gather
+    b["tile_ranges"] = npart * ks
     b["interp"] = binned * (4 * esize + 8) + npart * 4 * esize   # sorted records in, a + Phi out
     b["unpack"] = npart * (4 * esize + 4 + 4 * esize)   # (a, Phi) records + owner in, 4 arrays out
     if plan.cfg.boundary == 1:                          # periodic: the average density
@@ -141,16 +149,13 @@ def kernel_bytes(plan, npart, npart_level, esize, root_gas=False, pot_only_adjoi
     b["totals"] = (sum(L["gmf_elems"] for L in plan.levels) * esize
                    + npart * (5 * esize + 4))           # GMFs, m, a, Phi, owner
     b["bin_clear"] = b["bin_scan"] = 0.0
-    for l in range(nl):                                 # per level: tile counters, mass grid
+    for l in range(nl):                                 # per level: tile runs, mass grid
         gs = plan.level_grids(l)
-        kn = [max(g["gmf_lo"][a] + g["gmf_n"][a] for g in gs) + 1 -
-              (min(g["gmf_lo"][a] for g in gs) - 1) for a in range(3)]
-        ntiles = int(np.prod([(k + 7) // 8 for k in kn]))
-        rep = 1
-        while rep < 16 and ntiles * rep * 2 <= 1 << 23:
-            rep *= 2
-        b["bin_clear"] += (ntiles * rep + 1) * 4 + int(np.prod(kn)) * 8
-        b["bin_scan"] += 2 * ntiles * rep * 4 + ntiles * 8   # counters in and out, items
+        klo = [min(g["gmf_lo"][a] for g in gs) - 1 for a in range(3)]
+        khi = [max(g["gmf_lo"][a] + g["gmf_n"][a] for g in gs) for a in range(3)]   # inclusive
+        ntiles = int(np.prod([khi[a] // 8 - klo[a] // 8 + 1 for a in range(3)]))
+        b["bin_clear"] += ntiles * 8 + int(np.prod([khi[a] - klo[a] + 1 for a in range(3)])) * 8
+        b["bin_scan"] += ntiles * 8 * 2 + ntiles * 4        # runs in (twice), item starts out
     return b
 
 

@@ -144,7 +144,8 @@ void apm_config_default(apm_config* cfg);
  * grids: host array of ngrids descriptors, sorted by level, parents first.
  * On success *out owns a plan to release with apm_plan_destroy.
  * Errors: APM_ERR_INVALID (descriptor / nesting), APM_ERR_RANGE (FFT length
- * beyond 1024 or index space beyond int32). */
+ * beyond 1024, index space beyond int32, or a finest level of more than 2^24
+ * cells per axis: root_n 2^maxlevel <= 2^24). */
 apm_status apm_plan_create(const apm_config* cfg, const apm_grid* grids, int32_t ngrids,
                            apm_plan* out);
 apm_status apm_plan_destroy(apm_plan plan);

@@ -13,8 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libapm.so")
-SOURCES = ["plan.cpp", "fft.hip", "fft_adj.hip", "greens.hip", "particles.hip", "field.hip",
-           "dynamics.hip", "adjoint.hip", "api.hip"]
+SOURCES = ["plan.cpp", "fft.hip", "fft_adj.hip", "greens.hip", "particles.hip", "sort.hip",
+           "field.hip", "dynamics.hip", "adjoint.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

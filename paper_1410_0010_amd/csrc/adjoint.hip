@@ -6,9 +6,9 @@
 //   own-field cotangents --convolution^T (fft_adj.hip)--> GMF cotangents
 //   --deposit^T--> level key boxes (FP64) --TSC gather--> particle gradients.
 //
-// All cotangent accumulation is FP64.  Particles are visited in the tile order the
-// forward deposit built (the sorted lists and work items stay valid until the next
-// solve), so neighbouring lanes touch neighbouring cells.
+// All cotangent accumulation is FP64.  Particles are visited in the order of the
+// forward solve's sorted list and tile work items (valid until the next solve), so
+// neighbouring lanes touch neighbouring cells.
 #include "apm_kernels.hpp"
 
 namespace apm {
@@ -77,8 +77,8 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
   const int tile = wk.x;
   const int64_t begin = wk.y, end = wk.z;
   if (threadIdx.x < KG) gsl[threadIdx.x] = INT32_MAX;
-  const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
-            oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;
+  int ox, oy, oz;
+  tile_origin(L, tile, ox, oy, oz);
   static_assert(kChunk == 8 * kBlock, "a chunk is eight records per thread");
   int2 ref[8];
   V4<T> rec[8];
@@ -86,8 +86,8 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
   for (int k = 0; k < 8; ++k) {                      // the chunk's loads first
     const int64_t q = begin + threadIdx.x + (int64_t)k * kBlock;
     const int64_t qc = q < end ? q : begin;          // begin < end: a valid entry
-    ref[k] = load_i2(L.sref, qc);
-    rec[k] = load_v4<T>(L.sorted, qc);
+    ref[k] = level_ref(L, qc);
+    rec[k] = level_rec<T>(L, qc);
     if (q >= end) ref[k].y = -1;
   }
 #pragma unroll
@@ -204,26 +204,24 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
   }
 }
 
-// Position part of the interpolation transpose: one thread per tile-sorted entry of a
-// level (neighbouring lanes gather neighbouring cells), owned entries only:
-//   pint[level][q] = (1/dx) sum_f grad w(f) . <F(f), cot_i>
+// Position part of the interpolation transpose: one thread per entry of the sorted list
+// (neighbouring lanes gather neighbouring cells), owned entries only:
+//   pint[q] = (1/dx) sum_f grad w(f) . <F(f), cot_i>
 // with F the forward composed field of the owner grid and cot_i the particle's
 // cotangent (abar, phibar + wbar m / 2).  One writer per particle.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_adj_interp_grad(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __restrict__ grids) {
-  const int lb = batch_of(io.part_blk0, io.nlev, blockIdx.x);
-  const DepLevel& L = tab[lb];
-  const int64_t q = (blockIdx.x - io.part_blk0[lb]) * (int64_t)kBlock + threadIdx.x;
-  if (q >= *L.binned) return;
-  const int2 r = load_i2(L.sref, q);
-  const V4<T> v = load_v4<T>(L.sorted, q);
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= io.npart) return;
+  const int2 r = load_i2(tab[0].sref, q);
   if (r.y < 0) return;
+  const GridDesc& g = grids[r.y];
+  const V4<T> v = level_rec<T>(tab[g.level], q);
   const int64_t i = r.x;
   const double cot[4] = {io.abx ? (double)io.abx[i] : 0.0, io.aby ? (double)io.aby[i] : 0.0,
                          io.abz ? (double)io.abz[i] : 0.0,
                          (io.phib ? (double)io.phib[i] : 0.0) + io.wbar * 0.5 * (double)v.w};
-  const GridDesc& g = grids[r.y];
   const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
   const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
   const int cx = (int)fx - g.fld_lo[0], cy = (int)fy - g.fld_lo[1], cz = (int)fz - g.fld_lo[2];
@@ -249,7 +247,7 @@ k_adj_interp_grad(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc*
     dwy[d] = oy_ ? (double)tsc_dw_a(d - 1, ty) : 0.0;
     dwz[d] = oz_ ? (double)tsc_dw_a(d - 1, tz) : 0.0;
   }
-  const V4<T>* F = io.fld[lb] + g.fld_offset;
+  const V4<T>* F = io.fld[g.level] + g.fld_offset;
   double gx = 0.0, gy = 0.0, gz = 0.0;
 #pragma unroll
   for (int dz = 0; dz < 3; ++dz) {
@@ -274,8 +272,8 @@ k_adj_interp_grad(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc*
     }
   }
   const double inv = 1.0 / g.dx;
-  // at the entry's sorted position on its owner level (coalesced), not at i
-  io.pint[lb][q] = V4<T>{(T)(gx * inv), (T)(gy * inv), (T)(gz * inv), (T)0};
+  // at the entry's sorted position (coalesced), not at i
+  io.pint[q] = V4<T>{(T)(gx * inv), (T)(gy * inv), (T)(gz * inv), (T)0};
 }
 
 template <typename T>
@@ -287,9 +285,9 @@ hipError_t launch_adj_interp(const AdjIO<T>& io, const DepLevel* tab, const Grid
     hipLaunchKernelGGL((k_adj_interp<T, 1>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab, grids);
   else
     hipLaunchKernelGGL((k_adj_interp<T, 4>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab, grids);
-  const int64_t np = io.part_blk0[io.nlev];
-  if (np > 0)
-    hipLaunchKernelGGL((k_adj_interp_grad<T>), dim3((unsigned)np), dim3(kBlock), 0, s, io, tab, grids);
+  if (io.npart > 0)
+    hipLaunchKernelGGL((k_adj_interp_grad<T>), dim3((unsigned)((io.npart + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, io, tab, grids);
   return hipGetLastError();
 }
 
@@ -498,9 +496,9 @@ hipError_t launch_adj_deposit_grid(const AdjIO<T>& io, const DepLevel* tab, hipS
 }
 
 // ---- deposit transpose, particle side --------------------------------------------------
-// Entry q of a level's sorted list: (sum_c w(c) A(c), m sum_c grad w(c) A(c)), A the
-// level's key-box cotangent, stored in the level's per-particle slot (the levels are
-// summed per particle at the end, so no atomics).  One block per deposit work item; a
+// Entry q of a level's tile runs: (sum_c w(c) A(c), m sum_c grad w(c) A(c)), A the
+// level's key-box cotangent, stored in the level's slot at q (the levels are summed
+// per particle at the end, so no atomics).  One block per deposit work item; a
 // chunk of 64 entries or more reads the 10^3 key-box cells around its tile into LDS
 // (zero outside the box, wrapped on a periodic root) and gathers from there.
 template <typename T>
@@ -516,8 +514,8 @@ k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
   if (item >= total) return;                        // uniform for the block
   const int tile = wk.x;
   const int64_t begin = wk.y, end = wk.z;
-  const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
-            oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;
+  int ox, oy, oz;
+  tile_origin(L, tile, ox, oy, oz);
   const int nx = L.key_n[0], ny = L.key_n[1], nz = L.key_n[2];
   const gptr<double> acc_g = as_global<double>(L.accum);
   const bool staged = end - begin >= 64;            // uniform for the block
@@ -538,7 +536,7 @@ k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
   for (int k = 0; k < 8; ++k) {
     const int64_t q = begin + threadIdx.x + (int64_t)k * kBlock;
     if (q >= end) break;
-    const V4<T> v = load_v4<T>(L.sorted, q);
+    const V4<T> v = level_rec<T>(L, q);
     const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
     const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
     double wx[3], wy[3], wz[3], dwx[3], dwy[3], dwz[3];
@@ -615,32 +613,37 @@ hipError_t launch_adj_deposit_particles(const AdjIO<T>& io, const DepLevel* tab,
 }
 
 // ---- outputs -----------------------------------------------------------------------------
-// mbar, xbar = the sum over the levels the particle was binned on (key >= 0) of the
-// deposit transpose, plus the interpolation transpose's position gradient and
-// wbar Phi_p / 2 (mass) for owned particles.  Each level's terms are read at the
-// particle's sorted position there, count[key] + rank (the forward binning's).
+// One thread per entry q of the sorted list, for particle i = its original index:
+// mbar, xbar = the sum over the levels whose tiles hold the particle of the deposit
+// transpose, plus the interpolation transpose's position gradient and wbar Phi_p / 2
+// (mass) for owned particles; written at i.  A level's tiles hold the particle when
+// its tile floor(x / dx) / kTile lies in the level's tile box, as the tile runs do.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_adj_finish(AdjIO<T> io, const DepLevel* __restrict__ tab, const int32_t* __restrict__ owner,
-             const T* __restrict__ pot, T* __restrict__ xb, T* __restrict__ yb,
-             T* __restrict__ zb, T* __restrict__ mb) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= io.npart) return;
+k_adj_finish(AdjIO<T> io, const DepLevel* __restrict__ tab, const T* __restrict__ pot,
+             T* __restrict__ xb, T* __restrict__ yb, T* __restrict__ zb, T* __restrict__ mb) {
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= io.npart) return;
+  const int2 r = load_i2(tab[0].sref, q);
+  const int64_t i = r.x;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  const int32_t og = owner[i];
-  for (int l = 0; l < io.nlev; ++l) {
-    // the particle's entry on level l: sorted position count[key] + rank
-    const int32_t key = as_global<int32_t>(tab[l].key)[i];
-    if (key < 0) continue;
-    const int32_t q = as_global<int32_t>(tab[l].count)[key] + as_global<int32_t>(tab[l].rank)[i];
-    const V4<T> o = load_v4<T>(io.plev[l], q);
-    s0 += (double)o.x; s1 += (double)o.y; s2 += (double)o.z; s3 += (double)o.w;
-    if (og >= tab[l].first && og < tab[l].first + tab[l].ngrids) {   // owned on this level
-      const V4<T> pi = load_v4<T>(io.pint[l], q);
-      s1 += (double)pi.x; s2 += (double)pi.y; s3 += (double)pi.z;
+  if (r.y >= 0) {                                    // in the domain
+    const V4<T> w = load_v4<T>(tab[0].sorted, q);
+    for (int l = 0; l < io.nlev; ++l) {
+      const DepLevel& L = tab[l];
+      const T sc = (T)L.inv_dx;
+      const int cx = (int)floor(w.x * sc), cy = (int)floor(w.y * sc), cz = (int)floor(w.z * sc);
+      const int tx = (cx >> 3) - L.tile_lo[0], ty = (cy >> 3) - L.tile_lo[1],
+                tz = (cz >> 3) - L.tile_lo[2];
+      static_assert(kTile == 8, "tile index by shift");
+      if (tx < 0 || tx >= L.tiles_n[0] || ty < 0 || ty >= L.tiles_n[1] || tz < 0 ||
+          tz >= L.tiles_n[2])
+        continue;
+      const V4<T> o = load_v4<T>(io.plev[l], q);
+      s0 += (double)o.x; s1 += (double)o.y; s2 += (double)o.z; s3 += (double)o.w;
     }
-  }
-  if (og >= 0) {
+    const V4<T> pi = load_v4<T>(io.pint, q);
+    s1 += (double)pi.x; s2 += (double)pi.y; s3 += (double)pi.z;
     if (io.wbar != 0.0 && pot) s0 += io.wbar * 0.5 * (double)pot[i];
     if (io.rbar) s0 += as_global<double>(io.rbar)[0];   // periodic: the average density's
   }
@@ -666,11 +669,11 @@ hipError_t launch_add_scalar(double* a, int64_t n, const double* s, double scale
 }
 
 template <typename T>
-hipError_t launch_adj_finish(const AdjIO<T>& io, const DepLevel* tab, const int32_t* owner,
-                             const T* pot, T* xb, T* yb, T* zb, T* mb, hipStream_t s) {
+hipError_t launch_adj_finish(const AdjIO<T>& io, const DepLevel* tab, const T* pot, T* xb, T* yb,
+                             T* zb, T* mb, hipStream_t s) {
   if (io.npart == 0) return hipSuccess;
   hipLaunchKernelGGL((k_adj_finish<T>), dim3((unsigned)((io.npart + kBlock - 1) / kBlock)),
-                     dim3(kBlock), 0, s, io, tab, owner, pot, xb, yb, zb, mb);
+                     dim3(kBlock), 0, s, io, tab, pot, xb, yb, zb, mb);
   return hipGetLastError();
 }
 
@@ -698,8 +701,8 @@ hipError_t launch_to_t(const double* a, T* b, int64_t n, hipStream_t s) {
   template hipError_t launch_adj_deposit_grid<T>(const AdjIO<T>&, const DepLevel*, hipStream_t); \
   template hipError_t launch_adj_deposit_particles<T>(const AdjIO<T>&, const DepLevel*,        \
                                                       hipStream_t);                            \
-  template hipError_t launch_adj_finish<T>(const AdjIO<T>&, const DepLevel*, const int32_t*,    \
-                                           const T*, T*, T*, T*, T*, hipStream_t);              \
+  template hipError_t launch_adj_finish<T>(const AdjIO<T>&, const DepLevel*, const T*, T*, T*, \
+                                           T*, T*, hipStream_t);                                \
   template hipError_t launch_to_t<T>(const double*, T*, int64_t, hipStream_t);
 APM_INST_A(float)
 APM_INST_A(double)

@@ -60,10 +60,13 @@ struct apm_ctx_s {
   std::map<std::tuple<int, int, int>, void*> dsym;                // (dtype, level, M)
   std::map<std::tuple<int, int, int, int, int>, void*> kern;      // (dtype, level, Mx, My, Mz)
   std::vector<void*> owned;                                       // every table allocation
-  DevBuf spec, zbuf, ybuf, pres, owner, totals, binned, gpart, energy, lf_pot;
-  // per level: tile counters, work items, FP64 mass grid, particle keys/ranks, the
-  // tile-sorted records and their original indices
-  struct LevelBufs { DevBuf count, items, work, bsum, accum, key, rank, sref, sorted; };
+  DevBuf spec, zbuf, ybuf, pres, owner, totals, gpart, energy, lf_pot;
+  // the particle sort shared by the levels: ping-pong keys and indices, packed input
+  // records, digit counts and scan partials, the sorted records and references
+  DevBuf skey[2], sidx[2], sprec, shist, shsum, ssorted, ssref;
+  int sort_nbits = 0;                                             // of the last sort
+  // per level: tile runs, work items, scan sums, FP64 mass grid
+  struct LevelBufs { DevBuf tbegin, tend, items, work, bsum, accum; };
   std::vector<LevelBufs> lvb;
   std::vector<DepLevel> dep_host;                                 // level table, host copy
   std::vector<unsigned char> dep_dev_copy;                        // bytes last uploaded
@@ -561,21 +564,88 @@ apm_status sync_dep_table(apm_ctx c) {
   return APM_OK;
 }
 
+// Morton bits of the tiles of level lf: 3 log2(N_lf / kTile), 0 when one tile spans
+// the domain (N_lf is a power of two).
+int sort_bits(const Plan& P, int lf) {
+  const int64_t n = (int64_t)P.cfg.root_n << lf;
+  int b = 0;
+  while ((n >> (b + 3)) > 1) ++b;
+  return 3 * b;
+}
+// ping-pong slot of the sorted keys: one pass per 8 of the nbits + 1 key bits
+int sort_slot(int nbits) { return ((nbits + 8) / 8) & 1; }
+
+// Buffers and arguments of the particle sort by tiles of level lf; owner (or null: no
+// owners) receives every particle's owner grid.
+template <typename T>
+apm_status sort_prepare_t(apm_ctx c, int lf, const T* x, const T* y, const T* z, const T* m,
+                          int64_t npart, int32_t* owner, SortIO<T>* out) {
+  const Plan& P = c->plan;
+  const int nbits = sort_bits(P, lf);
+  if (nbits > kMaxMortonBits)
+    return fail(APM_ERR_RANGE, "particle sort: level " + std::to_string(lf) + " has more than "
+                               "2^21 tiles of 8 cells per axis");
+  const size_t np = (size_t)std::max<int64_t>(npart, 1);
+  const size_t ks = sort_key64(nbits) ? 8 : 4;
+  for (int k = 0; k < 2; ++k) {
+    APM_TRY(ensure(c, c->skey[k], np * ks, "sort keys"));
+    APM_TRY(ensure(c, c->sidx[k], np * 4, "sort indices"));
+  }
+  APM_TRY(ensure(c, c->sprec, np * sizeof(V4<T>), "packed particles"));
+  APM_TRY(ensure(c, c->shist, (size_t)sort_hist_elems(npart) * 4, "sort digit counts"));
+  APM_TRY(ensure(c, c->shsum, (size_t)std::max<int64_t>(sort_sum_elems(npart), 1) * 4,
+                 "sort scan partials"));
+  APM_TRY(ensure(c, c->ssorted, np * sizeof(V4<T>), "sorted particles"));
+  APM_TRY(ensure(c, c->ssref, np * 8, "sorted particle references"));
+  SortIO<T> io{};
+  io.x = x; io.y = y; io.z = z; io.m = m;
+  io.npart = npart;
+  io.cells_f = (double)((int64_t)P.cfg.root_n << lf);
+  io.nbits = nbits;
+  io.om = owner ? c->d_owner_map : nullptr;
+  io.om_nlev = (int32_t)P.levels.size();
+  io.owner = owner;
+  for (int k = 0; k < 2; ++k) {
+    io.key[k] = c->skey[k].p;
+    io.idx[k] = (int32_t*)c->sidx[k].p;
+  }
+  io.prec = c->sprec.p;
+  io.hist = (uint32_t*)c->shist.p;
+  io.hsum = (uint32_t*)c->shsum.p;
+  io.sorted = c->ssorted.p;
+  io.sref = (int2*)c->ssref.p;
+  c->sort_nbits = nbits;
+  *out = io;
+  return APM_OK;
+}
+
+template <typename T>
+apm_status sort_launch_t(apm_ctx c, const SortIO<T>& io) {
+  int which = 0;
+  HIP_TRY(timed(c, "sort", [&] { return launch_particle_sort<T>(io, &which, c->stream); }),
+          "particle sort");
+  if (io.npart > 0 && which != sort_slot(io.nbits))
+    return fail(APM_ERR_DEVICE, "particle sort: sorted keys in an unexpected buffer");
+  return APM_OK;
+}
+
 // A deposit batch: its launch arguments, prepared before any of its launches.
 template <typename T> struct DepBatch {
   int l0 = 0, nlev = 0;
   DepIO<T> io{};
   int64_t max_elems = 0;
   int32_t max_tiles = 1;
+  const void* skey = nullptr;                        // the sorted keys
+  int nbits = 0;
 };
 
-// Buffers and level-table entries of levels [l0, l0 + nlev); the table itself is
-// uploaded by sync_dep_table (once for every batch of a solve).
+// Buffers and level-table entries of levels [l0, l0 + nlev), whose tiles are runs of
+// the list sorted by tiles of level lf (sort_prepare_t with lf, prepared before); the
+// table itself is uploaded by sync_dep_table (once for every batch of a solve).
 template <typename T>
-apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y, const T* z,
-                             const T* m, int64_t npart, const int32_t* owner, const T* const* gas,
-                             const T* const* pgas, T* const* gmf, DepBatch<T>* out,
-                             bool find_owner = false) {
+apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, int lf, int64_t npart,
+                             const T* const* gas, const T* const* pgas, T* const* gmf,
+                             DepBatch<T>* out) {
   const Plan& P = c->plan;
   const int nl = (int)P.levels.size();
   c->lvb.resize(nl);
@@ -583,17 +653,7 @@ apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y
     c->dep_host.resize(nl);
     std::memset((void*)c->dep_host.data(), 0, nl * sizeof(DepLevel));
   }
-  APM_TRY(ensure(c, c->binned, (size_t)nl * 4, "binned totals"));
-  const size_t np = (size_t)std::max<int64_t>(npart, 1);
   DepIO<T> io{};
-  io.x = x; io.y = y; io.z = z; io.m = m;
-  io.owner = owner;
-  if (find_owner) {                                  // the scatter finds (and, for the
-    io.owner = nullptr;                              // root level, writes) the owners
-    io.om = c->d_owner_map;
-    io.om_nlev = nl;
-    io.owner_out = l0 == 0 ? (int32_t*)owner : nullptr;
-  }
   io.npart = npart;
   io.nlev = nlev;
   int64_t max_elems = 0, iblk = 0, fblk = 0;
@@ -601,29 +661,25 @@ apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y
     const int l = l0 + b;
     const LevelDesc& L = P.levels[l];
     apm_ctx_s::LevelBufs& B = c->lvb[l];
-    int32_t tn[3];
+    // the tiles (aligned at multiples of kTile cells) that cover the binning box
+    int32_t tlo[3], tn[3];
     int64_t ntiles = 1;
     for (int a = 0; a < 3; ++a) {
-      tn[a] = (L.key_n[a] + kTile - 1) / kTile;
+      const int32_t lo = L.key_lo[a], hi = L.key_lo[a] + L.key_n[a] - 1;
+      tlo[a] = lo >= 0 ? lo / kTile : -((-lo + kTile - 1) / kTile);
+      const int32_t thi = hi >= 0 ? hi / kTile : -((-hi + kTile - 1) / kTile);
+      tn[a] = thi - tlo[a] + 1;
       ntiles *= tn[a];
     }
-    // counter replicas per tile (blocks pick one by index): kMaxRep while the counters
-    // stay under 2^23 (32 MB); the many blocks of a dense core then spread their one
-    // atomic per (block, tile) over that many addresses (with one counter per tile the
-    // 8192 blocks of a 2^24-particle Plummer core queued on the same few addresses)
-    int32_t rep = 1;
-    while (rep < kMaxRep && ntiles * rep * 2 <= ((int64_t)1 << 23)) rep *= 2;
-    const int64_t ncount = ntiles * rep + 1;
-    APM_TRY(ensure(c, B.count, (size_t)ncount * 4, "tile counts"));
+    if (ntiles >= ((int64_t)1 << 31))
+      return fail(APM_ERR_UNSUPPORTED, "deposit: level " + std::to_string(l) + " has 2^31 tiles or more");
+    APM_TRY(ensure(c, B.tbegin, (size_t)ntiles * 4, "tile run starts"));
+    APM_TRY(ensure(c, B.tend, (size_t)ntiles * 4, "tile run ends"));
     APM_TRY(ensure(c, B.items, (size_t)(ntiles + 1) * 4, "tile work items"));
     const int64_t nwork = ntiles + (npart + kChunk - 1) / kChunk;    // deposit blocks of the level
     APM_TRY(ensure(c, B.work, (size_t)std::max<int64_t>(nwork, 1) * sizeof(int4), "work table"));
     APM_TRY(ensure(c, B.bsum, (size_t)((ntiles + 255) / 256 + 1) * sizeof(int2), "scan block sums"));
     APM_TRY(ensure(c, B.accum, (size_t)L.key_cells * 8, "fp64 mass grid"));
-    APM_TRY(ensure(c, B.key, np * 4, "particle keys"));
-    APM_TRY(ensure(c, B.rank, np * 4, "particle ranks"));
-    APM_TRY(ensure(c, B.sref, np * 8, "sorted particle references"));
-    APM_TRY(ensure(c, B.sorted, np * sizeof(V4<T>), "sorted particles"));
     DepLevel d;
     std::memset((void*)&d, 0, sizeof d);
     d.inv_dx = 1.0 / L.dx;
@@ -631,28 +687,27 @@ apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y
     for (int a = 0; a < 3; ++a) {
       d.key_lo[a] = L.key_lo[a];
       d.key_n[a] = L.key_n[a];
+      d.tile_lo[a] = tlo[a];
       d.tiles_n[a] = tn[a];
     }
     d.ntiles = (int32_t)ntiles;
-    d.rep = rep;
+    d.shift = 3 * (lf - l);
     d.first = L.first;
     d.ngrids = L.count;
     d.wrap = (l == 0 && P.cfg.boundary == APM_BC_PERIODIC) ? P.cfg.root_n : 0;
     d.key_cells = L.key_cells;
-    d.count = (int32_t*)B.count.p;
+    d.tbegin = (int32_t*)B.tbegin.p;
+    d.tend = (int32_t*)B.tend.p;
     d.items = (int32_t*)B.items.p;
     d.work = (int4*)B.work.p;
     d.bsum = (int2*)B.bsum.p;
-    d.key = (int32_t*)B.key.p;
-    d.rank = (int32_t*)B.rank.p;
-    d.sref = (int2*)B.sref.p;
-    d.sorted = B.sorted.p;
+    d.sref = (const int2*)c->ssref.p;
+    d.sorted = c->ssorted.p;
     d.accum = (double*)B.accum.p;
     d.grids = c->d_grids + L.first;
     d.block_begin = c->d_dep_begin[l];
-    d.binned = (int32_t*)c->binned.p + l;
     std::memcpy((void*)&c->dep_host[l], &d, sizeof d);
-    max_elems = std::max(max_elems, std::max(ncount, (int64_t)L.key_cells));
+    max_elems = std::max(max_elems, std::max(ntiles, (int64_t)L.key_cells));
     io.item_blk0[b] = iblk;
     iblk += ntiles + (npart + kChunk - 1) / kChunk;
     io.fin_blk0[b] = fblk;
@@ -669,12 +724,14 @@ apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, const T* x, const T* y
   out->max_elems = max_elems;
   out->max_tiles = 1;
   for (int b = 0; b < nlev; ++b) out->max_tiles = std::max(out->max_tiles, c->dep_host[l0 + b].ntiles);
+  out->nbits = c->sort_nbits;
+  out->skey = c->skey[sort_slot(c->sort_nbits)].p;
   return APM_OK;
 }
 
-// TSC deposit of a prepared batch (Sec. 2) as six steps of eight launches -- clear,
-// tile count, three scan launches, scatter, tile deposit, finalize -- on the
-// context's stream at the time each step runs.  The level table must be uploaded
+// TSC deposit of a prepared batch (Sec. 2) as five steps -- clear, tile runs, three
+// scan launches, tile deposit, finalize -- on the context's stream at the time each
+// step runs, after the particle sort.  The level table must be uploaded
 // (sync_dep_table) before the steps are built.
 template <typename T>
 void deposit_steps_t(apm_ctx c, const DepBatch<T>& d, std::vector<Step>& out) {
@@ -682,6 +739,8 @@ void deposit_steps_t(apm_ctx c, const DepBatch<T>& d, std::vector<Step>& out) {
   const int nlev = d.nlev;
   const int64_t max_elems = d.max_elems;
   const int32_t max_tiles = d.max_tiles;
+  const void* skey = d.skey;
+  const int nbits = d.nbits;
   const DepLevel* tab = (const DepLevel*)c->dep_tab.p + d.l0;
   out.push_back([=]() -> apm_status {
     HIP_TRY(timed(c, "bin_clear", [&] { return launch_dep_clear(tab, nlev, max_elems, c->stream); }),
@@ -689,18 +748,14 @@ void deposit_steps_t(apm_ctx c, const DepBatch<T>& d, std::vector<Step>& out) {
     return APM_OK;
   });
   out.push_back([=]() -> apm_status {
-    HIP_TRY(timed(c, "bin_count", [&] { return launch_bin_count<T>(io, tab, c->stream); }),
-            "bin count");
+    HIP_TRY(timed(c, "tile_ranges", [&] {
+              return launch_tile_ranges(tab, nlev, skey, nbits, io.npart, c->stream);
+            }), "tile runs");
     return APM_OK;
   });
   out.push_back([=]() -> apm_status {
     HIP_TRY(timed(c, "bin_scan", [&] { return launch_bin_scan(tab, nlev, max_tiles, c->stream); }),
             "bin scan");
-    return APM_OK;
-  });
-  out.push_back([=]() -> apm_status {
-    HIP_TRY(timed(c, "bin_scatter", [&] { return launch_bin_scatter<T>(io, tab, c->stream); }),
-            "bin scatter");
     return APM_OK;
   });
   out.push_back([=]() -> apm_status {
@@ -723,16 +778,19 @@ apm_status deposit_launch_t(apm_ctx c, const DepBatch<T>& d) {
   return run_steps(steps);
 }
 
-// TSC deposit of levels [l0, l0 + nlev) in one batch.  gas/pgas/gmf are indexed by
-// batch position.
+// Particle sort by tiles of the batch's finest level and TSC deposit of levels
+// [l0, l0 + nlev) in one batch.  gas/pgas/gmf are indexed by batch position; owner
+// (or null) receives the owner grids.
 template <typename T>
 apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y, const T* z,
-                            const T* m, int64_t npart, const int32_t* owner, const T* const* gas,
-                            const T* const* pgas, T* const* gmf, bool find_owner = false) {
+                            const T* m, int64_t npart, int32_t* owner, const T* const* gas,
+                            const T* const* pgas, T* const* gmf) {
+  SortIO<T> so{};
+  APM_TRY(sort_prepare_t<T>(c, l0 + nlev - 1, x, y, z, m, npart, owner, &so));
   DepBatch<T> d;
-  APM_TRY(deposit_prepare_t<T>(c, l0, nlev, x, y, z, m, npart, owner, gas, pgas, gmf, &d,
-                               find_owner));
+  APM_TRY(deposit_prepare_t<T>(c, l0, nlev, l0 + nlev - 1, npart, gas, pgas, gmf, &d));
   APM_TRY(sync_dep_table(c));
+  APM_TRY(sort_launch_t<T>(c, so));
   return deposit_launch_t<T>(c, d);
 }
 
@@ -781,7 +839,7 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
   }
   APM_TRY(ensure(c, c->owner, (size_t)std::max<int64_t>(npart, 1) * 4, "owner"));
   int32_t* own = (int32_t*)c->owner.p;
-  // owner grids: found by the binning scatter (the root level's blocks write them)
+  // owner grids: found by the particle sort
   if (P.cfg.boundary == APM_BC_PERIODIC) APM_TRY(mean_density_t<T>(c, x, y, z, m, npart,
                                                                    gas ? (const T*)gas[0] : nullptr));
   {
@@ -801,19 +859,21 @@ apm_status solve_body_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T
       lp.fld[l] = (V4<T>*)c->fld[di][l].p;
     }
     if (c->prof_on || nl < 2) {                      // one stream (kernels timed one by one)
-      APM_TRY(deposit_levels_t<T>(c, 0, nl, x, y, z, m, npart, own, gl, pg, gm, true));
+      APM_TRY(deposit_levels_t<T>(c, 0, nl, x, y, z, m, npart, own, gl, pg, gm));
       APM_TRY(convolve_t<T>(c, kAllLevels, lp));
     } else {
-      // The root's deposit and transforms, and those of the subgrid levels, touch
-      // disjoint buffers until the composition: the subgrid levels run on a second
-      // stream, forked from and joined back to the context's stream (two branches of
-      // the captured graph).
+      // One particle sort for every level; then the root's deposit and transforms, and
+      // those of the subgrid levels, touch disjoint buffers until the composition: the
+      // subgrid levels run on a second stream, forked from and joined back to the
+      // context's stream (two branches of the captured graph).
+      SortIO<T> so{};
+      APM_TRY(sort_prepare_t<T>(c, nl - 1, x, y, z, m, npart, own, &so));
       DepBatch<T> d0, d1;
-      APM_TRY(deposit_prepare_t<T>(c, 0, 1, x, y, z, m, npart, own, gl, pg, gm, &d0, true));
-      APM_TRY(deposit_prepare_t<T>(c, 1, nl - 1, x, y, z, m, npart, own, gl + 1, pg + 1, gm + 1,
-                                   &d1, true));
+      APM_TRY(deposit_prepare_t<T>(c, 0, 1, nl - 1, npart, gl, pg, gm, &d0));
+      APM_TRY(deposit_prepare_t<T>(c, 1, nl - 1, nl - 1, npart, gl + 1, pg + 1, gm + 1, &d1));
       APM_TRY(sync_dep_table(c));
       APM_TRY(prepare_branch_stream(c));
+      APM_TRY(sort_launch_t<T>(c, so));
       std::vector<Step> root, sub;
       deposit_steps_t<T>(c, d0, root);
       APM_TRY(convolve_steps_t<T>(c, 0, lp, root));
@@ -1162,9 +1222,9 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
       APM_TRY(ensure(c, c->adj_gas[l], (size_t)std::max<int64_t>(P.levels[l].gas_elems, 1) * 8,
                      "gas cotangents"));
   }
-  // per level and sorted entry, two 4-vectors of T: the interpolation transpose's
-  // record and the deposit transpose's
-  APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * sizeof(V4<T>) * 2 * nl,
+  // per sorted entry, a 4-vector of T for each level's deposit transpose and one for
+  // the interpolation transpose
+  APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * sizeof(V4<T>) * (nl + 1),
                  "particle cotangents"));
   ZeroList zl{};
   hipError_t zerr = hipSuccess;
@@ -1187,20 +1247,15 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
   // field cotangents per cell: all four components, or the Phi one alone, densely
   const int fs = pot_only ? 1 : 4;
   V4<T>* pacc = (V4<T>*)c->adj_pacc.p;
-  for (int l = 0; l < nl; ++l) {
-    io.plev[l] = pacc + (int64_t)n * (2 * l);
-    io.pint[l] = pacc + (int64_t)n * (2 * l + 1);
-  }
-  int64_t iblk = 0, fblk = 0, pblk = 0;
-  const int64_t nbp = (n + kBlock - 1) / kBlock;
+  for (int l = 0; l < nl; ++l) io.plev[l] = pacc + (int64_t)n * l;
+  io.pint = pacc + (int64_t)n * nl;
+  int64_t iblk = 0, fblk = 0;
   for (int l = 0; l < nl; ++l) {
     const DepLevel& d = c->dep_host[l];
     io.item_blk0[l] = iblk;
     iblk += (int64_t)d.ntiles + (n + kChunk - 1) / kChunk;
     io.fin_blk0[l] = fblk;
     fblk += c->dep_blocks[l];
-    io.part_blk0[l] = pblk;
-    pblk += nbp;
     io.fld[l] = (const V4<T>*)c->fld[di][l].p;
     io.fbar[l] = (double*)c->adj_fbar[l].p;
     io.gmf_bar[l] = (const T*)c->adj_gmf[di][l].p;
@@ -1212,7 +1267,6 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
   }
   io.item_blk0[nl] = iblk;
   io.fin_blk0[nl] = fblk;
-  io.part_blk0[nl] = pblk;
   const DepLevel* tab = (const DepLevel*)c->dep_tab.p;
   HIP_TRY(zerr, "adjoint clear");
   HIP_TRY(timed(c, "adj_clear", [&] { return launch_zero_ranges(zl, c->stream); }), "adjoint clear");
@@ -1274,8 +1328,7 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
             return launch_adj_deposit_particles<T>(io, tab, c->stream);
           }), "deposit transpose (particles)");
   HIP_TRY(timed(c, "adj_finish", [&] {
-            return launch_adj_finish<T>(io, tab, (const int32_t*)c->owner.p, pot, xb, yb, zb, mb,
-                                        c->stream);
+            return launch_adj_finish<T>(io, tab, pot, xb, yb, zb, mb, c->stream);
           }), "adjoint outputs");
   if (gas_bar) {
     for (int l = 0; l < nl; ++l) {
@@ -1556,10 +1609,11 @@ apm_status apm_destroy(apm_ctx c) {
   for (void* p : c->owned) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   DevBuf* bufs[] = {&c->spec, &c->zbuf, &c->ybuf, &c->pres, &c->owner, &c->totals,
-                    &c->binned, &c->dep_tab, &c->gpart, &c->energy, &c->lf_pot, &c->meanbuf};
+                    &c->dep_tab, &c->gpart, &c->energy, &c->lf_pot, &c->meanbuf,
+                    &c->skey[0], &c->skey[1], &c->sidx[0], &c->sidx[1], &c->sprec, &c->shist,
+                    &c->shsum, &c->ssorted, &c->ssref};
   for (auto& B : c->lvb)
-    for (DevBuf* b : {&B.count, &B.items, &B.work, &B.bsum, &B.accum, &B.key, &B.rank, &B.sref,
-                      &B.sorted})
+    for (DevBuf* b : {&B.tbegin, &B.tend, &B.items, &B.work, &B.bsum, &B.accum})
       if (b->p) (void)hipFree(b->p);
   for (auto* v : {&c->adj_fbar, &c->adj_gas, &c->adj_gmf[0], &c->adj_gmf[1], &c->adj_gmf[2]})
     for (auto& b : *v) if (b.p) (void)hipFree(b.p);
@@ -1608,7 +1662,7 @@ apm_status apm_deposit(apm_ctx c, apm_dtype dt, int32_t level, const void* x, co
   if (!gmf || (npart > 0 && (!x || !y || !z || !m)))
     return fail(APM_ERR_INVALID, "apm_deposit: NULL array");
   if (level == 0 && parent_gas) return fail(APM_ERR_INVALID, "apm_deposit: root has no parent gas");
-  c->last_solve.clear();                             // the level's binning is replaced
+  c->last_solve.clear();                             // the particle sort is replaced
   const bool mean = level == 0 && c->plan.cfg.boundary == APM_BC_PERIODIC;
   if (dt == APM_F32) {
     const float* g = (const float*)gas;

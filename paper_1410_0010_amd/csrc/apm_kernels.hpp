@@ -146,48 +146,96 @@ __device__ __forceinline__ int owner_lookup(const OwnerLevel* __restrict__ om, i
   return -1;
 }
 
-// Particles: binning by 8^3 tile of the particle's cell i0 = floor(x/dx) inside the
-// level's binning box (union of GMF boxes grown by one cell), then the tile-wise
-// TSC deposit.  Every stage is one launch over a batch of consecutive levels.
+// Particles: one sort of every particle by the Morton code (bits interleaved, x in
+// the lowest) of its kTile^3-cell tile on the sort's finest level, tiles aligned at
+// multiples of kTile cells on every level.  A tile s levels coarser is a cube of 2^(3s)
+// finest tiles whose codes form one aligned range, so on every level each tile's
+// particles are one contiguous run of the sorted list: the levels share the list,
+// each finds its tiles' runs, and the tile-wise TSC deposit reads them.  Every
+// per-level stage is one launch over a batch of consecutive levels.
 constexpr int kTile = 8;
 constexpr int kHaloCells = (kTile + 2) * (kTile + 2) * (kTile + 2);   // tile + one-cell halo
-constexpr int kMaxRep = 16;        // counter replicas per tile, at most (a power of two)
 constexpr int kChunk = 2048;       // particles per deposit work item
+constexpr int kMaxMortonBits = 63; // tiles per axis of the sort's finest level up to 2^21
 
 // Static part of one level (device table, rewritten only when buffers move).
 struct DepLevel {
   double inv_dx, dx;
-  int32_t key_lo[3], key_n[3];     // binning box (cells)
+  int32_t key_lo[3], key_n[3];     // binning box (cells): the level's GMF boxes grown by one
+  int32_t tile_lo[3];              // global index of the first tile covering the box
   int32_t tiles_n[3];              // tiles per axis
-  int32_t ntiles, rep;             // rep: counter replicas per tile (power of two)
+  int32_t ntiles;
+  int32_t shift;                   // Morton bits below the level's tiles: 3 (sort's finest
+                                   // level - level)
   int32_t first, ngrids;           // the level's grids: [first, first + ngrids)
   int32_t wrap;                    // periodic root: cells per axis (clouds wrap), else 0
   int64_t key_cells;
-  int32_t* count;                  // ntiles * rep + 1; replica r of tile t at t rep + r;
-                                   // scanned in place into start offsets
+  int32_t* tbegin;                 // ntiles: first sorted position of each tile's run
+  int32_t* tend;                   // ntiles: one past its last (both 0: empty tile)
   int32_t* items;                  // ntiles + 1: scanned work-item counts
   int4* work;                      // work item -> (tile, first entry, end entry, 0); room
                                    // for ntiles + ceil(npart / kChunk) items
   int2* bsum;                      // per 256 tiles: (count, items) sums, then their starts
-  int32_t* key;                    // npart: counter slot or -1
-  int32_t* rank;                   // npart: rank within the slot
-  int2* sref;                      // sorted position -> (original index, owner grid if
-                                   // that grid is on this level, else -1)
-  void* sorted;                    // npart records (x/dx, y/dx, z/dx, m); x/dx is exact
+  const int2* sref;                // the shared sorted list: (original index, owner grid)
+  const void* sorted;              // the shared sorted list: (x, y, z, m), world units
   double* accum;                   // key_cells FP64 mass (the reverse sweep: GMF cotangent)
   const GridDesc* grids;           // the level's grids
   const int64_t* block_begin;      // first finalize block of each grid (ngrids + 1)
-  int32_t* binned;                 // number of particles binned on the level
 };
 
-// Per-call part: the particles, the batch's block offsets and its in/out buffers
-// (index b = level - first level of the batch).
-template <typename T> struct DepIO {
+// First cell of tile t of a level, relative to the level's binning box (between
+// 1 - kTile and 0 for the first tile of an axis).
+__host__ __device__ __forceinline__ void tile_origin(const DepLevel& L, int t, int& ox, int& oy,
+                                                     int& oz) {
+  ox = (L.tile_lo[0] + t % L.tiles_n[0]) * kTile - L.key_lo[0];
+  oy = (L.tile_lo[1] + (t / L.tiles_n[0]) % L.tiles_n[1]) * kTile - L.key_lo[1];
+  oz = (L.tile_lo[2] + t / (L.tiles_n[0] * L.tiles_n[1])) * kTile - L.key_lo[2];
+}
+// Entry q of the sorted list in the level's cell units (exact: dx is a power of two).
+template <typename T> __device__ __forceinline__ V4<T> level_rec(const DepLevel& L, int64_t q) {
+  V4<T> v = load_v4<T>(L.sorted, q);
+  const T s = (T)L.inv_dx;
+  v.x *= s; v.y *= s; v.z *= s;
+  return v;
+}
+// (original index, owner grid when that grid is on the level, else -1) of entry q
+__device__ __forceinline__ int2 level_ref(const DepLevel& L, int64_t q) {
+  int2 r = load_i2(L.sref, q);
+  if (r.y < L.first || r.y >= L.first + L.ngrids) r.y = -1;
+  return r;
+}
+
+// The particle sort (sort.hip), once per solve or deposit, before any level's tiles.
+// Keys are 32-bit while nbits < 32, else 64-bit.
+constexpr int kRadixBlock = 256, kRadixItems = 16, kRadixTile = kRadixBlock * kRadixItems;
+template <typename T> struct SortIO {
   const T* x; const T* y; const T* z; const T* m;
-  const int32_t* owner;                // owner grid per particle, or null (no owners)
-  const OwnerLevel* om;                // or the owner lookup of every level (om_nlev), the
-  int32_t om_nlev;                     // owner computed in the scatter, and written to
-  int32_t* owner_out;                  // owner_out (if not null) by the root level's blocks
+  int64_t npart;
+  double cells_f;                      // cells per axis of the sort's finest level
+  int32_t nbits;                       // Morton bits of its tiles (3 per axis); the key of a
+                                       // particle outside [0, 1)^3 is 1 << nbits, after all
+  const OwnerLevel* om;                // owner lookup of every level, or null (no owners:
+  int32_t om_nlev;                     // the sorted references hold -1)
+  int32_t* owner;                      // out (with om): owner grid per particle, -1 outside
+  void* key[2];                        // npart each: ping-pong keys
+  int32_t* idx[2];                     // npart each: ping-pong original indices
+  void* prec;                          // npart records (x, y, z, m) in input order
+  uint32_t* hist;                      // 256 ceil(npart / kRadixTile): digit counts, then
+                                       // their exclusive scan (digit-major)
+  uint32_t* hsum;                      // scan partials, sort_sum_elems(npart)
+  void* sorted;                        // out: npart records (x, y, z, m), sorted
+  int2* sref;                          // out: npart (original index, owner grid)
+};
+int64_t sort_hist_elems(int64_t npart);
+int64_t sort_sum_elems(int64_t npart);
+inline bool sort_key64(int nbits) { return nbits >= 32; }
+// The whole sort on s; *which gets the ping-pong slot (0 or 1) holding the sorted keys.
+template <typename T> hipError_t launch_particle_sort(const SortIO<T>& io, int* which,
+                                                      hipStream_t s);
+
+// Per-call part: the batch's block offsets and its in/out buffers (index b = level -
+// first level of the batch).
+template <typename T> struct DepIO {
   int64_t npart;
   int32_t nlev;
   int64_t item_blk0[kMaxLevels + 1];   // deposit-tile blocks of level b: [item_blk0[b], [b+1])
@@ -197,11 +245,11 @@ template <typename T> struct DepIO {
   T* gmf[kMaxLevels];
 };
 hipError_t launch_dep_clear(const DepLevel* tab, int nlev, int64_t max_elems, hipStream_t s);
-template <typename T> hipError_t launch_bin_count(const DepIO<T>& io, const DepLevel* tab,
-                                                  hipStream_t s);
+// each tile's run of the sorted keys (sorted by launch_particle_sort with nbits) on
+// every level of the batch; tbegin and tend cleared before (launch_dep_clear)
+hipError_t launch_tile_ranges(const DepLevel* tab, int nlev, const void* skey, int nbits,
+                              int64_t npart, hipStream_t s);
 hipError_t launch_bin_scan(const DepLevel* tab, int nlev, int32_t max_tiles, hipStream_t s);
-template <typename T> hipError_t launch_bin_scatter(const DepIO<T>& io, const DepLevel* tab,
-                                                    hipStream_t s);
 template <typename T> hipError_t launch_deposit_tiles(const DepIO<T>& io, const DepLevel* tab,
                                                       hipStream_t s);
 template <typename T> hipError_t launch_deposit_finalize(const DepIO<T>& io, const DepLevel* tab,
@@ -252,7 +300,6 @@ template <typename T> struct AdjIO {
   const T* phib;                       // potential cotangents (npart) or null
   int64_t item_blk0[kMaxLevels + 1];   // interpolation-transpose blocks (deposit items)
   int64_t fin_blk0[kMaxLevels + 1];    // GMF-cell blocks
-  int64_t part_blk0[kMaxLevels + 1];   // sorted-list blocks
   const V4<T>* fld[kMaxLevels];        // forward composed fields
   double* fbar[kMaxLevels];            // field cotangents, FP64: 4 per field cell, or
                                        // the Phi one alone (dense) when c0 == 3
@@ -261,11 +308,12 @@ template <typename T> struct AdjIO {
   double* pgas_bar[kMaxLevels];        // the parent level's gas cotangent, or null
   // Per-entry partial results, in the working precision T (each is one term of a
   // sum over at most a few levels, formed in FP64 and rounded once), stored at the
-  // entry's tile-sorted position on its level (coalesced):
-  V4<T>* pint[kMaxLevels];             // per level: the interpolation transpose's
-                                       // position gradient (x, y, z; owned entries)
+  // entry's position in the sorted list (coalesced):
+  V4<T>* pint;                         // the interpolation transpose's position gradient
+                                       // (x, y, z; owned entries)
   V4<T>* plev[kMaxLevels];             // per level: the deposit transpose's
-                                       // (mbar, xbar, ybar, zbar) (binned entries)
+                                       // (mbar, xbar, ybar, zbar) (entries of the level's
+                                       // tiles)
   const double* rbar;                  // periodic: device scalar, the cotangent of the
                                        // average density (added to every in-domain
                                        // particle's mass cotangent); else null
@@ -286,8 +334,8 @@ template <typename T> hipError_t launch_adj_deposit_grid(const AdjIO<T>& io, con
 template <typename T> hipError_t launch_adj_deposit_particles(const AdjIO<T>& io,
                                                               const DepLevel* tab, hipStream_t s);
 template <typename T> hipError_t launch_adj_finish(const AdjIO<T>& io, const DepLevel* tab,
-                                                   const int32_t* owner, const T* pot, T* xb,
-                                                   T* yb, T* zb, T* mb, hipStream_t s);
+                                                   const T* pot, T* xb, T* yb, T* zb, T* mb,
+                                                   hipStream_t s);
 template <typename T> hipError_t launch_to_t(const double* a, T* b, int64_t n, hipStream_t s);
 hipError_t launch_add_scalar(double* a, int64_t n, const double* s, double scale, hipStream_t st);
 

@@ -1,19 +1,17 @@
-// Particle-side kernels: binning, TSC deposit (Sec. 2), owner grid, TSC
+// Particle-side kernels: tile runs, TSC deposit (Sec. 2), owner grid, TSC
 // interpolation.
 //
-// Deposit design: particles are counted into 8^3-cell tiles of their cell
-// i0 = floor(x / dx_l) over the level's binning box (union of the level's GMF boxes
-// grown by one cell), with block-aggregated atomics (one global atomic per distinct
-// tile in a block of 2048 particles), and scattered tile by tile as 16 B records (s_x, s_y, s_z, m),
-// s = x/dx - binning-box origin, plus the original index.  A work item is one tile's chunk of at most kChunk
-// particles; its block counting-sorts the chunk by cell, sums the 27 TSC
-// contributions of each same-cell run in registers, adds them to a 10^3
-// halo-extended tile in LDS with FP64 atomics, then adds the non-zero cells to an
-// FP64 key-box grid with global atomics.  A finalize pass divides by dx^3,
-// adds the gas and writes the GMF in the working precision.  Heavy tiles (a
-// Plummer core holds ~1e5 particles per tile on the root) are split across many
-// blocks, so the load is balanced; FP64 accumulation keeps the result at the
-// working precision's rounding of the exact sum.
+// Deposit design: the particles, sorted once by the Morton code of their tile
+// (sort.hip), form one contiguous run per 8^3-cell tile on every level; the tiles of a
+// level are those covering its binning box (the union of its GMF boxes grown by one
+// cell).  A work item is one tile's chunk of at most kChunk particles; its block
+// counting-sorts the chunk by cell, sums the 27 TSC contributions of each same-cell
+// run in registers, adds them to a 10^3 halo-extended tile in LDS with FP64 atomics,
+// then adds the non-zero cells to an FP64 key-box grid with global atomics.  A finalize
+// pass divides by dx^3, adds the gas and writes the GMF in the working precision.
+// Heavy tiles (a Plummer core holds ~1e5 particles per tile on the root) are split
+// across many blocks, so the load is balanced; FP64 accumulation keeps the result at
+// the working precision's rounding of the exact sum.
 #include <algorithm>
 
 #include "apm_kernels.hpp"
@@ -95,13 +93,14 @@ __device__ __forceinline__ V4<T> tsc_gather(const V4<T>* __restrict__ F, int nx,
   return acc;
 }
 
-// ---- clear: counters and FP64 mass grids of every level of the batch ---------------
+// ---- clear: tile runs and FP64 mass grids of every level of the batch ------------------
 __global__ void __launch_bounds__(kBlock) k_dep_clear(const DepLevel* __restrict__ tab) {
   const DepLevel& L = tab[blockIdx.y];
-  const int64_t ncount = (int64_t)L.ntiles * L.rep + 1;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ncount; i += stride)
-    L.count[i] = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < L.ntiles; i += stride) {
+    L.tbegin[i] = 0;
+    L.tend[i] = 0;
+  }
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < L.key_cells; i += stride)
     L.accum[i] = 0.0;
 }
@@ -114,107 +113,11 @@ hipError_t launch_dep_clear(const DepLevel* tab, int nlev, int64_t max_elems, hi
   return hipGetLastError();
 }
 
-// ---- tile counting ------------------------------------------------------------------
-// Block-aggregated: each block takes kBinPer particles per thread, inserts their tile
-// keys into an LDS hash table (linear probing, CAS), takes local ranks from LDS
-// atomics, then reserves one range per distinct tile with a single global atomic on
-// the block's replica of that tile's counter.  A tile holding many particles (the
-// Plummer core) thus sees one global atomic per block, not one per particle.
-// blockIdx.y = level of the batch.
-constexpr int kBinPer = 8;
-constexpr int kBinBlockParticles = kBlock * kBinPer;     // 2048
-constexpr int kHash = 2 * kBinBlockParticles;            // load factor <= 1/2
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_bin_count(DepIO<T> io, const DepLevel* __restrict__ tab) {
-  __shared__ int32_t hkey[kHash];
-  __shared__ int32_t hcnt[kHash];
-  const DepLevel& L = tab[blockIdx.y];
-  for (int h = threadIdx.x; h < kHash; h += kBlock) { hkey[h] = -1; hcnt[h] = 0; }
-  __syncthreads();
-  const int32_t rep = L.rep;
-  const int32_t r = (int32_t)(blockIdx.x & (rep - 1));
-  const int64_t base = (int64_t)blockIdx.x * kBinBlockParticles + threadIdx.x;
-  const T sc = (T)L.inv_dx;
-  int32_t key[kBinPer], slot[kBinPer], lrank[kBinPer];
-  T px[kBinPer], py[kBinPer], pz[kBinPer];
-#pragma unroll
-  for (int q = 0; q < kBinPer; ++q) {                // all loads before the hashing
-    const int64_t i = base + (int64_t)q * kBlock;
-    const bool ok = i < io.npart;
-    px[q] = ok ? io.x[i] : (T)-1;
-    py[q] = ok ? io.y[i] : (T)-1;
-    pz[q] = ok ? io.z[i] : (T)-1;
-  }
-#pragma unroll
-  for (int q = 0; q < kBinPer; ++q) {
-    key[q] = -1;
-    slot[q] = -1;
-    lrank[q] = 0;
-    {
-      const T x = px[q], y = py[q], z = pz[q];
-      if (in_domain(x, y, z)) {
-        const int ix = (int)floor(x * sc) - L.key_lo[0];
-        const int iy = (int)floor(y * sc) - L.key_lo[1];
-        const int iz = (int)floor(z * sc) - L.key_lo[2];
-        if (ix >= 0 && ix < L.key_n[0] && iy >= 0 && iy < L.key_n[1] && iz >= 0 && iz < L.key_n[2])
-          key[q] = ((iz / kTile) * L.tiles_n[1] + iy / kTile) * L.tiles_n[0] + ix / kTile;
-      }
-    }
-    if (key[q] >= 0) {
-      int h = (int)(((uint32_t)key[q] * 2654435761u) >> 19) & (kHash - 1);
-      while (true) {                                   // table never full: terminates
-        const int32_t old = atomicCAS(&hkey[h], -1, key[q]);
-        if (old == -1 || old == key[q]) break;
-        h = (h + 1) & (kHash - 1);
-      }
-      slot[q] = h;
-      lrank[q] = atomicAdd(&hcnt[h], 1);
-    }
-  }
-  __syncthreads();
-  {
-    // one range per distinct tile: all of this thread's global atomics are issued
-    // before any of their results is waited for
-    static_assert(kHash % kBlock == 0, "whole hash slots per thread");
-    constexpr int kSlots = kHash / kBlock;
-    const gmut<int32_t> cnt = as_global_mut<int32_t>(L.count);
-    int32_t n[kSlots], base[kSlots];
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k) n[k] = hcnt[threadIdx.x + k * kBlock];
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k)
-      base[k] = n[k] > 0 ? global_add(cnt + hkey[threadIdx.x + k * kBlock] * rep + r, n[k]) : 0;
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k)
-      if (n[k] > 0) hcnt[threadIdx.x + k * kBlock] = base[k];   // becomes the base
-  }
-  __syncthreads();
-  const gmut<int32_t> kout = as_global_mut<int32_t>(L.key), rout = as_global_mut<int32_t>(L.rank);
-#pragma unroll
-  for (int q = 0; q < kBinPer; ++q) {
-    const int64_t i = base + (int64_t)q * kBlock;
-    if (i < io.npart) {
-      kout[i] = key[q] < 0 ? -1 : key[q] * rep + r;           // counter slot
-      rout[i] = key[q] < 0 ? 0 : hcnt[slot[q]] + lrank[q];
-    }
-  }
-}
-
-template <typename T>
-hipError_t launch_bin_count(const DepIO<T>& io, const DepLevel* tab, hipStream_t s) {
-  if (io.npart == 0 || io.nlev == 0) return hipSuccess;
-  const unsigned nb = (unsigned)((io.npart + kBinBlockParticles - 1) / kBinBlockParticles);
-  hipLaunchKernelGGL((k_bin_count<T>), dim3(nb, (unsigned)io.nlev), dim3(kBlock), 0, s, io, tab);
-  return hipGetLastError();
-}
-
 // ---- per-level scans ------------------------------------------------------------------
-// The replica counters, in tile-major order, become start offsets in place (entry
-// ntiles * rep becomes the binned total); each tile's work items, ceil(tile count /
-// kChunk), get item starts and work-table entries.  Three short launches, all levels
-// in each: per-block sums over kScanTiles tiles (one tile per thread), a scan of
-// those sums per level, then every block scans its own tiles from its offset.
+// Each tile's work items, ceil(tile count / kChunk), get item starts and work-table
+// entries.  Three short launches, all levels in each: per-block sums over kScanTiles
+// tiles (one tile per thread), a scan of those sums per level, then every block scans
+// its own tiles from its offset.
 constexpr int kScanTiles = 256;                      // tiles per block (one per thread)
 constexpr int kScanThreads = 1024;                   // threads of the per-level scan
 
@@ -244,22 +147,10 @@ __device__ static int2 block_scan2(int2 v, int32_t* sh, int2* tot) {
   return make_int2(base.x + inc.x - v.x, base.y + inc.y - v.y);
 }
 
-// tile t's count (sum of its replicas) and work items
+// tile t's particle count and work items
 __device__ __forceinline__ int2 tile_count(const DepLevel& L, int32_t t) {
-  int32_t tot = 0;
-  if (t < L.ntiles) {
-    const int rep = L.rep;                           // power of two, <= kMaxRep
-    const int32_t* c = L.count + (int64_t)t * rep;
-    if (rep >= 4) {
-      for (int k = 0; k < rep / 4; ++k) {
-        const int4 q = reinterpret_cast<const int4*>(c)[k];
-        tot += q.x + q.y + q.z + q.w;
-      }
-    } else {
-      for (int r = 0; r < rep; ++r) tot += c[r];
-    }
-  }
-  return make_int2(tot, (tot + kChunk - 1) / kChunk);
+  const int32_t n = t < L.ntiles ? L.tend[t] - L.tbegin[t] : 0;
+  return make_int2(n, (n + kChunk - 1) / kChunk);
 }
 
 __global__ void __launch_bounds__(kScanTiles) k_scan_tiles(const DepLevel* __restrict__ tab) {
@@ -286,11 +177,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_blocks(const DepLevel* __
     carry.x += tot.x;
     carry.y += tot.y;
   }
-  if (threadIdx.x == 0) {
-    L.count[(int64_t)L.ntiles * L.rep] = carry.x;
-    L.items[L.ntiles] = carry.y;
-    *L.binned = carry.x;
-  }
+  if (threadIdx.x == 0) L.items[L.ntiles] = carry.y;
 }
 
 __global__ void __launch_bounds__(kScanTiles) k_scan_emit(const DepLevel* __restrict__ tab) {
@@ -302,16 +189,8 @@ __global__ void __launch_bounds__(kScanTiles) k_scan_emit(const DepLevel* __rest
   int2 tot;
   const int2 ex = block_scan2<kScanTiles>(c, sh, &tot);
   if (t >= L.ntiles) return;
-  const int2 off = L.bsum[blockIdx.x];
-  const int32_t start = off.x + ex.x, istart = off.y + ex.y;
-  const int rep = L.rep;
-  int32_t o = start;
-  int32_t* cnt = L.count + (int64_t)t * rep;
-  for (int r = 0; r < rep; ++r) {                    // replica starts (tile-major), in place
-    const int32_t n = cnt[r];
-    cnt[r] = o;
-    o += n;
-  }
+  const int32_t istart = L.bsum[blockIdx.x].y + ex.y;
+  const int32_t start = L.tbegin[t];
   L.items[t] = istart;
   for (int32_t q = 0; q < c.y; ++q) {                // the tile's work items
     const int32_t b = start + q * kChunk;
@@ -325,49 +204,6 @@ hipError_t launch_bin_scan(const DepLevel* tab, int nlev, int32_t max_tiles, hip
   hipLaunchKernelGGL(k_scan_tiles, dim3(nb, (unsigned)nlev), dim3(kScanTiles), 0, s, tab);
   hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nlev), dim3(kScanThreads), 0, s, tab);
   hipLaunchKernelGGL(k_scan_emit, dim3(nb, (unsigned)nlev), dim3(kScanTiles), 0, s, tab);
-  return hipGetLastError();
-}
-
-// ---- scatter into tile order --------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_bin_scatter(DepIO<T> io, const DepLevel* __restrict__ tab) {
-  const DepLevel& L = tab[blockIdx.y];
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= io.npart) return;
-  const int32_t key = as_global<int32_t>(L.key)[i];
-  // the root level bins every in-domain particle (key >= 0 exactly for those), so its
-  // blocks write the owner of every particle
-  const bool root = io.owner_out != nullptr && L.first == 0;
-  if (key < 0) {
-    if (root) io.owner_out[i] = -1;
-    return;
-  }
-  const T px = io.x[i], py = io.y[i], pz = io.z[i];
-  const T sc = (T)L.inv_dx;
-  V4<T> r;
-  r.x = px * sc;                                     // exact: dx is a power of two
-  r.y = py * sc;
-  r.z = pz * sc;
-  r.w = io.m[i];
-  int32_t og = -1;
-  if (io.om) {                                       // as k_owner (in-domain: key >= 0)
-    const int32_t o = owner_lookup(io.om, io.om_nlev, px, py, pz);
-    if (root) io.owner_out[i] = o;
-    if (o >= L.first && o < L.first + L.ngrids) og = o;
-  } else if (io.owner) {
-    const int32_t o = io.owner[i];
-    if (o >= L.first && o < L.first + L.ngrids) og = o;
-  }
-  const int32_t slot = as_global<int32_t>(L.count)[key] + as_global<int32_t>(L.rank)[i];
-  as_global_mut<nvec4<T>>(L.sorted)[slot] = nvec4<T>{r.x, r.y, r.z, r.w};
-  as_global_mut<nvec2<int32_t>>(L.sref)[slot] = nvec2<int32_t>{(int32_t)i, og};
-}
-
-template <typename T>
-hipError_t launch_bin_scatter(const DepIO<T>& io, const DepLevel* tab, hipStream_t s) {
-  if (io.npart == 0 || io.nlev == 0) return hipSuccess;
-  const unsigned nb = (unsigned)((io.npart + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_bin_scatter<T>), dim3(nb, (unsigned)io.nlev), dim3(kBlock), 0, s, io, tab);
   return hipGetLastError();
 }
 
@@ -405,15 +241,15 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
   const int n = (int)(end - begin);                  // 1 .. kChunk
   for (int c = threadIdx.x; c < kTH3; c += kBlock) acc[c] = 0.0;
   for (int c = threadIdx.x; c < kCells; c += kBlock) cstart[c] = 0;
-  const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
-            oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;
+  int ox, oy, oz;
+  tile_origin(L, tile, ox, oy, oz);
   const int bx = L.key_lo[0] + ox, by = L.key_lo[1] + oy, bz = L.key_lo[2] + oz;
   static_assert(kChunk == 8 * kBlock, "a chunk is eight records per thread");
   V4<T> rec[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {                      // the whole chunk's loads first
     const int64_t q = begin + threadIdx.x + (int64_t)k * kBlock;
-    rec[k] = load_v4<T>(L.sorted, q < end ? q : begin);   // begin < end: a valid record
+    rec[k] = level_rec<T>(L, q < end ? q : begin);   // begin < end: a valid record
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) pin4(rec[k]);
@@ -444,7 +280,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
     }
   } else {
     // counting sort of the chunk by cell of the tile (cells clamped into the tile
-    // defensively; every binned particle's cell is inside its tile)
+    // defensively; every particle of a tile's run has its cell inside the tile)
     int cell[8], rk[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -509,7 +345,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int e = min((int)threadIdx.x * 8 + j, n - 1);
-      sv[j] = load_v4<T>(L.sorted, begin + sidx[e]);
+      sv[j] = level_rec<T>(L, begin + sidx[e]);
     }
     for (int j = 0; j < 8; ++j) {
       const int e = (int)threadIdx.x * 8 + j;
@@ -700,8 +536,8 @@ __global__ void __launch_bounds__(kBlock) k_interp_tiles(InterpIO<T> io, const D
   if (item >= total) return;                        // uniform for the block
   const int tile = wk.x;
   const int64_t begin = wk.y, end = wk.z;
-  const int ox = (tile % L.tiles_n[0]) * kTile, oy = ((tile / L.tiles_n[0]) % L.tiles_n[1]) * kTile,
-            oz = (tile / (L.tiles_n[0] * L.tiles_n[1])) * kTile;
+  int ox, oy, oz;
+  tile_origin(L, tile, ox, oy, oz);
   // staged when the level has one grid and the chunk is not sparse (a few entries
   // read fewer bytes with their own gathers than the 10^3 tile)
   const bool staged = L.ngrids == 1 && end - begin >= 64;   // uniform for the block
@@ -731,14 +567,14 @@ __global__ void __launch_bounds__(kBlock) k_interp_tiles(InterpIO<T> io, const D
   for (int k = 0; k < 8; ++k) {
     const int64_t q = begin + threadIdx.x + (int64_t)k * kBlock;
     if (q >= end) break;
-    const int2 r = load_i2(L.sref, q);
+    const int2 r = level_ref(L, q);
     if (r.y < 0) continue;
-    const V4<T> v = load_v4<T>(L.sorted, q);
+    const V4<T> v = level_rec<T>(L, q);
     const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
     const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
     V4<T> a;
     if (staged) {
-      // the entry's cell inside the tile (binned there; clamped defensively)
+      // the entry's cell inside the tile (its run's tile; clamped defensively)
       const int ix = min(max((int)fx - bx, 0), kTile - 1), iy = min(max((int)fy - by, 0), kTile - 1),
                 iz = min(max((int)fz - bz, 0), kTile - 1);
       const T wx[3] = {tsc_w(-1, tx), tsc_w(0, tx), tsc_w(1, tx)};
@@ -805,8 +641,6 @@ hipError_t launch_unpack(const InterpIO<T>& io, const DepLevel* tab, const int32
 
 
 #define APM_INST(T)                                                                          \
-  template hipError_t launch_bin_count<T>(const DepIO<T>&, const DepLevel*, hipStream_t);      \
-  template hipError_t launch_bin_scatter<T>(const DepIO<T>&, const DepLevel*, hipStream_t);    \
   template hipError_t launch_deposit_tiles<T>(const DepIO<T>&, const DepLevel*, hipStream_t);  \
   template hipError_t launch_deposit_finalize<T>(const DepIO<T>&, const DepLevel*, hipStream_t); \
   template hipError_t launch_owner<T>(const OwnerLevel*, int32_t, const T*, const T*, const T*, \

@@ -125,6 +125,12 @@ apm_status build_plan(const apm_config& cfg, const apm_grid* grids, int32_t ngri
     }
     P.grids.push_back(d);
   }
+  // the particle sort keys a particle by its 8^3-cell tile on the finest level, 21
+  // bits per axis in a 64-bit Morton code
+  if (((int64_t)N << maxlev) > ((int64_t)1 << 24)) {
+    e << "finest level has " << ((int64_t)N << maxlev) << " cells per axis (at most 2^24)";
+    return fail(APM_ERR_RANGE, e.str());
+  }
   // levels: grids are sorted, so each level is a contiguous range
   P.levels.resize(maxlev + 1);
   for (auto& L : P.levels) { L = LevelDesc{}; L.first = -1; }

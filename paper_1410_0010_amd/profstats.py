@@ -27,11 +27,14 @@ FAMILY = {
     "k_adj_x": "adj_fft_x", "k_adjp_x": "adj_fft_x", "k_adj_y": "adj_fft_y", "k_adjp_y": "adj_fft_y",
     "k_adj_z": "adj_fft_z", "k_adjp_z": "adj_fft_z", "k_adj_y_inv": "adj_fft_y_inv",
     "k_adj_x_inv": "adj_fft_x_inv",
-    "k_dep_clear": "bin_clear", "k_bin_count": "bin_count", "k_scan_tiles": "bin_scan",
+    "k_dep_clear": "bin_clear", "k_scan_tiles": "bin_scan",
+    "k_sort_keys": "sort", "k_radix_hist": "sort", "k_hscan_reduce": "sort", "k_hscan_mid": "sort",
+    "k_hscan_down": "sort", "k_radix_scatter": "sort", "k_sort_gather": "sort",
+    "k_tile_ranges": "tile_ranges",
     "k_scan_blocks": "bin_scan", "k_scan_emit": "bin_scan",
     "k_adj_interp_grad": "adj_interp", "k_totals_parts": "totals", "k_particle_totals": "totals",
     "k_totals_finish": "totals",
-    "k_bin_scatter": "bin_scatter", "k_deposit_tiles": "deposit_tiles",
+    "k_deposit_tiles": "deposit_tiles",
     "k_deposit_finalize": "deposit_finalize", "k_owner": "owner", "k_compose": "compose",
     "k_interp_tiles": "interp", "k_interp": "interp", "k_unpack": "unpack",
     "k_adj_interp": "adj_interp", "k_adj_deposit_particles": "adj_deposit_particles",
