@@ -97,7 +97,8 @@ def kernel_bytes(plan, npart, npart_level, esize, root_gas=False, pot_only_adjoi
     names = ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv", "deposit_tiles",
              "deposit_finalize", "compose", "interp", "unpack", "sort", "tile_ranges",
              "adj_fft_x", "adj_fft_y", "adj_fft_z", "adj_fft_y_inv", "adj_fft_x_inv",
-             "adj_interp", "adj_deposit_grid", "adj_deposit_particles", "adj_restrict")
+             "adj_interp", "adj_deposit_grid", "adj_deposit_particles", "adj_restrict",
+             "adj_finish")
     b = {k: 0.0 for k in names}
     nz, ny, tv = conv_arrays(plan)
     for g in plan.grids:
@@ -145,6 +146,10 @@ def kernel_bytes(plan, npart, npart_level, esize, root_gas=False, pot_only_adjoi
         N = plan.grids[0]["n"][0]
         b["mean_density"] = npart * 4 * esize + (N ** 3 * esize if root_gas else 0)
     b["adj_interp"] = binned * (4 * esize + 8) + npart * (esize + 3 * 8)
+    # sorted reference and record, each level's and the interpolation's terms, the
+    # potential, the record out; then the records and owners in, four arrays out
+    b["adj_finish"] = (npart * (8 + 4 * esize + 4 * esize + esize + 4 * esize) + binned * 4 * esize
+                       + npart * (4 * esize + 4 + 4 * esize))
     b["owner"] = npart * (3 * esize + 4)                # positions in, owner out
     b["totals"] = (sum(L["gmf_elems"] for L in plan.levels) * esize
                    + npart * (5 * esize + 4))           # GMFs, m, a, Phi, owner

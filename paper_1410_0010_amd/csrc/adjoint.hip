@@ -616,41 +616,53 @@ hipError_t launch_adj_deposit_particles(const AdjIO<T>& io, const DepLevel* tab,
 // One thread per entry q of the sorted list, for particle i = its original index:
 // mbar, xbar = the sum over the levels whose tiles hold the particle of the deposit
 // transpose, plus the interpolation transpose's position gradient and wbar Phi_p / 2
-// (mass) for owned particles; written at i.  A level's tiles hold the particle when
-// its tile floor(x / dx) / kTile lies in the level's tile box, as the tile runs do.
+// (mass) for owned particles, formed in FP64 and rounded once into the record
+// pout[i] (one 16 B write a particle; the four output arrays are then written
+// coalesced by k_adj_unpack).  A level's tiles hold the particle when its tile
+// floor(x / dx) / kTile lies in the level's tile box, as the tile runs do.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_adj_finish(AdjIO<T> io, const DepLevel* __restrict__ tab, const T* __restrict__ pot,
-             T* __restrict__ xb, T* __restrict__ yb, T* __restrict__ zb, T* __restrict__ mb) {
+k_adj_finish(AdjIO<T> io, const DepLevel* __restrict__ tab, const T* __restrict__ pot) {
   const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (q >= io.npart) return;
   const int2 r = load_i2(tab[0].sref, q);
+  if (r.y < 0) return;                               // outside the domain: zero (unpack)
   const int64_t i = r.x;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  if (r.y >= 0) {                                    // in the domain
-    const V4<T> w = load_v4<T>(tab[0].sorted, q);
-    for (int l = 0; l < io.nlev; ++l) {
-      const DepLevel& L = tab[l];
-      const T sc = (T)L.inv_dx;
-      const int cx = (int)floor(w.x * sc), cy = (int)floor(w.y * sc), cz = (int)floor(w.z * sc);
-      const int tx = (cx >> 3) - L.tile_lo[0], ty = (cy >> 3) - L.tile_lo[1],
-                tz = (cz >> 3) - L.tile_lo[2];
-      static_assert(kTile == 8, "tile index by shift");
-      if (tx < 0 || tx >= L.tiles_n[0] || ty < 0 || ty >= L.tiles_n[1] || tz < 0 ||
-          tz >= L.tiles_n[2])
-        continue;
-      const V4<T> o = load_v4<T>(io.plev[l], q);
-      s0 += (double)o.x; s1 += (double)o.y; s2 += (double)o.z; s3 += (double)o.w;
-    }
-    const V4<T> pi = load_v4<T>(io.pint, q);
-    s1 += (double)pi.x; s2 += (double)pi.y; s3 += (double)pi.z;
-    if (io.wbar != 0.0 && pot) s0 += io.wbar * 0.5 * (double)pot[i];
-    if (io.rbar) s0 += as_global<double>(io.rbar)[0];   // periodic: the average density's
+  const V4<T> w = load_v4<T>(tab[0].sorted, q);
+  for (int l = 0; l < io.nlev; ++l) {
+    const DepLevel& L = tab[l];
+    const T sc = (T)L.inv_dx;
+    const int cx = (int)floor(w.x * sc), cy = (int)floor(w.y * sc), cz = (int)floor(w.z * sc);
+    static_assert(kTile == 8, "tile index by shift");
+    const int tx = (cx >> 3) - L.tile_lo[0], ty = (cy >> 3) - L.tile_lo[1],
+              tz = (cz >> 3) - L.tile_lo[2];
+    if (tx < 0 || tx >= L.tiles_n[0] || ty < 0 || ty >= L.tiles_n[1] || tz < 0 ||
+        tz >= L.tiles_n[2])
+      continue;
+    const V4<T> o = load_v4<T>(io.plev[l], q);
+    s0 += (double)o.x; s1 += (double)o.y; s2 += (double)o.z; s3 += (double)o.w;
   }
-  if (mb) mb[i] = (T)s0;
-  if (xb) xb[i] = (T)s1;
-  if (yb) yb[i] = (T)s2;
-  if (zb) zb[i] = (T)s3;
+  const V4<T> pi = load_v4<T>(io.pint, q);
+  s1 += (double)pi.x; s2 += (double)pi.y; s3 += (double)pi.z;
+  if (io.wbar != 0.0 && pot) s0 += io.wbar * 0.5 * (double)pot[i];
+  if (io.rbar) s0 += as_global<double>(io.rbar)[0];   // periodic: the average density's
+  io.pout[i] = V4<T>{(T)s0, (T)s1, (T)s2, (T)s3};
+}
+
+// The records -> the four gradient arrays (zero outside the domain: owner < 0).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_adj_unpack(const V4<T>* __restrict__ pout, const int32_t* __restrict__ owner, int64_t n,
+             T* __restrict__ xb, T* __restrict__ yb, T* __restrict__ zb, T* __restrict__ mb) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const V4<T> r = load_v4<T>(pout, i);
+  const V4<T> v = owner[i] >= 0 ? r : V4<T>{0, 0, 0, 0};
+  if (mb) mb[i] = v.x;
+  if (xb) xb[i] = v.y;
+  if (yb) yb[i] = v.z;
+  if (zb) zb[i] = v.w;
 }
 
 // a[i] += scale * s[0] for i < n (a periodic root's gas cotangent: the average
@@ -669,11 +681,13 @@ hipError_t launch_add_scalar(double* a, int64_t n, const double* s, double scale
 }
 
 template <typename T>
-hipError_t launch_adj_finish(const AdjIO<T>& io, const DepLevel* tab, const T* pot, T* xb, T* yb,
-                             T* zb, T* mb, hipStream_t s) {
+hipError_t launch_adj_finish(const AdjIO<T>& io, const DepLevel* tab, const int32_t* owner,
+                             const T* pot, T* xb, T* yb, T* zb, T* mb, hipStream_t s) {
   if (io.npart == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_adj_finish<T>), dim3((unsigned)((io.npart + kBlock - 1) / kBlock)),
-                     dim3(kBlock), 0, s, io, tab, pot, xb, yb, zb, mb);
+  const unsigned nb = (unsigned)((io.npart + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((k_adj_finish<T>), dim3(nb), dim3(kBlock), 0, s, io, tab, pot);
+  hipLaunchKernelGGL((k_adj_unpack<T>), dim3(nb), dim3(kBlock), 0, s, io.pout, owner, io.npart, xb,
+                     yb, zb, mb);
   return hipGetLastError();
 }
 
@@ -701,8 +715,8 @@ hipError_t launch_to_t(const double* a, T* b, int64_t n, hipStream_t s) {
   template hipError_t launch_adj_deposit_grid<T>(const AdjIO<T>&, const DepLevel*, hipStream_t); \
   template hipError_t launch_adj_deposit_particles<T>(const AdjIO<T>&, const DepLevel*,        \
                                                       hipStream_t);                            \
-  template hipError_t launch_adj_finish<T>(const AdjIO<T>&, const DepLevel*, const T*, T*, T*, \
-                                           T*, T*, hipStream_t);                                \
+  template hipError_t launch_adj_finish<T>(const AdjIO<T>&, const DepLevel*, const int32_t*,    \
+                                           const T*, T*, T*, T*, T*, hipStream_t);              \
   template hipError_t launch_to_t<T>(const double*, T*, int64_t, hipStream_t);
 APM_INST_A(float)
 APM_INST_A(double)

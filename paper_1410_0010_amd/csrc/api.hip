@@ -572,8 +572,8 @@ int sort_bits(const Plan& P, int lf) {
   while ((n >> (b + 3)) > 1) ++b;
   return 3 * b;
 }
-// ping-pong slot of the sorted keys: one pass per 8 of the nbits + 1 key bits
-int sort_slot(int nbits) { return ((nbits + 8) / 8) & 1; }
+// ping-pong slot of the sorted keys
+int sort_slot(int nbits) { return sort_passes(nbits) & 1; }
 
 // Buffers and arguments of the particle sort by tiles of level lf; owner (or null: no
 // owners) receives every particle's owner grid.
@@ -1223,8 +1223,8 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
                      "gas cotangents"));
   }
   // per sorted entry, a 4-vector of T for each level's deposit transpose and one for
-  // the interpolation transpose
-  APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * sizeof(V4<T>) * (nl + 1),
+  // the interpolation transpose; per particle, the gradient record
+  APM_TRY(ensure(c, c->adj_pacc, (size_t)std::max<int64_t>(n, 1) * sizeof(V4<T>) * (nl + 2),
                  "particle cotangents"));
   ZeroList zl{};
   hipError_t zerr = hipSuccess;
@@ -1249,6 +1249,7 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
   V4<T>* pacc = (V4<T>*)c->adj_pacc.p;
   for (int l = 0; l < nl; ++l) io.plev[l] = pacc + (int64_t)n * l;
   io.pint = pacc + (int64_t)n * nl;
+  io.pout = pacc + (int64_t)n * (nl + 1);
   int64_t iblk = 0, fblk = 0;
   for (int l = 0; l < nl; ++l) {
     const DepLevel& d = c->dep_host[l];
@@ -1328,7 +1329,8 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
             return launch_adj_deposit_particles<T>(io, tab, c->stream);
           }), "deposit transpose (particles)");
   HIP_TRY(timed(c, "adj_finish", [&] {
-            return launch_adj_finish<T>(io, tab, pot, xb, yb, zb, mb, c->stream);
+            return launch_adj_finish<T>(io, tab, (const int32_t*)c->owner.p, pot, xb, yb, zb, mb,
+                                        c->stream);
           }), "adjoint outputs");
   if (gas_bar) {
     for (int l = 0; l < nl; ++l) {

@@ -212,23 +212,27 @@ template <typename T> struct SortIO {
   const T* x; const T* y; const T* z; const T* m;
   int64_t npart;
   double cells_f;                      // cells per axis of the sort's finest level
-  int32_t nbits;                       // Morton bits of its tiles (3 per axis); the key of a
-                                       // particle outside [0, 1)^3 is 1 << nbits, after all
+  int32_t nbits;                       // Morton bits of its tiles (3 per axis)
   const OwnerLevel* om;                // owner lookup of every level, or null (no owners:
   int32_t om_nlev;                     // the sorted references hold -1)
   int32_t* owner;                      // out (with om): owner grid per particle, -1 outside
   void* key[2];                        // npart each: ping-pong keys
-  int32_t* idx[2];                     // npart each: ping-pong original indices
-  void* prec;                          // npart records (x, y, z, m) in input order
-  uint32_t* hist;                      // 256 ceil(npart / kRadixTile): digit counts, then
-                                       // their exclusive scan (digit-major)
+  int32_t* idx[2];                     // npart each: ping-pong original indices (their
+                                       // complement for particles outside [0, 1)^3)
+  void* prec;                          // npart records (x, y, z, m) in input order (outside
+                                       // [0, 1)^3: a point of the last tile, mass 0)
+  uint32_t* hist;                      // sort_hist_elems(npart): digit counts, then their
+                                       // exclusive scan (digit-major)
   uint32_t* hsum;                      // scan partials, sort_sum_elems(npart)
   void* sorted;                        // out: npart records (x, y, z, m), sorted
   int2* sref;                          // out: npart (original index, owner grid)
 };
 int64_t sort_hist_elems(int64_t npart);
 int64_t sort_sum_elems(int64_t npart);
-inline bool sort_key64(int nbits) { return nbits >= 32; }
+inline bool sort_key64(int nbits) { return nbits > 32; }
+// radix passes of at most 9 bits over the nbits key bits; the sorted keys end in
+// ping-pong slot passes % 2
+inline int sort_passes(int nbits) { return (nbits + 8) / 9; }
 // The whole sort on s; *which gets the ping-pong slot (0 or 1) holding the sorted keys.
 template <typename T> hipError_t launch_particle_sort(const SortIO<T>& io, int* which,
                                                       hipStream_t s);
@@ -314,6 +318,8 @@ template <typename T> struct AdjIO {
   V4<T>* plev[kMaxLevels];             // per level: the deposit transpose's
                                        // (mbar, xbar, ybar, zbar) (entries of the level's
                                        // tiles)
+  V4<T>* pout;                         // per particle (original index): the gradient
+                                       // record (mbar, xbar, ybar, zbar)
   const double* rbar;                  // periodic: device scalar, the cotangent of the
                                        // average density (added to every in-domain
                                        // particle's mass cotangent); else null
@@ -333,9 +339,11 @@ template <typename T> hipError_t launch_adj_deposit_grid(const AdjIO<T>& io, con
                                                          hipStream_t s);
 template <typename T> hipError_t launch_adj_deposit_particles(const AdjIO<T>& io,
                                                               const DepLevel* tab, hipStream_t s);
+// the particle gradients (two launches: sums in sorted order into io.pout, then the
+// four arrays in particle order, zero where owner < 0); any output may be null
 template <typename T> hipError_t launch_adj_finish(const AdjIO<T>& io, const DepLevel* tab,
-                                                   const T* pot, T* xb, T* yb, T* zb, T* mb,
-                                                   hipStream_t s);
+                                                   const int32_t* owner, const T* pot, T* xb,
+                                                   T* yb, T* zb, T* mb, hipStream_t s);
 template <typename T> hipError_t launch_to_t(const double* a, T* b, int64_t n, hipStream_t s);
 hipError_t launch_add_scalar(double* a, int64_t n, const double* s, double scale, hipStream_t st);
 

@@ -2,22 +2,25 @@
 // TSC assignment visits particles tile by tile).
 //
 // Each particle gets the Morton code of its kTile^3 tile on the sort's finest level
-// (floor(x N_f) / kTile per axis, bits interleaved with x lowest); a particle outside
-// [0, 1)^3 gets 1 << nbits, after every tile.  A stable least-significant-digit
-// radix sort of (key, index) pairs, 8 bits a pass, orders the particles; a gather
-// then writes the sorted records and references.  A tile s levels coarser holds the
-// finest tiles whose codes share all but the lowest 3 s bits, so its particles form
-// one run of the list; k_tile_ranges finds every level's runs in one read of the
-// sorted keys.
+// (floor(x N_f) / kTile per axis, bits interleaved with x lowest).  A particle outside
+// [0, 1)^3 takes the code of the last tile and a record of zero mass at a point of
+// that tile's last cell, so it adds nothing to any grid, and its owner -1 keeps it out
+// of the interpolation.  A stable least-significant-digit radix sort of (key, index)
+// pairs, at most 9 bits a pass, orders the particles; a gather then writes the sorted
+// records and references.  A tile s levels coarser holds the finest tiles whose codes
+// share all but the lowest 3 s bits, so its particles form one run of the list;
+// k_tile_ranges finds every level's runs in one read of the sorted keys.
 //
 // A pass is three steps: per-block digit counts (kRadixTile keys a block), their
 // exclusive scan in digit-major order (so each block knows where its keys of each
-// digit go), and the scatter: each block ranks its keys stably (wavefront ballots
-// give a lane's rank among the lanes with its digit; the waves and rounds of the
-// block follow input order), sorts them by digit in LDS and writes each digit's run
-// with consecutive threads on consecutive addresses.  Every step reads its input once,
-// with no global atomics: the per-level counting by global atomics that this replaces
-// serialised the many blocks of a dense core on the same few counters.
+// digit go), and the scatter.  There each wave ranks its quarter of the block's keys
+// stably in 16 rounds of 64: wavefront ballots give a lane's rank among the lanes
+// with its digit, and a per-wave count of each digit in LDS carries over between
+// rounds, so no barrier is needed until the block combines its waves' counts; the
+// keys are then sorted by digit in LDS and each digit's run is written with
+// consecutive threads on consecutive addresses.  No global atomics: the per-level
+// counting by global atomics that this replaces serialised the many blocks of a dense
+// core on the same few counters.
 #include <algorithm>
 
 #include "apm_kernels.hpp"
@@ -26,11 +29,12 @@ namespace apm {
 
 namespace {
 
-constexpr int kRadixBits = 8, kDigits = 1 << kRadixBits;
+constexpr int kMaxRadixBits = 9, kMaxDigits = 1 << kMaxRadixBits;
 constexpr int kRadixWaves = kRadixBlock / 64;
-static_assert(kDigits == kRadixBlock, "one digit per thread");
+constexpr int kWaveItems = kRadixTile / kRadixWaves;   // keys per wave (16 rounds of 64)
 constexpr int kScanChunk = 4096;                    // digit counts per scan block
 constexpr int kScanMid = 1024;                      // threads of the partials' scan
+static_assert(kMaxDigits == 2 * kRadixBlock, "two digits per thread");
 
 template <typename K> __device__ __forceinline__ K spread3(uint32_t v, int nb) {
   K r = 0;
@@ -59,28 +63,29 @@ __global__ void __launch_bounds__(kBlock) k_sort_keys(SortIO<T> io) {
   const T x = io.x[i], y = io.y[i], z = io.z[i], m = io.m[i];
   const bool in = in_unit_box(x, y, z);
   const int nb = io.nbits / 3;
-  K key = (K)1 << io.nbits;
-  if (in) {
-    // x N_f is exact (a power of two) and below N_f for x < 1
-    const T s = (T)io.cells_f;
-    const uint32_t tx = (uint32_t)(int32_t)floor(x * s) / kTile,
-                   ty = (uint32_t)(int32_t)floor(y * s) / kTile,
-                   tz = (uint32_t)(int32_t)floor(z * s) / kTile;
-    key = spread3<K>(tx, nb) | (spread3<K>(ty, nb) << 1) | (spread3<K>(tz, nb) << 2);
-  }
+  // outside: the last cell, 1 - 1/N_f per axis (exact for N_f <= 2^24), zero mass
+  const T s = (T)io.cells_f, edge = (T)1 - (T)1 / s;
+  const T px = in ? x : edge, py = in ? y : edge, pz = in ? z : edge;
+  // x N_f is exact (a power of two) and below N_f for x < 1
+  const uint32_t tx = (uint32_t)(int32_t)floor(px * s) / kTile,
+                 ty = (uint32_t)(int32_t)floor(py * s) / kTile,
+                 tz = (uint32_t)(int32_t)floor(pz * s) / kTile;
+  const K key = spread3<K>(tx, nb) | (spread3<K>(ty, nb) << 1) | (spread3<K>(tz, nb) << 2);
   if (io.om) io.owner[i] = in ? owner_lookup(io.om, io.om_nlev, x, y, z) : -1;
   reinterpret_cast<K*>(io.key[0])[i] = key;
-  io.idx[0][i] = (int32_t)i;
-  as_global_mut<nvec4<T>>(io.prec)[i] = nvec4<T>{x, y, z, m};
+  io.idx[0][i] = in ? (int32_t)i : ~(int32_t)i;      // outside: the complement (negative)
+  as_global_mut<nvec4<T>>(io.prec)[i] = nvec4<T>{px, py, pz, in ? m : (T)0};
 }
 
 // ---- per-block digit counts ------------------------------------------------------------
 template <typename K>
 __global__ void __launch_bounds__(kRadixBlock) k_radix_hist(const K* __restrict__ key, int64_t n,
-                                                            int shift, uint32_t* __restrict__ hist,
+                                                            int shift, int rb,
+                                                            uint32_t* __restrict__ hist,
                                                             int64_t nblk) {
-  __shared__ uint32_t h[kDigits];
-  h[threadIdx.x] = 0;
+  __shared__ uint32_t h[kMaxDigits];
+  const int nd = 1 << rb;
+  for (int d = threadIdx.x; d < nd; d += kRadixBlock) h[d] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kRadixTile;
   const gptr<K> kg = as_global<K>(key);
@@ -93,10 +98,10 @@ __global__ void __launch_bounds__(kRadixBlock) k_radix_hist(const K* __restrict_
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
     const int64_t q = base + r * kRadixBlock + threadIdx.x;
-    if (q < n) atomicAdd(&h[(uint32_t)(k[r] >> shift) & (kDigits - 1)], 1u);
+    if (q < n) atomicAdd(&h[(uint32_t)(k[r] >> shift) & (uint32_t)(nd - 1)], 1u);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < nd; d += kRadixBlock) hist[(int64_t)d * nblk + blockIdx.x] = h[d];
 }
 
 // ---- exclusive scan of the counts (three launches) ---------------------------------------
@@ -172,99 +177,117 @@ __global__ void __launch_bounds__(kRadixBlock) k_hscan_down(uint32_t* __restrict
 }
 
 // ---- stable scatter by one digit ------------------------------------------------------------
-// Item j of the block (input position base + j) is handled in round j / kRadixBlock by
-// wave (j % kRadixBlock) / 64, lane j % 64, so (round, wave, lane) order is input order.
+// Key j of the block (input position base + j) is taken by wave j / kWaveItems in round
+// (j % kWaveItems) / 64, lane j % 64: (wave, round, lane) order is input order.
 template <typename K>
 __global__ void __launch_bounds__(kRadixBlock)
 k_radix_scatter(const K* __restrict__ kin, const int32_t* __restrict__ iin, K* __restrict__ kout,
-                int32_t* __restrict__ iout, int64_t n, int shift, const uint32_t* __restrict__ offs,
-                int64_t nblk) {
+                int32_t* __restrict__ iout, int64_t n, int shift, int rb,
+                const uint32_t* __restrict__ offs, int64_t nblk) {
   __shared__ K sk[kRadixTile];
   __shared__ int32_t si[kRadixTile];
-  __shared__ uint32_t wc[kRadixWaves][kDigits];     // per-wave digit counts of a round
-  __shared__ uint32_t run[kDigits];                 // the block's digit counts so far
-  __shared__ uint32_t lstart[kDigits], gstart[kDigits];
+  __shared__ uint32_t wc[kRadixWaves][kMaxDigits];  // per-wave digit counts, then starts
+  __shared__ uint32_t ls[kMaxDigits], gs[kMaxDigits];   // block-local and global digit starts
   __shared__ uint32_t sh[kRadixWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  const int nd = 1 << rb;
+  const uint32_t dmask = (uint32_t)nd - 1;
+  const int64_t blk0 = (int64_t)blockIdx.x * kRadixTile;
+  const int64_t base = blk0 + (int64_t)wave * kWaveItems;
   const gptr<K> kg = as_global<K>(kin);
   const gptr<int32_t> ig = as_global<int32_t>(iin);
   K k[kRadixItems];
   int32_t id[kRadixItems];
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
-    const int64_t q = base + r * kRadixBlock + threadIdx.x;
+    const int64_t q = base + r * 64 + lane;
     k[r] = q < n ? kg[q] : (K)0;
     id[r] = q < n ? ig[q] : 0;
   }
+  for (int d = threadIdx.x; d < nd; d += kRadixBlock) {
 #pragma unroll
-  for (int w = 0; w < kRadixWaves; ++w) wc[w][threadIdx.x] = 0;
-  run[threadIdx.x] = 0;
-  gstart[threadIdx.x] = offs[(int64_t)threadIdx.x * nblk + blockIdx.x];
+    for (int w = 0; w < kRadixWaves; ++w) wc[w][d] = 0;
+    gs[d] = offs[(int64_t)d * nblk + blockIdx.x];
+  }
   __syncthreads();
+  uint32_t* mine = wc[wave];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));   // lanes below this one
   uint32_t rank[kRadixItems];
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
-    const bool valid = base + r * kRadixBlock + threadIdx.x < n;
-    const uint32_t d = (uint32_t)(k[r] >> shift) & (kDigits - 1);
+    const bool valid = base + r * 64 + lane < n;
+    const uint32_t d = (uint32_t)(k[r] >> shift) & dmask;
     uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < rb; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
     }
     const uint32_t lr = (uint32_t)__popcll(peers & lt);
-    if (valid && lr == 0) wc[wave][d] = (uint32_t)__popcll(peers);   // one leader per digit
-    __syncthreads();
-    uint32_t before = 0;
-#pragma unroll
-    for (int w = 0; w < kRadixWaves; ++w) before += w < wave ? wc[w][d] : 0u;
-    rank[r] = run[d] + before + lr;
-    __syncthreads();
-    uint32_t add = 0;
+    // the wave's earlier keys of this digit; the digit's leader (lowest lane) then
+    // adds the round's count (the wave's LDS accesses complete in program order)
+    const uint32_t prior = mine[d];
+    rank[r] = prior + lr;
+    if (valid && lr == 0) mine[d] = prior + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  {                                                  // digits 2t, 2t + 1 of thread t
+    const int d0 = 2 * threadIdx.x, d1 = d0 + 1;
+    uint32_t c0[kRadixWaves], c1[kRadixWaves], t0 = 0, t1 = 0;
 #pragma unroll
     for (int w = 0; w < kRadixWaves; ++w) {
-      add += wc[w][threadIdx.x];
-      wc[w][threadIdx.x] = 0;
+      c0[w] = d0 < nd ? wc[w][d0] : 0u;
+      c1[w] = d1 < nd ? wc[w][d1] : 0u;
+      t0 += c0[w];
+      t1 += c1[w];
     }
-    run[threadIdx.x] += add;
-    __syncthreads();
-  }
-  {                                                  // the block's digit starts
     uint32_t tot;
-    lstart[threadIdx.x] = block_exscan<kRadixBlock>(run[threadIdx.x], sh, &tot);
+    const uint32_t s0 = block_exscan<kRadixBlock>(t0 + t1, sh, &tot), s1 = s0 + t0;
+    if (d0 < nd) ls[d0] = s0;
+    if (d1 < nd) ls[d1] = s1;
+    uint32_t a0 = s0, a1 = s1;
+#pragma unroll
+    for (int w = 0; w < kRadixWaves; ++w) {       // wave w's first local position per digit
+      if (d0 < nd) wc[w][d0] = a0;
+      if (d1 < nd) wc[w][d1] = a1;
+      a0 += c0[w];
+      a1 += c1[w];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
-    if (base + r * kRadixBlock + threadIdx.x < n) {
-      const uint32_t d = (uint32_t)(k[r] >> shift) & (kDigits - 1);
-      const uint32_t p = lstart[d] + rank[r];
+    if (base + r * 64 + lane < n) {
+      const uint32_t d = (uint32_t)(k[r] >> shift) & dmask;
+      const uint32_t p = mine[d] + rank[r];
       sk[p] = k[r];
       si[p] = id[r];
     }
   }
   __syncthreads();
-  const int cnt = n - base < kRadixTile ? (int)(n - base) : kRadixTile;
+  const int cnt = n - blk0 < kRadixTile ? (int)(n - blk0) : kRadixTile;
   for (int j = threadIdx.x; j < cnt; j += kRadixBlock) {
     const K kk = sk[j];
-    const uint32_t d = (uint32_t)(kk >> shift) & (kDigits - 1);
-    const int64_t o = (int64_t)gstart[d] + (j - (int64_t)lstart[d]);
+    const uint32_t d = (uint32_t)(kk >> shift) & dmask;
+    const int64_t o = (int64_t)gs[d] + (j - (int64_t)ls[d]);
     kout[o] = kk;
     iout[o] = si[j];
   }
 }
 
 // ---- sorted records and references ---------------------------------------------------------
+// The owner grid is looked up again from the record (the particle's own position when
+// inside the domain), not read back at the particle's index: one random read a
+// particle instead of two.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_sort_gather(SortIO<T> io, const int32_t* __restrict__ idx) {
   const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (q >= io.npart) return;
-  const int32_t p = as_global<int32_t>(idx)[q];
+  const int32_t e = as_global<int32_t>(idx)[q];
+  const bool in = e >= 0;
+  const int32_t p = in ? e : ~e;
   const V4<T> v = load_v4<T>(io.prec, p);
-  const int32_t o = io.om ? as_global<int32_t>(io.owner)[p] : -1;
+  const int32_t o = (io.om && in) ? owner_lookup(io.om, io.om_nlev, v.x, v.y, v.z) : -1;
   as_global_mut<nvec4<T>>(io.sorted)[q] = nvec4<T>{v.x, v.y, v.z, v.w};
   as_global_mut<nvec2<int32_t>>(io.sref)[q] = nvec2<int32_t>{p, o};
 }
@@ -273,7 +296,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_gather(SortIO<T> io, const int3
 // Thread q: for each level of the batch, entry q starts (ends) a run when the previous
 // (next) key differs in the bits above the level's shift; the run's code is decoded to
 // the level's tile, whose begin (end) the thread writes when the tile lies in the
-// level's tile box.  Entries with the outside key take part in no run.
+// level's tile box.
 template <typename K>
 __global__ void __launch_bounds__(kBlock) k_tile_ranges(const DepLevel* __restrict__ tab, int nlev,
                                                         const K* __restrict__ key, int nbits,
@@ -281,9 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_ranges(const DepLevel* __restri
   const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (q >= n) return;
   const gptr<K> kg = as_global<K>(key);
-  const K lim = (K)1 << nbits;
   const K k = kg[q];
-  if (k >= lim) return;
   const bool has_prev = q > 0, has_next = q + 1 < n;
   const K kp = has_prev ? kg[q - 1] : (K)0, kn = has_next ? kg[q + 1] : (K)0;
   for (int b = 0; b < nlev; ++b) {
@@ -291,7 +312,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_ranges(const DepLevel* __restri
     const int s = L.shift;
     const K c = shr(k, s);
     const bool start = !has_prev || shr(kp, s) != c;
-    const bool end = !has_next || kn >= lim || shr(kn, s) != c;
+    const bool end = !has_next || shr(kn, s) != c;
     if (!start && !end) continue;
     const int nb = (nbits - s) / 3;
     const int tx = compact3<K>(c, nb) - L.tile_lo[0], ty = compact3<K>(c >> 1, nb) - L.tile_lo[1],
@@ -313,22 +334,24 @@ hipError_t sort_impl(const SortIO<T>& io, int* which, hipStream_t s) {
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_sort_keys<T, K>), dim3(nb), dim3(kBlock), 0, s, io);
   const int64_t nblk = (n + kRadixTile - 1) / kRadixTile;
-  const int64_t nh = nblk * kDigits;
+  const int passes = sort_passes(io.nbits);
+  const int rb = passes > 0 ? (io.nbits + passes - 1) / passes : 0;
+  const int64_t nh = nblk << rb;
   const int64_t nsum = (nh + kScanChunk - 1) / kScanChunk;
-  const int passes = (io.nbits + 1 + kRadixBits - 1) / kRadixBits;
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
-    const int shift = p * kRadixBits;
+    const int shift = p * rb;
     const K* kin = (const K*)io.key[cur];
     hipLaunchKernelGGL((k_radix_hist<K>), dim3((unsigned)nblk), dim3(kRadixBlock), 0, s, kin, n,
-                       shift, io.hist, nblk);
+                       shift, rb, io.hist, nblk);
     hipLaunchKernelGGL(k_hscan_reduce, dim3((unsigned)nsum), dim3(kRadixBlock), 0, s, io.hist, nh,
                        io.hsum);
     hipLaunchKernelGGL(k_hscan_mid, dim3(1), dim3(kScanMid), 0, s, io.hsum, nsum);
     hipLaunchKernelGGL(k_hscan_down, dim3((unsigned)nsum), dim3(kRadixBlock), 0, s, io.hist, nh,
                        io.hsum);
     hipLaunchKernelGGL((k_radix_scatter<K>), dim3((unsigned)nblk), dim3(kRadixBlock), 0, s, kin,
-                       io.idx[cur], (K*)io.key[1 - cur], io.idx[1 - cur], n, shift, io.hist, nblk);
+                       io.idx[cur], (K*)io.key[1 - cur], io.idx[1 - cur], n, shift, rb, io.hist,
+                       nblk);
     cur = 1 - cur;
   }
   hipLaunchKernelGGL((k_sort_gather<T>), dim3(nb), dim3(kBlock), 0, s, io, io.idx[cur]);
@@ -339,7 +362,7 @@ hipError_t sort_impl(const SortIO<T>& io, int* which, hipStream_t s) {
 }  // namespace
 
 int64_t sort_hist_elems(int64_t npart) {
-  return std::max<int64_t>(1, (npart + kRadixTile - 1) / kRadixTile) * kDigits;
+  return std::max<int64_t>(1, (npart + kRadixTile - 1) / kRadixTile) * kMaxDigits;
 }
 int64_t sort_sum_elems(int64_t npart) {
   return (sort_hist_elems(npart) + kScanChunk - 1) / kScanChunk;

@@ -39,7 +39,7 @@ FAMILY = {
     "k_interp_tiles": "interp", "k_interp": "interp", "k_unpack": "unpack",
     "k_adj_interp": "adj_interp", "k_adj_deposit_particles": "adj_deposit_particles",
     "k_adj_deposit_grid": "adj_deposit_grid", "k_adj_restrict": "adj_restrict",
-    "k_adj_finish": "adj_finish", "k_zero_ranges": "adj_clear",
+    "k_adj_finish": "adj_finish", "k_adj_unpack": "adj_finish", "k_zero_ranges": "adj_clear",
 }
 
 
