@@ -488,7 +488,10 @@ def main():
     from paper_1410_0010_amd import Context, Plan
 
     plan = Plan(w.root_n, w.grids, boundary=w.boundary)
-    ctx = Context(plan, 0)
+    ctx = ctx0 = Context(plan, 0)
+    # the same solve with the compensated FP32 deposit (FP32 pairs, no FP64 accumulation)
+    plan_c = Plan(w.root_n, w.grids, boundary=w.boundary, deposit_accum="f32_comp")
+    ctx_c = Context(plan_c, 0)
     active = w.active_cells()
     n = w.npart
     fp64_ok = not args.no_fp64
@@ -504,7 +507,8 @@ def main():
 
     tuned = {}
 
-    def run(dtype, steps, warmup, adjoint=False, profile=False):
+    def run(dtype, steps, warmup, adjoint=False, profile=False, c=None):
+        ctx = c or ctx0
         x, y, z, m = tens(dtype)
         gas = gas_for(x.dtype)
         out = [torch.empty(n, dtype=x.dtype, device=dev) for _ in range(4)]
@@ -512,8 +516,8 @@ def main():
         grads = None
         ctx.solve(x, y, z, m, gas, *out)
         torch.cuda.synchronize()
-        if x.dtype not in tuned:
-            tuned[x.dtype] = ctx.autotune(x.dtype, reps=5)
+        if (id(ctx), x.dtype) not in tuned:
+            tuned[(id(ctx), x.dtype)] = ctx.autotune(x.dtype, reps=5)
 
         def step():
             ctx.solve(x, y, z, m, gas, *out)
@@ -550,10 +554,11 @@ def main():
         del x, y, z, m, out
         return res
 
-    def staged_path(dtype, steps, src=None, outputs=False):
+    def staged_path(dtype, steps, src=None, outputs=False, c=None):
         """The plain per-level path through the staged entry points (owner, deposit,
         solve_level, accel, interp per level, totals), eager: ms per step, and the
         outputs of the last step when asked."""
+        ctx = c or ctx0
         x, y, z, m = tens(dtype, src)
         gas = [ctx.pack_gas(l, w.gas, x.dtype) for l in range(plan.nlevels)]
         ax, ay, az, pot = (torch.zeros(n, dtype=x.dtype, device=dev) for _ in range(4))
@@ -607,6 +612,18 @@ def main():
     log("FP32: profiled pass (HIP events around every kernel, one stream, no graph)")
     psteps = max(3, args.steps // 3)
     p32 = run(np.float32, psteps, 1, adjoint=do_adj, profile=True)
+    rc = run(np.float32, args.steps, args.warmup, c=ctx_c)
+    log(f"FP32 forward, compensated FP32 deposit: {rc['ms']:.3f} ms/step")
+    pc = run(np.float32, psteps, 1, profile=True, c=ctx_c)
+    comp = {"ms_per_step": rc["ms"],
+            "deposit_ms_per_step": {k: pc["prof"][k][0] / psteps for k in
+                                    ("deposit_tiles", "deposit_finalize") if k in pc["prof"]},
+            "deposit_ms_per_step_fp64_accum": {k: p32["prof"][k][0] / psteps for k in
+                                               ("deposit_tiles", "deposit_finalize")
+                                               if k in p32["prof"]}}
+    log("deposit kernels, compensated FP32 vs FP64 accumulation (ms): "
+        + ", ".join(f"{k} {v:.3f} vs {comp['deposit_ms_per_step_fp64_accum'].get(k, 0):.3f}"
+                    for k, v in comp["deposit_ms_per_step"].items()))
     if fp64_ok:
         r64 = run(np.float64, args.steps, args.warmup)
         log(f"FP64 forward: {r64['ms']:.3f} ms/step")
@@ -715,10 +732,11 @@ def main():
     err = {}
     if ref is not None:
         rd = [np.asarray(a, np.float32) for a in (w.x, w.y, w.z, w.m)]
-        for name, dt in (("fp32", np.float32), ("fp64", np.float64)):
+        for name, dt, c in (("fp32", np.float32, None), ("fp32comp", np.float32, ctx_c),
+                            ("fp64", np.float64, None)):
             if dt == np.float64 and not fp64_ok:
                 continue
-            got = staged_path(dt, 1, src=rd, outputs=True)
+            got = staged_path(dt, 1, src=rd, outputs=True, c=c)
             e = staged_errors(ref, got, plan.grids)
             err.update({f"{name}_{k}": v for k, v in e.items()})
             del got
@@ -804,6 +822,8 @@ def main():
                    "gradient": "spectral", "boundary": w.boundary},
         "cells_per_s": active / (r32["ms"] * 1e-3),
         "fwd_adjoint_fp32": step_info(a32),
+        "fp32_compensated_deposit": dict(step_info(rc), **{k: v for k, v in comp.items()
+                                                          if k != "ms_per_step"}),
         "fp64": step_info(r64),
         "fwd_adjoint_fp64": step_info(a64),
         "staged_per_level_fp64": step_info(s64),

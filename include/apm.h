@@ -77,6 +77,17 @@ typedef enum {
                                and interpolation stencils wrap at the box edges    */
 } apm_boundary;
 
+/* Accumulation of the FP32 deposit (apm_deposit, apm_solve with APM_F32; the FP64
+ * dtype always accumulates in FP64).  Sec. 2 sums each particle's TSC weights into
+ * the 27 cells around it; both modes give the exact sum to well below FP32 rounding
+ * before the GMF is rounded once. */
+typedef enum {
+  APM_ACC_F64 = 0,          /* sums in FP64 registers, LDS and key-box grid       */
+  APM_ACC_F32_COMP = 1      /* FP32 throughout: TwoSum-compensated (sum, error)
+                               pairs in registers, in LDS and in the level's
+                               key-box grid (Kahan-style compensation)            */
+} apm_accum;
+
 typedef struct {
   double G;                 /* gravitational constant [1.0]                       */
   int32_t root_n;           /* root cells per axis, power of two in [8, 512]
@@ -94,6 +105,7 @@ typedef struct {
                                a particle has a coordinate outside [0,1) or NaN;
                                0: such particles are left out silently (see
                                apm_dropped)                                        */
+  int32_t deposit_accum;    /* apm_accum of the FP32 deposit [APM_ACC_F64]        */
 } apm_config;
 
 /* One grid of the static hierarchy.  Grid 0 must be the root: level 0, parent

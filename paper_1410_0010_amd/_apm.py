@@ -22,6 +22,8 @@ APM_F32 = 1
 APM_F64 = 2
 APM_GRAD_SPECTRAL = 0
 APM_GRAD_FD2 = 1
+APM_ACC_F64 = 0
+APM_ACC_F32_COMP = 1
 APM_BC_ISOLATED = 0
 APM_BC_PERIODIC = 1
 
@@ -34,7 +36,8 @@ class apm_config(ctypes.Structure):
                 ("a_cells", ctypes.c_double), ("pad_factor", ctypes.c_double),
                 ("ghost", ctypes.c_int32), ("brillouin", ctypes.c_int32),
                 ("gradient", ctypes.c_int32), ("workspace_limit", ctypes.c_int64),
-                ("boundary", ctypes.c_int32), ("strict", ctypes.c_int32)]
+                ("boundary", ctypes.c_int32), ("strict", ctypes.c_int32),
+                ("deposit_accum", ctypes.c_int32)]
 
 
 class apm_grid(ctypes.Structure):

@@ -10,6 +10,7 @@
 #include <sstream>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "apm_kernels.hpp"
@@ -656,6 +657,7 @@ apm_status deposit_prepare_t(apm_ctx c, int l0, int nlev, int lf, int64_t npart,
   DepIO<T> io{};
   io.npart = npart;
   io.nlev = nlev;
+  io.comp = (std::is_same<T, float>::value && P.cfg.deposit_accum == APM_ACC_F32_COMP) ? 1 : 0;
   int64_t max_elems = 0, iblk = 0, fblk = 0;
   for (int b = 0; b < nlev; ++b) {
     const int l = l0 + b;

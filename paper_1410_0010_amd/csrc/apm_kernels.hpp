@@ -242,6 +242,8 @@ template <typename T> hipError_t launch_particle_sort(const SortIO<T>& io, int* 
 template <typename T> struct DepIO {
   int64_t npart;
   int32_t nlev;
+  int32_t comp;                        // T = float: 1 = compensated FP32 accumulation (the
+                                       // key-box grid holds (sum, error) FP32 pairs)
   int64_t item_blk0[kMaxLevels + 1];   // deposit-tile blocks of level b: [item_blk0[b], [b+1])
   int64_t fin_blk0[kMaxLevels + 1];    // finalize blocks of level b
   const T* gas[kMaxLevels];            // level active gas (packed) or null

@@ -13,6 +13,7 @@
 // across many blocks, so the load is balanced; FP64 accumulation keeps the result at
 // the working precision's rounding of the exact sum.
 #include <algorithm>
+#include <type_traits>
 
 #include "apm_kernels.hpp"
 
@@ -209,9 +210,15 @@ hipError_t launch_bin_scan(const DepLevel* tab, int nlev, int32_t max_tiles, hip
 
 // ---- deposit: work item = chunk of one tile ------------------------------------------
 // The chunk is counting-sorted by cell in LDS; runs of one cell accumulate in registers
-// and go to an FP64 LDS tile (the tile and its one-cell halo) once per run; then global
-// FP64 atomics add the tile into the level's key-box grid.  Blocks past a level's
-// item count exit at once.
+// and go to an LDS tile (the tile and its one-cell halo) once per run; then global
+// atomics add the tile into the level's key-box grid.  Blocks past a level's item
+// count exit at once.
+//
+// Two accumulations.  FP64: weights, run sums, the LDS tile and the key-box grid in
+// FP64.  Compensated FP32 (COMP): weights in FP32, each sum a pair (s, e) whose exact
+// value s + e tracks the exact sum: TwoSum recovers the rounding error of every FP32
+// addition (in registers directly; in LDS and in the key-box grid from the value a
+// returning atomic add found there), and the errors are summed in the low word.
 __device__ __forceinline__ int find_grid(const int64_t* __restrict__ begin, int ngrids, int64_t b) {
   int lo = 0, hi = ngrids - 1;
   while (lo < hi) {
@@ -224,12 +231,27 @@ __device__ __forceinline__ int find_grid(const int64_t* __restrict__ begin, int 
 constexpr int kTH = kTile + 2;
 constexpr int kTH3 = kHaloCells;
 
-template <typename T>
+// s + e == a + b exactly (Knuth's TwoSum; round to nearest)
+__device__ __forceinline__ float two_sum(float a, float b, float& e) {
+  const float s = a + b;
+  const float bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+  return s;
+}
+// A pair (hi, lo) takes (v + c) with a returning atomic add of v to hi: it gives the
+// value v was added to, so the rounding error of that addition is known exactly and
+// joins c in the low word (an ordinary atomic add).  The returning adds of a batch of
+// cells are all issued before any error add, so their round trips overlap.
+
+template <typename T, bool COMP>
 __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const DepLevel* __restrict__ tab) {
+  using A = typename std::conditional<COMP, float, double>::type;   // accumulation type
   constexpr int kCells = kTile * kTile * kTile;
-  __shared__ double acc[kTH3];
+  __shared__ double acc_raw[kTH3];                   // FP64 sums, or (hi, lo) FP32 pairs
   __shared__ int32_t cstart[kCells];                 // per-cell counts, then starts
   __shared__ uint16_t sidx[kChunk];                  // the chunk's entries, sorted by cell
+  double* acc = acc_raw;
+  float2* accp = reinterpret_cast<float2*>(acc_raw);
   const int lb = batch_level(io.item_blk0, io.nlev, blockIdx.x);
   const DepLevel& L = tab[lb];
   const int64_t item = blockIdx.x - io.item_blk0[lb];
@@ -239,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
   const int tile = wk.x;
   const int64_t begin = wk.y, end = wk.z;
   const int n = (int)(end - begin);                  // 1 .. kChunk
-  for (int c = threadIdx.x; c < kTH3; c += kBlock) acc[c] = 0.0;
+  for (int c = threadIdx.x; c < kTH3; c += kBlock) acc[c] = 0.0;   // both words zero
   for (int c = threadIdx.x; c < kCells; c += kBlock) cstart[c] = 0;
   int ox, oy, oz;
   tile_origin(L, tile, ox, oy, oz);
@@ -253,7 +275,15 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) pin4(rec[k]);
-  __syncthreads();                                   // counters cleared
+  __syncthreads();                                   // tile and counters cleared
+  // TSC weights of offset t = x - cell - 1/2 (exact in T: x and its cell share an
+  // exponent range), in the accumulation type
+  auto weights = [](T t, A w[3]) {
+    const A u = (A)t;
+    w[0] = (A)0.5 * ((A)0.5 - u) * ((A)0.5 - u);
+    w[1] = (A)0.75 - u * u;
+    w[2] = (A)0.5 * ((A)0.5 + u) * ((A)0.5 + u);
+  };
   if (n <= kBlock) {
     // a small chunk (at most one record per thread): each record's 27 weighted masses
     // go straight to the LDS tile; sorting would cost more than it saves
@@ -262,21 +292,31 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
       const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
       const int ix = min(max((int)fx - bx, 0), kTile - 1), iy = min(max((int)fy - by, 0), kTile - 1),
                 iz = min(max((int)fz - bz, 0), kTile - 1);
-      const double tx = (double)(v.x - fx) - 0.5, ty = (double)(v.y - fy) - 0.5,
-                   tz = (double)(v.z - fz) - 0.5;
-      const double wx[3] = {0.5 * (0.5 - tx) * (0.5 - tx), 0.75 - tx * tx, 0.5 * (0.5 + tx) * (0.5 + tx)};
-      const double wy[3] = {0.5 * (0.5 - ty) * (0.5 - ty), 0.75 - ty * ty, 0.5 * (0.5 + ty) * (0.5 + ty)};
-      const double wz[3] = {0.5 * (0.5 - tz) * (0.5 - tz), 0.75 - tz * tz, 0.5 * (0.5 + tz) * (0.5 + tz)};
-      const double m = (double)v.w;
-      double* base = acc + (iz * kTH + iy) * kTH + ix;
+      A wx[3], wy[3], wz[3];
+      weights(v.x - fx - (T)0.5, wx);
+      weights(v.y - fy - (T)0.5, wy);
+      weights(v.z - fz - (T)0.5, wz);
+      const A m = (A)v.w;
+      const int base = (iz * kTH + iy) * kTH + ix;
+      A w27[27];
 #pragma unroll
-      for (int dz = 0; dz < 3; ++dz)
+      for (int c = 0; c < 27; ++c) w27[c] = m * wz[c / 9] * wy[(c / 3) % 3] * wx[c % 3];
+      if constexpr (COMP) {
+        float old[27];                                 // returning adds first, as in flush
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-          const double mzy = m * wz[dz] * wy[dy];
+        for (int c = 0; c < 27; ++c)
+          old[c] = atomicAdd(&accp[base + ((c / 9) * kTH + (c / 3) % 3) * kTH + c % 3].x, w27[c]);
 #pragma unroll
-          for (int dx = 0; dx < 3; ++dx) atomicAdd(base + (dz * kTH + dy) * kTH + dx, mzy * wx[dx]);
+        for (int c = 0; c < 27; ++c) {
+          float e;
+          two_sum(old[c], w27[c], e);
+          atomicAdd(&accp[base + ((c / 9) * kTH + (c / 3) % 3) * kTH + c % 3].y, e);
         }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 27; ++c)
+          atomicAdd(acc + base + ((c / 9) * kTH + (c / 3) % 3) * kTH + c % 3, (double)w27[c]);
+      }
     }
   } else {
     // counting sort of the chunk by cell of the tile (cells clamped into the tile
@@ -322,22 +362,34 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
     __syncthreads();
     // eight consecutive sorted records per thread: a run of one cell accumulates its
     // 27 weighted masses in registers and adds them to the tile once
-    double a27[27];
+    A a27[27], e27[27];                                // sums (and, COMP, their errors)
 #pragma unroll
-    for (int c = 0; c < 27; ++c) a27[c] = 0.0;
+    for (int c = 0; c < 27; ++c) { a27[c] = 0; e27[c] = 0; }
     int cur = -1;
     auto flush = [&](int cl) {
       const int ix = cl % kTile, iy = (cl / kTile) % kTile, iz = cl / (kTile * kTile);
-      double* base = acc + (iz * kTH + iy) * kTH + ix;  // halo tile index of cell i0 + d - 1
+      const int base = (iz * kTH + iy) * kTH + ix;     // halo tile index of cell i0 + d - 1
+      if constexpr (COMP) {
+        // the 27 returning adds first (independent cells), then the error adds
+        float old[27];
 #pragma unroll
-      for (int dz = 0; dz < 3; ++dz)
+        for (int c = 0; c < 27; ++c)
+          old[c] = atomicAdd(&accp[base + ((c / 9) * kTH + (c / 3) % 3) * kTH + c % 3].x, a27[c]);
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
+        for (int c = 0; c < 27; ++c) {
+          float e;
+          two_sum(old[c], a27[c], e);
+          atomicAdd(&accp[base + ((c / 9) * kTH + (c / 3) % 3) * kTH + c % 3].y, e + e27[c]);
+          a27[c] = 0;
+          e27[c] = 0;
+        }
+      } else {
 #pragma unroll
-          for (int dx = 0; dx < 3; ++dx) {
-            atomicAdd(base + (dz * kTH + dy) * kTH + dx, a27[(dz * 3 + dy) * 3 + dx]);
-            a27[(dz * 3 + dy) * 3 + dx] = 0.0;
-          }
+        for (int c = 0; c < 27; ++c) {
+          atomicAdd(acc + base + ((c / 9) * kTH + (c / 3) % 3) * kTH + c % 3, (double)a27[c]);
+          a27[c] = 0;
+        }
+      }
     };
     // this thread's eight sorted entries, re-read from the chunk's records (cache
     // hits: the block read them above) so the LDS holds 2 B per entry, not a record
@@ -359,20 +411,28 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
         if (cur >= 0) flush(cur);
         cur = cl;
       }
-      const double tx = (double)(v.x - fx) - 0.5, ty = (double)(v.y - fy) - 0.5,
-                   tz = (double)(v.z - fz) - 0.5;
-      const double wx[3] = {0.5 * (0.5 - tx) * (0.5 - tx), 0.75 - tx * tx, 0.5 * (0.5 + tx) * (0.5 + tx)};
-      const double wy[3] = {0.5 * (0.5 - ty) * (0.5 - ty), 0.75 - ty * ty, 0.5 * (0.5 + ty) * (0.5 + ty)};
-      const double wz[3] = {0.5 * (0.5 - tz) * (0.5 - tz), 0.75 - tz * tz, 0.5 * (0.5 + tz) * (0.5 + tz)};
-      const double m = (double)v.w;
+      A wx[3], wy[3], wz[3];
+      weights(v.x - fx - (T)0.5, wx);
+      weights(v.y - fy - (T)0.5, wy);
+      weights(v.z - fz - (T)0.5, wz);
+      const A m = (A)v.w;
 #pragma unroll
       for (int dz = 0; dz < 3; ++dz) {
-        const double mz = m * wz[dz];
+        const A mz = m * wz[dz];
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
-          const double mzy = mz * wy[dy];
+          const A mzy = mz * wy[dy];
 #pragma unroll
-          for (int dx = 0; dx < 3; ++dx) a27[(dz * 3 + dy) * 3 + dx] += mzy * wx[dx];
+          for (int dx = 0; dx < 3; ++dx) {
+            const int c = (dz * 3 + dy) * 3 + dx;
+            if constexpr (COMP) {
+              float err;
+              a27[c] = two_sum(a27[c], mzy * wx[dx], err);
+              e27[c] += err;
+            } else {
+              a27[c] += mzy * wx[dx];
+            }
+          }
         }
       }
     }
@@ -383,9 +443,13 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
   // fall on a few rows of the key-box grid; on a periodic root the cells one past the
   // box edges (-1 and N) are cells N - 1 and 0
   const int tx0 = ox - 1, ty0 = oy - 1, tz0 = oz - 1;
-  for (int c = threadIdx.x; c < kTH3; c += kBlock) {
-    const double v = acc[c];
-    if (v == 0.0) continue;
+  constexpr int kPer = (kTH3 + kBlock - 1) / kBlock;   // halo cells per thread
+  int64_t gidx[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int c = threadIdx.x + k * kBlock;
+    gidx[k] = -1;
+    if (c >= kTH3 || acc[c] == 0.0) continue;        // both words zero (or an exact zero)
     int gx = tx0 + c % kTH, gy = ty0 + (c / kTH) % kTH, gz = tz0 + c / (kTH * kTH);
     if (L.wrap) {
       gx = wrap_cell(gx + L.key_lo[0], L.wrap) - L.key_lo[0];
@@ -394,7 +458,29 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
     }
     if (gx < 0 || gx >= L.key_n[0] || gy < 0 || gy >= L.key_n[1] || gz < 0 || gz >= L.key_n[2])
       continue;
-    global_add(as_global_mut<double>(L.accum) + ((int64_t)gz * L.key_n[1] + gy) * L.key_n[0] + gx, v);
+    gidx[k] = ((int64_t)gz * L.key_n[1] + gy) * L.key_n[0] + gx;
+  }
+  if constexpr (COMP) {
+    // every returning add of the thread first, then the error adds
+    float* cells = reinterpret_cast<float*>(L.accum);
+    float old[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      old[k] = gidx[k] >= 0
+                   ? global_add(as_global_mut<float>(cells + 2 * gidx[k]), accp[threadIdx.x + k * kBlock].x)
+                   : 0.f;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (gidx[k] < 0) continue;
+      const float2 v = accp[threadIdx.x + k * kBlock];
+      float e;
+      two_sum(old[k], v.x, e);
+      global_add(as_global_mut<float>(cells + 2 * gidx[k] + 1), e + v.y);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (gidx[k] >= 0) global_add(as_global_mut<double>(L.accum) + gidx[k], acc[threadIdx.x + k * kBlock]);
   }
 }
 
@@ -402,14 +488,21 @@ template <typename T>
 hipError_t launch_deposit_tiles(const DepIO<T>& io, const DepLevel* tab, hipStream_t s) {
   const int64_t nb = io.item_blk0[io.nlev];
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_deposit_tiles<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab);
+  if constexpr (std::is_same<T, float>::value) {
+    if (io.comp) {
+      hipLaunchKernelGGL((k_deposit_tiles<T, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_deposit_tiles<T, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab);
   return hipGetLastError();
 }
 
 // ---- finalize: GMF cell = accumulated mass / dx^3 + gas ------------------------------
 // (own gas on active cells, the parent's copied onto ghost cells); one thread per GMF
-// cell of every grid of every level of the batch.
-template <typename T>
+// cell of every grid of every level of the batch.  COMP: the pair's sum, scaled by
+// 1/dx^3 (a power of two: exact) in FP32.
+template <typename T, bool COMP>
 __global__ void __launch_bounds__(kBlock) k_deposit_finalize(DepIO<T> io, const DepLevel* __restrict__ tab) {
   const int lb = batch_level(io.fin_blk0, io.nlev, blockIdx.x);
   const DepLevel& L = tab[lb];
@@ -427,9 +520,15 @@ __global__ void __launch_bounds__(kBlock) k_deposit_finalize(DepIO<T> io, const 
   const int lz = (int)(row / ny);
   const int ly = (int)(row - (uint32_t)lz * ny);
   const int cx = g.gmf_lo[0] + lx, cy = g.gmf_lo[1] + ly, cz = g.gmf_lo[2] + lz;
-  const double mass = as_global<double>(L.accum)[((int64_t)(cz - L.key_lo[2]) * L.key_n[1] +
-                                                  (cy - L.key_lo[1])) * L.key_n[0] + (cx - L.key_lo[0])];
-  T rho = (T)(mass / (L.dx * L.dx * L.dx));
+  const int64_t kc = ((int64_t)(cz - L.key_lo[2]) * L.key_n[1] + (cy - L.key_lo[1])) * L.key_n[0] +
+                     (cx - L.key_lo[0]);
+  T rho;
+  if constexpr (COMP) {
+    const nvec2<float> p = as_global<nvec2<float>>(L.accum)[kc];
+    rho = (T)((p.x + p.y) * (float)(L.inv_dx * L.inv_dx * L.inv_dx));
+  } else {
+    rho = (T)(as_global<double>(L.accum)[kc] / (L.dx * L.dx * L.dx));
+  }
   const bool active = cx >= g.lo[0] && cx < g.lo[0] + g.n[0] && cy >= g.lo[1] &&
                       cy < g.lo[1] + g.n[1] && cz >= g.lo[2] && cz < g.lo[2] + g.n[2];
   const T* gas = io.gas[lb];
@@ -450,7 +549,14 @@ template <typename T>
 hipError_t launch_deposit_finalize(const DepIO<T>& io, const DepLevel* tab, hipStream_t s) {
   const int64_t nb = io.fin_blk0[io.nlev];
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_deposit_finalize<T>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab);
+  if constexpr (std::is_same<T, float>::value) {
+    if (io.comp) {
+      hipLaunchKernelGGL((k_deposit_finalize<T, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, io,
+                         tab);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_deposit_finalize<T, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, io, tab);
   return hipGetLastError();
 }
 

@@ -55,6 +55,8 @@ apm_status build_plan(const apm_config& cfg, const apm_grid* grids, int32_t ngri
     return fail(APM_ERR_INVALID, "unknown gradient");
   if (cfg.workspace_limit < 0) return fail(APM_ERR_INVALID, "workspace_limit < 0");
   if (cfg.strict != 0 && cfg.strict != 1) return fail(APM_ERR_INVALID, "strict must be 0 or 1");
+  if (cfg.deposit_accum != APM_ACC_F64 && cfg.deposit_accum != APM_ACC_F32_COMP)
+    return fail(APM_ERR_INVALID, "unknown deposit_accum");
 
   P.cfg = cfg;
   P.pad = (int32_t)std::ceil(cfg.pad_factor * 2.0 * cfg.a_cells - 1e-12);
@@ -206,6 +208,7 @@ void apm_config_default(apm_config* cfg) {
   cfg->gradient = APM_GRAD_SPECTRAL;
   cfg->workspace_limit = 0;
   cfg->boundary = APM_BC_ISOLATED;
+  cfg->deposit_accum = APM_ACC_F64;
 }
 
 apm_status apm_plan_create(const apm_config* cfg, const apm_grid* grids, int32_t ngrids,

@@ -31,13 +31,16 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+_ACC = {"f64": _apm.APM_ACC_F64, "f32_comp": _apm.APM_ACC_F32_COMP}
+
+
 class Plan:
     """Validated static hierarchy and its buffer layout (host only)."""
 
     def __init__(self, root_n: int, grids: Sequence, G: float = 1.0, gradient: str = "spectral",
                  a_cells: float = 3.4, pad_factor: float = 0.65, ghost: int = 3,
                  brillouin: int = 1, workspace_limit: int = 0, boundary: str = "isolated",
-                 strict: bool = False):
+                 strict: bool = False, deposit_accum: str = "f64"):
         L = _apm.lib()
         cfg = _apm.apm_config()
         L.apm_config_default(ctypes.byref(cfg))
@@ -51,6 +54,7 @@ class Plan:
         cfg.workspace_limit = workspace_limit
         cfg.boundary = _BC[boundary]
         cfg.strict = 1 if strict else 0
+        cfg.deposit_accum = _ACC[deposit_accum]
         arr = (_apm.apm_grid * len(grids))()
         for i, g in enumerate(grids):
             arr[i].level = g.level

@@ -97,6 +97,9 @@ def test_periodic_root_fft_is_not_doubled():
     cfg.strict = 2
     assert P.lib().apm_plan_create(ctypes.byref(cfg), arr, 1, ctypes.byref(h)) == _apm.APM_ERR_INVALID
     cfg.strict = 1
+    cfg.deposit_accum = 2
+    assert P.lib().apm_plan_create(ctypes.byref(cfg), arr, 1, ctypes.byref(h)) == _apm.APM_ERR_INVALID
+    cfg.deposit_accum = _apm.APM_ACC_F32_COMP
     assert P.lib().apm_plan_create(ctypes.byref(cfg), arr, 1, ctypes.byref(h)) == _apm.APM_OK
     P.lib().apm_plan_destroy(h)
 
@@ -123,6 +126,10 @@ def test_plan_validation_errors():
     # subgrid FFT length beyond 1024
     big = [GridSpec(0, -1, (0, 0, 0), (512,) * 3), GridSpec(1, 0, (4, 8, 8), (1014, 8, 8))]
     assert _bad(big, root_n=512) == _apm.APM_ERR_RANGE
+    # the particle sort keys 8^3 tiles of the finest level in 64 bits: at most 2^24
+    # cells per axis there (root 32 and 19 levels of refinement), one level more fails
+    P.Plan(32, W.centred_nested_grids(32, 16, 19))
+    assert _bad(W.centred_nested_grids(32, 16, 20), root_n=32) == _apm.APM_ERR_RANGE
 
 
 def test_plan_accepts_paper_geometries():

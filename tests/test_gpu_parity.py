@@ -43,8 +43,8 @@ def dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype))).to(DEV)
 
 
-def run_staged(w, dtype, gradient="spectral"):
-    plan = P.Plan(w.root_n, w.grids, gradient=gradient, boundary=w.boundary)
+def run_staged(w, dtype, gradient="spectral", accum="f64"):
+    plan = P.Plan(w.root_n, w.grids, gradient=gradient, boundary=w.boundary, deposit_accum=accum)
     ctx = P.Context(plan, 0)
     x, y, z, m = (dev(a, dtype) for a in (w.x, w.y, w.z, w.m))
     tdt = x.dtype
@@ -217,6 +217,30 @@ def test_parity_small(case, dtype):
     compare(case, w, dtype, got, ref)
 
 
+# The compensated FP32 deposit (FP32 weights and (sum, error) pairs in registers, LDS
+# and the key-box grid) meets the same FP32 bar as the FP64-accumulated one.
+COMP_CASES = ("nested32_2x16_plummer", "gas_nested32", "periodic_edges16", "edge_particles",
+              "clumps32_24grids", "slab_chain_L1024_z", "tiny_grids_L16")
+
+
+@pytest.mark.parametrize("case", COMP_CASES)
+def test_parity_compensated_fp32_deposit(case):
+    w = CASES[case]()
+    say(f"[parity] compensated FP32 deposit case={case} npart={w.npart}")
+    ref = run_oracle(w, np.float32)
+    got = run_staged(w, np.float32, accum="f32_comp")
+    compare(case + "_comp", w, np.float32, got, ref)
+    ctx = got["ctx"]
+    x, y, z, m, gas = got["tensors"]
+    ax, ay, az, pot = ctx.solve(x, y, z, m, gas)
+    torch.cuda.synchronize()
+    acc = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()], 1)
+    if w.npart:
+        own = ref["owner"] >= 0
+        assert rel(acc[own], ref["acc"][own]) <= TOL[np.float32]["acc"]
+        assert rel(pot.cpu().numpy()[own], ref["pot"][own]) <= TOL[np.float32]["pot"]
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
 def test_parity_fd2_gradient(dtype):
     w = W.workload_plummer_nested(root_n=32, sub_n=16, nlevels=2, npart=8000)
@@ -259,12 +283,14 @@ def bench_oracle():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
-def test_parity_bench_workload_full_size(bench_oracle, dtype):
+@pytest.mark.parametrize("dtype,accum", [(np.float64, "f64"), (np.float32, "f64"),
+                                         (np.float32, "f32_comp")],
+                         ids=["f64", "f32", "f32_comp"])
+def test_parity_bench_workload_full_size(bench_oracle, dtype, accum):
     w, cache = bench_oracle
-    say(f"[parity] full bench workload dtype={dtype.__name__} npart={w.npart}")
+    say(f"[parity] full bench workload dtype={dtype.__name__} accum={accum} npart={w.npart}")
     ref = run_oracle(w, dtype, cache=cache)
-    got = run_staged(w, dtype)
+    got = run_staged(w, dtype, accum=accum)
     compare("bench_full", w, dtype, got, ref)
 
 
