@@ -376,6 +376,29 @@ apm_status apm_leapfrog(apm_ctx ctx, apm_dtype dtype, void* x, void* y, void* z,
                         double h, int32_t nsteps, void* ax, void* ay, void* az, void* pot,
                         double* energy);
 
+/* Subcycled evolution (Sec. 2: levels advance with their own steps, Eq. 10 taken
+ * with equality, dt_l = h0 / 2^l; Sec. 3.1 and 3.5 evolve the self-force and orbit
+ * tests this way).  nroot root steps of h0; the levels step recursively (a step of
+ * level l, then two of level l + 1, and so on).  A step of size h on level l, from
+ * its clock t_l: (i) each particle of level l or finer joins level max(l, level of
+ * its owner grid); (ii) every particle is deposited at x + v (t_l + h/2 - t_own),
+ * its position predicted to the mid-step time from its own level's clock (the
+ * time-centred density of Sec. 2); the level's grids are solved and each adds its
+ * parent's composed field taken linearly in time through the parent's two latest
+ * solves to this mid-step time (the parent's latest alone before it has solved
+ * twice); (iii) the level's own particles move about the predicted position:
+ * v += h a, x = x_mid + v h/2, a interpolated from the finest grid of level <= l
+ * holding x_mid (zero outside the domain).  With one level the step is a
+ * drift-kick-drift leapfrog.  x..vz are updated in place; gas as in apm_solve,
+ * held fixed.  energy (host, NULL or nroot + 1 values) receives K + W (W as in
+ * apm_solve_totals) from a solve at the synchronised positions before the first
+ * and after every root step.  Isolated root only (APM_ERR_UNSUPPORTED otherwise);
+ * replaces the state an apm_solve_adjoint would read.  Synchronises at the end. */
+apm_status apm_evolve_subcycled(apm_ctx ctx, apm_dtype dtype, void* x, void* y, void* z,
+                                void* vx, void* vy, void* vz, const void* m, int64_t npart,
+                                const void* const* gas, double h0, int32_t nroot,
+                                double* energy);
+
 /* Device pointer to the library-owned composed field (or GMF) of `level` written
  * by the last apm_solve; NULL on error. */
 const void* apm_field_ptr(apm_ctx ctx, apm_dtype dtype, int32_t level);

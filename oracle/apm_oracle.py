@@ -87,6 +87,27 @@ wave test of Sec. 3): with boundary="periodic"
       (cell indices modulo N); subgrids are unchanged (their GMF boxes lie inside
       the root's active box);
   R26 the leapfrog drift maps positions back into [0, 1).
+
+Subcycling (Sec. 2: levels advance with their own steps, dt_{l+1} <= dt_l / 2,
+Eq. 10; Sec. 3.1 and 3.5 evolve with dt_{l+1} = dt_l / 2):
+  R27 the levels advance recursively (root step, then two steps of the next level,
+      and so on): a step of size h on level l, starting at the level's clock t_l,
+      (i) hands every particle of level l or finer to level max(l, level of its
+      owner grid) (those particles all sit at time t_l), (ii) deposits every
+      particle at its position predicted to the mid-step time t_l + h/2 from its
+      own level's clock, x + v (t_l + h/2 - t_own) (the time-centred density of
+      Sec. 2), solves the level's grids and adds the parent's latest composed
+      field (Sec. 2.2), then (iii) moves the particles of level l only, about the
+      predicted position: v += h a(x_mid), x = x_mid + v h/2, a interpolated from
+      the finest grid of level <= l holding x_mid.  The parent field a level adds
+      (Sec. 2.2) is the parent's composed field taken linearly in time through the
+      parent's two latest solves (at their mid-step times) to the level's own
+      mid-step time (the paper leaves the parent's time open; held fixed instead,
+      the coarse part of a particle's own field, centred at another time, pulls
+      it).  The different levels' contributions still come from different times,
+      the time-integration error Sec. 3.1 and 3.5 attribute to subcycling; with
+      one step size on every level each step reduces to a single consistent solve
+      at the mid-step positions.
 """
 
 from __future__ import annotations
@@ -837,6 +858,102 @@ def pp_reference_accel(x, y, z, m, a: float, G: float = 1.0):
         dphi = -G * m[nz] * (2.0 / a) * s2s2_potential_shape_deriv(2.0 * r[nz] / a) * (2.0 / a)
         acc[i] = ((dphi / r[nz])[:, None] * d[nz]).sum(axis=0)
     return acc
+
+
+def owner_up_to(plan: OraclePlan, x, y, z, lmax: int) -> np.ndarray:
+    """owner_of restricted to the grids of levels 0..lmax (R15, R27)."""
+    own = np.full(x.shape, -1, dtype=np.int64)
+    ok = valid_particles(x, y, z)
+    for lev in range(min(lmax, plan.nlevels - 1) + 1):
+        for g in reversed(plan.level_grids(lev)):
+            inside = ok.copy()
+            for a, c in enumerate((x, y, z)):
+                i = np.floor(np.where(ok, c, 0.0) / g.dx)
+                inside &= (i >= g.lo[a]) & (i < g.lo[a] + g.n[a])
+            own[inside] = g.index
+    return own
+
+
+def evolve_subcycled(plan: OraclePlan, x, y, z, vx, vy, vz, m, dt0: float, nroot: int,
+                     gas=None, ratio: int = 2, energy: bool = False):
+    """``nroot`` root steps of ``dt0`` with level l stepping dt0 / ratio^l (R27);
+    ratio = 2 is Eq. 10 with equality, ratio = 1 steps every level together.
+    Returns the final state and, per root step (and at the start), the positions,
+    velocities and, with ``energy``, K + W from a solve at the synchronised
+    positions."""
+    if plan.periodic:
+        raise ValueError("subcycling is read for the isolated root only")
+    x, y, z = (np.array(c, np.float64) for c in (x, y, z))
+    v = [np.array(c, np.float64) for c in (vx, vy, vz)]
+    m = np.asarray(m, np.float64)
+    if gas is None:
+        gas = [None] * len(plan.grids)
+    gas = [None if a is None else np.asarray(a, np.float64) for a in gas]
+    nl = plan.nlevels
+    cache = {g.index: greens(plan, g) for g in plan.grids}
+    level_of = np.array([g.level for g in plan.grids])
+    own0 = owner_of(plan, x, y, z)
+    lev = np.where(own0 >= 0, level_of[np.maximum(own0, 0)], 0)
+    clock = np.zeros(nl)
+    fld = [None] * len(plan.grids)          # latest composed field of each grid
+    prev = [None] * len(plan.grids)         # the one before
+    t_cur = np.full(nl, np.nan)             # mid-step times of those two solves
+    t_prev = np.full(nl, np.nan)
+
+    def parent_field(g, tm):
+        """The parent's composed field at time tm: linear in time through its two
+        latest solves (R27), or its latest alone when it has solved once."""
+        p, lp = g.parent, g.level - 1
+        if prev[p] is None or t_cur[lp] == t_prev[lp]:
+            return fld[p]
+        al = (tm - t_prev[lp]) / (t_cur[lp] - t_prev[lp])
+        return (1.0 - al) * prev[p] + al * fld[p]
+
+    def level_step(l, h):
+        nonlocal x, y, z
+        mine = lev >= l                                        # (i) at time clock[l]
+        if np.any(mine):
+            o = owner_of(plan, x[mine], y[mine], z[mine])
+            lev[mine] = np.maximum(l, np.where(o >= 0, level_of[np.maximum(o, 0)], 0))
+        tm = clock[l] + 0.5 * h
+        dt_p = tm - clock[lev]                                 # (ii) predicted positions
+        xp, yp, zp = x + v[0] * dt_p, y + v[1] * dt_p, z + v[2] * dt_p
+        for g in plan.level_grids(l):
+            rho = deposit_grid(plan, g, xp, yp, zp, m, gas)
+            short = convolve(plan, g, rho, cache[g.index])
+            prev[g.index] = fld[g.index]
+            fld[g.index] = compose(plan, g, short,
+                                   parent_field(g, tm) if g.parent >= 0 else None)
+        t_prev[l], t_cur[l] = t_cur[l], tm
+        sel = np.nonzero(lev == l)[0]                          # (iii) level l moves
+        if sel.size:
+            o = owner_up_to(plan, xp[sel], yp[sel], zp[sel], l)
+            a = interp(plan, fld, o, xp[sel], yp[sel], zp[sel])
+            for c in range(3):
+                v[c][sel] += h * a[:, c]
+            x[sel] = xp[sel] + 0.5 * h * v[0][sel]
+            y[sel] = yp[sel] + 0.5 * h * v[1][sel]
+            z[sel] = zp[sel] + 0.5 * h * v[2][sel]
+        clock[l] += h
+        if l + 1 < nl:
+            for _ in range(ratio):
+                level_step(l + 1, h / ratio)
+
+    def total_energy():
+        r = solve(plan, x, y, z, m, gas, cache)
+        return r["energy"] + 0.5 * float(np.sum(m * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2)))
+
+    pos, vel, en = [np.stack([x, y, z], 1)], [np.stack(v, 1)], []
+    if energy:
+        en.append(total_energy())
+    for _ in range(nroot):
+        level_step(0, dt0)
+        pos.append(np.stack([x, y, z], 1))
+        vel.append(np.stack(v, 1))
+        if energy:
+            en.append(total_energy())
+    return dict(x=x, y=y, z=z, vx=v[0], vy=v[1], vz=v[2], level=lev, pos=np.array(pos),
+                vel=np.array(vel), energy=np.array(en))
 
 
 def wrap_unit(a: np.ndarray) -> np.ndarray:

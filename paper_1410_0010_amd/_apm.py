@@ -108,6 +108,9 @@ SIGNATURES = {
     "apm_leapfrog": (_st, [_vp, _st, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_vp),
                            ctypes.c_double, _i32, _vp, _vp, _vp, _vp,
                            ctypes.POINTER(ctypes.c_double)]),
+    "apm_evolve_subcycled": (_st, [_vp, _st, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64,
+                                   ctypes.POINTER(_vp), ctypes.c_double, _i32,
+                                   ctypes.POINTER(ctypes.c_double)]),
     "apm_field_ptr": (_vp, [_vp, _st, _i32]),
     "apm_gmf_ptr": (_vp, [_vp, _st, _i32]),
     "apm_set_graph": (_st, [_vp, _i32]),

@@ -65,6 +65,10 @@ struct apm_ctx_s {
   // the particle sort shared by the levels: ping-pong keys and indices, packed input
   // records, digit counts and scan partials, the sorted records and references
   DevBuf skey[2], sidx[2], sprec, shist, shsum, ssorted, ssref;
+  // subcycled evolution: level of each particle, predicted positions, accelerations
+  // of the synchronised solves, and two composed fields per level (latest, previous)
+  DevBuf sc_lev, sc_pred, sc_acc;
+  std::vector<DevBuf> sc_fld[3];
   int sort_nbits = 0;                                             // of the last sort
   // per level: tile runs, work items, scan sums, FP64 mass grid
   struct LevelBufs { DevBuf tbegin, tend, items, work, bsum, accum; };
@@ -780,17 +784,18 @@ apm_status deposit_launch_t(apm_ctx c, const DepBatch<T>& d) {
   return run_steps(steps);
 }
 
-// Particle sort by tiles of the batch's finest level and TSC deposit of levels
-// [l0, l0 + nlev) in one batch.  gas/pgas/gmf are indexed by batch position; owner
-// (or null) receives the owner grids.
+// Particle sort by tiles of level lf (the batch's finest level by default) and TSC
+// deposit of levels [l0, l0 + nlev) in one batch.  gas/pgas/gmf are indexed by batch
+// position; owner (or null) receives the owner grids.
 template <typename T>
 apm_status deposit_levels_t(apm_ctx c, int l0, int nlev, const T* x, const T* y, const T* z,
                             const T* m, int64_t npart, int32_t* owner, const T* const* gas,
-                            const T* const* pgas, T* const* gmf) {
+                            const T* const* pgas, T* const* gmf, int lf = -1) {
+  if (lf < l0 + nlev - 1) lf = l0 + nlev - 1;        // the sort's finest level
   SortIO<T> so{};
-  APM_TRY(sort_prepare_t<T>(c, l0 + nlev - 1, x, y, z, m, npart, owner, &so));
+  APM_TRY(sort_prepare_t<T>(c, lf, x, y, z, m, npart, owner, &so));
   DepBatch<T> d;
-  APM_TRY(deposit_prepare_t<T>(c, l0, nlev, l0 + nlev - 1, npart, gas, pgas, gmf, &d));
+  APM_TRY(deposit_prepare_t<T>(c, l0, nlev, lf, npart, gas, pgas, gmf, &d));
   APM_TRY(sync_dep_table(c));
   APM_TRY(sort_launch_t<T>(c, so));
   return deposit_launch_t<T>(c, d);
@@ -1158,6 +1163,119 @@ apm_status leapfrog_t(apm_ctx c, apm_dtype dt, T* x, T* y, T* z, T* vx, T* vy, T
     for (int32_t s = 0; s <= nsteps; ++s) energy[s] = h6[6 * s] + h6[6 * s + 1] + h6[6 * s + 5];
   } else {
     HIP_TRY(hipStreamSynchronize(c->stream), "leapfrog sync");
+  }
+  return APM_OK;
+}
+
+// Subcycled evolution (see include/apm.h): the levels step recursively, level l with
+// h0 / 2^l.  A level step reassigns the particles of its level and finer ones,
+// deposits every particle at its position predicted to the mid-step time, solves
+// the level's grids, adds the parent's composed field taken linearly in time through
+// the parent's two latest solves, and moves the level's own particles about their
+// predicted positions.
+template <typename T>
+apm_status evolve_subcycled_t(apm_ctx c, apm_dtype dt, T* x, T* y, T* z, T* vx, T* vy, T* vz,
+                              const T* m, int64_t n, const void* const* gas, double h0,
+                              int32_t nroot, double* energy) {
+  const Plan& P = c->plan;
+  const int nl = (int)P.levels.size();
+  const int di = (int)dt;
+  if (P.cfg.boundary == APM_BC_PERIODIC)
+    return fail(APM_ERR_UNSUPPORTED, "apm_evolve_subcycled: isolated root only");
+  const size_t np = (size_t)std::max<int64_t>(n, 1);
+  APM_TRY(ensure(c, c->sc_lev, np * 4, "subcycling levels"));
+  APM_TRY(ensure(c, c->sc_pred, np * 3 * sizeof(T), "predicted positions"));
+  c->gmf[di].resize(nl);
+  c->sc_fld[di].resize(2 * nl);
+  for (int l = 0; l < nl; ++l) {
+    APM_TRY(ensure(c, c->gmf[di][l], (size_t)P.levels[l].gmf_elems * sizeof(T), "level gmf"));
+    for (int k = 0; k < 2; ++k)
+      APM_TRY(ensure(c, c->sc_fld[di][2 * l + k], (size_t)P.levels[l].fld_cells * sizeof(V4<T>),
+                     "subcycling fields"));
+  }
+  if (energy) {
+    APM_TRY(ensure(c, c->sc_acc, np * 3 * sizeof(T), "subcycling accelerations"));
+    APM_TRY(ensure(c, c->lf_pot, np * sizeof(T), "leapfrog potential"));
+    APM_TRY(ensure(c, c->totals, (size_t)(nl + 4 + 8 + 4 * kMaxParts) * 8, "totals"));
+    APM_TRY(ensure(c, c->energy, (size_t)(nroot + 1) * 6 * 8, "energies"));
+    HIP_TRY(launch_fill_f64((double*)c->energy.p, (int64_t)(nroot + 1) * 6, 0.0, c->stream),
+            "energy fill");
+  }
+  HIP_TRY(launch_fill_i32((int32_t*)c->sc_lev.p, n, 0, c->stream), "levels fill");
+  SubIO<T> io{};
+  io.npart = n;
+  io.x = x; io.y = y; io.z = z; io.vx = vx; io.vy = vy; io.vz = vz;
+  io.xp = (T*)c->sc_pred.p;
+  io.yp = io.xp + np;
+  io.zp = io.yp + np;
+  io.lev = (int32_t*)c->sc_lev.p;
+  io.om = c->d_owner_map;
+  io.nlev = nl;
+  io.grids = c->d_grids;
+  std::vector<int> cur(nl, 0), solved(nl, 0);
+  std::vector<double> t_cur(nl, 0.0), t_prev(nl, 0.0);
+  auto field = [&](int l, int k) { return (V4<T>*)c->sc_fld[di][2 * l + k].p; };
+  std::function<apm_status(int, double)> level_step = [&](int l, double h) -> apm_status {
+    const LevelDesc& L = P.levels[l];
+    io.level = l;
+    HIP_TRY(launch_sub_assign<T>(io, c->stream), "subcycling: levels");
+    io.tm = io.clock[l] + 0.5 * h;
+    io.h = h;
+    HIP_TRY(launch_sub_predict<T>(io, c->stream), "subcycling: prediction");
+    const T* gl = gas ? (const T*)gas[l] : nullptr;
+    const T* pg = (gas && l > 0) ? (const T*)gas[l - 1] : nullptr;
+    T* gm = (T*)c->gmf[di][l].p;
+    APM_TRY(deposit_levels_t<T>(c, l, 1, io.xp, io.yp, io.zp, m, n, nullptr, &gl, &pg, &gm, nl - 1));
+    V4<T>* out = field(l, 1 - cur[l]);                // the older buffer takes the new field
+    LevelPtrs<T> lp{};
+    lp.gmf[l] = gm;
+    lp.fld[l] = out;
+    APM_TRY(convolve_t<T>(c, l, lp));
+    if (l > 0) {
+      const bool two = solved[l - 1] >= 2 && t_cur[l - 1] != t_prev[l - 1];
+      const double al = two ? (io.tm - t_prev[l - 1]) / (t_cur[l - 1] - t_prev[l - 1]) : 1.0;
+      HIP_TRY(timed(c, "compose", [&] {
+                return launch_compose<T>(c->d_grids + L.first, c->d_cmp_begin[l], L.count, out,
+                                         field(l - 1, cur[l - 1]), out, c->cmp_blocks[l],
+                                         c->stream, two ? field(l - 1, 1 - cur[l - 1]) : nullptr,
+                                         al);
+              }), "subcycling: composition");
+    }
+    cur[l] = 1 - cur[l];
+    solved[l]++;
+    t_prev[l] = t_cur[l];
+    t_cur[l] = io.tm;
+    for (int k = 0; k <= l; ++k) io.fld[k] = field(k, cur[k]);
+    io.level = l;
+    io.tm = t_cur[l];
+    io.h = h;
+    HIP_TRY(launch_sub_move<T>(io, c->stream), "subcycling: move");
+    io.clock[l] += h;
+    if (l + 1 < nl)
+      for (int r = 0; r < 2; ++r) APM_TRY(level_step(l + 1, 0.5 * h));
+    return APM_OK;
+  };
+  double* E = (double*)c->energy.p;
+  auto energy_at = [&](int r) -> apm_status {
+    T* acc = (T*)c->sc_acc.p;
+    T* pot = (T*)c->lf_pot.p;
+    APM_TRY(solve_t<T>(c, dt, x, y, z, m, n, gas, acc, acc + np, acc + 2 * np, pot));
+    return step_energy_t<T>(c, dt, m, vx, vy, vz, n, acc, acc + np, acc + 2 * np, pot, gas,
+                            E + 6 * r);
+  };
+  if (energy) APM_TRY(energy_at(0));
+  for (int32_t r = 0; r < nroot; ++r) {
+    APM_TRY(level_step(0, h0));
+    if (energy) APM_TRY(energy_at(r + 1));
+  }
+  if (energy) {
+    std::vector<double> h6((size_t)(nroot + 1) * 6);
+    HIP_TRY(hipMemcpyAsync(h6.data(), E, h6.size() * 8, hipMemcpyDeviceToHost, c->stream),
+            "energy copy");
+    HIP_TRY(hipStreamSynchronize(c->stream), "subcycling sync");
+    for (int32_t r = 0; r <= nroot; ++r) energy[r] = h6[6 * r] + h6[6 * r + 1] + h6[6 * r + 5];
+  } else {
+    HIP_TRY(hipStreamSynchronize(c->stream), "subcycling sync");
   }
   return APM_OK;
 }
@@ -1615,7 +1733,7 @@ apm_status apm_destroy(apm_ctx c) {
   DevBuf* bufs[] = {&c->spec, &c->zbuf, &c->ybuf, &c->pres, &c->owner, &c->totals,
                     &c->dep_tab, &c->gpart, &c->energy, &c->lf_pot, &c->meanbuf,
                     &c->skey[0], &c->skey[1], &c->sidx[0], &c->sidx[1], &c->sprec, &c->shist,
-                    &c->shsum, &c->ssorted, &c->ssref};
+                    &c->shsum, &c->ssorted, &c->ssref, &c->sc_lev, &c->sc_pred, &c->sc_acc};
   for (auto& B : c->lvb)
     for (DevBuf* b : {&B.tbegin, &B.tend, &B.items, &B.work, &B.bsum, &B.accum})
       if (b->p) (void)hipFree(b->p);
@@ -1627,6 +1745,8 @@ apm_status apm_destroy(apm_ctx c) {
   for (auto& v : c->gmf)
     for (auto& b : v) if (b.p) (void)hipFree(b.p);
   for (auto& v : c->fld)
+    for (auto& b : v) if (b.p) (void)hipFree(b.p);
+  for (auto& v : c->sc_fld)
     for (auto& b : v) if (b.p) (void)hipFree(b.p);
   delete c;
   return APM_OK;
@@ -1976,6 +2096,28 @@ apm_status apm_leapfrog(apm_ctx c, apm_dtype dt, void* x, void* y, void* z, void
   return leapfrog_t<double>(c, dt, (double*)x, (double*)y, (double*)z, (double*)vx, (double*)vy,
                             (double*)vz, (const double*)m, npart, gas, h, nsteps, (double*)ax,
                             (double*)ay, (double*)az, (double*)pot, energy);
+}
+
+apm_status apm_evolve_subcycled(apm_ctx c, apm_dtype dt, void* x, void* y, void* z, void* vx,
+                                void* vy, void* vz, const void* m, int64_t npart,
+                                const void* const* gas, double h0, int32_t nroot,
+                                double* energy) {
+  APM_TRY(check_ctx(c));
+  APM_TRY(check_dtype(dt));
+  if (npart < 0 || npart > INT32_MAX)
+    return fail(APM_ERR_RANGE, "apm_evolve_subcycled: npart out of range");
+  if (nroot < 0) return fail(APM_ERR_RANGE, "apm_evolve_subcycled: nroot < 0");
+  if (!(h0 > 0.0)) return fail(APM_ERR_INVALID, "apm_evolve_subcycled: h0 must be positive");
+  if (npart > 0 && (!x || !y || !z || !vx || !vy || !vz || !m))
+    return fail(APM_ERR_INVALID, "apm_evolve_subcycled: NULL array");
+  c->last_solve.clear();                             // the particle sort is replaced
+  if (dt == APM_F32)
+    return evolve_subcycled_t<float>(c, dt, (float*)x, (float*)y, (float*)z, (float*)vx,
+                                     (float*)vy, (float*)vz, (const float*)m, npart, gas, h0,
+                                     nroot, energy);
+  return evolve_subcycled_t<double>(c, dt, (double*)x, (double*)y, (double*)z, (double*)vx,
+                                    (double*)vy, (double*)vz, (const double*)m, npart, gas, h0,
+                                    nroot, energy);
 }
 
 const void* apm_field_ptr(apm_ctx c, apm_dtype dt, int32_t level) {

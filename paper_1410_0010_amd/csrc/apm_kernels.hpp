@@ -349,10 +349,34 @@ template <typename T> hipError_t launch_adj_finish(const AdjIO<T>& io, const Dep
 template <typename T> hipError_t launch_to_t(const double* a, T* b, int64_t n, hipStream_t s);
 hipError_t launch_add_scalar(double* a, int64_t n, const double* s, double scale, hipStream_t st);
 
+// field = own + P(parent) on every grid of a level (own may be field: in place); with
+// pprev, P((1 - alpha) pprev + alpha parent), the parent taken linearly in time
 template <typename T> hipError_t launch_compose(const GridDesc* grids, const int64_t* block_begin,
                                                 int32_t ngrids, const V4<T>* own,
                                                 const V4<T>* parent, V4<T>* field,
-                                                int64_t nblocks, hipStream_t s);
+                                                int64_t nblocks, hipStream_t s,
+                                                const V4<T>* pprev = nullptr, double alpha = 1.0);
+// ---- subcycled evolution (particles.hip) ----
+template <typename T> struct SubIO {
+  int64_t npart;
+  T* x; T* y; T* z; T* vx; T* vy; T* vz;
+  T* xp; T* yp; T* zp;                 // positions predicted to the step's mid-time
+  int32_t* lev;                        // level each particle moves with
+  double clock[kMaxLevels];            // the levels' clocks
+  int32_t level;                       // the stepping level
+  double h, tm;                        // its step and mid-step time
+  const OwnerLevel* om;
+  int32_t nlev;
+  const GridDesc* grids;
+  const V4<T>* fld[kMaxLevels];        // latest composed field of every level <= level
+};
+// particles of level >= io.level: level = max(io.level, level of the owner grid)
+template <typename T> hipError_t launch_sub_assign(const SubIO<T>& io, hipStream_t s);
+// every particle: xp = x + v (tm - clock[lev])
+template <typename T> hipError_t launch_sub_predict(const SubIO<T>& io, hipStream_t s);
+// particles of io.level: v += h a(xp) (finest grid of level <= io.level holding xp),
+// x = xp + v h / 2
+template <typename T> hipError_t launch_sub_move(const SubIO<T>& io, hipStream_t s);
 // Deterministic FP64 reductions: per-block partials (part, kMaxParts per quantity),
 // then one block sums them in a fixed order into out.
 constexpr int kMaxParts = 1024;

@@ -17,11 +17,14 @@ __device__ __forceinline__ int find_grid_f(const int64_t* __restrict__ begin, in
 
 // field = own + P(parent): P trilinear between cell centres; a child cell c has
 // its centre a quarter parent cell from parent centre floor(c/2), towards parent
-// floor(c/2) - 1 (c even) or + 1 (c odd): weights 3/4 and 1/4 per axis.
+// floor(c/2) - 1 (c even) or + 1 (c odd): weights 3/4 and 1/4 per axis.  With
+// pprev, the parent field is first taken linearly in time on the parent's cells,
+// (1 - alpha) pprev + alpha parent, then interpolated.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_compose(const GridDesc* __restrict__ grids, const int64_t* __restrict__ begin, int32_t ngrids,
-          const V4<T>* own, const V4<T>* __restrict__ parent, V4<T>* field) {
+          const V4<T>* own, const V4<T>* __restrict__ parent, V4<T>* field,
+          const V4<T>* __restrict__ pprev, T alpha) {
   const int gi = find_grid_f(begin, ngrids, blockIdx.x);
   const GridDesc& g = grids[gi];
   const int64_t cells = (int64_t)g.fld_n[0] * g.fld_n[1] * g.fld_n[2];
@@ -40,13 +43,21 @@ k_compose(const GridDesc* __restrict__ grids, const int64_t* __restrict__ begin,
       pi[a][1] = ((c[a] & 1) ? p + 1 : p - 1) - g.parent_fld_lo[a];
     }
     const V4<T>* P = parent + g.parent_fld_offset;
+    const V4<T>* Q = pprev ? pprev + g.parent_fld_offset : nullptr;
     const T wts[2] = {(T)0.75, (T)0.25};
     T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b)
         for (int d = 0; d < 2; ++d) {
           const T w = wts[a] * wts[b] * wts[d];
-          const V4<T> f = P[((int64_t)pi[2][a] * g.parent_fld_n[1] + pi[1][b]) * g.parent_fld_n[0] + pi[0][d]];
+          const int64_t k = ((int64_t)pi[2][a] * g.parent_fld_n[1] + pi[1][b]) * g.parent_fld_n[0] + pi[0][d];
+          V4<T> f = P[k];
+          if (Q) {
+            const V4<T> q = Q[k];
+            const T be = (T)1 - alpha;
+            f.x = be * q.x + alpha * f.x; f.y = be * q.y + alpha * f.y;
+            f.z = be * q.z + alpha * f.z; f.w = be * q.w + alpha * f.w;
+          }
           s0 += w * f.x; s1 += w * f.y; s2 += w * f.z; s3 += w * f.w;
         }
     v.x += s0; v.y += s1; v.z += s2; v.w += s3;
@@ -57,9 +68,9 @@ k_compose(const GridDesc* __restrict__ grids, const int64_t* __restrict__ begin,
 template <typename T>
 hipError_t launch_compose(const GridDesc* grids, const int64_t* begin, int32_t ngrids,
                           const V4<T>* own, const V4<T>* parent, V4<T>* field, int64_t nblocks,
-                          hipStream_t s) {
+                          hipStream_t s, const V4<T>* pprev, double alpha) {
   hipLaunchKernelGGL((k_compose<T>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, grids, begin,
-                     ngrids, own, parent, field);
+                     ngrids, own, parent, field, pprev, (T)alpha);
   return hipGetLastError();
 }
 
@@ -330,7 +341,8 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
 
 #define APM_INST_F(T)                                                                          \
   template hipError_t launch_compose<T>(const GridDesc*, const int64_t*, int32_t, const V4<T>*,  \
-                                        const V4<T>*, V4<T>*, int64_t, hipStream_t);             \
+                                        const V4<T>*, V4<T>*, int64_t, hipStream_t, const V4<T>*, \
+                                        double);             \
   template hipError_t launch_mean_density<T>(const T*, const T*, const T*, const T*, int64_t,     \
                                              const T*, int64_t, double, double*, double*,         \
                                              hipStream_t);                                        \

@@ -746,9 +746,75 @@ hipError_t launch_unpack(const InterpIO<T>& io, const DepLevel* tab, const int32
 }
 
 
+// ---- subcycled evolution -------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sub_assign(SubIO<T> io) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= io.npart || io.lev[i] < io.level) return;
+  const T px = io.x[i], py = io.y[i], pz = io.z[i];
+  const int o = in_domain(px, py, pz) ? owner_lookup(io.om, io.nlev, px, py, pz) : -1;
+  io.lev[i] = max(io.level, o >= 0 ? io.grids[o].level : 0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sub_predict(SubIO<T> io) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= io.npart) return;
+  const T d = (T)(io.tm - io.clock[io.lev[i]]);
+  io.xp[i] = io.x[i] + io.vx[i] * d;
+  io.yp[i] = io.y[i] + io.vy[i] * d;
+  io.zp[i] = io.z[i] + io.vz[i] * d;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sub_move(SubIO<T> io) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= io.npart || io.lev[i] != io.level) return;
+  const T px = io.xp[i], py = io.yp[i], pz = io.zp[i];
+  const int o = in_domain(px, py, pz) ? owner_lookup(io.om, io.level + 1, px, py, pz) : -1;
+  V4<T> a{0, 0, 0, 0};
+  if (o >= 0) {
+    const GridDesc& g = io.grids[o];
+    const T s = (T)(1.0 / g.dx);
+    const T sx = px * s, sy = py * s, sz = pz * s;
+    const T fx = floor(sx), fy = floor(sy), fz = floor(sz);
+    a = tsc_gather<T>(io.fld[g.level] + g.fld_offset, g.fld_n[0], g.fld_n[1], g.fld_n[2],
+                      (int)fx - g.fld_lo[0], (int)fy - g.fld_lo[1], (int)fz - g.fld_lo[2],
+                      sx - fx - (T)0.5, sy - fy - (T)0.5, sz - fz - (T)0.5, g.wrap);
+  }
+  const T h = (T)io.h, hh = (T)(0.5 * io.h);
+  const T vx = io.vx[i] + h * a.x, vy = io.vy[i] + h * a.y, vz = io.vz[i] + h * a.z;
+  io.vx[i] = vx; io.vy[i] = vy; io.vz[i] = vz;
+  io.x[i] = px + hh * vx;
+  io.y[i] = py + hh * vy;
+  io.z[i] = pz + hh * vz;
+}
+
+template <typename T> hipError_t launch_sub_assign(const SubIO<T>& io, hipStream_t s) {
+  if (io.npart <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sub_assign<T>), dim3((unsigned)((io.npart + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, io);
+  return hipGetLastError();
+}
+template <typename T> hipError_t launch_sub_predict(const SubIO<T>& io, hipStream_t s) {
+  if (io.npart <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sub_predict<T>), dim3((unsigned)((io.npart + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, io);
+  return hipGetLastError();
+}
+template <typename T> hipError_t launch_sub_move(const SubIO<T>& io, hipStream_t s) {
+  if (io.npart <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_sub_move<T>), dim3((unsigned)((io.npart + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, io);
+  return hipGetLastError();
+}
+
 #define APM_INST(T)                                                                          \
   template hipError_t launch_deposit_tiles<T>(const DepIO<T>&, const DepLevel*, hipStream_t);  \
   template hipError_t launch_deposit_finalize<T>(const DepIO<T>&, const DepLevel*, hipStream_t); \
+  template hipError_t launch_sub_assign<T>(const SubIO<T>&, hipStream_t);                     \
+  template hipError_t launch_sub_predict<T>(const SubIO<T>&, hipStream_t);                    \
+  template hipError_t launch_sub_move<T>(const SubIO<T>&, hipStream_t);                       \
   template hipError_t launch_owner<T>(const OwnerLevel*, int32_t, const T*, const T*, const T*, \
                                       int64_t, int32_t*, T*, T*, T*, T*, hipStream_t);          \
   template hipError_t launch_interp_tiles<T>(const InterpIO<T>&, const DepLevel*,               \

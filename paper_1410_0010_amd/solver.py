@@ -325,6 +325,17 @@ class Context:
                                       _ptr(az), _ptr(pot), e), "apm_leapfrog")
         return ax, ay, az, pot, (np.array(e[:]) if energy else None)
 
+    def evolve_subcycled(self, x, y, z, vx, vy, vz, m, h0, nroot, gas=None, energy=True):
+        """nroot root steps of h0 with level l stepping h0 / 2^l (apm_evolve_subcycled),
+        in place; returns the (nroot + 1) energies K + W, or None."""
+        self.solve_count += 1          # the library's forward state is replaced
+        e = (ctypes.c_double * (nroot + 1))() if energy else None
+        check(_apm.lib().apm_evolve_subcycled(self.handle, _dtype_code(x), _ptr(x), _ptr(y),
+                                              _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), _ptr(m),
+                                              x.shape[0], self._gas_array(gas), h0, nroot, e),
+              "apm_evolve_subcycled")
+        return np.array(e[:]) if energy else None
+
     def set_graph(self, enable: bool):
         check(_apm.lib().apm_set_graph(self.handle, 1 if enable else 0), "apm_set_graph")
 
