@@ -457,6 +457,11 @@ def main():
                          "at most 16)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-compensated", action="store_true",
+                    help="skip the solve with the compensated FP32 deposit")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the FP32 profiled pass (serial, no graph) and its roofline: "
+                         "the run to take a kernel trace of")
     ap.add_argument("--no-staged", action="store_true",
                     help="skip the staged per-level FP64 timing")
     ap.add_argument("--leapfrog-steps", type=int, default=100,
@@ -519,8 +524,10 @@ def main():
 
     tuned = {}
 
-    def run(dtype, steps, warmup, adjoint=False, profile=False, c=None):
+    def run(dtype, steps, warmup, adjoint=False, profile=False, c=None, serial=False):
         ctx = c or ctx0
+        if serial:                             # every solve on one stream, no graph
+            ctx.profile(True)
         x, y, z, m = tens(dtype)
         gas = gas_for(x.dtype)
         out = [torch.empty(n, dtype=x.dtype, device=dev) for _ in range(4)]
@@ -618,28 +625,38 @@ def main():
         del x, y, z, m, gmf, own, fld
         return res
 
-    log(f"FP32 forward: warmup {args.warmup}, {args.steps} timed steps")
-    r32 = run(np.float32, args.steps, args.warmup)
-    log(f"FP32 forward: {r32['ms']:.3f} ms/step")
-    a32 = a64 = r64 = s64 = None
-    if do_adj:
-        a32 = run(np.float32, args.steps, 1, adjoint=True)
-        log(f"FP32 forward+adjoint: {a32['ms']:.3f} ms/step")
-    log("FP32: profiled pass (HIP events around every kernel, one stream, no graph)")
-    psteps = max(3, args.steps // 3)
-    p32 = run(np.float32, psteps, 1, adjoint=do_adj, profile=True)
-    rc = run(np.float32, args.steps, args.warmup, c=ctx_c)
-    log(f"FP32 forward, compensated FP32 deposit: {rc['ms']:.3f} ms/step")
-    pc = run(np.float32, psteps, 1, profile=True, c=ctx_c)
-    comp = {"ms_per_step": rc["ms"],
-            "deposit_ms_per_step": {k: pc["prof"][k][0] / psteps for k in
-                                    ("deposit_tiles", "deposit_finalize") if k in pc["prof"]},
-            "deposit_ms_per_step_fp64_accum": {k: p32["prof"][k][0] / psteps for k in
-                                               ("deposit_tiles", "deposit_finalize")
-                                               if k in p32["prof"]}}
-    log("deposit kernels, compensated FP32 vs FP64 accumulation (ms): "
-        + ", ".join(f"{k} {v:.3f} vs {comp['deposit_ms_per_step_fp64_accum'].get(k, 0):.3f}"
-                    for k, v in comp["deposit_ms_per_step"].items()))
+    a32 = a64 = r64 = s64 = rc = None
+    comp = {}
+    if args.profile_only:
+        # only the profiled pass, every solve of the process serial (for a kernel trace
+        # whose per-kernel averages are the figures this line reports)
+        log(f"FP32: profiled pass only, {args.steps} steps, every solve on one stream")
+        psteps = args.steps
+        p32 = run(np.float32, psteps, args.warmup, adjoint=do_adj, profile=True, serial=True)
+        r32 = p32
+        fp64_ok = False
+    else:
+        log(f"FP32 forward: warmup {args.warmup}, {args.steps} timed steps")
+        r32 = run(np.float32, args.steps, args.warmup)
+        log(f"FP32 forward: {r32['ms']:.3f} ms/step")
+        if do_adj:
+            a32 = run(np.float32, args.steps, 1, adjoint=True)
+            log(f"FP32 forward+adjoint: {a32['ms']:.3f} ms/step")
+        log("FP32: profiled pass (HIP events around every kernel, one stream, no graph)")
+        psteps = max(3, args.steps // 3)
+        p32 = run(np.float32, psteps, 1, adjoint=do_adj, profile=True)
+    if not args.profile_only and not args.no_compensated:
+        rc = run(np.float32, args.steps, args.warmup, c=ctx_c)
+        log(f"FP32 forward, compensated FP32 deposit: {rc['ms']:.3f} ms/step")
+        pc = run(np.float32, psteps, 1, profile=True, c=ctx_c)
+        comp = {"deposit_ms_per_step": {k: pc["prof"][k][0] / psteps for k in
+                                        ("deposit_tiles", "deposit_finalize") if k in pc["prof"]},
+                "deposit_ms_per_step_fp64_accum": {k: p32["prof"][k][0] / psteps for k in
+                                                   ("deposit_tiles", "deposit_finalize")
+                                                   if k in p32["prof"]}}
+        log("deposit kernels, compensated FP32 vs FP64 accumulation (ms): "
+            + ", ".join(f"{k} {v:.3f} vs {comp['deposit_ms_per_step_fp64_accum'].get(k, 0):.3f}"
+                        for k, v in comp["deposit_ms_per_step"].items()))
     if fp64_ok:
         r64 = run(np.float64, args.steps, args.warmup)
         log(f"FP64 forward: {r64['ms']:.3f} ms/step")
@@ -752,7 +769,7 @@ def main():
         rdg = [None if a is None else np.asarray(a, np.float32).astype(np.float64) for a in w.gas]
         for name, dt, c in (("fp32", np.float32, None), ("fp32comp", np.float32, ctx_c),
                             ("fp64", np.float64, None)):
-            if dt == np.float64 and not fp64_ok:
+            if (dt == np.float64 and not fp64_ok) or (c is ctx_c and args.no_compensated):
                 continue
             got = staged_path(dt, 1, src=rd, outputs=True, c=c, gas_src=rdg)
             e = staged_errors(ref, got, plan.grids)
@@ -840,8 +857,7 @@ def main():
                    "gradient": "spectral", "boundary": w.boundary},
         "cells_per_s": active / (r32["ms"] * 1e-3),
         "fwd_adjoint_fp32": step_info(a32),
-        "fp32_compensated_deposit": dict(step_info(rc), **{k: v for k, v in comp.items()
-                                                          if k != "ms_per_step"}),
+        "fp32_compensated_deposit": (dict(step_info(rc), **comp) if rc is not None else None),
         "fp64": step_info(r64),
         "fwd_adjoint_fp64": step_info(a64),
         "staged_per_level_fp64": step_info(s64),
@@ -863,7 +879,8 @@ def main():
                      "profiled_ms_per_step": p32["ms"],
                      "forward_kernels_ms_per_step": fwd_kernels_ms},
         "kernels_fp32": per_kernel,
-        "launch": {"graph": "apm_solve captured once, replayed per step",
+        "launch": {"graph": ("none: every solve serial (profile-only run)" if args.profile_only
+                             else "apm_solve captured once, replayed per step"),
                    "autotuned_lines_per_block": {k: v["lines"] for d in tuned.values()
                                                  for k, v in d.items()}},
         "cpu_baseline": cpu,

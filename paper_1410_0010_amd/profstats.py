@@ -72,7 +72,7 @@ def traffic_record(path):
 
 
 def short_name(full):
-    s = full.replace("void ", "").replace("apm::", "")
+    s = full.replace("void ", "").replace("apm::", "").replace("(anonymous namespace)::", "")
     depth, out = 0, []
     for ch in s:                      # drop the argument list, keep template arguments
         if ch == "(" and depth == 0:
@@ -81,6 +81,11 @@ def short_name(full):
         depth -= ch == ">"
         out.append(ch)
     return "".join(out).strip()
+
+
+def other_dtype(dtype):
+    """The precision a family table leaves out (instantiations on index types stay)."""
+    return "double" if dtype == "float" else "float"
 
 
 def find(path, suffix):
@@ -120,7 +125,7 @@ def counters_main(path, dtype):
         allv = [x for v in shapes.values() for x in v]
         rows.append((name, ctr, sel, allv))
         base = name.split("<")[0]
-        if base in FAMILY and (dtype in name[len(base):] or "<" not in name):
+        if base in FAMILY and other_dtype(dtype) not in name[len(base):]:
             fam[(FAMILY[base], ctr)].extend(sel)
     for name, ctr, sel, allv in sorted(rows, key=lambda r: -sum(r[2]) / len(r[2])):
         print(f"| `{name}` | {ctr} | {len(sel)} | {sum(sel) / len(sel):.1f} | {len(allv)} | "
@@ -150,13 +155,68 @@ def stats(v):
                 tot=sum(v))
 
 
+def timeline_main(path, first, last):
+    """Launch timeline of repeated solves in a kernel trace: a solve runs from a
+    dispatch of `first` to the next dispatch of `last`; per solve, its span, the time
+    some kernel was running (union of the dispatch intervals, both streams), the sum
+    of the dispatch times, and the idle gaps between dispatches."""
+    path = find(path, "kernel_trace.csv")
+    rows = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]),
+                         short_name(r["Kernel_Name"])))
+    rows.sort()
+    starts = [i for i, r in enumerate(rows) if r[2].split("<")[0] == first]
+    solves = []
+    for a, b in zip(starts, starts[1:] + [len(rows)]):
+        seg = rows[a:b]
+        ends = [j for j, r in enumerate(seg) if r[2].split("<")[0] == last]
+        if not ends:
+            continue
+        seg = seg[:ends[0] + 1]
+        iv = sorted((r[0], r[1]) for r in seg)
+        busy, gaps = 0, []
+        cs, ce = iv[0]
+        for s0, e0 in iv[1:]:
+            if s0 > ce:
+                busy += ce - cs
+                gaps.append(s0 - ce)
+                cs, ce = s0, e0
+            else:
+                ce = max(ce, e0)
+        busy += ce - cs
+        solves.append(dict(n=len(seg), span=(max(r[1] for r in seg) - seg[0][0]) / 1e3,
+                           busy=busy / 1e3, ksum=sum(r[1] - r[0] for r in seg) / 1e3,
+                           gaps=len(gaps), gapsum=sum(gaps) / 1e3,
+                           maxgap=max(gaps) / 1e3 if gaps else 0.0))
+    if not solves:
+        sys.exit("no solve found between the given kernels")
+    common = statistics.mode(s["n"] for s in solves)
+    sel = [s for s in solves if s["n"] == common]
+    print(f"timeline: {os.path.basename(path)}, {len(solves)} solves from `{first}` to "
+          f"`{last}`; {len(sel)} of {common} dispatches (the common shape) summarised\n")
+    print("| per solve | median | min | max |")
+    print("|---|---:|---:|---:|")
+    for k, label in (("span", "span, us"), ("busy", "some kernel running, us"),
+                     ("ksum", "sum of dispatch times, us"), ("gapsum", "idle gaps, us"),
+                     ("gaps", "idle gaps, count"), ("maxgap", "largest gap, us")):
+        v = [s[k] for s in sel]
+        print(f"| {label} | {statistics.median(v):.1f} | {min(v):.1f} | {max(v):.1f} |")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("trace", nargs="?")
     ap.add_argument("--dtype", default="float", help="precision for the family table")
     ap.add_argument("--counters", action="store_true", help="the input is a counter collection")
     ap.add_argument("--sha", action="store_true", help="print the native sources' fingerprint")
+    ap.add_argument("--timeline", nargs=2, metavar=("FIRST", "LAST"),
+                    help="launch timeline of the solves from kernel FIRST to kernel LAST")
     a = ap.parse_args(argv)
+    if a.timeline:
+        timeline_main(a.trace, *a.timeline)
+        return
     if a.sha:
         print(sources_sha256())
         return
@@ -176,7 +236,7 @@ def main(argv=None):
         table.append((name, stats([us for _, us in d]), stats(sel), top))
         base = name.split("<")[0]
         targs = name[len(base):]
-        if base in FAMILY and (a.dtype in targs or "<" not in name):
+        if base in FAMILY and other_dtype(a.dtype) not in targs:
             fam[FAMILY[base]].extend(sel)
     table.sort(key=lambda t: -t[1]["tot"])
     total = sum(t[1]["tot"] for t in table)
