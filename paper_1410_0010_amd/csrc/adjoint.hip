@@ -94,13 +94,19 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
   for (int k = 0; k < 8; ++k) pin4(rec[k]);
   // the KG smallest distinct owner grids of the chunk, one round each, until a round
   // finds none (the usual chunk has one); then only those tiles are cleared
+  // (a wavefront's minimum first, then one LDS atomic per wavefront: every thread
+  // hitting the one word serialised 2048 atomics per round)
   int prev = -1, ng = 0;
   for (int r = 0; r < KG; ++r) {
     if (threadIdx.x == 0) gnext = INT32_MAX;
     __syncthreads();
+    int mn = INT32_MAX;
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (ref[k].y > prev) atomicMin(&gnext, ref[k].y);
+      if (ref[k].y > prev) mn = min(mn, ref[k].y);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mn = min(mn, __shfl_xor(mn, off, 64));
+    if ((threadIdx.x & 63) == 0 && mn != INT32_MAX) atomicMin(&gnext, mn);
     __syncthreads();
     prev = gnext;                                    // the same value in every thread
     if (threadIdx.x == 0) gsl[r] = prev;
