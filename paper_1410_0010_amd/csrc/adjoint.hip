@@ -316,9 +316,8 @@ k_adj_gas_seed(const GridDesc* __restrict__ grids, const OwnerLevel* __restrict_
   const int64_t cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
   const int64_t local = (b - begin[lo]) * (int64_t)kBlock + threadIdx.x;
   if (local >= cells) return;
-  const int lx = (int)(local % g.n[0]);
-  const int ly = (int)((local / g.n[0]) % g.n[1]);
-  const int lz = (int)(local / ((int64_t)g.n[0] * g.n[1]));
+  int lx, ly, lz;
+  box_cell(local, g.n[0], g.n[1], lx, ly, lz);
   const double px = (g.lo[0] + lx + 0.5) * g.dx, py = (g.lo[1] + ly + 0.5) * g.dx,
                pz = (g.lo[2] + lz + 0.5) * g.dx;
   if (owner_lookup(om, nlev, px, py, pz) != first + lo) return;
@@ -344,7 +343,8 @@ hipError_t launch_adj_gas_seed(const GridDesc* grids, const OwnerLevel* om, int3
 // ---- composition transpose: one child level into its parents -------------------------
 // Thread = parent field cell q in the footprint of one child grid; it gathers the child
 // cells 2q-1, 2q, 2q+1, 2q+2 per axis (weights 1/4, 3/4, 3/4, 1/4: the trilinear
-// prolongation between cell centres, transposed) and adds the sum to the parent.
+// prolongation between cell centres, transposed) and adds the sum to the parent (a
+// plain read-modify-write when the child level has one grid: one writer per cell).
 template <int FS>
 __global__ void __launch_bounds__(kBlock)
 k_adj_restrict(const GridDesc* __restrict__ grids, int32_t first, int32_t count,
@@ -367,8 +367,11 @@ k_adj_restrict(const GridDesc* __restrict__ grids, int32_t first, int32_t count,
   }
   const int64_t local = (b - begin[lo]) * (int64_t)kBlock + threadIdx.x;
   if (local >= cells) return;
-  const int q[3] = {flo[0] + (int)(local % fn[0]), flo[1] + (int)((local / fn[0]) % fn[1]),
-                    flo[2] + (int)(local / ((int64_t)fn[0] * fn[1]))};
+  // a parent footprint has fewer than 2^31 cells: 32-bit index arithmetic
+  const uint32_t loc = (uint32_t)local, rowu = loc / (uint32_t)fn[0];
+  const uint32_t zq = rowu / (uint32_t)fn[1];
+  const int q[3] = {flo[0] + (int)(loc - rowu * (uint32_t)fn[0]),
+                    flo[1] + (int)(rowu - zq * (uint32_t)fn[1]), flo[2] + (int)zq};
   // the 4 child cells per axis, clamped into the box with weight 0 outside, so a
   // row's four loads issue together
   const double wts[4] = {0.25, 0.75, 0.75, 0.25};
@@ -408,10 +411,14 @@ k_adj_restrict(const GridDesc* __restrict__ grids, int32_t first, int32_t count,
     }
     if (s0 == 0.0 && s1 == 0.0 && s2 == 0.0 && s3 == 0.0) return;
     double* p = parent_bar + 4 * pc;
-    atomicAdd(p + 0, s0);
-    atomicAdd(p + 1, s1);
-    atomicAdd(p + 2, s2);
-    atomicAdd(p + 3, s3);
+    if (count == 1) {                                // the parent cell's only writer here
+      p[0] += s0; p[1] += s1; p[2] += s2; p[3] += s3;
+    } else {
+      atomicAdd(p + 0, s0);
+      atomicAdd(p + 1, s1);
+      atomicAdd(p + 2, s2);
+      atomicAdd(p + 3, s3);
+    }
   } else {                                           // the Phi component alone, dense
     const gptr<double> cb = as_global<double>(child_bar + g.fld_offset);
     double s3 = 0.0;
@@ -429,7 +436,8 @@ k_adj_restrict(const GridDesc* __restrict__ grids, int32_t first, int32_t count,
       }
     }
     if (s3 == 0.0) return;
-    atomicAdd(parent_bar + pc, s3);
+    if (count == 1) parent_bar[pc] += s3;            // the parent cell's only writer here
+    else atomicAdd(parent_bar + pc, s3);
   }
 }
 
@@ -447,8 +455,9 @@ hipError_t launch_adj_restrict(const GridDesc* grids, int32_t first, int32_t cou
 }
 
 // ---- deposit transpose, grid side ------------------------------------------------------
-// Thread = GMF cell of a grid: the level's FP64 key-box cotangent += gmf_bar / dx^3;
-// own gas (active cells) += gmf_bar; the parent's gas += gmf_bar on ghost cells.
+// kGmfPer GMF cells of a grid per thread: the level's FP64 key-box cotangent +=
+// gmf_bar / dx^3 (a store on a level of one grid); own gas (active cells) += gmf_bar;
+// the parent's gas += gmf_bar on ghost cells.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_adj_deposit_grid(AdjIO<T> io, const DepLevel* __restrict__ tab) {
@@ -462,33 +471,44 @@ k_adj_deposit_grid(AdjIO<T> io, const DepLevel* __restrict__ tab) {
   }
   const GridDesc& g = L.grids[lo];
   const int64_t cells = (int64_t)g.gmf_n[0] * g.gmf_n[1] * g.gmf_n[2];
-  const int64_t local = (blk - L.block_begin[lo]) * (int64_t)kBlock + threadIdx.x;
-  if (local >= cells) return;
-  const double gb = (double)io.gmf_bar[lb][g.gmf_offset + local];
-  if (gb == 0.0) return;
-  const int lx = (int)(local % g.gmf_n[0]);
-  const int ly = (int)((local / g.gmf_n[0]) % g.gmf_n[1]);
-  const int lz = (int)(local / ((int64_t)g.gmf_n[0] * g.gmf_n[1]));
-  const int cx = g.gmf_lo[0] + lx, cy = g.gmf_lo[1] + ly, cz = g.gmf_lo[2] + lz;
-  atomicAdd(L.accum + ((int64_t)(cz - L.key_lo[2]) * L.key_n[1] + (cy - L.key_lo[1])) * L.key_n[0] +
-                (cx - L.key_lo[0]),
-            gb / (L.dx * L.dx * L.dx));
-  const bool active = cx >= g.lo[0] && cx < g.lo[0] + g.n[0] && cy >= g.lo[1] &&
-                      cy < g.lo[1] + g.n[1] && cz >= g.lo[2] && cz < g.lo[2] + g.n[2];
-  if (active) {
-    // atomic: a finer level of the same launch adds its ghost cells to this array
-    double* gbar = io.gas_bar[lb];
-    if (gbar)
-      atomicAdd(gbar + g.gas_offset + ((int64_t)(cz - g.lo[2]) * g.n[1] + (cy - g.lo[1])) * g.n[0] +
-                    (cx - g.lo[0]),
-                gb);
-  } else if (g.parent >= 0) {
-    double* pbar = io.pgas_bar[lb];
-    if (pbar) {
-      const int px = (cx >> 1) - g.parent_lo[0], py = (cy >> 1) - g.parent_lo[1],
-                pz = (cz >> 1) - g.parent_lo[2];
-      atomicAdd(pbar + g.parent_gas_offset + ((int64_t)pz * g.parent_n[1] + py) * g.parent_n[0] + px,
-                gb);
+  const int64_t first = (blk - L.block_begin[lo]) * (int64_t)(kBlock * kGmfPer) + threadIdx.x;
+  double gbv[kGmfPer];
+#pragma unroll
+  for (int k = 0; k < kGmfPer; ++k) {               // the loads first
+    const int64_t local = first + (int64_t)k * kBlock;
+    gbv[k] = local < cells ? (double)io.gmf_bar[lb][g.gmf_offset + local] : 0.0;
+  }
+  const double inv_vol = 1.0 / (L.dx * L.dx * L.dx);   // exact: dx is a power of two
+#pragma unroll
+  for (int k = 0; k < kGmfPer; ++k) {
+    const double gb = gbv[k];
+    if (gb == 0.0) continue;                        // also every cell past the grid's end
+    int lx, ly, lz;
+    box_cell(first + (int64_t)k * kBlock, g.gmf_n[0], g.gmf_n[1], lx, ly, lz);
+    const int cx = g.gmf_lo[0] + lx, cy = g.gmf_lo[1] + ly, cz = g.gmf_lo[2] + lz;
+    double* kc = L.accum + ((int64_t)(cz - L.key_lo[2]) * L.key_n[1] + (cy - L.key_lo[1])) * L.key_n[0] +
+                 (cx - L.key_lo[0]);
+    // one grid on the level: this thread is the cell's only writer and the grid was
+    // cleared, so a store gives the atomic add's value
+    if (L.ngrids == 1) *kc = gb * inv_vol;
+    else atomicAdd(kc, gb * inv_vol);
+    const bool active = cx >= g.lo[0] && cx < g.lo[0] + g.n[0] && cy >= g.lo[1] &&
+                        cy < g.lo[1] + g.n[1] && cz >= g.lo[2] && cz < g.lo[2] + g.n[2];
+    if (active) {
+      // atomic: a finer level of the same launch adds its ghost cells to this array
+      double* gbar = io.gas_bar[lb];
+      if (gbar)
+        atomicAdd(gbar + g.gas_offset + ((int64_t)(cz - g.lo[2]) * g.n[1] + (cy - g.lo[1])) * g.n[0] +
+                      (cx - g.lo[0]),
+                  gb);
+    } else if (g.parent >= 0) {
+      double* pbar = io.pgas_bar[lb];
+      if (pbar) {
+        const int px = (cx >> 1) - g.parent_lo[0], py = (cy >> 1) - g.parent_lo[1],
+                  pz = (cz >> 1) - g.parent_lo[2];
+        atomicAdd(pbar + g.parent_gas_offset + ((int64_t)pz * g.parent_n[1] + py) * g.parent_n[0] + px,
+                  gb);
+      }
     }
   }
 }

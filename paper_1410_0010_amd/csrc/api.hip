@@ -1636,7 +1636,7 @@ apm_status apm_create(apm_plan plan, int32_t device, void* stream, apm_ctx* out)
       const int64_t gc = (int64_t)g.gmf_n[0] * g.gmf_n[1] * g.gmf_n[2];
       const int64_t fc = (int64_t)g.fld_n[0] * g.fld_n[1] * g.fld_n[2];
       const int64_t ac = (int64_t)g.n[0] * g.n[1] * g.n[2];
-      dep[i + 1] = dep[i] + (gc + kBlock - 1) / kBlock;
+      dep[i + 1] = dep[i] + (gc + kBlock * kGmfPer - 1) / (kBlock * kGmfPer);
       cmp[i + 1] = cmp[i] + (fc + kBlock - 1) / kBlock;
       act[i + 1] = act[i] + (ac + kBlock - 1) / kBlock;
       int64_t fc2 = 0;                               // parent field cells under g's stencils

@@ -140,6 +140,16 @@ template <int L> __device__ __forceinline__ void stage_sync() {
   }
 }
 
+// Cell (x, y, z) of flat index i (x fastest) in a box of nx by ny by any cells, with
+// 32-bit arithmetic: every box of a plan has fewer than 2^31 cells (64-bit division is
+// a long software sequence).
+__device__ __forceinline__ void box_cell(int64_t i, int nx, int ny, int& x, int& y, int& z) {
+  const uint32_t u = (uint32_t)i, row = u / (uint32_t)nx, zz = row / (uint32_t)ny;
+  x = (int)(u - row * (uint32_t)nx);
+  y = (int)(row - zz * (uint32_t)ny);
+  z = (int)zz;
+}
+
 // ---- LDS layout of a transform line ---------------------------------------------
 // Element i of a line of length L sits at swz<L>(i) (an XOR permutation of the
 // 8-value groups), and lines are line_stride(L) values apart.  Both are chosen so

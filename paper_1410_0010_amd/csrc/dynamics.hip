@@ -112,9 +112,8 @@ k_gas_energy(const GridDesc* __restrict__ grids, const OwnerLevel* __restrict__ 
   const int64_t cells = (int64_t)g.n[0] * g.n[1] * g.n[2];
   const int64_t local = (b - begin[gl]) * (int64_t)kBlock + threadIdx.x;
   if (local < cells) {
-    const int lx = (int)(local % g.n[0]);
-    const int ly = (int)((local / g.n[0]) % g.n[1]);
-    const int lz = (int)(local / ((int64_t)g.n[0] * g.n[1]));
+    int lx, ly, lz;
+    box_cell(local, g.n[0], g.n[1], lx, ly, lz);
     // owner of the cell centre: finest grid containing it, lowest index on that level
     const double px = (g.lo[0] + lx + 0.5) * g.dx, py = (g.lo[1] + ly + 0.5) * g.dx,
                  pz = (g.lo[2] + lz + 0.5) * g.dx;   // exact: dx is a power of two

@@ -32,9 +32,8 @@ k_compose(const GridDesc* __restrict__ grids, const int64_t* __restrict__ begin,
   if (local >= cells) return;
   V4<T> v = own[g.fld_offset + local];
   if (parent) {
-    const int lx = (int)(local % g.fld_n[0]);
-    const int ly = (int)((local / g.fld_n[0]) % g.fld_n[1]);
-    const int lz = (int)(local / ((int64_t)g.fld_n[0] * g.fld_n[1]));
+    int lx, ly, lz;
+    box_cell(local, g.fld_n[0], g.fld_n[1], lx, ly, lz);
     const int c[3] = {g.fld_lo[0] + lx, g.fld_lo[1] + ly, g.fld_lo[2] + lz};
     int pi[3][2];
     for (int a = 0; a < 3; ++a) {

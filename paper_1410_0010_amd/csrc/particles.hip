@@ -499,9 +499,9 @@ hipError_t launch_deposit_tiles(const DepIO<T>& io, const DepLevel* tab, hipStre
 }
 
 // ---- finalize: GMF cell = accumulated mass / dx^3 + gas ------------------------------
-// (own gas on active cells, the parent's copied onto ghost cells); one thread per GMF
-// cell of every grid of every level of the batch.  COMP: the pair's sum, scaled by
-// 1/dx^3 (a power of two: exact) in FP32.
+// (own gas on active cells, the parent's copied onto ghost cells); kGmfPer GMF cells
+// per thread over every grid of every level of the batch.  COMP: the pair's sum,
+// scaled by 1/dx^3 (a power of two: exact) in FP32.
 template <typename T, bool COMP>
 __global__ void __launch_bounds__(kBlock) k_deposit_finalize(DepIO<T> io, const DepLevel* __restrict__ tab) {
   const int lb = batch_level(io.fin_blk0, io.nlev, blockIdx.x);
@@ -510,39 +510,45 @@ __global__ void __launch_bounds__(kBlock) k_deposit_finalize(DepIO<T> io, const 
   const int gi = find_grid(L.block_begin, L.ngrids, blk);
   const GridDesc& g = L.grids[gi];
   const int64_t cells = (int64_t)g.gmf_n[0] * g.gmf_n[1] * g.gmf_n[2];
-  const int64_t local = (blk - L.block_begin[gi]) * (int64_t)kBlock + threadIdx.x;
-  if (local >= cells) return;
-  // a GMF box has fewer than 2^31 cells: 32-bit index arithmetic (64-bit division is
-  // a long software sequence)
-  const uint32_t loc = (uint32_t)local, nx = (uint32_t)g.gmf_n[0], ny = (uint32_t)g.gmf_n[1];
-  const uint32_t row = loc / nx;
-  const int lx = (int)(loc - row * nx);
-  const int lz = (int)(row / ny);
-  const int ly = (int)(row - (uint32_t)lz * ny);
-  const int cx = g.gmf_lo[0] + lx, cy = g.gmf_lo[1] + ly, cz = g.gmf_lo[2] + lz;
-  const int64_t kc = ((int64_t)(cz - L.key_lo[2]) * L.key_n[1] + (cy - L.key_lo[1])) * L.key_n[0] +
-                     (cx - L.key_lo[0]);
-  T rho;
-  if constexpr (COMP) {
-    const nvec2<float> p = as_global<nvec2<float>>(L.accum)[kc];
-    rho = (T)((p.x + p.y) * (float)(L.inv_dx * L.inv_dx * L.inv_dx));
-  } else {
-    rho = (T)(as_global<double>(L.accum)[kc] / (L.dx * L.dx * L.dx));
-  }
-  const bool active = cx >= g.lo[0] && cx < g.lo[0] + g.n[0] && cy >= g.lo[1] &&
-                      cy < g.lo[1] + g.n[1] && cz >= g.lo[2] && cz < g.lo[2] + g.n[2];
+  const int64_t first = (blk - L.block_begin[gi]) * (int64_t)(kBlock * kGmfPer) + threadIdx.x;
   const T* gas = io.gas[lb];
   const T* pgas = io.pgas[lb];
-  if (active) {
-    if (gas)
-      rho += gas[g.gas_offset + ((int64_t)(cz - g.lo[2]) * g.n[1] + (cy - g.lo[1])) * g.n[0] +
-                 (cx - g.lo[0])];
-  } else if (pgas && g.parent >= 0) {
-    const int px = (cx >> 1) - g.parent_lo[0], py = (cy >> 1) - g.parent_lo[1],
-              pz = (cz >> 1) - g.parent_lo[2];
-    rho += pgas[g.parent_gas_offset + ((int64_t)pz * g.parent_n[1] + py) * g.parent_n[0] + px];
+  int cx[kGmfPer], cy[kGmfPer], cz[kGmfPer];
+  double mass[kGmfPer];
+  T add[kGmfPer];
+#pragma unroll
+  for (int k = 0; k < kGmfPer; ++k) {               // every load first
+    const int64_t local = first + (int64_t)k * kBlock;
+    const int64_t lc = local < cells ? local : 0;   // a valid cell; not written below
+    int lx, ly, lz;
+    box_cell(lc, g.gmf_n[0], g.gmf_n[1], lx, ly, lz);
+    cx[k] = g.gmf_lo[0] + lx; cy[k] = g.gmf_lo[1] + ly; cz[k] = g.gmf_lo[2] + lz;
+    const int64_t kc = ((int64_t)(cz[k] - L.key_lo[2]) * L.key_n[1] + (cy[k] - L.key_lo[1])) *
+                           L.key_n[0] + (cx[k] - L.key_lo[0]);
+    if constexpr (COMP) {
+      const nvec2<float> p = as_global<nvec2<float>>(L.accum)[kc];
+      mass[k] = (double)((p.x + p.y) * (float)(L.inv_dx * L.inv_dx * L.inv_dx));
+    } else {
+      mass[k] = as_global<double>(L.accum)[kc] / (L.dx * L.dx * L.dx);
+    }
+    const bool active = cx[k] >= g.lo[0] && cx[k] < g.lo[0] + g.n[0] && cy[k] >= g.lo[1] &&
+                        cy[k] < g.lo[1] + g.n[1] && cz[k] >= g.lo[2] && cz[k] < g.lo[2] + g.n[2];
+    add[k] = (T)0;
+    if (active) {
+      if (gas)
+        add[k] = gas[g.gas_offset + ((int64_t)(cz[k] - g.lo[2]) * g.n[1] + (cy[k] - g.lo[1])) * g.n[0] +
+                     (cx[k] - g.lo[0])];
+    } else if (pgas && g.parent >= 0) {
+      const int px = (cx[k] >> 1) - g.parent_lo[0], py = (cy[k] >> 1) - g.parent_lo[1],
+                pz = (cz[k] >> 1) - g.parent_lo[2];
+      add[k] = pgas[g.parent_gas_offset + ((int64_t)pz * g.parent_n[1] + py) * g.parent_n[0] + px];
+    }
   }
-  io.gmf[lb][g.gmf_offset + local] = rho;
+#pragma unroll
+  for (int k = 0; k < kGmfPer; ++k) {
+    const int64_t local = first + (int64_t)k * kBlock;
+    if (local < cells) io.gmf[lb][g.gmf_offset + local] = (T)mass[k] + add[k];
+  }
 }
 
 template <typename T>
