@@ -190,14 +190,6 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       X[q] = (z < gz && col_ok) ? src[q * qstride] : mk<T>(0, 0);
     }
   }
-  fft_regs<T, L, false>(line, w, X, tb);
-  // the forward result waits in LDS, each thread's own values in its own slots (no
-  // barrier: the same thread reads them back), so the inverse transforms do not
-  // hold it in registers
-  C2<T>* xs = lds + (int64_t)nl * ls + t;
-  const int nt = (int)blockDim.x;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) xs[q * nt] = X[q];
   // multipliers of this column: kx fastest in the table, so lanes read neighbours
   const int kxc = col_ok ? c0 + cb : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
@@ -205,6 +197,28 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   using TV = typename std::conditional<KS == 2, nvec2<T>, T>::type;
   const uint32_t ostride = (uint32_t)((My / 2 + 1) * W);
   const gptr<TV> gcol = as_global<TV>(J.kern) + (int64_t)kyo * W;
+  // with one kernel the multiplier is read once, while the forward transform runs,
+  // and the slots below hold Gf X: both products are formed from them
+  T gf[KS == 1 ? 8 : 1];
+  if constexpr (KS == 1) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int kz = w + q * (L / 8);
+      const int kzo = kz <= L / 2 ? kz : L - kz;
+      gf[q] = gcol[(uint32_t)kzo * ostride + (uint32_t)kxc];
+    }
+  }
+  fft_regs<T, L, false>(line, w, X, tb);
+  // the forward result waits in LDS, each thread's own values in its own slots (no
+  // barrier: the same thread reads them back), so the inverse transforms do not
+  // hold it in registers
+  C2<T>* xs = lds + (int64_t)nl * ls + t;
+  const int nt = (int)blockDim.x;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    if constexpr (KS == 1) xs[q * nt] = mk<T>(gf[q] * X[q].x, gf[q] * X[q].y);
+    else xs[q * nt] = X[q];
+  }
   const int64_t zas = (int64_t)fz * My * P;            // stride between z arrays
   C2<T>* dst = zo + tile_row(0, ky, fz) * P + c0 + cb;
   constexpr int kProducts = KS == 1 ? 2 : 3;        // arrays written
@@ -214,17 +228,24 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int kz = w + q * (L / 8);
-      const int kzo = kz <= L / 2 ? kz : L - kz;
-      const TV gv = gcol[(uint32_t)kzo * ostride + (uint32_t)kxc];
-      T mul;
-      if constexpr (KS == 2) mul = s == 0 ? gv.x : (s == 1 ? dzs[kz] * gv.x : gv.y);
-      else mul = s == 0 ? gv : dzs[kz] * gv;
       const C2<T> x = xs[q * nt];
+      T mul;
+      if constexpr (KS == 2) {
+        const int kzo = kz <= L / 2 ? kz : L - kz;
+        const TV gv = gcol[(uint32_t)kzo * ostride + (uint32_t)kxc];
+        mul = s == 0 ? gv.x : (s == 1 ? dzs[kz] * gv.x : gv.y);
+      } else {
+        mul = s == 0 ? (T)1 : dzs[kz];
+      }
       v[q] = s == 1 ? mk<T>(mul * x.y, -mul * x.x)   // -i d_z Gf X
                     : mk<T>(mul * x.x, mul * x.y);
     }
     __syncthreads();                                 // the previous transform's reads
-    fft_regs<T, L, true>(line, w, v, tb);
+    // the worker index, opaque to the compiler here: the LDS addresses of the stages
+    // are formed again in each product instead of held in registers across the loop
+    int wr = w;
+    asm volatile("" : "+v"(wr));
+    fft_regs<T, L, true>(line, wr, v, tb);
     if (col_ok) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
