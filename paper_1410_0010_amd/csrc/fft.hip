@@ -262,12 +262,12 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 // a_y <- -i d_y(k_y) Gf rho, a_z <- array 1, and with NC = 4 Phi <- array 2 (with
 // NC = 3 the potential is the a_x line itself); inverse FFT along y; rows j' < fy
 // written from transform index (off_y + j') mod L into the y buffer (planes c fz + j,
-// fy rows, W columns).  Thread t is worker t / (NC nl) of line (component
-// (t / nl) mod NC, column t mod nl): its column loads and stores go straight to and
-// from the transform's registers (the a_x and a_y lines of a column read the same
-// array 0 elements; the second read hits the cache).
+// fy rows, W columns).  Thread t is worker t / nl of column t mod nl and transforms
+// the column's lines one after another: its column loads and stores go straight to
+// and from the transform's registers, a block covers nl adjacent columns of every
+// row it touches, and array 0 is read once for the a_x and a_y lines.
 template <typename T, int L, int NC>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(kZConvMaxThreads)
 k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
             const C2<T>* __restrict__ zb, C2<T>* __restrict__ yb, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
@@ -282,32 +282,55 @@ k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int c0 = (int)(blk % nbw) * nl;
   const gptr<T> dys = as_global<T>(J.dsym[1]);
   const int t = threadIdx.x;
-  const int cb = t % nl, c = (t / nl) % NC, w = t / (NC * nl);
+  const int cb = t % nl, w = t / nl;
   const Twid<T, L> tb(w, tw);
   const bool col_ok = c0 + cb < W;
   const int64_t zs = (int64_t)fz * My * P;             // stride between z arrays
-  const C2<T>* zin = zb + J.z_off + (c == 0 ? 0 : c - 1) * zs + c0 + cb;
-  C2<T> v[8];
+  const C2<T>* zin = zb + J.z_off + c0 + cb;
+  C2<T>* line = lds + cb * ls;
+  // arrays 0 and 1, both read before the first transform
+  C2<T> a0[8], a1[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int r = w + q * (L / 8);
-    v[q] = col_ok ? zin[tile_row(j, r, fz) * P] : mk<T>(0, 0);
+    const int64_t o = tile_row(j, w + q * (L / 8), fz) * P;
+    a0[q] = col_ok ? zin[o] : mk<T>(0, 0);
+    a1[q] = col_ok ? zin[zs + o] : mk<T>(0, 0);
   }
-  if (c == 1) {                                      // -i d_y Gf rho
+  const int64_t ys = (int64_t)fz * fy * P;             // stride between components
+  C2<T>* yout = yb + J.y_off + (int64_t)j * fy * P + c0 + cb;
+#pragma unroll 1
+  for (int c = 0; c < NC; ++c) {
+    // the worker index, opaque to the compiler here: the addresses of the stages' LDS
+    // accesses and of the stores are formed again for each line instead of held in
+    // registers across the loop
+    int wr = w;
+    asm volatile("" : "+v"(wr));
+    C2<T> v[8];
+    if (c == 0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const T d = dys[w + q * (L / 8)];
-      v[q] = mk<T>(d * v[q].y, -d * v[q].x);
+      for (int q = 0; q < 8; ++q) v[q] = a0[q];
+    } else if (c == 1) {                             // -i d_y Gf rho
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const T d = dys[wr + q * (L / 8)];
+        v[q] = mk<T>(d * a0[q].y, -d * a0[q].x);
+      }
+    } else if (c == 2) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = a1[q];
+    } else {                                         // NC = 4: Phi from array 2
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        v[q] = col_ok ? zin[2 * zs + tile_row(j, wr + q * (L / 8), fz) * P] : mk<T>(0, 0);
     }
-  }
-  fft_regs<T, L, true>(lds + (c * nl + cb) * ls, w, v, tb);
-  if (col_ok) {
-    const int64_t ys = (int64_t)fz * fy * P;           // stride between components
-    C2<T>* yout = yb + J.y_off + c * ys + (int64_t)j * fy * P + c0 + cb;
+    if (c > 0) __syncthreads();                      // the previous line's LDS reads
+    fft_regs<T, L, true>(line, wr, v, tb);
+    if (col_ok) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int jj = (w + q * (L / 8) - oy) & (L - 1);  // field row of this element
-      if (jj < fy) yout[(int64_t)jj * P] = v[q];
+      for (int q = 0; q < 8; ++q) {
+        const int jj = (wr + q * (L / 8) - oy) & (L - 1);  // field row of this element
+        if (jj < fy) yout[c * ys + (int64_t)jj * P] = v[q];
+      }
     }
   }
 }
@@ -422,17 +445,20 @@ int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], in
 }
 
 template <typename T> int default_lines(int pass, int L) {
+  const bool mirror = mirror_pass(pass) != pass;
   pass = mirror_pass(pass);
   int nl = (std::is_same<T, float>::value ? 4096 : 2048) / L;
   if (pass == PASS_X_INV) return nl < 4 ? 4 : nl;
-  if (pass == PASS_Y_INV) return nl / 4 < 1 ? 1 : nl / 4;
+  if (pass == PASS_Y_INV && mirror) return nl / 4 < 1 ? 1 : nl / 4;
   if (pass == PASS_Z_CONV) while (nl > 1 && nl * (L / 8) > kZConvMaxThreads) nl /= 2;
   return nl;
 }
 
 static int pass_lines_per_block(int pass, int nl, int nc) {
-  // the y inverse pass has nc lines per column; its transpose always four
-  if (pass == PASS_Y_INV) return nc * nl;
+  // the y inverse pass transforms its nc lines per column one after another; its
+  // transpose holds all four at once
+  (void)nc;
+  if (pass == PASS_Y_INV) return nl;
   return mirror_pass(pass) == PASS_Y_INV ? 4 * nl : nl;
 }
 
@@ -450,11 +476,13 @@ int pass_threads(int pass, int L, int nl, int nc) {
 template <typename T> size_t pass_lds(int pass, int L, int nl, int nc) {
   if (nl < 1 || (nc != 3 && nc != 4)) return 0;
   const int lines = pass_lines_per_block(pass, nl, nc);
+  // the z passes and the forward y inverse pass hold two sets of line values per thread
+  const bool two_sets = pass == PASS_Y_INV || mirror_pass(pass) == PASS_Z_CONV;
   pass = mirror_pass(pass);
   // the z pass also parks each thread's eight forward-transform values (nl L values)
   const size_t bytes = ((size_t)lines * pass_ls<T>(pass, L, nl) + (pass == PASS_Z_CONV ? (size_t)nl * L : 0)) *
                        sizeof(C2<T>);
-  const int max_threads = pass == PASS_Z_CONV ? kZConvMaxThreads : 1024;
+  const int max_threads = two_sets ? kZConvMaxThreads : 1024;
   if (lines * (L / 8) > max_threads || bytes > (size_t)kMaxLDS) return 0;
   if (pass == PASS_X_INV && (nl % 4) != 0) return 0;
   return bytes;

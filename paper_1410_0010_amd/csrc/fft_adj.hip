@@ -222,8 +222,10 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   // multipliers of this column: kx fastest in the table, so lanes read neighbours;
   // each product's set is read where it is used (holding all three for the whole
   // kernel spills FP64 registers)
-  const int64_t ks = J.kstride, kp = J.kpot;          // table values per entry, Gp's offset
-  const int64_t ostride = (int64_t)(My / 2 + 1) * W * ks;
+  // 32-bit offsets from a per-thread base (an octant table has < 2^31 values)
+  const int64_t ks = J.kstride;                        // table values per entry
+  const uint32_t kp = (uint32_t)J.kpot;                // Gp's offset in an entry
+  const uint32_t ostride = (uint32_t)((My / 2 + 1) * W * ks);
   const gptr<T> gcol = as_global<T>(J.kern) + ((int64_t)kyo * W + kxc) * ks;
   // S accumulates in LDS, each thread's values in its own slots (no barrier: the same
   // thread reads them back), so the forward transforms do not hold it in registers
@@ -231,26 +233,31 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int nt = (int)blockDim.x;
 #pragma unroll 1
   for (int s = 0; s < 3; ++s) {
+    // the worker index, opaque to the compiler here: the addresses of the loads and
+    // of the stages' LDS accesses are formed again in each pass of the loop instead of
+    // held in registers across it
+    int wr = w;
+    asm volatile("" : "+v"(wr));
     const C2<T>* zs_in = zin + s * zs;
     C2<T> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int r = w + q * (L / 8);                 // transform position
+      const int r = wr + q * (L / 8);                // transform position
       const int jz = (r - oz) & (L - 1);             // field plane landing there
       v[q] = (col_ok && jz < fz) ? zs_in[__umul24((uint32_t)jz, ps32) + cb] : mk<T>(0, 0);
     }
     if (s > 0) __syncthreads();                      // the previous transform's reads
-    fft_regs<T, L, false>(line, w, v, tb);
+    fft_regs<T, L, false>(line, wr, v, tb);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int kz = w + q * (L / 8);
+      const int kz = wr + q * (L / 8);
       const int kzo = kz <= L / 2 ? kz : L - kz;
-      const T gf = gcol[kzo * ostride];
+      const T gf = gcol[(uint32_t)kzo * ostride];
       const C2<T> X = v[q];
       if (s == 0) ss[q * nt] = mk<T>(gf * X.x, gf * X.y);
       else if (s == 1) ss[q * nt] = cadd(ss[q * nt], mul_id<T>(gf * dzs[kz], X));
       else {
-        const T gp = gcol[kzo * ostride + kp];
+        const T gp = gcol[(uint32_t)kzo * ostride + kp];
         ss[q * nt] = cadd(ss[q * nt], mk<T>(gp * X.x, gp * X.y));
       }
     }
@@ -259,7 +266,9 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 #pragma unroll
   for (int q = 0; q < 8; ++q) S[q] = ss[q * nt];
   __syncthreads();
-  fft_regs<T, L, true>(line, w, S, tb);
+  int wi = w;
+  asm volatile("" : "+v"(wi));
+  fft_regs<T, L, true>(line, wi, S, tb);
   if (col_ok) {
     C2<T>* dst = spec + w * pstride + cb;
     const int64_t qstride = (int64_t)(L / 8) * pstride;
