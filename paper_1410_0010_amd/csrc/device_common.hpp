@@ -150,13 +150,12 @@ __device__ __forceinline__ void box_cell(int64_t i, int nx, int ny, int& x, int&
   z = (int)zz;
 }
 
-// ---- LDS layout of a transform line ---------------------------------------------
-// Element i of a line of length L sits at swz<L>(i) (an XOR permutation of the
-// 8-value groups), and lines are line_stride(L) values apart.  Both are chosen so
-// the strided writes of the first Stockham stages, the contiguous reads and the
-// column-wise loads and stores (lane -> line) spread over the LDS banks: simulated
-// on 32- and 64-bank models, the stage accesses cost 1.0-2.0x the conflict-free
-// cycle count instead of 2.1-3.5x for the plain layout.
+// ---- LDS layout of a row-pass line ------------------------------------------------
+// In the transforms that run on lines held in LDS (fft_line, fft_line_rin: the x
+// passes and the y transpose) element i of a line of length L sits at swz<L>(i) (an
+// XOR permutation of the 8-value groups), and lines are line_stride(L) values apart.
+// Both are chosen so the strided writes of the first Stockham stages and the
+// contiguous reads spread over the LDS banks when a wavefront's lanes walk one line.
 template <int L> __device__ __forceinline__ int swz(int i) {
   if constexpr (L >= 512) return i ^ (((i >> 3) & 7) ^ (((i >> 6) & 7) << 3));
   else if constexpr (L >= 32) return i ^ ((i >> 3) & (L / 8 - 1 < 63 ? L / 8 - 1 : 63));
@@ -165,6 +164,28 @@ template <int L> __device__ __forceinline__ int swz(int i) {
 __host__ __device__ constexpr int line_stride(int L) {
   return L == 16 ? 18 : L == 32 ? 37 : L == 64 ? 70 : L == 128 ? 133 : L == 256 ? 261
        : L == 512 ? 517 : L + 5;
+}
+
+// ---- LDS layout of a column-pass line ------------------------------------------------
+// Transforms that start and end in registers (fft_regs) keep element i of a line at
+// i + (i >> s): one spare slot after every 2^s elements, s = 3 (s = log2(L/8) for lines
+// shorter than 64).  Every LDS access of their Stockham stages has the form base + o
+// with o fixed for the stage, and for all of them pad(base + o) = pad(base) + o +
+// (o >> s) (o is a multiple of 2^s, or base + o stays inside one aligned 2^s block): a
+// worker forms one address per stage and its eight accesses take compile-time offsets.
+// Lines are col_stride(L, nl) values apart, a stride the host picks so the nl lines a
+// wavefront touches start on different banks.
+template <int L> struct CPad {
+  static constexpr int s = Log2<L / 8>::v < 3 ? Log2<L / 8>::v : 3;
+  __device__ static __forceinline__ int at(int i) { return i + (i >> s); }
+  static constexpr int off(int o) { return o + (o >> s); }
+};
+template <typename T> __host__ __device__ constexpr int col_stride(int L, int nl) {
+  const int s = L >= 64 ? 3 : (L >= 32 ? 2 : 1);     // CPad<L>::s
+  // 64 banks of 4 bytes: neighbouring lines start 64 / (dwords per value * nl) values
+  // apart in bank order
+  const int skew = 64 / ((int)(sizeof(T) / 2) * (nl > 0 ? nl : 1));
+  return L + (L >> s) + (skew > 0 ? skew : 1);
 }
 
 // ---- twiddles ---------------------------------------------------------------------
@@ -272,9 +293,11 @@ __device__ __forceinline__ void fft_line(C2<T>* line, int w, const Twid<T, L>& t
 // fastest across lanes, the layout of coalesced column loads), so the LDS exchanges
 // use block barriers and every thread of the block must call this.  On entry no
 // thread may still read the line's LDS; on exit reads of it may still be in flight:
-// the caller puts a block barrier before the line's LDS is written again.
+// the caller puts a block barrier before the line's LDS is written again.  PAD picks
+// the line layout: the padded one of CPad (lines col_stride apart) or the swizzled one
+// of swz (lines line_stride apart); the z passes measured faster with the latter.
 
-template <typename T, int L, int R, int NS, bool INV, bool FIRST>
+template <typename T, int L, int R, int NS, bool INV, bool FIRST, bool PAD>
 __device__ __forceinline__ void regs_stage(C2<T>* line, int w, C2<T> (&v)[8], const Twid<T, L>& tb) {
   constexpr int B = 8 / R;
   constexpr int W8 = L / 8;
@@ -284,8 +307,17 @@ __device__ __forceinline__ void regs_stage(C2<T>* line, int w, C2<T> (&v)[8], co
 #pragma unroll
   for (int q = 0; q < B; ++q) {
     const int j = w + q * W8;
+    if constexpr (FIRST) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) u[q][r] = FIRST ? v[q + r * B] : line[swz<L>(j + r * (L / R))];
+      for (int r = 0; r < R; ++r) u[q][r] = v[q + r * B];
+    } else if constexpr (PAD) {
+      const C2<T>* src = line + CPad<L>::at(j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[q][r] = src[CPad<L>::off(r * (L / R))];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[q][r] = line[swz<L>(j + r * (L / R))];
+    }
     if constexpr (NS > 1) {
       C2<T> p[8];
       twiddle_powers(p, tb.t[Twid<T, L>::index(NS)]);
@@ -308,34 +340,40 @@ __device__ __forceinline__ void regs_stage(C2<T>* line, int w, C2<T> (&v)[8], co
     for (int q = 0; q < B; ++q) {
       const int j = w + q * W8;
       const int base = (j / NS) * NS * R + j % NS;
+      if constexpr (PAD) {
+        C2<T>* dst = line + CPad<L>::at(base);
 #pragma unroll
-      for (int r = 0; r < R; ++r) line[swz<L>(base + r * NS)] = u[q][r];
+        for (int r = 0; r < R; ++r) dst[CPad<L>::off(r * NS)] = u[q][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) line[swz<L>(base + r * NS)] = u[q][r];
+      }
     }
     __syncthreads();                                 // writes seen by the next stage
   }
 }
 
-template <typename T, int L, int NS, bool INV, bool FIRST>
+template <typename T, int L, int NS, bool INV, bool FIRST, bool PAD>
 __device__ __forceinline__ void regs_radix8(C2<T>* line, int w, C2<T> (&v)[8], const Twid<T, L>& tb) {
   if constexpr (NS < L) {
-    regs_stage<T, L, 8, NS, INV, FIRST>(line, w, v, tb);
-    regs_radix8<T, L, NS * 8, INV, false>(line, w, v, tb);
+    regs_stage<T, L, 8, NS, INV, FIRST, PAD>(line, w, v, tb);
+    regs_radix8<T, L, NS * 8, INV, false, PAD>(line, w, v, tb);
   }
 }
 
 // Unnormalised; INV: exp(+2 pi i ...).  Same stage sequence as fft_line; tb from
 // Twid<T, L>(w, tw) of the same worker.
-template <typename T, int L, bool INV>
+template <typename T, int L, bool INV, bool PAD = true>
 __device__ __forceinline__ void fft_regs(C2<T>* line, int w, C2<T> (&v)[8], const Twid<T, L>& tb) {
   constexpr int r0 = Log2<L>::v % 3;
   if constexpr (r0 == 1) {
-    regs_stage<T, L, 2, 1, INV, true>(line, w, v, tb);
-    regs_radix8<T, L, 2, INV, false>(line, w, v, tb);
+    regs_stage<T, L, 2, 1, INV, true, PAD>(line, w, v, tb);
+    regs_radix8<T, L, 2, INV, false, PAD>(line, w, v, tb);
   } else if constexpr (r0 == 2) {
-    regs_stage<T, L, 4, 1, INV, true>(line, w, v, tb);
-    regs_radix8<T, L, 4, INV, false>(line, w, v, tb);
+    regs_stage<T, L, 4, 1, INV, true, PAD>(line, w, v, tb);
+    regs_radix8<T, L, 4, INV, false, PAD>(line, w, v, tb);
   } else {
-    regs_radix8<T, L, 1, INV, true>(line, w, v, tb);
+    regs_radix8<T, L, 1, INV, true, PAD>(line, w, v, tb);
   }
 }
 

@@ -208,7 +208,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       gf[q] = gcol[(uint32_t)kzo * ostride + (uint32_t)kxc];
     }
   }
-  fft_regs<T, L, false>(line, w, X, tb);
+  fft_regs<T, L, false, false>(line, w, X, tb);
   // the forward result waits in LDS, each thread's own values in its own slots (no
   // barrier: the same thread reads them back), so the inverse transforms do not
   // hold it in registers
@@ -245,7 +245,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
     // are formed again in each product instead of held in registers across the loop
     int wr = w;
     asm volatile("" : "+v"(wr));
-    fft_regs<T, L, true>(line, wr, v, tb);
+    fft_regs<T, L, true, false>(line, wr, v, tb);
     if (col_ok) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -462,10 +462,12 @@ static int pass_lines_per_block(int pass, int nl, int nc) {
   return mirror_pass(pass) == PASS_Y_INV ? 4 * nl : nl;
 }
 
-// LDS line stride: line_stride(L) for every pass (the swizzled layout).
+// LDS line stride: line_stride(L) for the passes on swizzled lines (the row passes'
+// fft_line and the z passes), col_stride(L, nl) for the y passes (the padded layout
+// of fft_regs; also room enough for the swizzled lines of the y transpose).
 template <typename T> static int pass_ls(int pass, int L, int nl) {
-  (void)pass; (void)nl;
-  return line_stride(L);
+  const int m = mirror_pass(pass);
+  return m == PASS_Y_FWD || m == PASS_Y_INV ? col_stride<T>(L, nl) : line_stride(L);
 }
 
 template <typename T> int pass_row_stride(int pass, int L, int nl) { return pass_ls<T>(pass, L, nl); }

@@ -247,7 +247,7 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       v[q] = (col_ok && jz < fz) ? zs_in[__umul24((uint32_t)jz, ps32) + cb] : mk<T>(0, 0);
     }
     if (s > 0) __syncthreads();                      // the previous transform's reads
-    fft_regs<T, L, false>(line, wr, v, tb);
+    fft_regs<T, L, false, false>(line, wr, v, tb);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int kz = wr + q * (L / 8);
@@ -268,7 +268,7 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   __syncthreads();
   int wi = w;
   asm volatile("" : "+v"(wi));
-  fft_regs<T, L, true>(line, wi, S, tb);
+  fft_regs<T, L, true, false>(line, wi, S, tb);
   if (col_ok) {
     C2<T>* dst = spec + w * pstride + cb;
     const int64_t qstride = (int64_t)(L / 8) * pstride;
@@ -514,11 +514,11 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
     const int kzo = kz <= L / 2 ? kz : L - kz;
     gp[q] = gcol[kzo * ostride];
   }
-  fft_regs<T, L, false>(line, w, v, tb);
+  fft_regs<T, L, false, false>(line, w, v, tb);
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = mk<T>(gp[q] * v[q].x, gp[q] * v[q].y);
   __syncthreads();
-  fft_regs<T, L, true>(line, w, v, tb);
+  fft_regs<T, L, true, false>(line, w, v, tb);
   if (col_ok) {
     C2<T>* dst = spec + w * pstride + cb;
     const int64_t qstride = (int64_t)(L / 8) * pstride;
