@@ -80,7 +80,9 @@ struct ConvJob {
 };
 int64_t pass_blocks(int pass, const int g[3], const int M[3], const int f[3], int nl);
 template <typename T> int default_lines(int pass, int L);
-constexpr int kZConvMaxThreads = 512;     // keeps the FP64 z passes free of spills
+// threads per block of the passes that hold two sets of line values per thread (the z
+// passes, the y inverse pass): 512 keeps the FP64 kernels free of spills
+template <typename T> constexpr int kTwoSetThreads = sizeof(T) == 4 ? 1024 : 512;
 constexpr int kMaxLDS = 163840;           // dynamic LDS per workgroup on gfx950
 hipError_t allow_lds_forward();           // raise every transform kernel's LDS limit
 hipError_t allow_lds_adjoint();

@@ -157,7 +157,7 @@ k_fft_y_fwd(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls, C2<T>* 
 // KS: kernel-table values per octant entry (2: (Gf, Gp) pairs, 1: Gf alone, whose
 // potential product is then array 0 itself and is not written).
 template <typename T, int L, int KS>
-__global__ void __launch_bounds__(kZConvMaxThreads)
+__global__ void __launch_bounds__(kTwoSetThreads<T>)
 k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
              const C2<T>* __restrict__ specb, C2<T>* __restrict__ zb,
              const C2<T>* __restrict__ tw) {
@@ -267,7 +267,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 // and from the transform's registers, a block covers nl adjacent columns of every
 // row it touches, and array 0 is read once for the a_x and a_y lines.
 template <typename T, int L, int NC>
-__global__ void __launch_bounds__(kZConvMaxThreads)
+__global__ void __launch_bounds__(kTwoSetThreads<T>)
 k_fft_y_inv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
             const C2<T>* __restrict__ zb, C2<T>* __restrict__ yb, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
@@ -450,7 +450,7 @@ template <typename T> int default_lines(int pass, int L) {
   int nl = (std::is_same<T, float>::value ? 4096 : 2048) / L;
   if (pass == PASS_X_INV) return nl < 4 ? 4 : nl;
   if (pass == PASS_Y_INV && mirror) return nl / 4 < 1 ? 1 : nl / 4;
-  if (pass == PASS_Z_CONV) while (nl > 1 && nl * (L / 8) > kZConvMaxThreads) nl /= 2;
+  if (pass == PASS_Z_CONV) while (nl > 1 && nl * (L / 8) > kTwoSetThreads<T>) nl /= 2;
   return nl;
 }
 
@@ -484,7 +484,7 @@ template <typename T> size_t pass_lds(int pass, int L, int nl, int nc) {
   // the z pass also parks each thread's eight forward-transform values (nl L values)
   const size_t bytes = ((size_t)lines * pass_ls<T>(pass, L, nl) + (pass == PASS_Z_CONV ? (size_t)nl * L : 0)) *
                        sizeof(C2<T>);
-  const int max_threads = two_sets ? kZConvMaxThreads : 1024;
+  const int max_threads = two_sets ? kTwoSetThreads<T> : 1024;
   if (lines * (L / 8) > max_threads || bytes > (size_t)kMaxLDS) return 0;
   if (pass == PASS_X_INV && (nl % 4) != 0) return 0;
   return bytes;

@@ -192,7 +192,7 @@ k_adj_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 // planes into the spectrum buffer.  Thread t is worker t / nl of column t mod nl,
 // as in the forward z pass: loads and stores go straight to the transform registers.
 template <typename T, int L>
-__global__ void __launch_bounds__(kZConvMaxThreads)
+__global__ void __launch_bounds__(kTwoSetThreads<T>)
 k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
         const C2<T>* __restrict__ zb, C2<T>* __restrict__ specb, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
@@ -472,7 +472,7 @@ k_adjp_y(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
 }
 
 template <typename T, int L>
-__global__ void __launch_bounds__(kZConvMaxThreads)
+__global__ void __launch_bounds__(kTwoSetThreads<T>)
 k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
          const C2<T>* __restrict__ zb, C2<T>* __restrict__ specb, const C2<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
