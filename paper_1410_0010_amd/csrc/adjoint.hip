@@ -93,11 +93,16 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
 #pragma unroll
   for (int k = 0; k < 8; ++k) pin4(rec[k]);
   // the KG smallest distinct owner grids of the chunk, one round each, until a round
-  // finds none (the usual chunk has one); then only those tiles are cleared
+  // finds none (the usual chunk has one; on a level of one grid it is that grid, with
+  // no round); then only those tiles are cleared
   // (a wavefront's minimum first, then one LDS atomic per wavefront: every thread
   // hitting the one word serialised 2048 atomics per round)
   int prev = -1, ng = 0;
-  for (int r = 0; r < KG; ++r) {
+  if (L.ngrids == 1) {                              // the level's one grid owns them all
+    if (threadIdx.x == 0) gsl[0] = L.first;
+    ng = 1;
+  }
+  for (int r = 0; r < KG && L.ngrids > 1; ++r) {
     if (threadIdx.x == 0) gnext = INT32_MAX;
     __syncthreads();
     int mn = INT32_MAX;
@@ -456,8 +461,9 @@ hipError_t launch_adj_restrict(const GridDesc* grids, int32_t first, int32_t cou
 
 // ---- deposit transpose, grid side ------------------------------------------------------
 // kGmfPer GMF cells of a grid per thread: the level's FP64 key-box cotangent +=
-// gmf_bar / dx^3 (a store on a level of one grid); own gas (active cells) += gmf_bar;
-// the parent's gas += gmf_bar on ghost cells.
+// gmf_bar / dx^3 (on a level of one grid a store, and the binning box's one-cell shell
+// set to zero here rather than cleared before); own gas (active cells) += gmf_bar; the
+// parent's gas += gmf_bar on ghost cells.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_adj_deposit_grid(AdjIO<T> io, const DepLevel* __restrict__ tab) {
@@ -479,19 +485,35 @@ k_adj_deposit_grid(AdjIO<T> io, const DepLevel* __restrict__ tab) {
     gbv[k] = local < cells ? (double)io.gmf_bar[lb][g.gmf_offset + local] : 0.0;
   }
   const double inv_vol = 1.0 / (L.dx * L.dx * L.dx);   // exact: dx is a power of two
+  const int64_t kx = L.key_n[0], kxy = (int64_t)L.key_n[0] * L.key_n[1];
 #pragma unroll
   for (int k = 0; k < kGmfPer; ++k) {
     const double gb = gbv[k];
-    if (gb == 0.0) continue;                        // also every cell past the grid's end
+    const int64_t local = first + (int64_t)k * kBlock;
+    if (local >= cells) continue;
     int lx, ly, lz;
-    box_cell(first + (int64_t)k * kBlock, g.gmf_n[0], g.gmf_n[1], lx, ly, lz);
+    box_cell(local, g.gmf_n[0], g.gmf_n[1], lx, ly, lz);
     const int cx = g.gmf_lo[0] + lx, cy = g.gmf_lo[1] + ly, cz = g.gmf_lo[2] + lz;
-    double* kc = L.accum + ((int64_t)(cz - L.key_lo[2]) * L.key_n[1] + (cy - L.key_lo[1])) * L.key_n[0] +
-                 (cx - L.key_lo[0]);
-    // one grid on the level: this thread is the cell's only writer and the grid was
-    // cleared, so a store gives the atomic add's value
-    if (L.ngrids == 1) *kc = gb * inv_vol;
-    else atomicAdd(kc, gb * inv_vol);
+    double* kc = L.accum + (cz - L.key_lo[2]) * kxy + (int64_t)(cy - L.key_lo[1]) * kx + (cx - L.key_lo[0]);
+    if (L.ngrids == 1) {
+      // One grid on the level: its GMF box is the binning box less a one-cell shell,
+      // which is not cleared for this pass.  This thread is the cell's only writer, so
+      // a store (zero included) gives the cleared grid's atomic sum, and the cells on
+      // the GMF box's faces also zero the shell cells beside them.
+      *kc = gb * inv_vol;
+      const int x0 = lx == 0 ? -1 : 0, x1 = lx == g.gmf_n[0] - 1 ? 1 : 0;
+      const int y0 = ly == 0 ? -1 : 0, y1 = ly == g.gmf_n[1] - 1 ? 1 : 0;
+      const int z0 = lz == 0 ? -1 : 0, z1 = lz == g.gmf_n[2] - 1 ? 1 : 0;
+      if (x0 | x1 | y0 | y1 | z0 | z1)
+        for (int dz = z0; dz <= z1; ++dz)
+          for (int dy = y0; dy <= y1; ++dy)
+            for (int dx = x0; dx <= x1; ++dx)
+              if (dx | dy | dz) kc[dz * kxy + (int64_t)dy * kx + dx] = 0.0;
+      if (gb == 0.0) continue;
+    } else {
+      if (gb == 0.0) continue;
+      atomicAdd(kc, gb * inv_vol);
+    }
     const bool active = cx >= g.lo[0] && cx < g.lo[0] + g.n[0] && cy >= g.lo[1] &&
                         cy < g.lo[1] + g.n[1] && cz >= g.lo[2] && cz < g.lo[2] + g.n[2];
     if (active) {

@@ -1383,7 +1383,8 @@ apm_status adjoint_t(apm_ctx c, apm_dtype dt, const T* x, const T* y, const T* z
     io.gas_bar[l] = (gas && gas[l]) ? (double*)c->adj_gas[l].p : nullptr;
     io.pgas_bar[l] = (l > 0 && gas && gas[l - 1]) ? (double*)c->adj_gas[l - 1].p : nullptr;
     add(io.fbar[l], P.levels[l].fld_cells * fs);
-    add(c->lvb[l].accum.p, P.levels[l].key_cells);
+    // the GMF cotangent grid: on a level of one grid, the grid pass writes every cell
+    if (P.levels[l].count > 1) add(c->lvb[l].accum.p, P.levels[l].key_cells);
     if (io.gas_bar[l]) add(io.gas_bar[l], P.levels[l].gas_elems);
   }
   io.item_blk0[nl] = iblk;

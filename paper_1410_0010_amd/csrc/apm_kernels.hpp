@@ -439,8 +439,9 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 
 constexpr int kBlock = 256;
 // GMF cells per thread in the deposit's finalize pass and in its transpose (the grid
-// side): four coalesced rows of a block, their loads issued together, so each thread
-// keeps several reads in flight; the per-grid block tables count kBlock kGmfPer cells
-constexpr int kGmfPer = 4;
+// side): kGmfPer coalesced rows of a block, their loads issued together, so each thread
+// keeps several reads in flight and a block's table lookups serve more cells; the
+// per-grid block tables count kBlock kGmfPer cells
+constexpr int kGmfPer = 8;
 
 }  // namespace apm
