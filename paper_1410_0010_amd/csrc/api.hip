@@ -387,9 +387,14 @@ const char* pass_name(int pass) {
 
 template <typename T>
 int lines_for(apm_ctx c, int pass, int L) {
-  // an adjoint pass has the shape of the forward pass it reverses: its tuned value
+  // an adjoint pass takes the tuned value of the forward pass it reverses where its own
+  // block holds that many lines (the y transpose keeps four lines per column at once,
+  // the forward y inverse pass one at a time), else its default
   auto it = c->lines.find(std::make_tuple((int)sizeof(T), mirror_pass(pass), L));
-  return it != c->lines.end() ? it->second : default_lines<T>(pass, L);
+  if (it == c->lines.end()) return default_lines<T>(pass, L);
+  if (pass != mirror_pass(pass) && pass_lds<T>(pass, L, it->second) == 0)   // as launch_adj_pass checks
+    return default_lines<T>(pass, L);
+  return it->second;
 }
 
 // Grids of `level` (or of every level when level < 0).

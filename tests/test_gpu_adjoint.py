@@ -114,12 +114,15 @@ CASES = {
 }
 
 
-def gpu_adjoint(w, dtype, abar=None, phibar=None, wbar=0.0):
+def gpu_adjoint(w, dtype, abar=None, phibar=None, wbar=0.0, autotune=False):
     plan = P.Plan(w.root_n, w.grids, boundary=w.boundary)
     ctx = P.Context(plan, 0)
     x, y, z, m = (dev(a, dtype) for a in (w.x, w.y, w.z, w.m))
     gas = [ctx.pack_gas(l, w.gas, x.dtype) for l in range(plan.nlevels)]
     has_gas = any(g is not None for g in gas)
+    if autotune:                       # the transposes then take the tuned launch shapes
+        ctx.solve(x, y, z, m, gas if has_gas else None)
+        ctx.autotune(x.dtype, reps=2)
     ax, ay, az, pot = ctx.solve(x, y, z, m, gas if has_gas else None)
     ab = None if abar is None else tuple(dev(abar[:, k], dtype) for k in range(3))
     pb = None if phibar is None else dev(phibar, dtype)
@@ -163,6 +166,23 @@ def test_energy_gradient_matches_oracle(case, dtype):
     ref = A.energy_gradient(O.OraclePlan(w.root_n, w.grids, boundary=w.boundary), x, y, z, m,
                             gas)
     check(case, dtype, gpu_adjoint(w, dtype, wbar=1.0), ref, w)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_general_loss_after_autotune(dtype):
+    """The four-component transposes after the autotuner has tuned the forward passes
+    (lengths 256 to 1024 along y): each transpose takes a forward pass's tuned launch
+    shape only where its own block holds it."""
+    w = CASES["slab_chain_L1024_y"]()
+    rng = np.random.default_rng(5)
+    ab = np.asarray(rng.standard_normal((w.npart, 3)), dtype).astype(np.float64)
+    pb = np.asarray(rng.standard_normal(w.npart), dtype).astype(np.float64)
+    say(f"[adjoint] general loss after autotune dtype={dtype.__name__}")
+    x, y, z, m, gas = rounded(w, dtype)
+    ref = A.adjoint(O.OraclePlan(w.root_n, w.grids, boundary=w.boundary), x, y, z, m, gas,
+                    abar=ab, phibar=pb, wbar=0.5)
+    check("slab_chain_L1024_y tuned", dtype, gpu_adjoint(w, dtype, ab, pb, 0.5, autotune=True),
+          ref, w)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
