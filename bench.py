@@ -66,9 +66,10 @@ def log(msg):
 # --------------------------------------------------------------------------------------
 
 def pass_b_floor(plan, esize):
-    """Bytes per step of the survey's three-pass floor for the z pass (pass B): read and
-    write the gz My (Mx/2+1) complex intermediate and read the (M/2+1)^3 kernel octant
-    (one real per entry), summed over the grids."""
+    """Bytes per step of the z pass (pass B) in a three-pass convolution (x-y planes,
+    z columns with the multiply, y-x planes): read and write the gz My (Mx/2+1)
+    complex intermediate once and read the (M/2+1)^3 kernel octant (one real per
+    entry), summed over the grids."""
     b = 0.0
     for g in plan.grids:
         gz = g["gmf_n"][2]
@@ -164,8 +165,8 @@ def kernel_bytes(plan, npart, npart_level, esize, root_gas=False, pot_only_adjoi
     return b
 
 
-def survey_floor_bytes(kernel, plan, npart_level, esize):
-    """Bytes per step of the survey's floor for a kernel family (the roofline's
+def floor_bytes(kernel, plan, npart_level, esize):
+    """Floor bytes per step of a kernel family (the roofline's
     `achieved`): pass B for the z pass, 4 esize per binned particle + esize per GMF
     cell for the deposit, else None (the kernel's own algorithmic bytes are used)."""
     if kernel == "fft_z_conv":
@@ -473,7 +474,7 @@ def main():
                          "kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+        print("bench.py: the library runs on one GPU only (no multi-GPU path); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
@@ -686,7 +687,7 @@ def main():
     dom_ms = per_kernel[dom]["ms_per_step"]
     dom_launches = per_kernel[dom]["launches_per_step"]
     dom_launch_ms = dom_ms / dom_launches
-    floor_b = survey_floor_bytes(dom, plan, npl, 4)
+    floor_b = floor_bytes(dom, plan, npl, 4)
     ach_b = floor_b if floor_b is not None else kb.get(dom, 0.0)
     achieved = ach_b / (dom_ms * 1e-3) / 1e9
     for k in per_kernel:
@@ -871,7 +872,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, args.workload),
                      "avg_launch_ms": dom_launch_ms,
-                     "bytes_basis": ("survey floor (pass B for the z pass)" if floor_b is not None
+                     "bytes_basis": ("three-pass floor (pass B: the z pass)" if floor_b is not None
                                      else "kernel's algorithmic bytes"),
                      "algorithmic_bytes_per_launch": ach_b / dom_launches,
                      "algorithmic_bytes_per_step": ach_b,

@@ -52,7 +52,7 @@ typedef enum {
   APM_ERR_OOM = 2,          /* device allocation failed or workspace limit    */
   APM_ERR_DEVICE = 3,       /* no usable device / HIP runtime error           */
   APM_ERR_RANGE = 4,        /* size beyond a supported maximum                */
-  APM_ERR_UNSUPPORTED = 5,  /* valid request this build does not support      */
+  APM_ERR_UNSUPPORTED = 5,  /* valid request the library does not support     */
   APM_ERR_STATE = 6         /* call out of order (e.g. missing parent field)  */
 } apm_status;
 
