@@ -98,7 +98,23 @@ def slab_chain(axis):
                       [None] * len(grids))
 
 
+def clustered():
+    """5000 particles at one point and 5000 inside one cell of the subgrid, 3000 at
+    one point of the root, 500 spread out: the transposed deposit and interpolation
+    gather many equal cells into one chunk."""
+    grids = W.centred_nested_grids(16, 8, 1)
+    rng = np.random.default_rng(83)
+    p = np.concatenate([np.tile([0.5 + 0.3 / 32, 0.5 - 0.1 / 32, 0.5 + 0.7 / 32], (5000, 1)),
+                        0.5 + rng.uniform(0, 1.0 / 32, (5000, 3)),
+                        np.tile([0.2, 0.3, 0.7], (3000, 1)),
+                        rng.uniform(0.1, 0.9, (500, 3))])
+    m = rng.uniform(0.5, 1.5, p.shape[0]) / p.shape[0]
+    return W.Workload("clustered", 16, grids, p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy(),
+                      m, [None] * 2)
+
+
 CASES = {
+    "clustered_one_cell": clustered,
     "slab_chain_L1024_x": lambda: slab_chain(0),
     "slab_chain_L1024_y": lambda: slab_chain(1),
     "slab_chain_L1024_z": lambda: slab_chain(2),
@@ -187,7 +203,8 @@ def test_general_loss_after_autotune(dtype):
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
 @pytest.mark.parametrize("case", ["gas_nested32", "clumps32_24grids_gas", "periodic_edges16_gas",
-                                  "periodic_sine32", "slab_chain_L1024_y", "slab_chain_L1024_z"])
+                                  "periodic_sine32", "slab_chain_L1024_y", "slab_chain_L1024_z",
+                                  "clustered_one_cell"])
 def test_general_loss_gradient_matches_oracle(case, dtype):
     w = CASES[case]()
     rng = np.random.default_rng(3)

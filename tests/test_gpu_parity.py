@@ -154,6 +154,21 @@ def edge_workload():
     return W.Workload("edge", 16, grids, x, y, z, m, [None] * 2)
 
 
+def clustered_workload(seed=80, boundary="isolated"):
+    """Extreme clustering: 5000 particles at one point and 5000 inside one cell of the
+    subgrid, 3000 at one point of the root outside it, 500 spread out.  The hot tiles
+    hold several deposit chunks whose entries all share a cell."""
+    grids = W.centred_nested_grids(16, 8, 1)
+    rng = np.random.default_rng(seed)
+    p = np.concatenate([np.tile([0.5 + 0.3 / 32, 0.5 - 0.1 / 32, 0.5 + 0.7 / 32], (5000, 1)),
+                        0.5 + rng.uniform(0, 1.0 / 32, (5000, 3)),
+                        np.tile([0.2, 0.3, 0.7], (3000, 1)),
+                        rng.uniform(0.1, 0.9, (500, 3))])
+    m = rng.uniform(0.5, 1.5, p.shape[0]) / p.shape[0]
+    return W.Workload("clustered", 16, grids, p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy(),
+                      m, [None] * 2, boundary=boundary)
+
+
 def periodic_edge_workload(seed=78):
     """Periodic root 16^3 with one subgrid: particles within a cell of every face and
     corner (clouds and stencils that wrap), exactly at 0, just below 1, outside the
@@ -203,6 +218,8 @@ CASES = {
     "slab_chain_L1024_z": lambda: slab_workload(axis=2),
     "tiny_grids_L16": tiny_grid_workload,
     "edge_particles": edge_workload,
+    "clustered_one_cell": clustered_workload,
+    "clustered_one_cell_periodic": lambda: clustered_workload(boundary="periodic"),
     "uniform_sphere_gas_only": W.workload_uniform_sphere,
 }
 
@@ -220,7 +237,7 @@ def test_parity_small(case, dtype):
 # The compensated FP32 deposit (FP32 weights and (sum, error) pairs in registers, LDS
 # and the key-box grid) meets the same FP32 bar as the FP64-accumulated one.
 COMP_CASES = ("nested32_2x16_plummer", "gas_nested32", "periodic_edges16", "edge_particles",
-              "clumps32_24grids", "slab_chain_L1024_z", "tiny_grids_L16")
+              "clumps32_24grids", "slab_chain_L1024_z", "tiny_grids_L16", "clustered_one_cell")
 
 
 @pytest.mark.parametrize("case", COMP_CASES)
