@@ -1,0 +1,209 @@
+"""Parity at the full sizes of the two largest workloads, in the launch configuration
+the benchmark times (the one-call solve after autotuning):
+
+* root 256^3 + two centred 128^3 levels, 2^22 Plummer particles and a lognormal
+  random gas field on every grid;
+* root 512^3 (a 1024^3 doubled transform) + three centred 256^3 levels, 2^24 Plummer
+  particles and two point masses.
+
+The oracle's whole solve does not fit a test at these sizes, so the checks are the
+ones it can afford one value at a time, plus properties that hold at any size:
+
+* each grid's GMF at sampled cells (uniform cells and cells of sampled particles):
+  the oracle deposits exactly the particles whose clouds reach those cells (Sec. 2
+  density assignment) and adds the gas, which fixes the GMF there, FP64 to 1e-13 and
+  FP32 to 1e-6 (relative L2);
+* each level's mass: particles whose whole cloud lies inside a GMF box add their
+  mass, the others are deposited by the oracle, plus the gas; FP64 to 1e-12, FP32
+  (FP64 accumulation) to 1e-6;
+* the owner grid of every particle, exactly;
+* the FP32 composed fields and particle accelerations and potentials against the
+  FP64 solve of the same FP32-rounded inputs (pinned to the oracle element by element
+  at every smaller size), at the FP32 bar of 1e-5.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import apm_workloads as W
+from oracle import apm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+P = pytest.importorskip("paper_1410_0010_amd")
+
+DEV = torch.device("cuda", 0)
+NSAMPLE = 2048
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def trel(a, b):
+    """Relative L2 of two device tensors, in FP64 on the device."""
+    a = a.to(torch.float64)
+    b = b.to(torch.float64)
+    nb = float(torch.linalg.norm(b))
+    return float(torch.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
+
+
+WORKLOADS = {
+    "plummer_gas_256_2x128": W.workload_plummer_gas,
+    "large_nested_512_3x256": lambda: W.workload_large_nested(with_velocities=False),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(WORKLOADS))
+def full(request):
+    w = WORKLOADS[request.param]()
+    say(f"[full] workload {request.param}: {w.npart} particles, {len(w.grids)} grids")
+    rd = lambda a: None if a is None else np.asarray(a, np.float32).astype(np.float64)
+    inputs = dict(x=rd(w.x), y=rd(w.y), z=rd(w.z), m=rd(w.m), gas=[rd(a) for a in w.gas])
+    return request.param, w, inputs
+
+
+def gpu_run(w, inp, dtype, samples):
+    """Staged owner and deposit (GMF at the sampled cells), then the one-call solve
+    after autotuning: fields, particle outputs and FP64 totals stay on the device."""
+    plan = P.Plan(w.root_n, w.grids, boundary=w.boundary)
+    ctx = P.Context(plan, 0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype))).to(DEV)
+    x, y, z, m = (dev(inp[k]) for k in "xyzm")
+    gas = [ctx.pack_gas(l, inp["gas"], x.dtype) for l in range(plan.nlevels)]
+    has_gas = any(g is not None for g in gas)
+    owner = ctx.owner(x, y, z).cpu().numpy()
+    gmf = {}
+    for l in range(plan.nlevels):
+        buf = ctx.deposit(l, x, y, z, m, gas[l], gas[l - 1] if l > 0 else None)
+        for g in plan.level_grids(l):
+            flat = ctx.gmf_view(buf, g["index"]).reshape(-1)
+            idx = torch.from_numpy(samples[g["index"]]).to(DEV)
+            gmf[g["index"]] = flat[idx].cpu().numpy().astype(np.float64)
+        del buf
+    ctx.solve(x, y, z, m, gas if has_gas else None)
+    torch.cuda.synchronize()
+    ctx.autotune(x.dtype, reps=2)
+    ax, ay, az, pot = ctx.solve(x, y, z, m, gas if has_gas else None)
+    tot = ctx.solve_totals(m, ax, ay, az, pot, gas if has_gas else None)
+    fields = [ctx.solved_field(l, x.dtype) for l in range(plan.nlevels)]
+    torch.cuda.synchronize()
+    out = dict(plan=plan, owner=owner, gmf=gmf, fields=fields, acc=torch.stack([ax, ay, az], 1),
+               pot=pot, totals=tot)
+    del ctx
+    return out
+
+
+def sample_cells(g, cells, rng):
+    """Flat GMF indices: uniform cells and the cells of sampled particles inside the box."""
+    n = int(np.prod(g.gmf_n))
+    uni = rng.choice(n, min(NSAMPLE, n), replace=False)
+    c = [cells[a] - int(g.gmf_lo[a]) for a in range(3)]
+    inside = np.flatnonzero((c[0] >= 0) & (c[0] < g.gmf_n[0]) & (c[1] >= 0) & (c[1] < g.gmf_n[1])
+                            & (c[2] >= 0) & (c[2] < g.gmf_n[2]))
+    pick = rng.choice(inside, min(NSAMPLE, inside.size), replace=False) if inside.size else inside
+    occ = (c[2][pick] * g.gmf_n[1] + c[1][pick]) * g.gmf_n[0] + c[0][pick]
+    return np.unique(np.concatenate([uni, occ]).astype(np.int64))
+
+
+def reaching(g, cells, flat_samples):
+    """Particles whose TSC cloud (their cell and its 26 neighbours) touches a sample."""
+    nx, ny, nz = (int(v) for v in g.gmf_n)
+    mask = np.zeros((nz + 2, ny + 2, nx + 2), dtype=bool)     # one cell of margin
+    sz, r = np.divmod(flat_samples, ny * nx)
+    sy, sx = np.divmod(r, nx)
+    for dz in (0, 1, 2):
+        for dy in (0, 1, 2):
+            for dx in (0, 1, 2):
+                mask[sz + dz, sy + dy, sx + dx] = True
+    c = [cells[a] - int(g.gmf_lo[a]) + 1 for a in range(3)]
+    ok = (c[0] >= 0) & (c[0] < nx + 2) & (c[1] >= 0) & (c[1] < ny + 2) & (c[2] >= 0) & (c[2] < nz + 2)
+    sel = np.zeros(ok.shape, dtype=bool)
+    sel[ok] = mask[c[2][ok], c[1][ok], c[0][ok]]
+    return sel
+
+
+@pytest.mark.timeout(900)
+def test_full_size_parity(full):
+    name, w, inp = full
+    x, y, z, m = inp["x"], inp["y"], inp["z"], inp["m"]
+    oplan = O.OraclePlan(w.root_n, w.grids, boundary=w.boundary)
+    valid = O.valid_particles(x, y, z)
+    rng = np.random.default_rng(1410)
+    cells, samples = {}, {}
+    for g in oplan.grids:
+        cells[g.index] = [O.cell_coords(v, g.dx)[0] for v in (x, y, z)]
+        samples[g.index] = sample_cells(g, cells[g.index], rng)
+
+    say(f"[full] {name}: GPU FP64 (staged deposit, autotuned one-call solve)")
+    r64 = gpu_run(w, inp, np.float64, samples)
+    say(f"[full] {name}: GPU FP32")
+    r32 = gpu_run(w, inp, np.float32, samples)
+
+    say(f"[full] {name}: oracle owners")
+    own_ref = O.owner_of(oplan, x, y, z)
+    assert np.array_equal(r64["owner"], own_ref), "FP64 owner grids differ"
+    assert np.array_equal(r32["owner"], own_ref), "FP32 owner grids differ"
+
+    level_mass = np.zeros(oplan.nlevels)
+    for g in oplan.grids:
+        say(f"[full] {name}: oracle GMF of grid {g.index} at {samples[g.index].size} cells")
+        c = cells[g.index]
+        near = reaching(g, c, samples[g.index]) & valid
+        rho = O.add_gas(oplan, g, O.deposit_particles(oplan, g, x[near], y[near], z[near], m[near]),
+                        inp["gas"])
+        ref = rho.reshape(-1)[samples[g.index]]
+        del rho
+        e64, e32 = rel(r64["gmf"][g.index], ref), rel(r32["gmf"][g.index], ref)
+        say(f"[full]   GMF rel L2: FP64 {e64:.2e}  FP32 {e32:.2e}")
+        assert e64 <= 1e-13, f"{name}: grid {g.index} FP64 GMF {e64:.3e}"
+        assert e32 <= 1e-6, f"{name}: grid {g.index} FP32 GMF {e32:.3e}"
+        # mass: whole clouds inside the box count m, the others are deposited
+        lo = [int(v) for v in g.gmf_lo]
+        n = [int(v) for v in g.gmf_n]
+        inner = valid.copy()
+        touch = valid.copy()
+        for a in range(3):
+            ca = c[a] - lo[a]
+            inner &= (ca >= 1) & (ca <= n[a] - 2)
+            touch &= (ca >= -1) & (ca <= n[a])
+        edge = touch & ~inner
+        mass = float(np.sum(m[inner]))
+        if edge.any():
+            mass += float(O.deposit_particles(oplan, g, x[edge], y[edge], z[edge], m[edge]).sum()) \
+                * g.dx ** 3
+        gas0 = O.add_gas(oplan, g, np.zeros(tuple(n[::-1])), inp["gas"])
+        mass += float(gas0.sum()) * g.dx ** 3
+        level_mass[g.level] += mass
+    for lev in range(oplan.nlevels):
+        e64 = abs(r64["totals"][lev] - level_mass[lev]) / abs(level_mass[lev])
+        e32 = abs(r32["totals"][lev] - level_mass[lev]) / abs(level_mass[lev])
+        say(f"[full]   level {lev} mass rel: FP64 {e64:.2e}  FP32 {e32:.2e}")
+        assert e64 <= 1e-12, f"{name}: level {lev} FP64 mass {e64:.3e}"
+        assert e32 <= 1e-6, f"{name}: level {lev} FP32 mass {e32:.3e}"
+
+    # FP32 against the FP64 solve of the same inputs
+    for lev in range(oplan.nlevels):
+        f32, f64 = r32["fields"][lev], r64["fields"][lev]
+        ea, ep = trel(f32[:, :3], f64[:, :3]), trel(f32[:, 3], f64[:, 3])
+        say(f"[full]   level {lev} composed field FP32 vs FP64: acc {ea:.2e} pot {ep:.2e}")
+        assert ea <= 1e-5 and ep <= 1e-5, f"{name}: level {lev} field acc {ea:.3e} pot {ep:.3e}"
+    owned = torch.from_numpy(own_ref >= 0).to(DEV)
+    ea = trel(r32["acc"][owned], r64["acc"][owned])
+    ep = trel(r32["pot"][owned], r64["pot"][owned])
+    say(f"[full]   particles FP32 vs FP64: acc {ea:.2e} pot {ep:.2e}")
+    assert ea <= 1e-5 and ep <= 1e-5, f"{name}: particle acc {ea:.3e} pot {ep:.3e}"
+    assert torch.all(r32["acc"][~owned] == 0) and torch.all(r64["acc"][~owned] == 0)
