@@ -17,9 +17,10 @@ ones it can afford one value at a time, plus properties that hold at any size:
   mass, the others are deposited by the oracle, plus the gas; FP64 to 1e-12, FP32
   (FP64 accumulation) to 1e-6;
 * the owner grid of every particle, exactly;
-* the FP32 composed fields and particle accelerations and potentials against the
-  FP64 solve of the same FP32-rounded inputs (pinned to the oracle element by element
-  at every smaller size), at the FP32 bar of 1e-5.
+* the FP32 composed fields, particle accelerations and potentials, and the reverse
+  sweep's gradients of W (positions, masses, gas) against the FP64 solve of the same
+  FP32-rounded inputs (pinned to the oracle element by element at every smaller
+  size), at the FP32 bar of 1e-5.
 """
 
 import sys
@@ -100,9 +101,13 @@ def gpu_run(w, inp, dtype, samples):
     ax, ay, az, pot = ctx.solve(x, y, z, m, gas if has_gas else None)
     tot = ctx.solve_totals(m, ax, ay, az, pot, gas if has_gas else None)
     fields = [ctx.solved_field(l, x.dtype) for l in range(plan.nlevels)]
+    # the reverse sweep of W (as the benchmark's forward + adjoint step)
+    xb, yb, zb, mb, gb = ctx.solve_adjoint(x, y, z, m, gas if has_gas else None, pot, None,
+                                           None, 1.0)
     torch.cuda.synchronize()
     out = dict(plan=plan, owner=owner, gmf=gmf, fields=fields, acc=torch.stack([ax, ay, az], 1),
-               pot=pot, totals=tot)
+               pot=pot, totals=tot, dx=torch.stack([xb, yb, zb], 1), dm=mb,
+               dgas=None if gb is None else [g for g in gb if g is not None])
     del ctx
     return out
 
@@ -207,3 +212,11 @@ def test_full_size_parity(full):
     say(f"[full]   particles FP32 vs FP64: acc {ea:.2e} pot {ep:.2e}")
     assert ea <= 1e-5 and ep <= 1e-5, f"{name}: particle acc {ea:.3e} pot {ep:.3e}"
     assert torch.all(r32["acc"][~owned] == 0) and torch.all(r64["acc"][~owned] == 0)
+    ex, em = trel(r32["dx"], r64["dx"]), trel(r32["dm"], r64["dm"])
+    say(f"[full]   dW/dx FP32 vs FP64 {ex:.2e}, dW/dm {em:.2e}")
+    assert ex <= 1e-5 and em <= 1e-5, f"{name}: gradient x {ex:.3e} m {em:.3e}"
+    if r64["dgas"] is not None:
+        for lev, (a, b) in enumerate(zip(r32["dgas"], r64["dgas"])):
+            eg = trel(a, b)
+            say(f"[full]   dW/dgas level {lev} FP32 vs FP64 {eg:.2e}")
+            assert eg <= 1e-5, f"{name}: gas gradient level {lev} {eg:.3e}"
