@@ -358,17 +358,21 @@ apm_status kernel_table(apm_ctx c, apm_dtype dt, const GridDesc& g, const void**
     }
     c->kern[k64] = t64;
   }
-  if (dt == APM_F64 && !single) { *out = t64; return APM_OK; }
+  // the working table: the transforms' tiled layout, in the working precision
   const size_t es = dt == APM_F32 ? 4 : 8;
   void* pw = nullptr;
-  APM_TRY(dev_alloc(c, &pw, es * (single ? 1 : 2) * oct, "green's function table (working)"));
+  APM_TRY(dev_alloc(c, &pw, es * (single ? 1 : 2) * (size_t)oct_entries(Mx, My, Mz),
+                    "green's function table (working)"));
   c->owned.push_back(pw);
-  if (!single)
-    HIP_TRY(launch_to_f32((const double*)t64, (float*)pw, 2 * oct, c->stream), "table to fp32");
-  else if (dt == APM_F32)
-    HIP_TRY(launch_table_pick<float>((const double*)t64, (float*)pw, oct, 0, c->stream), "table");
+  const double* src = (const double*)t64;
+  hipError_t te;
+  if (dt == APM_F32)
+    te = single ? launch_table_tiles<float, 1>(src, (float*)pw, Mx, My, Mz, 0, c->stream)
+                : launch_table_tiles<float, 2>(src, (float*)pw, Mx, My, Mz, 0, c->stream);
   else
-    HIP_TRY(launch_table_pick<double>((const double*)t64, (double*)pw, oct, 0, c->stream), "table");
+    te = single ? launch_table_tiles<double, 1>(src, (double*)pw, Mx, My, Mz, 0, c->stream)
+                : launch_table_tiles<double, 2>(src, (double*)pw, Mx, My, Mz, 0, c->stream);
+  HIP_TRY(te, "green's function table layout");
   c->kern[kw] = pw;
   *out = pw;
   return APM_OK;

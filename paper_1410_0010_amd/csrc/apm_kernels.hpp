@@ -95,9 +95,25 @@ template <typename T>
 hipError_t launch_pass(int pass, int L, int nl, int nc, const ConvJob* jobs, int njobs,
                        int64_t nblocks, const LevelPtrs<T>& lp, C2<T>* spec, C2<T>* zbuf,
                        C2<T>* ybuf, const void* tw, hipStream_t s);
-// one value of every octant pair (comp 0: Gf) in the working precision
-template <typename T> hipError_t launch_table_pick(const double* pairs, T* out, int64_t n, int comp,
-                                                   hipStream_t s);
+// Working octant tables (the kernel values the z passes multiply by) are tiled for
+// those passes' reads: entry (kx, |ky|, |kz|) of an Mx x My x Mz box sits at
+// ((|ky| NT + kx / kOctKx) Oz + |kz|) kOctKx + kx mod kOctKx, NT = ceil((Mx/2 + 1) /
+// kOctKx), Oz = Mz/2 + 1.  A block's kOctKx neighbouring columns and a wavefront's
+// consecutive kz then read one contiguous run instead of one short piece per kz.
+constexpr int kOctKx = 4;
+__host__ __device__ __forceinline__ int oct_tiles(int Mx) { return (Mx / 2 + kOctKx) / kOctKx; }
+__host__ __device__ __forceinline__ int64_t oct_entries(int Mx, int My, int Mz) {
+  return (int64_t)oct_tiles(Mx) * kOctKx * (My / 2 + 1) * (Mz / 2 + 1);
+}
+// offset of column kx's run of |ky| row kyo (entry |kz| follows at kz kOctKx)
+__host__ __device__ __forceinline__ int64_t oct_col(int kx, int kyo, int Mx, int Mz) {
+  return ((int64_t)kyo * oct_tiles(Mx) + kx / kOctKx) * (Mz / 2 + 1) * kOctKx + kx % kOctKx;
+}
+// The working table from the FP64 (Gf, Gp) pairs in natural order (index (|kz| (My/2+1)
+// + |ky|) (Mx/2+1) + kx): KS = 1 takes value comp of each pair, KS = 2 both.
+template <typename T, int KS>
+hipError_t launch_table_tiles(const double* pairs, T* out, int Mx, int My, int Mz, int comp,
+                              hipStream_t s);
 
 // Buffers of the transposed convolution: GMF cotangents out (working precision) and
 // FP64 field-box cotangents in (field layout: 4 per cell, or the Phi one alone for the
@@ -123,7 +139,6 @@ struct InfluenceParams {
 hipError_t launch_influence(const InfluenceParams& p, double2* out, hipStream_t s);
 hipError_t launch_james(int N, double dx, double a0, double G, const double* costab,
                         double* buf0, double* buf1, double** result, hipStream_t s);
-hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 
 // Owner lookup (finest grid whose active box holds a point, lowest index on that level):
 // per level either its single grid's active box or, for several grids, a table over

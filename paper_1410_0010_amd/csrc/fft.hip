@@ -190,13 +190,12 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       X[q] = (z < gz && col_ok) ? src[q * qstride] : mk<T>(0, 0);
     }
   }
-  // multipliers of this column: kx fastest in the table, so lanes read neighbours
+  // multipliers of this column: its run of the tiled table, kz after kz, beside the
+  // runs of the block's neighbouring columns
   const int kxc = col_ok ? c0 + cb : 0;
   const int kyo = ky <= My / 2 ? ky : My - ky;
-  // 32-bit offsets from block-uniform bases (an octant table has < 2^31 entries)
   using TV = typename std::conditional<KS == 2, nvec2<T>, T>::type;
-  const uint32_t ostride = (uint32_t)((My / 2 + 1) * W);
-  const gptr<TV> gcol = as_global<TV>(J.kern) + (int64_t)kyo * W;
+  const gptr<TV> gcol = as_global<TV>(J.kern) + oct_col(kxc, kyo, J.M[0], L);
   // with one kernel the multiplier is read once, while the forward transform runs,
   // and the slots below hold Gf X: both products are formed from them
   T gf[KS == 1 ? 8 : 1];
@@ -205,7 +204,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
     for (int q = 0; q < 8; ++q) {
       const int kz = w + q * (L / 8);
       const int kzo = kz <= L / 2 ? kz : L - kz;
-      gf[q] = gcol[(uint32_t)kzo * ostride + (uint32_t)kxc];
+      gf[q] = gcol[(uint32_t)kzo * kOctKx];
     }
   }
   fft_regs<T, L, false, false>(line, w, X, tb);
@@ -232,7 +231,7 @@ k_fft_z_conv(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
       T mul;
       if constexpr (KS == 2) {
         const int kzo = kz <= L / 2 ? kz : L - kz;
-        const TV gv = gcol[(uint32_t)kzo * ostride + (uint32_t)kxc];
+        const TV gv = gcol[(uint32_t)kzo * kOctKx];
         mul = s == 0 ? gv.x : (s == 1 ? dzs[kz] * gv.x : gv.y);
       } else {
         mul = s == 0 ? (T)1 : dzs[kz];
@@ -586,21 +585,39 @@ template hipError_t launch_pass<double>(int, int, int, int, const ConvJob*, int,
                                         C2<double>*, const void*, hipStream_t);
 
 // ---------------------------------------------------------- kernel-table copies --
-template <typename T>
-__global__ void k_table_pick(const double* __restrict__ pairs, T* __restrict__ out, int64_t n,
-                             int comp) {
+// One thread per natural-order entry; padding columns (kx >= Mx/2 + 1) are never read.
+template <typename T, int KS>
+__global__ void k_table_tiles(const double* __restrict__ pairs, T* __restrict__ out, int Mx,
+                              int My, int Mz, int comp, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (T)pairs[2 * i + comp];
+  if (i >= n) return;
+  const int W = Mx / 2 + 1, Oy = My / 2 + 1;
+  const int kx = (int)(i % W);
+  const int64_t r = i / W;
+  const int ky = (int)(r % Oy), kz = (int)(r / Oy);
+  const int64_t o = oct_col(kx, ky, Mx, Mz) + (int64_t)kz * kOctKx;
+  if constexpr (KS == 1) {
+    out[o] = (T)pairs[2 * i + comp];
+  } else {
+    out[2 * o] = (T)pairs[2 * i];
+    out[2 * o + 1] = (T)pairs[2 * i + 1];
+  }
 }
 
-template <typename T>
-hipError_t launch_table_pick(const double* pairs, T* out, int64_t n, int comp, hipStream_t s) {
+template <typename T, int KS>
+hipError_t launch_table_tiles(const double* pairs, T* out, int Mx, int My, int Mz, int comp,
+                              hipStream_t s) {
+  const int64_t n = (int64_t)(Mx / 2 + 1) * (My / 2 + 1) * (Mz / 2 + 1);
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_table_pick<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
-                     0, s, pairs, out, n, comp);
+  hipLaunchKernelGGL((k_table_tiles<T, KS>), dim3((unsigned)((n + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, pairs, out, Mx, My, Mz, comp, n);
   return hipGetLastError();
 }
-template hipError_t launch_table_pick<float>(const double*, float*, int64_t, int, hipStream_t);
-template hipError_t launch_table_pick<double>(const double*, double*, int64_t, int, hipStream_t);
+template hipError_t launch_table_tiles<float, 1>(const double*, float*, int, int, int, int, hipStream_t);
+template hipError_t launch_table_tiles<float, 2>(const double*, float*, int, int, int, int, hipStream_t);
+template hipError_t launch_table_tiles<double, 1>(const double*, double*, int, int, int, int,
+                                                  hipStream_t);
+template hipError_t launch_table_tiles<double, 2>(const double*, double*, int, int, int, int,
+                                                  hipStream_t);
 
 }  // namespace apm

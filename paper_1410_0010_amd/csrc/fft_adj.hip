@@ -219,14 +219,14 @@ k_adj_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   const int kyo = ky <= My / 2 ? ky : My - ky;
   // 24-bit multiplies: jz < 2^11, kYT P < 2^24, every product < 2^31
   const uint32_t ps32 = (uint32_t)pstride;
-  // multipliers of this column: kx fastest in the table, so lanes read neighbours;
+  // multipliers of this column: its run of the tiled table (entries kOctKx apart);
   // each product's set is read where it is used (holding all three for the whole
   // kernel spills FP64 registers)
   // 32-bit offsets from a per-thread base (an octant table has < 2^31 values)
   const int64_t ks = J.kstride;                        // table values per entry
   const uint32_t kp = (uint32_t)J.kpot;                // Gp's offset in an entry
-  const uint32_t ostride = (uint32_t)((My / 2 + 1) * W * ks);
-  const gptr<T> gcol = as_global<T>(J.kern) + ((int64_t)kyo * W + kxc) * ks;
+  const uint32_t ostride = (uint32_t)(kOctKx * ks);
+  const gptr<T> gcol = as_global<T>(J.kern) + oct_col(kxc, kyo, J.M[0], L) * ks;
   // S accumulates in LDS, each thread's values in its own slots (no barrier: the same
   // thread reads them back), so the forward transforms do not hold it in registers
   C2<T>* ss = lds + (int64_t)nl * ls + t;
@@ -498,8 +498,8 @@ k_adjp_z(const ConvJob* __restrict__ jobs, int njobs, int nl, int ls,
   // 24-bit multiplies: jz < 2^11, kYT P < 2^24, every product < 2^31
   const uint32_t ps32 = (uint32_t)pstride;
   const int64_t ks = J.kstride;                        // table values per entry
-  const int64_t ostride = (int64_t)(My / 2 + 1) * W * ks;
-  const gptr<T> gcol = as_global<T>(J.kern) + ((int64_t)kyo * W + kxc) * ks + J.kpot;
+  const int64_t ostride = kOctKx * ks;                 // next |kz| of the column's run
+  const gptr<T> gcol = as_global<T>(J.kern) + oct_col(kxc, kyo, J.M[0], L) * ks + J.kpot;
   C2<T> v[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {

@@ -223,15 +223,4 @@ hipError_t launch_james(int N, double dx, double a0, double G, const double* cos
   return hipGetLastError();
 }
 
-__global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (float)in[i];
-}
-
-hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s) {
-  const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(kBlock), 0, s, in, out, n);
-  return hipGetLastError();
-}
-
 }  // namespace apm
