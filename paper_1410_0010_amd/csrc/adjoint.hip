@@ -468,24 +468,36 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_adj_deposit_grid(AdjIO<T> io, const DepLevel* __restrict__ tab) {
   const int lb = batch_of(io.fin_blk0, io.nlev, blockIdx.x);
-  const DepLevel& L = tab[lb];
+  const DepLevel L = load_global(tab + lb);
   const int64_t blk = blockIdx.x - io.fin_blk0[lb];
+  const gptr<int64_t> bbeg = as_global<int64_t>(L.block_begin);
   int lo = 0, hi = L.ngrids - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (L.block_begin[mid] <= blk) lo = mid; else hi = mid - 1;
+    if (bbeg[mid] <= blk) lo = mid; else hi = mid - 1;
   }
-  const GridDesc& g = L.grids[lo];
+  // the grid's descriptor as values read once, and global-space pointers: through
+  // plain pointers every store below could alias the descriptors, which then had to be
+  // read again after it (generic loads and stores, each waiting on the last)
+  const GridDesc g = load_global(L.grids + lo);
   const int64_t cells = (int64_t)g.gmf_n[0] * g.gmf_n[1] * g.gmf_n[2];
-  const int64_t first = (blk - L.block_begin[lo]) * (int64_t)(kBlock * kGmfPer) + threadIdx.x;
+  const int64_t first = (blk - bbeg[lo]) * (int64_t)(kBlock * kGmfPer) + threadIdx.x;
+  const gptr<T> gin = as_global<T>(io.gmf_bar[lb]) + g.gmf_offset;
   double gbv[kGmfPer];
 #pragma unroll
   for (int k = 0; k < kGmfPer; ++k) {               // the loads first
     const int64_t local = first + (int64_t)k * kBlock;
-    gbv[k] = local < cells ? (double)io.gmf_bar[lb][g.gmf_offset + local] : 0.0;
+    gbv[k] = local < cells ? (double)gin[local] : 0.0;
   }
   const double inv_vol = 1.0 / (L.dx * L.dx * L.dx);   // exact: dx is a power of two
   const int64_t kx = L.key_n[0], kxy = (int64_t)L.key_n[0] * L.key_n[1];
+  const bool single = L.ngrids == 1;
+  const gmut<double> acc = as_global_mut<double>(L.accum);
+  const gmut<double> gbar = io.gas_bar[lb] ? as_global_mut<double>(io.gas_bar[lb]) + g.gas_offset
+                                           : nullptr;
+  const gmut<double> pbar = io.pgas_bar[lb] && g.parent >= 0
+                                ? as_global_mut<double>(io.pgas_bar[lb]) + g.parent_gas_offset
+                                : nullptr;
 #pragma unroll
   for (int k = 0; k < kGmfPer; ++k) {
     const double gb = gbv[k];
@@ -494,8 +506,9 @@ k_adj_deposit_grid(AdjIO<T> io, const DepLevel* __restrict__ tab) {
     int lx, ly, lz;
     box_cell(local, g.gmf_n[0], g.gmf_n[1], lx, ly, lz);
     const int cx = g.gmf_lo[0] + lx, cy = g.gmf_lo[1] + ly, cz = g.gmf_lo[2] + lz;
-    double* kc = L.accum + (cz - L.key_lo[2]) * kxy + (int64_t)(cy - L.key_lo[1]) * kx + (cx - L.key_lo[0]);
-    if (L.ngrids == 1) {
+    const gmut<double> kc = acc + (cz - L.key_lo[2]) * kxy + (int64_t)(cy - L.key_lo[1]) * kx +
+                            (cx - L.key_lo[0]);
+    if (single) {
       // One grid on the level: its GMF box is the binning box less a one-cell shell,
       // which is not cleared for this pass.  This thread is the cell's only writer, so
       // a store (zero included) gives the cleared grid's atomic sum, and the cells on
@@ -512,25 +525,20 @@ k_adj_deposit_grid(AdjIO<T> io, const DepLevel* __restrict__ tab) {
       if (gb == 0.0) continue;
     } else {
       if (gb == 0.0) continue;
-      atomicAdd(kc, gb * inv_vol);
+      global_add(kc, gb * inv_vol);
     }
     const bool active = cx >= g.lo[0] && cx < g.lo[0] + g.n[0] && cy >= g.lo[1] &&
                         cy < g.lo[1] + g.n[1] && cz >= g.lo[2] && cz < g.lo[2] + g.n[2];
     if (active) {
       // atomic: a finer level of the same launch adds its ghost cells to this array
-      double* gbar = io.gas_bar[lb];
       if (gbar)
-        atomicAdd(gbar + g.gas_offset + ((int64_t)(cz - g.lo[2]) * g.n[1] + (cy - g.lo[1])) * g.n[0] +
-                      (cx - g.lo[0]),
-                  gb);
-    } else if (g.parent >= 0) {
-      double* pbar = io.pgas_bar[lb];
-      if (pbar) {
-        const int px = (cx >> 1) - g.parent_lo[0], py = (cy >> 1) - g.parent_lo[1],
-                  pz = (cz >> 1) - g.parent_lo[2];
-        atomicAdd(pbar + g.parent_gas_offset + ((int64_t)pz * g.parent_n[1] + py) * g.parent_n[0] + px,
-                  gb);
-      }
+        global_add(gbar + ((int64_t)(cz - g.lo[2]) * g.n[1] + (cy - g.lo[1])) * g.n[0] +
+                       (cx - g.lo[0]),
+                   gb);
+    } else if (pbar) {
+      const int px = (cx >> 1) - g.parent_lo[0], py = (cy >> 1) - g.parent_lo[1],
+                pz = (cz >> 1) - g.parent_lo[2];
+      global_add(pbar + ((int64_t)pz * g.parent_n[1] + py) * g.parent_n[0] + px, gb);
     }
   }
 }

@@ -27,6 +27,18 @@ template <typename T> using gmut = __attribute__((address_space(1))) T*;
 template <typename T> __device__ __forceinline__ gmut<T> as_global_mut(void* p) {
   return (gmut<T>)p;
 }
+// A descriptor struct copied out of global memory word by word through a global-space
+// pointer: its fields become values (only the words used are loaded), read with
+// global or scalar loads rather than generic ones.
+template <typename S> __device__ __forceinline__ S load_global(const S* p) {
+  static_assert(sizeof(S) % 4 == 0 && alignof(S) >= 4, "a struct of 4-byte words");
+  S v;
+  const gptr<uint32_t> src = as_global<uint32_t>(p);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) dst[i] = src[i];
+  return v;
+}
 // relaxed device-scope atomic add through a global-address-space pointer
 template <typename T> __device__ __forceinline__ T global_add(gmut<T> p, T v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

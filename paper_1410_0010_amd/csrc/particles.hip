@@ -223,7 +223,7 @@ __device__ __forceinline__ int find_grid(const int64_t* __restrict__ begin, int 
   int lo = 0, hi = ngrids - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (begin[mid] <= b) lo = mid; else hi = mid - 1;
+    if (as_global<int64_t>(begin)[mid] <= b) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
@@ -505,14 +505,18 @@ hipError_t launch_deposit_tiles(const DepIO<T>& io, const DepLevel* tab, hipStre
 template <typename T, bool COMP>
 __global__ void __launch_bounds__(kBlock) k_deposit_finalize(DepIO<T> io, const DepLevel* __restrict__ tab) {
   const int lb = batch_level(io.fin_blk0, io.nlev, blockIdx.x);
-  const DepLevel& L = tab[lb];
+  // the descriptors as values read once, and global-space pointers (generic loads
+  // of their fields in the loops would each wait on the previous memory operation)
+  const DepLevel L = load_global(tab + lb);
   const int64_t blk = blockIdx.x - io.fin_blk0[lb];
   const int gi = find_grid(L.block_begin, L.ngrids, blk);
-  const GridDesc& g = L.grids[gi];
+  const GridDesc g = load_global(L.grids + gi);
   const int64_t cells = (int64_t)g.gmf_n[0] * g.gmf_n[1] * g.gmf_n[2];
-  const int64_t first = (blk - L.block_begin[gi]) * (int64_t)(kBlock * kGmfPer) + threadIdx.x;
-  const T* gas = io.gas[lb];
-  const T* pgas = io.pgas[lb];
+  const int64_t first = (blk - as_global<int64_t>(L.block_begin)[gi]) * (int64_t)(kBlock * kGmfPer) +
+                        threadIdx.x;
+  const gptr<T> gas = io.gas[lb] ? as_global<T>(io.gas[lb]) : nullptr;
+  const gptr<T> pgas = io.pgas[lb] ? as_global<T>(io.pgas[lb]) : nullptr;
+  const gmut<T> out = as_global_mut<T>(io.gmf[lb]) + g.gmf_offset;
   int cx[kGmfPer], cy[kGmfPer], cz[kGmfPer];
   double mass[kGmfPer];
   T add[kGmfPer];
@@ -547,7 +551,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_finalize(DepIO<T> io, const 
 #pragma unroll
   for (int k = 0; k < kGmfPer; ++k) {
     const int64_t local = first + (int64_t)k * kBlock;
-    if (local < cells) io.gmf[lb][g.gmf_offset + local] = (T)mass[k] + add[k];
+    if (local < cells) out[local] = (T)mass[k] + add[k];
   }
 }
 
