@@ -69,7 +69,7 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
   __shared__ int gsl[KG];
   __shared__ int gnext;
   const int lb = batch_of(io.item_blk0, io.nlev, blockIdx.x);
-  const DepLevel& L = tab[lb];
+  const DepLevel L = load_global(tab + lb);   // its fields as values, not re-read after stores
   const int64_t item = blockIdx.x - io.item_blk0[lb];
   const int32_t total = L.items[L.ntiles];
   const int4 wk = L.work[item];                     // in the table's room; read with the count
@@ -563,7 +563,7 @@ k_adj_deposit_particles(AdjIO<T> io, const DepLevel* __restrict__ tab) {
   __shared__ double ta[kTH3];
   constexpr int kTH = kTile + 2;
   const int lb = batch_of(io.item_blk0, io.nlev, blockIdx.x);
-  const DepLevel& L = tab[lb];
+  const DepLevel L = load_global(tab + lb);   // its fields as values, not re-read after stores
   const int64_t item = blockIdx.x - io.item_blk0[lb];
   const int32_t total = L.items[L.ntiles];
   const int4 wk = L.work[item];                     // in the table's room; read with the count

@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(kBlock) k_deposit_tiles(DepIO<T> io, const Dep
   double* acc = acc_raw;
   float2* accp = reinterpret_cast<float2*>(acc_raw);
   const int lb = batch_level(io.item_blk0, io.nlev, blockIdx.x);
-  const DepLevel& L = tab[lb];
+  const DepLevel L = load_global(tab + lb);   // its fields as values, not re-read after stores
   const int64_t item = blockIdx.x - io.item_blk0[lb];
   const int32_t total = L.items[L.ntiles];
   const int4 wk = L.work[item];                     // in the table's room; read with the count
@@ -645,7 +645,7 @@ __global__ void __launch_bounds__(kBlock) k_interp_tiles(InterpIO<T> io, const D
                                                          const GridDesc* __restrict__ grids) {
   __shared__ V4<T> tf[kTH3];
   const int lb = batch_level(io.item_blk0, io.nlev, blockIdx.x);
-  const DepLevel& L = tab[lb];
+  const DepLevel L = load_global(tab + lb);   // its fields as values, not re-read after stores
   const int64_t item = blockIdx.x - io.item_blk0[lb];
   const int32_t total = L.items[L.ntiles];
   const int4 wk = L.work[item];                     // in the table's room; read with the count
