@@ -20,7 +20,9 @@ ones it can afford one value at a time, plus properties that hold at any size:
 * the FP32 composed fields, particle accelerations and potentials, and the reverse
   sweep's gradients of W (positions, masses, gas) against the FP64 solve of the same
   FP32-rounded inputs (pinned to the oracle element by element at every smaller
-  size), at the FP32 bar of 1e-5.
+  size), at the FP32 bar of 1e-5;
+* the same GMF, mass, field and particle checks for the compensated FP32 deposit
+  (FP32 (sum, error) pairs instead of FP64 accumulation).
 """
 
 import sys
@@ -77,10 +79,10 @@ def full(request):
     return request.param, w, inputs
 
 
-def gpu_run(w, inp, dtype, samples):
+def gpu_run(w, inp, dtype, samples, accum="f64", adjoint=True):
     """Staged owner and deposit (GMF at the sampled cells), then the one-call solve
     after autotuning: fields, particle outputs and FP64 totals stay on the device."""
-    plan = P.Plan(w.root_n, w.grids, boundary=w.boundary)
+    plan = P.Plan(w.root_n, w.grids, boundary=w.boundary, deposit_accum=accum)
     ctx = P.Context(plan, 0)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype))).to(DEV)
     x, y, z, m = (dev(inp[k]) for k in "xyzm")
@@ -101,13 +103,14 @@ def gpu_run(w, inp, dtype, samples):
     ax, ay, az, pot = ctx.solve(x, y, z, m, gas if has_gas else None)
     tot = ctx.solve_totals(m, ax, ay, az, pot, gas if has_gas else None)
     fields = [ctx.solved_field(l, x.dtype) for l in range(plan.nlevels)]
-    # the reverse sweep of W (as the benchmark's forward + adjoint step)
-    xb, yb, zb, mb, gb = ctx.solve_adjoint(x, y, z, m, gas if has_gas else None, pot, None,
-                                           None, 1.0)
-    torch.cuda.synchronize()
     out = dict(plan=plan, owner=owner, gmf=gmf, fields=fields, acc=torch.stack([ax, ay, az], 1),
-               pot=pot, totals=tot, dx=torch.stack([xb, yb, zb], 1), dm=mb,
-               dgas=None if gb is None else [g for g in gb if g is not None])
+               pot=pot, totals=tot)
+    if adjoint:                        # the reverse sweep of W (the benchmark's second step)
+        xb, yb, zb, mb, gb = ctx.solve_adjoint(x, y, z, m, gas if has_gas else None, pot, None,
+                                               None, 1.0)
+        out.update(dx=torch.stack([xb, yb, zb], 1), dm=mb,
+                   dgas=None if gb is None else [g for g in gb if g is not None])
+    torch.cuda.synchronize()
     del ctx
     return out
 
@@ -157,6 +160,8 @@ def test_full_size_parity(full):
     r64 = gpu_run(w, inp, np.float64, samples)
     say(f"[full] {name}: GPU FP32")
     r32 = gpu_run(w, inp, np.float32, samples)
+    say(f"[full] {name}: GPU FP32, compensated FP32 deposit")
+    rc = gpu_run(w, inp, np.float32, samples, accum="f32_comp", adjoint=False)
 
     say(f"[full] {name}: oracle owners")
     own_ref = O.owner_of(oplan, x, y, z)
@@ -173,9 +178,10 @@ def test_full_size_parity(full):
         ref = rho.reshape(-1)[samples[g.index]]
         del rho
         e64, e32 = rel(r64["gmf"][g.index], ref), rel(r32["gmf"][g.index], ref)
-        say(f"[full]   GMF rel L2: FP64 {e64:.2e}  FP32 {e32:.2e}")
+        ec = rel(rc["gmf"][g.index], ref)
+        say(f"[full]   GMF rel L2: FP64 {e64:.2e}  FP32 {e32:.2e}  compensated {ec:.2e}")
         assert e64 <= 1e-13, f"{name}: grid {g.index} FP64 GMF {e64:.3e}"
-        assert e32 <= 1e-6, f"{name}: grid {g.index} FP32 GMF {e32:.3e}"
+        assert e32 <= 1e-6 and ec <= 1e-6, f"{name}: grid {g.index} FP32 GMF {e32:.3e} {ec:.3e}"
         # mass: whole clouds inside the box count m, the others are deposited
         lo = [int(v) for v in g.gmf_lo]
         n = [int(v) for v in g.gmf_n]
@@ -196,21 +202,24 @@ def test_full_size_parity(full):
     for lev in range(oplan.nlevels):
         e64 = abs(r64["totals"][lev] - level_mass[lev]) / abs(level_mass[lev])
         e32 = abs(r32["totals"][lev] - level_mass[lev]) / abs(level_mass[lev])
-        say(f"[full]   level {lev} mass rel: FP64 {e64:.2e}  FP32 {e32:.2e}")
+        ec = abs(rc["totals"][lev] - level_mass[lev]) / abs(level_mass[lev])
+        say(f"[full]   level {lev} mass rel: FP64 {e64:.2e}  FP32 {e32:.2e}  compensated {ec:.2e}")
         assert e64 <= 1e-12, f"{name}: level {lev} FP64 mass {e64:.3e}"
-        assert e32 <= 1e-6, f"{name}: level {lev} FP32 mass {e32:.3e}"
+        assert e32 <= 1e-6 and ec <= 1e-6, f"{name}: level {lev} FP32 mass {e32:.3e} {ec:.3e}"
 
     # FP32 against the FP64 solve of the same inputs
-    for lev in range(oplan.nlevels):
-        f32, f64 = r32["fields"][lev], r64["fields"][lev]
-        ea, ep = trel(f32[:, :3], f64[:, :3]), trel(f32[:, 3], f64[:, 3])
-        say(f"[full]   level {lev} composed field FP32 vs FP64: acc {ea:.2e} pot {ep:.2e}")
-        assert ea <= 1e-5 and ep <= 1e-5, f"{name}: level {lev} field acc {ea:.3e} pot {ep:.3e}"
     owned = torch.from_numpy(own_ref >= 0).to(DEV)
-    ea = trel(r32["acc"][owned], r64["acc"][owned])
-    ep = trel(r32["pot"][owned], r64["pot"][owned])
-    say(f"[full]   particles FP32 vs FP64: acc {ea:.2e} pot {ep:.2e}")
-    assert ea <= 1e-5 and ep <= 1e-5, f"{name}: particle acc {ea:.3e} pot {ep:.3e}"
+    for tag, r in (("FP32", r32), ("compensated", rc)):
+        for lev in range(oplan.nlevels):
+            f32, f64 = r["fields"][lev], r64["fields"][lev]
+            ea, ep = trel(f32[:, :3], f64[:, :3]), trel(f32[:, 3], f64[:, 3])
+            say(f"[full]   level {lev} composed field {tag} vs FP64: acc {ea:.2e} pot {ep:.2e}")
+            assert ea <= 1e-5 and ep <= 1e-5, \
+                f"{name}: {tag} level {lev} field acc {ea:.3e} pot {ep:.3e}"
+        ea = trel(r["acc"][owned], r64["acc"][owned])
+        ep = trel(r["pot"][owned], r64["pot"][owned])
+        say(f"[full]   particles {tag} vs FP64: acc {ea:.2e} pot {ep:.2e}")
+        assert ea <= 1e-5 and ep <= 1e-5, f"{name}: {tag} particle acc {ea:.3e} pot {ep:.3e}"
     assert torch.all(r32["acc"][~owned] == 0) and torch.all(r64["acc"][~owned] == 0)
     ex, em = trel(r32["dx"], r64["dx"]), trel(r32["dm"], r64["dm"])
     say(f"[full]   dW/dx FP32 vs FP64 {ex:.2e}, dW/dm {em:.2e}")
