@@ -123,6 +123,15 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
   __syncthreads();
   double* fbar = io.fbar[lb];
   const int c0 = 4 - NC;                            // first component carried
+  // the owner grid's field box per entry; on a level of one grid, read once
+  struct Box { int lo[3], n[3], wrap; int64_t off; };
+  const auto box_of = [&](int gi) {
+    const GridDesc& d = grids[gi];
+    return Box{{d.fld_lo[0], d.fld_lo[1], d.fld_lo[2]}, {d.fld_n[0], d.fld_n[1], d.fld_n[2]},
+               d.wrap, d.fld_offset};
+  };
+  const bool one = L.ngrids == 1;
+  const Box box1 = one ? box_of(L.first) : Box{};
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     if (ref[k].y < 0) continue;
@@ -131,11 +140,11 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
     const double cot[4] = {io.abx ? (double)io.abx[i] : 0.0, io.aby ? (double)io.aby[i] : 0.0,
                            io.abz ? (double)io.abz[i] : 0.0,
                            (io.phib ? (double)io.phib[i] : 0.0) + io.wbar * 0.5 * (double)v.w};
-    const GridDesc& g = grids[ref[k].y];
+    const Box g = one ? box1 : box_of(ref[k].y);
     const T fx = floor(v.x), fy = floor(v.y), fz = floor(v.z);
     const T tx = v.x - fx - (T)0.5, ty = v.y - fy - (T)0.5, tz = v.z - fz - (T)0.5;
-    const int cx = (int)fx - g.fld_lo[0], cy = (int)fy - g.fld_lo[1], cz = (int)fz - g.fld_lo[2];
-    const int nx = g.fld_n[0], ny = g.fld_n[1], nz = g.fld_n[2];
+    const int cx = (int)fx - g.lo[0], cy = (int)fy - g.lo[1], cz = (int)fz - g.lo[2];
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     int slot = -1;                                  // LDS tile of this particle's grid
 #pragma unroll
     for (int r = 0; r < KG; ++r)
@@ -177,7 +186,7 @@ k_adj_interp(AdjIO<T> io, const DepLevel* __restrict__ tab, const GridDesc* __re
           } else {
             // 4 components per cell, or the Phi component alone, densely (NC == 1)
             double* a = fbar + (NC == 1 ? 1 : 4) *
-                                   (g.fld_offset + ((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]);
+                                   (g.off + ((int64_t)az_[dz] * ny + ay_[dy]) * nx + ax_[dx]);
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc) atomicAdd(a + (NC == 1 ? 0 : c0 + cc), w * cot[c0 + cc]);
           }
